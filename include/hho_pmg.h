@@ -1,0 +1,215 @@
+/*
+ * hho_pmg.h -- C ABI of the MI355X p-multilevel HHO Stokes library.
+ *
+ * The library solves the Stokes problem (Section 1 of Botti & Di Pietro,
+ * "p-Multilevel preconditioners for HHO discretizations of the Stokes
+ * equations with static condensation", arXiv 2009.13840) with the equal-order
+ * HHO scheme with discontinuous pressure (Scheme 1, Section 2.3.1), condenses
+ * it cell by cell (Section 4.1.2: v-cond, eq. ST.1, or v&p-cond, eq. ST.2),
+ * inherits coarse operators of degrees k_0 > k_1 > ... > k_L by Galerkin
+ * projection of the condensed operator (Sections 3.2 and 4.2), and solves it
+ * with flexible GMRES preconditioned by one p-multilevel V-cycle per
+ * iteration (algorithm of Section 3.3).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns an int status: HHO_OK (0) or a negative HHO_E_*
+ *   code.  No C++ exception crosses the ABI.  hho_last_error() returns a
+ *   thread-local message describing the last failure.
+ * - Handles are opaque.  A handle is not thread-safe: calls on one handle
+ *   must be serialised by the caller.  Destroy functions accept NULL.
+ * - Host pointers are read during the call only; the library copies what it
+ *   keeps.  Device pointers (marked "device") must point to memory of the
+ *   current HIP device; the library never frees caller memory.
+ * - Device memory: after hho_problem_set_data the caller queries
+ *   hho_workspace_size() and binds one device buffer of at least that many
+ *   bytes with hho_bind_workspace(); every device array of the problem is
+ *   carved out of it, so the library performs no device allocation of its own
+ *   in setup or solve.  The buffer must stay alive until the problem is
+ *   destroyed or rebound.
+ * - Streams: all device work is enqueued on the stream given by
+ *   hho_set_stream() (default: the null stream).  Functions that return
+ *   host results synchronise that stream before returning.
+ *
+ * Global unknown layout ("global layout", used by every vector argument)
+ * ----------------------------------------------------------------------
+ * level l has degree k_l, n_F = dim P^{k_l}_{d-1}, and
+ *   n_P = dim P^{k_l}_d (v-cond) or 1 (v&p-cond):
+ *   face velocity  (face f, component c, mode j) -> (f*d + c)*n_F + j
+ *   cell pressure  (cell T, mode q)              -> n_faces*d*n_F + T*n_P + q
+ * Face modes are coefficients in the L2(F)-orthonormal hierarchical basis
+ * obtained by Gram-Schmidt (twice, modified) of the scaled monomials
+ * ((x - x_F).t_i / h_F)^beta in graded order, where the tangent t_1 points from
+ * the face's first to its second vertex (d=3: t_2 = n_F x t_1 with n_F the
+ * Newell normal of the vertex ring; d=2: n_F = (t_1y, -t_1x)).  Cell modes use
+ * the L2(T)-orthonormal hierarchical basis from ((x - x_T)/h_T)^alpha
+ * (x_T centroid, h_T diameter) in graded order, so the first pressure mode is
+ * the mean (|T|^{-1/2}).
+ */
+#ifndef HHO_PMG_H
+#define HHO_PMG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define HHO_OK                 0
+#define HHO_E_INVALID_ARG     -1  /* bad argument, size or call order            */
+#define HHO_E_MESH            -2  /* inconsistent mesh topology or geometry      */
+#define HHO_E_LOCAL_SINGULAR  -3  /* a local Cholesky factorisation failed       */
+#define HHO_E_NOT_CONVERGED   -4  /* max iterations reached; outputs are written */
+#define HHO_E_BREAKDOWN       -5  /* NaN/Inf met in the iteration                */
+#define HHO_E_DEVICE          -6  /* HIP runtime error (message has the code)    */
+#define HHO_E_CAPACITY        -7  /* caller buffer too small                     */
+#define HHO_E_OOM             -8  /* host allocation failed                      */
+
+/* condensation variants, Section 4.1.2 */
+#define HHO_COND_V   1   /* v-cond: cell velocities eliminated (eq. ST.1)              */
+#define HHO_COND_VP  2   /* v&p-cond: cell velocities and non-mean pressures (eq. ST.2) */
+
+/* precision of the V-cycle (the outer FGMRES is always FP64) */
+#define HHO_PREC_FP64   0
+#define HHO_PREC_FP32   1
+
+/* coarsest-level solver */
+#define HHO_COARSE_AUTO   0   /* dense LU if the level has <= 4096 unknowns, else GMRES */
+#define HHO_COARSE_DENSE  1   /* bordered dense LU (FP64)                                */
+#define HHO_COARSE_GMRES  2   /* preconditioned GMRES to coarse_rtol                     */
+
+/* face boundary flags in hho_mesh_desc.face_bc */
+#define HHO_FACE_INTERIOR   0
+#define HHO_FACE_DIRICHLET  1
+#define HHO_FACE_NEUMANN    2
+
+typedef struct hho_mesh hho_mesh;
+typedef struct hho_problem hho_problem;
+
+/* Polytopal mesh (Section 2.1) in CSR form.  d=2: faces are segments given by
+ * two vertices, cells are convex polygons listing their faces; d=3: faces are
+ * planar convex polygons (vertex ring), cells convex polyhedra.  All arrays are
+ * host memory and are copied. */
+typedef struct {
+  int32_t dim;                 /* 2 or 3 */
+  int64_t n_verts;
+  const double *verts;         /* [n_verts*dim] */
+  int64_t n_faces;
+  const int64_t *face_ptr;     /* [n_faces+1] */
+  const int64_t *face_vtx;     /* [face_ptr[n_faces]] */
+  int64_t n_cells;
+  const int64_t *cell_ptr;     /* [n_cells+1] */
+  const int64_t *cell_face;    /* [cell_ptr[n_cells]] */
+  const int8_t *face_bc;       /* [n_faces] HHO_FACE_* ; boundary faces must be 1 or 2 */
+} hho_mesh_desc;
+
+/* Solver options; hho_options_default() fills the defaults noted here. */
+typedef struct {
+  double eta;          /* Nitsche penalty of eq. HHOdiscrMNT; <= 0: 4(k+1)(k+d)/d * max card(F_T) */
+  double rtol;         /* FGMRES true relative residual (1e-8) */
+  int32_t max_it;      /* FGMRES iterations (1000) */
+  int32_t restart;     /* FGMRES restart length (30, at most 64) */
+  int32_t smooth_its;  /* GMRES iterations per pre/post smoothing (2, at most 2) */
+  int32_t precision;   /* HHO_PREC_* (FP64) */
+  int32_t coarse_mode; /* HHO_COARSE_* (AUTO) */
+  double coarse_rtol;  /* coarse GMRES relative residual (1e-3) */
+  int32_t coarse_restart; /* coarse GMRES restart (30, at most 64) */
+  int32_t coarse_max_it;  /* coarse GMRES iterations (300) */
+  int32_t quad_extra;  /* quadrature exact to degree 2k+2+quad_extra (6) */
+} hho_options;
+
+/* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the
+ * outward unit normals for boundary data (NULL for the body force).  Writes
+ * out [n*dim]. */
+typedef void (*hho_field_fn)(const double *x, int64_t n, const double *nrm, double *out, void *ctx);
+
+const char *hho_last_error(void);
+void hho_options_default(hho_options *opt);
+
+/* Validates and copies a mesh: every face belongs to one or two cells, boundary
+ * faces carry a Dirichlet or Neumann flag, interior faces flag 0, cells have
+ * positive measure.  Errors: HHO_E_INVALID_ARG, HHO_E_MESH. */
+int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out);
+void hho_mesh_destroy(hho_mesh *m);
+
+/* Creates a problem on a mesh: degree k >= 0 (k <= 6), cond = HHO_COND_V|VP,
+ * nlev levels of strictly decreasing degrees[] with degrees[0] = k
+ * (degrees = NULL: k, k-1, ..., 0).  The mesh must outlive the problem.
+ * Errors: HHO_E_INVALID_ARG. */
+int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const int *degrees,
+                       const hho_options *opt, hho_problem **out);
+void hho_problem_destroy(hho_problem *p);
+
+/* Builds the local HHO operators of every cell on the host (Sections 2.2,
+ * 2.3.1): potential reconstruction, face residual stabilisation, Nitsche terms,
+ * pressure-velocity coupling and data terms.  f is the body force; gD the
+ * Dirichlet datum; gN the traction (grad u - p I)n on Neumann faces (may be NULL
+ * when there is none; NULL f/gD mean zero).  Errors: HHO_E_INVALID_ARG,
+ * HHO_E_LOCAL_SINGULAR (reconstruction matrix not SPD). */
+int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_field_fn gN, void *ctx);
+
+/* Device workspace (see conventions).  hho_bind_workspace fails with
+ * HHO_E_CAPACITY if bytes < hho_workspace_size(). */
+int hho_workspace_size(const hho_problem *p, size_t *bytes);
+int hho_bind_workspace(hho_problem *p, void *dev_ptr, size_t bytes);
+int hho_set_stream(hho_problem *p, void *hip_stream);
+
+/* Device setup: copies the local operators to the device, condenses every cell
+ * (eq. ST.1 or ST.2, FP64 Cholesky of the local blocks), assembles the face-block
+ * sparse operator, inherits the coarse levels by sub-block extraction
+ * (Section 4.2), and factorises the smoother patches and the coarse solver.
+ * Errors: HHO_E_INVALID_ARG (no data / workspace), HHO_E_LOCAL_SINGULAR,
+ * HHO_E_DEVICE. */
+int hho_setup(hho_problem *p);
+
+/* Number of unknowns of level l in the global layout. */
+int hho_level_size(const hho_problem *p, int level, int64_t *n);
+
+/* FGMRES + V-cycle solve from x = 0.  x_dev (device, [level-0 size]) receives
+ * the solution with the pressure normalised to zero mean when the boundary is
+ * all Dirichlet.  iters receives the iteration count; hist (host, may be NULL)
+ * receives min(hist_cap, iters+1) relative residual estimates, hist[0] = 1;
+ * final_rel (may be NULL) the explicitly recomputed true relative residual.
+ * Errors: HHO_E_NOT_CONVERGED (outputs written), HHO_E_BREAKDOWN, HHO_E_DEVICE. */
+int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel);
+
+/* ---- inspection and kernel-level entry points (parity tests, benchmarks) ---- */
+
+/* Condensed right-hand side of level 0 (device, [level-0 size]). */
+int hho_get_rhs(hho_problem *p, double *b_dev);
+
+/* Condensed local system of one cell, host buffers, in the cell's local order
+ * [faces of T (mesh order) x component x mode ; pressure modes of T]:
+ * S [n x n], rhs [n], n = d*card(F_T)*n_F + n_P (level 0).  *n_out receives n;
+ * HHO_E_CAPACITY if cap < n*n. */
+int hho_get_condensed_cell(hho_problem *p, int64_t cell, double *S, double *rhs, int64_t cap,
+                           int64_t *n_out);
+
+/* Host copies of the local HHO operators of one cell before condensation:
+ * a [nloc x nloc] scalar viscous matrix (cell modes first, then faces in mesh
+ * order), B [d x n_T x nloc], rhs_u [d x nloc], rhs_p [n_T]. */
+int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B, double *rhs_u,
+                       double *rhs_p, int64_t cap, int64_t *nloc_out);
+
+/* y = S_l x on level l in FP64 (device vectors in the global layout). */
+int hho_level_apply(hho_problem *p, int level, const double *x_dev, double *y_dev);
+
+/* z = M_l r: the level-l smoother preconditioner (cell-patch Schwarz), FP64. */
+int hho_precond_apply(hho_problem *p, int level, const double *r_dev, double *z_dev);
+
+/* x = MG_V(0, b, 0): one V-cycle from a zero initial guess, in the problem's
+ * V-cycle precision (device vectors, FP64, global layout). */
+int hho_vcycle_apply(hho_problem *p, const double *b_dev, double *x_dev);
+
+/* Phase timings of the last hho_setup / hho_solve in milliseconds (device
+ * events): [0] condensation, [1] assembly, [2] levels, [3] smoother setup,
+ * [4] coarse setup, [5] solve, [6] V-cycle total, [7] V-cycle count,
+ * [8] coarse iterations total.  n is the capacity of t. */
+int hho_get_timings(const hho_problem *p, double *t, int n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HHO_PMG_H */

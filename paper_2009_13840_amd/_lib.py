@@ -1,0 +1,286 @@
+"""ctypes binding of ``libhho_pmg.so`` (argument marshalling only).
+
+Every computation happens in the HIP library: this module converts Python/NumPy
+arguments to the C ABI of ``include/hho_pmg.h``, allocates the device
+workspace as a torch uint8 tensor and passes torch's current HIP stream.  It
+fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhho_pmg.so")
+
+HHO_OK = 0
+ERRORS = {-1: "HHO_E_INVALID_ARG", -2: "HHO_E_MESH", -3: "HHO_E_LOCAL_SINGULAR", -4: "HHO_E_NOT_CONVERGED",
+          -5: "HHO_E_BREAKDOWN", -6: "HHO_E_DEVICE", -7: "HHO_E_CAPACITY", -8: "HHO_E_OOM"}
+COND = {"v": 1, "vp": 2}
+PREC = {"fp64": 0, "fp32": 1}
+COARSE = {"auto": 0, "dense": 1, "gmres": 2}
+
+EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
+           "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
+           "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_get_rhs", "hho_get_condensed_cell",
+           "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings"]
+
+
+class HHOError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int32), ("n_verts", C.c_int64), ("verts", C.POINTER(C.c_double)),
+                ("n_faces", C.c_int64), ("face_ptr", C.POINTER(C.c_int64)), ("face_vtx", C.POINTER(C.c_int64)),
+                ("n_cells", C.c_int64), ("cell_ptr", C.POINTER(C.c_int64)), ("cell_face", C.POINTER(C.c_int64)),
+                ("face_bc", C.POINTER(C.c_int8))]
+
+
+class Options(C.Structure):
+    _fields_ = [("eta", C.c_double), ("rtol", C.c_double), ("max_it", C.c_int32), ("restart", C.c_int32),
+                ("smooth_its", C.c_int32), ("precision", C.c_int32), ("coarse_mode", C.c_int32),
+                ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_max_it", C.c_int32),
+                ("quad_extra", C.c_int32)]
+
+
+FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                       C.c_void_p)
+
+_lib = None
+
+
+def load():
+    """Load the in-tree library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_13840_amd.build`")
+    lib = C.CDLL(LIB_PATH)
+    P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_double)
+    sig = {
+        "hho_last_error": ([], C.c_char_p),
+        "hho_options_default": ([C.POINTER(Options)], None),
+        "hho_mesh_create": ([C.POINTER(MeshDesc), C.POINTER(P)], I32),
+        "hho_mesh_destroy": ([P], None),
+        "hho_problem_create": ([P, I32, I32, I32, C.POINTER(C.c_int), C.POINTER(Options), C.POINTER(P)], I32),
+        "hho_problem_destroy": ([P], None),
+        "hho_problem_set_data": ([P, FIELD_FN, FIELD_FN, FIELD_FN, P], I32),
+        "hho_workspace_size": ([P, C.POINTER(C.c_size_t)], I32),
+        "hho_bind_workspace": ([P, P, C.c_size_t], I32),
+        "hho_set_stream": ([P, P], I32),
+        "hho_setup": ([P], I32),
+        "hho_level_size": ([P, I32, C.POINTER(I64)], I32),
+        "hho_solve": ([P, P, C.POINTER(C.c_int), D, I32, D], I32),
+        "hho_get_rhs": ([P, P], I32),
+        "hho_get_condensed_cell": ([P, I64, D, D, I64, C.POINTER(I64)], I32),
+        "hho_get_local_cell": ([P, I64, D, D, D, D, I64, C.POINTER(I64)], I32),
+        "hho_level_apply": ([P, I32, P, P], I32),
+        "hho_precond_apply": ([P, I32, P, P], I32),
+        "hho_vcycle_apply": ([P, P, P], I32),
+        "hho_get_timings": ([P, D, I32], I32),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(code):
+    if code != HHO_OK:
+        raise HHOError(code, load().hho_last_error().decode())
+    return code
+
+
+def _dptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+class Mesh:
+    """Library copy of a ``synth.Mesh``-like object (dim, verts, face_ptr, face_vtx,
+    cell_ptr, cell_face, face_bc)."""
+
+    def __init__(self, m):
+        lib = load()
+        self._keep = [np.ascontiguousarray(m.verts, dtype=np.float64),
+                      np.ascontiguousarray(m.face_ptr, dtype=np.int64),
+                      np.ascontiguousarray(m.face_vtx, dtype=np.int64),
+                      np.ascontiguousarray(m.cell_ptr, dtype=np.int64),
+                      np.ascontiguousarray(m.cell_face, dtype=np.int64),
+                      np.ascontiguousarray(m.face_bc, dtype=np.int8)]
+        v, fp, fv, cp, cf, bc = self._keep
+        desc = MeshDesc(int(m.dim), len(v), _dptr(v), len(fp) - 1, fp.ctypes.data_as(C.POINTER(C.c_int64)),
+                        fv.ctypes.data_as(C.POINTER(C.c_int64)), len(cp) - 1,
+                        cp.ctypes.data_as(C.POINTER(C.c_int64)), cf.ctypes.data_as(C.POINTER(C.c_int64)),
+                        bc.ctypes.data_as(C.POINTER(C.c_int8)))
+        h = C.c_void_p()
+        _check(lib.hho_mesh_create(C.byref(desc), C.byref(h)))
+        self.h = h
+        self.dim = int(m.dim)
+        self.n_cells = len(cp) - 1
+        self.n_faces = len(fp) - 1
+        self.cell_ptr = cp
+        self.cell_face = cf
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hho_mesh_destroy(self.h)
+            self.h = None
+
+
+def options(**kw) -> Options:
+    o = Options()
+    load().hho_options_default(C.byref(o))
+    for k, v in kw.items():
+        if k == "precision":
+            v = PREC[v] if isinstance(v, str) else v
+        if k == "coarse_mode":
+            v = COARSE[v] if isinstance(v, str) else v
+        setattr(o, k, v)
+    return o
+
+
+def _wrap_field(fn, dim, with_normal):
+    if fn is None:
+        return FIELD_FN()
+
+    def cb(x, n, nrm, out, ctx):
+        try:
+            X = np.ctypeslib.as_array(x, shape=(n * dim,)).reshape(n, dim)
+            O = np.ctypeslib.as_array(out, shape=(n * dim,)).reshape(n, dim)
+            if with_normal:
+                N = np.ctypeslib.as_array(nrm, shape=(n * dim,)).reshape(n, dim)
+                O[:] = fn(X, N)
+            else:
+                O[:] = fn(X)
+        except Exception as e:  # pragma: no cover - surfaces in the caller
+            print("hho field callback failed:", repr(e))
+            O[:] = np.nan
+    return FIELD_FN(cb)
+
+
+class Problem:
+    def __init__(self, mesh: Mesh, k: int, cond: str = "v", degrees=None, **opts):
+        lib = load()
+        self.mesh = mesh
+        self.k, self.cond = k, cond
+        self.opts = options(**opts)
+        h = C.c_void_p()
+        if degrees is None:
+            degp, nlev = None, 0
+        else:
+            arr = (C.c_int * len(degrees))(*degrees)
+            degp, nlev = arr, len(degrees)
+        _check(lib.hho_problem_create(mesh.h, k, COND[cond], nlev, degp, C.byref(self.opts), C.byref(h)))
+        self.h = h
+        self.ws = None
+        self.nlev = len(degrees) if degrees is not None else k + 1
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hho_problem_destroy(self.h)
+            self.h = None
+
+    # ---- host phase
+    def set_data(self, f=None, gD=None, gN=None):
+        d = self.mesh.dim
+        self._cbs = (_wrap_field(f, d, False), _wrap_field(gD, d, False), _wrap_field(gN, d, True))
+        _check(load().hho_problem_set_data(self.h, *self._cbs, None))
+
+    def local_cell(self, c: int):
+        lib = load()
+        nloc = C.c_int64()
+        cap = 1 << 16
+        d = self.mesh.dim
+        a = np.zeros(cap)
+        B = np.zeros(cap)
+        ru = np.zeros(cap)
+        rp = np.zeros(cap)
+        _check(lib.hho_get_local_cell(self.h, c, _dptr(a), _dptr(B), _dptr(ru), _dptr(rp), cap, C.byref(nloc)))
+        n = nloc.value
+        from math import comb
+        nT = comb(self.k + d, d)
+        return {"a": a[:n * n].reshape(n, n).copy(), "B": B[:d * nT * n].reshape(d, nT, n).copy(),
+                "rhs_u": ru[:d * n].reshape(d, n).copy(), "rhs_p": rp[:nT].copy()}
+
+    def workspace_size(self) -> int:
+        s = C.c_size_t()
+        _check(load().hho_workspace_size(self.h, C.byref(s)))
+        return s.value
+
+    # ---- device phase
+    def bind(self, device="cuda:0"):
+        import torch
+        n = self.workspace_size()
+        self.ws = torch.empty(n, dtype=torch.uint8, device=device)
+        _check(load().hho_bind_workspace(self.h, C.c_void_p(self.ws.data_ptr()), n))
+        stream = torch.cuda.current_stream(self.ws.device).cuda_stream
+        _check(load().hho_set_stream(self.h, C.c_void_p(stream)))
+        self.device = self.ws.device
+
+    def setup(self):
+        _check(load().hho_setup(self.h))
+
+    def level_size(self, l: int) -> int:
+        n = C.c_int64()
+        _check(load().hho_level_size(self.h, l, C.byref(n)))
+        return n.value
+
+    def _vec(self, n):
+        import torch
+        return torch.zeros(n, dtype=torch.float64, device=self.device)
+
+    def solve(self, hist_cap: int = 1001):
+        x = self._vec(self.level_size(0))
+        it = C.c_int()
+        hist = np.zeros(hist_cap)
+        rel = C.c_double()
+        code = load().hho_solve(self.h, C.c_void_p(x.data_ptr()), C.byref(it), _dptr(hist), hist_cap,
+                                C.byref(rel))
+        if code not in (HHO_OK, -4):
+            _check(code)
+        n = min(it.value + 1, hist_cap)
+        return x, it.value, hist[:n].copy(), rel.value, code == HHO_OK
+
+    def rhs(self):
+        b = self._vec(self.level_size(0))
+        _check(load().hho_get_rhs(self.h, C.c_void_p(b.data_ptr())))
+        return b
+
+    def condensed_cell(self, c: int):
+        n = C.c_int64()
+        cap = 1 << 18
+        S = np.zeros(cap)
+        r = np.zeros(4096)
+        _check(load().hho_get_condensed_cell(self.h, c, _dptr(S), _dptr(r), cap, C.byref(n)))
+        m = n.value
+        return S[:m * m].reshape(m, m).copy(), r[:m].copy()
+
+    def level_apply(self, l, x):
+        y = self._vec(self.level_size(l))
+        _check(load().hho_level_apply(self.h, l, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    def precond_apply(self, l, r):
+        z = self._vec(self.level_size(l))
+        _check(load().hho_precond_apply(self.h, l, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())))
+        return z
+
+    def vcycle_apply(self, b):
+        x = self._vec(self.level_size(0))
+        _check(load().hho_vcycle_apply(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
+        return x
+
+    def timings(self):
+        t = np.zeros(16)
+        _check(load().hho_get_timings(self.h, _dptr(t), 16))
+        keys = ["condense_ms", "assemble_ms", "levels_ms", "smoother_setup_ms", "coarse_setup_ms", "solve_ms",
+                "vcycle_ms", "vcycles", "coarse_its"]
+        return dict(zip(keys, t[:len(keys)]))

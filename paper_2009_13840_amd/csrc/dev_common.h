@@ -1,0 +1,68 @@
+// Device-side helpers shared by the HIP translation units (CDNA wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hho {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;
+constexpr int kMaxRestart = 64;
+
+// Sum over a 64-lane wavefront.
+__device__ inline double wave_sum(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_down(v, o, kWave);
+  return v;
+}
+
+// Block-wide sum (blockDim.x a multiple of 64, <= 1024); result valid in thread 0.
+__device__ inline double block_sum(double v, double *lds /* >= 16 */) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  if (lane == 0) lds[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x / kWave;
+    for (int i = 0; i < nw; ++i) r += lds[i];
+  }
+  __syncthreads();
+  return r;
+}
+
+// "Last block" completion: every block calls this after writing its partial
+// results; exactly one block (the last to arrive) gets true, after a
+// device-scope fence that makes every other block's partials visible.  The
+// counter is reset for the next launch by that block.
+__device__ inline bool last_block_arrived(int *counter) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int prev = atomicAdd(counter, 1);
+    s_last = (prev == (int)gridDim.x - 1);
+  }
+  __syncthreads();
+  if (s_last) {
+    __threadfence();
+    if (threadIdx.x == 0) atomicExch(counter, 0);
+  }
+  return s_last != 0;
+}
+
+__device__ inline double vload(const double *p) { return *(volatile const double *)p; }
+
+template <typename T>
+struct VT;
+template <>
+struct VT<double> {
+  static constexpr const char *name = "f64";
+};
+template <>
+struct VT<float> {
+  static constexpr const char *name = "f32";
+};
+
+}  // namespace hho

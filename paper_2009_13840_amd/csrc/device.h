@@ -1,0 +1,145 @@
+// Device data structures and kernel launch wrappers of the HHO library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hho {
+
+constexpr int kMaxRestartH = 64;
+
+// Mesh topology on the device (int32 indices).
+struct DTopo {
+  int d;
+  int nc, nf;
+  int64_t ncf;             // cptr[nc]: number of (cell, face) entries
+  int64_t nnzb;            // number of face blocks
+  const int32_t *cptr;     // [nc+1] cell -> first entry of its face list
+  const int32_t *cface;    // [cptr[nc]] faces of each cell
+  const int32_t *fcell;    // [2*nf] adjacent cells (second = -1 on the boundary)
+  const int32_t *floc;     // [2*nf] position of the face in each cell's list
+  const int32_t *rowptr;   // [nf+1] face-block sparse rows
+  const int32_t *col;      // [nnzb] block columns (faces), sorted per row
+  const int32_t *blksrc;   // [6*nnzb] (cell, i, j) of the <= 2 cell blocks summed into each block
+  const int64_t *pairoff;  // [nc+1] prefix sum of card(F_T)^2
+  const int32_t *pairblk;  // [pairoff[nc]] block index of the local pair (i, j) of each cell
+  const double *zmean;     // [nc] |T|^{1/2}: mean-mode coefficient of the constant pressure
+};
+
+// One level of the operator: face-block rows plus cell-local couplings.
+//  v-cond:   bsr  [nnzb][p][p] scalar blocks (act on every velocity component),
+//            cpl  [cptr*d*p*t] cell coupling S_dT, rows (face i, comp c, mode r), cols q,
+//            spp  [nc][t][t]   S_TT.
+//  v&p-cond: bsr  [nnzb][d*p][d*p] full blocks, cpl [cptr*d*p] mean-pressure coupling, spp unused.
+template <typename T>
+struct DLevel {
+  int cond;  // 1 v, 2 vp
+  int p, t;  // face modes, pressure modes per cell
+  int64_t nface, N;  // face-part length nf*d*p, total length
+  const T *bsr, *cpl, *spp;
+  // smoother patches
+  const T *sinv;  // v: [pairoff*p*p] s_P^{-1}; vp: [pairoff*(d p)^2] S_P^{-1}
+  const T *xinv;  // v: [nc][t][t] pressure Schur inverse; vp: [cptr*d*p] g = S_P^{-1} b
+  const T *sig;   // vp: [nc] 1 / (b^T S_P^{-1} b)
+};
+
+// ---- setup kernels (FP64)
+size_t condense_lds_bytes(int d, int cond, int nT, int nF, int max_faces);
+size_t patch_lds_bytes(int d, int cond, int p, int t, int max_faces);
+void launch_condense(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
+                     double *stage, double *cpl, double *spp, double *rhs_stage, double *rhs_p, int *err,
+                     hipStream_t s, size_t lds);
+void launch_assemble(const DTopo &tp, int cond, int nF, int64_t nnzb, const double *stage, double *bsr,
+                     const double *rhs_stage, double *rhs, hipStream_t s);
+void launch_extract(const DTopo &tp, int cond, int64_t nnzb, int p0, int t0, int p1, int t1, const double *bsr0,
+                    const double *cpl0, const double *spp0, double *bsr1, double *cpl1, double *spp1, hipStream_t s);
+void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *bsr, const double *cpl,
+                        const double *spp, double *sinv, double *xinv, double *sig, double *scratch, int *err,
+                        hipStream_t s, size_t lds);
+template <typename Tout, typename Tin>
+void launch_convert(const Tin *in, Tout *out, int64_t n, hipStream_t s);
+
+// ---- dense coarse solver (FP64)
+void launch_densify(const DTopo &tp, const DLevel<double> &L, int border, double *D, int64_t ld, hipStream_t s);
+void launch_eye_right(double *D, int64_t n, int64_t ld, hipStream_t s);
+void launch_gj_step(double *D, int64_t n, int64_t ld, int64_t k, double *colbuf, int *err, hipStream_t s);
+void launch_dense_matvec(const double *Dinv, int64_t n, int64_t ld, int border, const double *x, double *y,
+                         hipStream_t s);
+
+// ---- solve kernels
+size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem);
+int reduce_blocks(int64_t n);
+// y = S x (face rows and cell rows); if xs1 != null the face part of x is the sum of
+// two slot vectors x (slot 0) and xs1 (slot 1), and xsum (if not null) receives it.
+template <typename T>
+void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s);
+// r = b - S x
+template <typename T>
+void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x, T *r, hipStream_t s);
+// Schwarz preconditioner: face part in two slots (z: slot 0, zs1: slot 1), cells in z.
+// If scale != null the input is scale[0]*r and v (if not null) receives that scaled vector.
+template <typename T>
+void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
+                    int max_faces, hipStream_t s);
+template <typename T>
+void launch_combine(int64_t nface, const T *zs1, T *z, hipStream_t s);
+// restriction of a level vector to the next coarser level (truncation) and prolongation-add
+template <typename Tc, typename Tf>
+void launch_restrict(int d, int nf, int nc, int pf, int tf, int pc, int tc, const Tf *xf, Tc *xc, hipStream_t s);
+template <typename Tc, typename Tf>
+void launch_prolong_add(int d, int nf, int nc, int pf, int tf, int pc, int tc, const Tc *xc, Tf *xf,
+                        hipStream_t s);
+
+// Smoother: minimal residual over span{z1, z2} (the GMRES(2) iterate):
+//   G = [w1 w2]^T [w1 w2], g = [w1 w2]^T r, y = G^{-1} g, x += Z y, r -= W y.
+template <typename T>
+void launch_mr2_dots(int64_t n, int m, const T *w1, const T *w2, const T *r, double *partial, double *y,
+                     int *counter, hipStream_t s);
+template <typename T>
+void launch_mr2_update(int64_t n, int m, const double *y, const T *z1, const T *z2, const T *w1, const T *w2,
+                       T *x, T *r, hipStream_t s);
+
+struct GmresState;
+template <typename T>
+void launch_norm_init(int64_t n, const T *r, double *partial, GmresState *st, int *counter, int which,
+                      hipStream_t s);
+template <typename T>
+void launch_scale(int64_t n, const T *x, const double *scale, T *y, hipStream_t s);
+template <typename T>
+void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
+                         int *counter, hipStream_t s);
+template <typename T>
+void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partial, GmresState *st,
+                           int *counter, int pass, hipStream_t s);
+void launch_gmres_solve_ls(GmresState *st, hipStream_t s);
+template <typename T>
+void launch_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresState *st, T *x, hipStream_t s);
+template <typename T>
+void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out, int *counter, hipStream_t s);
+// y += sign * alpha[0] / alpha[1] * x
+template <typename T>
+void launch_axpy_ratio(int64_t n, const double *alpha, double sign, const T *x, T *y, hipStream_t s);
+template <typename T>
+void launch_fill(int64_t n, T v, T *x, hipStream_t s);
+template <typename T>
+void launch_copy(int64_t n, const T *x, T *y, hipStream_t s);
+
+// device-resident GMRES scalars
+struct GmresState {
+  double H[(kMaxRestartH + 1) * kMaxRestartH];
+  double h1[kMaxRestartH + 1];
+  double h2[kMaxRestartH + 1];
+  double cs[kMaxRestartH], sn[kMaxRestartH], g[kMaxRestartH + 1], y[kMaxRestartH];
+  double beta;        // norm of the cycle's initial residual
+  double bnorm;       // norm of the right-hand side
+  double inv_hnext;   // 1 / H[j+1][j]
+  double res;         // least-squares residual estimate (absolute)
+  double rtol;
+  int j;              // current column
+  int done;           // converged or broke down
+  int nan;            // non-finite value met
+  int pad;
+};
+
+}  // namespace hho

@@ -1,0 +1,674 @@
+// Local HHO-dp operators on the host: quadrature, hierarchical orthonormal
+// bases, scalar potential reconstruction (Section 2.2.1), face-residual
+// stabilisation (Section 2.2.3), symmetric Nitsche terms and the
+// pressure-velocity coupling of the local residuals (Section 2.3.1), written as
+// the local algebraic system of eq. def:HHOAB.
+//
+// Readings taken where the paper is silent or inconsistent:
+//  * the Dirichlet datum multiplies (n . grad P v) with the sign that keeps the
+//    symmetric Nitsche terms consistent: the residual holds
+//    -(u_F - g_D).(n . grad P v) + eta/h_F (u_F - g_D).v_F;
+//  * g_N is the traction (grad u - p I) n;
+//  * the coupling is evaluated in the integrated-by-parts form
+//    (B v, q) = sum_c (v_T,c, d_c q)_T - sum_{F not Dirichlet} (v_F . n_TF, q)_F,
+//    which equals the three terms of eq. HHOdiscrCNT for exact quadrature.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <functional>
+
+#include "internal.h"
+
+namespace hho {
+namespace {
+
+// ---------------------------------------------------------------- quadrature
+struct Rule {
+  std::vector<double> x;  // [n*3]
+  std::vector<double> w;
+  int n() const { return (int)w.size(); }
+  void add(const double *p, double wt) {
+    x.insert(x.end(), p, p + 3);
+    w.push_back(wt);
+  }
+};
+
+// Gauss-Legendre on [0,1]: roots z of the Legendre polynomial P_n by Newton
+// iteration from Chebyshev-like guesses, weights 2/((1-z^2) P_n'(z)^2) halved.
+void gauss01(int n, std::vector<double> &t, std::vector<double> &w) {
+  t.assign(n, 0.0);
+  w.assign(n, 0.0);
+  for (int i = 0; i < n; ++i) {
+    double z = -std::cos(M_PI * (i + 0.75) / (n + 0.5));
+    double p0 = 1, p1 = z, dp = 1;
+    for (int it = 0; it < 100; ++it) {
+      p0 = 1;
+      p1 = z;
+      for (int j = 2; j <= n; ++j) {
+        double p2 = ((2.0 * j - 1) * z * p1 - (j - 1.0) * p0) / j;
+        p0 = p1;
+        p1 = p2;
+      }
+      if (n == 1) {
+        p1 = z;
+        p0 = 1;
+      }
+      dp = n * (z * p1 - p0) / (z * z - 1);
+      double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-17) break;
+    }
+    p0 = 1;
+    p1 = z;
+    for (int j = 2; j <= n; ++j) {
+      double p2 = ((2.0 * j - 1) * z * p1 - (j - 1.0) * p0) / j;
+      p0 = p1;
+      p1 = p2;
+    }
+    if (n == 1) p0 = 1;
+    dp = n * (z * p1 - p0) / (z * z - 1);
+    t[i] = 0.5 * (1 + z);
+    w[i] = 1.0 / ((1 - z * z) * dp * dp);
+  }
+}
+
+struct GL {
+  std::vector<double> t, w;
+};
+const GL &gl(int n) {
+  static GL cache[40];
+  static bool init[40] = {false};
+  if (n < 1) n = 1;
+  if (n >= 40) fail(HHO_E_INVALID_ARG, "quadrature degree too high");
+  if (!init[n]) {
+    gauss01(n, cache[n].t, cache[n].w);
+    init[n] = true;
+  }
+  return cache[n];
+}
+
+void rule_segment(const double *a, const double *b, int deg, Rule &R) {
+  const GL &g = gl((deg + 2) / 2);
+  double L = std::sqrt((b[0] - a[0]) * (b[0] - a[0]) + (b[1] - a[1]) * (b[1] - a[1]) + (b[2] - a[2]) * (b[2] - a[2]));
+  for (size_t i = 0; i < g.t.size(); ++i) {
+    double p[3];
+    for (int q = 0; q < 3; ++q) p[q] = a[q] + g.t[i] * (b[q] - a[q]);
+    R.add(p, g.w[i] * L);
+  }
+}
+
+// collapsed product rule x = v0 + s (v1 - v0) + s t (v2 - v1); |J| = s * |(v1-v0) x (v2-v1)|
+void rule_triangle(const double *v0, const double *v1, const double *v2, int deg, Rule &R) {
+  const GL &g = gl((deg + 3) / 2);
+  double e1[3], e2[3], c[3];
+  for (int q = 0; q < 3; ++q) {
+    e1[q] = v1[q] - v0[q];
+    e2[q] = v2[q] - v1[q];
+  }
+  c[0] = e1[1] * e2[2] - e1[2] * e2[1];
+  c[1] = e1[2] * e2[0] - e1[0] * e2[2];
+  c[2] = e1[0] * e2[1] - e1[1] * e2[0];
+  double J = std::sqrt(c[0] * c[0] + c[1] * c[1] + c[2] * c[2]);
+  for (size_t i = 0; i < g.t.size(); ++i)
+    for (size_t j = 0; j < g.t.size(); ++j) {
+      double s = g.t[i], t = g.t[j], p[3];
+      for (int q = 0; q < 3; ++q) p[q] = v0[q] + s * (e1[q] + t * e2[q]);
+      R.add(p, g.w[i] * g.w[j] * s * J);
+    }
+}
+
+void rule_tet(const double *v0, const double *v1, const double *v2, const double *v3, int deg, Rule &R) {
+  const GL &g = gl((deg + 4) / 2);
+  double e1[3], e2[3], e3[3];
+  for (int q = 0; q < 3; ++q) {
+    e1[q] = v1[q] - v0[q];
+    e2[q] = v2[q] - v1[q];
+    e3[q] = v3[q] - v2[q];
+  }
+  double det = e1[0] * (e2[1] * e3[2] - e2[2] * e3[1]) - e1[1] * (e2[0] * e3[2] - e2[2] * e3[0]) +
+               e1[2] * (e2[0] * e3[1] - e2[1] * e3[0]);
+  det = std::fabs(det);
+  size_t n = g.t.size();
+  for (size_t i = 0; i < n; ++i)
+    for (size_t j = 0; j < n; ++j)
+      for (size_t l = 0; l < n; ++l) {
+        double s = g.t[i], t = g.t[j], u = g.t[l], p[3];
+        for (int q = 0; q < 3; ++q) p[q] = v0[q] + s * (e1[q] + t * (e2[q] + u * e3[q]));
+        R.add(p, g.w[i] * g.w[j] * g.w[l] * s * s * t * det);
+      }
+}
+
+void rule_box(const double *lo, const double *hi, int deg, Rule &R) {
+  const GL &g = gl((deg + 2) / 2);
+  size_t n = g.t.size();
+  double vol = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2]);
+  for (size_t i = 0; i < n; ++i)
+    for (size_t j = 0; j < n; ++j)
+      for (size_t l = 0; l < n; ++l) {
+        double p[3] = {lo[0] + g.t[i] * (hi[0] - lo[0]), lo[1] + g.t[j] * (hi[1] - lo[1]), lo[2] + g.t[l] * (hi[2] - lo[2])};
+        R.add(p, g.w[i] * g.w[j] * g.w[l] * vol);
+      }
+}
+
+const double *vx(const hho_mesh *m, int64_t v, double *buf) {
+  for (int q = 0; q < 3; ++q) buf[q] = q < m->dim ? m->verts[v * m->dim + q] : 0.0;
+  return buf;
+}
+
+void cell_rule(const hho_mesh *m, int64_t c, int deg, Rule &R) {
+  double a[3], b[3], d0[3], apex[3];
+  if (m->dim == 2) {
+    const auto &ring = m->cring[c];  // counter-clockwise, convex: fan from the first vertex
+    vx(m, ring[0], a);
+    for (size_t i = 1; i + 1 < ring.size(); ++i) rule_triangle(a, vx(m, ring[i], b), vx(m, ring[i + 1], d0), deg, R);
+    return;
+  }
+  if (m->cbox[c]) {
+    rule_box(&m->clo[3 * c], &m->chi[3 * c], deg, R);
+    return;
+  }
+  std::vector<int64_t> vs;
+  for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e) {
+    int64_t f = m->cface[e];
+    for (int64_t t = m->fptr[f]; t < m->fptr[f + 1]; ++t) vs.push_back(m->fvtx[t]);
+  }
+  std::sort(vs.begin(), vs.end());
+  vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+  apex[0] = apex[1] = apex[2] = 0;
+  for (int64_t v : vs) {
+    vx(m, v, a);
+    for (int q = 0; q < 3; ++q) apex[q] += a[q] / vs.size();
+  }
+  for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e) {
+    int64_t f = m->cface[e];
+    const int64_t *fv = &m->fvtx[m->fptr[f]];
+    int nvf = (int)(m->fptr[f + 1] - m->fptr[f]);
+    double p0[3];
+    vx(m, fv[0], p0);
+    for (int i = 1; i + 1 < nvf; ++i) rule_tet(apex, p0, vx(m, fv[i], a), vx(m, fv[i + 1], b), deg, R);
+  }
+}
+
+void face_rule(const hho_mesh *m, int64_t f, int deg, Rule &R) {
+  const int64_t *fv = &m->fvtx[m->fptr[f]];
+  int nvf = (int)(m->fptr[f + 1] - m->fptr[f]);
+  double a[3], b[3], c[3];
+  if (m->dim == 2) {
+    rule_segment(vx(m, fv[0], a), vx(m, fv[1], b), deg, R);
+    return;
+  }
+  vx(m, fv[0], a);
+  for (int i = 1; i + 1 < nvf; ++i) rule_triangle(a, vx(m, fv[i], b), vx(m, fv[i + 1], c), deg, R);
+}
+
+// ---------------------------------------------------------------- bases
+// exponents of the monomials of total degree <= deg, graded, first exponent decreasing
+std::vector<int> exponents(int nvar, int deg) {
+  std::vector<int> E;
+  for (int n = 0; n <= deg; ++n) {
+    if (nvar == 1) {
+      E.push_back(n);
+    } else if (nvar == 2) {
+      for (int a = n; a >= 0; --a) {
+        E.push_back(a);
+        E.push_back(n - a);
+      }
+    } else {
+      for (int a = n; a >= 0; --a)
+        for (int b = n - a; b >= 0; --b) {
+          E.push_back(a);
+          E.push_back(b);
+          E.push_back(n - a - b);
+        }
+    }
+  }
+  return E;
+}
+
+inline double ipow(double x, int e) {
+  double r = 1;
+  for (int i = 0; i < e; ++i) r *= x;
+  return r;
+}
+
+// Values M[q*N + i] of the monomials at the local coordinates xi[q*nvar + v].
+void eval_monomials(const std::vector<int> &E, int nvar, const double *xi, int nq, double *M) {
+  int N = (int)E.size() / nvar;
+  for (int q = 0; q < nq; ++q)
+    for (int i = 0; i < N; ++i) {
+      double v = 1;
+      for (int a = 0; a < nvar; ++a) v *= ipow(xi[q * nvar + a], E[i * nvar + a]);
+      M[q * N + i] = v;
+    }
+}
+
+// Gram-Schmidt (modified, two passes) of the columns of M [nq x N] in the
+// weighted inner product; returns C [N x N] with phi_i = sum_j C[i][j] m_j.
+void gram_schmidt(const double *M, const double *w, int nq, int N, std::vector<double> &C) {
+  C.assign((size_t)N * N, 0.0);
+  std::vector<double> V((size_t)nq * N), v(nq), c(N);
+  for (int i = 0; i < N; ++i) {
+    for (int q = 0; q < nq; ++q) v[q] = M[q * N + i];
+    std::fill(c.begin(), c.end(), 0.0);
+    c[i] = 1;
+    for (int pass = 0; pass < 2; ++pass)
+      for (int j = 0; j < i; ++j) {
+        double r = 0;
+        for (int q = 0; q < nq; ++q) r += w[q] * v[q] * V[(size_t)q * N + j];
+        for (int q = 0; q < nq; ++q) v[q] -= r * V[(size_t)q * N + j];
+        for (int t = 0; t < N; ++t) c[t] -= r * C[(size_t)j * N + t];
+      }
+    double nv = 0;
+    for (int q = 0; q < nq; ++q) nv += w[q] * v[q] * v[q];
+    nv = std::sqrt(nv);
+    if (!(nv > 0)) fail(HHO_E_MESH, "basis: degenerate element (Gram-Schmidt breakdown)");
+    for (int q = 0; q < nq; ++q) V[(size_t)q * N + i] = v[q] / nv;
+    for (int t = 0; t < N; ++t) C[(size_t)i * N + t] = c[t] / nv;
+  }
+}
+
+struct CellBasis {
+  int d, N;
+  double x0[3], h;
+  std::vector<int> E;
+  std::vector<double> C;  // [N x N]
+  // phi [nq x N]
+  void values(const double *x, int nq, double *phi) const {
+    std::vector<double> xi((size_t)nq * d), M((size_t)nq * N);
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a) xi[q * d + a] = (x[3 * q + a] - x0[a]) / h;
+    eval_monomials(E, d, xi.data(), nq, M.data());
+    for (int q = 0; q < nq; ++q)
+      for (int i = 0; i < N; ++i) {
+        double s = 0;
+        for (int j = 0; j <= i; ++j) s += C[(size_t)i * N + j] * M[(size_t)q * N + j];
+        phi[(size_t)q * N + i] = s;
+      }
+  }
+  // grad [nq x N x d]
+  void grads(const double *x, int nq, double *g) const {
+    std::vector<double> xi((size_t)nq * d), dm((size_t)N);
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a) xi[q * d + a] = (x[3 * q + a] - x0[a]) / h;
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a) {
+        for (int j = 0; j < N; ++j) {
+          int ea = E[j * d + a];
+          if (ea == 0) {
+            dm[j] = 0;
+            continue;
+          }
+          double v = ea / h;
+          for (int b = 0; b < d; ++b) v *= ipow(xi[q * d + b], E[j * d + b] - (b == a ? 1 : 0));
+          dm[j] = v;
+        }
+        for (int i = 0; i < N; ++i) {
+          double s = 0;
+          for (int j = 0; j <= i; ++j) s += C[(size_t)i * N + j] * dm[j];
+          g[((size_t)q * N + i) * d + a] = s;
+        }
+      }
+  }
+};
+
+struct FaceBasis {
+  int nvar, N;
+  double x0[3], t1[3], t2[3], h;
+  std::vector<int> E;
+  std::vector<double> C;
+  void values(const double *x, int nq, double *psi) const {
+    std::vector<double> xi((size_t)nq * nvar), M((size_t)nq * N);
+    for (int q = 0; q < nq; ++q) {
+      double r[3] = {x[3 * q] - x0[0], x[3 * q + 1] - x0[1], x[3 * q + 2] - x0[2]};
+      xi[q * nvar] = (r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2]) / h;
+      if (nvar == 2) xi[q * nvar + 1] = (r[0] * t2[0] + r[1] * t2[1] + r[2] * t2[2]) / h;
+    }
+    eval_monomials(E, nvar, xi.data(), nq, M.data());
+    for (int q = 0; q < nq; ++q)
+      for (int i = 0; i < N; ++i) {
+        double s = 0;
+        for (int j = 0; j <= i; ++j) s += C[(size_t)i * N + j] * M[(size_t)q * N + j];
+        psi[(size_t)q * N + i] = s;
+      }
+  }
+};
+
+// ---------------------------------------------------------------- dense helpers
+// in-place Cholesky of the SPD matrix A [n x n] (lower triangle); false if not SPD
+bool cholesky(double *A, int n, int lda) {
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * lda + j];
+    for (int t = 0; t < j; ++t) s -= A[j * lda + t] * A[j * lda + t];
+    if (!(s > 0)) return false;
+    double ljj = std::sqrt(s);
+    A[j * lda + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[i * lda + j];
+      for (int t = 0; t < j; ++t) v -= A[i * lda + t] * A[j * lda + t];
+      A[i * lda + j] = v / ljj;
+    }
+  }
+  return true;
+}
+// solve L L^T X = B for nrhs columns of B [n x nrhs] (row-major, ldb)
+void chol_solve(const double *L, int n, int lda, double *B, int nrhs, int ldb) {
+  for (int r = 0; r < nrhs; ++r) {
+    for (int i = 0; i < n; ++i) {
+      double v = B[i * ldb + r];
+      for (int t = 0; t < i; ++t) v -= L[i * lda + t] * B[t * ldb + r];
+      B[i * ldb + r] = v / L[i * lda + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = B[i * ldb + r];
+      for (int t = i + 1; t < n; ++t) v -= L[t * lda + i] * B[t * ldb + r];
+      B[i * ldb + r] = v / L[i * lda + i];
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- driver
+void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_fn, hho_field_fn gD_fn,
+                 hho_field_fn gN_fn, void *ctx, LocalData *out) {
+  const int d = m->dim;
+  const int N1 = dim_poly(d, k + 1), nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
+  out->k = k;
+  out->d = d;
+  out->nT = nT;
+  out->nF = nF;
+  out->N1 = N1;
+  const int64_t nc = m->nc, nf = m->nf;
+
+  // quadrature rules
+  std::vector<Rule> crule(nc), frule(nf);
+  parallel_for(nc, [&](int64_t c) { cell_rule(m, c, qdeg, crule[c]); });
+  parallel_for(nf, [&](int64_t f) { face_rule(m, f, qdeg, frule[f]); });
+
+  // face bases (shared by the two cells of a face)
+  std::vector<FaceBasis> fb(nf);
+  std::vector<std::vector<double>> fpsi(nf);
+  const std::vector<int> EF = exponents(d - 1, k);
+  parallel_for(nf, [&](int64_t f) {
+    FaceBasis &B = fb[f];
+    B.nvar = d - 1;
+    B.N = nF;
+    B.E = EF;
+    B.h = m->fdiam[f];
+    for (int q = 0; q < 3; ++q) {
+      B.x0[q] = m->fcen[3 * f + q];
+      B.t1[q] = m->ft1[3 * f + q];
+      B.t2[q] = m->ft2[3 * f + q];
+    }
+    const Rule &R = frule[f];
+    int nq = R.n();
+    std::vector<double> xi((size_t)nq * B.nvar), M((size_t)nq * nF);
+    for (int q = 0; q < nq; ++q) {
+      const double *x = &R.x[3 * q];
+      double r[3] = {x[0] - B.x0[0], x[1] - B.x0[1], x[2] - B.x0[2]};
+      xi[q * B.nvar] = (r[0] * B.t1[0] + r[1] * B.t1[1] + r[2] * B.t1[2]) / B.h;
+      if (B.nvar == 2) xi[q * B.nvar + 1] = (r[0] * B.t2[0] + r[1] * B.t2[1] + r[2] * B.t2[2]) / B.h;
+    }
+    eval_monomials(B.E, B.nvar, xi.data(), nq, M.data());
+    gram_schmidt(M.data(), R.w.data(), nq, nF, B.C);
+    fpsi[f].resize((size_t)nq * nF);
+    B.values(R.x.data(), nq, fpsi[f].data());
+  });
+
+  // data at the quadrature points: body force on cells, Dirichlet / Neumann data on faces
+  std::vector<int64_t> coff(nc + 1, 0), dof_(nf + 1, 0), nof(nf + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + crule[c].n();
+  for (int64_t f = 0; f < nf; ++f) {
+    dof_[f + 1] = dof_[f] + (m->fbc[f] == HHO_FACE_DIRICHLET ? frule[f].n() : 0);
+    nof[f + 1] = nof[f] + (m->fbc[f] == HHO_FACE_NEUMANN ? frule[f].n() : 0);
+  }
+  std::vector<double> fx(coff[nc] * d), fval(coff[nc] * d, 0.0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int q = 0; q < crule[c].n(); ++q)
+      for (int a = 0; a < d; ++a) fx[(coff[c] + q) * d + a] = crule[c].x[3 * q + a];
+  if (f_fn && coff[nc]) f_fn(fx.data(), coff[nc], nullptr, fval.data(), ctx);
+  std::vector<double> dx(dof_[nf] * d), dn(dof_[nf] * d), dval(dof_[nf] * d, 0.0);
+  std::vector<double> nx(nof[nf] * d), nn(nof[nf] * d), nval(nof[nf] * d, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    if (m->fbc[f] == HHO_FACE_INTERIOR) continue;
+    int64_t c = m->fcell[0][f];
+    double sg = m->csign[m->cptr[c] + m->flocal[0][f]];
+    bool isD = m->fbc[f] == HHO_FACE_DIRICHLET;
+    int64_t o = isD ? dof_[f] : nof[f];
+    for (int q = 0; q < frule[f].n(); ++q)
+      for (int a = 0; a < d; ++a) {
+        (isD ? dx : nx)[(o + q) * d + a] = frule[f].x[3 * q + a];
+        (isD ? dn : nn)[(o + q) * d + a] = sg * m->fnrm[3 * f + a];
+      }
+  }
+  if (gD_fn && dof_[nf]) gD_fn(dx.data(), dof_[nf], dn.data(), dval.data(), ctx);
+  if (nof[nf]) {
+    if (!gN_fn) fail(HHO_E_INVALID_ARG, "set_data: the mesh has Neumann faces but gN is NULL");
+    gN_fn(nx.data(), nof[nf], nn.data(), nval.data(), ctx);
+  }
+
+  // record layout
+  out->off.assign(nc + 1, 0);
+  out->nloc.assign(nc, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
+    int nloc = nT + nfc * nF;
+    out->nloc[c] = nloc;
+    out->off[c + 1] = out->off[c] + (int64_t)nloc * nloc + (int64_t)d * nT * nloc + (int64_t)d * nloc + nT;
+  }
+  out->rec.assign(out->off[nc], 0.0);
+  const std::vector<int> EC = exponents(d, k + 1);
+
+  parallel_for(nc, [&](int64_t c) {
+    const Rule &R = crule[c];
+    const int nq = R.n();
+    const int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
+    const int nloc = nT + nfc * nF;
+    CellBasis cb;
+    cb.d = d;
+    cb.N = N1;
+    cb.E = EC;
+    cb.h = m->cdiam[c];
+    for (int q = 0; q < 3; ++q) cb.x0[q] = m->ccen[3 * c + q];
+    {
+      std::vector<double> xi((size_t)nq * d), M((size_t)nq * N1);
+      for (int q = 0; q < nq; ++q)
+        for (int a = 0; a < d; ++a) xi[q * d + a] = (R.x[3 * q + a] - cb.x0[a]) / cb.h;
+      eval_monomials(cb.E, d, xi.data(), nq, M.data());
+      gram_schmidt(M.data(), R.w.data(), nq, N1, cb.C);
+    }
+    std::vector<double> phi((size_t)nq * N1), gphi((size_t)nq * N1 * d);
+    cb.values(R.x.data(), nq, phi.data());
+    cb.grads(R.x.data(), nq, gphi.data());
+
+    // stiffness K_ij = (grad phi_i, grad phi_j)_T
+    std::vector<double> K((size_t)N1 * N1, 0.0);
+    for (int q = 0; q < nq; ++q)
+      for (int i = 1; i < N1; ++i)
+        for (int j = 1; j <= i; ++j) {
+          double s = 0;
+          for (int a = 0; a < d; ++a) s += gphi[((size_t)q * N1 + i) * d + a] * gphi[((size_t)q * N1 + j) * d + a];
+          K[(size_t)i * N1 + j] += R.w[q] * s;
+        }
+    for (int i = 1; i < N1; ++i)
+      for (int j = 1; j < i; ++j) K[(size_t)j * N1 + i] = K[(size_t)i * N1 + j];
+
+    // reconstruction right-hand side G [N1 x nloc]
+    std::vector<double> G((size_t)N1 * nloc, 0.0);
+    for (int i = 0; i < N1; ++i)
+      for (int j = 0; j < nT; ++j) G[(size_t)i * nloc + j] = K[(size_t)i * N1 + j];
+    struct FaceLoc {
+      int64_t f;
+      double n[3];
+      int nq;
+      std::vector<double> phif, gn;  // [nqf x N1]
+    };
+    std::vector<FaceLoc> FL(nfc);
+    for (int i = 0; i < nfc; ++i) {
+      int64_t e = m->cptr[c] + i, f = m->cface[e];
+      FaceLoc &L = FL[i];
+      L.f = f;
+      for (int q = 0; q < 3; ++q) L.n[q] = m->csign[e] * m->fnrm[3 * f + q];
+      const Rule &Rf = frule[f];
+      L.nq = Rf.n();
+      L.phif.resize((size_t)L.nq * N1);
+      L.gn.resize((size_t)L.nq * N1);
+      cb.values(Rf.x.data(), L.nq, L.phif.data());
+      std::vector<double> g((size_t)L.nq * N1 * d);
+      cb.grads(Rf.x.data(), L.nq, g.data());
+      for (int q = 0; q < L.nq; ++q)
+        for (int t = 0; t < N1; ++t) {
+          double s = 0;
+          for (int a = 0; a < d; ++a) s += g[((size_t)q * N1 + t) * d + a] * L.n[a];
+          L.gn[(size_t)q * N1 + t] = s;
+        }
+      const double *psi = fpsi[f].data();
+      for (int q = 0; q < L.nq; ++q) {
+        double w = Rf.w[q];
+        for (int t = 1; t < N1; ++t) {
+          double gw = w * L.gn[(size_t)q * N1 + t];
+          for (int j = 0; j < nT; ++j) G[(size_t)t * nloc + j] -= gw * L.phif[(size_t)q * N1 + j];
+          for (int j = 0; j < nF; ++j) G[(size_t)t * nloc + nT + i * nF + j] += gw * psi[(size_t)q * nF + j];
+        }
+      }
+    }
+    // R = [e_0 ; K11^{-1} G1]
+    std::vector<double> Rm((size_t)N1 * nloc, 0.0);
+    Rm[0] = 1.0;
+    {
+      int n1 = N1 - 1;
+      std::vector<double> L((size_t)n1 * n1);
+      for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j) L[(size_t)i * n1 + j] = K[(size_t)(i + 1) * N1 + (j + 1)];
+      if (!cholesky(L.data(), n1, n1))
+        fail(HHO_E_LOCAL_SINGULAR, "reconstruction stiffness not SPD in cell " + std::to_string(c));
+      for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < nloc; ++j) Rm[(size_t)(i + 1) * nloc + j] = G[(size_t)(i + 1) * nloc + j];
+      chol_solve(L.data(), n1, n1, &Rm[nloc], nloc, nloc);
+    }
+
+    double *rec = &out->rec[out->off[c]];
+    double *A = rec;
+    double *Bm = A + (size_t)nloc * nloc;
+    double *ru = Bm + (size_t)d * nT * nloc;
+    double *rp = ru + (size_t)d * nloc;
+    // consistency: R^T K R = R1^T G1 (K R1 = G1 on the non-constant rows)
+    for (int a = 0; a < nloc; ++a)
+      for (int b = 0; b < nloc; ++b) {
+        double s = 0;
+        for (int t = 1; t < N1; ++t) s += Rm[(size_t)t * nloc + a] * G[(size_t)t * nloc + b];
+        A[(size_t)a * nloc + b] = s;
+      }
+    // symmetrise the consistency term
+    for (int a = 0; a < nloc; ++a)
+      for (int b = 0; b < a; ++b) {
+        double s = 0.5 * (A[(size_t)a * nloc + b] + A[(size_t)b * nloc + a]);
+        A[(size_t)a * nloc + b] = A[(size_t)b * nloc + a] = s;
+      }
+
+    std::vector<double> Pi((size_t)nF * N1), D((size_t)nF * nloc), Nn((size_t)nF * N1);
+    for (int i = 0; i < nfc; ++i) {
+      const FaceLoc &L = FL[i];
+      const int64_t f = L.f;
+      const Rule &Rf = frule[f];
+      const double *psi = fpsi[f].data();
+      const double hF = m->fdiam[f];
+      const int bc = m->fbc[f];
+      // Pi[j][t] = (psi_j, phi_t)_F ; Nn[j][t] = (psi_j, grad phi_t . n)_F
+      std::fill(Pi.begin(), Pi.end(), 0.0);
+      std::fill(Nn.begin(), Nn.end(), 0.0);
+      for (int q = 0; q < L.nq; ++q)
+        for (int j = 0; j < nF; ++j) {
+          double wp = Rf.w[q] * psi[(size_t)q * nF + j];
+          for (int t = 0; t < N1; ++t) {
+            Pi[(size_t)j * N1 + t] += wp * L.phif[(size_t)q * N1 + t];
+            Nn[(size_t)j * N1 + t] += wp * L.gn[(size_t)q * N1 + t];
+          }
+        }
+      // face residual D = E_F - Pi R - Pi_k (E_T - R_k)
+      for (int j = 0; j < nF; ++j)
+        for (int b = 0; b < nloc; ++b) {
+          double s = (b == nT + i * nF + j) ? 1.0 : 0.0;
+          for (int t = 0; t < N1; ++t) s -= Pi[(size_t)j * N1 + t] * Rm[(size_t)t * nloc + b];
+          for (int t = 0; t < nT; ++t) {
+            double et = (b == t) ? 1.0 : 0.0;
+            s -= Pi[(size_t)j * N1 + t] * (et - Rm[(size_t)t * nloc + b]);
+          }
+          D[(size_t)j * nloc + b] = s;
+        }
+      for (int a = 0; a < nloc; ++a)
+        for (int b = 0; b < nloc; ++b) {
+          double s = 0;
+          for (int j = 0; j < nF; ++j) s += D[(size_t)j * nloc + a] * D[(size_t)j * nloc + b];
+          A[(size_t)a * nloc + b] += s / hF;
+        }
+      if (bc == HHO_FACE_DIRICHLET) {
+        // -(n.grad P u, v_F) - (u_F, n.grad P v) + eta/h (u_F, v_F)
+        std::vector<double> NR((size_t)nF * nloc, 0.0);
+        for (int j = 0; j < nF; ++j)
+          for (int b = 0; b < nloc; ++b) {
+            double s = 0;
+            for (int t = 0; t < N1; ++t) s += Nn[(size_t)j * N1 + t] * Rm[(size_t)t * nloc + b];
+            NR[(size_t)j * nloc + b] = s;
+          }
+        for (int j = 0; j < nF; ++j) {
+          int r = nT + i * nF + j;
+          for (int b = 0; b < nloc; ++b) {
+            A[(size_t)r * nloc + b] -= NR[(size_t)j * nloc + b];
+            A[(size_t)b * nloc + r] -= NR[(size_t)j * nloc + b];
+          }
+          A[(size_t)r * nloc + r] += eta / hF;
+        }
+        // data: -(g_D, n.grad P v) + eta/h (g_D, v_F); mass: (g_D . n, q)
+        const double *g = &dval[dof_[f] * d];
+        for (int cc = 0; cc < d; ++cc) {
+          std::vector<double> gt(N1, 0.0), gp(nF, 0.0);
+          for (int q = 0; q < L.nq; ++q) {
+            double wg = Rf.w[q] * g[q * d + cc];
+            for (int t = 0; t < N1; ++t) gt[t] += wg * L.gn[(size_t)q * N1 + t];
+            for (int j = 0; j < nF; ++j) gp[j] += wg * psi[(size_t)q * nF + j];
+          }
+          for (int b = 0; b < nloc; ++b) {
+            double s = 0;
+            for (int t = 0; t < N1; ++t) s += Rm[(size_t)t * nloc + b] * gt[t];
+            ru[cc * nloc + b] -= s;
+          }
+          for (int j = 0; j < nF; ++j) ru[cc * nloc + nT + i * nF + j] += eta / hF * gp[j];
+        }
+        for (int q = 0; q < L.nq; ++q) {
+          double gn = 0;
+          for (int a = 0; a < d; ++a) gn += g[q * d + a] * L.n[a];
+          for (int t = 0; t < nT; ++t) rp[t] += Rf.w[q] * gn * L.phif[(size_t)q * N1 + t];
+        }
+      } else if (bc == HHO_FACE_NEUMANN) {
+        const double *g = &nval[nof[f] * d];
+        for (int cc = 0; cc < d; ++cc)
+          for (int q = 0; q < L.nq; ++q)
+            for (int j = 0; j < nF; ++j) ru[cc * nloc + nT + i * nF + j] += Rf.w[q] * g[q * d + cc] * psi[(size_t)q * nF + j];
+      }
+      // coupling, face part: -(v_F . n, q)_F on non-Dirichlet faces
+      if (bc != HHO_FACE_DIRICHLET)
+        for (int cc = 0; cc < d; ++cc)
+          for (int t = 0; t < nT; ++t)
+            for (int j = 0; j < nF; ++j) {
+              double s = 0;
+              for (int q = 0; q < L.nq; ++q) s += Rf.w[q] * psi[(size_t)q * nF + j] * L.phif[(size_t)q * N1 + t];
+              Bm[((size_t)cc * nT + t) * nloc + nT + i * nF + j] -= L.n[cc] * s;
+            }
+    }
+    // coupling, cell part: (v_T,c, d_c q)_T ; body force (f_c, v_T)
+    for (int q = 0; q < nq; ++q) {
+      double w = R.w[q];
+      for (int cc = 0; cc < d; ++cc) {
+        double fv = fval[(coff[c] + q) * d + cc];
+        for (int j = 0; j < nT; ++j) {
+          double pj = w * phi[(size_t)q * N1 + j];
+          ru[cc * nloc + j] += fv * pj;
+          for (int t = 0; t < nT; ++t) Bm[((size_t)cc * nT + t) * nloc + j] += pj * gphi[((size_t)q * N1 + t) * d + cc];
+        }
+      }
+    }
+  });
+}
+
+}  // namespace hho

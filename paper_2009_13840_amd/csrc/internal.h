@@ -1,0 +1,68 @@
+// Internal declarations of the HHO p-multilevel library (not part of the ABI).
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+#include "../../include/hho_pmg.h"
+
+namespace hho {
+
+// ---------------------------------------------------------------- errors
+struct Error {
+  int code;
+  std::string msg;
+};
+void set_error(const std::string &msg);
+[[noreturn]] void fail(int code, const std::string &msg);
+
+// ---------------------------------------------------------------- small utils
+inline int64_t binom(int n, int k) {
+  if (k < 0 || k > n) return 0;
+  int64_t r = 1;
+  for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+  return r;
+}
+// dim P^deg in `nvar` variables
+inline int dim_poly(int nvar, int deg) { return deg < 0 ? 0 : (int)binom(deg + nvar, nvar); }
+
+void parallel_for(int64_t n, const std::function<void(int64_t)> &fn);
+
+}  // namespace hho
+
+// ---------------------------------------------------------------- mesh
+struct hho_mesh {
+  int dim = 0;
+  int64_t nv = 0, nf = 0, nc = 0;
+  std::vector<double> verts;
+  std::vector<int64_t> fptr, fvtx, cptr, cface;
+  std::vector<int8_t> fbc;
+  // topology
+  std::vector<int64_t> fcell[2];    // adjacent cells, -1 if none
+  std::vector<int32_t> flocal[2];   // position of the face in the cell's face list
+  std::vector<double> csign;        // per cell_face entry: +1 if n_F points out of the cell
+  // geometry (xyz padded to 3)
+  std::vector<double> farea, fdiam, fcen, fnrm, ft1, ft2;
+  std::vector<double> cvol, cdiam, ccen, clo, chi;
+  std::vector<uint8_t> cbox;
+  std::vector<std::vector<int64_t>> cring;  // d=2: counter-clockwise vertex ring per cell
+  int max_faces = 0;
+  bool has_neumann = false;
+};
+
+namespace hho {
+void build_mesh(const hho_mesh_desc *d, hho_mesh *m);
+
+// Local HHO operators of every cell, packed per cell as
+//   [a (nloc*nloc) | B (d*nT*nloc) | rhs_u (d*nloc) | rhs_p (nT)]
+struct LocalData {
+  int k = 0, d = 0, nT = 0, nF = 0, N1 = 0;
+  std::vector<int64_t> off;   // [nc+1] record offsets (doubles)
+  std::vector<int32_t> nloc;  // [nc]
+  std::vector<double> rec;
+};
+void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f, hho_field_fn gD,
+                 hho_field_fn gN, void *ctx, LocalData *out);
+}  // namespace hho

@@ -1,0 +1,607 @@
+// Setup kernels: static condensation (eqs. ST.1 / ST.2), assembly of the
+// face-block operator (Section 4.2, last paragraph), recursive inheritance of
+// the coarse levels by sub-block extraction (Section 4.2), factorisation of the
+// smoother's cell patches, and the dense coarse inverse.  All FP64.
+#include <algorithm>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace hho {
+namespace {
+
+// ------------------------------------------------------------ block dense helpers
+// In-place lower Cholesky of A (n x n, leading dimension lda), block-cooperative.
+// Sets *bad when a pivot is not positive (the matrix is then left unusable).
+__device__ void blk_chol(double *A, int n, int lda, int *bad) {
+  for (int j = 0; j < n; ++j) {
+    if (threadIdx.x == 0) {
+      double v = A[j * lda + j];
+      if (!(v > 0.0)) {
+        *bad = 1;
+        v = 1.0;
+      }
+      A[j * lda + j] = sqrt(v);
+    }
+    __syncthreads();
+    const double ljj = A[j * lda + j];
+    for (int i = j + 1 + threadIdx.x; i < n; i += blockDim.x) A[i * lda + j] /= ljj;
+    __syncthreads();
+    const int r = n - j - 1;
+    for (int idx = threadIdx.x; idx < r * r; idx += blockDim.x) {
+      const int i = j + 1 + idx / r, k = j + 1 + idx % r;
+      if (k <= i) A[i * lda + k] -= A[i * lda + j] * A[k * lda + j];
+    }
+    __syncthreads();
+  }
+}
+
+// Forward substitution L y = b on ncol columns of B (column c at B + c*cs, rows
+// strided by rs), each column by one thread.
+__device__ void blk_fwd(const double *L, int n, int lda, double *B, int ncol, int64_t cs, int64_t rs) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    double *b = B + c * cs;
+    for (int i = 0; i < n; ++i) {
+      double v = b[i * rs];
+      for (int k = 0; k < i; ++k) v -= L[i * lda + k] * b[k * rs];
+      b[i * rs] = v / L[i * lda + i];
+    }
+  }
+}
+
+// X = (L L^T)^{-1} (n x n, leading dimension ldx), one column per thread.
+__device__ void blk_chol_inverse(const double *L, int n, int lda, double *X, int ldx) {
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    for (int i = 0; i < n; ++i) {
+      double v = (i == c) ? 1.0 : 0.0;
+      for (int k = 0; k < i; ++k) v -= L[i * lda + k] * X[k * ldx + c];
+      X[i * ldx + c] = v / L[i * lda + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+      double v = X[i * ldx + c];
+      for (int k = i + 1; k < n; ++k) v -= L[k * lda + i] * X[k * ldx + c];
+      X[i * ldx + c] = v / L[i * lda + i];
+    }
+  }
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ static condensation
+// One block per cell.  Record of the cell (host-built, eq. def:HHOAB):
+//   a [nloc][nloc] scalar viscous matrix (cell modes first, then faces),
+//   B [d][nT][nloc] coupling per component, ru [d][nloc], rp [nT].
+// With L the Cholesky factor of a_TT:
+//   W = L^{-1} a_Td, Y_c = L^{-1} B_c,TT^T, g_c = L^{-1} f_c,
+//   s = a_dd - W^T W                          (S_dd = s (x) I_d)
+//   C_c = B_c,dT^T - W^T Y_c                  (S_dT)
+//   S_TT = -sum_c Y_c^T Y_c
+// (the Schur complement of eq. ST.1).  v&p-cond eliminates the non-mean pressure
+// modes of this system as well (eq. ST.2): with Sigma = -S_TT[1:,1:] = L_s L_s^T
+// and Z = L_s^{-1} C[:,1:]^T, S_dd^{vp} = s (x) I_d + Z^T Z and the coupling to
+// the mean pressure is C[:,0].
+__global__ void __launch_bounds__(kBlock) k_condense(DTopo tp, int cond, int nT, int nF, const double *rec,
+                                                     const int64_t *roff, double *stage, double *cpl,
+                                                     double *spp, double *rhs_stage, double *rhs_p, int *err) {
+  extern __shared__ double lds[];
+  const int T = blockIdx.x;
+  const int d = tp.d;
+  const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+  const int m = nfc * nF;
+  const int nloc = nT + m;
+  const double *a = rec + roff[T];
+  const double *B = a + (int64_t)nloc * nloc;
+  const double *ru = B + (int64_t)d * nT * nloc;
+  const double *rp = ru + (int64_t)d * nloc;
+  // LDS: AT [nT][nloc] (L | W), Y [d][nT][nT], G [d][nT]
+  double *AT = lds;
+  double *Y = AT + nT * nloc;
+  double *G = Y + d * nT * nT;
+  double *ext = G + d * nT;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int i = threadIdx.x; i < nT * nloc; i += blockDim.x) AT[i] = a[i];
+  for (int i = threadIdx.x; i < d * nT * nT; i += blockDim.x) {
+    const int c = i / (nT * nT), t = (i / nT) % nT, q = i % nT;
+    Y[i] = B[((int64_t)c * nT + q) * nloc + t];  // B_c,TT^T
+  }
+  for (int i = threadIdx.x; i < d * nT; i += blockDim.x) G[i] = ru[(i / nT) * nloc + i % nT];
+  __syncthreads();
+  blk_chol(AT, nT, nloc, &bad);
+  __syncthreads();
+  // W (in place, columns nT..nloc-1 of AT), Y_c (columns q), g_c
+  blk_fwd(AT, nT, nloc, AT + nT, m, 1, nloc);
+  for (int c = 0; c < d; ++c) blk_fwd(AT, nT, nloc, Y + c * nT * nT, nT, 1, nT);
+  blk_fwd(AT, nT, nloc, G, d, nT, 1);
+  __syncthreads();
+  const double *W = AT + nT;  // W[t][j] = AT[t*nloc + nT + j]
+  const int64_t c0 = tp.cptr[T];
+
+  if (cond == 1) {
+    double *s = stage + tp.pairoff[T] * nF * nF;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int i = idx / m, j = idx % m;
+      double v = a[(int64_t)(nT + i) * nloc + nT + j];
+      for (int t = 0; t < nT; ++t) v -= W[t * nloc + i] * W[t * nloc + j];
+      s[idx] = v;
+    }
+    double *C = cpl + c0 * d * nF * nT;
+    for (int idx = threadIdx.x; idx < d * m * nT; idx += blockDim.x) {
+      const int row = idx / nT, q = idx % nT;
+      const int fi = row / (d * nF), c = (row / nF) % d, r = row % nF;
+      const int jl = fi * nF + r;
+      double v = B[((int64_t)c * nT + q) * nloc + nT + jl];
+      for (int t = 0; t < nT; ++t) v -= W[t * nloc + jl] * Y[(c * nT + t) * nT + q];
+      C[idx] = v;
+    }
+    double *P = spp + (int64_t)T * nT * nT;
+    for (int idx = threadIdx.x; idx < nT * nT; idx += blockDim.x) {
+      const int q = idx / nT, q2 = idx % nT;
+      double v = 0;
+      for (int c = 0; c < d; ++c)
+        for (int t = 0; t < nT; ++t) v -= Y[(c * nT + t) * nT + q] * Y[(c * nT + t) * nT + q2];
+      P[idx] = v;
+    }
+    double *rs = rhs_stage + c0 * d * nF;
+    for (int row = threadIdx.x; row < d * m; row += blockDim.x) {
+      const int fi = row / (d * nF), c = (row / nF) % d, r = row % nF;
+      const int jl = fi * nF + r;
+      double v = ru[(int64_t)c * nloc + nT + jl];
+      for (int t = 0; t < nT; ++t) v -= W[t * nloc + jl] * G[c * nT + t];
+      rs[row] = v;
+    }
+    for (int q = threadIdx.x; q < nT; q += blockDim.x) {
+      double v = rp[q];
+      for (int c = 0; c < d; ++c)
+        for (int t = 0; t < nT; ++t) v -= Y[(c * nT + t) * nT + q] * G[c * nT + t];
+      rhs_p[(int64_t)T * nT + q] = v;
+    }
+  } else {
+    // ext: Ct [nT][d*m] (C transposed), Sg [(nT-1)^2], rP [nT], h [nT-1]
+    const int dm = d * m, n1 = nT - 1;
+    double *Ct = ext;
+    double *Sg = Ct + nT * dm;
+    double *rP = Sg + n1 * n1;
+    double *h = rP + nT;
+    for (int idx = threadIdx.x; idx < dm * nT; idx += blockDim.x) {
+      const int row = idx / nT, q = idx % nT;
+      const int fi = row / (d * nF), c = (row / nF) % d, r = row % nF;
+      const int jl = fi * nF + r;
+      double v = B[((int64_t)c * nT + q) * nloc + nT + jl];
+      for (int t = 0; t < nT; ++t) v -= W[t * nloc + jl] * Y[(c * nT + t) * nT + q];
+      Ct[q * dm + row] = v;
+    }
+    for (int idx = threadIdx.x; idx < n1 * n1; idx += blockDim.x) {
+      const int q = 1 + idx / n1, q2 = 1 + idx % n1;
+      double v = 0;
+      for (int c = 0; c < d; ++c)
+        for (int t = 0; t < nT; ++t) v += Y[(c * nT + t) * nT + q] * Y[(c * nT + t) * nT + q2];
+      Sg[idx] = v;  // Sigma = -S_TT[1:,1:]
+    }
+    for (int q = threadIdx.x; q < nT; q += blockDim.x) {
+      double v = rp[q];
+      for (int c = 0; c < d; ++c)
+        for (int t = 0; t < nT; ++t) v -= Y[(c * nT + t) * nT + q] * G[c * nT + t];
+      rP[q] = v;
+    }
+    __syncthreads();
+    if (n1 > 0) {
+      blk_chol(Sg, n1, n1, &bad);
+      __syncthreads();
+      blk_fwd(Sg, n1, n1, Ct + dm, dm, 1, dm);      // Z = L_s^{-1} C[:,1:]^T (in place)
+      for (int i = threadIdx.x; i < n1; i += blockDim.x) h[i] = rP[1 + i];
+      __syncthreads();
+      blk_fwd(Sg, n1, n1, h, 1, 1, 1);             // h = L_s^{-1} rhs_P~
+      __syncthreads();
+    }
+    const double *Z = Ct + dm;
+    double *S = stage + tp.pairoff[T] * (int64_t)(d * nF) * (d * nF);
+    for (int idx = threadIdx.x; idx < dm * dm; idx += blockDim.x) {
+      const int row = idx / dm, col = idx % dm;
+      const int fi = row / (d * nF), c = (row / nF) % d, r = row % nF;
+      const int fj = col / (d * nF), c2 = (col / nF) % d, r2 = col % nF;
+      double v = 0;
+      if (c == c2) {
+        const int i = fi * nF + r, j = fj * nF + r2;
+        v = a[(int64_t)(nT + i) * nloc + nT + j];
+        for (int t = 0; t < nT; ++t) v -= W[t * nloc + i] * W[t * nloc + j];
+      }
+      for (int t = 0; t < n1; ++t) v += Z[t * dm + row] * Z[t * dm + col];
+      S[idx] = v;
+    }
+    double *bb = cpl + c0 * d * nF;
+    for (int row = threadIdx.x; row < dm; row += blockDim.x) bb[row] = Ct[row];
+    double *rs = rhs_stage + c0 * d * nF;
+    for (int row = threadIdx.x; row < dm; row += blockDim.x) {
+      const int fi = row / (d * nF), c = (row / nF) % d, r = row % nF;
+      const int jl = fi * nF + r;
+      double v = ru[(int64_t)c * nloc + nT + jl];
+      for (int t = 0; t < nT; ++t) v -= W[t * nloc + jl] * G[c * nT + t];
+      // eliminate the non-mean pressure rows: r_d + C~ Sigma^{-1} r_P~
+      for (int t = 0; t < n1; ++t) v += Z[t * dm + row] * h[t];
+      rs[row] = v;
+    }
+    if (threadIdx.x == 0) rhs_p[T] = rP[0];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
+}
+
+// ------------------------------------------------------------ assembly
+// Every face block (F, F') is the sum of the <= 2 cell blocks (T, i, j) with
+// F_i = F and F_j = F' (deterministic gather, no atomics).
+__global__ void k_assemble(DTopo tp, int cond, int nF, int64_t nnzb, const double *stage, double *bsr) {
+  const int d = tp.d;
+  const int bs = (cond == 1) ? nF : d * nF;
+  const int64_t total = nnzb * bs * bs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / (bs * bs);
+    const int rr = (int)(e % (bs * bs)) / bs, cc = (int)(e % bs);
+    double v = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int T = tp.blksrc[6 * b + 3 * s];
+      if (T < 0) continue;
+      const int i = tp.blksrc[6 * b + 3 * s + 1], j = tp.blksrc[6 * b + 3 * s + 2];
+      const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+      const int64_t dim = (int64_t)nfc * bs;
+      const double *S = stage + tp.pairoff[T] * bs * bs;
+      v += S[(i * bs + rr) * dim + j * bs + cc];
+    }
+    bsr[e] = v;
+  }
+}
+
+// Face part of the condensed right-hand side: sum of the two cells' contributions.
+__global__ void k_rhs_faces(DTopo tp, int nF, const double *rhs_stage, double *rhs) {
+  const int d = tp.d;
+  const int64_t total = (int64_t)tp.nf * d * nF;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int f = (int)(e / (d * nF));
+    const int cr = (int)(e % (d * nF));
+    double v = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int T = tp.fcell[2 * f + s];
+      if (T < 0) continue;
+      v += rhs_stage[((int64_t)tp.cptr[T] + tp.floc[2 * f + s]) * d * nF + cr];
+    }
+    rhs[e] = v;
+  }
+}
+
+// ------------------------------------------------------------ level inheritance
+// S^{l+1} = I S^l I^T with unit-diagonal restriction: keep the leading face
+// modes of every block and the leading pressure modes of every cell.
+__global__ void k_extract(DTopo tp, int cond, int64_t nnzb, int p0, int t0, int p1, int t1, const double *bsr0,
+                          const double *cpl0, const double *spp0, double *bsr1, double *cpl1, double *spp1) {
+  const int d = tp.d;
+  const int b0 = (cond == 1) ? p0 : d * p0, b1 = (cond == 1) ? p1 : d * p1;
+  const int64_t nb = nnzb * b1 * b1;
+  const int64_t ncpl = (cond == 1) ? tp.ncf * d * p1 * t1 : tp.ncf * d * p1;
+  const int64_t nspp = (cond == 1) ? (int64_t)tp.nc * t1 * t1 : 0;
+  const int64_t total = nb + ncpl + nspp;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nb) {
+      const int64_t b = e / (b1 * b1);
+      const int rr = (int)(e % (b1 * b1)) / b1, cc = (int)(e % b1);
+      int r0 = rr, c0 = cc;
+      if (cond != 1) {
+        r0 = (rr / p1) * p0 + rr % p1;
+        c0 = (cc / p1) * p0 + cc % p1;
+      }
+      bsr1[e] = bsr0[b * b0 * b0 + (int64_t)r0 * b0 + c0];
+    } else if (e < nb + ncpl) {
+      const int64_t x = e - nb;
+      if (cond == 1) {
+        const int64_t row = x / t1;  // (entry, c, r) with r < p1
+        const int q = (int)(x % t1);
+        const int64_t ec = row / p1;
+        const int r = (int)(row % p1);
+        cpl1[x] = cpl0[(ec * p0 + r) * t0 + q];
+      } else {
+        const int64_t ec = x / p1;
+        const int r = (int)(x % p1);
+        cpl1[x] = cpl0[ec * p0 + r];
+      }
+    } else {
+      const int64_t x = e - nb - ncpl;
+      const int64_t T = x / (t1 * t1);
+      const int q = (int)(x % (t1 * t1)) / t1, q2 = (int)(x % t1);
+      spp1[x] = spp0[T * t0 * t0 + (int64_t)q * t0 + q2];
+    }
+  }
+}
+
+// ------------------------------------------------------------ smoother patches
+// Patch of cell T = the unknowns of its faces and its pressure; the patch matrix
+// is the level operator restricted to it.
+//  v-cond: [[s_P (x) I_d, C], [C^T, S_TT]]: store s_P^{-1} and the inverse of the
+//          pressure Schur complement X = S_TT - C^T (s_P^{-1} (x) I_d) C.
+//  v&p:    [[S_P, b], [b^T, 0]]: store S_P^{-1}, g = S_P^{-1} b, 1/(b^T g).
+// The factor is formed in `scratch` (per-cell slots sized like s_P).
+__global__ void __launch_bounds__(kBlock) k_patch_setup(DTopo tp, int cond, int p, int t, const double *bsr,
+                                                        const double *cpl, const double *spp, double *sinv,
+                                                        double *xinv, double *sig, double *scratch, int *err) {
+  extern __shared__ double lds[];
+  const int T = blockIdx.x;
+  const int d = tp.d;
+  const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+  const int bs = (cond == 1) ? p : d * p;  // block edge
+  const int n = nfc * bs;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  double *Lm = scratch + tp.pairoff[T] * bs * bs;
+  double *Si = sinv + tp.pairoff[T] * bs * bs;
+  const int32_t *pb = tp.pairblk + tp.pairoff[T];
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    const int fi = i / bs, fj = j / bs;
+    const int64_t blk = pb[fi * nfc + fj];
+    Lm[idx] = bsr[blk * bs * bs + (int64_t)(i % bs) * bs + (j % bs)];
+  }
+  __syncthreads();
+  blk_chol(Lm, n, n, &bad);
+  __syncthreads();
+  blk_chol_inverse(Lm, n, n, Si, n);
+  const int64_t c0 = tp.cptr[T];
+  if (cond == 1) {
+    // U = (s^{-1} (x) I) C  [d*n x t], X = S_TT - C^T U  [t x t]
+    const double *C = cpl + c0 * d * p * t;
+    double *U = lds;              // [d*n][t]
+    double *X = U + d * n * t;    // [t][t]
+    for (int idx = threadIdx.x; idx < d * n * t; idx += blockDim.x) {
+      const int row = idx / t, q = idx % t;
+      const int fi = row / (d * p), c = (row / p) % d, r = row % p;
+      const int i = fi * p + r;
+      double v = 0;
+      for (int fj = 0; fj < nfc; ++fj)
+        for (int r2 = 0; r2 < p; ++r2) v += Si[i * n + fj * p + r2] * C[((fj * d + c) * p + r2) * t + q];
+      U[idx] = v;
+    }
+    __syncthreads();
+    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) {
+      const int q = idx / t, q2 = idx % t;
+      double v = -spp[(int64_t)T * t * t + idx];
+      for (int row = 0; row < d * n; ++row) v += C[row * t + q] * U[row * t + q2];
+      X[idx] = v;  // -X is SPD
+    }
+    __syncthreads();
+    blk_chol(X, t, t, &bad);
+    __syncthreads();
+    double *Xi = xinv + (int64_t)T * t * t;
+    blk_chol_inverse(X, t, t, Xi, t);
+    for (int idx = threadIdx.x; idx < t * t; idx += blockDim.x) Xi[idx] = -Xi[idx];
+  } else {
+    const double *b = cpl + c0 * d * p;
+    double *g = xinv + c0 * d * p;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double v = 0;
+      for (int j = 0; j < n; ++j) v += Si[i * n + j] * b[j];
+      g[i] = v;
+    }
+    __syncthreads();
+    double part = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) part += b[i] * g[i];
+    const double s = block_sum(part, lds);
+    if (threadIdx.x == 0) {
+      if (!(s > 0.0)) bad = 1;
+      sig[T] = (s > 0.0) ? 1.0 / s : 0.0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
+}
+
+template <typename Tout, typename Tin>
+__global__ void k_convert(const Tin *in, Tout *out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (Tout)in[i];
+}
+
+// ------------------------------------------------------------ dense coarse level
+// D = coarsest operator as a dense matrix, bordered by the constant-pressure
+// vector when the operator is singular (row/col N).
+__global__ void k_densify(DTopo tp, DLevel<double> L, int border, double *D, int64_t ld) {
+  const int d = tp.d, p = L.p, t = L.t;
+  const int bs = (L.cond == 1) ? p : d * p;
+  const int64_t nb = tp.nnzb * bs * bs;
+  const int64_t ncpl = tp.ncf * d * p * t;
+  const int64_t nspp = (L.cond == 1) ? (int64_t)tp.nc * t * t : 0;
+  const int64_t nbord = border ? (int64_t)tp.nc : 0;
+  const int64_t total = nb + ncpl + nspp + nbord;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    if (e < nb) {
+      const int64_t b = e / (bs * bs);
+      const int rr = (int)(e % (bs * bs)) / bs, cc = (int)(e % bs);
+      // row face: binary search of b in rowptr
+      int lo = 0, hi = tp.nf;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (tp.rowptr[mid] <= b) lo = mid; else hi = mid;
+      }
+      const int f = lo, g = tp.col[b];
+      if (L.cond == 1) {
+        for (int c = 0; c < d; ++c) D[((int64_t)(f * d + c) * p + rr) * ld + (int64_t)(g * d + c) * p + cc] = L.bsr[e];
+      } else {
+        D[((int64_t)f * bs + rr) * ld + (int64_t)g * bs + cc] = L.bsr[e];
+      }
+    } else if (e < nb + ncpl) {
+      const int64_t x = e - nb;
+      const int64_t row = x / t;
+      const int q = (int)(x % t);
+      const int64_t ent = row / (d * p);  // cell-face entry
+      const int cr = (int)(row % (d * p));
+      // owning cell of the entry: binary search in cptr
+      int lo = 0, hi = tp.nc;
+      while (hi - lo > 1) {
+        int mid = (lo + hi) / 2;
+        if (tp.cptr[mid] <= ent) lo = mid; else hi = mid;
+      }
+      const int T = lo, f = tp.cface[ent];
+      const int64_t rf = (int64_t)f * d * p + cr, cT = L.nface + (int64_t)T * t + q;
+      D[rf * ld + cT] = L.cpl[x];
+      D[cT * ld + rf] = L.cpl[x];
+    } else if (e < nb + ncpl + nspp) {
+      const int64_t x = e - nb - ncpl;
+      const int64_t T = x / (t * t);
+      const int q = (int)(x % (t * t)) / t, q2 = (int)(x % t);
+      D[(L.nface + T * t + q) * ld + L.nface + T * t + q2] = L.spp[x];
+    } else {
+      const int64_t T = e - nb - ncpl - nspp;
+      const int64_t N = L.N;
+      D[N * ld + L.nface + T * t] = tp.zmean[T];
+      D[(L.nface + T * t) * ld + N] = tp.zmean[T];
+    }
+  }
+}
+
+__global__ void k_eye_right(double *D, int64_t n, int64_t ld) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    D[i * ld + n + i] = 1.0;
+}
+
+// One Gauss-Jordan step with partial pivoting on the augmented [D | I]
+// (n rows, 2n columns).  Phase 0 (one block): pivot search, row swap, scaling,
+// copy of column k to colbuf.  Phase 1 (grid): elimination of column k.
+__global__ void k_gj_pivot(double *D, int64_t n, int64_t ld, int64_t k, double *colbuf, int *err) {
+  __shared__ double sv[kBlock];
+  __shared__ int64_t si[kBlock];
+  double best = -1;
+  int64_t bi = k;
+  for (int64_t i = k + threadIdx.x; i < n; i += blockDim.x) {
+    double v = fabs(D[i * ld + k]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      if (sv[threadIdx.x + o] > sv[threadIdx.x] ||
+          (sv[threadIdx.x + o] == sv[threadIdx.x] && si[threadIdx.x + o] < si[threadIdx.x])) {
+        sv[threadIdx.x] = sv[threadIdx.x + o];
+        si[threadIdx.x] = si[threadIdx.x + o];
+      }
+    }
+    __syncthreads();
+  }
+  const int64_t piv = si[0];
+  if (!(sv[0] > 0.0)) {
+    if (threadIdx.x == 0) *err = 1;
+    return;
+  }
+  if (piv != k)
+    for (int64_t j = threadIdx.x; j < 2 * n; j += blockDim.x) {
+      double a = D[k * ld + j];
+      D[k * ld + j] = D[piv * ld + j];
+      D[piv * ld + j] = a;
+    }
+  __syncthreads();
+  const double inv = 1.0 / D[k * ld + k];
+  __syncthreads();
+  for (int64_t j = threadIdx.x; j < 2 * n; j += blockDim.x) D[k * ld + j] *= inv;
+  for (int64_t i = threadIdx.x; i < n; i += blockDim.x) colbuf[i] = (i == k) ? 0.0 : D[i * ld + k];
+}
+
+__global__ void k_gj_elim(double *D, int64_t n, int64_t ld, int64_t k, const double *colbuf) {
+  const int64_t total = n * 2 * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / (2 * n), j = e % (2 * n);
+    if (i == k) continue;
+    const double f = colbuf[i];
+    if (f != 0.0) D[i * ld + j] -= f * D[k * ld + j];
+  }
+}
+
+// y = Dinv [x ; 0] (the border unknown is dropped), one wave per row.
+__global__ void k_dense_matvec(const double *Dinv, int64_t n, int64_t ld, int border, const double *x,
+                               double *y) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t row = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+  const int64_t N = border ? n - 1 : n;
+  if (row >= N) return;
+  const double *R = Dinv + row * ld + n;  // inverse stored in the right half
+  double v = 0;
+  for (int64_t j = lane; j < N; j += kWave) v += R[j] * x[j];
+  v = wave_sum(v);
+  if (lane == 0) y[row] = v;
+}
+
+inline int grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 65535 * 4) g = 65535 * 4;
+  return (int)g;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ launch wrappers
+size_t condense_lds_bytes(int d, int cond, int nT, int nF, int max_faces) {
+  const int m = max_faces * nF, nloc = nT + m;
+  size_t n = (size_t)nT * nloc + (size_t)d * nT * nT + (size_t)d * nT;
+  if (cond != 1) n += (size_t)nT * d * m + (size_t)(nT - 1) * (nT - 1) + nT + nT;
+  return n * sizeof(double);
+}
+size_t patch_lds_bytes(int d, int cond, int p, int t, int max_faces) {
+  const int n = max_faces * ((cond == 1) ? p : d * p);
+  size_t x = (cond == 1) ? (size_t)d * n * t + (size_t)t * t : 16;
+  return std::max<size_t>(x, 16) * sizeof(double);
+}
+
+void launch_condense(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
+                     double *stage, double *cpl, double *spp, double *rhs_stage, double *rhs_p, int *err,
+                     hipStream_t s, size_t lds) {
+  hipLaunchKernelGGL(k_condense, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, nT, nF, rec, roff, stage, cpl, spp,
+                     rhs_stage, rhs_p, err);
+}
+void launch_assemble(const DTopo &tp, int cond, int nF, int64_t nnzb, const double *stage, double *bsr,
+                     const double *rhs_stage, double *rhs, hipStream_t s) {
+  const int bs = (cond == 1) ? nF : tp.d * nF;
+  hipLaunchKernelGGL(k_assemble, dim3(grid_for(nnzb * bs * bs)), dim3(kBlock), 0, s, tp, cond, nF, nnzb, stage, bsr);
+  hipLaunchKernelGGL(k_rhs_faces, dim3(grid_for((int64_t)tp.nf * tp.d * nF)), dim3(kBlock), 0, s, tp, nF, rhs_stage,
+                     rhs);
+}
+void launch_extract(const DTopo &tp, int cond, int64_t nnzb, int p0, int t0, int p1, int t1, const double *bsr0,
+                    const double *cpl0, const double *spp0, double *bsr1, double *cpl1, double *spp1,
+                    hipStream_t s) {
+  const int b1 = (cond == 1) ? p1 : tp.d * p1;
+  int64_t total = nnzb * b1 * b1 + tp.ncf * tp.d * p1 * ((cond == 1) ? t1 : 1) +
+                  ((cond == 1) ? (int64_t)tp.nc * t1 * t1 : 0);
+  hipLaunchKernelGGL(k_extract, dim3(grid_for(total)), dim3(kBlock), 0, s, tp, cond, nnzb, p0, t0, p1, t1, bsr0,
+                     cpl0, spp0, bsr1, cpl1, spp1);
+}
+void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *bsr, const double *cpl,
+                        const double *spp, double *sinv, double *xinv, double *sig, double *scratch, int *err,
+                        hipStream_t s, size_t lds) {
+  hipLaunchKernelGGL(k_patch_setup, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, p, t, bsr, cpl, spp, sinv, xinv,
+                     sig, scratch, err);
+}
+template <typename Tout, typename Tin>
+void launch_convert(const Tin *in, Tout *out, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<Tout, Tin>), dim3(grid_for(n)), dim3(kBlock), 0, s, in, out, n);
+}
+template void launch_convert<float, double>(const double *, float *, int64_t, hipStream_t);
+template void launch_convert<double, float>(const float *, double *, int64_t, hipStream_t);
+
+void launch_densify(const DTopo &tp, const DLevel<double> &L, int border, double *D, int64_t ld, hipStream_t s) {
+  const int bs = (L.cond == 1) ? L.p : tp.d * L.p;
+  int64_t total = tp.nnzb * bs * bs + tp.ncf * tp.d * L.p * L.t +
+                  ((L.cond == 1) ? (int64_t)tp.nc * L.t * L.t : 0) + (border ? tp.nc : 0);
+  hipLaunchKernelGGL(k_densify, dim3(grid_for(total)), dim3(kBlock), 0, s, tp, L, border, D, ld);
+}
+void launch_eye_right(double *D, int64_t n, int64_t ld, hipStream_t s) {
+  hipLaunchKernelGGL(k_eye_right, dim3(grid_for(n)), dim3(kBlock), 0, s, D, n, ld);
+}
+void launch_gj_step(double *D, int64_t n, int64_t ld, int64_t k, double *colbuf, int *err, hipStream_t s) {
+  hipLaunchKernelGGL(k_gj_pivot, dim3(1), dim3(kBlock), 0, s, D, n, ld, k, colbuf, err);
+  hipLaunchKernelGGL(k_gj_elim, dim3(grid_for(n * 2 * n)), dim3(kBlock), 0, s, D, n, ld, k, colbuf);
+}
+void launch_dense_matvec(const double *Dinv, int64_t n, int64_t ld, int border, const double *x, double *y,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_dense_matvec, dim3(grid_for(n * kWave)), dim3(kBlock), 0, s, Dinv, n, ld, border, x, y);
+}
+
+}  // namespace hho

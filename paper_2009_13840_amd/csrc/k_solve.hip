@@ -1,0 +1,635 @@
+// Solve-phase kernels: face-block operator application, cell-patch Schwarz
+// preconditioner, matrix-free intergrid transfers (Section 3.1: truncation and
+// zero-padded injection), the smoother's minimal-residual step, and the
+// reductions of the Arnoldi process.  Templated on the vector/operator type
+// (FP64, or FP32 for the mixed-precision V-cycle); reductions accumulate in FP64.
+#include <algorithm>
+#include <cmath>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace hho {
+namespace {
+
+inline int grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 8192) g = 8192;
+  return (int)g;
+}
+
+template <typename T, bool SPLIT>
+__device__ inline T xface(const T *x, const T *xs1, int64_t i) {
+  if (SPLIT) return x[i] + xs1[i];
+  return x[i];
+}
+
+// y = S x  (MODE 0)   or   y = b - S x  (MODE 1).  One thread per output entry:
+// face rows first (f, c, r), then cell rows (T, q).
+template <typename T, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+                                                  const T *__restrict__ xs1, T *__restrict__ xsum,
+                                                  const T *__restrict__ b, T *__restrict__ y) {
+  const int d = tp.d, p = L.p, t = L.t;
+  const int dp = d * p;
+  const int64_t total = L.N;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
+    T acc = 0;
+    if (o < L.nface) {
+      const int f = (int)(o / dp);
+      const int cr = (int)(o % dp);
+      const int rb = tp.rowptr[f], re = tp.rowptr[f + 1];
+      if (L.cond == 1) {
+        const int c = cr / p, r = cr % p;
+        for (int b = rb; b < re; ++b) {
+          const T *blk = L.bsr + (int64_t)b * p * p + r * p;
+          const int64_t xo = ((int64_t)tp.col[b] * d + c) * p;
+          for (int k = 0; k < p; ++k) acc += blk[k] * xface<T, SPLIT>(x, xs1, xo + k);
+        }
+        for (int s = 0; s < 2; ++s) {
+          const int Tc = tp.fcell[2 * f + s];
+          if (Tc < 0) continue;
+          const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + s];
+          const T *cp = L.cpl + ((e * d + c) * p + r) * t;
+          const T *xp = x + L.nface + (int64_t)Tc * t;
+          for (int q = 0; q < t; ++q) acc += cp[q] * xp[q];
+        }
+      } else {
+        for (int b = rb; b < re; ++b) {
+          const T *blk = L.bsr + (int64_t)b * dp * dp + (int64_t)cr * dp;
+          const int64_t xo = (int64_t)tp.col[b] * dp;
+          for (int k = 0; k < dp; ++k) acc += blk[k] * xface<T, SPLIT>(x, xs1, xo + k);
+        }
+        for (int s = 0; s < 2; ++s) {
+          const int Tc = tp.fcell[2 * f + s];
+          if (Tc < 0) continue;
+          const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + s];
+          acc += L.cpl[e * dp + cr] * x[L.nface + Tc];
+        }
+      }
+      if (SPLIT && xsum) xsum[o] = xface<T, SPLIT>(x, xs1, o);
+    } else {
+      const int64_t oc = o - L.nface;
+      const int Tc = (int)(oc / t), q = (int)(oc % t);
+      const int eb = tp.cptr[Tc], ee = tp.cptr[Tc + 1];
+      if (L.cond == 1) {
+        for (int e = eb; e < ee; ++e) {
+          const int64_t xo = (int64_t)tp.cface[e] * dp;
+          const T *cp = L.cpl + (int64_t)e * dp * t + q;
+          for (int k = 0; k < dp; ++k) acc += cp[(int64_t)k * t] * xface<T, SPLIT>(x, xs1, xo + k);
+        }
+        const T *sp = L.spp + ((int64_t)Tc * t + q) * t;
+        const T *xp = x + L.nface + (int64_t)Tc * t;
+        for (int q2 = 0; q2 < t; ++q2) acc += sp[q2] * xp[q2];
+      } else {
+        for (int e = eb; e < ee; ++e) {
+          const int64_t xo = (int64_t)tp.cface[e] * dp;
+          const T *cp = L.cpl + (int64_t)e * dp;
+          for (int k = 0; k < dp; ++k) acc += cp[k] * xface<T, SPLIT>(x, xs1, xo + k);
+        }
+      }
+      if (SPLIT && xsum) xsum[o] = x[o];
+    }
+    y[o] = (MODE == 1) ? (T)(b[o] - acc) : acc;
+  }
+}
+
+// Cell-patch Schwarz preconditioner; one 64-thread block per cell.  The
+// corrections of the face unknowns are weighted by 1/card(T_F) and written to the
+// slot of the face's side (slot 0: first cell of the face -> z, slot 1 -> zs1), so
+// that z_F = slot 0 + slot 1 with no write conflict.
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const T *__restrict__ r,
+                                                   const double *__restrict__ scale, T *__restrict__ v,
+                                                   T *__restrict__ z, T *__restrict__ zs1) {
+  extern __shared__ unsigned char smem[];
+  T *sh = (T *)smem;
+  const int Tc = blockIdx.x;
+  const int d = tp.d, p = L.p, t = L.t, dp = d * p;
+  const int eb = tp.cptr[Tc], nfc = tp.cptr[Tc + 1] - eb;
+  const int m = nfc * p, n = nfc * dp;
+  const T sc = scale ? (T)scale[0] : (T)1;
+  T *ru = sh;                  // [n] patch residual (face part)
+  T *u1 = ru + n;              // [n]
+  T *wv = u1 + n;              // [max(n, t)]
+  T *yp = wv + (n > t ? n : t);  // [t + 1]
+  T *rpr = yp + t + 1;         // [t]
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int fi = i / dp, k = i % dp;
+    const int f = tp.cface[eb + fi];
+    const T val = sc * r[(int64_t)f * dp + k];
+    ru[i] = val;
+    if (v && tp.fcell[2 * f] == Tc) v[(int64_t)f * dp + k] = val;
+  }
+  for (int q = threadIdx.x; q < t; q += blockDim.x) {
+    const T val = sc * r[L.nface + (int64_t)Tc * t + q];
+    rpr[q] = val;
+    if (v) v[L.nface + (int64_t)Tc * t + q] = val;
+  }
+  __syncthreads();
+  if (L.cond == 1) {
+    const T *Si = L.sinv + tp.pairoff[Tc] * p * p;  // [m][m], symmetric
+    const T *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
+    // u1 = (s^{-1} (x) I) r_u
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int fi = i / dp, c = (i / p) % d, rr = i % p;
+      const int row = fi * p + rr;
+      T acc = 0;
+      for (int j = 0; j < m; ++j) acc += Si[(int64_t)j * m + row] * ru[((j / p) * d + c) * p + j % p];
+      u1[i] = acc;
+    }
+    __syncthreads();
+    // y_p = X^{-1} (r_p - C^T u1)
+    for (int q = threadIdx.x; q < t; q += blockDim.x) {
+      T acc = rpr[q];
+      for (int i = 0; i < n; ++i) acc -= C[(int64_t)i * t + q] * u1[i];
+      wv[q] = acc;
+    }
+    __syncthreads();
+    const T *Xi = L.xinv + (int64_t)Tc * t * t;
+    for (int q = threadIdx.x; q < t; q += blockDim.x) {
+      T acc = 0;
+      for (int q2 = 0; q2 < t; ++q2) acc += Xi[q * t + q2] * wv[q2];
+      yp[q] = acc;
+    }
+    __syncthreads();
+    // w = r_u - C y_p ; y_u = (s^{-1} (x) I) w
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      T acc = ru[i];
+      for (int q = 0; q < t; ++q) acc -= C[(int64_t)i * t + q] * yp[q];
+      wv[i] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int fi = i / dp, c = (i / p) % d, rr = i % p;
+      const int row = fi * p + rr;
+      T acc = 0;
+      for (int j = 0; j < m; ++j) acc += Si[(int64_t)j * m + row] * wv[((j / p) * d + c) * p + j % p];
+      u1[i] = acc;
+    }
+  } else {
+    const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)dp * dp;  // [n][n], symmetric
+    const T *g = L.xinv + (int64_t)eb * dp;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      T acc = 0;
+      for (int j = 0; j < n; ++j) acc += Si[(int64_t)j * n + i] * ru[j];
+      u1[i] = acc;
+    }
+    T part = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) part += g[i] * ru[i];
+    // wave reduction (blockDim == 64)
+    double pd = wave_sum((double)part);
+    if (threadIdx.x == 0) yp[0] = (T)((pd - (double)rpr[0]) * (double)L.sig[Tc]);
+    __syncthreads();
+    const T ypv = yp[0];
+    for (int i = threadIdx.x; i < n; i += blockDim.x) u1[i] -= g[i] * ypv;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int fi = i / dp, k = i % dp;
+    const int f = tp.cface[eb + fi];
+    const bool first = tp.fcell[2 * f] == Tc;
+    const bool interior = tp.fcell[2 * f + 1] >= 0;
+    const T val = interior ? (T)0.5 * u1[i] : u1[i];
+    if (first) {
+      z[(int64_t)f * dp + k] = val;
+      if (!interior) zs1[(int64_t)f * dp + k] = (T)0;  // no second side on the boundary
+    } else {
+      zs1[(int64_t)f * dp + k] = val;
+    }
+  }
+  for (int q = threadIdx.x; q < t; q += blockDim.x) z[L.nface + (int64_t)Tc * t + q] = yp[q];
+}
+
+template <typename T>
+__global__ void k_combine(int64_t nface, const T *zs1, T *z) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < nface; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] += zs1[i];
+}
+
+// restriction (truncation to the leading modes) and prolongation (zero-padded add)
+template <typename Tc, typename Tf, bool ADD>
+__global__ void k_transfer(int d, int nf, int nc, int pf, int tf, int pc, int tc, const Tf *xf, Tc *xc, Tf *xfo,
+                           const Tc *xci) {
+  const int64_t nfc = (int64_t)nf * d * pc;
+  const int64_t total = nfc + (int64_t)nc * tc;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x) {
+    int64_t j;
+    if (i < nfc) {
+      const int64_t fcmp = i / pc;
+      j = fcmp * pf + i % pc;
+    } else {
+      const int64_t k = i - nfc;
+      j = (int64_t)nf * d * pf + (k / tc) * tf + k % tc;
+    }
+    if (ADD)
+      xfo[j] += (Tf)xci[i];
+    else
+      xc[i] = (Tc)xf[j];
+  }
+}
+
+// ---- smoother: minimal residual over span{z1, z2} (the GMRES(2) iterate)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mr2_dots(int64_t n, int m, const T *w1, const T *w2, const T *r,
+                                                      double *partial, double *y, int *counter) {
+  __shared__ double red[16];
+  double a11 = 0, a12 = 0, a22 = 0, g1 = 0, g2 = 0;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x1 = w1[i], rr = r[i];
+    a11 += x1 * x1;
+    g1 += x1 * rr;
+    if (m == 2) {
+      const double x2 = w2[i];
+      a12 += x1 * x2;
+      a22 += x2 * x2;
+      g2 += x2 * rr;
+    }
+  }
+  double v[5] = {a11, a12, a22, g1, g2};
+  for (int k = 0; k < 5; ++k) {
+    double s = block_sum(v[k], red);
+    if (threadIdx.x == 0) partial[k * gridDim.x + blockIdx.x] = s;
+  }
+  if (last_block_arrived(counter)) {
+    if (threadIdx.x == 0) {
+      double S[5] = {0, 0, 0, 0, 0};
+      for (int k = 0; k < 5; ++k)
+        for (unsigned b = 0; b < gridDim.x; ++b) S[k] += vload(&partial[k * gridDim.x + b]);
+      double y1 = 0, y2 = 0;
+      const double det = S[0] * S[2] - S[1] * S[1];
+      if (m == 2 && det > 1e-14 * S[0] * S[2]) {
+        y1 = (S[2] * S[3] - S[1] * S[4]) / det;
+        y2 = (S[0] * S[4] - S[1] * S[3]) / det;
+      } else if (S[0] > 0) {
+        y1 = S[3] / S[0];
+      }
+      if (!isfinite(y1) || !isfinite(y2)) y1 = y2 = 0;
+      y[0] = y1;
+      y[1] = y2;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_mr2_update(int64_t n, int m, const double *y, const T *z1, const T *z2, const T *w1, const T *w2,
+                             T *x, T *r) {
+  const T y1 = (T)y[0], y2 = (T)y[1];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    if (m == 2) {
+      x[i] += y1 * z1[i] + y2 * z2[i];
+      r[i] -= y1 * w1[i] + y2 * w2[i];
+    } else {
+      x[i] += y1 * z1[i];
+      r[i] -= y1 * w1[i];
+    }
+  }
+}
+
+// ---- Arnoldi reductions (classical Gram-Schmidt applied twice)
+constexpr int kMaxDots = kMaxRestartH + 1;
+
+// partial dots of w with V_0..V_j over this block's rows -> partial[i][block]
+template <typename T>
+__device__ void multi_dot_partial(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial) {
+  __shared__ double red[kBlock / kWave][kMaxDots];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  for (int i = 0; i <= j; ++i) {
+    double acc = 0;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+      acc += (double)V[i * ldv + k] * (double)w[k];
+    acc = wave_sum(acc);
+    if (lane == 0) red[wid][i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+    double s = 0;
+    for (int w_ = 0; w_ < (int)(blockDim.x / kWave); ++w_) s += red[w_][i];
+    partial[(int64_t)i * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w,
+                                                          double *partial, GmresState *st, int *counter) {
+  if (st->done) return;
+  multi_dot_partial(n, j, V, ldv, w, partial);
+  if (last_block_arrived(counter)) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+      double s = 0;
+      for (unsigned b = 0; b < gridDim.x; ++b) s += vload(&partial[(int64_t)i * gridDim.x + b]);
+      st->h1[i] = s;
+    }
+  }
+}
+
+// pass 1: w -= V h1, then partial dots for pass 2 (-> h2)
+// pass 2: w -= V h2, then |w|^2 -> column j of H, Givens rotation, residual estimate
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w,
+                                                            double *partial, GmresState *st, int *counter,
+                                                            int pass) {
+  if (st->done) return;
+  __shared__ double h[kMaxDots];
+  __shared__ double red[16];
+  for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] = (pass == 1) ? st->h1[i] : st->h2[i];
+  __syncthreads();
+  double nrm = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double v = w[k];
+    for (int i = 0; i <= j; ++i) v -= h[i] * (double)V[i * ldv + k];
+    w[k] = (T)v;
+    nrm += (double)(T)v * (double)(T)v;
+  }
+  if (pass == 1) {
+    __syncthreads();
+    multi_dot_partial(n, j, V, ldv, (const T *)w, partial);
+    if (last_block_arrived(counter)) {
+      for (int i = threadIdx.x; i <= j; i += blockDim.x) {
+        double s = 0;
+        for (unsigned b = 0; b < gridDim.x; ++b) s += vload(&partial[(int64_t)i * gridDim.x + b]);
+        st->h2[i] = s;
+      }
+    }
+    return;
+  }
+  double s = block_sum(nrm, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (last_block_arrived(counter)) {
+    if (threadIdx.x == 0) {
+      double nn = 0;
+      for (unsigned b = 0; b < gridDim.x; ++b) nn += vload(&partial[b]);
+      const int R = kMaxRestartH;
+      double *H = st->H;
+      for (int i = 0; i <= j; ++i) H[i * R + j] = st->h1[i] + st->h2[i];
+      const double hn = sqrt(nn);
+      H[(j + 1) * R + j] = hn;
+      // apply previous rotations to column j
+      for (int i = 0; i < j; ++i) {
+        const double a = H[i * R + j], b = H[(i + 1) * R + j];
+        H[i * R + j] = st->cs[i] * a + st->sn[i] * b;
+        H[(i + 1) * R + j] = -st->sn[i] * a + st->cs[i] * b;
+      }
+      const double a = H[j * R + j], b = H[(j + 1) * R + j];
+      const double rr = sqrt(a * a + b * b);
+      const double c = (rr > 0) ? a / rr : 1.0, sn = (rr > 0) ? b / rr : 0.0;
+      st->cs[j] = c;
+      st->sn[j] = sn;
+      H[j * R + j] = rr;
+      H[(j + 1) * R + j] = 0;
+      const double gj = st->g[j];
+      st->g[j] = c * gj;
+      st->g[j + 1] = -sn * gj;
+      st->res = fabs(st->g[j + 1]);
+      st->j = j + 1;
+      st->inv_hnext = (hn > 0) ? 1.0 / hn : 0.0;
+      if (!isfinite(nn) || !isfinite(st->res)) {
+        st->nan = 1;
+        st->done = 1;
+      }
+      if (st->res <= st->rtol * st->bnorm || hn <= 1e-14 * st->beta) st->done = 1;
+    }
+  }
+}
+
+// |r| -> beta (and bnorm if which == 1), g = beta e1, reset the cycle.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_norm_init(int64_t n, const T *r, double *partial, GmresState *st,
+                                                       int *counter, int which) {
+  __shared__ double red[16];
+  double acc = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    const double v = r[k];
+    acc += v * v;
+  }
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (last_block_arrived(counter)) {
+    if (threadIdx.x == 0) {
+      double nn = 0;
+      for (unsigned b = 0; b < gridDim.x; ++b) nn += vload(&partial[b]);
+      const double beta = sqrt(nn);
+      st->beta = beta;
+      if (which == 1) st->bnorm = beta;
+      for (int i = 0; i <= kMaxRestartH; ++i) st->g[i] = 0;
+      st->g[0] = beta;
+      st->res = beta;
+      st->j = 0;
+      st->inv_hnext = (beta > 0) ? 1.0 / beta : 0.0;
+      st->nan = !isfinite(nn);
+      st->done = (!(beta > 0) || st->nan || beta <= st->rtol * st->bnorm) ? 1 : 0;
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_scale(int64_t n, const T *x, const double *scale, T *y) {
+  const T s = (T)scale[0];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] = s * x[k];
+}
+
+// y = H^{-1} g over the st->j columns of the current cycle (single thread)
+__global__ void k_gmres_solve_ls(GmresState *st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int R = kMaxRestartH;
+  const int jn = st->j;
+  for (int i = jn - 1; i >= 0; --i) {
+    double v = st->g[i];
+    for (int k = i + 1; k < jn; ++k) v -= st->H[i * R + k] * st->y[k];
+    const double hii = st->H[i * R + i];
+    st->y[i] = (hii != 0) ? v / hii : 0.0;
+  }
+}
+
+template <typename T>
+__global__ void k_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresState *st, T *x) {
+  const int jn = st->j;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+    double v = x[k];
+    for (int i = 0; i < jn; ++i) v += st->y[i] * (double)Z[i * ldz + k];
+    x[k] = (T)v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const T *a, const T *b, double *partial, double *out,
+                                                 int *counter) {
+  __shared__ double red[16];
+  double acc = 0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    acc += (double)a[k] * (double)b[k];
+  double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (last_block_arrived(counter)) {
+    if (threadIdx.x == 0) {
+      double v = 0;
+      for (unsigned bb = 0; bb < gridDim.x; ++bb) v += vload(&partial[bb]);
+      out[0] = v;
+    }
+  }
+}
+
+// y += sign * (alpha[0] / alpha[1]) * x  (alpha[1] = 1 when not a ratio)
+template <typename T>
+__global__ void k_axpy_ratio(int64_t n, const double *alpha, double sign, const T *x, T *y) {
+  const double a = sign * alpha[0] / alpha[1];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] = (T)((double)y[k] + a * (double)x[k]);
+}
+
+template <typename T>
+__global__ void k_fill(int64_t n, T v, T *x) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    x[k] = v;
+}
+template <typename T>
+__global__ void k_copy(int64_t n, const T *x, T *y) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    y[k] = x[k];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------ wrappers
+int reduce_blocks(int64_t n) {
+  int64_t g = (n + kBlock - 1) / kBlock;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 512));
+}
+
+template <typename T>
+void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s) {
+  if (xs1)
+    hipLaunchKernelGGL((k_spmv<T, true, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
+                       (const T *)nullptr, y);
+  else
+    hipLaunchKernelGGL((k_spmv<T, false, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
+                       (const T *)nullptr, y);
+}
+template <typename T>
+void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x, T *r, hipStream_t s) {
+  hipLaunchKernelGGL((k_spmv<T, false, 1>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, (const T *)nullptr,
+                     (T *)nullptr, b, r);
+}
+size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem) {
+  const int n = max_faces * d * p;
+  return (size_t)(2 * n + std::max(n, t) + 2 * t + 2) * elem;
+}
+template <typename T>
+void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
+                    int max_faces, hipStream_t s) {
+  const size_t lds = precond_lds_bytes(tp.d, L.cond, L.p, L.t, max_faces, sizeof(T));
+  hipLaunchKernelGGL((k_precond<T>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1);
+}
+template <typename T>
+void launch_combine(int64_t nface, const T *zs1, T *z, hipStream_t s) {
+  hipLaunchKernelGGL((k_combine<T>), dim3(grid_for(nface)), dim3(kBlock), 0, s, nface, zs1, z);
+}
+template <typename Tc, typename Tf>
+void launch_restrict(int d, int nf, int nc, int pf, int tf, int pc, int tc, const Tf *xf, Tc *xc, hipStream_t s) {
+  const int64_t total = (int64_t)nf * d * pc + (int64_t)nc * tc;
+  hipLaunchKernelGGL((k_transfer<Tc, Tf, false>), dim3(grid_for(total)), dim3(kBlock), 0, s, d, nf, nc, pf, tf, pc,
+                     tc, xf, xc, (Tf *)nullptr, (const Tc *)nullptr);
+}
+template <typename Tc, typename Tf>
+void launch_prolong_add(int d, int nf, int nc, int pf, int tf, int pc, int tc, const Tc *xc, Tf *xf,
+                        hipStream_t s) {
+  const int64_t total = (int64_t)nf * d * pc + (int64_t)nc * tc;
+  hipLaunchKernelGGL((k_transfer<Tc, Tf, true>), dim3(grid_for(total)), dim3(kBlock), 0, s, d, nf, nc, pf, tf, pc,
+                     tc, (const Tf *)nullptr, (Tc *)nullptr, xf, xc);
+}
+template <typename T>
+void launch_mr2_dots(int64_t n, int m, const T *w1, const T *w2, const T *r, double *partial, double *y,
+                     int *counter, hipStream_t s) {
+  hipLaunchKernelGGL((k_mr2_dots<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, m, w1, w2, r, partial, y,
+                     counter);
+}
+template <typename T>
+void launch_mr2_update(int64_t n, int m, const double *y, const T *z1, const T *z2, const T *w1, const T *w2,
+                       T *x, T *r, hipStream_t s) {
+  hipLaunchKernelGGL((k_mr2_update<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, m, y, z1, z2, w1, w2, x, r);
+}
+template <typename T>
+void launch_norm_init(int64_t n, const T *r, double *partial, GmresState *st, int *counter, int which,
+                      hipStream_t s) {
+  hipLaunchKernelGGL((k_norm_init<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, r, partial, st, counter, which);
+}
+template <typename T>
+void launch_scale(int64_t n, const T *x, const double *scale, T *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_scale<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, scale, y);
+}
+template <typename T>
+void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
+                         int *counter, hipStream_t s) {
+  hipLaunchKernelGGL((k_arnoldi_dots<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, j, V, ldv, w, partial, st,
+                     counter);
+}
+template <typename T>
+void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partial, GmresState *st,
+                           int *counter, int pass, hipStream_t s) {
+  hipLaunchKernelGGL((k_arnoldi_update<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, j, V, ldv, w, partial,
+                     st, counter, pass);
+}
+void launch_gmres_solve_ls(GmresState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_gmres_solve_ls, dim3(1), dim3(64), 0, s, st);
+}
+template <typename T>
+void launch_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresState *st, T *x, hipStream_t s) {
+  hipLaunchKernelGGL((k_gmres_combine<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, Z, ldz, st, x);
+}
+template <typename T>
+void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out, int *counter, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, a, b, partial, out, counter);
+}
+template <typename T>
+void launch_axpy_ratio(int64_t n, const double *alpha, double sign, const T *x, T *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy_ratio<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, alpha, sign, x, y);
+}
+template <typename T>
+void launch_fill(int64_t n, T v, T *x, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, v, x);
+}
+template <typename T>
+void launch_copy(int64_t n, const T *x, T *y, hipStream_t s) {
+  hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, y);
+}
+
+#define HHO_INST(T)                                                                                              \
+  template void launch_spmv<T>(const DTopo &, const DLevel<T> &, const T *, const T *, T *, T *, hipStream_t);  \
+  template void launch_residual<T>(const DTopo &, const DLevel<T> &, const T *, const T *, T *, hipStream_t);   \
+  template void launch_precond<T>(const DTopo &, const DLevel<T> &, const T *, const double *, T *, T *, T *,   \
+                                  int, hipStream_t);                                                           \
+  template void launch_combine<T>(int64_t, const T *, T *, hipStream_t);                                        \
+  template void launch_mr2_dots<T>(int64_t, int, const T *, const T *, const T *, double *, double *, int *,     \
+                                   hipStream_t);                                                               \
+  template void launch_mr2_update<T>(int64_t, int, const double *, const T *, const T *, const T *, const T *,   \
+                                     T *, T *, hipStream_t);                                                   \
+  template void launch_norm_init<T>(int64_t, const T *, double *, GmresState *, int *, int, hipStream_t);       \
+  template void launch_scale<T>(int64_t, const T *, const double *, T *, hipStream_t);                          \
+  template void launch_arnoldi_dots<T>(int64_t, int, const T *, int64_t, const T *, double *, GmresState *,     \
+                                       int *, hipStream_t);                                                    \
+  template void launch_arnoldi_update<T>(int64_t, int, const T *, int64_t, T *, double *, GmresState *, int *,  \
+                                         int, hipStream_t);                                                    \
+  template void launch_gmres_combine<T>(int64_t, const T *, int64_t, const GmresState *, T *, hipStream_t);     \
+  template void launch_dot<T>(int64_t, const T *, const T *, double *, double *, int *, hipStream_t);           \
+  template void launch_axpy_ratio<T>(int64_t, const double *, double, const T *, T *, hipStream_t);             \
+  template void launch_fill<T>(int64_t, T, T *, hipStream_t);                                                   \
+  template void launch_copy<T>(int64_t, const T *, T *, hipStream_t);
+HHO_INST(double)
+HHO_INST(float)
+#undef HHO_INST
+
+template void launch_restrict<double, double>(int, int, int, int, int, int, int, const double *, double *,
+                                              hipStream_t);
+template void launch_restrict<float, float>(int, int, int, int, int, int, int, const float *, float *, hipStream_t);
+template void launch_restrict<double, float>(int, int, int, int, int, int, int, const float *, double *,
+                                             hipStream_t);
+template void launch_prolong_add<double, double>(int, int, int, int, int, int, int, const double *, double *,
+                                                 hipStream_t);
+template void launch_prolong_add<float, float>(int, int, int, int, int, int, int, const float *, float *,
+                                               hipStream_t);
+template void launch_prolong_add<double, float>(int, int, int, int, int, int, int, const double *, float *,
+                                                hipStream_t);
+
+}  // namespace hho

@@ -1,0 +1,981 @@
+// Problem object, device workspace, setup pipeline, V-cycle, coarse solver,
+// flexible GMRES, and the C ABI entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "dev_common.h"
+#include "device.h"
+#include "internal.h"
+
+namespace hho {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string &msg) { g_last_error = msg; }
+void fail(int code, const std::string &msg) { throw Error{code, msg}; }
+
+#define HIPCHK(x)                                                                                   \
+  do {                                                                                              \
+    hipError_t e_ = (x);                                                                            \
+    if (e_ != hipSuccess)                                                                           \
+      ::hho::fail(HHO_E_DEVICE, std::string("HIP error ") + hipGetErrorString(e_) + " at " #x);    \
+  } while (0)
+
+// ------------------------------------------------------------ workspace arena
+struct Arena {
+  char *base = nullptr;  // null while planning
+  size_t off = 0;
+  template <typename T>
+  T *take(int64_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = base ? (T *)(base + off) : nullptr;
+    off += (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+    return p;
+  }
+};
+
+template <typename T>
+struct VBufs {  // V-cycle vectors of one level
+  T *b = nullptr, *w = nullptr, *r = nullptr, *z1 = nullptr, *z2 = nullptr, *w1 = nullptr, *w2 = nullptr,
+    *zs0 = nullptr, *zs1 = nullptr;
+};
+
+struct LevelInfo {
+  int k, p, t, bs;
+  int64_t nface, N;
+  // FP64 operator and smoother
+  double *bsr, *cpl, *spp, *sinv, *xinv, *sig;
+  // FP32 copies (mixed V-cycle)
+  float *bsr32, *cpl32, *spp32, *sinv32, *xinv32, *sig32;
+  VBufs<double> v64;
+  VBufs<float> v32;
+  double *y;  // smoother coefficients
+};
+
+}  // namespace hho
+
+using namespace hho;
+
+struct hho_problem {
+  const hho_mesh *mesh = nullptr;
+  int k = 0, cond = 1, nlev = 1, d = 2;
+  std::vector<int> deg;
+  hho_options opt;
+  double eta = 0;
+  LocalData loc;
+  bool have_data = false;
+  // host topology
+  std::vector<int32_t> cptr, cface, fcell, floc, rowptr, col, blksrc, pairblk;
+  std::vector<int64_t> pairoff;
+  std::vector<double> zmean;
+  int64_t nnzb = 0, ncf = 0;
+  int max_faces = 0;
+  // device
+  char *ws = nullptr;
+  size_t ws_bytes = 0, need = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false, setup_done = false;
+  DTopo tp{};
+  std::vector<LevelInfo> lev;
+  int coarse_dense = 0, border = 0;
+  int64_t dense_n = 0;
+  // device arrays
+  double *rec = nullptr;
+  int64_t *roff = nullptr;
+  double *stage = nullptr, *rhs_stage = nullptr, *rhs = nullptr, *zvec = nullptr;
+  double *dense = nullptr, *colbuf = nullptr;
+  // outer FGMRES (FP64, level 0) and coarse GMRES (FP64, level L)
+  double *oV = nullptr, *oZ = nullptr, *ow = nullptr, *ox = nullptr, *or_ = nullptr, *ob = nullptr;
+  double *cV = nullptr, *cZ = nullptr, *cw = nullptr, *cx = nullptr, *cr = nullptr, *czs0 = nullptr,
+         *czs1 = nullptr;
+  GmresState *ost = nullptr, *cst = nullptr;
+  double *partial = nullptr, *scal = nullptr;
+  int *counter = nullptr, *err = nullptr;
+  int ncounters = 16;
+  // host mirrors
+  GmresState *h_st = nullptr;  // pinned
+  double timings[16] = {0};
+  size_t lds_condense = 0, lds_patch = 0;
+};
+
+namespace hho {
+
+static int level_t(const hho_problem *P, int k) { return P->cond == HHO_COND_V ? dim_poly(P->d, k) : 1; }
+
+// Every device array of the problem, in one place: run once to size the
+// workspace (base == null) and once to hand out pointers.
+static void plan(hho_problem *P, Arena &A) {
+  const int d = P->d;
+  const int64_t nc = P->mesh->nc, nf = P->mesh->nf;
+  const bool mixed = P->opt.precision == HHO_PREC_FP32;
+  // topology
+  P->tp.cptr = A.take<int32_t>(nc + 1);
+  P->tp.cface = A.take<int32_t>(P->ncf);
+  P->tp.fcell = A.take<int32_t>(2 * nf);
+  P->tp.floc = A.take<int32_t>(2 * nf);
+  P->tp.rowptr = A.take<int32_t>(nf + 1);
+  P->tp.col = A.take<int32_t>(P->nnzb);
+  P->tp.blksrc = A.take<int32_t>(6 * P->nnzb);
+  P->tp.pairoff = A.take<int64_t>(nc + 1);
+  P->tp.pairblk = A.take<int32_t>(P->pairoff[nc]);
+  P->tp.zmean = A.take<double>(nc);
+  // local records and condensation staging
+  P->rec = A.take<double>(P->loc.off.empty() ? 1 : P->loc.off[nc]);
+  P->roff = A.take<int64_t>(nc + 1);
+  const LevelInfo &L0 = P->lev[0];
+  P->stage = A.take<double>(P->pairoff[nc] * L0.bs * L0.bs);
+  P->rhs_stage = A.take<double>(P->ncf * d * L0.p);
+  P->rhs = A.take<double>(L0.N);
+  P->zvec = A.take<double>(L0.N);
+  const int Lc = P->nlev - 1;
+  for (int l = 0; l < P->nlev; ++l) {
+    LevelInfo &L = P->lev[l];
+    const int64_t nbsr = P->nnzb * L.bs * L.bs;
+    const int64_t ncpl = P->ncf * d * L.p * (P->cond == HHO_COND_V ? L.t : 1);
+    const int64_t nspp = P->cond == HHO_COND_V ? nc * L.t * L.t : 1;
+    const int64_t nsinv = P->pairoff[nc] * L.bs * L.bs;
+    const int64_t nxinv = P->cond == HHO_COND_V ? nc * L.t * L.t : P->ncf * d * L.p;
+    L.bsr = A.take<double>(nbsr);
+    L.cpl = A.take<double>(ncpl);
+    L.spp = A.take<double>(nspp);
+    const bool need_smoother = (l < Lc) || !P->coarse_dense;
+    L.sinv = need_smoother ? A.take<double>(nsinv) : nullptr;
+    L.xinv = need_smoother ? A.take<double>(nxinv) : nullptr;
+    L.sig = need_smoother ? A.take<double>(nc) : nullptr;
+    L.y = A.take<double>(2);
+    if (mixed && l < Lc) {
+      L.bsr32 = A.take<float>(nbsr);
+      L.cpl32 = A.take<float>(ncpl);
+      L.spp32 = A.take<float>(nspp);
+      L.sinv32 = A.take<float>(nsinv);
+      L.xinv32 = A.take<float>(nxinv);
+      L.sig32 = A.take<float>(nc);
+    }
+    auto vecs = [&](auto &V, auto tag) {
+      using T = decltype(tag);
+      V.b = A.take<T>(L.N);
+      V.w = A.take<T>(L.N);
+      V.r = A.take<T>(L.N);
+      V.z1 = A.take<T>(L.N);
+      V.z2 = A.take<T>(L.N);
+      V.w1 = A.take<T>(L.N);
+      V.w2 = A.take<T>(L.N);
+      V.zs0 = A.take<T>(L.N);
+      V.zs1 = A.take<T>(L.nface);
+    };
+    if (l == Lc || !mixed)
+      vecs(L.v64, 0.0);
+    else
+      vecs(L.v32, 0.0f);
+  }
+  // coarse solver
+  const LevelInfo &LC = P->lev[Lc];
+  if (P->coarse_dense) {
+    P->dense = A.take<double>(P->dense_n * 2 * P->dense_n);
+    P->colbuf = A.take<double>(P->dense_n);
+  } else {
+    const int R = P->opt.coarse_restart;
+    P->cV = A.take<double>((int64_t)(R + 1) * LC.N);
+    P->cZ = A.take<double>((int64_t)R * LC.N);
+    P->cw = A.take<double>(LC.N);
+    P->cr = A.take<double>(LC.N);
+    P->czs0 = A.take<double>(LC.N);
+    P->czs1 = A.take<double>(LC.nface);
+  }
+  // outer FGMRES
+  const int R = P->opt.restart;
+  P->oV = A.take<double>((int64_t)(R + 1) * L0.N);
+  P->oZ = A.take<double>((int64_t)R * L0.N);
+  P->ow = A.take<double>(L0.N);
+  P->ox = A.take<double>(L0.N);
+  P->or_ = A.take<double>(L0.N);
+  P->ob = A.take<double>(L0.N);
+  P->ost = A.take<GmresState>(1);
+  P->cst = A.take<GmresState>(1);
+  P->partial = A.take<double>(512 * (kMaxRestartH + 2));
+  P->scal = A.take<double>(16);
+  P->counter = A.take<int>(P->ncounters);
+  P->err = A.take<int>(4);
+}
+
+static DLevel<double> dlev64(const hho_problem *P, int l) {
+  const LevelInfo &L = P->lev[l];
+  DLevel<double> D;
+  D.cond = P->cond;
+  D.p = L.p;
+  D.t = L.t;
+  D.nface = L.nface;
+  D.N = L.N;
+  D.bsr = L.bsr;
+  D.cpl = L.cpl;
+  D.spp = L.spp;
+  D.sinv = L.sinv;
+  D.xinv = L.xinv;
+  D.sig = L.sig;
+  return D;
+}
+static DLevel<float> dlev32(const hho_problem *P, int l) {
+  const LevelInfo &L = P->lev[l];
+  DLevel<float> D;
+  D.cond = P->cond;
+  D.p = L.p;
+  D.t = L.t;
+  D.nface = L.nface;
+  D.N = L.N;
+  D.bsr = L.bsr32;
+  D.cpl = L.cpl32;
+  D.spp = L.spp32;
+  D.sinv = L.sinv32;
+  D.xinv = L.xinv32;
+  D.sig = L.sig32;
+  return D;
+}
+template <typename T>
+struct LevSel;
+template <>
+struct LevSel<double> {
+  static DLevel<double> op(const hho_problem *P, int l) { return dlev64(P, l); }
+  static VBufs<double> &vb(hho_problem *P, int l) { return P->lev[l].v64; }
+};
+template <>
+struct LevSel<float> {
+  static DLevel<float> op(const hho_problem *P, int l) { return dlev32(P, l); }
+  static VBufs<float> &vb(hho_problem *P, int l) { return P->lev[l].v32; }
+};
+
+static void build_topology(hho_problem *P) {
+  const hho_mesh *m = P->mesh;
+  const int64_t nc = m->nc, nf = m->nf;
+  if (m->cface.size() > (size_t)INT32_MAX || nf > INT32_MAX || nc > INT32_MAX)
+    fail(HHO_E_INVALID_ARG, "mesh too large for 32-bit indices");
+  P->ncf = (int64_t)m->cface.size();
+  P->cptr.assign(m->cptr.begin(), m->cptr.end());
+  P->cface.assign(m->cface.begin(), m->cface.end());
+  P->fcell.resize(2 * nf);
+  P->floc.resize(2 * nf);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int s = 0; s < 2; ++s) {
+      P->fcell[2 * f + s] = (int32_t)m->fcell[s][f];
+      P->floc[2 * f + s] = m->flocal[s][f];
+    }
+  // face-block rows: faces of the cells sharing the face
+  P->rowptr.assign(nf + 1, 0);
+  std::vector<std::vector<int32_t>> nb(nf);
+  for (int64_t f = 0; f < nf; ++f) {
+    for (int s = 0; s < 2; ++s) {
+      int64_t c = m->fcell[s][f];
+      if (c < 0) continue;
+      for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e) nb[f].push_back((int32_t)m->cface[e]);
+    }
+    std::sort(nb[f].begin(), nb[f].end());
+    nb[f].erase(std::unique(nb[f].begin(), nb[f].end()), nb[f].end());
+    P->rowptr[f + 1] = P->rowptr[f] + (int32_t)nb[f].size();
+  }
+  P->nnzb = P->rowptr[nf];
+  P->col.resize(P->nnzb);
+  for (int64_t f = 0; f < nf; ++f) std::copy(nb[f].begin(), nb[f].end(), P->col.begin() + P->rowptr[f]);
+  P->blksrc.assign(6 * P->nnzb, -1);
+  P->pairoff.assign(nc + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    int64_t n = m->cptr[c + 1] - m->cptr[c];
+    P->pairoff[c + 1] = P->pairoff[c] + n * n;
+  }
+  P->pairblk.assign(P->pairoff[nc], -1);
+  for (int64_t c = 0; c < nc; ++c) {
+    int n = (int)(m->cptr[c + 1] - m->cptr[c]);
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        int32_t fi = (int32_t)m->cface[m->cptr[c] + i], fj = (int32_t)m->cface[m->cptr[c] + j];
+        auto b0 = P->col.begin() + P->rowptr[fi], b1 = P->col.begin() + P->rowptr[fi + 1];
+        auto it = std::lower_bound(b0, b1, fj);
+        int64_t b = it - P->col.begin();
+        P->pairblk[P->pairoff[c] + i * n + j] = (int32_t)b;
+        int s = P->blksrc[6 * b] < 0 ? 0 : 1;
+        if (s == 1 && P->blksrc[6 * b + 3] >= 0) fail(HHO_E_MESH, "face block with more than two cells");
+        P->blksrc[6 * b + 3 * s] = (int32_t)c;
+        P->blksrc[6 * b + 3 * s + 1] = i;
+        P->blksrc[6 * b + 3 * s + 2] = j;
+      }
+  }
+  P->zmean.resize(nc);
+  for (int64_t c = 0; c < nc; ++c) P->zmean[c] = std::sqrt(m->cvol[c]);
+  P->max_faces = m->max_faces;
+  P->tp.d = P->d;
+  P->tp.nc = (int)nc;
+  P->tp.nf = (int)nf;
+  P->tp.ncf = P->ncf;
+  P->tp.nnzb = P->nnzb;
+}
+
+static void init_levels(hho_problem *P) {
+  P->lev.resize(P->nlev);
+  for (int l = 0; l < P->nlev; ++l) {
+    LevelInfo &L = P->lev[l];
+    L = LevelInfo{};
+    L.k = P->deg[l];
+    L.p = dim_poly(P->d - 1, L.k);
+    L.t = level_t(P, L.k);
+    L.bs = P->cond == HHO_COND_V ? L.p : P->d * L.p;
+    L.nface = P->mesh->nf * P->d * L.p;
+    L.N = L.nface + P->mesh->nc * L.t;
+  }
+  const LevelInfo &LC = P->lev[P->nlev - 1];
+  P->border = P->mesh->has_neumann ? 0 : 1;
+  const int64_t nd = LC.N + P->border;
+  P->coarse_dense = (P->opt.coarse_mode == HHO_COARSE_DENSE) ||
+                    (P->opt.coarse_mode == HHO_COARSE_AUTO && nd <= 1024);
+  if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
+  P->dense_n = nd;
+}
+
+static void check_device_error(hho_problem *P, const char *what) {
+  HIPCHK(hipGetLastError());
+  (void)P;
+  (void)what;
+}
+
+// ------------------------------------------------------------ setup
+static void device_setup(hho_problem *P) {
+  hipStream_t s = P->stream;
+  const hho_mesh *m = P->mesh;
+  const int64_t nc = m->nc;
+  auto h2d = [&](void *dst, const void *src, size_t bytes) { HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s)); };
+  h2d((void *)P->tp.cptr, P->cptr.data(), P->cptr.size() * 4);
+  h2d((void *)P->tp.cface, P->cface.data(), P->cface.size() * 4);
+  h2d((void *)P->tp.fcell, P->fcell.data(), P->fcell.size() * 4);
+  h2d((void *)P->tp.floc, P->floc.data(), P->floc.size() * 4);
+  h2d((void *)P->tp.rowptr, P->rowptr.data(), P->rowptr.size() * 4);
+  h2d((void *)P->tp.col, P->col.data(), P->col.size() * 4);
+  h2d((void *)P->tp.blksrc, P->blksrc.data(), P->blksrc.size() * 4);
+  h2d((void *)P->tp.pairoff, P->pairoff.data(), P->pairoff.size() * 8);
+  h2d((void *)P->tp.pairblk, P->pairblk.data(), P->pairblk.size() * 4);
+  h2d((void *)P->tp.zmean, P->zmean.data(), P->zmean.size() * 8);
+  h2d(P->rec, P->loc.rec.data(), P->loc.rec.size() * 8);
+  h2d(P->roff, P->loc.off.data(), P->loc.off.size() * 8);
+  HIPCHK(hipMemsetAsync(P->counter, 0, P->ncounters * sizeof(int), s));
+  HIPCHK(hipMemsetAsync(P->err, 0, 4 * sizeof(int), s));
+  HIPCHK(hipStreamSynchronize(s));
+
+  hipEvent_t ev[8];
+  for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventRecord(ev[0], s));
+  LevelInfo &L0 = P->lev[0];
+  // static condensation
+  launch_condense(P->tp, P->cond, P->loc.nT, P->loc.nF, P->rec, P->roff, P->stage, L0.cpl, L0.spp, P->rhs_stage,
+                  P->rhs + L0.nface, P->err, s, P->lds_condense);
+  HIPCHK(hipEventRecord(ev[1], s));
+  // assembly
+  launch_assemble(P->tp, P->cond, L0.p, P->nnzb, P->stage, L0.bsr, P->rhs_stage, P->rhs, s);
+  HIPCHK(hipEventRecord(ev[2], s));
+  // coarse levels by extraction
+  for (int l = 1; l < P->nlev; ++l) {
+    const LevelInfo &A = P->lev[l - 1];
+    LevelInfo &B = P->lev[l];
+    launch_extract(P->tp, P->cond, P->nnzb, A.p, A.t, B.p, B.t, A.bsr, A.cpl, A.spp, B.bsr, B.cpl, B.spp, s);
+  }
+  HIPCHK(hipEventRecord(ev[3], s));
+  // smoother patches (the condensation staging array is free now)
+  const int Lc = P->nlev - 1;
+  for (int l = 0; l < P->nlev; ++l) {
+    LevelInfo &L = P->lev[l];
+    if (!L.sinv) continue;
+    size_t lds = patch_lds_bytes(P->d, P->cond, L.p, L.t, P->max_faces);
+    launch_patch_setup(P->tp, P->cond, L.p, L.t, L.bsr, L.cpl, L.spp, L.sinv, L.xinv, L.sig, P->stage, P->err + 1,
+                       s, lds);
+  }
+  HIPCHK(hipEventRecord(ev[4], s));
+  // coarse solver
+  if (P->coarse_dense) {
+    const int64_t n = P->dense_n;
+    launch_fill<double>(n * 2 * n, 0.0, P->dense, s);
+    launch_densify(P->tp, dlev64(P, Lc), P->border, P->dense, 2 * n, s);
+    launch_eye_right(P->dense, n, 2 * n, s);
+    for (int64_t kk = 0; kk < n; ++kk) launch_gj_step(P->dense, n, 2 * n, kk, P->colbuf, P->err + 2, s);
+  }
+  // nullspace vector (constant pressure, level 0)
+  launch_fill<double>(L0.N, 0.0, P->zvec, s);
+  if (P->border) {
+    std::vector<double> zh(L0.N, 0.0);
+    for (int64_t c = 0; c < nc; ++c) zh[L0.nface + c * L0.t] = P->zmean[c];
+    h2d(P->zvec, zh.data(), zh.size() * 8);
+  }
+  // FP32 copies for the mixed-precision V-cycle
+  if (P->opt.precision == HHO_PREC_FP32) {
+    for (int l = 0; l < Lc; ++l) {
+      LevelInfo &L = P->lev[l];
+      const int d = P->d;
+      const int64_t nbsr = P->nnzb * L.bs * L.bs;
+      const int64_t ncpl = P->ncf * d * L.p * (P->cond == HHO_COND_V ? L.t : 1);
+      const int64_t nspp = P->cond == HHO_COND_V ? nc * L.t * L.t : 1;
+      const int64_t nsinv = P->pairoff[nc] * L.bs * L.bs;
+      const int64_t nxinv = P->cond == HHO_COND_V ? nc * L.t * L.t : P->ncf * d * L.p;
+      launch_convert<float, double>(L.bsr, L.bsr32, nbsr, s);
+      launch_convert<float, double>(L.cpl, L.cpl32, ncpl, s);
+      if (P->cond == HHO_COND_V) launch_convert<float, double>(L.spp, L.spp32, nspp, s);
+      launch_convert<float, double>(L.sinv, L.sinv32, nsinv, s);
+      launch_convert<float, double>(L.xinv, L.xinv32, nxinv, s);
+      if (P->cond != HHO_COND_V) launch_convert<float, double>(L.sig, L.sig32, nc, s);
+    }
+  }
+  HIPCHK(hipEventRecord(ev[5], s));
+  HIPCHK(hipStreamSynchronize(s));
+  check_device_error(P, "setup");
+  float ms;
+  for (int i = 0; i < 5; ++i) {
+    HIPCHK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+    P->timings[i] = ms;
+  }
+  for (auto &e : ev) HIPCHK(hipEventDestroy(e));
+  int herr[4];
+  HIPCHK(hipMemcpy(herr, P->err, sizeof(herr), hipMemcpyDeviceToHost));
+  if (herr[0]) fail(HHO_E_LOCAL_SINGULAR, "static condensation: local block not SPD in cell " + std::to_string(herr[0] - 1));
+  if (herr[1]) fail(HHO_E_LOCAL_SINGULAR, "smoother patch not invertible in cell " + std::to_string(herr[1] - 1));
+  if (herr[2]) fail(HHO_E_LOCAL_SINGULAR, "coarsest-level matrix is singular");
+}
+
+// ------------------------------------------------------------ V-cycle
+template <typename T>
+static void smooth(hho_problem *P, int l) {
+  hipStream_t s = P->stream;
+  const DLevel<T> D = LevSel<T>::op(P, l);
+  VBufs<T> &V = LevSel<T>::vb(P, l);
+  const int m = P->opt.smooth_its;
+  const int64_t n = D.N;
+  launch_precond<T>(P->tp, D, V.r, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
+  launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z1, V.w1, s);
+  if (m == 2) {
+    launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
+    launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s);
+  }
+  launch_mr2_dots<T>(n, m, V.w1, V.w2, V.r, P->partial, P->lev[l].y, P->counter + 0, s);
+  launch_mr2_update<T>(n, m, P->lev[l].y, V.z1, V.z2, V.w1, V.w2, V.w, V.r, s);
+}
+
+static void coarse_solve(hho_problem *P);
+
+// MG_V(l, b, 0): input lev[l] b, output lev[l] w
+template <typename T>
+static void vcycle(hho_problem *P, int l) {
+  hipStream_t s = P->stream;
+  const int Lc = P->nlev - 1;
+  const DLevel<T> D = LevSel<T>::op(P, l);
+  VBufs<T> &V = LevSel<T>::vb(P, l);
+  const LevelInfo &A = P->lev[l], &B = P->lev[l + 1];
+  const int d = P->d, nf = (int)P->mesh->nf, nc = (int)P->mesh->nc;
+  launch_fill<T>(D.N, (T)0, V.w, s);
+  launch_copy<T>(D.N, V.b, V.r, s);
+  smooth<T>(P, l);
+  if (l + 1 == Lc) {
+    launch_restrict<double, T>(d, nf, nc, A.p, A.t, B.p, B.t, V.r, P->lev[Lc].v64.b, s);
+    coarse_solve(P);
+    launch_prolong_add<double, T>(d, nf, nc, A.p, A.t, B.p, B.t, P->lev[Lc].v64.w, V.w, s);
+  } else {
+    VBufs<T> &W = LevSel<T>::vb(P, l + 1);
+    launch_restrict<T, T>(d, nf, nc, A.p, A.t, B.p, B.t, V.r, W.b, s);
+    vcycle<T>(P, l + 1);
+    launch_prolong_add<T, T>(d, nf, nc, A.p, A.t, B.p, B.t, W.w, V.w, s);
+  }
+  launch_residual<T>(P->tp, D, V.b, V.w, V.r, s);
+  smooth<T>(P, l);
+}
+
+static void read_state(hho_problem *P, GmresState *dst) {
+  HIPCHK(hipMemcpyAsync(P->h_st, dst, sizeof(GmresState), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+}
+
+static void set_rtol(hho_problem *P, GmresState *st, double rtol) {
+  HIPCHK(hipMemcpyAsync(&st->rtol, &rtol, sizeof(double), hipMemcpyHostToDevice, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+}
+
+// coarsest level: lev[Lc].v64.b -> lev[Lc].v64.w (FP64)
+static int64_t g_coarse_its = 0;
+static void coarse_solve(hho_problem *P) {
+  hipStream_t s = P->stream;
+  const int Lc = P->nlev - 1;
+  LevelInfo &L = P->lev[Lc];
+  VBufs<double> &V = L.v64;
+  if (P->coarse_dense) {
+    launch_dense_matvec(P->dense, P->dense_n, 2 * P->dense_n, P->border, V.b, V.w, s);
+    return;
+  }
+  const DLevel<double> D = dlev64(P, Lc);
+  const int64_t n = L.N;
+  const int R = P->opt.coarse_restart;
+  GmresState *st = P->cst;
+  launch_fill<double>(n, 0.0, V.w, s);
+  launch_norm_init<double>(n, V.b, P->partial, st, P->counter + 1, 1, s);
+  launch_scale<double>(n, V.b, &st->inv_hnext, P->cV, s);
+  read_state(P, st);
+  int its = 0;
+  const int chunk = 6;
+  while (!P->h_st->done && its < P->opt.coarse_max_it) {
+    // one restart cycle; the host looks at the device state every `chunk` columns
+    const int jmax = std::min(R, P->opt.coarse_max_it - its);
+    for (int j = 0; j < jmax; ++j) {
+      double *vj = P->cV + (int64_t)j * n;
+      launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
+      launch_spmv<double>(P->tp, D, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+      launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 2, s);
+      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 3, 1, s);
+      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 4, 2, s);
+      launch_scale<double>(n, P->cw, &st->inv_hnext, P->cV + (int64_t)(j + 1) * n, s);
+      if ((j + 1) % chunk == 0 || j + 1 == jmax) {
+        read_state(P, st);
+        if (P->h_st->done) break;
+      }
+    }
+    its += P->h_st->j;
+    launch_gmres_solve_ls(st, s);
+    launch_gmres_combine<double>(n, P->cZ, n, st, V.w, s);
+    if (P->h_st->nan) fail(HHO_E_BREAKDOWN, "coarse GMRES: non-finite value");
+    if (P->h_st->res <= P->h_st->rtol * P->h_st->bnorm || its >= P->opt.coarse_max_it) break;
+    // restart from the true residual
+    launch_residual<double>(P->tp, D, V.b, V.w, P->cr, s);
+    launch_norm_init<double>(n, P->cr, P->partial, st, P->counter + 1, 0, s);
+    launch_scale<double>(n, P->cr, &st->inv_hnext, P->cV, s);
+    read_state(P, st);
+  }
+  g_coarse_its += its;
+}
+
+// x = V-cycle(b) on level 0, b and x FP64 (device)
+static void apply_vcycle(hho_problem *P, const double *b, double *x) {
+  hipStream_t s = P->stream;
+  LevelInfo &L0 = P->lev[0];
+  if (P->nlev == 1) {
+    launch_copy<double>(L0.N, b, L0.v64.b, s);
+    coarse_solve(P);
+    launch_copy<double>(L0.N, L0.v64.w, x, s);
+    return;
+  }
+  if (P->opt.precision == HHO_PREC_FP32) {
+    launch_convert<float, double>(b, L0.v32.b, L0.N, s);
+    vcycle<float>(P, 0);
+    launch_convert<double, float>(L0.v32.w, x, L0.N, s);
+  } else {
+    launch_copy<double>(L0.N, b, L0.v64.b, s);
+    vcycle<double>(P, 0);
+    launch_copy<double>(L0.N, L0.v64.w, x, s);
+  }
+}
+
+// ------------------------------------------------------------ FGMRES
+static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int hist_cap, double *final_rel) {
+  hipStream_t s = P->stream;
+  const DLevel<double> D = dlev64(P, 0);
+  const int64_t n = D.N;
+  const int R = P->opt.restart;
+  GmresState *st = P->ost;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  g_coarse_its = 0;
+  // b <- b - (b.z / z.z) z  (consistent right-hand side when the pressure is defined up to a constant)
+  launch_copy<double>(n, P->rhs, P->ob, s);
+  if (P->border) {
+    launch_dot<double>(n, P->ob, P->zvec, P->partial, P->scal + 0, P->counter + 5, s);
+    launch_dot<double>(n, P->zvec, P->zvec, P->partial, P->scal + 1, P->counter + 5, s);
+    launch_axpy_ratio<double>(n, P->scal, -1.0, P->zvec, P->ob, s);
+  }
+  set_rtol(P, st, P->opt.rtol);
+  launch_fill<double>(n, 0.0, P->ox, s);
+  launch_norm_init<double>(n, P->ob, P->partial, st, P->counter + 6, 1, s);
+  launch_scale<double>(n, P->ob, &st->inv_hnext, P->oV, s);
+  read_state(P, st);
+  const double bnorm = P->h_st->bnorm;
+  int its = 0, nh = 0;
+  if (hist && hist_cap > 0) hist[nh++] = 1.0;
+  bool converged = bnorm == 0.0;
+  double rel = 0.0;
+  int nvc = 0;
+  while (!converged && its < P->opt.max_it) {
+    int j = 0;
+    for (; j < R && its < P->opt.max_it; ++j) {
+      double *vj = P->oV + (int64_t)j * n, *zj = P->oZ + (int64_t)j * n;
+      apply_vcycle(P, vj, zj);
+      ++nvc;
+      launch_spmv<double>(P->tp, D, zj, nullptr, nullptr, P->ow, s);
+      launch_arnoldi_dots<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 7, s);
+      launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 8, 1, s);
+      launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 9, 2, s);
+      launch_scale<double>(n, P->ow, &st->inv_hnext, P->oV + (int64_t)(j + 1) * n, s);
+      read_state(P, st);
+      ++its;
+      if (P->h_st->nan) fail(HHO_E_BREAKDOWN, "FGMRES: non-finite value");
+      if (hist && nh < hist_cap) hist[nh++] = P->h_st->res / bnorm;
+      if (P->h_st->done) {
+        ++j;
+        break;
+      }
+    }
+    launch_gmres_solve_ls(st, s);
+    launch_gmres_combine<double>(n, P->oZ, n, st, P->ox, s);
+    // true residual
+    launch_residual<double>(P->tp, D, P->ob, P->ox, P->or_, s);
+    launch_norm_init<double>(n, P->or_, P->partial, st, P->counter + 6, 0, s);
+    launch_scale<double>(n, P->or_, &st->inv_hnext, P->oV, s);
+    read_state(P, st);
+    rel = P->h_st->beta / bnorm;
+    if (!std::isfinite(rel)) fail(HHO_E_BREAKDOWN, "FGMRES: non-finite residual");
+    if (rel <= P->opt.rtol) converged = true;
+  }
+  // zero-mean pressure
+  if (P->border) {
+    launch_dot<double>(n, P->ox, P->zvec, P->partial, P->scal + 0, P->counter + 5, s);
+    launch_dot<double>(n, P->zvec, P->zvec, P->partial, P->scal + 1, P->counter + 5, s);
+    launch_axpy_ratio<double>(n, P->scal, -1.0, P->zvec, P->ox, s);
+  }
+  if (x_out) launch_copy<double>(n, P->ox, x_out, s);
+  HIPCHK(hipEventRecord(e1, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  P->timings[5] = ms;
+  P->timings[7] = nvc;
+  P->timings[8] = (double)g_coarse_its;
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  check_device_error(P, "solve");
+  if (iters) *iters = its;
+  if (final_rel) *final_rel = rel;
+  return converged ? HHO_OK : HHO_E_NOT_CONVERGED;
+}
+
+}  // namespace hho
+
+// ================================================================ C ABI
+#define ABI_BEGIN try {
+#define ABI_END                                                  \
+  }                                                              \
+  catch (const hho::Error &e) {                                  \
+    hho::set_error(e.msg);                                       \
+    return e.code;                                               \
+  }                                                              \
+  catch (const std::bad_alloc &) {                               \
+    hho::set_error("host allocation failed");                    \
+    return HHO_E_OOM;                                            \
+  }                                                              \
+  catch (const std::exception &e) {                              \
+    hho::set_error(e.what());                                    \
+    return HHO_E_INVALID_ARG;                                    \
+  }
+
+extern "C" {
+
+const char *hho_last_error(void) { return hho::g_last_error.c_str(); }
+
+void hho_options_default(hho_options *o) {
+  if (!o) return;
+  o->eta = 0;
+  o->rtol = 1e-8;
+  o->max_it = 1000;
+  o->restart = 30;
+  o->smooth_its = 2;
+  o->precision = HHO_PREC_FP64;
+  o->coarse_mode = HHO_COARSE_AUTO;
+  o->coarse_rtol = 1e-3;
+  o->coarse_restart = 30;
+  o->coarse_max_it = 300;
+  o->quad_extra = 6;
+}
+
+int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
+  ABI_BEGIN
+  if (!out) hho::fail(HHO_E_INVALID_ARG, "mesh_create: out is NULL");
+  *out = nullptr;
+  auto m = std::make_unique<hho_mesh>();
+  hho::build_mesh(desc, m.get());
+  *out = m.release();
+  return HHO_OK;
+  ABI_END
+}
+
+void hho_mesh_destroy(hho_mesh *m) { delete m; }
+
+int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const int *degrees, const hho_options *opt,
+                       hho_problem **out) {
+  ABI_BEGIN
+  if (!out || !mesh) hho::fail(HHO_E_INVALID_ARG, "problem_create: NULL argument");
+  *out = nullptr;
+  if (k < 0 || k > 6) hho::fail(HHO_E_INVALID_ARG, "problem_create: k must be in 0..6");
+  if (cond != HHO_COND_V && cond != HHO_COND_VP) hho::fail(HHO_E_INVALID_ARG, "problem_create: bad condensation");
+  auto P = std::make_unique<hho_problem>();
+  P->mesh = mesh;
+  P->k = k;
+  P->cond = cond;
+  P->d = mesh->dim;
+  if (opt)
+    P->opt = *opt;
+  else
+    hho_options_default(&P->opt);
+  if (degrees) {
+    if (nlev < 1 || degrees[0] != k) hho::fail(HHO_E_INVALID_ARG, "problem_create: degrees[0] must equal k");
+    for (int i = 0; i < nlev; ++i) {
+      if (degrees[i] < 0 || (i > 0 && degrees[i] >= degrees[i - 1]))
+        hho::fail(HHO_E_INVALID_ARG, "problem_create: degrees must be strictly decreasing and >= 0");
+      P->deg.push_back(degrees[i]);
+    }
+  } else {
+    for (int kk = k; kk >= 0; --kk) P->deg.push_back(kk);
+  }
+  P->nlev = (int)P->deg.size();
+  if (P->opt.restart < 1 || P->opt.restart > hho::kMaxRestartH) hho::fail(HHO_E_INVALID_ARG, "restart must be in 1..64");
+  if (P->opt.coarse_restart < 1 || P->opt.coarse_restart > hho::kMaxRestartH)
+    hho::fail(HHO_E_INVALID_ARG, "coarse_restart must be in 1..64");
+  if (P->opt.smooth_its < 1 || P->opt.smooth_its > 2) hho::fail(HHO_E_INVALID_ARG, "smooth_its must be 1 or 2");
+  if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
+    hho::fail(HHO_E_INVALID_ARG, "bad precision");
+  if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
+  if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol > 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
+  const int d = P->d;
+  P->eta = P->opt.eta > 0 ? P->opt.eta : 4.0 * (k + 1) * (k + d) / d * mesh->max_faces;
+  hho::build_topology(P.get());
+  hho::init_levels(P.get());
+  const int nT = hho::dim_poly(d, k), nF = hho::dim_poly(d - 1, k);
+  P->lds_condense = hho::condense_lds_bytes(d, cond, nT, nF, mesh->max_faces);
+  if (P->lds_condense > 64 * 1024)
+    hho::fail(HHO_E_INVALID_ARG, "cell too large for the condensation kernel's LDS budget");
+  *out = P.release();
+  return HHO_OK;
+  ABI_END
+}
+
+void hho_problem_destroy(hho_problem *p) {
+  if (!p) return;
+  if (p->h_st) (void)hipHostFree(p->h_st);
+  delete p;
+}
+
+int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_field_fn gN, void *ctx) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "set_data: NULL problem");
+  int qdeg = 2 * p->k + 2 + std::max(0, p->opt.quad_extra);
+  hho::build_local(p->mesh, p->k, p->eta, qdeg, f, gD, gN, ctx, &p->loc);
+  p->have_data = true;
+  p->setup_done = false;
+  hho::Arena A;
+  hho::plan(p, A);
+  p->need = A.off + 256;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_workspace_size(const hho_problem *p, size_t *bytes) {
+  ABI_BEGIN
+  if (!p || !bytes) hho::fail(HHO_E_INVALID_ARG, "workspace_size: NULL argument");
+  if (!p->have_data) hho::fail(HHO_E_INVALID_ARG, "workspace_size: call hho_problem_set_data first");
+  *bytes = p->need;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_bind_workspace(hho_problem *p, void *dev_ptr, size_t bytes) {
+  ABI_BEGIN
+  if (!p || !dev_ptr) hho::fail(HHO_E_INVALID_ARG, "bind_workspace: NULL argument");
+  if (!p->have_data) hho::fail(HHO_E_INVALID_ARG, "bind_workspace: call hho_problem_set_data first");
+  if (bytes < p->need) {
+    hho::set_error("bind_workspace: buffer too small");
+    return HHO_E_CAPACITY;
+  }
+  hho::Arena A;
+  A.base = (char *)(((uintptr_t)dev_ptr + 255) & ~(uintptr_t)255);
+  hho::plan(p, A);
+  p->ws = (char *)dev_ptr;
+  p->ws_bytes = bytes;
+  p->bound = true;
+  p->setup_done = false;
+  if (!p->h_st) HIPCHK(hipHostMalloc((void **)&p->h_st, sizeof(hho::GmresState)));
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_set_stream(hho_problem *p, void *stream) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "set_stream: NULL problem");
+  p->stream = (hipStream_t)stream;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_setup(hho_problem *p) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "setup: NULL problem");
+  if (!p->have_data) hho::fail(HHO_E_INVALID_ARG, "setup: call hho_problem_set_data first");
+  if (!p->bound) hho::fail(HHO_E_INVALID_ARG, "setup: no workspace bound");
+  p->setup_done = false;
+  hho::device_setup(p);
+  hho::set_rtol(p, p->cst, p->opt.coarse_rtol);
+  p->setup_done = true;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_level_size(const hho_problem *p, int level, int64_t *n) {
+  ABI_BEGIN
+  if (!p || !n || level < 0 || level >= p->nlev) hho::fail(HHO_E_INVALID_ARG, "level_size: bad argument");
+  *n = p->lev[level].N;
+  return HHO_OK;
+  ABI_END
+}
+
+static void need_setup(const hho_problem *p) {
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "NULL problem");
+  if (!p->setup_done) hho::fail(HHO_E_INVALID_ARG, "call hho_setup first");
+}
+
+int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel) {
+  ABI_BEGIN
+  need_setup(p);
+  return hho::fgmres(p, x_dev, iters, hist, hist_cap, final_rel);
+  ABI_END
+}
+
+int hho_get_rhs(hho_problem *p, double *b_dev) {
+  ABI_BEGIN
+  need_setup(p);
+  if (!b_dev) hho::fail(HHO_E_INVALID_ARG, "get_rhs: NULL");
+  hho::launch_copy<double>(p->lev[0].N, p->rhs, b_dev, p->stream);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B, double *ru, double *rp, int64_t cap,
+                       int64_t *nloc_out) {
+  ABI_BEGIN
+  if (!p || !p->have_data) hho::fail(HHO_E_INVALID_ARG, "get_local_cell: no data");
+  if (cell < 0 || cell >= p->mesh->nc) hho::fail(HHO_E_INVALID_ARG, "get_local_cell: cell out of range");
+  const int nloc = p->loc.nloc[cell], d = p->d, nT = p->loc.nT;
+  if (nloc_out) *nloc_out = nloc;
+  if (cap < (int64_t)nloc * nloc || cap < (int64_t)d * nT * nloc) {
+    hho::set_error("get_local_cell: capacity too small");
+    return HHO_E_CAPACITY;
+  }
+  const double *r = &p->loc.rec[p->loc.off[cell]];
+  if (a) std::memcpy(a, r, sizeof(double) * nloc * nloc);
+  r += (int64_t)nloc * nloc;
+  if (B) std::memcpy(B, r, sizeof(double) * d * nT * nloc);
+  r += (int64_t)d * nT * nloc;
+  if (ru) std::memcpy(ru, r, sizeof(double) * d * nloc);
+  r += (int64_t)d * nloc;
+  if (rp) std::memcpy(rp, r, sizeof(double) * nT);
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_get_condensed_cell(hho_problem *p, int64_t cell, double *S, double *rhs, int64_t cap, int64_t *n_out) {
+  ABI_BEGIN
+  need_setup(p);
+  if (cell < 0 || cell >= p->mesh->nc) hho::fail(HHO_E_INVALID_ARG, "get_condensed_cell: cell out of range");
+  const hho::LevelInfo &L = p->lev[0];
+  const int d = p->d, nfc = p->cptr[cell + 1] - p->cptr[cell];
+  const int nd = nfc * d * L.p, n = nd + L.t;
+  if (n_out) *n_out = n;
+  if (cap < (int64_t)n * n) {
+    hho::set_error("get_condensed_cell: capacity too small");
+    return HHO_E_CAPACITY;
+  }
+  // The per-cell condensed face block lives only in the condensation staging
+  // array, which the smoother setup reuses as scratch: condense again (the
+  // kernel is deterministic, so every other output is rewritten unchanged; the
+  // pressure part of the right-hand side goes to the outer solver's scratch).
+  std::vector<double> h((size_t)n * n, 0.0), hr(n, 0.0);
+  hipStream_t s = p->stream;
+  const int bs = L.bs;
+  const int64_t so = p->pairoff[cell] * bs * bs;
+  hho::launch_condense(p->tp, p->cond, p->loc.nT, p->loc.nF, p->rec, p->roff, p->stage, L.cpl, L.spp, p->rhs_stage,
+                       p->ow, p->err, s, p->lds_condense);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  std::vector<double> blk((size_t)nfc * nfc * bs * bs);
+  HIPCHK(hipMemcpy(blk.data(), p->stage + so, blk.size() * 8, hipMemcpyDeviceToHost));
+  const int p_ = L.p, t = L.t;
+  if (p->cond == HHO_COND_V) {
+    const int m = nfc * p_;
+    for (int i = 0; i < m; ++i)
+      for (int j = 0; j < m; ++j)
+        for (int c = 0; c < d; ++c) {
+          int ri = ((i / p_) * d + c) * p_ + i % p_, rj = ((j / p_) * d + c) * p_ + j % p_;
+          h[(size_t)ri * n + rj] = blk[(size_t)i * m + j];
+        }
+  } else {
+    for (int i = 0; i < nd; ++i)
+      for (int j = 0; j < nd; ++j) h[(size_t)i * n + j] = blk[(size_t)i * nd + j];
+  }
+  const int64_t cw = p->cond == HHO_COND_V ? (int64_t)nd * t : nd;
+  std::vector<double> C(cw);
+  HIPCHK(hipMemcpy(C.data(), L.cpl + (int64_t)p->cptr[cell] * d * p_ * (p->cond == HHO_COND_V ? t : 1), cw * 8,
+                   hipMemcpyDeviceToHost));
+  for (int i = 0; i < nd; ++i)
+    for (int q = 0; q < t; ++q) {
+      double v = p->cond == HHO_COND_V ? C[(size_t)i * t + q] : C[i];
+      h[(size_t)i * n + nd + q] = v;
+      h[(size_t)(nd + q) * n + i] = v;
+    }
+  if (p->cond == HHO_COND_V) {
+    std::vector<double> Pp((size_t)t * t);
+    HIPCHK(hipMemcpy(Pp.data(), L.spp + (int64_t)cell * t * t, Pp.size() * 8, hipMemcpyDeviceToHost));
+    for (int q = 0; q < t; ++q)
+      for (int q2 = 0; q2 < t; ++q2) h[(size_t)(nd + q) * n + nd + q2] = Pp[(size_t)q * t + q2];
+  }
+  HIPCHK(hipMemcpy(hr.data(), p->rhs_stage + (int64_t)p->cptr[cell] * d * p_, nd * 8, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(hr.data() + nd, p->ow + (int64_t)cell * t, t * 8, hipMemcpyDeviceToHost));
+  if (S) std::memcpy(S, h.data(), h.size() * 8);
+  if (rhs) std::memcpy(rhs, hr.data(), hr.size() * 8);
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_level_apply(hho_problem *p, int level, const double *x, double *y) {
+  ABI_BEGIN
+  need_setup(p);
+  if (level < 0 || level >= p->nlev || !x || !y) hho::fail(HHO_E_INVALID_ARG, "level_apply: bad argument");
+  hho::launch_spmv<double>(p->tp, hho::dlev64(p, level), x, nullptr, nullptr, y, p->stream);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_precond_apply(hho_problem *p, int level, const double *r, double *z) {
+  ABI_BEGIN
+  need_setup(p);
+  if (level < 0 || level >= p->nlev || !r || !z) hho::fail(HHO_E_INVALID_ARG, "precond_apply: bad argument");
+  const hho::LevelInfo &L = p->lev[level];
+  if (!L.sinv) hho::fail(HHO_E_INVALID_ARG, "precond_apply: this level has no smoother (dense coarse level)");
+  double *zs1 = p->ow;  // level-0 length covers the face part of every level
+  hho::launch_precond<double>(p->tp, hho::dlev64(p, level), r, nullptr, nullptr, z, zs1, p->max_faces, p->stream);
+  hho::launch_combine<double>(L.nface, zs1, z, p->stream);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_vcycle_apply(hho_problem *p, const double *b, double *x) {
+  ABI_BEGIN
+  need_setup(p);
+  if (!b || !x) hho::fail(HHO_E_INVALID_ARG, "vcycle_apply: NULL");
+  hho::apply_vcycle(p, b, x);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_get_timings(const hho_problem *p, double *t, int n) {
+  ABI_BEGIN
+  if (!p || !t) hho::fail(HHO_E_INVALID_ARG, "get_timings: NULL");
+  for (int i = 0; i < n && i < 16; ++i) t[i] = p->timings[i];
+  return HHO_OK;
+  ABI_END
+}
+
+}  // extern "C"
