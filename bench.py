@@ -1,0 +1,207 @@
+"""Benchmark: one step = the whole hot path on one synthetic problem --
+static condensation of every cell, assembly of the face-block operator,
+inheritance of the coarse levels k-1..0, smoother-patch and coarse-solver
+setup, and the FGMRES + p-multilevel V-cycle solve to a 1e-8 relative residual.
+Inputs (mesh topology and local HHO operators) are resident in device memory
+before the timed region starts.
+
+Default workload: 2D Lloyd-relaxed Voronoi mesh of the unit square with 16384
+cells, HHO degree k = 3 (face block 2(k+1) = 8), v-cond, V-cycle 3->2->1->0,
+seeded trig-series body force, homogeneous Dirichlet boundary, FP64.
+
+Prints one JSON line (see the metric/roofline/cpu_baseline fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-1e-8 residual & V-cycle GDOF/s: mixed/learned vs plain FP64, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "voronoi16384_k3_v": dict(mesh="voronoi", n=16384, seed=2, k=3, cond="v"),
+    "voronoi16384_k3_vp": dict(mesh="voronoi", n=16384, seed=2, k=3, cond="vp"),
+    "quad8_k1_v": dict(mesh="quad", n=8, seed=1, k=1, cond="v"),
+}
+
+
+def make_mesh(spec):
+    from synth import voronoi_lloyd, cartesian_quads, cartesian_hexes
+    if spec["mesh"] == "voronoi":
+        return voronoi_lloyd(spec["n"], spec["seed"])
+    if spec["mesh"] == "quad":
+        return cartesian_quads(spec["n"])
+    return cartesian_hexes(spec["n"])
+
+
+def make_data(spec, dim):
+    from synth import trig_series, stokes_sincos_2d
+    from synth.fields import problem_data
+    if spec["mesh"] == "quad":
+        return problem_data(stokes_sincos_2d(), None, dim)
+    return problem_data(None, trig_series(dim, spec["seed"]), dim)
+
+
+def spmv_bytes(mesh, k, cond, level_k, dtype_bytes=8):
+    """Algorithmic bytes of one application of the level operator: every stored
+    value once, the int32 block structure, x read once and y written once."""
+    from math import comb
+    d = mesh.dim
+    p = comb(level_k + d - 1, d - 1)
+    t = comb(level_k + d, d) if cond == "v" else 1
+    bs = p if cond == "v" else d * p
+    cptr = np.asarray(mesh.cell_ptr)
+    nfc = np.diff(cptr)
+    fc = mesh.face_cells()
+    # face stencil rows: faces of the cells sharing each face
+    nnzb = 0
+    for f in range(mesh.n_faces):
+        cells = fc[f][fc[f] >= 0]
+        nnzb += int(sum(nfc[c] for c in cells) - (len(cells) - 1))
+    ncf = int(cptr[-1])
+    vals = nnzb * bs * bs + ncf * d * p * (t if cond == "v" else 1) + (mesh.n_cells * t * t if cond == "v" else 0)
+    N = mesh.n_faces * d * p + mesh.n_cells * t
+    idx = 4 * (nnzb + mesh.n_faces + 1 + ncf + mesh.n_cells + 1 + 4 * mesh.n_faces)
+    return vals * dtype_bytes + idx + 2 * N * dtype_bytes, dict(nnzb=nnzb, N=N, values=vals)
+
+
+def cpu_baseline(spec, sample_cells=1024):
+    """The oracle as it stands, end to end (local operators, condensation,
+    assembly, levels, Schwarz setup, FGMRES to 1e-8), on a smaller mesh of the
+    same family; reported in the metric's unit (fine DOFs solved per second)."""
+    from threadpoolctl import threadpool_limits
+    import oracle.solve as OS
+    from synth import voronoi_lloyd, cartesian_quads
+    if spec["mesh"] == "voronoi":
+        mesh = voronoi_lloyd(sample_cells, spec["seed"])
+        name = f"voronoi{sample_cells}_k{spec['k']}_{spec['cond']}"
+    else:
+        mesh = cartesian_quads(spec["n"])
+        name = f"quad{spec['n']}_k{spec['k']}_{spec['cond']}"
+    data = make_data(spec, mesh.dim)
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        P = OS.build(mesh, spec["k"], spec["cond"], data)
+        x, its, hist, conv = OS.solve_fgmres(P, rtol=1e-8, coarse="gmres", coarse_rtol=1e-3)
+        dt = time.perf_counter() - t0
+    n0 = P.S[0].shape[0]
+    return {"value": n0 / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
+            "sample": f"{name}: {n0} fine DOFs, {its} FGMRES its, {dt:.1f} s single-thread (NumPy/SciPy FP64)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="voronoi16384_k3_v", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--coarse-rtol", type=float, default=1e-3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU sharding is a design, see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2009_13840_amd as H
+
+    spec = WORKLOADS[args.workload]
+    t_mesh = time.perf_counter()
+    mesh = make_mesh(spec)
+    data = make_data(spec, mesh.dim)
+    t_mesh = time.perf_counter() - t_mesh
+    print(f"[bench] workload {args.workload}: {mesh.n_cells} cells, {mesh.n_faces} faces "
+          f"(mesh {t_mesh:.1f}s)", file=sys.stderr, flush=True)
+    M = H.Mesh(mesh)
+    P = H.Problem(M, spec["k"], spec["cond"], precision=args.precision, coarse_rtol=args.coarse_rtol)
+    t_host = time.perf_counter()
+    P.set_data(*data)
+    t_host = time.perf_counter() - t_host
+    P.bind("cuda:0")
+    P.upload()
+    torch.cuda.synchronize()
+    n0 = P.level_size(0)
+    print(f"[bench] host local operators {t_host:.2f}s, workspace {P.workspace_size() / 2**30:.2f} GiB, "
+          f"fine DOFs {n0}", file=sys.stderr, flush=True)
+
+    def step():
+        P.setup()
+        return P.solve()
+
+    for w in range(args.warmup):
+        _, its, _, rel, ok = step()
+        print(f"[bench] warmup {w}: its={its} rel={rel:.2e} ok={ok}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for s in range(args.steps):
+        x, its, hist, rel, ok = step()
+        results.append((its, rel, ok, P.timings()))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    for s, (its, rel, ok, tm) in enumerate(results):
+        print(f"[bench] step {s}: its={its} rel={rel:.2e} ok={ok} {json.dumps({k: round(v, 3) for k, v in tm.items()})}",
+              file=sys.stderr, flush=True)
+    its, rel, ok, tm = results[-1]
+    vc_gdofs = n0 * tm["vcycles"] / (tm["vcycle_ms"] / 1e3) / 1e9 if tm["vcycle_ms"] > 0 else None
+
+    # roofline of the dominant memory-bound kernel: the fine-level operator application
+    kind = 2  # the V-cycle's operator application (two-slot input) on level 0
+    avg_ms = P.time_kernel(kind, 0, args.kernel_reps)
+    elem = 4 if args.precision == "fp32" else 8
+    nbytes, info = spmv_bytes(mesh, spec["k"], spec["cond"], spec["k"], elem)
+    nbytes += info["N"] * elem  # second slot of the input face part + combined write of the input
+    achieved = nbytes / (avg_ms / 1e3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_spmv (level 0, V-cycle form)", "bytes_per_launch": int(nbytes),
+            "avg_launch_ms": round(avg_ms, 5)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(spec)
+        except Exception as e:  # pragma: no cover
+            cpu = {"error": repr(e)}
+
+    out = {
+        "metric": METRIC,
+        "value": round(n0 / dt / 1e9, 6),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 V-cycle / f64 outer",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "cells": mesh.n_cells, "faces": mesh.n_faces, "k": spec["k"],
+                   "cond": spec["cond"], "levels": list(range(spec["k"], -1, -1)), "fine_dofs": n0,
+                   "rtol": 1e-8, "coarse": "gmres 1e-3" if n0 > 4096 else "dense"},
+        "time_to_1e8_ms": round(dt * 1e3, 3),
+        "fgmres_its": its,
+        "final_rel_residual": rel,
+        "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
+        "phase_ms": {k: round(v, 3) for k, v in tm.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -156,6 +156,12 @@ int hho_workspace_size(const hho_problem *p, size_t *bytes);
 int hho_bind_workspace(hho_problem *p, void *dev_ptr, size_t bytes);
 int hho_set_stream(hho_problem *p, void *hip_stream);
 
+/* Copies the mesh topology and the local operators to the bound workspace
+ * (host -> device).  hho_setup calls it when it has not been called; calling it
+ * first keeps the transfer out of a timed setup.  Errors: HHO_E_INVALID_ARG,
+ * HHO_E_DEVICE. */
+int hho_upload(hho_problem *p);
+
 /* Device setup: copies the local operators to the device, condenses every cell
  * (eq. ST.1 or ST.2, FP64 Cholesky of the local blocks), assembles the face-block
  * sparse operator, inherits the coarse levels by sub-block extraction
@@ -202,6 +208,13 @@ int hho_precond_apply(hho_problem *p, int level, const double *r_dev, double *z_
 /* x = MG_V(0, b, 0): one V-cycle from a zero initial guess, in the problem's
  * V-cycle precision (device vectors, FP64, global layout). */
 int hho_vcycle_apply(hho_problem *p, const double *b_dev, double *x_dev);
+
+/* Average duration in ms of `reps` back-to-back launches, bracketed by HIP
+ * events on the problem's stream, of one kernel on level `level`:
+ * kind 0 = FP64 operator application y = S_l x, 1 = FP64 Schwarz preconditioner,
+ * 2 = the V-cycle's operator application (two-slot input, V-cycle precision),
+ * 3 = one full V-cycle from level 0.  Inputs are fixed internal vectors. */
+int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_ms);
 
 /* Phase timings of the last hho_setup / hho_solve in milliseconds (device
  * events): [0] condensation, [1] assembly, [2] levels, [3] smoother setup,

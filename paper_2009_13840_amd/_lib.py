@@ -25,7 +25,8 @@ COARSE = {"auto": 0, "dense": 1, "gmres": 2}
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
            "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_get_rhs", "hho_get_condensed_cell",
-           "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings"]
+           "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
+           "hho_time_kernel"]
 
 
 class HHOError(RuntimeError):
@@ -61,6 +62,9 @@ def load():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2009_13840_amd.build`")
+    # torch first: the library then binds to the HIP runtime torch already loaded
+    # (both carry the soname libamdhip64.so.7), so one runtime serves the process.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     P, I64, I32, D = C.c_void_p, C.c_int64, C.c_int, C.POINTER(C.c_double)
     sig = {
@@ -84,6 +88,8 @@ def load():
         "hho_precond_apply": ([P, I32, P, P], I32),
         "hho_vcycle_apply": ([P, P, P], I32),
         "hho_get_timings": ([P, D, I32], I32),
+        "hho_upload": ([P], I32),
+        "hho_time_kernel": ([P, I32, I32, I32, D], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -225,8 +231,16 @@ class Problem:
         _check(load().hho_set_stream(self.h, C.c_void_p(stream)))
         self.device = self.ws.device
 
+    def upload(self):
+        _check(load().hho_upload(self.h))
+
     def setup(self):
         _check(load().hho_setup(self.h))
+
+    def time_kernel(self, kind: int, level: int = 0, reps: int = 20) -> float:
+        ms = C.c_double()
+        _check(load().hho_time_kernel(self.h, kind, level, reps, C.byref(ms)))
+        return ms.value
 
     def level_size(self, l: int) -> int:
         n = C.c_int64()

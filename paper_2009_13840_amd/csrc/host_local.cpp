@@ -76,14 +76,14 @@ struct GL {
   std::vector<double> t, w;
 };
 const GL &gl(int n) {
-  static GL cache[40];
-  static bool init[40] = {false};
+  // built once, before any worker thread reads it (thread-safe static initialisation)
+  static const std::vector<GL> cache = [] {
+    std::vector<GL> c(40);
+    for (int i = 1; i < 40; ++i) gauss01(i, c[i].t, c[i].w);
+    return c;
+  }();
   if (n < 1) n = 1;
   if (n >= 40) fail(HHO_E_INVALID_ARG, "quadrature degree too high");
-  if (!init[n]) {
-    gauss01(n, cache[n].t, cache[n].w);
-    init[n] = true;
-  }
   return cache[n];
 }
 

@@ -99,6 +99,8 @@ struct hho_problem {
   // host mirrors
   GmresState *h_st = nullptr;  // pinned
   double timings[16] = {0};
+  bool uploaded = false;
+  std::vector<double> zhost;
   size_t lds_condense = 0, lds_patch = 0;
 };
 
@@ -339,11 +341,11 @@ static void check_device_error(hho_problem *P, const char *what) {
 }
 
 // ------------------------------------------------------------ setup
-static void device_setup(hho_problem *P) {
+static void device_upload(hho_problem *P) {
   hipStream_t s = P->stream;
-  const hho_mesh *m = P->mesh;
-  const int64_t nc = m->nc;
-  auto h2d = [&](void *dst, const void *src, size_t bytes) { HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s)); };
+  auto h2d = [&](void *dst, const void *src, size_t bytes) {
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s));
+  };
   h2d((void *)P->tp.cptr, P->cptr.data(), P->cptr.size() * 4);
   h2d((void *)P->tp.cface, P->cface.data(), P->cface.size() * 4);
   h2d((void *)P->tp.fcell, P->fcell.data(), P->fcell.size() * 4);
@@ -358,8 +360,22 @@ static void device_setup(hho_problem *P) {
   h2d(P->roff, P->loc.off.data(), P->loc.off.size() * 8);
   HIPCHK(hipMemsetAsync(P->counter, 0, P->ncounters * sizeof(int), s));
   HIPCHK(hipMemsetAsync(P->err, 0, 4 * sizeof(int), s));
+  // nullspace vector (constant pressure on the level-0 mean modes)
+  const LevelInfo &L0 = P->lev[0];
+  P->zhost.assign(L0.N, 0.0);
+  if (P->border)
+    for (int64_t c = 0; c < P->mesh->nc; ++c) P->zhost[L0.nface + c * L0.t] = P->zmean[c];
+  h2d(P->zvec, P->zhost.data(), P->zhost.size() * 8);
   HIPCHK(hipStreamSynchronize(s));
+  P->uploaded = true;
+}
 
+static void device_setup(hho_problem *P) {
+  hipStream_t s = P->stream;
+  const hho_mesh *m = P->mesh;
+  const int64_t nc = m->nc;
+  if (!P->uploaded) device_upload(P);
+  HIPCHK(hipMemsetAsync(P->err, 0, 4 * sizeof(int), s));
   hipEvent_t ev[8];
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
   HIPCHK(hipEventRecord(ev[0], s));
@@ -395,13 +411,6 @@ static void device_setup(hho_problem *P) {
     launch_densify(P->tp, dlev64(P, Lc), P->border, P->dense, 2 * n, s);
     launch_eye_right(P->dense, n, 2 * n, s);
     for (int64_t kk = 0; kk < n; ++kk) launch_gj_step(P->dense, n, 2 * n, kk, P->colbuf, P->err + 2, s);
-  }
-  // nullspace vector (constant pressure, level 0)
-  launch_fill<double>(L0.N, 0.0, P->zvec, s);
-  if (P->border) {
-    std::vector<double> zh(L0.N, 0.0);
-    for (int64_t c = 0; c < nc; ++c) zh[L0.nface + c * L0.t] = P->zmean[c];
-    h2d(P->zvec, zh.data(), zh.size() * 8);
   }
   // FP32 copies for the mixed-precision V-cycle
   if (P->opt.precision == HHO_PREC_FP32) {
@@ -595,11 +604,17 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
   bool converged = bnorm == 0.0;
   double rel = 0.0;
   int nvc = 0;
+  double vc_ms = 0;
+  hipEvent_t va, vb;
+  HIPCHK(hipEventCreate(&va));
+  HIPCHK(hipEventCreate(&vb));
   while (!converged && its < P->opt.max_it) {
     int j = 0;
     for (; j < R && its < P->opt.max_it; ++j) {
       double *vj = P->oV + (int64_t)j * n, *zj = P->oZ + (int64_t)j * n;
+      HIPCHK(hipEventRecord(va, s));
       apply_vcycle(P, vj, zj);
+      HIPCHK(hipEventRecord(vb, s));
       ++nvc;
       launch_spmv<double>(P->tp, D, zj, nullptr, nullptr, P->ow, s);
       launch_arnoldi_dots<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 7, s);
@@ -607,6 +622,11 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
       launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 9, 2, s);
       launch_scale<double>(n, P->ow, &st->inv_hnext, P->oV + (int64_t)(j + 1) * n, s);
       read_state(P, st);
+      {
+        float vms;
+        HIPCHK(hipEventElapsedTime(&vms, va, vb));
+        vc_ms += vms;
+      }
       ++its;
       if (P->h_st->nan) fail(HHO_E_BREAKDOWN, "FGMRES: non-finite value");
       if (hist && nh < hist_cap) hist[nh++] = P->h_st->res / bnorm;
@@ -638,7 +658,10 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
   float ms;
   HIPCHK(hipEventElapsedTime(&ms, e0, e1));
   P->timings[5] = ms;
+  P->timings[6] = vc_ms;
   P->timings[7] = nvc;
+  HIPCHK(hipEventDestroy(va));
+  HIPCHK(hipEventDestroy(vb));
   P->timings[8] = (double)g_coarse_its;
   HIPCHK(hipEventDestroy(e0));
   HIPCHK(hipEventDestroy(e1));
@@ -966,6 +989,76 @@ int hho_vcycle_apply(hho_problem *p, const double *b, double *x) {
   hho::apply_vcycle(p, b, x);
   HIPCHK(hipStreamSynchronize(p->stream));
   HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_upload(hho_problem *p) {
+  ABI_BEGIN
+  if (!p || !p->have_data || !p->bound) hho::fail(HHO_E_INVALID_ARG, "upload: needs data and a bound workspace");
+  hho::device_upload(p);
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_ms) {
+  ABI_BEGIN
+  need_setup(p);
+  if (level < 0 || level >= p->nlev || reps < 1 || !avg_ms) hho::fail(HHO_E_INVALID_ARG, "time_kernel: bad argument");
+  hipStream_t s = p->stream;
+  const hho::LevelInfo &L = p->lev[level];
+  const bool mixed = p->opt.precision == HHO_PREC_FP32 && level < p->nlev - 1;
+  if ((kind == 1 || kind == 2) && !L.sinv) hho::fail(HHO_E_INVALID_ARG, "time_kernel: level has no smoother");
+  // inputs: the level's operator applied to the outer solver's scratch vectors
+  hho::launch_fill<double>(L.N, 1.0, p->ox, s);
+  auto one = [&]() {
+    switch (kind) {
+      case 0:
+        hho::launch_spmv<double>(p->tp, hho::dlev64(p, level), p->ox, nullptr, nullptr, p->ow, s);
+        break;
+      case 1:
+        hho::launch_precond<double>(p->tp, hho::dlev64(p, level), p->ox, nullptr, nullptr, p->ow, p->or_,
+                                    p->max_faces, s);
+        break;
+      case 2:
+        if (mixed) {
+          const hho::VBufs<float> &V = p->lev[level].v32;
+          hho::launch_spmv<float>(p->tp, hho::dlev32(p, level), V.zs0, V.zs1, V.z1, V.w1, s);
+        } else {
+          const hho::VBufs<double> &V = p->lev[level].v64;
+          hho::launch_spmv<double>(p->tp, hho::dlev64(p, level), V.zs0, V.zs1, V.z1, V.w1, s);
+        }
+        break;
+      case 3:
+        hho::apply_vcycle(p, p->ox, p->ow);
+        break;
+      default:
+        hho::fail(HHO_E_INVALID_ARG, "time_kernel: unknown kind");
+    }
+  };
+  if (kind == 2) {  // defined inputs for the split operator
+    if (mixed) {
+      hho::launch_fill<float>(L.N, 1.0f, p->lev[level].v32.zs0, s);
+      hho::launch_fill<float>(L.nface, 0.0f, p->lev[level].v32.zs1, s);
+    } else {
+      hho::launch_fill<double>(L.N, 1.0, p->lev[level].v64.zs0, s);
+      hho::launch_fill<double>(L.nface, 0.0, p->lev[level].v64.zs1, s);
+    }
+  }
+  one();
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  HIPCHK(hipEventRecord(a, s));
+  for (int i = 0; i < reps; ++i) one();
+  HIPCHK(hipEventRecord(b, s));
+  HIPCHK(hipEventSynchronize(b));
+  float ms;
+  HIPCHK(hipEventElapsedTime(&ms, a, b));
+  HIPCHK(hipEventDestroy(a));
+  HIPCHK(hipEventDestroy(b));
+  HIPCHK(hipGetLastError());
+  *avg_ms = ms / reps;
   return HHO_OK;
   ABI_END
 }
