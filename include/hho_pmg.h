@@ -76,9 +76,11 @@ extern "C" {
 #define HHO_PREC_FP32   1
 
 /* coarsest-level solver */
-#define HHO_COARSE_AUTO   0   /* dense LU if the level has <= 4096 unknowns, else GMRES */
-#define HHO_COARSE_DENSE  1   /* bordered dense LU (FP64)                                */
-#define HHO_COARSE_GMRES  2   /* preconditioned GMRES to coarse_rtol                     */
+#define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns, else AMG when k_L = 0, else GMRES */
+#define HHO_COARSE_DENSE  1   /* bordered dense inverse (FP64)                                */
+#define HHO_COARSE_GMRES  2   /* GMRES to coarse_rtol, cell-patch Schwarz preconditioner      */
+#define HHO_COARSE_AMG    3   /* GMRES to coarse_rtol, block-triangular Stokes preconditioner
+                                 with a smoothed-aggregation velocity block (k_L = 0 only)     */
 
 /* face boundary flags in hho_mesh_desc.face_bc */
 #define HHO_FACE_INTERIOR   0
@@ -204,6 +206,18 @@ int hho_level_apply(hho_problem *p, int level, const double *x_dev, double *y_de
 
 /* z = M_l r: the level-l smoother preconditioner (cell-patch Schwarz), FP64. */
 int hho_precond_apply(hho_problem *p, int level, const double *r_dev, double *z_dev);
+
+/* z = block-triangular preconditioner of the coarsest level applied to v
+ * (device vectors of the coarsest level's size, FP64): pressure
+ * y_T = -v_T / S_T with S_T = sum_{(f,c) in T} C[(f,c),T]^2 / S[(f,c),(f,c)], velocity
+ * one smoothed-aggregation V-cycle on v_f - C y per component.  Only when the
+ * problem uses HHO_COARSE_AMG (explicitly or through AUTO). */
+int hho_coarse_prec_apply(hho_problem *p, const double *v, double *z);
+
+/* Host copy of an internal device array for inspection: name "amg_val",
+ * "amg_pval", "amg_dinv", "amg_lam", "amg_ainv" (AMG level `level`) or "sd"
+ * (pressure Schur approximation).  *n_out receives the length. */
+int hho_debug_copy(hho_problem *p, const char *name, int level, double *out, int64_t cap, int64_t *n_out);
 
 /* x = MG_V(0, b, 0): one V-cycle from a zero initial guess, in the problem's
  * V-cycle precision (device vectors, FP64, global layout). */

@@ -1,0 +1,103 @@
+"""Coarsest-level solver of the GPU library, replayed on the CPU (test
+infrastructure; see the package header).
+
+The paper solves the coarsest level with a sparse LU (2D) or ILU-GMRES to a
+three-orders-of-magnitude residual reduction (3D), Section 5.2.2.  The GPU
+library keeps the "GMRES to 1e-3" rule but preconditions it with a
+block-triangular Stokes preconditioner whose velocity block is approximated by
+one smoothed-aggregation AMG V-cycle.  This module is the plain definition of
+that preconditioner, used to check the GPU implementation:
+
+* scalar face operator  s[f,g] = (1/d) sum_c S[(f,c),(g,c)]   (coarsest level, k_L = 0)
+* aggregation: nodes in index order; an unaggregated node opens an aggregate
+  holding itself and its unaggregated neighbours (matrix pattern)
+* tentative prolongator T (0/1), lambda = max_i sum_j |A_ij| / A_ii,
+  P = T - (omega/lambda) D^{-1} A T with omega = 4/3, A_next = P^T A P,
+  down to <= 128 unknowns, then a dense inverse
+* V-cycle with nu damped-Jacobi sweeps (weight 2/3) before and after
+* pressure Schur approximation  S_T = sum_{(f,c)} C[(f,c),T]^2 / S[(f,c),(f,c)]
+* apply: y = -g / S_T,   x = V-cycle(f - C y) per velocity component.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+OMEGA_SA = 4.0 / 3.0
+OMEGA_JAC = 2.0 / 3.0
+COARSEST = 128
+
+
+def aggregate(A: sp.csr_matrix) -> np.ndarray:
+    n = A.shape[0]
+    agg = -np.ones(n, dtype=np.int64)
+    na = 0
+    for i in range(n):
+        if agg[i] >= 0:
+            continue
+        for j in A.indices[A.indptr[i]:A.indptr[i + 1]]:
+            if agg[j] < 0:
+                agg[j] = na
+        agg[i] = na
+        na += 1
+    return agg
+
+
+class SA:
+    def __init__(self, A: sp.csr_matrix, nu: int = 1):
+        self.nu = nu
+        self.levels = []
+        A = sp.csr_matrix(A)
+        A.sort_indices()
+        while A.shape[0] > COARSEST:
+            agg = aggregate(A)
+            na = int(agg.max()) + 1
+            if na >= A.shape[0]:
+                break
+            T = sp.csr_matrix((np.ones(A.shape[0]), (np.arange(A.shape[0]), agg)), shape=(A.shape[0], na))
+            D = A.diagonal()
+            lam = float(np.max(np.asarray(abs(A).sum(axis=1)).ravel() / D))
+            P = (T - (OMEGA_SA / lam) * (sp.diags(1.0 / D) @ A @ T)).tocsr()
+            self.levels.append((A, P, 1.0 / D))
+            A = (P.T @ A @ P).tocsr()
+            A.sort_indices()
+        self.Ainv = np.linalg.inv(A.toarray())
+        self.sizes = [L[0].shape[0] for L in self.levels] + [A.shape[0]]
+
+    def vcycle(self, r: np.ndarray, l: int = 0) -> np.ndarray:
+        if l == len(self.levels):
+            return self.Ainv @ r
+        A, P, Di = self.levels[l]
+        x = np.zeros_like(r)
+        for _ in range(self.nu):
+            x = x + OMEGA_JAC * Di * (r - A @ x)
+        x = x + P @ self.vcycle(P.T @ (r - A @ x), l + 1)
+        for _ in range(self.nu):
+            x = x + OMEGA_JAC * Di * (r - A @ x)
+        return x
+
+
+class BlockStokesPrec:
+    """Block-triangular preconditioner of the coarsest (k = 0) level."""
+
+    def __init__(self, S: sp.csr_matrix, nface_dofs: int, d: int, nu: int = 1):
+        S = sp.csr_matrix(S)
+        self.nf, self.d = nface_dofs, d
+        nfaces = nface_dofs // d
+        blocks = [S[c:nface_dofs:d][:, c:nface_dofs:d] for c in range(d)]
+        s = sum(blocks[1:], blocks[0]) / d
+        self.amg = SA(s.tocsr(), nu)
+        C = S[:nface_dofs, nface_dofs:].tocsc()
+        diagA = S.diagonal()[:nface_dofs]
+        Sd = np.asarray((C.multiply(C)).T @ (1.0 / diagA)).ravel()
+        Sd[~(Sd > 0)] = 1.0
+        self.Sd = Sd
+        self.C = C.tocsr()
+        del nfaces
+
+    def __call__(self, v: np.ndarray) -> np.ndarray:
+        f, g = v[:self.nf], v[self.nf:]
+        y = -g / self.Sd
+        rhs = (f - self.C @ y).reshape(-1, self.d)
+        x = np.stack([self.amg.vcycle(rhs[:, c]) for c in range(self.d)], axis=1).ravel()
+        return np.concatenate([x, y])

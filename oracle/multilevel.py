@@ -10,8 +10,10 @@ densely and added back with weight 1/card(T_F) on face unknowns (1/2 on interior
 faces) and 1 on pressure unknowns.
 
 Coarsest level: either a direct solve (bordered with the constant-pressure
-vector when the operator is singular) or GMRES with the same preconditioner to
-a relative tolerance (Section 5.2.2 uses LU in 2D and ILU-GMRES to 1e-3 in 3D).
+vector when the operator is singular), or GMRES to a relative tolerance
+(Section 5.2.2 uses LU in 2D and ILU-GMRES to 1e-3 in 3D) preconditioned by the
+same Schwarz method ("gmres") or by the block-triangular preconditioner with a
+smoothed-aggregation velocity block of ``oracle.amg`` ("amg", k_L = 0 only).
 """
 from __future__ import annotations
 
@@ -54,12 +56,15 @@ class Hierarchy:
     prec: list              # Schwarz per level (the coarsest too, for GMRES)
     z: list                 # constant-pressure vector per level or None
     smooth_its: int = 2
-    coarse: str = "direct"  # "direct" | "gmres"
+    coarse: str = "direct"  # "direct" | "gmres" | "amg"
     coarse_rtol: float = 1e-3
     coarse_restart: int = 30
     coarse_maxit: int = 500
     coarse_its: list = field(default_factory=list)
+    nface_dofs: list = field(default_factory=list)
+    dim: int = 2
     _lu: object = None
+    _amg: object = None
 
     @property
     def L(self):
@@ -86,8 +91,13 @@ class Hierarchy:
                 self._lu = spla.splu(Sb)
             rhs = np.concatenate([d, [0.0]]) if z is not None else d
             return self._lu.solve(rhs)[:S.shape[0]]
-        x, its = gmres_solve(lambda v: S @ v, self.prec[L], d, self.coarse_rtol,
-                             self.coarse_restart, self.coarse_maxit)
+        M = self.prec[L]
+        if self.coarse == "amg":
+            if self._amg is None:
+                from .amg import BlockStokesPrec
+                self._amg = BlockStokesPrec(S, self.nface_dofs[L], self.dim)
+            M = self._amg
+        x, its = gmres_solve(lambda v: S @ v, M, d, self.coarse_rtol, self.coarse_restart, self.coarse_maxit)
         self.coarse_its.append(its)
         return x
 

@@ -86,8 +86,10 @@ def solve_direct(P: Problem) -> np.ndarray:
 def hierarchy(P: Problem, smooth_its=2, coarse="direct", coarse_rtol=1e-3,
               coarse_restart=30, coarse_maxit=500) -> Hierarchy:
     precs = [Schwarz(S, P.mesh, lay) for S, lay in zip(P.S, P.lays)]
-    return Hierarchy(P.S, P.idx, precs, P.z, smooth_its, coarse, coarse_rtol,
-                     coarse_restart, coarse_maxit)
+    H = Hierarchy(P.S, P.idx, precs, P.z, smooth_its, coarse, coarse_rtol, coarse_restart, coarse_maxit)
+    H.nface_dofs = [lay.off for lay in P.lays]
+    H.dim = P.mesh.dim
+    return H
 
 
 def solve_fgmres(P: Problem, rtol=1e-8, restart=30, maxit=1000, H: Hierarchy | None = None, **hk):

@@ -20,13 +20,13 @@ ERRORS = {-1: "HHO_E_INVALID_ARG", -2: "HHO_E_MESH", -3: "HHO_E_LOCAL_SINGULAR",
           -5: "HHO_E_BREAKDOWN", -6: "HHO_E_DEVICE", -7: "HHO_E_CAPACITY", -8: "HHO_E_OOM"}
 COND = {"v": 1, "vp": 2}
 PREC = {"fp64": 0, "fp32": 1}
-COARSE = {"auto": 0, "dense": 1, "gmres": 2}
+COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
            "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_get_rhs", "hho_get_condensed_cell",
            "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
-           "hho_time_kernel"]
+           "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy"]
 
 
 class HHOError(RuntimeError):
@@ -90,6 +90,8 @@ def load():
         "hho_get_timings": ([P, D, I32], I32),
         "hho_upload": ([P], I32),
         "hho_time_kernel": ([P, I32, I32, I32, D], I32),
+        "hho_coarse_prec_apply": ([P, P, P], I32),
+        "hho_debug_copy": ([P, C.c_char_p, I32, D, I64, C.POINTER(I64)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -285,6 +287,17 @@ class Problem:
     def precond_apply(self, l, r):
         z = self._vec(self.level_size(l))
         _check(load().hho_precond_apply(self.h, l, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())))
+        return z
+
+    def debug_copy(self, name: str, level: int = 0):
+        n = C.c_int64()
+        out = np.zeros(1 << 22)
+        _check(load().hho_debug_copy(self.h, name.encode(), level, _dptr(out), out.size, C.byref(n)))
+        return out[:n.value].copy()
+
+    def coarse_prec_apply(self, v):
+        z = self._vec(self.level_size(self.nlev - 1))
+        _check(load().hho_coarse_prec_apply(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr())))
         return z
 
     def vcycle_apply(self, b):

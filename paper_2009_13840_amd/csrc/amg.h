@@ -1,0 +1,34 @@
+// Smoothed-aggregation hierarchy for the velocity block of the coarsest level.
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+#include "internal.h"
+
+namespace hho {
+
+constexpr double kAmgOmegaSA = 4.0 / 3.0;   // prolongator smoothing weight (divided by lambda)
+constexpr double kAmgOmegaJac = 2.0 / 3.0;  // damped-Jacobi smoother weight
+constexpr int kAmgCoarsest = 128;           // dense inverse at or below this size
+
+struct AmgHostLevel {
+  int n = 0, nc = 0;                     // rows; aggregates (0 on the coarsest level)
+  std::vector<int32_t> rp, ci, diag;     // A pattern, diagonal positions
+  std::vector<int32_t> agg;              // aggregate of every row
+  std::vector<int32_t> prp, pci;         // P pattern (n x nc)
+  std::vector<int32_t> pgp, pgi;         // A entries summed into each P entry
+  std::vector<int32_t> pself;            // 1 where the entry is the tentative injection
+  std::vector<int32_t> ptp, pti, pte;    // P^T by coarse row: fine row, P entry
+  std::vector<int32_t> brp, bci;         // B = A P pattern
+  std::vector<int32_t> bpp, bpa, bpb;    // B pairs (A entry, P entry)
+  std::vector<int32_t> cpp, cpa, cpb;    // next A pairs (P entry, B entry)
+};
+
+struct AmgHost {
+  std::vector<AmgHostLevel> levels;
+};
+
+void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, AmgHost *H);
+
+}  // namespace hho

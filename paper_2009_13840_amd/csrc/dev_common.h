@@ -54,6 +54,26 @@ __device__ inline bool last_block_arrived(int *counter) {
 
 __device__ inline double vload(const double *p) { return *(volatile const double *)p; }
 
+// Inside the last block: out[k] = sum_b partial[k*G + b] for k < K.  Waves take
+// the sums in turn, lanes split the G partials (parallel loads), the per-lane
+// order and the wave tree are fixed, so the result is deterministic.  `out` must
+// be visible to the whole block (LDS); a barrier ends the function.
+__device__ inline void reduce_partials(const double *partial, int G, int K, double *out) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  for (int k = wid; k < K; k += nw) {
+    double s = 0;
+    for (int b = lane; b < G; b += kWave) s += vload(&partial[(int64_t)k * G + b]);
+    s = wave_sum(s);
+    if (lane == 0) out[k] = s;
+  }
+  __syncthreads();
+}
+
+__device__ inline double wave_max(double v) {
+  for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
+  return v;
+}
+
 template <typename T>
 struct VT;
 template <>

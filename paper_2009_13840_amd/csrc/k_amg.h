@@ -1,0 +1,44 @@
+// Device-side smoothed-aggregation hierarchy (pointers into the workspace).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "amg.h"
+#include "device.h"
+
+namespace hho {
+
+constexpr int kMaxAmgLevels = 16;
+
+struct AmgDevLevel {
+  int n = 0, nc = 0;
+  int64_t nnz = 0, npe = 0, nbe = 0;
+  const int32_t *rp = nullptr, *ci = nullptr, *diag = nullptr;
+  double *val = nullptr, *dinv = nullptr, *lam = nullptr;
+  const int32_t *prp = nullptr, *pci = nullptr, *prow = nullptr, *pgp = nullptr, *pgi = nullptr, *pself = nullptr;
+  double *pval = nullptr;
+  const int32_t *ptp = nullptr, *pti = nullptr, *pte = nullptr;
+  const int32_t *bpp = nullptr, *bpa = nullptr, *bpb = nullptr;
+  double *bval = nullptr;
+  const int32_t *cpp = nullptr, *cpa = nullptr, *cpb = nullptr;
+  double *x = nullptr, *r = nullptr, *res = nullptr, *tmp = nullptr;  // [n][d]
+};
+
+struct AmgDev {
+  int nlev = 0;
+  AmgDevLevel lev[kMaxAmgLevels];
+  double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr;
+  int *counter = nullptr;
+};
+
+void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int *err,
+                       hipStream_t s);
+void bp_setup(const DTopo &tp, int cond, const int32_t *fdiag, const double *bsr, const double *cpl, double *Sd,
+              hipStream_t s);
+// z = block preconditioner applied to v (coarsest-level vectors in the global layout)
+void bp_apply(const DTopo &tp, const AmgDev &A, int64_t nface, const double *cpl, const double *Sd, const double *v,
+              double *z, int nu, hipStream_t s);
+
+}  // namespace hho

@@ -253,10 +253,9 @@ __global__ void __launch_bounds__(kBlock) k_mr2_dots(int64_t n, int m, const T *
     if (threadIdx.x == 0) partial[k * gridDim.x + blockIdx.x] = s;
   }
   if (last_block_arrived(counter)) {
+    __shared__ double S[5];
+    reduce_partials(partial, gridDim.x, 5, S);
     if (threadIdx.x == 0) {
-      double S[5] = {0, 0, 0, 0, 0};
-      for (int k = 0; k < 5; ++k)
-        for (unsigned b = 0; b < gridDim.x; ++b) S[k] += vload(&partial[k * gridDim.x + b]);
       double y1 = 0, y2 = 0;
       const double det = S[0] * S[2] - S[1] * S[1];
       if (m == 2 && det > 1e-14 * S[0] * S[2]) {
@@ -316,11 +315,9 @@ __global__ void __launch_bounds__(kBlock) k_arnoldi_dots(int64_t n, int j, const
   if (st->done) return;
   multi_dot_partial(n, j, V, ldv, w, partial);
   if (last_block_arrived(counter)) {
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-      double s = 0;
-      for (unsigned b = 0; b < gridDim.x; ++b) s += vload(&partial[(int64_t)i * gridDim.x + b]);
-      st->h1[i] = s;
-    }
+    __shared__ double hs[kMaxDots];
+    reduce_partials(partial, gridDim.x, j + 1, hs);
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) st->h1[i] = hs[i];
   }
 }
 
@@ -346,20 +343,19 @@ __global__ void __launch_bounds__(kBlock) k_arnoldi_update(int64_t n, int j, con
     __syncthreads();
     multi_dot_partial(n, j, V, ldv, (const T *)w, partial);
     if (last_block_arrived(counter)) {
-      for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-        double s = 0;
-        for (unsigned b = 0; b < gridDim.x; ++b) s += vload(&partial[(int64_t)i * gridDim.x + b]);
-        st->h2[i] = s;
-      }
+      __shared__ double hs[kMaxDots];
+      reduce_partials(partial, gridDim.x, j + 1, hs);
+      for (int i = threadIdx.x; i <= j; i += blockDim.x) st->h2[i] = hs[i];
     }
     return;
   }
   double s = block_sum(nrm, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
   if (last_block_arrived(counter)) {
+    __shared__ double nsum[1];
+    reduce_partials(partial, gridDim.x, 1, nsum);
     if (threadIdx.x == 0) {
-      double nn = 0;
-      for (unsigned b = 0; b < gridDim.x; ++b) nn += vload(&partial[b]);
+      const double nn = nsum[0];
       const int R = kMaxRestartH;
       double *H = st->H;
       for (int i = 0; i <= j; ++i) H[i * R + j] = st->h1[i] + st->h2[i];
@@ -406,9 +402,10 @@ __global__ void __launch_bounds__(kBlock) k_norm_init(int64_t n, const T *r, dou
   double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
   if (last_block_arrived(counter)) {
+    __shared__ double nsum[1];
+    reduce_partials(partial, gridDim.x, 1, nsum);
     if (threadIdx.x == 0) {
-      double nn = 0;
-      for (unsigned b = 0; b < gridDim.x; ++b) nn += vload(&partial[b]);
+      const double nn = nsum[0];
       const double beta = sqrt(nn);
       st->beta = beta;
       if (which == 1) st->bnorm = beta;
@@ -463,11 +460,9 @@ __global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const T *a, const T *
   double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
   if (last_block_arrived(counter)) {
-    if (threadIdx.x == 0) {
-      double v = 0;
-      for (unsigned bb = 0; bb < gridDim.x; ++bb) v += vload(&partial[bb]);
-      out[0] = v;
-    }
+    __shared__ double vs[1];
+    reduce_partials(partial, gridDim.x, 1, vs);
+    if (threadIdx.x == 0) out[0] = vs[0];
   }
 }
 
@@ -494,8 +489,8 @@ __global__ void k_copy(int64_t n, const T *x, T *y) {
 
 // ------------------------------------------------------------ wrappers
 int reduce_blocks(int64_t n) {
-  int64_t g = (n + kBlock - 1) / kBlock;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 512));
+  int64_t g = (n + 4 * kBlock - 1) / (4 * kBlock);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 256));
 }
 
 template <typename T>

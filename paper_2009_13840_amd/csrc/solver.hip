@@ -11,6 +11,7 @@
 #include "dev_common.h"
 #include "device.h"
 #include "internal.h"
+#include "k_amg.h"
 
 namespace hho {
 
@@ -100,6 +101,14 @@ struct hho_problem {
   GmresState *h_st = nullptr;  // pinned
   double timings[16] = {0};
   bool uploaded = false;
+  // coarsest-level block preconditioner (smoothed aggregation)
+  bool coarse_amg = false;
+  int amg_nu = 1;
+  std::vector<int32_t> fdiag;
+  int32_t *d_fdiag = nullptr;
+  double *Sd = nullptr;
+  AmgHost amgh;
+  AmgDev amgd;
   std::vector<double> zhost;
   size_t lds_condense = 0, lds_patch = 0;
 };
@@ -188,6 +197,55 @@ static void plan(hho_problem *P, Arena &A) {
     P->czs0 = A.take<double>(LC.N);
     P->czs1 = A.take<double>(LC.nface);
   }
+  // smoothed-aggregation hierarchy of the coarsest level
+  if (P->coarse_amg) {
+    P->d_fdiag = A.take<int32_t>(nf);
+    P->Sd = A.take<double>(nc);
+    AmgDev &D = P->amgd;
+    D.nlev = (int)P->amgh.levels.size();
+    for (int l = 0; l < D.nlev; ++l) {
+      const AmgHostLevel &H = P->amgh.levels[l];
+      AmgDevLevel &G = D.lev[l];
+      G.n = H.n;
+      G.nc = H.nc;
+      G.nnz = (int64_t)H.ci.size();
+      G.npe = (int64_t)H.pci.size();
+      G.nbe = (int64_t)H.bci.size();
+      G.rp = A.take<int32_t>(H.rp.size());
+      G.ci = A.take<int32_t>(H.ci.size());
+      G.diag = A.take<int32_t>(H.diag.size());
+      G.val = A.take<double>(G.nnz);
+      G.dinv = A.take<double>(G.n);
+      G.lam = A.take<double>(1);
+      G.x = A.take<double>((int64_t)G.n * d);
+      G.r = A.take<double>((int64_t)G.n * d);
+      G.res = A.take<double>((int64_t)G.n * d);
+      G.tmp = A.take<double>((int64_t)G.n * d);
+      if (H.nc > 0) {
+        G.prp = A.take<int32_t>(H.prp.size());
+        G.pci = A.take<int32_t>(H.pci.size());
+        G.prow = A.take<int32_t>(H.pci.size());
+        G.pgp = A.take<int32_t>(H.pgp.size());
+        G.pgi = A.take<int32_t>(H.pgi.size());
+        G.pself = A.take<int32_t>(H.pself.size());
+        G.pval = A.take<double>(G.npe);
+        G.ptp = A.take<int32_t>(H.ptp.size());
+        G.pti = A.take<int32_t>(H.pti.size());
+        G.pte = A.take<int32_t>(H.pte.size());
+        G.bpp = A.take<int32_t>(H.bpp.size());
+        G.bpa = A.take<int32_t>(H.bpa.size());
+        G.bpb = A.take<int32_t>(H.bpb.size());
+        G.bval = A.take<double>(G.nbe);
+        G.cpp = A.take<int32_t>(H.cpp.size());
+        G.cpa = A.take<int32_t>(H.cpa.size());
+        G.cpb = A.take<int32_t>(H.cpb.size());
+      }
+    }
+    const int nlast = P->amgh.levels.back().n;
+    D.ainv = A.take<double>((int64_t)nlast * nlast);
+    D.dense_scratch = A.take<double>((int64_t)nlast * nlast);
+    D.partial = A.take<double>(512);
+  }
   // outer FGMRES
   const int R = P->opt.restart;
   P->oV = A.take<double>((int64_t)(R + 1) * L0.N);
@@ -202,6 +260,7 @@ static void plan(hho_problem *P, Arena &A) {
   P->scal = A.take<double>(16);
   P->counter = A.take<int>(P->ncounters);
   P->err = A.take<int>(4);
+  P->amgd.counter = P->counter + 12;
 }
 
 static DLevel<double> dlev64(const hho_problem *P, int l) {
@@ -303,6 +362,11 @@ static void build_topology(hho_problem *P) {
         P->blksrc[6 * b + 3 * s + 2] = j;
       }
   }
+  P->fdiag.assign(nf, -1);
+  for (int64_t f = 0; f < nf; ++f) {
+    auto b0 = P->col.begin() + P->rowptr[f], b1 = P->col.begin() + P->rowptr[f + 1];
+    P->fdiag[f] = (int32_t)(std::lower_bound(b0, b1, (int32_t)f) - P->col.begin());
+  }
   P->zmean.resize(nc);
   for (int64_t c = 0; c < nc; ++c) P->zmean[c] = std::sqrt(m->cvol[c]);
   P->max_faces = m->max_faces;
@@ -332,6 +396,13 @@ static void init_levels(hho_problem *P) {
                     (P->opt.coarse_mode == HHO_COARSE_AUTO && nd <= 1024);
   if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
   P->dense_n = nd;
+  P->coarse_amg = !P->coarse_dense && (P->opt.coarse_mode == HHO_COARSE_AMG ||
+                                       (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
+  if (P->coarse_amg && LC.k != 0) fail(HHO_E_INVALID_ARG, "AMG coarse solver needs a coarsest degree of 0");
+  if (P->coarse_amg) {
+    amg_symbolic((int)P->mesh->nf, P->rowptr.data(), P->col.data(), kAmgCoarsest, &P->amgh);
+    if ((int)P->amgh.levels.size() > kMaxAmgLevels) fail(HHO_E_INVALID_ARG, "AMG hierarchy too deep");
+  }
 }
 
 static void check_device_error(hho_problem *P, const char *what) {
@@ -366,6 +437,36 @@ static void device_upload(hho_problem *P) {
   if (P->border)
     for (int64_t c = 0; c < P->mesh->nc; ++c) P->zhost[L0.nface + c * L0.t] = P->zmean[c];
   h2d(P->zvec, P->zhost.data(), P->zhost.size() * 8);
+  if (P->coarse_amg) {
+    h2d(P->d_fdiag, P->fdiag.data(), P->fdiag.size() * 4);
+    for (int l = 0; l < P->amgd.nlev; ++l) {
+      const AmgHostLevel &H = P->amgh.levels[l];
+      AmgDevLevel &G = P->amgd.lev[l];
+      h2d((void *)G.rp, H.rp.data(), H.rp.size() * 4);
+      h2d((void *)G.ci, H.ci.data(), H.ci.size() * 4);
+      h2d((void *)G.diag, H.diag.data(), H.diag.size() * 4);
+      if (H.nc > 0) {
+        std::vector<int32_t> prow(H.pci.size());
+        for (int i = 0; i < H.n; ++i)
+          for (int e = H.prp[i]; e < H.prp[i + 1]; ++e) prow[e] = i;
+        h2d((void *)G.prp, H.prp.data(), H.prp.size() * 4);
+        h2d((void *)G.pci, H.pci.data(), H.pci.size() * 4);
+        h2d((void *)G.prow, prow.data(), prow.size() * 4);
+        h2d((void *)G.pgp, H.pgp.data(), H.pgp.size() * 4);
+        h2d((void *)G.pgi, H.pgi.data(), H.pgi.size() * 4);
+        h2d((void *)G.pself, H.pself.data(), H.pself.size() * 4);
+        h2d((void *)G.ptp, H.ptp.data(), H.ptp.size() * 4);
+        h2d((void *)G.pti, H.pti.data(), H.pti.size() * 4);
+        h2d((void *)G.pte, H.pte.data(), H.pte.size() * 4);
+        h2d((void *)G.bpp, H.bpp.data(), H.bpp.size() * 4);
+        h2d((void *)G.bpa, H.bpa.data(), H.bpa.size() * 4);
+        h2d((void *)G.bpb, H.bpb.data(), H.bpb.size() * 4);
+        h2d((void *)G.cpp, H.cpp.data(), H.cpp.size() * 4);
+        h2d((void *)G.cpa, H.cpa.data(), H.cpa.size() * 4);
+        h2d((void *)G.cpb, H.cpb.data(), H.cpb.size() * 4);
+      }
+    }
+  }
   HIPCHK(hipStreamSynchronize(s));
   P->uploaded = true;
 }
@@ -412,6 +513,11 @@ static void device_setup(hho_problem *P) {
     launch_eye_right(P->dense, n, 2 * n, s);
     for (int64_t kk = 0; kk < n; ++kk) launch_gj_step(P->dense, n, 2 * n, kk, P->colbuf, P->err + 2, s);
   }
+  if (P->coarse_amg) {
+    const LevelInfo &LC = P->lev[Lc];
+    bp_setup(P->tp, P->cond, P->d_fdiag, LC.bsr, LC.cpl, P->Sd, s);
+    amg_numeric_setup(P->amgd, P->cond, P->d, LC.bs, P->nnzb, LC.bsr, P->err + 3, s);
+  }
   // FP32 copies for the mixed-precision V-cycle
   if (P->opt.precision == HHO_PREC_FP32) {
     for (int l = 0; l < Lc; ++l) {
@@ -444,6 +550,7 @@ static void device_setup(hho_problem *P) {
   if (herr[0]) fail(HHO_E_LOCAL_SINGULAR, "static condensation: local block not SPD in cell " + std::to_string(herr[0] - 1));
   if (herr[1]) fail(HHO_E_LOCAL_SINGULAR, "smoother patch not invertible in cell " + std::to_string(herr[1] - 1));
   if (herr[2]) fail(HHO_E_LOCAL_SINGULAR, "coarsest-level matrix is singular");
+  if (herr[3]) fail(HHO_E_LOCAL_SINGULAR, "AMG coarsest matrix is not SPD");
 }
 
 // ------------------------------------------------------------ V-cycle
@@ -528,8 +635,13 @@ static void coarse_solve(hho_problem *P) {
     const int jmax = std::min(R, P->opt.coarse_max_it - its);
     for (int j = 0; j < jmax; ++j) {
       double *vj = P->cV + (int64_t)j * n;
-      launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
-      launch_spmv<double>(P->tp, D, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+      if (P->coarse_amg) {
+        bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, P->cZ + (int64_t)j * n, P->amg_nu, s);
+        launch_spmv<double>(P->tp, D, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s);
+      } else {
+        launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
+        launch_spmv<double>(P->tp, D, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+      }
       launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 2, s);
       launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 3, 1, s);
       launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 4, 2, s);
@@ -987,6 +1099,47 @@ int hho_vcycle_apply(hho_problem *p, const double *b, double *x) {
   need_setup(p);
   if (!b || !x) hho::fail(HHO_E_INVALID_ARG, "vcycle_apply: NULL");
   hho::apply_vcycle(p, b, x);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_debug_copy(hho_problem *p, const char *name, int level, double *out, int64_t cap, int64_t *n_out) {
+  ABI_BEGIN
+  need_setup(p);
+  std::string nm = name ? name : "";
+  const double *src = nullptr;
+  int64_t n = 0;
+  if (nm.rfind("amg_", 0) == 0) {
+    if (!p->coarse_amg || level < 0 || level >= p->amgd.nlev) hho::fail(HHO_E_INVALID_ARG, "debug_copy: bad AMG level");
+    const hho::AmgDevLevel &G = p->amgd.lev[level];
+    if (nm == "amg_val") src = G.val, n = G.nnz;
+    else if (nm == "amg_pval") src = G.pval, n = G.npe;
+    else if (nm == "amg_dinv") src = G.dinv, n = G.n;
+    else if (nm == "amg_lam") src = G.lam, n = 1;
+    else if (nm == "amg_ainv") src = p->amgd.ainv, n = (int64_t)G.n * G.n;
+  } else if (nm == "sd" && p->coarse_amg) {
+    src = p->Sd, n = p->mesh->nc;
+  }
+  if (!src) hho::fail(HHO_E_INVALID_ARG, "debug_copy: unknown array " + nm);
+  if (n_out) *n_out = n;
+  if (cap < n) {
+    hho::set_error("debug_copy: capacity");
+    return HHO_E_CAPACITY;
+  }
+  HIPCHK(hipMemcpy(out, src, n * 8, hipMemcpyDeviceToHost));
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_coarse_prec_apply(hho_problem *p, const double *v, double *z) {
+  ABI_BEGIN
+  need_setup(p);
+  if (!v || !z) hho::fail(HHO_E_INVALID_ARG, "coarse_prec_apply: NULL");
+  if (!p->coarse_amg) hho::fail(HHO_E_INVALID_ARG, "coarse_prec_apply: the coarsest level does not use the AMG solver");
+  const hho::LevelInfo &L = p->lev[p->nlev - 1];
+  hho::bp_apply(p->tp, p->amgd, L.nface, L.cpl, p->Sd, v, z, p->amg_nu, p->stream);
   HIPCHK(hipStreamSynchronize(p->stream));
   HIPCHK(hipGetLastError());
   return HHO_OK;

@@ -110,6 +110,40 @@ def test_vcycle_matches_oracle(built, name, mk, k, cond):
     assert _rel(x, xo) < 1e-9, _rel(x, xo)
 
 
+AMG_CASES = [
+    ("vor120_k2_v", lambda: voronoi_lloyd(120, 7), 2, "v"),
+    ("vor120_k2_vp", lambda: voronoi_lloyd(120, 7), 2, "vp"),
+    ("hex4_k1_v", lambda: cartesian_hexes(4), 1, "v"),
+]
+
+
+@pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
+def test_coarse_block_preconditioner(built, name, mk, k, cond):
+    """Coarsest-level block-triangular preconditioner with the smoothed-aggregation
+    velocity block: GPU vs the oracle's plain definition."""
+    import torch
+    from oracle.amg import BlockStokesPrec
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg")
+    L = len(O.S) - 1
+    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim)
+    assert len(prec.amg.sizes) >= 2
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(O.S[L].shape[0])
+    z = P.coarse_prec_apply(torch.from_numpy(v).cuda()).cpu().numpy()
+    assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
+
+
+@pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
+def test_fgmres_solution_amg_coarse(built, name, mk, k, cond):
+    import oracle.solve as OS
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", rtol=1e-11)
+    x, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-11
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert its <= 40
+
+
 @pytest.mark.parametrize("name,mk,k,cond", CASES)
 @pytest.mark.parametrize("coarse", ["dense", "gmres"])
 def test_fgmres_solution(built, name, mk, k, cond, coarse):
