@@ -120,6 +120,7 @@ typedef struct {
   int32_t coarse_restart; /* coarse GMRES restart (30, at most 64) */
   int32_t coarse_max_it;  /* coarse GMRES iterations (300) */
   int32_t quad_extra;  /* quadrature exact to degree 2k+2+quad_extra (6) */
+  int32_t coarse_amg_sweeps; /* damped-Jacobi sweeps before/after the AMG coarse correction (2; 1 or 2) */
 } hho_options;
 
 /* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the

@@ -10,11 +10,15 @@ that preconditioner, used to check the GPU implementation:
 
 * scalar face operator  s[f,g] = (1/d) sum_c S[(f,c),(g,c)]   (coarsest level, k_L = 0)
 * aggregation: nodes in index order; an unaggregated node opens an aggregate
-  holding itself and its unaggregated neighbours (matrix pattern)
-* tentative prolongator T (0/1), lambda = max_i sum_j |A_ij| / A_ii,
-  P = T - (omega/lambda) D^{-1} A T with omega = 4/3, A_next = P^T A P,
-  down to <= 128 unknowns, then a dense inverse
-* V-cycle with nu damped-Jacobi sweeps (weight 2/3) before and after
+  holding itself and its unaggregated neighbours in the aggregation graph G
+  (G_0 = pattern of A_0, G_{l+1} = pattern of T^T G_l T: aggregates are
+  neighbours when their members are)
+* lambda: 15 power-iteration steps v <- D^{-1} A v / |.| from the start vector
+  v_i = frac(i * 2654435761 / 2^32) - 1/2, times 1.05 (estimate of rho(D^{-1} A))
+* tentative prolongator T (0/1), P = T - (omega/lambda) D^{-1} A T with
+  omega = 4/3, A_next = P^T A P, down to <= 128 unknowns, then a dense inverse
+* V-cycle with nu (default 2) damped-Jacobi sweeps of weight 4/(3 lambda) before
+  and after the coarse correction
 * pressure Schur approximation  S_T = sum_{(f,c)} C[(f,c),T]^2 / S[(f,c),(f,c)]
 * apply: y = -g / S_T,   x = V-cycle(f - C y) per velocity component.
 """
@@ -24,8 +28,27 @@ import numpy as np
 import scipy.sparse as sp
 
 OMEGA_SA = 4.0 / 3.0
-OMEGA_JAC = 2.0 / 3.0
 COARSEST = 128
+POWER_STEPS = 15
+LAMBDA_SAFETY = 1.05
+
+
+def start_vector(n: int) -> np.ndarray:
+    """Deterministic start vector of the power iteration (Knuth multiplicative hash)."""
+    i = np.arange(n, dtype=np.uint64)
+    h = (i * np.uint64(2654435761)) % np.uint64(2 ** 32)
+    return h.astype(np.float64) / 2.0 ** 32 - 0.5
+
+
+def spectral_radius_estimate(A: sp.csr_matrix) -> float:
+    Di = 1.0 / A.diagonal()
+    v = start_vector(A.shape[0])
+    lam = 1.0
+    for _ in range(POWER_STEPS):
+        v = Di * (A @ v)
+        lam = float(np.linalg.norm(v))
+        v = v / lam
+    return LAMBDA_SAFETY * lam
 
 
 def aggregate(A: sp.csr_matrix) -> np.ndarray:
@@ -44,23 +67,30 @@ def aggregate(A: sp.csr_matrix) -> np.ndarray:
 
 
 class SA:
-    def __init__(self, A: sp.csr_matrix, nu: int = 1):
+    def __init__(self, A: sp.csr_matrix, nu: int = 2):
         self.nu = nu
         self.levels = []
+        self.lams = []
         A = sp.csr_matrix(A)
         A.sort_indices()
+        G = A.copy()
+        G.data[:] = 1.0
         while A.shape[0] > COARSEST:
-            agg = aggregate(A)
+            agg = aggregate(G)
             na = int(agg.max()) + 1
             if na >= A.shape[0]:
                 break
             T = sp.csr_matrix((np.ones(A.shape[0]), (np.arange(A.shape[0]), agg)), shape=(A.shape[0], na))
             D = A.diagonal()
-            lam = float(np.max(np.asarray(abs(A).sum(axis=1)).ravel() / D))
+            lam = spectral_radius_estimate(A)
             P = (T - (OMEGA_SA / lam) * (sp.diags(1.0 / D) @ A @ T)).tocsr()
             self.levels.append((A, P, 1.0 / D))
+            self.lams.append(lam)
             A = (P.T @ A @ P).tocsr()
             A.sort_indices()
+            G = (T.T @ G @ T).tocsr()
+            G.data[:] = 1.0
+            G.sort_indices()
         self.Ainv = np.linalg.inv(A.toarray())
         self.sizes = [L[0].shape[0] for L in self.levels] + [A.shape[0]]
 
@@ -68,19 +98,20 @@ class SA:
         if l == len(self.levels):
             return self.Ainv @ r
         A, P, Di = self.levels[l]
+        w = 4.0 / (3.0 * self.lams[l])
         x = np.zeros_like(r)
         for _ in range(self.nu):
-            x = x + OMEGA_JAC * Di * (r - A @ x)
+            x = x + w * Di * (r - A @ x)
         x = x + P @ self.vcycle(P.T @ (r - A @ x), l + 1)
         for _ in range(self.nu):
-            x = x + OMEGA_JAC * Di * (r - A @ x)
+            x = x + w * Di * (r - A @ x)
         return x
 
 
 class BlockStokesPrec:
     """Block-triangular preconditioner of the coarsest (k = 0) level."""
 
-    def __init__(self, S: sp.csr_matrix, nface_dofs: int, d: int, nu: int = 1):
+    def __init__(self, S: sp.csr_matrix, nface_dofs: int, d: int, nu: int = 2):
         S = sp.csr_matrix(S)
         self.nf, self.d = nface_dofs, d
         nfaces = nface_dofs // d

@@ -63,6 +63,7 @@ class Hierarchy:
     coarse_its: list = field(default_factory=list)
     nface_dofs: list = field(default_factory=list)
     dim: int = 2
+    amg_nu: int = 2
     _lu: object = None
     _amg: object = None
 
@@ -95,7 +96,7 @@ class Hierarchy:
         if self.coarse == "amg":
             if self._amg is None:
                 from .amg import BlockStokesPrec
-                self._amg = BlockStokesPrec(S, self.nface_dofs[L], self.dim)
+                self._amg = BlockStokesPrec(S, self.nface_dofs[L], self.dim, self.amg_nu)
             M = self._amg
         x, its = gmres_solve(lambda v: S @ v, M, d, self.coarse_rtol, self.coarse_restart, self.coarse_maxit)
         self.coarse_its.append(its)

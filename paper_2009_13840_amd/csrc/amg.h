@@ -9,8 +9,10 @@
 namespace hho {
 
 constexpr double kAmgOmegaSA = 4.0 / 3.0;   // prolongator smoothing weight (divided by lambda)
-constexpr double kAmgOmegaJac = 2.0 / 3.0;  // damped-Jacobi smoother weight
+constexpr double kAmgOmegaJac = 4.0 / 3.0;  // damped-Jacobi smoother weight (divided by lambda)
 constexpr int kAmgCoarsest = 128;           // dense inverse at or below this size
+constexpr int kAmgPowerSteps = 15;          // power iterations for lambda ~ rho(D^{-1} A)
+constexpr double kAmgLambdaSafety = 1.05;
 
 struct AmgHostLevel {
   int n = 0, nc = 0;                     // rows; aggregates (0 on the coarsest level)

@@ -5,7 +5,8 @@
 //
 // Level l holds A_l (CSR, sorted columns), the aggregates of its rows (an
 // unaggregated row in index order opens an aggregate holding itself and its
-// unaggregated neighbours), the pattern of P = T - w D^{-1} A T (T the 0/1
+// unaggregated neighbours in the aggregation graph G_l, with G_0 the pattern of
+// A_0 and G_{l+1} the pattern of T^T G_l T), the pattern of P = T - w D^{-1} A T (T the 0/1
 // aggregate injection), and the gather lists that evaluate
 //   P        (entries of A summed per (row, aggregate)),
 //   B = A P  (pairs (A entry, P entry)),
@@ -28,6 +29,7 @@ static void csr_from_rows(const std::vector<std::vector<int32_t>> &rows, std::ve
 void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, AmgHost *H) {
   H->levels.clear();
   std::vector<int32_t> rp(rp0, rp0 + n0 + 1), ci(ci0, ci0 + rp0[n0]);
+  std::vector<int32_t> grp = rp, gci = ci;  // aggregation graph (pattern of T^T G T)
   int n = n0;
   for (;;) {
     AmgHostLevel L;
@@ -50,8 +52,8 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
     int na = 0;
     for (int i = 0; i < n; ++i) {
       if (L.agg[i] >= 0) continue;
-      for (int e = rp[i]; e < rp[i + 1]; ++e)
-        if (L.agg[ci[e]] < 0) L.agg[ci[e]] = na;
+      for (int e = grp[i]; e < grp[i + 1]; ++e)
+        if (L.agg[gci[e]] < 0) L.agg[gci[e]] = na;
       L.agg[i] = na;
       ++na;
     }
@@ -148,6 +150,15 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
         }
         ++k;
       }
+    // next aggregation graph: aggregates adjacent when any of their members are
+    std::vector<std::vector<int32_t>> grow(na);
+    for (int i = 0; i < n; ++i)
+      for (int e = grp[i]; e < grp[i + 1]; ++e) grow[L.agg[i]].push_back(L.agg[gci[e]]);
+    for (auto &r : grow) {
+      std::sort(r.begin(), r.end());
+      r.erase(std::unique(r.begin(), r.end()), r.end());
+    }
+    csr_from_rows(grow, grp, gci);
     H->levels.push_back(std::move(L));
     rp = nrp;
     ci = nci;

@@ -29,7 +29,7 @@ struct AmgDevLevel {
 struct AmgDev {
   int nlev = 0;
   AmgDevLevel lev[kMaxAmgLevels];
-  double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr;
+  double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr, *pw = nullptr;
   int *counter = nullptr;
 };
 

@@ -32,33 +32,37 @@ __global__ void k_amg_extract0(int64_t nnzb, int bs, int d, int cond, const doub
   }
 }
 
-// D^{-1} and lambda = max_i sum_j |A_ij| / A_ii (Gershgorin bound of D^{-1} A)
-__global__ void __launch_bounds__(kBlock) k_amg_diag(int n, const int32_t *rp, const int32_t *diag,
-                                                      const double *val, double *dinv, double *partial,
-                                                      double *lam, int *counter) {
-  __shared__ double red[kBlock];
-  double mx = 0;
+// D^{-1} and the power-iteration start vector v_i = frac(i * 2654435761 / 2^32) - 1/2
+__global__ void k_amg_diag(int n, const int32_t *diag, const double *val, double *dinv, double *v) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    const double a = val[diag[i]];
-    double s = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) s += fabs(val[e]);
-    dinv[i] = 1.0 / a;
-    mx = fmax(mx, s / a);
+    dinv[i] = 1.0 / val[diag[i]];
+    const uint64_t h = ((uint64_t)i * 2654435761ull) % 4294967296ull;
+    v[i] = (double)h / 4294967296.0 - 0.5;
   }
-  red[threadIdx.x] = mx;
-  __syncthreads();
-  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
-    if ((int)threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
-    __syncthreads();
+}
+
+// one power-iteration step: vout = D^{-1} A (vin / lam_in), lam_out = |vout|
+// (lam_in == null: no scaling).  The last block writes lam_out, times `safety`.
+__global__ void __launch_bounds__(kBlock) k_amg_power(int n, const int32_t *rp, const int32_t *ci, const double *val,
+                                                       const double *dinv, const double *vin, const double *lam_in,
+                                                       double *vout, double *partial, double *lam_out, double safety,
+                                                       int *counter) {
+  __shared__ double red[16];
+  const double sc = lam_in ? 1.0 / lam_in[0] : 1.0;
+  double acc = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    double t = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) t += val[e] * vin[ci[e]];
+    t *= sc * dinv[i];
+    vout[i] = t;
+    acc += t * t;
   }
-  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
   if (last_block_arrived(counter)) {
-    if (threadIdx.x < kWave) {
-      double m = 0;
-      for (unsigned b = threadIdx.x; b < gridDim.x; b += kWave) m = fmax(m, vload(&partial[b]));
-      m = wave_max(m);
-      if (threadIdx.x == 0) *lam = m;
-    }
+    __shared__ double tot[1];
+    reduce_partials(partial, gridDim.x, 1, tot);
+    if (threadIdx.x == 0) lam_out[0] = safety * sqrt(tot[0]);
   }
 }
 
@@ -144,30 +148,66 @@ __global__ void k_bp_rhs(DTopo tp, int64_t nface, const double *cpl, const doubl
   }
 }
 
-// xout = xin + w D^{-1} (r - A xin)   (xin == null: xout = w D^{-1} r)
-__global__ void k_amg_jacobi(int n, int d, const int32_t *rp, const int32_t *ci, const double *val,
-                             const double *dinv, const double *r, const double *xin, double *xout) {
-  const int64_t total = (int64_t)n * d;
-  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(o / d), c = (int)(o % d);
-    double t = r[o];
-    double x0 = 0;
-    if (xin) {
-      for (int e = rp[i]; e < rp[i + 1]; ++e) t -= val[e] * xin[(int64_t)ci[e] * d + c];
-      x0 = xin[o];
-    }
-    xout[o] = x0 + kAmgOmegaJac * dinv[i] * t;
-  }
+// Sum over the G lanes of a row group (G a power of two dividing 64).
+template <int G>
+__device__ inline double group_sum(double v) {
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
+  return v;
 }
 
-__global__ void k_amg_residual(int n, int d, const int32_t *rp, const int32_t *ci, const double *val,
-                               const double *r, const double *x, double *res) {
-  const int64_t total = (int64_t)n * d;
-  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(o / d), c = (int)(o % d);
-    double t = r[o];
-    for (int e = rp[i]; e < rp[i + 1]; ++e) t -= val[e] * x[(int64_t)ci[e] * d + c];
-    res[o] = t;
+// G lanes per row, all d (<= 3) components at once.
+// MODE 0: xout = xin + w D^{-1} (r - A xin); xin == null means xin = w D^{-1} r (a
+//         first sweep from zero folded in), so one launch gives two sweeps.
+// MODE 1: res = r - A xin (xin == null: xin = w D^{-1} r) and, if xout is set,
+//         xout = xin: the residual after the sweep(s) already taken.
+template <int MODE, int G>
+__global__ void __launch_bounds__(kBlock) k_amg_rows(int n, int d, const int32_t *rp, const int32_t *ci,
+                                                      const double *val, const double *dinv, const double *lam,
+                                                      const double *r, const double *xin, double *xout, double *res) {
+  const double w = kAmgOmegaJac / lam[0];
+  const int lane = threadIdx.x % G;
+  const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
+  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; i < n; i += ngroups) {
+    double t0 = 0, t1 = 0, t2 = 0;
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += G) {
+      const int j = ci[e];
+      const double a = val[e];
+      double x0, x1 = 0, x2 = 0;
+      if (xin) {
+        const double *xj = xin + (int64_t)j * d;
+        x0 = xj[0];
+        if (d > 1) x1 = xj[1];
+        if (d > 2) x2 = xj[2];
+      } else {
+        const double sc = w * dinv[j];
+        const double *rj = r + (int64_t)j * d;
+        x0 = sc * rj[0];
+        if (d > 1) x1 = sc * rj[1];
+        if (d > 2) x2 = sc * rj[2];
+      }
+      t0 += a * x0;
+      t1 += a * x1;
+      t2 += a * x2;
+    }
+    t0 = group_sum<G>(t0);
+    t1 = group_sum<G>(t1);
+    t2 = group_sum<G>(t2);
+    if (lane != 0) continue;
+    const double si = w * dinv[i];
+    double y[3] = {0, 0, 0}, q[3] = {t0, t1, t2};
+    for (int c = 0; c < d; ++c) {
+      const double rc = r[i * d + c];
+      y[c] = xin ? xin[i * d + c] : si * rc;
+      q[c] = rc - q[c];
+    }
+    for (int c = 0; c < d; ++c) {
+      if (MODE == 0) {
+        xout[i * d + c] = y[c] + si * q[c];
+      } else {
+        res[i * d + c] = q[c];
+        if (xout) xout[i * d + c] = y[c];
+      }
+    }
   }
 }
 
@@ -197,26 +237,52 @@ __global__ void __launch_bounds__(kBlock) k_amg_restrict(int nc, int d, const in
   }
 }
 
-// xout = xin + P xc (xout may alias xin: every entry is read and written by one thread)
-__global__ void k_amg_prolong(int n, int d, const int32_t *prp, const int32_t *pci, const double *pval,
-                              const double *xc, const double *xin, double *xout) {
-  const int64_t total = (int64_t)n * d;
-  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(o / d), c = (int)(o % d);
-    double s = 0;
-    for (int e = prp[i]; e < prp[i + 1]; ++e) s += pval[e] * xc[(int64_t)pci[e] * d + c];
-    xout[o] = xin[o] + s;
+// xout = xin + P xc (xout may alias xin: every entry is read and written by one lane)
+template <int G>
+__global__ void __launch_bounds__(kBlock) k_amg_prolong(int n, int d, const int32_t *prp, const int32_t *pci,
+                                                         const double *pval, const double *xc, const double *xin,
+                                                         double *xout) {
+  const int lane = threadIdx.x % G;
+  const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
+  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; i < n; i += ngroups) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int e = prp[i] + lane; e < prp[i + 1]; e += G) {
+      const double pv = pval[e];
+      const double *xj = xc + (int64_t)pci[e] * d;
+      s0 += pv * xj[0];
+      if (d > 1) s1 += pv * xj[1];
+      if (d > 2) s2 += pv * xj[2];
+    }
+    s0 = group_sum<G>(s0);
+    s1 = group_sum<G>(s1);
+    s2 = group_sum<G>(s2);
+    if (lane != 0) continue;
+    const double s[3] = {s0, s1, s2};
+    for (int c = 0; c < d; ++c) xout[i * d + c] = xin[i * d + c] + s[c];
   }
 }
 
-// x = Ainv r (dense, n <= 128), one thread per output
-__global__ void k_amg_dense(int n, int d, const double *Ainv, const double *r, double *x) {
-  const int64_t total = (int64_t)n * d;
-  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
-    const int i = (int)(o / d), c = (int)(o % d);
-    double s = 0;
-    for (int j = 0; j < n; ++j) s += Ainv[(int64_t)i * n + j] * r[(int64_t)j * d + c];
-    x[o] = s;
+// x = Ainv r (dense, n <= 128), one wavefront per row
+__global__ void __launch_bounds__(kBlock) k_amg_dense(int n, int d, const double *Ainv, const double *r,
+                                                       double *x) {
+  const int lane = threadIdx.x % kWave;
+  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
+  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; i < n; i += nw) {
+    double s0 = 0, s1 = 0, s2 = 0;
+    for (int j = lane; j < n; j += kWave) {
+      const double a = Ainv[i * n + j];
+      s0 += a * r[(int64_t)j * d];
+      if (d > 1) s1 += a * r[(int64_t)j * d + 1];
+      if (d > 2) s2 += a * r[(int64_t)j * d + 2];
+    }
+    s0 = wave_sum(s0);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+      x[i * d] = s0;
+      if (d > 1) x[i * d + 1] = s1;
+      if (d > 2) x[i * d + 2] = s2;
+    }
   }
 }
 
@@ -234,8 +300,17 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
       break;
     }
     const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((L.n + kBlock - 1) / kBlock, 256));
-    hipLaunchKernelGGL(k_amg_diag, dim3(nb), dim3(kBlock), 0, s, L.n, L.rp, L.diag, L.val, L.dinv, A.partial,
-                       L.lam, A.counter);
+    hipLaunchKernelGGL(k_amg_diag, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.diag, (const double *)L.val,
+                       L.dinv, L.tmp);
+    // lambda ~ rho(D^{-1} A) by power iteration (ping-pong between tmp and res)
+    for (int k = 0; k < kAmgPowerSteps; ++k) {
+      const double *vin = (k % 2 == 0) ? L.tmp : L.res;
+      double *vout = (k % 2 == 0) ? L.res : L.tmp;
+      const bool last = k == kAmgPowerSteps - 1;
+      hipLaunchKernelGGL(k_amg_power, dim3(nb), dim3(kBlock), 0, s, L.n, L.rp, L.ci, (const double *)L.val,
+                         (const double *)L.dinv, vin, (const double *)(k ? A.pw + k - 1 : nullptr), vout, A.partial,
+                         last ? L.lam : A.pw + k, last ? kAmgLambdaSafety : 1.0, A.counter);
+    }
     hipLaunchKernelGGL(k_amg_p, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.prow, L.pgp, L.pgi, L.pself,
                        L.val, L.dinv, L.lam, L.pval);
     hipLaunchKernelGGL(k_amg_pairs, dim3(grid_for(L.nbe)), dim3(kBlock), 0, s, L.nbe, L.bpp, L.bpa, L.bpb,
@@ -251,38 +326,65 @@ void bp_setup(const DTopo &tp, int cond, const int32_t *fdiag, const double *bsr
   hipLaunchKernelGGL(k_bp_setup, dim3(grid_for(tp.nc)), dim3(kBlock), 0, s, tp, cond, fdiag, bsr, cpl, Sd);
 }
 
-// V-cycle on level l: x = AMG_l(r); x, r are [n_l][d]
+// V-cycle on level l: x = AMG_l(r); x, r are [n_l][d].  nu damped-Jacobi sweeps
+// before and after the coarse correction (nu = 1 or 2).
+template <int MODE>
+static void rows(int G, int n, int d, const AmgDevLevel &L, const double *r, const double *xin, double *xout,
+                 double *res, hipStream_t s) {
+  const dim3 b(kBlock), g(grid_for((int64_t)n * G));
+  const double *val = L.val, *dinv = L.dinv, *lam = L.lam;
+  switch (G) {
+    case 64: hipLaunchKernelGGL((k_amg_rows<MODE, 64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
+    case 16: hipLaunchKernelGGL((k_amg_rows<MODE, 16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
+    case 4: hipLaunchKernelGGL((k_amg_rows<MODE, 4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
+    default: hipLaunchKernelGGL((k_amg_rows<MODE, 1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
+  }
+}
+
+static void prolong(int G, const AmgDevLevel &L, int d, const double *xc, const double *xin, double *xout,
+                    hipStream_t s) {
+  const dim3 b(kBlock), g(grid_for((int64_t)L.n * G));
+  const double *pv = L.pval;
+  switch (G) {
+    case 64: hipLaunchKernelGGL((k_amg_prolong<64>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
+    case 16: hipLaunchKernelGGL((k_amg_prolong<16>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
+    case 4: hipLaunchKernelGGL((k_amg_prolong<4>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
+    default: hipLaunchKernelGGL((k_amg_prolong<1>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
+  }
+}
+
+// lanes per row for a given average row length
+int amg_group(double avg) { return avg >= 48 ? 64 : avg >= 12 ? 16 : avg >= 3 ? 4 : 1; }
+
+// V-cycle on level l: x = AMG_l(r); x, r are [n_l][d].  nu damped-Jacobi sweeps
+// before and after the coarse correction (nu = 1 or 2).
 static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, double *x, hipStream_t s) {
   const AmgDevLevel &L = A.lev[l];
   const int64_t nd = (int64_t)L.n * d;
   if (l == A.nlev - 1) {
-    hipLaunchKernelGGL(k_amg_dense, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, (const double *)A.ainv, r, x);
+    hipLaunchKernelGGL(k_amg_dense, dim3(grid_for((int64_t)L.n * kWave)), dim3(kBlock), 0, s, L.n, d,
+                       (const double *)A.ainv, r, x);
     return;
   }
-  // pre-smoothing (from zero): ends in x
+  (void)nd;
+  const int GA = amg_group((double)L.nnz / L.n), GP = amg_group((double)L.npe / L.n);
+  // pre-smoothing from zero and the residual after it
   if (nu == 1) {
-    hipLaunchKernelGGL(k_amg_jacobi, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, L.rp, L.ci,
-                       (const double *)L.val, (const double *)L.dinv, r, (const double *)nullptr, x);
+    rows<1>(GA, L.n, d, L, r, nullptr, x, L.res, s);
   } else {
-    hipLaunchKernelGGL(k_amg_jacobi, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, L.rp, L.ci,
-                       (const double *)L.val, (const double *)L.dinv, r, (const double *)nullptr, L.tmp);
-    hipLaunchKernelGGL(k_amg_jacobi, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, L.rp, L.ci,
-                       (const double *)L.val, (const double *)L.dinv, r, (const double *)L.tmp, x);
+    rows<0>(GA, L.n, d, L, r, nullptr, x, nullptr, s);
+    rows<1>(GA, L.n, d, L, r, x, nullptr, L.res, s);
   }
-  hipLaunchKernelGGL(k_amg_residual, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, L.rp, L.ci,
-                     (const double *)L.val, r, (const double *)x, L.res);
   const AmgDevLevel &N = A.lev[l + 1];
   hipLaunchKernelGGL(k_amg_restrict, dim3(grid_for((int64_t)N.n * kWave)), dim3(kBlock), 0, s, N.n, d, L.ptp, L.pti,
                      L.pte, (const double *)L.pval, (const double *)L.res, N.r);
   vcycle(A, l + 1, d, nu, N.r, N.x, s);
   // prolongation, then nu post-smoothing sweeps alternating between tmp and x, ending in x
   double *cur = (nu % 2 == 1) ? L.tmp : x;
-  hipLaunchKernelGGL(k_amg_prolong, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, L.prp, L.pci,
-                     (const double *)L.pval, (const double *)N.x, (const double *)x, cur);
+  prolong(GP, L, d, N.x, x, cur, s);
   for (int it = 0; it < nu; ++it) {
     double *nxt = (cur == x) ? L.tmp : x;
-    hipLaunchKernelGGL(k_amg_jacobi, dim3(grid_for(nd)), dim3(kBlock), 0, s, L.n, d, L.rp, L.ci,
-                       (const double *)L.val, (const double *)L.dinv, r, (const double *)cur, nxt);
+    rows<0>(GA, L.n, d, L, r, cur, nxt, nullptr, s);
     cur = nxt;
   }
 }

@@ -289,17 +289,28 @@ __global__ void k_mr2_update(int64_t n, int m, const double *y, const T *z1, con
 // ---- Arnoldi reductions (classical Gram-Schmidt applied twice)
 constexpr int kMaxDots = kMaxRestartH + 1;
 
-// partial dots of w with V_0..V_j over this block's rows -> partial[i][block]
+// partial dots of w with V_0..V_j over this block's rows -> partial[i][block].
+// The vectors are taken eight at a time so that their loads are in flight together.
 template <typename T>
 __device__ void multi_dot_partial(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial) {
   __shared__ double red[kBlock / kWave][kMaxDots];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  for (int i = 0; i <= j; ++i) {
-    double acc = 0;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
-      acc += (double)V[i * ldv + k] * (double)w[k];
-    acc = wave_sum(acc);
-    if (lane == 0) red[wid][i] = acc;
+  for (int i0 = 0; i0 <= j; i0 += 8) {
+    const int ni = (j + 1 - i0) < 8 ? (j + 1 - i0) : 8;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
+      const double wk = w[k];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (q < ni) acc[q] += (double)V[(i0 + q) * ldv + k] * wk;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (q < ni) {
+        const double sq = wave_sum(acc[q]);
+        if (lane == 0) red[wid][i0 + q] = sq;
+      }
+    }
   }
   __syncthreads();
   for (int i = threadIdx.x; i <= j; i += blockDim.x) {

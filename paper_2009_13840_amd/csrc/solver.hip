@@ -103,7 +103,7 @@ struct hho_problem {
   bool uploaded = false;
   // coarsest-level block preconditioner (smoothed aggregation)
   bool coarse_amg = false;
-  int amg_nu = 1;
+  int amg_nu = 2;
   std::vector<int32_t> fdiag;
   int32_t *d_fdiag = nullptr;
   double *Sd = nullptr;
@@ -245,6 +245,7 @@ static void plan(hho_problem *P, Arena &A) {
     D.ainv = A.take<double>((int64_t)nlast * nlast);
     D.dense_scratch = A.take<double>((int64_t)nlast * nlast);
     D.partial = A.take<double>(512);
+    D.pw = A.take<double>(kAmgPowerSteps + 1);
   }
   // outer FGMRES
   const int R = P->opt.restart;
@@ -819,6 +820,7 @@ void hho_options_default(hho_options *o) {
   o->coarse_restart = 30;
   o->coarse_max_it = 300;
   o->quad_extra = 6;
+  o->coarse_amg_sweeps = 2;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -865,6 +867,9 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.coarse_restart < 1 || P->opt.coarse_restart > hho::kMaxRestartH)
     hho::fail(HHO_E_INVALID_ARG, "coarse_restart must be in 1..64");
   if (P->opt.smooth_its < 1 || P->opt.smooth_its > 2) hho::fail(HHO_E_INVALID_ARG, "smooth_its must be 1 or 2");
+  if (P->opt.coarse_amg_sweeps < 1 || P->opt.coarse_amg_sweeps > 2)
+    hho::fail(HHO_E_INVALID_ARG, "coarse_amg_sweeps must be 1 or 2");
+  P->amg_nu = P->opt.coarse_amg_sweeps;
   if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");

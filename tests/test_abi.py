@@ -1,0 +1,101 @@
+"""CPU tests of the C ABI: the library loads and exports every declared symbol,
+argument validation and error codes, and the host-built local HHO operators
+against the oracle (no device calls)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from synth import cartesian_quads, voronoi_lloyd, cartesian_hexes, polynomial_stokes
+from synth.fields import problem_data
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2009_13840_amd as H
+    return H, H.load()
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "hho_pmg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(hho_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol():
+    H, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(H.EXPORTS)
+
+
+def test_mesh_validation_errors():
+    H, _ = _lib()
+    m = cartesian_quads(2)
+    bad = cartesian_quads(2)
+    bad.face_bc = bad.face_bc.copy()
+    bad.face_bc[np.argmax(bad.face_bc)] = 0      # boundary face without a boundary flag
+    with pytest.raises(H.HHOError) as e:
+        H.Mesh(bad)
+    assert e.value.code == -2
+    bad2 = cartesian_quads(2)
+    bad2.face_bc = bad2.face_bc.copy()
+    bad2.face_bc[np.argmin(bad2.face_bc)] = 1    # interior face with a boundary flag
+    with pytest.raises(H.HHOError) as e:
+        H.Mesh(bad2)
+    assert e.value.code == -2
+    H.Mesh(m)
+
+
+def test_problem_argument_validation():
+    H, _ = _lib()
+    M = H.Mesh(cartesian_quads(2))
+    for kw in (dict(k=-1), dict(k=7), dict(k=2, degrees=[2, 2, 0]), dict(k=2, degrees=[1, 0]),
+               dict(k=1, restart=0), dict(k=1, smooth_its=3)):
+        k = kw.pop("k")
+        with pytest.raises(H.HHOError) as e:
+            H.Problem(M, k, "v", **kw)
+        assert e.value.code == -1, kw
+    P = H.Problem(M, 1, "v")
+    with pytest.raises(H.HHOError) as e:
+        P.workspace_size()                        # before set_data
+    assert e.value.code == -1
+    with pytest.raises(H.HHOError) as e:
+        P.setup()
+    assert e.value.code == -1
+
+
+def test_workspace_capacity_error():
+    import ctypes as C
+    H, lib = _lib()
+    P = H.Problem(H.Mesh(cartesian_quads(2)), 1, "v")
+    P.set_data(*problem_data(polynomial_stokes(2, 1, 0), None, 2))
+    n = P.workspace_size()
+    assert n > 0
+    code = lib.hho_bind_workspace(P.h, C.c_void_p(0x1000), n - 1)
+    assert code == -7
+
+
+@pytest.mark.parametrize("mesh,k", [(cartesian_quads(3), 1), (voronoi_lloyd(20, 3), 3), (cartesian_hexes(2), 2),
+                                    (cartesian_quads(3).with_bc(lambda x: 2 if x[0] > 1 - 1e-12 else 1), 2)])
+def test_host_local_operators_match_oracle(mesh, k):
+    """The library's host-built local operators (its own quadrature, bases and
+    integrated-by-parts coupling) equal the oracle's to rounding."""
+    H, _ = _lib()
+    from oracle.hho import mesh_geometry, local_hho
+    from oracle.solve import default_eta
+    data = problem_data(polynomial_stokes(mesh.dim, k, 5), None, mesh.dim)
+    P = H.Problem(H.Mesh(mesh), k, "v")
+    P.set_data(*data)
+    geo = mesh_geometry(mesh, k)
+    for c in range(mesh.n_cells):
+        L = local_hho(mesh, geo, c, default_eta(mesh, k), *data)
+        G = P.local_cell(c)
+        assert np.abs(G["a"] - L.a).max() <= 1e-12 * np.abs(L.a).max()
+        assert np.abs(G["B"] - L.B).max() <= 1e-12 * np.abs(L.B).max()
+        assert np.abs(G["rhs_u"] - L.rhs_u).max() <= 1e-12 * max(1.0, np.abs(L.rhs_u).max())
+        assert np.abs(G["rhs_p"] - L.rhs_p).max() <= 1e-12 * max(1.0, np.abs(L.rhs_p).max())
