@@ -21,6 +21,7 @@ struct DTopo {
   const int32_t *floc;     // [2*nf] position of the face in each cell's list
   const int32_t *rowptr;   // [nf+1] face-block sparse rows
   const int32_t *col;      // [nnzb] block columns (faces), sorted per row
+  const int32_t *mirror;   // [nnzb] index of the block (col, row) of each block (row, col)
   const int32_t *blksrc;   // [6*nnzb] (cell, i, j) of the <= 2 cell blocks summed into each block
   const int64_t *pairoff;  // [nc+1] prefix sum of card(F_T)^2
   const int32_t *pairblk;  // [pairoff[nc]] block index of the local pair (i, j) of each cell
@@ -74,6 +75,11 @@ int reduce_blocks(int64_t n);
 // two slot vectors x (slot 0) and xs1 (slot 1), and xsum (if not null) receives it.
 template <typename T>
 void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s);
+// Compile-time-sized variants of the two calls above (b != null: residual form);
+// false when no variant matches the level's block sizes.
+template <typename T>
+bool launch_spmv_fixed(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+                       hipStream_t s);
 // r = b - S x
 template <typename T>
 void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x, T *r, hipStream_t s);

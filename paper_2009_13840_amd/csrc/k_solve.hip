@@ -506,6 +506,7 @@ int reduce_blocks(int64_t n) {
 
 template <typename T>
 void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s) {
+  if (launch_spmv_fixed<T>(tp, L, x, xs1, xsum, nullptr, y, s)) return;
   if (xs1)
     hipLaunchKernelGGL((k_spmv<T, true, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
                        (const T *)nullptr, y);
@@ -515,6 +516,7 @@ void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, 
 }
 template <typename T>
 void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x, T *r, hipStream_t s) {
+  if (launch_spmv_fixed<T>(tp, L, x, nullptr, nullptr, b, r, s)) return;
   hipLaunchKernelGGL((k_spmv<T, false, 1>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, (const T *)nullptr,
                      (T *)nullptr, b, r);
 }

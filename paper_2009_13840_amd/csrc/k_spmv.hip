@@ -1,0 +1,191 @@
+// Face-block operator application with the block sizes fixed at compile time
+// (one instantiation per (dimension, level degree, condensation variant)).
+//
+// y = S x (MODE 0) or y = b - S x (MODE 1) for the condensed operator of
+// Section 3.2 stored as face-block rows (plus the cell couplings):
+//  * v-cond: S_{FF'} = s_{FF'} (x) I_d, so a thread owns the face row (F, r) for
+//    every velocity component c and reads each scalar block entry once for all
+//    d components; the cell rows (T, q) use the same coupling array read by
+//    column (lanes q contiguous) and S_TT by column (it is symmetric);
+//  * v&p-cond: a thread owns one row of the d*p face block.
+// The operator is symmetric, so the entry (r, k) of the block (F, F') equals the
+// entry (k, r) of its mirror block (F', F): reading the mirror by columns gives
+// lanes r consecutive addresses (coalesced) where the block itself would be
+// read with a row stride.
+// With SPLIT the face part of x is the sum of the two slot vectors x and xs1
+// (Schwarz output), and xsum (if not null) receives that sum.
+#include "dev_common.h"
+#include "device.h"
+
+namespace hho {
+namespace {
+
+template <typename T, bool SPLIT>
+__device__ inline T xface(const T *__restrict__ x, const T *__restrict__ xs1, int64_t i) {
+  if (SPLIT) return x[i] + xs1[i];
+  return x[i];
+}
+
+template <typename T, int D, int P, int TT, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+                                                    const T *__restrict__ xs1, T *__restrict__ xsum,
+                                                    const T *__restrict__ b, T *__restrict__ y) {
+  constexpr int DP = D * P;
+  const int64_t nfr = (int64_t)tp.nf * P;
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= nfr + (int64_t)tp.nc * TT) return;
+  if (o < nfr) {
+    const int f = (int)(o / P), r = (int)(o % P);
+    T acc[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = 0;
+    const int rb = tp.rowptr[f], re = tp.rowptr[f + 1];
+    for (int bi = rb; bi < re; ++bi) {
+      const int64_t fc = tp.col[bi];
+      const T *blk = L.bsr + (int64_t)tp.mirror[bi] * (P * P) + r;
+      T bv[P];
+#pragma unroll
+      for (int k = 0; k < P; ++k) bv[k] = blk[k * P];
+      const int64_t xo = fc * DP;
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int k = 0; k < P; ++k) acc[c] += bv[k] * xface<T, SPLIT>(x, xs1, xo + c * P + k);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int Tc = tp.fcell[2 * f + s];
+      if (Tc < 0) continue;
+      const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + s];
+      const T *cp = L.cpl + (e * DP + r) * TT;
+      const T *xp = x + L.nface + (int64_t)Tc * TT;
+      T xv[TT];
+#pragma unroll
+      for (int q = 0; q < TT; ++q) xv[q] = xp[q];
+#pragma unroll
+      for (int c = 0; c < D; ++c)
+#pragma unroll
+        for (int q = 0; q < TT; ++q) acc[c] += cp[c * P * TT + q] * xv[q];
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+      const int64_t i = (int64_t)f * DP + c * P + r;
+      y[i] = (MODE == 1) ? (T)(b[i] - acc[c]) : acc[c];
+      if (SPLIT && xsum) xsum[i] = x[i] + xs1[i];
+    }
+  } else {
+    const int64_t oc = o - nfr;
+    const int Tc = (int)(oc / TT), q = (int)(oc % TT);
+    T acc = 0;
+    const int eb = tp.cptr[Tc], ee = tp.cptr[Tc + 1];
+    for (int e = eb; e < ee; ++e) {
+      const int64_t xo = (int64_t)tp.cface[e] * DP;
+      const T *cp = L.cpl + (int64_t)e * DP * TT + q;
+#pragma unroll
+      for (int j = 0; j < DP; ++j) acc += cp[j * TT] * xface<T, SPLIT>(x, xs1, xo + j);
+    }
+    const T *sp = L.spp + (int64_t)Tc * TT * TT + q;
+    const T *xp = x + L.nface + (int64_t)Tc * TT;
+#pragma unroll
+    for (int q2 = 0; q2 < TT; ++q2) acc += sp[q2 * TT] * xp[q2];
+    const int64_t i = L.nface + oc;
+    y[i] = (MODE == 1) ? (T)(b[i] - acc) : acc;
+    if (SPLIT && xsum) xsum[i] = x[i];
+  }
+}
+
+template <typename T, int BS, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+                                                     const T *__restrict__ xs1, T *__restrict__ xsum,
+                                                     const T *__restrict__ b, T *__restrict__ y) {
+  const int64_t nfr = (int64_t)tp.nf * BS;
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= nfr + tp.nc) return;
+  if (o < nfr) {
+    const int f = (int)(o / BS), i = (int)(o % BS);
+    T acc = 0;
+    const int rb = tp.rowptr[f], re = tp.rowptr[f + 1];
+    for (int bi = rb; bi < re; ++bi) {
+      const int64_t xo = (int64_t)tp.col[bi] * BS;
+      const T *blk = L.bsr + (int64_t)tp.mirror[bi] * (BS * BS) + i;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) acc += blk[k * BS] * xface<T, SPLIT>(x, xs1, xo + k);
+    }
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int Tc = tp.fcell[2 * f + s];
+      if (Tc < 0) continue;
+      const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + s];
+      acc += L.cpl[e * BS + i] * x[L.nface + Tc];
+    }
+    y[o] = (MODE == 1) ? (T)(b[o] - acc) : acc;
+    if (SPLIT && xsum) xsum[o] = x[o] + xs1[o];
+  } else {
+    const int Tc = (int)(o - nfr);
+    T acc = 0;
+    const int eb = tp.cptr[Tc], ee = tp.cptr[Tc + 1];
+    for (int e = eb; e < ee; ++e) {
+      const int64_t xo = (int64_t)tp.cface[e] * BS;
+      const T *cp = L.cpl + (int64_t)e * BS;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) acc += cp[k] * xface<T, SPLIT>(x, xs1, xo + k);
+    }
+    y[o] = (MODE == 1) ? (T)(b[o] - acc) : acc;
+    if (SPLIT && xsum) xsum[o] = x[o];
+  }
+}
+
+constexpr int dimP(int d, int k) { return d == 2 ? k + 1 : (k + 1) * (k + 2) / 2; }
+constexpr int dimT(int d, int k) { return d == 2 ? (k + 1) * (k + 2) / 2 : (k + 1) * (k + 2) * (k + 3) / 6; }
+
+template <typename T, bool SPLIT, int MODE, int D, int K>
+bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+                hipStream_t s) {
+  constexpr int P = dimP(D, K), TT = dimT(D, K);
+  if (tp.d != D || L.p != P) return false;
+  if (L.cond == 1) {
+    if (L.t != TT) return false;
+    const int64_t total = (int64_t)tp.nf * P + (int64_t)tp.nc * TT;
+    const int grid = (int)((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(kBlock), 0, s, tp, L, x, xs1, xsum, b,
+                       y);
+  } else {
+    const int64_t total = (int64_t)tp.nf * D * P + tp.nc;
+    const int grid = (int)((total + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(kBlock), 0, s, tp, L, x, xs1, xsum, b,
+                       y);
+  }
+  return true;
+}
+
+template <typename T, bool SPLIT, int MODE>
+bool dispatch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+              hipStream_t s) {
+  return try_launch<T, SPLIT, MODE, 2, 0>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 2, 1>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 2, 2>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 2, 3>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 2, 4>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 3, 0>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 3, 1>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 3, 2>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, SPLIT, MODE, 3, 3>(tp, L, x, xs1, xsum, b, y, s);
+}
+
+}  // namespace
+
+template <typename T>
+bool launch_spmv_fixed(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+                       hipStream_t s) {
+  if (tp.nf == 0 && tp.nc == 0) return true;
+  if (b) return dispatch<T, false, 1>(tp, L, x, nullptr, nullptr, b, y, s);
+  if (xs1) return dispatch<T, true, 0>(tp, L, x, xs1, xsum, nullptr, y, s);
+  return dispatch<T, false, 0>(tp, L, x, nullptr, nullptr, nullptr, y, s);
+}
+
+template bool launch_spmv_fixed<double>(const DTopo &, const DLevel<double> &, const double *, const double *,
+                                        double *, const double *, double *, hipStream_t);
+template bool launch_spmv_fixed<float>(const DTopo &, const DLevel<float> &, const float *, const float *, float *,
+                                       const float *, float *, hipStream_t);
+
+}  // namespace hho

@@ -70,7 +70,7 @@ struct hho_problem {
   LocalData loc;
   bool have_data = false;
   // host topology
-  std::vector<int32_t> cptr, cface, fcell, floc, rowptr, col, blksrc, pairblk;
+  std::vector<int32_t> cptr, cface, fcell, floc, rowptr, col, mirror, blksrc, pairblk;
   std::vector<int64_t> pairoff;
   std::vector<double> zmean;
   int64_t nnzb = 0, ncf = 0;
@@ -130,6 +130,7 @@ static void plan(hho_problem *P, Arena &A) {
   P->tp.floc = A.take<int32_t>(2 * nf);
   P->tp.rowptr = A.take<int32_t>(nf + 1);
   P->tp.col = A.take<int32_t>(P->nnzb);
+  P->tp.mirror = A.take<int32_t>(P->nnzb);
   P->tp.blksrc = A.take<int32_t>(6 * P->nnzb);
   P->tp.pairoff = A.take<int64_t>(nc + 1);
   P->tp.pairblk = A.take<int32_t>(P->pairoff[nc]);
@@ -363,6 +364,17 @@ static void build_topology(hho_problem *P) {
         P->blksrc[6 * b + 3 * s + 2] = j;
       }
   }
+  // mirror block: (f, g) -> (g, f); the operator is symmetric, so the transpose of
+  // the mirror block is the block itself (column access becomes contiguous)
+  P->mirror.assign(P->nnzb, -1);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int32_t b = P->rowptr[f]; b < P->rowptr[f + 1]; ++b) {
+      const int32_t g = P->col[b];
+      auto b0 = P->col.begin() + P->rowptr[g], b1 = P->col.begin() + P->rowptr[g + 1];
+      auto it = std::lower_bound(b0, b1, (int32_t)f);
+      if (it == b1 || *it != (int32_t)f) fail(HHO_E_MESH, "face-block pattern is not symmetric");
+      P->mirror[b] = (int32_t)(it - P->col.begin());
+    }
   P->fdiag.assign(nf, -1);
   for (int64_t f = 0; f < nf; ++f) {
     auto b0 = P->col.begin() + P->rowptr[f], b1 = P->col.begin() + P->rowptr[f + 1];
@@ -424,6 +436,7 @@ static void device_upload(hho_problem *P) {
   h2d((void *)P->tp.floc, P->floc.data(), P->floc.size() * 4);
   h2d((void *)P->tp.rowptr, P->rowptr.data(), P->rowptr.size() * 4);
   h2d((void *)P->tp.col, P->col.data(), P->col.size() * 4);
+  h2d((void *)P->tp.mirror, P->mirror.data(), P->mirror.size() * 4);
   h2d((void *)P->tp.blksrc, P->blksrc.data(), P->blksrc.size() * 4);
   h2d((void *)P->tp.pairoff, P->pairoff.data(), P->pairoff.size() * 8);
   h2d((void *)P->tp.pairblk, P->pairblk.data(), P->pairblk.size() * 4);
