@@ -26,6 +26,33 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time-to-1e-8 residual & V-cycle GDOF/s: mixed/learned vs plain FP64, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+COPY_BYTES = 1 << 30
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_digest():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_spmv.hip", "device.h", "dev_common.h"):
+        with open(os.path.join(ROOT, "paper_2009_13840_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, kernel):
+    """HBM bytes per launch of `kernel` on `workload` from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the plain-copy factor), or
+    None when no summary exists or the kernel sources changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_digest") != kernel_source_digest():
+        return None
+    return ent["bytes_per_launch"]
+
 
 WORKLOADS = {
     "voronoi16384_k3_v": dict(mesh="voronoi", n=16384, seed=2, k=3, cond="v"),
@@ -74,6 +101,16 @@ def spmv_bytes(mesh, k, cond, level_k, dtype_bytes=8):
     return vals * dtype_bytes + idx + 2 * N * dtype_bytes, dict(nnzb=nnzb, N=N, values=vals)
 
 
+def fine_kernel_name(d, k, cond, precision):
+    """Name of the fine-level operator kernel in its V-cycle (two-slot input) form."""
+    from math import comb
+    T = "float" if precision == "fp32" else "double"
+    p = comb(k + d - 1, d - 1)
+    if cond == "v":
+        return f"k_spmv_v<{T}, {d}, {p}, {comb(k + d, d)}, true, 0>"
+    return f"k_spmv_vp<{T}, {d * p}, true, 0>"
+
+
 def cpu_baseline(spec, sample_cells=1024):
     """The oracle as it stands, end to end (local operators, condensation,
     assembly, levels, Schwarz setup, FGMRES to 1e-8), on a smaller mesh of the
@@ -108,6 +145,8 @@ def main():
     ap.add_argument("--coarse-rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--traffic-calibration", action="store_true",
+                    help="run a plain 1 GiB device copy first (reference point for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -132,6 +171,13 @@ def main():
     P.bind("cuda:0")
     P.upload()
     torch.cuda.synchronize()
+    if args.traffic_calibration:
+        src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     n0 = P.level_size(0)
     print(f"[bench] host local operators {t_host:.2f}s, workspace {P.workspace_size() / 2**30:.2f} GiB, "
           f"fine DOFs {n0}", file=sys.stderr, flush=True)
@@ -164,10 +210,10 @@ def main():
     nbytes, info = spmv_bytes(mesh, spec["k"], spec["cond"], spec["k"], elem)
     nbytes += info["N"] * elem  # second slot of the input face part + combined write of the input
     achieved = nbytes / (avg_ms / 1e3) / 1e9
+    kname = fine_kernel_name(mesh.dim, spec["k"], spec["cond"], args.precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": "k_spmv (level 0, V-cycle form)", "bytes_per_launch": int(nbytes),
-            "avg_launch_ms": round(avg_ms, 5)}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, kname),
+            "kernel": kname, "bytes_per_launch": int(nbytes), "avg_launch_ms": round(avg_ms, 5)}
 
     cpu = None
     if not args.no_cpu_baseline:
