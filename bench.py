@@ -58,6 +58,10 @@ WORKLOADS = {
     "voronoi16384_k3_v": dict(mesh="voronoi", n=16384, seed=2, k=3, cond="v"),
     "voronoi16384_k3_vp": dict(mesh="voronoi", n=16384, seed=2, k=3, cond="vp"),
     "quad8_k1_v": dict(mesh="quad", n=8, seed=1, k=1, cond="v"),
+    # unit cube, uniform hexahedra, homogeneous Dirichlet, trig-series force
+    "hex32_k2_vp": dict(mesh="hex", n=32, seed=3, k=2, cond="vp"),
+    "hex32_k3_vp": dict(mesh="hex", n=32, seed=3, k=3, cond="vp"),
+    "hex24_k3_v": dict(mesh="hex", n=24, seed=1000, k=3, cond="v"),
 }
 
 
@@ -117,10 +121,13 @@ def cpu_baseline(spec, sample_cells=1024):
     same family; reported in the metric's unit (fine DOFs solved per second)."""
     from threadpoolctl import threadpool_limits
     import oracle.solve as OS
-    from synth import voronoi_lloyd, cartesian_quads
+    from synth import voronoi_lloyd, cartesian_quads, cartesian_hexes
     if spec["mesh"] == "voronoi":
         mesh = voronoi_lloyd(sample_cells, spec["seed"])
         name = f"voronoi{sample_cells}_k{spec['k']}_{spec['cond']}"
+    elif spec["mesh"] == "hex":
+        mesh = cartesian_hexes(4)
+        name = f"hex4_k{spec['k']}_{spec['cond']}"
     else:
         mesh = cartesian_quads(spec["n"])
         name = f"quad{spec['n']}_k{spec['k']}_{spec['cond']}"

@@ -16,7 +16,9 @@ that preconditioner, used to check the GPU implementation:
 * lambda: 15 power-iteration steps v <- D^{-1} A v / |.| from the start vector
   v_i = frac(i * 2654435761 / 2^32) - 1/2, times 1.05 (estimate of rho(D^{-1} A))
 * tentative prolongator T (0/1), P = T - (omega/lambda) D^{-1} A T with
-  omega = 4/3, A_next = P^T A P, down to <= 128 unknowns, then a dense inverse
+  omega = 4/3, A_next = P^T A P, down to <= 128 unknowns, then a dense inverse;
+  coarsening stops earlier when A_next would hold more than 160 entries per row
+  (structurally), and such a coarsest level gets 6 damped-Jacobi sweeps from zero
 * V-cycle with nu (default 2) damped-Jacobi sweeps of weight 4/(3 lambda) before
   and after the coarse correction
 * pressure Schur approximation  S_T = sum_{(f,c)} C[(f,c),T]^2 / S[(f,c),(f,c)]
@@ -29,6 +31,8 @@ import scipy.sparse as sp
 
 OMEGA_SA = 4.0 / 3.0
 COARSEST = 128
+MAX_ROW_NNZ = 160
+COARSE_SWEEPS = 6
 POWER_STEPS = 15
 LAMBDA_SAFETY = 1.05
 
@@ -81,6 +85,13 @@ class SA:
             if na >= A.shape[0]:
                 break
             T = sp.csr_matrix((np.ones(A.shape[0]), (np.arange(A.shape[0]), agg)), shape=(A.shape[0], na))
+            # structural pattern of the next operator (P pattern = T + A T)
+            Ab = A.copy()
+            Ab.data[:] = 1.0
+            Pb = (T + Ab @ T).tocsr()
+            Pb.data[:] = 1.0
+            if (Pb.T @ Ab @ Pb).nnz > MAX_ROW_NNZ * na:
+                break
             D = A.diagonal()
             lam = spectral_radius_estimate(A)
             P = (T - (OMEGA_SA / lam) * (sp.diags(1.0 / D) @ A @ T)).tocsr()
@@ -91,12 +102,24 @@ class SA:
             G = (T.T @ G @ T).tocsr()
             G.data[:] = 1.0
             G.sort_indices()
-        self.Ainv = np.linalg.inv(A.toarray())
+        self.Ac = A
+        if A.shape[0] <= COARSEST:
+            self.Ainv = np.linalg.inv(A.toarray())
+        else:
+            self.Ainv = None
+            self.Dc = 1.0 / A.diagonal()
+            self.lam_c = spectral_radius_estimate(A)
         self.sizes = [L[0].shape[0] for L in self.levels] + [A.shape[0]]
 
     def vcycle(self, r: np.ndarray, l: int = 0) -> np.ndarray:
         if l == len(self.levels):
-            return self.Ainv @ r
+            if self.Ainv is not None:
+                return self.Ainv @ r
+            w = 4.0 / (3.0 * self.lam_c)
+            x = np.zeros_like(r)
+            for _ in range(COARSE_SWEEPS):
+                x = x + w * self.Dc * (r - self.Ac @ x)
+            return x
         A, P, Di = self.levels[l]
         w = 4.0 / (3.0 * self.lams[l])
         x = np.zeros_like(r)

@@ -146,7 +146,10 @@ class Mesh:
 def options(**kw) -> Options:
     o = Options()
     load().hho_options_default(C.byref(o))
+    names = {f[0] for f in Options._fields_}
     for k, v in kw.items():
+        if k not in names:
+            raise TypeError(f"unknown option {k!r}; known: {sorted(names)}")
         if k == "precision":
             v = PREC[v] if isinstance(v, str) else v
         if k == "coarse_mode":

@@ -11,6 +11,8 @@ namespace hho {
 constexpr double kAmgOmegaSA = 4.0 / 3.0;   // prolongator smoothing weight (divided by lambda)
 constexpr double kAmgOmegaJac = 4.0 / 3.0;  // damped-Jacobi smoother weight (divided by lambda)
 constexpr int kAmgCoarsest = 128;           // dense inverse at or below this size
+constexpr int kAmgMaxRowNnz = 160;          // stop coarsening before a level this dense (entries per row)
+constexpr int kAmgCoarseSweeps = 6;         // Jacobi sweeps on a coarsest level above kAmgCoarsest
 constexpr int kAmgPowerSteps = 15;          // power iterations for lambda ~ rho(D^{-1} A)
 constexpr double kAmgLambdaSafety = 1.05;
 

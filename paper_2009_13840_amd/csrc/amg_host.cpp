@@ -12,25 +12,45 @@
 //   B = A P  (pairs (A entry, P entry)),
 //   A_{l+1} = P^T B  (pairs (P entry, B entry)).
 #include <algorithm>
-#include <map>
 
 #include "amg.h"
 
 namespace hho {
 
-static void csr_from_rows(const std::vector<std::vector<int32_t>> &rows, std::vector<int32_t> &rp,
-                          std::vector<int32_t> &ci) {
-  rp.assign(rows.size() + 1, 0);
-  for (size_t i = 0; i < rows.size(); ++i) rp[i + 1] = rp[i] + (int32_t)rows[i].size();
-  ci.resize(rp.back());
-  for (size_t i = 0; i < rows.size(); ++i) std::copy(rows[i].begin(), rows[i].end(), ci.begin() + rp[i]);
-}
+// Entries (column, first source, second source) of one output row, grouped by
+// column: columns ascending and, within a column, the entries in the order they
+// were produced (the device sums them in that order).
+struct RowGroups {
+  struct E {
+    int32_t col, seq, a, b;
+  };
+  std::vector<E> e;
+  void clear() { e.clear(); }
+  void add(int32_t col, int32_t a, int32_t b) { e.push_back({col, (int32_t)e.size(), a, b}); }
+  // appends the row to (cols, pair offsets, pair lists)
+  // (skip_negative: entries whose first source is < 0 only create their column)
+  void flush(std::vector<int32_t> &cols, std::vector<int32_t> &pp, std::vector<int32_t> &pa,
+             std::vector<int32_t> *pb, bool skip_negative = false) {
+    std::sort(e.begin(), e.end(), [](const E &x, const E &y) { return x.col != y.col ? x.col < y.col : x.seq < y.seq; });
+    for (size_t i = 0; i < e.size(); ++i) {
+      if (i == 0 || e[i].col != e[i - 1].col) {
+        cols.push_back(e[i].col);
+        pp.push_back((int32_t)pa.size());
+      }
+      if (skip_negative && e[i].a < 0) continue;
+      pa.push_back(e[i].a);
+      if (pb) pb->push_back(e[i].b);
+    }
+    e.clear();
+  }
+};
 
 void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, AmgHost *H) {
   H->levels.clear();
   std::vector<int32_t> rp(rp0, rp0 + n0 + 1), ci(ci0, ci0 + rp0[n0]);
   std::vector<int32_t> grp = rp, gci = ci;  // aggregation graph (pattern of T^T G T)
   int n = n0;
+  RowGroups rg;
   for (;;) {
     AmgHostLevel L;
     L.n = n;
@@ -64,101 +84,99 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
       break;
     }
     L.nc = na;
-    // P pattern and its gather lists (A entries per (row, aggregate))
-    std::vector<std::vector<int32_t>> prow(n);
-    std::vector<std::vector<std::vector<int32_t>>> plist(n);
+    // P pattern and its gather lists (A entries summed per (row, aggregate));
+    // the tentative entry (i, agg[i]) exists even if no A entry falls in it
+    L.prp.assign(1, 0);
     for (int i = 0; i < n; ++i) {
-      std::map<int32_t, std::vector<int32_t>> m;
-      m[L.agg[i]];  // T contributes (i, agg[i]) even if nothing else does
-      for (int e = rp[i]; e < rp[i + 1]; ++e) m[L.agg[ci[e]]].push_back(e);
-      for (auto &kv : m) {
-        prow[i].push_back(kv.first);
-        plist[i].push_back(kv.second);
-      }
+      rg.add(L.agg[i], -1, 0);
+      for (int e = rp[i]; e < rp[i + 1]; ++e) rg.add(L.agg[ci[e]], e, 0);
+      rg.flush(L.pci, L.pgp, L.pgi, nullptr, /*skip_negative=*/true);
+      L.prp.push_back((int32_t)L.pci.size());
     }
-    csr_from_rows(prow, L.prp, L.pci);
-    L.pgp.assign(L.pci.size() + 1, 0);
-    for (int i = 0, k = 0; i < n; ++i)
-      for (auto &lst : plist[i]) {
-        L.pgp[k + 1] = L.pgp[k] + (int32_t)lst.size();
-        L.pgi.insert(L.pgi.end(), lst.begin(), lst.end());
-        ++k;
-      }
+    L.pgp.push_back((int32_t)L.pgi.size());
     L.pself.resize(L.pci.size());
     for (int i = 0; i < n; ++i)
       for (int e = L.prp[i]; e < L.prp[i + 1]; ++e) L.pself[e] = (L.pci[e] == L.agg[i]) ? 1 : 0;
-    // P^T (by coarse column): rows i and P entry indices
-    std::vector<std::vector<std::pair<int32_t, int32_t>>> pt(na);
-    for (int i = 0; i < n; ++i)
-      for (int e = L.prp[i]; e < L.prp[i + 1]; ++e) pt[L.pci[e]].push_back({i, e});
+    // P^T (by coarse column): rows i and P entry indices, rows ascending
     L.ptp.assign(na + 1, 0);
-    for (int I = 0; I < na; ++I) {
-      L.ptp[I + 1] = L.ptp[I] + (int32_t)pt[I].size();
-      for (auto &pr : pt[I]) {
-        L.pti.push_back(pr.first);
-        L.pte.push_back(pr.second);
+    for (size_t e = 0; e < L.pci.size(); ++e) ++L.ptp[L.pci[e] + 1];
+    for (int I = 0; I < na; ++I) L.ptp[I + 1] += L.ptp[I];
+    L.pti.resize(L.pci.size());
+    L.pte.resize(L.pci.size());
+    {
+      std::vector<int32_t> fill(L.ptp.begin(), L.ptp.end() - 1);
+      for (int i = 0; i < n; ++i)
+        for (int e = L.prp[i]; e < L.prp[i + 1]; ++e) {
+          const int32_t q = fill[L.pci[e]]++;
+          L.pti[q] = i;
+          L.pte[q] = e;
+        }
+    }
+    // stop when the next operator would be nearly dense (three-dimensional
+    // meshes fill in quickly): this level becomes the coarsest, handled by
+    // Jacobi sweeps (or the dense inverse when small)
+    {
+      std::vector<int32_t> mark(na, -1);
+      int64_t cnt = 0;
+      for (int I = 0; I < na; ++I)
+        for (int k = L.ptp[I]; k < L.ptp[I + 1]; ++k) {
+          const int i = L.pti[k];
+          for (int e = rp[i]; e < rp[i + 1]; ++e)
+            for (int pe = L.prp[ci[e]]; pe < L.prp[ci[e] + 1]; ++pe)
+              if (mark[L.pci[pe]] != I) {
+                mark[L.pci[pe]] = I;
+                ++cnt;
+              }
+        }
+      if (cnt > (int64_t)kAmgMaxRowNnz * na) {
+        AmgHostLevel C;
+        C.n = L.n;
+        C.nc = 0;
+        C.rp.swap(L.rp);
+        C.ci.swap(L.ci);
+        C.diag.swap(L.diag);
+        H->levels.push_back(std::move(C));
+        break;
       }
     }
     // B = A P : pattern + pairs (A entry, P entry)
-    std::vector<std::vector<int32_t>> brow(n);
-    std::vector<std::vector<std::vector<std::pair<int32_t, int32_t>>>> bpairs(n);
+    L.brp.assign(1, 0);
     for (int i = 0; i < n; ++i) {
-      std::map<int32_t, std::vector<std::pair<int32_t, int32_t>>> m;
       for (int e = rp[i]; e < rp[i + 1]; ++e) {
         const int j = ci[e];
-        for (int pe = L.prp[j]; pe < L.prp[j + 1]; ++pe) m[L.pci[pe]].push_back({e, pe});
+        for (int pe = L.prp[j]; pe < L.prp[j + 1]; ++pe) rg.add(L.pci[pe], e, pe);
       }
-      for (auto &kv : m) {
-        brow[i].push_back(kv.first);
-        bpairs[i].push_back(kv.second);
-      }
+      rg.flush(L.bci, L.bpp, L.bpa, &L.bpb);
+      L.brp.push_back((int32_t)L.bci.size());
     }
-    csr_from_rows(brow, L.brp, L.bci);
-    L.bpp.assign(L.bci.size() + 1, 0);
-    for (int i = 0, k = 0; i < n; ++i)
-      for (auto &lst : bpairs[i]) {
-        L.bpp[k + 1] = L.bpp[k] + (int32_t)lst.size();
-        for (auto &pr : lst) {
-          L.bpa.push_back(pr.first);
-          L.bpb.push_back(pr.second);
-        }
-        ++k;
-      }
+    L.bpp.push_back((int32_t)L.bpa.size());
     // A_next = P^T B : pattern + pairs (P entry, B entry)
-    std::vector<std::vector<int32_t>> crow(na);
-    std::vector<std::vector<std::vector<std::pair<int32_t, int32_t>>>> cpairs(na);
+    std::vector<int32_t> nrp(1, 0), nci;
     for (int I = 0; I < na; ++I) {
-      std::map<int32_t, std::vector<std::pair<int32_t, int32_t>>> m;
       for (int k = L.ptp[I]; k < L.ptp[I + 1]; ++k) {
         const int i = L.pti[k], pe = L.pte[k];
-        for (int be = L.brp[i]; be < L.brp[i + 1]; ++be) m[L.bci[be]].push_back({pe, be});
+        for (int be = L.brp[i]; be < L.brp[i + 1]; ++be) rg.add(L.bci[be], pe, be);
       }
-      for (auto &kv : m) {
-        crow[I].push_back(kv.first);
-        cpairs[I].push_back(kv.second);
-      }
+      rg.flush(nci, L.cpp, L.cpa, &L.cpb);
+      nrp.push_back((int32_t)nci.size());
     }
-    std::vector<int32_t> nrp, nci;
-    csr_from_rows(crow, nrp, nci);
-    L.cpp.assign(nci.size() + 1, 0);
-    for (int I = 0, k = 0; I < na; ++I)
-      for (auto &lst : cpairs[I]) {
-        L.cpp[k + 1] = L.cpp[k] + (int32_t)lst.size();
-        for (auto &pr : lst) {
-          L.cpa.push_back(pr.first);
-          L.cpb.push_back(pr.second);
-        }
-        ++k;
-      }
+    L.cpp.push_back((int32_t)L.cpa.size());
     // next aggregation graph: aggregates adjacent when any of their members are
-    std::vector<std::vector<int32_t>> grow(na);
-    for (int i = 0; i < n; ++i)
-      for (int e = grp[i]; e < grp[i + 1]; ++e) grow[L.agg[i]].push_back(L.agg[gci[e]]);
-    for (auto &r : grow) {
-      std::sort(r.begin(), r.end());
-      r.erase(std::unique(r.begin(), r.end()), r.end());
+    {
+      std::vector<int32_t> ngp(1, 0), ngi, dummy;
+      std::vector<std::vector<int32_t>> members(na);
+      for (int i = 0; i < n; ++i) members[L.agg[i]].push_back(i);
+      for (int I = 0; I < na; ++I) {
+        for (int i : members[I])
+          for (int e = grp[i]; e < grp[i + 1]; ++e) rg.add(L.agg[gci[e]], 0, 0);
+        std::vector<int32_t> pp;
+        rg.flush(ngi, pp, dummy, nullptr);
+        dummy.clear();
+        ngp.push_back((int32_t)ngi.size());
+      }
+      grp.swap(ngp);
+      gci.swap(ngi);
     }
-    csr_from_rows(grow, grp, gci);
     H->levels.push_back(std::move(L));
     rp = nrp;
     ci = nci;

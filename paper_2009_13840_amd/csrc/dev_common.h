@@ -32,29 +32,7 @@ __device__ inline double block_sum(double v, double *lds /* >= 16 */) {
   return r;
 }
 
-// "Last block" completion: every block calls this after writing its partial
-// results; exactly one block (the last to arrive) gets true, after a
-// device-scope fence that makes every other block's partials visible.  The
-// counter is reset for the next launch by that block.
-__device__ inline bool last_block_arrived(int *counter) {
-  __shared__ int s_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int prev = atomicAdd(counter, 1);
-    s_last = (prev == (int)gridDim.x - 1);
-  }
-  __syncthreads();
-  if (s_last) {
-    __threadfence();
-    if (threadIdx.x == 0) atomicExch(counter, 0);
-  }
-  return s_last != 0;
-}
-
-__device__ inline double vload(const double *p) { return *(volatile const double *)p; }
-
-// Inside the last block: out[k] = sum_b partial[k*G + b] for k < K.  Waves take
+// Inside a one-block finishing kernel: out[k] = sum_b partial[k*G + b] for k < K.  Waves take
 // the sums in turn, lanes split the G partials (parallel loads), the per-lane
 // order and the wave tree are fixed, so the result is deterministic.  `out` must
 // be visible to the whole block (LDS); a barrier ends the function.
@@ -62,7 +40,7 @@ __device__ inline void reduce_partials(const double *partial, int G, int K, doub
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
   for (int k = wid; k < K; k += nw) {
     double s = 0;
-    for (int b = lane; b < G; b += kWave) s += vload(&partial[(int64_t)k * G + b]);
+    for (int b = lane; b < G; b += kWave) s += partial[(int64_t)k * G + b];
     s = wave_sum(s);
     if (lane == 0) out[k] = s;
   }

@@ -101,28 +101,31 @@ void launch_prolong_add(int d, int nf, int nc, int pf, int tf, int pc, int tc, c
 //   G = [w1 w2]^T [w1 w2], g = [w1 w2]^T r, y = G^{-1} g, x += Z y, r -= W y.
 template <typename T>
 void launch_mr2_dots(int64_t n, int m, const T *w1, const T *w2, const T *r, double *partial, double *y,
-                     int *counter, hipStream_t s);
+                     hipStream_t s);
 template <typename T>
 void launch_mr2_update(int64_t n, int m, const double *y, const T *z1, const T *z2, const T *w1, const T *w2,
                        T *x, T *r, hipStream_t s);
 
 struct GmresState;
 template <typename T>
-void launch_norm_init(int64_t n, const T *r, double *partial, GmresState *st, int *counter, int which,
-                      hipStream_t s);
+void launch_norm_init(int64_t n, const T *r, double *partial, GmresState *st, int which, hipStream_t s);
 template <typename T>
 void launch_scale(int64_t n, const T *x, const double *scale, T *y, hipStream_t s);
+// Arnoldi step j (Section 3.3) on the basis V (columns of length n, stride ldv):
+// dots: h1 = V^T w;  update pass 1: w -= V h1, h2 = V^T w;  update pass 2:
+// w -= V h (h2 when cgs2, else h1), H[:, j] = h1 (+ h2), Givens rotation,
+// residual estimate and convergence flag in *st.
 template <typename T>
 void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
-                         int *counter, hipStream_t s);
+                         hipStream_t s);
 template <typename T>
 void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partial, GmresState *st,
-                           int *counter, int pass, hipStream_t s);
+                           int pass, int cgs2, hipStream_t s);
 void launch_gmres_solve_ls(GmresState *st, hipStream_t s);
 template <typename T>
 void launch_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresState *st, T *x, hipStream_t s);
 template <typename T>
-void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out, int *counter, hipStream_t s);
+void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out, hipStream_t s);
 // y += sign * alpha[0] / alpha[1] * x
 template <typename T>
 void launch_axpy_ratio(int64_t n, const double *alpha, double sign, const T *x, T *y, hipStream_t s);

@@ -30,7 +30,6 @@ struct AmgDev {
   int nlev = 0;
   AmgDevLevel lev[kMaxAmgLevels];
   double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr, *pw = nullptr;
-  int *counter = nullptr;
 };
 
 void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int *err,

@@ -41,12 +41,11 @@ __global__ void k_amg_diag(int n, const int32_t *diag, const double *val, double
   }
 }
 
-// one power-iteration step: vout = D^{-1} A (vin / lam_in), lam_out = |vout|
-// (lam_in == null: no scaling).  The last block writes lam_out, times `safety`.
+// one power-iteration step: vout = D^{-1} A (vin / lam_in), partial sums of |vout|^2
+// (lam_in == null: no scaling); k_amg_power_finish writes lam_out = safety * |vout|.
 __global__ void __launch_bounds__(kBlock) k_amg_power(int n, const int32_t *rp, const int32_t *ci, const double *val,
                                                        const double *dinv, const double *vin, const double *lam_in,
-                                                       double *vout, double *partial, double *lam_out, double safety,
-                                                       int *counter) {
+                                                       double *vout, double *partial) {
   __shared__ double red[16];
   const double sc = lam_in ? 1.0 / lam_in[0] : 1.0;
   double acc = 0;
@@ -59,11 +58,13 @@ __global__ void __launch_bounds__(kBlock) k_amg_power(int n, const int32_t *rp, 
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  if (last_block_arrived(counter)) {
-    __shared__ double tot[1];
-    reduce_partials(partial, gridDim.x, 1, tot);
-    if (threadIdx.x == 0) lam_out[0] = safety * sqrt(tot[0]);
-  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_amg_power_finish(int G, const double *partial, double *lam_out,
+                                                              double safety) {
+  __shared__ double tot[1];
+  reduce_partials(partial, G, 1, tot);
+  if (threadIdx.x == 0) lam_out[0] = safety * sqrt(tot[0]);
 }
 
 // P = T - (omega / lambda) D^{-1} A T
@@ -294,7 +295,7 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
                      A.lev[0].val);
   for (int l = 0; l < A.nlev; ++l) {
     const AmgDevLevel &L = A.lev[l];
-    if (l == A.nlev - 1) {
+    if (l == A.nlev - 1 && A.ainv) {
       hipLaunchKernelGGL(k_amg_coarsest, dim3(1), dim3(kBlock), 0, s, L.n, L.rp, L.ci, L.val, A.dense_scratch,
                          A.ainv, err);
       break;
@@ -308,9 +309,11 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
       double *vout = (k % 2 == 0) ? L.res : L.tmp;
       const bool last = k == kAmgPowerSteps - 1;
       hipLaunchKernelGGL(k_amg_power, dim3(nb), dim3(kBlock), 0, s, L.n, L.rp, L.ci, (const double *)L.val,
-                         (const double *)L.dinv, vin, (const double *)(k ? A.pw + k - 1 : nullptr), vout, A.partial,
-                         last ? L.lam : A.pw + k, last ? kAmgLambdaSafety : 1.0, A.counter);
+                         (const double *)L.dinv, vin, (const double *)(k ? A.pw + k - 1 : nullptr), vout, A.partial);
+      hipLaunchKernelGGL(k_amg_power_finish, dim3(1), dim3(kBlock), 0, s, nb, (const double *)A.partial,
+                         last ? L.lam : A.pw + k, last ? kAmgLambdaSafety : 1.0);
     }
+    if (l == A.nlev - 1) break;  // large coarsest level: Jacobi sweeps only
     hipLaunchKernelGGL(k_amg_p, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.prow, L.pgp, L.pgi, L.pself,
                        L.val, L.dinv, L.lam, L.pval);
     hipLaunchKernelGGL(k_amg_pairs, dim3(grid_for(L.nbe)), dim3(kBlock), 0, s, L.nbe, L.bpp, L.bpa, L.bpb,
@@ -362,8 +365,21 @@ static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, doubl
   const AmgDevLevel &L = A.lev[l];
   const int64_t nd = (int64_t)L.n * d;
   if (l == A.nlev - 1) {
-    hipLaunchKernelGGL(k_amg_dense, dim3(grid_for((int64_t)L.n * kWave)), dim3(kBlock), 0, s, L.n, d,
-                       (const double *)A.ainv, r, x);
+    if (A.ainv) {
+      hipLaunchKernelGGL(k_amg_dense, dim3(grid_for((int64_t)L.n * kWave)), dim3(kBlock), 0, s, L.n, d,
+                         (const double *)A.ainv, r, x);
+      return;
+    }
+    // kAmgCoarseSweeps damped-Jacobi sweeps from zero (the first launch takes two)
+    const int GA = amg_group((double)L.nnz / L.n);
+    constexpr int rest = kAmgCoarseSweeps - 2;
+    double *cur = (rest % 2 == 1) ? L.tmp : x;
+    rows<0>(GA, L.n, d, L, r, nullptr, cur, nullptr, s);
+    for (int it = 0; it < rest; ++it) {
+      double *nxt = (cur == x) ? L.tmp : x;
+      rows<0>(GA, L.n, d, L, r, cur, nxt, nullptr, s);
+      cur = nxt;
+    }
     return;
   }
   (void)nd;

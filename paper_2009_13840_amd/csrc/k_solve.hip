@@ -233,7 +233,7 @@ __global__ void k_transfer(int d, int nf, int nc, int pf, int tf, int pc, int tc
 // ---- smoother: minimal residual over span{z1, z2} (the GMRES(2) iterate)
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_mr2_dots(int64_t n, int m, const T *w1, const T *w2, const T *r,
-                                                      double *partial, double *y, int *counter) {
+                                                      double *partial) {
   __shared__ double red[16];
   double a11 = 0, a12 = 0, a22 = 0, g1 = 0, g2 = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
@@ -252,22 +252,24 @@ __global__ void __launch_bounds__(kBlock) k_mr2_dots(int64_t n, int m, const T *
     double s = block_sum(v[k], red);
     if (threadIdx.x == 0) partial[k * gridDim.x + blockIdx.x] = s;
   }
-  if (last_block_arrived(counter)) {
-    __shared__ double S[5];
-    reduce_partials(partial, gridDim.x, 5, S);
-    if (threadIdx.x == 0) {
-      double y1 = 0, y2 = 0;
-      const double det = S[0] * S[2] - S[1] * S[1];
-      if (m == 2 && det > 1e-14 * S[0] * S[2]) {
-        y1 = (S[2] * S[3] - S[1] * S[4]) / det;
-        y2 = (S[0] * S[4] - S[1] * S[3]) / det;
-      } else if (S[0] > 0) {
-        y1 = S[3] / S[0];
-      }
-      if (!isfinite(y1) || !isfinite(y2)) y1 = y2 = 0;
-      y[0] = y1;
-      y[1] = y2;
+}
+
+// y = G^{-1} g from the partial sums of k_mr2_dots (one block)
+__global__ void __launch_bounds__(kBlock) k_mr2_finish(int G, int m, const double *partial, double *y) {
+  __shared__ double S[5];
+  reduce_partials(partial, G, 5, S);
+  if (threadIdx.x == 0) {
+    double y1 = 0, y2 = 0;
+    const double det = S[0] * S[2] - S[1] * S[1];
+    if (m == 2 && det > 1e-14 * S[0] * S[2]) {
+      y1 = (S[2] * S[3] - S[1] * S[4]) / det;
+      y2 = (S[0] * S[4] - S[1] * S[3]) / det;
+    } else if (S[0] > 0) {
+      y1 = S[3] / S[0];
     }
+    if (!isfinite(y1) || !isfinite(y2)) y1 = y2 = 0;
+    y[0] = y1;
+    y[1] = y2;
   }
 }
 
@@ -286,124 +288,9 @@ __global__ void k_mr2_update(int64_t n, int m, const double *y, const T *z1, con
   }
 }
 
-// ---- Arnoldi reductions (classical Gram-Schmidt applied twice)
-constexpr int kMaxDots = kMaxRestartH + 1;
-
-// partial dots of w with V_0..V_j over this block's rows -> partial[i][block].
-// The vectors are taken eight at a time so that their loads are in flight together.
+// |r|^2 partial sums
 template <typename T>
-__device__ void multi_dot_partial(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial) {
-  __shared__ double red[kBlock / kWave][kMaxDots];
-  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
-  for (int i0 = 0; i0 <= j; i0 += 8) {
-    const int ni = (j + 1 - i0) < 8 ? (j + 1 - i0) : 8;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-      const double wk = w[k];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (q < ni) acc[q] += (double)V[(i0 + q) * ldv + k] * wk;
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      if (q < ni) {
-        const double sq = wave_sum(acc[q]);
-        if (lane == 0) red[wid][i0 + q] = sq;
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) {
-    double s = 0;
-    for (int w_ = 0; w_ < (int)(blockDim.x / kWave); ++w_) s += red[w_][i];
-    partial[(int64_t)i * gridDim.x + blockIdx.x] = s;
-  }
-}
-
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w,
-                                                          double *partial, GmresState *st, int *counter) {
-  if (st->done) return;
-  multi_dot_partial(n, j, V, ldv, w, partial);
-  if (last_block_arrived(counter)) {
-    __shared__ double hs[kMaxDots];
-    reduce_partials(partial, gridDim.x, j + 1, hs);
-    for (int i = threadIdx.x; i <= j; i += blockDim.x) st->h1[i] = hs[i];
-  }
-}
-
-// pass 1: w -= V h1, then partial dots for pass 2 (-> h2)
-// pass 2: w -= V h2, then |w|^2 -> column j of H, Givens rotation, residual estimate
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w,
-                                                            double *partial, GmresState *st, int *counter,
-                                                            int pass) {
-  if (st->done) return;
-  __shared__ double h[kMaxDots];
-  __shared__ double red[16];
-  for (int i = threadIdx.x; i <= j; i += blockDim.x) h[i] = (pass == 1) ? st->h1[i] : st->h2[i];
-  __syncthreads();
-  double nrm = 0;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
-    double v = w[k];
-    for (int i = 0; i <= j; ++i) v -= h[i] * (double)V[i * ldv + k];
-    w[k] = (T)v;
-    nrm += (double)(T)v * (double)(T)v;
-  }
-  if (pass == 1) {
-    __syncthreads();
-    multi_dot_partial(n, j, V, ldv, (const T *)w, partial);
-    if (last_block_arrived(counter)) {
-      __shared__ double hs[kMaxDots];
-      reduce_partials(partial, gridDim.x, j + 1, hs);
-      for (int i = threadIdx.x; i <= j; i += blockDim.x) st->h2[i] = hs[i];
-    }
-    return;
-  }
-  double s = block_sum(nrm, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  if (last_block_arrived(counter)) {
-    __shared__ double nsum[1];
-    reduce_partials(partial, gridDim.x, 1, nsum);
-    if (threadIdx.x == 0) {
-      const double nn = nsum[0];
-      const int R = kMaxRestartH;
-      double *H = st->H;
-      for (int i = 0; i <= j; ++i) H[i * R + j] = st->h1[i] + st->h2[i];
-      const double hn = sqrt(nn);
-      H[(j + 1) * R + j] = hn;
-      // apply previous rotations to column j
-      for (int i = 0; i < j; ++i) {
-        const double a = H[i * R + j], b = H[(i + 1) * R + j];
-        H[i * R + j] = st->cs[i] * a + st->sn[i] * b;
-        H[(i + 1) * R + j] = -st->sn[i] * a + st->cs[i] * b;
-      }
-      const double a = H[j * R + j], b = H[(j + 1) * R + j];
-      const double rr = sqrt(a * a + b * b);
-      const double c = (rr > 0) ? a / rr : 1.0, sn = (rr > 0) ? b / rr : 0.0;
-      st->cs[j] = c;
-      st->sn[j] = sn;
-      H[j * R + j] = rr;
-      H[(j + 1) * R + j] = 0;
-      const double gj = st->g[j];
-      st->g[j] = c * gj;
-      st->g[j + 1] = -sn * gj;
-      st->res = fabs(st->g[j + 1]);
-      st->j = j + 1;
-      st->inv_hnext = (hn > 0) ? 1.0 / hn : 0.0;
-      if (!isfinite(nn) || !isfinite(st->res)) {
-        st->nan = 1;
-        st->done = 1;
-      }
-      if (st->res <= st->rtol * st->bnorm || hn <= 1e-14 * st->beta) st->done = 1;
-    }
-  }
-}
-
-// |r| -> beta (and bnorm if which == 1), g = beta e1, reset the cycle.
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_norm_init(int64_t n, const T *r, double *partial, GmresState *st,
-                                                       int *counter, int which) {
+__global__ void __launch_bounds__(kBlock) k_sumsq(int64_t n, const T *r, double *partial) {
   __shared__ double red[16];
   double acc = 0;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
@@ -412,22 +299,24 @@ __global__ void __launch_bounds__(kBlock) k_norm_init(int64_t n, const T *r, dou
   }
   double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  if (last_block_arrived(counter)) {
-    __shared__ double nsum[1];
-    reduce_partials(partial, gridDim.x, 1, nsum);
-    if (threadIdx.x == 0) {
-      const double nn = nsum[0];
-      const double beta = sqrt(nn);
-      st->beta = beta;
-      if (which == 1) st->bnorm = beta;
-      for (int i = 0; i <= kMaxRestartH; ++i) st->g[i] = 0;
-      st->g[0] = beta;
-      st->res = beta;
-      st->j = 0;
-      st->inv_hnext = (beta > 0) ? 1.0 / beta : 0.0;
-      st->nan = !isfinite(nn);
-      st->done = (!(beta > 0) || st->nan || beta <= st->rtol * st->bnorm) ? 1 : 0;
-    }
+}
+
+// |r| -> beta (and bnorm if which == 1), g = beta e1, reset the cycle (one block).
+__global__ void __launch_bounds__(kBlock) k_norm_finish(int G, const double *partial, GmresState *st, int which) {
+  __shared__ double nsum[1];
+  reduce_partials(partial, G, 1, nsum);
+  if (threadIdx.x == 0) {
+    const double nn = nsum[0];
+    const double beta = sqrt(nn);
+    st->beta = beta;
+    if (which == 1) st->bnorm = beta;
+    for (int i = 0; i <= kMaxRestartH; ++i) st->g[i] = 0;
+    st->g[0] = beta;
+    st->res = beta;
+    st->j = 0;
+    st->inv_hnext = (beta > 0) ? 1.0 / beta : 0.0;
+    st->nan = !isfinite(nn);
+    st->done = (!(beta > 0) || st->nan || beta <= st->rtol * st->bnorm) ? 1 : 0;
   }
 }
 
@@ -462,19 +351,19 @@ __global__ void k_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresS
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const T *a, const T *b, double *partial, double *out,
-                                                 int *counter) {
+__global__ void __launch_bounds__(kBlock) k_dot(int64_t n, const T *a, const T *b, double *partial) {
   __shared__ double red[16];
   double acc = 0;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
     acc += (double)a[k] * (double)b[k];
   double s = block_sum(acc, red);
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
-  if (last_block_arrived(counter)) {
-    __shared__ double vs[1];
-    reduce_partials(partial, gridDim.x, 1, vs);
-    if (threadIdx.x == 0) out[0] = vs[0];
-  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_sum_finish(int G, const double *partial, double *out) {
+  __shared__ double vs[1];
+  reduce_partials(partial, G, 1, vs);
+  if (threadIdx.x == 0) out[0] = vs[0];
 }
 
 // y += sign * (alpha[0] / alpha[1]) * x  (alpha[1] = 1 when not a ratio)
@@ -549,9 +438,10 @@ void launch_prolong_add(int d, int nf, int nc, int pf, int tf, int pc, int tc, c
 }
 template <typename T>
 void launch_mr2_dots(int64_t n, int m, const T *w1, const T *w2, const T *r, double *partial, double *y,
-                     int *counter, hipStream_t s) {
-  hipLaunchKernelGGL((k_mr2_dots<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, m, w1, w2, r, partial, y,
-                     counter);
+                     hipStream_t s) {
+  const int G = reduce_blocks(n);
+  hipLaunchKernelGGL((k_mr2_dots<T>), dim3(G), dim3(kBlock), 0, s, n, m, w1, w2, r, partial);
+  hipLaunchKernelGGL(k_mr2_finish, dim3(1), dim3(kBlock), 0, s, G, m, (const double *)partial, y);
 }
 template <typename T>
 void launch_mr2_update(int64_t n, int m, const double *y, const T *z1, const T *z2, const T *w1, const T *w2,
@@ -559,25 +449,14 @@ void launch_mr2_update(int64_t n, int m, const double *y, const T *z1, const T *
   hipLaunchKernelGGL((k_mr2_update<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, m, y, z1, z2, w1, w2, x, r);
 }
 template <typename T>
-void launch_norm_init(int64_t n, const T *r, double *partial, GmresState *st, int *counter, int which,
-                      hipStream_t s) {
-  hipLaunchKernelGGL((k_norm_init<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, r, partial, st, counter, which);
+void launch_norm_init(int64_t n, const T *r, double *partial, GmresState *st, int which, hipStream_t s) {
+  const int G = reduce_blocks(n);
+  hipLaunchKernelGGL((k_sumsq<T>), dim3(G), dim3(kBlock), 0, s, n, r, partial);
+  hipLaunchKernelGGL(k_norm_finish, dim3(1), dim3(kBlock), 0, s, G, (const double *)partial, st, which);
 }
 template <typename T>
 void launch_scale(int64_t n, const T *x, const double *scale, T *y, hipStream_t s) {
   hipLaunchKernelGGL((k_scale<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, scale, y);
-}
-template <typename T>
-void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
-                         int *counter, hipStream_t s) {
-  hipLaunchKernelGGL((k_arnoldi_dots<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, j, V, ldv, w, partial, st,
-                     counter);
-}
-template <typename T>
-void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partial, GmresState *st,
-                           int *counter, int pass, hipStream_t s) {
-  hipLaunchKernelGGL((k_arnoldi_update<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, j, V, ldv, w, partial,
-                     st, counter, pass);
 }
 void launch_gmres_solve_ls(GmresState *st, hipStream_t s) {
   hipLaunchKernelGGL(k_gmres_solve_ls, dim3(1), dim3(64), 0, s, st);
@@ -587,8 +466,10 @@ void launch_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresState *
   hipLaunchKernelGGL((k_gmres_combine<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, Z, ldz, st, x);
 }
 template <typename T>
-void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out, int *counter, hipStream_t s) {
-  hipLaunchKernelGGL((k_dot<T>), dim3(reduce_blocks(n)), dim3(kBlock), 0, s, n, a, b, partial, out, counter);
+void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out, hipStream_t s) {
+  const int G = reduce_blocks(n);
+  hipLaunchKernelGGL((k_dot<T>), dim3(G), dim3(kBlock), 0, s, n, a, b, partial);
+  hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kBlock), 0, s, G, (const double *)partial, out);
 }
 template <typename T>
 void launch_axpy_ratio(int64_t n, const double *alpha, double sign, const T *x, T *y, hipStream_t s) {
@@ -609,18 +490,14 @@ void launch_copy(int64_t n, const T *x, T *y, hipStream_t s) {
   template void launch_precond<T>(const DTopo &, const DLevel<T> &, const T *, const double *, T *, T *, T *,   \
                                   int, hipStream_t);                                                           \
   template void launch_combine<T>(int64_t, const T *, T *, hipStream_t);                                        \
-  template void launch_mr2_dots<T>(int64_t, int, const T *, const T *, const T *, double *, double *, int *,     \
+  template void launch_mr2_dots<T>(int64_t, int, const T *, const T *, const T *, double *, double *,           \
                                    hipStream_t);                                                               \
   template void launch_mr2_update<T>(int64_t, int, const double *, const T *, const T *, const T *, const T *,   \
                                      T *, T *, hipStream_t);                                                   \
-  template void launch_norm_init<T>(int64_t, const T *, double *, GmresState *, int *, int, hipStream_t);       \
+  template void launch_norm_init<T>(int64_t, const T *, double *, GmresState *, int, hipStream_t);              \
   template void launch_scale<T>(int64_t, const T *, const double *, T *, hipStream_t);                          \
-  template void launch_arnoldi_dots<T>(int64_t, int, const T *, int64_t, const T *, double *, GmresState *,     \
-                                       int *, hipStream_t);                                                    \
-  template void launch_arnoldi_update<T>(int64_t, int, const T *, int64_t, T *, double *, GmresState *, int *,  \
-                                         int, hipStream_t);                                                    \
   template void launch_gmres_combine<T>(int64_t, const T *, int64_t, const GmresState *, T *, hipStream_t);     \
-  template void launch_dot<T>(int64_t, const T *, const T *, double *, double *, int *, hipStream_t);           \
+  template void launch_dot<T>(int64_t, const T *, const T *, double *, double *, hipStream_t);                  \
   template void launch_axpy_ratio<T>(int64_t, const double *, double, const T *, T *, hipStream_t);             \
   template void launch_fill<T>(int64_t, T, T *, hipStream_t);                                                   \
   template void launch_copy<T>(int64_t, const T *, T *, hipStream_t);

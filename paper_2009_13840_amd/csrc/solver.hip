@@ -95,8 +95,7 @@ struct hho_problem {
          *czs1 = nullptr;
   GmresState *ost = nullptr, *cst = nullptr;
   double *partial = nullptr, *scal = nullptr;
-  int *counter = nullptr, *err = nullptr;
-  int ncounters = 16;
+  int *err = nullptr;
   // host mirrors
   GmresState *h_st = nullptr;  // pinned
   double timings[16] = {0};
@@ -243,8 +242,12 @@ static void plan(hho_problem *P, Arena &A) {
       }
     }
     const int nlast = P->amgh.levels.back().n;
-    D.ainv = A.take<double>((int64_t)nlast * nlast);
-    D.dense_scratch = A.take<double>((int64_t)nlast * nlast);
+    if (nlast <= kAmgCoarsest) {  // dense inverse of the coarsest level; Jacobi sweeps above that size
+      D.ainv = A.take<double>((int64_t)nlast * nlast);
+      D.dense_scratch = A.take<double>((int64_t)nlast * nlast);
+    } else {
+      D.ainv = D.dense_scratch = nullptr;
+    }
     D.partial = A.take<double>(512);
     D.pw = A.take<double>(kAmgPowerSteps + 1);
   }
@@ -260,9 +263,7 @@ static void plan(hho_problem *P, Arena &A) {
   P->cst = A.take<GmresState>(1);
   P->partial = A.take<double>(512 * (kMaxRestartH + 2));
   P->scal = A.take<double>(16);
-  P->counter = A.take<int>(P->ncounters);
   P->err = A.take<int>(4);
-  P->amgd.counter = P->counter + 12;
 }
 
 static DLevel<double> dlev64(const hho_problem *P, int l) {
@@ -443,7 +444,6 @@ static void device_upload(hho_problem *P) {
   h2d((void *)P->tp.zmean, P->zmean.data(), P->zmean.size() * 8);
   h2d(P->rec, P->loc.rec.data(), P->loc.rec.size() * 8);
   h2d(P->roff, P->loc.off.data(), P->loc.off.size() * 8);
-  HIPCHK(hipMemsetAsync(P->counter, 0, P->ncounters * sizeof(int), s));
   HIPCHK(hipMemsetAsync(P->err, 0, 4 * sizeof(int), s));
   // nullspace vector (constant pressure on the level-0 mean modes)
   const LevelInfo &L0 = P->lev[0];
@@ -581,7 +581,7 @@ static void smooth(hho_problem *P, int l) {
     launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
     launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s);
   }
-  launch_mr2_dots<T>(n, m, V.w1, V.w2, V.r, P->partial, P->lev[l].y, P->counter + 0, s);
+  launch_mr2_dots<T>(n, m, V.w1, V.w2, V.r, P->partial, P->lev[l].y, s);
   launch_mr2_update<T>(n, m, P->lev[l].y, V.z1, V.z2, V.w1, V.w2, V.w, V.r, s);
 }
 
@@ -639,7 +639,7 @@ static void coarse_solve(hho_problem *P) {
   const int R = P->opt.coarse_restart;
   GmresState *st = P->cst;
   launch_fill<double>(n, 0.0, V.w, s);
-  launch_norm_init<double>(n, V.b, P->partial, st, P->counter + 1, 1, s);
+  launch_norm_init<double>(n, V.b, P->partial, st, 1, s);
   launch_scale<double>(n, V.b, &st->inv_hnext, P->cV, s);
   read_state(P, st);
   int its = 0;
@@ -656,9 +656,9 @@ static void coarse_solve(hho_problem *P) {
         launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
         launch_spmv<double>(P->tp, D, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
       }
-      launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 2, s);
-      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 3, 1, s);
-      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, P->counter + 4, 2, s);
+      // coarse GMRES: classical Gram-Schmidt once (its target is a 1e-3 reduction)
+      launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
+      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, 2, 0, s);
       launch_scale<double>(n, P->cw, &st->inv_hnext, P->cV + (int64_t)(j + 1) * n, s);
       if ((j + 1) % chunk == 0 || j + 1 == jmax) {
         read_state(P, st);
@@ -672,7 +672,7 @@ static void coarse_solve(hho_problem *P) {
     if (P->h_st->res <= P->h_st->rtol * P->h_st->bnorm || its >= P->opt.coarse_max_it) break;
     // restart from the true residual
     launch_residual<double>(P->tp, D, V.b, V.w, P->cr, s);
-    launch_norm_init<double>(n, P->cr, P->partial, st, P->counter + 1, 0, s);
+    launch_norm_init<double>(n, P->cr, P->partial, st, 0, s);
     launch_scale<double>(n, P->cr, &st->inv_hnext, P->cV, s);
     read_state(P, st);
   }
@@ -715,13 +715,13 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
   // b <- b - (b.z / z.z) z  (consistent right-hand side when the pressure is defined up to a constant)
   launch_copy<double>(n, P->rhs, P->ob, s);
   if (P->border) {
-    launch_dot<double>(n, P->ob, P->zvec, P->partial, P->scal + 0, P->counter + 5, s);
-    launch_dot<double>(n, P->zvec, P->zvec, P->partial, P->scal + 1, P->counter + 5, s);
+    launch_dot<double>(n, P->ob, P->zvec, P->partial, P->scal + 0, s);
+    launch_dot<double>(n, P->zvec, P->zvec, P->partial, P->scal + 1, s);
     launch_axpy_ratio<double>(n, P->scal, -1.0, P->zvec, P->ob, s);
   }
   set_rtol(P, st, P->opt.rtol);
   launch_fill<double>(n, 0.0, P->ox, s);
-  launch_norm_init<double>(n, P->ob, P->partial, st, P->counter + 6, 1, s);
+  launch_norm_init<double>(n, P->ob, P->partial, st, 1, s);
   launch_scale<double>(n, P->ob, &st->inv_hnext, P->oV, s);
   read_state(P, st);
   const double bnorm = P->h_st->bnorm;
@@ -743,9 +743,9 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
       HIPCHK(hipEventRecord(vb, s));
       ++nvc;
       launch_spmv<double>(P->tp, D, zj, nullptr, nullptr, P->ow, s);
-      launch_arnoldi_dots<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 7, s);
-      launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 8, 1, s);
-      launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, P->counter + 9, 2, s);
+      launch_arnoldi_dots<double>(n, j, P->oV, n, P->ow, P->partial, st, s);
+      launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, 1, 1, s);
+      launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, 2, 1, s);
       launch_scale<double>(n, P->ow, &st->inv_hnext, P->oV + (int64_t)(j + 1) * n, s);
       read_state(P, st);
       {
@@ -765,7 +765,7 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
     launch_gmres_combine<double>(n, P->oZ, n, st, P->ox, s);
     // true residual
     launch_residual<double>(P->tp, D, P->ob, P->ox, P->or_, s);
-    launch_norm_init<double>(n, P->or_, P->partial, st, P->counter + 6, 0, s);
+    launch_norm_init<double>(n, P->or_, P->partial, st, 0, s);
     launch_scale<double>(n, P->or_, &st->inv_hnext, P->oV, s);
     read_state(P, st);
     rel = P->h_st->beta / bnorm;
@@ -774,8 +774,8 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
   }
   // zero-mean pressure
   if (P->border) {
-    launch_dot<double>(n, P->ox, P->zvec, P->partial, P->scal + 0, P->counter + 5, s);
-    launch_dot<double>(n, P->zvec, P->zvec, P->partial, P->scal + 1, P->counter + 5, s);
+    launch_dot<double>(n, P->ox, P->zvec, P->partial, P->scal + 0, s);
+    launch_dot<double>(n, P->zvec, P->zvec, P->partial, P->scal + 1, s);
     launch_axpy_ratio<double>(n, P->scal, -1.0, P->zvec, P->ox, s);
   }
   if (x_out) launch_copy<double>(n, P->ox, x_out, s);

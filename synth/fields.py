@@ -28,10 +28,25 @@ class TrigSeries:
 
     def __call__(self, x: np.ndarray) -> np.ndarray:
         x = np.atleast_2d(x)
-        ax = np.pi * x[:, None, :] * self.alphas[None, :, :]          # [n, na, d]
-        c = np.prod(np.cos(ax), axis=2)
-        s = np.prod(np.sin(ax), axis=2)
-        return c @ self.a.T + s @ self.b.T
+        n, d = x.shape
+        deg = int(self.alphas.max())
+        m = deg + 1
+        out = np.empty((n, self.a.shape[0]))
+        freq = np.arange(m, dtype=np.float64)
+        # alphas enumerate the full tensor grid {0..deg}^d with alpha_0 slowest, so the
+        # coefficients reshape to [out, m, ..., m] and the sum contracts one axis at a time
+        A = self.a.reshape((-1,) + (m,) * d)
+        B = self.b.reshape((-1,) + (m,) * d)
+        for s0 in range(0, n, 1 << 16):              # bounded temporaries
+            ang = (np.pi * x[s0:s0 + (1 << 16)])[:, :, None] * freq  # [p, d, m]
+            ct, st = np.cos(ang), np.sin(ang)
+            rc = np.einsum("pk,o...k->po...", ct[:, d - 1], A)
+            rs = np.einsum("pk,o...k->po...", st[:, d - 1], B)
+            for j in range(d - 2, -1, -1):
+                rc = np.einsum("pk,po...k->po...", ct[:, j], rc)
+                rs = np.einsum("pk,po...k->po...", st[:, j], rs)
+            out[s0:s0 + ang.shape[0]] = rc + rs
+        return out
 
 
 def trig_series(dim: int, seed: int, deg: int = 3) -> TrigSeries:

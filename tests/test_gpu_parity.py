@@ -114,6 +114,9 @@ AMG_CASES = [
     ("vor120_k2_v", lambda: voronoi_lloyd(120, 7), 2, "v"),
     ("vor120_k2_vp", lambda: voronoi_lloyd(120, 7), 2, "vp"),
     ("hex4_k1_v", lambda: cartesian_hexes(4), 1, "v"),
+    # 3D: coarsening stops before a nearly dense level; the coarsest AMG level
+    # (1008 unknowns) gets Jacobi sweeps instead of a dense inverse
+    ("hex12_k0_v", lambda: cartesian_hexes(12), 0, "v"),
 ]
 
 
