@@ -121,6 +121,7 @@ typedef struct {
   int32_t coarse_max_it;  /* coarse GMRES iterations (300) */
   int32_t quad_extra;  /* quadrature exact to degree 2k+2+quad_extra (6) */
   int32_t coarse_amg_sweeps; /* damped-Jacobi sweeps before/after the AMG coarse correction (2; 1 or 2) */
+  int32_t learned;     /* 1: reserve the learned fine-level smoother (hho_learned_*); 0 (default): no */
 } hho_options;
 
 /* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the
@@ -236,6 +237,59 @@ int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_m
  * [4] coarse setup, [5] solve, [6] V-cycle total, [7] V-cycle count,
  * [8] coarse iterations total.  n is the capacity of t. */
 int hho_get_timings(const hho_problem *p, double *t, int n);
+
+/* ---- learned fine-level smoother (not in the paper) ----
+ * Needs a problem created with options.learned = 1 and a bound workspace.
+ * Per face F of level 0 a network maps a window of the residual r to a
+ * correction of F's d*n_F velocity unknowns:
+ *   window: for the cells T_0 < T_1 of F (T_1 absent on the boundary), the
+ *     residual blocks of T_s's faces in its face order, zero padded to Fm (the
+ *     largest card(F_T) of the mesh), then T_s's pressure residual; then one-hots
+ *     of F's position in T_0's and T_1's face lists:
+ *     n_in = 2 (Fm d n_F + n_P) + 2 Fm entries;
+ *   scale s_F = root mean square of the residual part (over 2 (Fm d n_F + n_P)
+ *     entries), which is divided by s_F;
+ *   h = relu(W1 x + b1) (64 units), y = W2 h + b2 (n_out = d n_F), correction s_F y.
+ * Parameters are FP32, flat: [W1 (64 x n_in, row-major) | b1 | W2 (n_out x 64) | b2].
+ * When enabled, every level-0 smoothing step minimises the residual over the
+ * Schwarz directions plus this correction, so its residual never exceeds the
+ * plain step's: the plain smoother is both the fallback and the yardstick. */
+
+/* Sizes of the network: inputs, outputs, hidden units and parameter count. */
+int hho_learned_dims(const hho_problem *p, int *n_in, int *n_out, int *hidden, int64_t *n_params);
+
+/* Copy parameters in (host, exactly n_params floats); resets the Adam moments. */
+int hho_learned_set_params(hho_problem *p, const float *params, int64_t n);
+
+/* Copy the current parameters out (host, exactly n_params floats). */
+int hho_learned_get_params(const hho_problem *p, float *params, int64_t n);
+
+/* Use (on = 1) or stop using (0) the learned direction in level-0 smoothing. */
+int hho_learned_enable(hho_problem *p, int on);
+
+/* z = correction of every face for the level-0 residual r (device, FP64 in and
+ * out, network in FP32); cell entries of z are 0.  Needs hho_setup. */
+int hho_learned_apply(hho_problem *p, const double *r_dev, double *z_dev);
+
+/* Training pairs from the plain V-cycle: with b = S_0 x_true and x = 0, for
+ * each of `cycles` iterations the windows of r = b - S_0 x and the targets
+ * (x_true - x)_F / s_F of every face are written (rows cycle*n_faces + F of
+ * X [cap x n_in] and T [cap x n_out], device FP32), then x += MG_V(r).
+ * *n_out = cycles * n_faces; HHO_E_CAPACITY if cap is smaller. */
+int hho_learned_collect(hho_problem *p, const double *x_true_dev, int cycles, float *X_dev, float *T_dev,
+                        int64_t cap, int64_t *n_out);
+
+/* Loss 1/(2n) sum_i |y(X_i) - T_i|^2 and its gradient (host, n_params floats,
+ * same layout as the parameters) over the n rows of X, T (device, 1 <= n <= 4096). */
+int hho_learned_grad(hho_problem *p, const float *X_dev, const float *T_dev, int64_t n, float *grad,
+                     double *loss);
+
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
+ * batches of `batch` rows (<= 4096) drawn from the n rows of X, T with
+ * SplitMix64 of (seed, step, i); loss_hist (host, may be NULL) receives the
+ * batch loss of every step. */
+int hho_learned_train(hho_problem *p, const float *X_dev, const float *T_dev, int64_t n, int steps, int batch,
+                      float lr, uint64_t seed, float *loss_hist);
 
 #ifdef __cplusplus
 }

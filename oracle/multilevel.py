@@ -64,6 +64,7 @@ class Hierarchy:
     nface_dofs: list = field(default_factory=list)
     dim: int = 2
     amg_nu: int = 2
+    learned: object = None  # optional r -> correction on level 0 (oracle.mlp.apply), see smooth()
     _lu: object = None
     _amg: object = None
 
@@ -102,17 +103,33 @@ class Hierarchy:
         self.coarse_its.append(its)
         return x
 
+    def smooth(self, l, b, w):
+        """One smoothing step: right-preconditioned GMRES(smooth_its); on level 0
+        with a learned correction N, the residual is minimised over
+        span{M r, M A M r, N(r)} instead (not in the paper)."""
+        S = self.S[l]
+        A = lambda v: S @ v  # noqa: E731
+        r = b - S @ w
+        if l == 0 and self.learned is not None:
+            from .mlp import mr_step
+            M = self.prec[l]
+            dirs = [M(r)]
+            if self.smooth_its == 2:
+                dirs.append(M(S @ dirs[0]))
+            dirs.append(self.learned(r))
+            return mr_step(A, dirs, w, r)
+        return gmres_steps(A, self.prec[l], w, r, self.smooth_its)
+
     def vcycle(self, l, b, w=None):
         """MG_V(l, b, w) of the algorithm in Section 3.3."""
         S = self.S[l]
-        A = lambda v: S @ v  # noqa: E731
         w = np.zeros_like(b) if w is None else w
-        w = gmres_steps(A, self.prec[l], w, b - S @ w, self.smooth_its)     # pre-smoothing
+        w = self.smooth(l, b, w)                                           # pre-smoothing
         dc = self.restrict(l, b - S @ w)                                   # restricted defect
         if l + 1 == self.L:
             c = self.coarse_solve(dc)
         else:
             c = self.vcycle(l + 1, dc, None)
         w = w + self.prolong(l, c)                                         # coarse correction
-        w = gmres_steps(A, self.prec[l], w, b - S @ w, self.smooth_its)     # post-smoothing
+        w = self.smooth(l, b, w)                                           # post-smoothing
         return w

@@ -26,7 +26,9 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
            "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_get_rhs", "hho_get_condensed_cell",
            "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
-           "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy"]
+           "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
+           "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
+           "hho_learned_collect", "hho_learned_grad", "hho_learned_train"]
 
 
 class HHOError(RuntimeError):
@@ -46,7 +48,7 @@ class Options(C.Structure):
     _fields_ = [("eta", C.c_double), ("rtol", C.c_double), ("max_it", C.c_int32), ("restart", C.c_int32),
                 ("smooth_its", C.c_int32), ("precision", C.c_int32), ("coarse_mode", C.c_int32),
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_max_it", C.c_int32),
-                ("quad_extra", C.c_int32), ("coarse_amg_sweeps", C.c_int32)]
+                ("quad_extra", C.c_int32), ("coarse_amg_sweeps", C.c_int32), ("learned", C.c_int32)]
 
 
 FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -92,6 +94,14 @@ def load():
         "hho_time_kernel": ([P, I32, I32, I32, D], I32),
         "hho_coarse_prec_apply": ([P, P, P], I32),
         "hho_debug_copy": ([P, C.c_char_p, I32, D, I64, C.POINTER(I64)], I32),
+        "hho_learned_dims": ([P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(I64)], I32),
+        "hho_learned_set_params": ([P, C.POINTER(C.c_float), I64], I32),
+        "hho_learned_get_params": ([P, C.POINTER(C.c_float), I64], I32),
+        "hho_learned_enable": ([P, I32], I32),
+        "hho_learned_apply": ([P, P, P], I32),
+        "hho_learned_collect": ([P, P, I32, P, P, I64, C.POINTER(I64)], I32),
+        "hho_learned_grad": ([P, P, P, I64, C.POINTER(C.c_float), D], I32),
+        "hho_learned_train": ([P, P, P, I64, I32, I32, C.c_float, C.c_uint64, C.POINTER(C.c_float)], I32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -193,6 +203,7 @@ class Problem:
         self.h = h
         self.ws = None
         self.nlev = len(degrees) if degrees is not None else k + 1
+        self.nfaces = len(mesh._keep[1]) - 1
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -307,6 +318,53 @@ class Problem:
         x = self._vec(self.level_size(0))
         _check(load().hho_vcycle_apply(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
         return x
+
+    # ---- learned fine-level smoother (problem created with learned=1)
+    def learned_dims(self):
+        a, b, c, n = C.c_int(), C.c_int(), C.c_int(), C.c_int64()
+        _check(load().hho_learned_dims(self.h, C.byref(a), C.byref(b), C.byref(c), C.byref(n)))
+        return dict(n_in=a.value, n_out=b.value, hidden=c.value, n_params=n.value)
+
+    def learned_set_params(self, prm):
+        prm = np.ascontiguousarray(prm, dtype=np.float32)
+        _check(load().hho_learned_set_params(self.h, prm.ctypes.data_as(C.POINTER(C.c_float)), prm.size))
+
+    def learned_get_params(self):
+        out = np.zeros(self.learned_dims()["n_params"], dtype=np.float32)
+        _check(load().hho_learned_get_params(self.h, out.ctypes.data_as(C.POINTER(C.c_float)), out.size))
+        return out
+
+    def learned_enable(self, on=True):
+        _check(load().hho_learned_enable(self.h, 1 if on else 0))
+
+    def learned_apply(self, r):
+        z = self._vec(self.level_size(0))
+        _check(load().hho_learned_apply(self.h, C.c_void_p(r.data_ptr()), C.c_void_p(z.data_ptr())))
+        return z
+
+    def learned_collect(self, x_true, cycles):
+        import torch
+        dm = self.learned_dims()
+        cap = cycles * self.nfaces
+        X = torch.zeros((cap, dm["n_in"]), dtype=torch.float32, device=self.device)
+        T = torch.zeros((cap, dm["n_out"]), dtype=torch.float32, device=self.device)
+        n = C.c_int64()
+        _check(load().hho_learned_collect(self.h, C.c_void_p(x_true.data_ptr()), cycles, C.c_void_p(X.data_ptr()),
+                                          C.c_void_p(T.data_ptr()), cap, C.byref(n)))
+        return X[:n.value], T[:n.value]
+
+    def learned_grad(self, X, T):
+        g = np.zeros(self.learned_dims()["n_params"], dtype=np.float32)
+        loss = C.c_double()
+        _check(load().hho_learned_grad(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), X.shape[0],
+                                       g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
+        return loss.value, g
+
+    def learned_train(self, X, T, steps, batch=1024, lr=1e-3, seed=0):
+        hist = np.zeros(steps, dtype=np.float32)
+        _check(load().hho_learned_train(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), X.shape[0],
+                                        steps, batch, lr, seed, hist.ctypes.data_as(C.POINTER(C.c_float))))
+        return hist
 
     def timings(self):
         t = np.zeros(16)

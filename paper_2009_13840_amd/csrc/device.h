@@ -134,6 +134,38 @@ void launch_fill(int64_t n, T v, T *x, hipStream_t s);
 template <typename T>
 void launch_copy(int64_t n, const T *x, T *y, hipStream_t s);
 
+// ---- learned smoother (k_mlp.hip)
+constexpr int kMlpHidden = 64;
+constexpr int kMlpMaxBatch = 4096;
+constexpr int kMlpMaxSteps = 100000;
+struct MlpDims {
+  int d, p, t, Fm, dp, n_res, n_in, n_out;
+  int64_t nface;  // offset of the cell part of a level-0 vector
+};
+int64_t mlp_param_count(const MlpDims &md);
+// window of every face of r -> X [nf][n_in] (FP32, scaled), sc [nf] (scales)
+template <typename T>
+void launch_mlp_windows(const DTopo &tp, const MlpDims &md, const T *r, float *X, float *sc, hipStream_t s);
+// targets (xt - x)_F / s_F -> Tg [nf][dp]
+void launch_mlp_targets(int nf, int dp, const double *xt, const double *x, const float *sc, float *Tg, hipStream_t s);
+// Z (pre-activations, optional) and Y of the rows of X (rows == null: rows 0..n-1)
+void launch_mlp_forward(int n, int n_in, int n_out, const float *X, const int *rows, const float *prm, float *Z,
+                        float *Y, hipStream_t s);
+// z = s_F y_F on face blocks, 0 on cells
+template <typename T>
+void launch_mlp_scatter(int64_t nface, int64_t N, int dp, const float *Y, const float *sc, T *z, hipStream_t s);
+// gradient g of 1/(2B) sum |Y - T|^2; returns the number of loss partials written
+int launch_mlp_backward(int B, int n_in, int n_out, const float *X, const int *rows, const float *Tg, const float *prm,
+                        const float *Z, const float *Y, float *dY, float *dZ, float *g, double *partial,
+                        hipStream_t s);
+void launch_mlp_adam(int64_t n, float *prm, const float *g, float *m, float *v, float lr, int step, hipStream_t s);
+void launch_mlp_rows(int B, int64_t n, uint64_t seed, int step, int *rows, hipStream_t s);
+// minimal residual over {z1, z2 (if m == 2), z3}: x += Z y, r -= W y
+template <typename T>
+void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T *w1, const T *w2, const T *w3, T *x,
+                T *r, double *partial, double *y, hipStream_t s);
+void launch_sum_finish(int G, const double *partial, double *out, hipStream_t s);
+
 // device-resident GMRES scalars
 struct GmresState {
   double H[(kMaxRestartH + 1) * kMaxRestartH];

@@ -1,0 +1,374 @@
+// Learned fine-level smoother (not in the paper): a two-layer network per face
+// block maps a window of the residual to a correction of the face's velocity
+// unknowns; it enters the smoothing step as one more search direction of the
+// minimal-residual update, next to the Schwarz directions.
+//
+// Window of face F (n_in entries): for each side s of F (cells T_0 < T_1) the
+// residual blocks of T_s's faces in the cell's face order, zero padded to Fm
+// faces, then T_s's pressure residual; then a one-hot of F's position in T_0's
+// and in T_1's face list.  The residual part is divided by its root mean square
+// s_F (over 2 (Fm d p + t) entries) and the output is multiplied by s_F.
+// Network: h = relu(W1 x + b1) (64 units), y = W2 h + b2 (d p outputs).
+// Parameters are FP32 [W1 | b1 | W2 | b2]; all products accumulate in FP32.
+#include <algorithm>
+
+#include "dev_common.h"
+#include "device.h"
+
+namespace hho {
+namespace {
+
+constexpr int kRows = 32;   // samples per forward tile
+constexpr int kChunk = 64;  // K chunk of the first layer
+
+// one wavefront per face: gathers the window, its scale, and writes the scaled row
+template <typename T>
+__global__ void __launch_bounds__(kWave) k_mlp_windows(DTopo tp, MlpDims md, const T *__restrict__ r,
+                                                        float *__restrict__ X, float *__restrict__ sc) {
+  const int f = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int side = md.Fm * md.dp + md.t;
+  int cell[2], nfc[2], pos[2];
+  for (int s = 0; s < 2; ++s) {
+    cell[s] = tp.fcell[2 * f + s];
+    nfc[s] = cell[s] >= 0 ? tp.cptr[cell[s] + 1] - tp.cptr[cell[s]] : 0;
+    pos[s] = cell[s] >= 0 ? tp.floc[2 * f + s] : -1;
+  }
+  auto value = [&](int k) -> double {
+    const int s = k / side, q = k % side;
+    const int c = cell[s];
+    if (c < 0) return 0.0;
+    if (q < md.Fm * md.dp) {
+      const int i = q / md.dp, j = q % md.dp;
+      if (i >= nfc[s]) return 0.0;
+      const int g = tp.cface[tp.cptr[c] + i];
+      return (double)r[(int64_t)g * md.dp + j];
+    }
+    return (double)r[md.nface + (int64_t)c * md.t + (q - md.Fm * md.dp)];
+  };
+  double ss = 0;
+  for (int k = lane; k < md.n_res; k += kWave) {
+    const double v = value(k);
+    ss += v * v;
+  }
+  ss = wave_sum(ss);
+  ss = __shfl(ss, 0, kWave);
+  const double s = sqrt(ss / md.n_res);
+  const double inv = s > 0 ? 1.0 / s : 0.0;
+  float *row = X + (int64_t)f * md.n_in;
+  for (int k = lane; k < md.n_res; k += kWave) row[k] = (float)(value(k) * inv);
+  for (int k = md.n_res + lane; k < md.n_in; k += kWave) {
+    const int q = k - md.n_res, s_ = q / md.Fm, i = q % md.Fm;
+    row[k] = (pos[s_] == i) ? 1.0f : 0.0f;
+  }
+  if (lane == 0) sc[f] = (float)s;
+}
+
+// targets e_F / s_F (0 when s_F = 0)
+__global__ void k_mlp_targets(int nf, int dp, const double *xt, const double *x, const float *sc, float *Tg) {
+  const int64_t n = (int64_t)nf * dp;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float s = sc[i / dp];
+    Tg[i] = s > 0 ? (float)((xt[i] - x[i]) / (double)s) : 0.0f;
+  }
+}
+
+// Z = X W1^T + b1, H = relu(Z), Y = H W2^T + b2 for kRows rows per block.
+// rows (optional) maps the tile's row i to the row of X it reads.
+__global__ void __launch_bounds__(256) k_mlp_forward(int n, int n_in, int n_out, const float *__restrict__ X,
+                                                      const int *__restrict__ rows, const float *__restrict__ prm,
+                                                      float *__restrict__ Zout, float *__restrict__ Y) {
+  __shared__ float Xs[kRows][kChunk + 1];
+  __shared__ float Ws[kMlpHidden][kChunk + 1];
+  __shared__ float Hs[kRows][kMlpHidden + 1];
+  const float *W1 = prm, *b1 = W1 + (int64_t)kMlpHidden * n_in, *W2 = b1 + kMlpHidden, *b2 = W2 + n_out * kMlpHidden;
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;  // hidden 4tx..4tx+3, rows 2ty, 2ty+1
+  const int r0 = blockIdx.x * kRows;
+  float acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  for (int k0 = 0; k0 < n_in; k0 += kChunk) {
+    for (int idx = tid; idx < kRows * kChunk; idx += blockDim.x) {
+      const int i = idx / kChunk, k = idx % kChunk;
+      const int gi = r0 + i;
+      float v = 0;
+      if (gi < n && k0 + k < n_in) {
+        const int64_t src = rows ? rows[gi] : gi;
+        v = X[src * n_in + k0 + k];
+      }
+      Xs[i][k] = v;
+    }
+    for (int idx = tid; idx < kMlpHidden * kChunk; idx += blockDim.x) {
+      const int h = idx / kChunk, k = idx % kChunk;
+      Ws[h][k] = (k0 + k < n_in) ? W1[(int64_t)h * n_in + k0 + k] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll 8
+    for (int k = 0; k < kChunk; ++k) {
+      const float a0 = Xs[2 * ty][k], a1 = Xs[2 * ty + 1][k];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const float w = Ws[4 * tx + q][k];
+        acc[0][q] += a0 * w;
+        acc[1][q] += a1 * w;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = 2 * ty + a, h = 4 * tx + q;
+      const float z = acc[a][q] + b1[h];
+      Hs[i][h] = z > 0 ? z : 0.0f;
+      if (Zout && r0 + i < n) Zout[(int64_t)(r0 + i) * kMlpHidden + h] = z;
+    }
+  __syncthreads();
+  for (int idx = tid; idx < kRows * n_out; idx += blockDim.x) {
+    const int i = idx / n_out, o = idx % n_out;
+    if (r0 + i >= n) continue;
+    float y = b2[o];
+    const float *w = W2 + o * kMlpHidden;
+#pragma unroll 8
+    for (int h = 0; h < kMlpHidden; ++h) y += Hs[i][h] * w[h];
+    Y[(int64_t)(r0 + i) * n_out + o] = y;
+  }
+}
+
+// z (level 0 layout) = s_F * y_F on faces, 0 on cells
+template <typename T>
+__global__ void k_mlp_scatter(int64_t nface, int64_t N, int dp, const float *Y, const float *sc, T *z) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
+    z[i] = i < nface ? (T)(sc[i / dp] * Y[i]) : (T)0;
+}
+
+// dY = (Y - T[rows]) / B and per-block partial sums of |Y - T|^2
+__global__ void __launch_bounds__(kBlock) k_mlp_dy(int B, int n_out, const float *Y, const float *Tg,
+                                                    const int *rows, float *dY, double *partial) {
+  __shared__ double red[16];
+  double acc = 0;
+  const int64_t n = (int64_t)B * n_out;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / n_out, o = i % n_out;
+    const int64_t src = rows ? rows[b] : b;
+    const float dv = Y[i] - Tg[src * n_out + o];
+    dY[i] = dv / (float)B;
+    acc += (double)dv * dv;
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// dZ = (dY W2) .* (Z > 0)
+__global__ void k_mlp_dz(int B, int n_out, const float *dY, const float *Z, const float *prm, int n_in, float *dZ) {
+  const float *W2 = prm + (int64_t)kMlpHidden * n_in + kMlpHidden;
+  const int64_t n = (int64_t)B * kMlpHidden;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = i / kMlpHidden, h = i % kMlpHidden;
+    float s = 0;
+    for (int o = 0; o < n_out; ++o) s += dY[b * n_out + o] * W2[o * kMlpHidden + h];
+    dZ[i] = Z[i] > 0 ? s : 0.0f;
+  }
+}
+
+// gradient of every parameter: one thread per parameter, sum over the batch in order
+__global__ void k_mlp_wgrad(int B, int n_in, int n_out, const float *X, const int *rows, const float *Z,
+                            const float *dZ, const float *dY, float *g) {
+  const int64_t nW1 = (int64_t)kMlpHidden * n_in, nb1 = kMlpHidden, nW2 = (int64_t)n_out * kMlpHidden;
+  const int64_t total = nW1 + nb1 + nW2 + n_out;
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < total; p += (int64_t)gridDim.x * blockDim.x) {
+    float s = 0;
+    if (p < nW1) {
+      const int h = (int)(p / n_in), k = (int)(p % n_in);
+      for (int b = 0; b < B; ++b) {
+        const int64_t src = rows ? rows[b] : b;
+        s += dZ[(int64_t)b * kMlpHidden + h] * X[src * n_in + k];
+      }
+    } else if (p < nW1 + nb1) {
+      const int h = (int)(p - nW1);
+      for (int b = 0; b < B; ++b) s += dZ[(int64_t)b * kMlpHidden + h];
+    } else if (p < nW1 + nb1 + nW2) {
+      const int64_t q = p - nW1 - nb1;
+      const int o = (int)(q / kMlpHidden), h = (int)(q % kMlpHidden);
+      for (int b = 0; b < B; ++b) {
+        const float z = Z[(int64_t)b * kMlpHidden + h];
+        s += dY[(int64_t)b * n_out + o] * (z > 0 ? z : 0.0f);
+      }
+    } else {
+      const int o = (int)(p - nW1 - nb1 - nW2);
+      for (int b = 0; b < B; ++b) s += dY[(int64_t)b * n_out + o];
+    }
+    g[p] = s;
+  }
+}
+
+// Adam (Kingma & Ba): bias-corrected first and second moments
+__global__ void k_mlp_adam(int64_t n, float *prm, const float *g, float *m, float *v, float lr, float c1, float c2) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    prm[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// batch rows from SplitMix64 (Steele, Lea & Flood 2014) of (seed, step, i)
+__device__ inline uint64_t splitmix64(uint64_t x) {
+  x += 0x9E3779B97F4A7C15ull;
+  x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+  x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+  return x ^ (x >> 31);
+}
+__global__ void k_mlp_rows(int B, int64_t n, uint64_t seed, int step, int *rows) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < B; i += gridDim.x * blockDim.x)
+    rows[i] = (int)(splitmix64(seed ^ splitmix64(((uint64_t)step << 32) | (uint64_t)i)) % (uint64_t)n);
+}
+
+// ---- three-direction minimal residual (the smoothing step with the learned direction)
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_mr3_dots(int64_t n, const T *w1, const T *w2, const T *w3, const T *r,
+                                                      double *partial) {
+  __shared__ double red[16];
+  double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};  // a11 a12 a13 a22 a23 a33 g1 g2 g3
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const double x1 = w1[i], x2 = w2 ? (double)w2[i] : 0.0, x3 = w3[i], rr = r[i];
+    v[0] += x1 * x1;
+    v[1] += x1 * x2;
+    v[2] += x1 * x3;
+    v[3] += x2 * x2;
+    v[4] += x2 * x3;
+    v[5] += x3 * x3;
+    v[6] += x1 * rr;
+    v[7] += x2 * rr;
+    v[8] += x3 * rr;
+  }
+  for (int k = 0; k < 9; ++k) {
+    const double s = block_sum(v[k], red);
+    if (threadIdx.x == 0) partial[k * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// Solves the 3x3 (or 2x2 without the second Schwarz direction) normal equations
+// by Cholesky; a direction whose pivot is not clearly positive is dropped.
+__global__ void __launch_bounds__(kBlock) k_mr3_finish(int G, int m, const double *partial, double *y) {
+  __shared__ double S[9];
+  reduce_partials(partial, G, 9, S);
+  if (threadIdx.x != 0) return;
+  double A[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
+  double g[3] = {S[6], S[7], S[8]};
+  bool use[3] = {true, m == 2, true};
+  double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = 0; j < 3; ++j) {
+    if (!use[j]) continue;
+    double dj = A[j][j];
+    for (int k = 0; k < j; ++k)
+      if (use[k]) dj -= L[j][k] * L[j][k];
+    if (!(dj > 1e-12 * A[j][j]) || !(A[j][j] > 0)) {
+      use[j] = false;
+      continue;
+    }
+    L[j][j] = sqrt(dj);
+    for (int i = j + 1; i < 3; ++i) {
+      double s = A[i][j];
+      for (int k = 0; k < j; ++k)
+        if (use[k]) s -= L[i][k] * L[j][k];
+      L[i][j] = s / L[j][j];
+    }
+  }
+  double z[3] = {0, 0, 0}, x[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i) {
+    if (!use[i]) continue;
+    double s = g[i];
+    for (int k = 0; k < i; ++k)
+      if (use[k]) s -= L[i][k] * z[k];
+    z[i] = s / L[i][i];
+  }
+  for (int i = 2; i >= 0; --i) {
+    if (!use[i]) continue;
+    double s = z[i];
+    for (int k = i + 1; k < 3; ++k)
+      if (use[k]) s -= L[k][i] * x[k];
+    x[i] = s / L[i][i];
+  }
+  for (int i = 0; i < 3; ++i) y[i] = isfinite(x[i]) ? x[i] : 0.0;
+}
+
+template <typename T>
+__global__ void k_mr3_update(int64_t n, const double *y, const T *z1, const T *z2, const T *z3, const T *w1,
+                             const T *w2, const T *w3, T *x, T *r) {
+  const T y1 = (T)y[0], y2 = (T)y[1], y3 = (T)y[2];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const T a2 = z2 ? z2[i] : (T)0, b2 = w2 ? w2[i] : (T)0;
+    x[i] += y1 * z1[i] + y2 * a2 + y3 * z3[i];
+    r[i] -= y1 * w1[i] + y2 * b2 + y3 * w3[i];
+  }
+}
+
+inline int blocks_for(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + kBlock - 1) / kBlock, 8192)); }
+
+}  // namespace
+
+int64_t mlp_param_count(const MlpDims &md) {
+  return (int64_t)kMlpHidden * md.n_in + kMlpHidden + (int64_t)md.n_out * kMlpHidden + md.n_out;
+}
+
+template <typename T>
+void launch_mlp_windows(const DTopo &tp, const MlpDims &md, const T *r, float *X, float *sc, hipStream_t s) {
+  if (tp.nf == 0) return;
+  hipLaunchKernelGGL((k_mlp_windows<T>), dim3(tp.nf), dim3(kWave), 0, s, tp, md, r, X, sc);
+}
+void launch_mlp_targets(int nf, int dp, const double *xt, const double *x, const float *sc, float *Tg, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_targets, dim3(blocks_for((int64_t)nf * dp)), dim3(kBlock), 0, s, nf, dp, xt, x, sc, Tg);
+}
+void launch_mlp_forward(int n, int n_in, int n_out, const float *X, const int *rows, const float *prm, float *Z,
+                        float *Y, hipStream_t s) {
+  if (n <= 0) return;
+  hipLaunchKernelGGL(k_mlp_forward, dim3((n + kRows - 1) / kRows), dim3(256), 0, s, n, n_in, n_out, X, rows, prm, Z,
+                     Y);
+}
+template <typename T>
+void launch_mlp_scatter(int64_t nface, int64_t N, int dp, const float *Y, const float *sc, T *z, hipStream_t s) {
+  hipLaunchKernelGGL((k_mlp_scatter<T>), dim3(blocks_for(N)), dim3(kBlock), 0, s, nface, N, dp, Y, sc, z);
+}
+int launch_mlp_backward(int B, int n_in, int n_out, const float *X, const int *rows, const float *Tg, const float *prm,
+                        const float *Z, const float *Y, float *dY, float *dZ, float *g, double *partial,
+                        hipStream_t s) {
+  const int G = std::min(256, blocks_for((int64_t)B * n_out));
+  hipLaunchKernelGGL(k_mlp_dy, dim3(G), dim3(kBlock), 0, s, B, n_out, Y, Tg, rows, dY, partial);
+  hipLaunchKernelGGL(k_mlp_dz, dim3(blocks_for((int64_t)B * kMlpHidden)), dim3(kBlock), 0, s, B, n_out,
+                     (const float *)dY, Z, prm, n_in, dZ);
+  const int64_t np = (int64_t)kMlpHidden * n_in + kMlpHidden + (int64_t)n_out * kMlpHidden + n_out;
+  hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks_for(np)), dim3(kBlock), 0, s, B, n_in, n_out, X, rows, Z,
+                     (const float *)dZ, (const float *)dY, g);
+  return G;
+}
+void launch_mlp_adam(int64_t n, float *prm, const float *g, float *m, float *v, float lr, int step, hipStream_t s) {
+  const float c1 = 1.0f - powf(0.9f, (float)step), c2 = 1.0f - powf(0.999f, (float)step);
+  hipLaunchKernelGGL(k_mlp_adam, dim3(blocks_for(n)), dim3(kBlock), 0, s, n, prm, g, m, v, lr, c1, c2);
+}
+void launch_mlp_rows(int B, int64_t n, uint64_t seed, int step, int *rows, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_rows, dim3(blocks_for(B)), dim3(kBlock), 0, s, B, n, seed, step, rows);
+}
+template <typename T>
+void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T *w1, const T *w2, const T *w3, T *x,
+                T *r, double *partial, double *y, hipStream_t s) {
+  const int G = reduce_blocks(n);
+  hipLaunchKernelGGL((k_mr3_dots<T>), dim3(G), dim3(kBlock), 0, s, n, w1, m == 2 ? w2 : (const T *)nullptr, w3, r,
+                     partial);
+  hipLaunchKernelGGL(k_mr3_finish, dim3(1), dim3(kBlock), 0, s, G, m, (const double *)partial, y);
+  hipLaunchKernelGGL((k_mr3_update<T>), dim3(blocks_for(n)), dim3(kBlock), 0, s, n, (const double *)y, z1,
+                     m == 2 ? z2 : (const T *)nullptr, z3, w1, m == 2 ? w2 : (const T *)nullptr, w3, x, r);
+}
+
+#define HHO_INST(T)                                                                                             \
+  template void launch_mlp_windows<T>(const DTopo &, const MlpDims &, const T *, float *, float *, hipStream_t); \
+  template void launch_mlp_scatter<T>(int64_t, int64_t, int, const float *, const float *, T *, hipStream_t);    \
+  template void launch_mr3<T>(int64_t, int, const T *, const T *, const T *, const T *, const T *, const T *, T *, \
+                              T *, double *, double *, hipStream_t);
+HHO_INST(double)
+HHO_INST(float)
+#undef HHO_INST
+
+}  // namespace hho

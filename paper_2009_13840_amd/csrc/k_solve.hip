@@ -471,6 +471,9 @@ void launch_dot(int64_t n, const T *a, const T *b, double *partial, double *out,
   hipLaunchKernelGGL((k_dot<T>), dim3(G), dim3(kBlock), 0, s, n, a, b, partial);
   hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kBlock), 0, s, G, (const double *)partial, out);
 }
+void launch_sum_finish(int G, const double *partial, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_finish, dim3(1), dim3(kBlock), 0, s, G, partial, out);
+}
 template <typename T>
 void launch_axpy_ratio(int64_t n, const double *alpha, double sign, const T *x, T *y, hipStream_t s) {
   hipLaunchKernelGGL((k_axpy_ratio<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, alpha, sign, x, y);

@@ -43,6 +43,7 @@ template <typename T>
 struct VBufs {  // V-cycle vectors of one level
   T *b = nullptr, *w = nullptr, *r = nullptr, *z1 = nullptr, *z2 = nullptr, *w1 = nullptr, *w2 = nullptr,
     *zs0 = nullptr, *zs1 = nullptr;
+  T *z3 = nullptr, *w3 = nullptr;  // learned direction (level 0 only)
 };
 
 struct LevelInfo {
@@ -110,6 +111,14 @@ struct hho_problem {
   AmgDev amgd;
   std::vector<double> zhost;
   size_t lds_condense = 0, lds_patch = 0;
+  // learned fine-level smoother
+  MlpDims md{};
+  bool learned_on = false, learned_ready = false;
+  int adam_step = 0;
+  float *mlp_prm = nullptr, *mlp_g = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_X = nullptr, *mlp_sc = nullptr,
+        *mlp_Y = nullptr, *mlp_Z = nullptr, *mlp_dZ = nullptr, *mlp_Yb = nullptr, *mlp_dY = nullptr;
+  int *mlp_rows = nullptr;
+  double *mlp_loss = nullptr;
 };
 
 namespace hho {
@@ -157,7 +166,7 @@ static void plan(hho_problem *P, Arena &A) {
     L.sinv = need_smoother ? A.take<double>(nsinv) : nullptr;
     L.xinv = need_smoother ? A.take<double>(nxinv) : nullptr;
     L.sig = need_smoother ? A.take<double>(nc) : nullptr;
-    L.y = A.take<double>(2);
+    L.y = A.take<double>(4);
     if (mixed && l < Lc) {
       L.bsr32 = A.take<float>(nbsr);
       L.cpl32 = A.take<float>(ncpl);
@@ -177,6 +186,10 @@ static void plan(hho_problem *P, Arena &A) {
       V.w2 = A.take<T>(L.N);
       V.zs0 = A.take<T>(L.N);
       V.zs1 = A.take<T>(L.nface);
+      if (P->opt.learned && l == 0) {
+        V.z3 = A.take<T>(L.N);
+        V.w3 = A.take<T>(L.N);
+      }
     };
     if (l == Lc || !mixed)
       vecs(L.v64, 0.0);
@@ -250,6 +263,24 @@ static void plan(hho_problem *P, Arena &A) {
     }
     D.partial = A.take<double>(512);
     D.pw = A.take<double>(kAmgPowerSteps + 1);
+  }
+  // learned fine-level smoother
+  if (P->opt.learned) {
+    const MlpDims &md = P->md;
+    const int64_t np = mlp_param_count(md);
+    P->mlp_prm = A.take<float>(np);
+    P->mlp_g = A.take<float>(np);
+    P->mlp_m = A.take<float>(np);
+    P->mlp_v = A.take<float>(np);
+    P->mlp_X = A.take<float>(nf * (int64_t)md.n_in);
+    P->mlp_sc = A.take<float>(nf);
+    P->mlp_Y = A.take<float>(nf * (int64_t)md.n_out);
+    P->mlp_rows = A.take<int>(kMlpMaxBatch);
+    P->mlp_Z = A.take<float>((int64_t)kMlpMaxBatch * kMlpHidden);
+    P->mlp_dZ = A.take<float>((int64_t)kMlpMaxBatch * kMlpHidden);
+    P->mlp_Yb = A.take<float>((int64_t)kMlpMaxBatch * md.n_out);
+    P->mlp_dY = A.take<float>((int64_t)kMlpMaxBatch * md.n_out);
+    P->mlp_loss = A.take<double>(kMlpMaxSteps);
   }
   // outer FGMRES
   const int R = P->opt.restart;
@@ -575,11 +606,23 @@ static void smooth(hho_problem *P, int l) {
   VBufs<T> &V = LevSel<T>::vb(P, l);
   const int m = P->opt.smooth_its;
   const int64_t n = D.N;
+  const bool learned = l == 0 && P->learned_on;
+  if (learned) {  // learned direction from the residual at the start of the step
+    const MlpDims &md = P->md;
+    launch_mlp_windows<T>(P->tp, md, V.r, P->mlp_X, P->mlp_sc, s);
+    launch_mlp_forward(P->tp.nf, md.n_in, md.n_out, P->mlp_X, nullptr, P->mlp_prm, nullptr, P->mlp_Y, s);
+    launch_mlp_scatter<T>(md.nface, n, md.dp, P->mlp_Y, P->mlp_sc, V.z3, s);
+    launch_spmv<T>(P->tp, D, V.z3, nullptr, nullptr, V.w3, s);
+  }
   launch_precond<T>(P->tp, D, V.r, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
   launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z1, V.w1, s);
   if (m == 2) {
     launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
     launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s);
+  }
+  if (learned) {
+    launch_mr3<T>(n, m, V.z1, V.z2, V.z3, V.w1, V.w2, V.w3, V.w, V.r, P->partial, P->lev[l].y, s);
+    return;
   }
   launch_mr2_dots<T>(n, m, V.w1, V.w2, V.r, P->partial, P->lev[l].y, s);
   launch_mr2_update<T>(n, m, P->lev[l].y, V.z1, V.z2, V.w1, V.w2, V.w, V.r, s);
@@ -834,6 +877,7 @@ void hho_options_default(hho_options *o) {
   o->coarse_max_it = 300;
   o->quad_extra = 6;
   o->coarse_amg_sweeps = 2;
+  o->learned = 0;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -885,12 +929,26 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   P->amg_nu = P->opt.coarse_amg_sweeps;
   if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
+  if (P->opt.learned != 0 && P->opt.learned != 1) hho::fail(HHO_E_INVALID_ARG, "learned must be 0 or 1");
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
   if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol > 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
   const int d = P->d;
   P->eta = P->opt.eta > 0 ? P->opt.eta : 4.0 * (k + 1) * (k + d) / d * mesh->max_faces;
   hho::build_topology(P.get());
   hho::init_levels(P.get());
+  {
+    MlpDims &md = P->md;
+    const LevelInfo &L0 = P->lev[0];
+    md.d = d;
+    md.p = L0.p;
+    md.t = L0.t;
+    md.Fm = mesh->max_faces;
+    md.dp = d * L0.p;
+    md.n_res = 2 * (md.Fm * md.dp + md.t);
+    md.n_in = md.n_res + 2 * md.Fm;
+    md.n_out = md.dp;
+    md.nface = L0.nface;
+  }
   const int nT = hho::dim_poly(d, k), nF = hho::dim_poly(d - 1, k);
   P->lds_condense = hho::condense_lds_bytes(d, cond, nT, nF, mesh->max_faces);
   if (P->lds_condense > 64 * 1024)
@@ -1243,3 +1301,169 @@ int hho_get_timings(const hho_problem *p, double *t, int n) {
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ learned fine-level smoother
+static void need_learned(const hho_problem *p) {
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "learned: NULL problem");
+  if (!p->opt.learned) hho::fail(HHO_E_INVALID_ARG, "learned: create the problem with options.learned = 1");
+  if (!p->bound) hho::fail(HHO_E_INVALID_ARG, "learned: bind a workspace first");
+}
+
+int hho_learned_dims(const hho_problem *p, int *n_in, int *n_out, int *hidden, int64_t *n_params) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "learned_dims: NULL problem");
+  if (n_in) *n_in = p->md.n_in;
+  if (n_out) *n_out = p->md.n_out;
+  if (hidden) *hidden = hho::kMlpHidden;
+  if (n_params) *n_params = hho::mlp_param_count(p->md);
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_set_params(hho_problem *p, const float *prm, int64_t n) {
+  ABI_BEGIN
+  need_learned(p);
+  const int64_t np = hho::mlp_param_count(p->md);
+  if (!prm || n != np) hho::fail(HHO_E_INVALID_ARG, "learned_set_params: need exactly n_params values");
+  HIPCHK(hipMemcpyAsync(p->mlp_prm, prm, np * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  hho::launch_fill<float>(np, 0.0f, p->mlp_m, p->stream);
+  hho::launch_fill<float>(np, 0.0f, p->mlp_v, p->stream);
+  HIPCHK(hipStreamSynchronize(p->stream));
+  p->adam_step = 0;
+  p->learned_ready = true;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_get_params(const hho_problem *p, float *prm, int64_t n) {
+  ABI_BEGIN
+  need_learned(p);
+  const int64_t np = hho::mlp_param_count(p->md);
+  if (!prm || n != np) hho::fail(HHO_E_INVALID_ARG, "learned_get_params: need exactly n_params values");
+  if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_get_params: no parameters set");
+  HIPCHK(hipMemcpyAsync(prm, p->mlp_prm, np * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_enable(hho_problem *p, int on) {
+  ABI_BEGIN
+  need_learned(p);
+  if (on && !p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_enable: set or train parameters first");
+  p->learned_on = on != 0;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_apply(hho_problem *p, const double *r, double *z) {
+  ABI_BEGIN
+  need_learned(p);
+  need_setup(p);
+  if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_apply: no parameters set");
+  if (!r || !z) hho::fail(HHO_E_INVALID_ARG, "learned_apply: NULL");
+  const hho::MlpDims &md = p->md;
+  hipStream_t s = p->stream;
+  hho::launch_mlp_windows<double>(p->tp, md, r, p->mlp_X, p->mlp_sc, s);
+  hho::launch_mlp_forward(p->tp.nf, md.n_in, md.n_out, p->mlp_X, nullptr, p->mlp_prm, nullptr, p->mlp_Y, s);
+  hho::launch_mlp_scatter<double>(md.nface, p->lev[0].N, md.dp, p->mlp_Y, p->mlp_sc, z, s);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_collect(hho_problem *p, const double *x_true, int cycles, float *X, float *Tg, int64_t cap,
+                        int64_t *n_out) {
+  ABI_BEGIN
+  need_learned(p);
+  need_setup(p);
+  if (!x_true || !X || !Tg || !n_out || cycles < 1) hho::fail(HHO_E_INVALID_ARG, "learned_collect: bad argument");
+  const hho::MlpDims &md = p->md;
+  const int64_t nf = p->tp.nf, need = (int64_t)cycles * nf;
+  if (cap < need) {
+    *n_out = need;
+    hho::set_error("learned_collect: capacity below cycles * n_faces samples");
+    return HHO_E_CAPACITY;
+  }
+  hipStream_t s = p->stream;
+  const hho::DLevel<double> D = hho::dlev64(p, 0);
+  const int64_t n = D.N;
+  const bool was_on = p->learned_on;
+  p->learned_on = false;  // pairs come from the plain V-cycle
+  hho::launch_spmv<double>(p->tp, D, x_true, nullptr, nullptr, p->ob, s);  // b = S x_true
+  hho::launch_fill<double>(n, 0.0, p->ox, s);
+  hho::launch_fill<double>(2, 1.0, p->scal + 2, s);  // ratio 1/1 for the update below
+  for (int c = 0; c < cycles; ++c) {
+    hho::launch_residual<double>(p->tp, D, p->ob, p->ox, p->or_, s);
+    float *Xc = X + (int64_t)c * nf * md.n_in;
+    hho::launch_mlp_windows<double>(p->tp, md, p->or_, Xc, p->mlp_sc, s);
+    hho::launch_mlp_targets((int)nf, md.dp, x_true, p->ox, p->mlp_sc, Tg + (int64_t)c * nf * md.n_out, s);
+    if (c + 1 < cycles) {
+      hho::apply_vcycle(p, p->or_, p->ow);
+      hho::launch_axpy_ratio<double>(n, p->scal + 2, 1.0, p->ow, p->ox, s);  // x += V(r)
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  p->learned_on = was_on;
+  *n_out = need;
+  return HHO_OK;
+  ABI_END
+}
+
+// loss and gradient of the batch rows (rows == null: rows 0..B-1) at the current parameters
+static double mlp_loss_grad(hho_problem *p, const float *X, const float *Tg, const int *rows, int B, double *loss_dev) {
+  const hho::MlpDims &md = p->md;
+  hipStream_t s = p->stream;
+  hho::launch_mlp_forward(B, md.n_in, md.n_out, X, rows, p->mlp_prm, p->mlp_Z, p->mlp_Yb, s);
+  const int G = hho::launch_mlp_backward(B, md.n_in, md.n_out, X, rows, Tg, p->mlp_prm, p->mlp_Z, p->mlp_Yb,
+                                         p->mlp_dY, p->mlp_dZ, p->mlp_g, p->partial, s);
+  hho::launch_sum_finish(G, p->partial, loss_dev, s);
+  return 0.5 / B;  // factor turning the summed squares into the loss
+}
+
+int hho_learned_grad(hho_problem *p, const float *X, const float *Tg, int64_t n, float *grad, double *loss) {
+  ABI_BEGIN
+  need_learned(p);
+  if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_grad: no parameters set");
+  if (!X || !Tg || !grad || !loss || n < 1 || n > hho::kMlpMaxBatch)
+    hho::fail(HHO_E_INVALID_ARG, "learned_grad: bad argument (1 <= n <= 4096)");
+  const double f = mlp_loss_grad(p, X, Tg, nullptr, (int)n, p->mlp_loss);
+  const int64_t np = hho::mlp_param_count(p->md);
+  double ls = 0;
+  HIPCHK(hipMemcpyAsync(grad, p->mlp_g, np * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(&ls, p->mlp_loss, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  *loss = f * ls;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_train(hho_problem *p, const float *X, const float *Tg, int64_t n, int steps, int batch, float lr,
+                      uint64_t seed, float *loss_hist) {
+  ABI_BEGIN
+  need_learned(p);
+  if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_train: set initial parameters first");
+  if (!X || !Tg || n < 1 || steps < 1 || steps > hho::kMlpMaxSteps || batch < 1 || batch > hho::kMlpMaxBatch ||
+      !(lr > 0))
+    hho::fail(HHO_E_INVALID_ARG, "learned_train: bad argument");
+  hipStream_t s = p->stream;
+  const int64_t np = hho::mlp_param_count(p->md);
+  double f = 0;
+  for (int it = 0; it < steps; ++it) {
+    hho::launch_mlp_rows(batch, n, seed, p->adam_step, p->mlp_rows, s);
+    f = mlp_loss_grad(p, X, Tg, p->mlp_rows, batch, p->mlp_loss + it);
+    hho::launch_mlp_adam(np, p->mlp_prm, p->mlp_g, p->mlp_m, p->mlp_v, lr, ++p->adam_step, s);
+  }
+  if (loss_hist) {
+    std::vector<double> tmp(steps);
+    HIPCHK(hipMemcpyAsync(tmp.data(), p->mlp_loss, steps * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < steps; ++i) loss_hist[i] = (float)(f * tmp[i]);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
