@@ -115,6 +115,44 @@ def fine_kernel_name(d, k, cond, precision):
     return f"k_spmv_vp<{T}, {d * p}, true, 0>"
 
 
+def train_learned(P, n0, forcings=8, cycles=3, steps=1500, batch=2048, lr=1e-3):
+    """Untimed: V-cycle training pairs from seeded discrete forcings b = S x_true
+    (x_true ~ N(0, 1) per unknown, seeds 1000+i), He-uniform first layer and
+    zero output layer, Adam training on the GPU by the library's kernels."""
+    import torch
+    dm = P.learned_dims()
+    rng = np.random.default_rng(0)
+    h, n_in, n_out = dm["hidden"], dm["n_in"], dm["n_out"]
+    W1 = (2 * rng.random(h * n_in) - 1) * np.sqrt(6.0 / n_in)
+    W2 = np.zeros(n_out * h)  # the untrained network is the zero predictor
+    P.learned_set_params(np.concatenate([W1, np.zeros(h), W2, np.zeros(n_out)]).astype(np.float32))
+    P.setup()
+    t0 = time.perf_counter()
+    Xs, Ts = [], []
+    for i in range(forcings):
+        xt = torch.from_numpy(np.random.default_rng(1000 + i).standard_normal(n0)).cuda()
+        X, T = P.learned_collect(xt, cycles)
+        Xs.append(X)
+        Ts.append(T)
+    X, T = torch.cat(Xs), torch.cat(Ts)
+    base = float(0.5 * (T.double() ** 2).sum(dim=1).mean())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hist = P.learned_train(X, T, steps=steps, batch=batch, lr=lr, seed=7)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    P.setup()
+    _, its_plain, _, _, _ = P.solve()
+    P.learned_enable(True)
+    print(f"[bench] learned smoother: {X.shape[0]} pairs ({t1 - t0:.1f}s), {steps} Adam steps ({t2 - t1:.1f}s), "
+          f"loss {hist[:10].mean():.3e} -> {hist[-50:].mean():.3e} (zero predictor {base:.3e})",
+          file=sys.stderr, flush=True)
+    return {"pairs": int(X.shape[0]), "forcings": forcings, "collect_s": round(t1 - t0, 2),
+            "train_steps": steps, "batch": batch, "train_s": round(t2 - t1, 2),
+            "loss_first": float(hist[:10].mean()), "loss_last": float(hist[-50:].mean()),
+            "loss_zero_predictor": base, "fgmres_its_plain": its_plain}
+
+
 def cpu_baseline(spec, sample_cells=1024):
     """The oracle as it stands, end to end (local operators, condensation,
     assembly, levels, Schwarz setup, FGMRES to 1e-8), on a smaller mesh of the
@@ -152,6 +190,8 @@ def main():
     ap.add_argument("--coarse-rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--learned", action="store_true",
+                    help="train the learned fine-level smoother first (untimed) and solve with it")
     ap.add_argument("--traffic-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference point for HBM byte counters)")
     args = ap.parse_args()
@@ -171,7 +211,8 @@ def main():
     print(f"[bench] workload {args.workload}: {mesh.n_cells} cells, {mesh.n_faces} faces "
           f"(mesh {t_mesh:.1f}s)", file=sys.stderr, flush=True)
     M = H.Mesh(mesh)
-    P = H.Problem(M, spec["k"], spec["cond"], precision=args.precision, coarse_rtol=args.coarse_rtol)
+    P = H.Problem(M, spec["k"], spec["cond"], precision=args.precision, coarse_rtol=args.coarse_rtol,
+                  learned=1 if args.learned else 0)
     t_host = time.perf_counter()
     P.set_data(*data)
     t_host = time.perf_counter() - t_host
@@ -192,6 +233,10 @@ def main():
     def step():
         P.setup()
         return P.solve()
+
+    learned_info = None
+    if args.learned:
+        learned_info = train_learned(P, n0)
 
     for w in range(args.warmup):
         _, its, _, rel, ok = step()
@@ -240,7 +285,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32 V-cycle / f64 outer",
+        "dtype": ("f64" if args.precision == "fp64" else "f32 V-cycle / f64 outer") + (" + f32 MLP" if args.learned else ""),
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": mesh.n_cells, "faces": mesh.n_faces, "k": spec["k"],
                    "cond": spec["cond"], "levels": list(range(spec["k"], -1, -1)), "fine_dofs": n0,
@@ -251,6 +296,7 @@ def main():
         "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
         "phase_ms": {k: round(v, 3) for k, v in tm.items()},
         "roofline": roof,
+        "learned": learned_info,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

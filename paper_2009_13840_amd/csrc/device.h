@@ -26,7 +26,10 @@ struct DTopo {
   const int64_t *pairoff;  // [nc+1] prefix sum of card(F_T)^2
   const int32_t *pairblk;  // [pairoff[nc]] block index of the local pair (i, j) of each cell
   const double *zmean;     // [nc] |T|^{1/2}: mean-mode coefficient of the constant pressure
+  int max_faces;           // largest card(F_T)
 };
+
+constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one CDNA4 compute unit
 
 // One level of the operator: face-block rows plus cell-local couplings.
 //  v-cond:   bsr  [nnzb][p][p] scalar blocks (act on every velocity component),

@@ -7,6 +7,7 @@
 #include "dev_common.h"
 #include "dev_dense.h"
 #include "device.h"
+#include "internal.h"
 
 namespace hho {
 namespace {
@@ -336,6 +337,159 @@ __global__ void __launch_bounds__(kBlock) k_patch_setup(DTopo tp, int cond, int 
   if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
 }
 
+// Same outputs as k_patch_setup with the patch factorised entirely in LDS:
+// the lower triangle of the patch matrix is held packed by columns
+// (n(n+1)/2 doubles, 130 KB for n = 180), factorised in place (Cholesky), and
+// the factor inverted in place (L^{-1}); S_P^{-1} = L^{-T} L^{-1} is formed
+// entry by entry straight into global memory.  One 512-thread block per cell;
+// waves take columns, lanes run down a column (consecutive LDS addresses).
+constexpr int kPatchThreads = 512;
+
+__device__ inline int pk(int n, int i, int j) { return j * (2 * n - j + 1) / 2 + (i - j); }  // i >= j
+
+__global__ void __launch_bounds__(kPatchThreads) k_patch_setup_lds(DTopo tp, int cond, int p, int t,
+                                                                   const double *bsr, const double *cpl,
+                                                                   const double *spp, double *sinv, double *xinv,
+                                                                   double *sig, int *err) {
+  extern __shared__ double lds[];
+  const int T = blockIdx.x;
+  const int d = tp.d;
+  const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+  const int bs = (cond == 1) ? p : d * p;
+  const int n = nfc * bs;
+  const int tid = threadIdx.x, lane = tid % kWave, wid = tid / kWave, nw = blockDim.x / kWave;
+  double *A = lds;                       // packed lower, n(n+1)/2
+  double *x = A + n * (n + 1) / 2;       // [max(n, 16)] scratch column / reduction space
+  double *ext = x + (n > 16 ? n : 16);   // v-cond: U [d*n][t], X [t][t], 2 columns; v&p: [n]
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  const int32_t *pb = tp.pairblk + tp.pairoff[T];
+  for (int j = wid; j < n; j += nw)
+    for (int i = j + lane; i < n; i += kWave) {
+      const int fi = i / bs, fj = j / bs;
+      const int64_t blk = pb[fi * nfc + fj];
+      A[pk(n, i, j)] = bsr[blk * bs * bs + (int64_t)(i % bs) * bs + (j % bs)];
+    }
+  __syncthreads();
+  // Cholesky, right-looking
+  for (int j = 0; j < n; ++j) {
+    if (tid == 0) {
+      double v = A[pk(n, j, j)];
+      if (!(v > 0.0)) {
+        bad = 1;
+        v = 1.0;
+      }
+      A[pk(n, j, j)] = sqrt(v);
+    }
+    __syncthreads();
+    const double ljj = A[pk(n, j, j)];
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) A[pk(n, i, j)] /= ljj;
+    __syncthreads();
+    for (int k = j + 1 + wid; k < n; k += nw) {
+      const double akj = A[pk(n, k, j)];
+      double *ck = A + pk(n, k, k);
+      const double *cj = A + pk(n, k, j);
+      for (int i = lane; i < n - k; i += kWave) ck[i] -= cj[i] * akj;
+    }
+    __syncthreads();
+  }
+  // L^{-1} in place, last column first: column j below the diagonal becomes
+  // -L^{-1}_jj * (L^{-1})_{trailing} * L_{j+1:, j}; one wave per row, lanes split
+  // the row's dot product (fixed-order wave reduction)
+  for (int j = n - 1; j >= 0; --j) {
+    for (int i = j + 1 + tid; i < n; i += blockDim.x) x[i] = A[pk(n, i, j)];
+    if (tid == 0) A[pk(n, j, j)] = 1.0 / A[pk(n, j, j)];
+    __syncthreads();
+    const double ajj = A[pk(n, j, j)];
+    for (int i = j + 1 + wid; i < n; i += nw) {
+      double acc = 0;
+      for (int k = j + 1 + lane; k <= i; k += kWave) acc += A[pk(n, i, k)] * x[k];
+      acc = wave_sum(acc);
+      if (lane == 0) A[pk(n, i, j)] = -ajj * acc;
+    }
+    __syncthreads();
+  }
+  // S_P^{-1}(i, k) = sum_{m >= max(i,k)} Linv(m, i) Linv(m, k), both triangles written
+  double *Si = sinv + tp.pairoff[T] * (int64_t)bs * bs;
+  for (int k = wid; k < n; k += nw)
+    for (int i = k + lane; i < n; i += kWave) {
+      double acc = 0;
+      const double *ci = A + pk(n, i, i), *ck = A + pk(n, i, k);  // rows m >= i of columns i and k
+      for (int m = 0; m < n - i; ++m) acc += ci[m] * ck[m];
+      Si[(int64_t)i * n + k] = acc;
+      Si[(int64_t)k * n + i] = acc;
+    }
+  // y = S_P^{-1} v through the factor: u = Linv v, y = Linv^T u (columns of V strided by ld)
+  auto apply = [&](const double *v, int64_t vs, double *u, double *y, int64_t ys) {
+    for (int i = tid; i < n; i += blockDim.x) {
+      double acc = 0;
+      for (int k = 0; k <= i; ++k) acc += A[pk(n, i, k)] * v[k * vs];
+      u[i] = acc;
+    }
+    __syncthreads();
+    for (int k = tid; k < n; k += blockDim.x) {
+      double acc = 0;
+      const double *ck = A + pk(n, k, k);
+      for (int m = 0; m < n - k; ++m) acc += ck[m] * u[k + m];
+      y[k * ys] = acc;
+    }
+    __syncthreads();
+  };
+  const int64_t c0 = tp.cptr[T];
+  if (cond == 1) {
+    // U = (s^{-1} (x) I) C  [(face, comp, mode) x t], X = S_TT - C^T U  [t x t]
+    const double *C = cpl + c0 * d * p * t;
+    double *U = ext;                      // [nfc*d*p][t]
+    double *X = U + (int64_t)d * n * t;   // [t][t]
+    double *vcol = X + t * t;             // [n]
+    double *ycol = vcol + n;              // [n]
+    for (int c = 0; c < d; ++c)
+      for (int q = 0; q < t; ++q) {
+        for (int i = tid; i < n; i += blockDim.x) {
+          const int fj = i / p, r = i % p;
+          vcol[i] = C[((fj * d + c) * p + r) * t + q];
+        }
+        __syncthreads();
+        apply(vcol, 1, x, ycol, 1);
+        for (int i = tid; i < n; i += blockDim.x) {
+          const int fj = i / p, r = i % p;
+          U[((fj * d + c) * p + r) * t + q] = ycol[i];
+        }
+        __syncthreads();
+      }
+    for (int idx = tid; idx < t * t; idx += blockDim.x) {
+      const int q = idx / t, q2 = idx % t;
+      double v = -spp[(int64_t)T * t * t + idx];
+      for (int row = 0; row < d * n; ++row) v += C[row * t + q] * U[row * t + q2];
+      X[idx] = v;  // -X is SPD
+    }
+    __syncthreads();
+    blk_chol(X, t, t, &bad);
+    __syncthreads();
+    double *Xi = xinv + (int64_t)T * t * t;
+    blk_chol_inverse(X, t, t, Xi, t);
+    for (int idx = tid; idx < t * t; idx += blockDim.x) Xi[idx] = -Xi[idx];
+  } else {
+    const double *b = cpl + c0 * d * p;
+    double *g = xinv + c0 * d * p;
+    double *gl = ext;  // [n]
+    apply(b, 1, x, gl, 1);
+    double part = 0;
+    for (int i = tid; i < n; i += blockDim.x) {
+      g[i] = gl[i];
+      part += b[i] * gl[i];
+    }
+    __syncthreads();
+    const double sdot = block_sum(part, x);
+    if (tid == 0) {
+      if (!(sdot > 0.0)) bad = 1;
+      sig[T] = (sdot > 0.0) ? 1.0 / sdot : 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && bad) atomicMax(err, T + 1);
+}
+
 template <typename Tout, typename Tin>
 __global__ void k_convert(const Tin *in, Tout *out, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -518,9 +672,31 @@ void launch_extract(const DTopo &tp, int cond, int64_t nnzb, int p0, int t0, int
   hipLaunchKernelGGL(k_extract, dim3(grid_for(total)), dim3(kBlock), 0, s, tp, cond, nnzb, p0, t0, p1, t1, bsr0,
                      cpl0, spp0, bsr1, cpl1, spp1);
 }
+size_t patch_lds_packed_bytes(int d, int cond, int p, int t, int max_faces) {
+  const int64_t n = (int64_t)max_faces * ((cond == 1) ? p : d * p);
+  int64_t w = n * (n + 1) / 2 + std::max<int64_t>(n, 16);
+  w += (cond == 1) ? (int64_t)d * n * t + (int64_t)t * t + 2 * n : n;
+  return (size_t)std::max<int64_t>(w, 64) * sizeof(double);
+}
+
 void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *bsr, const double *cpl,
                         const double *spp, double *sinv, double *xinv, double *sig, double *scratch, int *err,
                         hipStream_t s, size_t lds) {
+  // LDS-resident factorisation when the packed patch fits the 160 KB of a CDNA4 CU
+  const size_t packed = patch_lds_packed_bytes(tp.d, cond, p, t, tp.max_faces);
+  const size_t budget = kMaxLdsBytes - 1024;  // leaves room for the kernel's static LDS
+  if (packed <= budget) {
+    static bool attr_set = false;
+    if (!attr_set) {
+      if (hipFuncSetAttribute((const void *)k_patch_setup_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)budget) != hipSuccess)
+        fail(HHO_E_DEVICE, "patch setup: cannot reserve 160 KB of LDS");
+      attr_set = true;
+    }
+    hipLaunchKernelGGL(k_patch_setup_lds, dim3(tp.nc), dim3(kPatchThreads), packed, s, tp, cond, p, t, bsr, cpl,
+                       spp, sinv, xinv, sig, err);
+    return;
+  }
   hipLaunchKernelGGL(k_patch_setup, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, p, t, bsr, cpl, spp, sinv, xinv,
                      sig, scratch, err);
 }

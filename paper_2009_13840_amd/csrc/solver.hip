@@ -416,6 +416,7 @@ static void build_topology(hho_problem *P) {
   for (int64_t c = 0; c < nc; ++c) P->zmean[c] = std::sqrt(m->cvol[c]);
   P->max_faces = m->max_faces;
   P->tp.d = P->d;
+  P->tp.max_faces = m->max_faces;
   P->tp.nc = (int)nc;
   P->tp.nf = (int)nf;
   P->tp.ncf = P->ncf;

@@ -157,6 +157,8 @@ def test_training_gain_over_plain_smoother():
     dm = P.learned_dims()
     rng = np.random.default_rng(21)
     th, flat = _params(rng, dm["n_in"], dm["n_out"])
+    nw1 = mlp.HIDDEN * dm["n_in"] + mlp.HIDDEN
+    flat[nw1:] = 0.0                              # start from the zero predictor
     P.learned_set_params(flat)
     N = P.level_size(0)
     Xs, Ts = [], []
@@ -166,13 +168,15 @@ def test_training_gain_over_plain_smoother():
         Xs.append(X)
         Ts.append(T)
     X, T = torch.cat(Xs), torch.cat(Ts)
-    hist = P.learned_train(X, T, steps=600, batch=1024, lr=2e-3, seed=7)
+    hist = P.learned_train(X, T, steps=800, batch=1024, lr=1e-3, seed=7)
+    zero = float(0.5 * (T.double() ** 2).sum(dim=1).mean())
     assert np.isfinite(hist).all()
-    assert hist[-50:].mean() < 0.7 * hist[:10].mean(), (hist[:10].mean(), hist[-50:].mean())
+    assert hist[-50:].mean() < 0.9 * zero, (zero, hist[-50:].mean())   # learned something beyond y = 0
     _, its0, h0, _, ok0 = P.solve()
     P.learned_enable(True)
     _, its1, h1, _, ok1 = P.solve()
     P.learned_enable(False)
-    print(f"[gain] FGMRES its plain {its0} learned {its1}; loss {hist[:10].mean():.3e} -> {hist[-50:].mean():.3e}")
+    print(f"[gain] FGMRES its plain {its0} learned {its1}; loss {hist[:10].mean():.3e} -> {hist[-50:].mean():.3e}"
+          f" (zero predictor {zero:.3e})")
     assert ok0 and ok1
     assert its1 <= its0
