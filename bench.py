@@ -180,12 +180,94 @@ def cpu_baseline(spec, sample_cells=1024):
             "sample": f"{name}: {n0} fine DOFs, {its} FGMRES its, {dt:.1f} s single-thread (NumPy/SciPy FP64)"}
 
 
+def run_batch(args):
+    """256 independent 2D Stokes problems (Cartesian meshes, side ~ U{16..96},
+    k ~ U{1..4}, trig-series force with seed 4000+i, v-cond, homogeneous
+    Dirichlet): members of equal degree form one disjoint-union problem with one
+    FGMRES process per member; the four degree groups run concurrently, one host
+    thread and one HIP stream each.  A step = setup + solve of every group."""
+    import threading
+    import torch
+    import paper_2009_13840_amd as H
+    from synth import cartesian_quads, trig_series
+    from synth.fields import problem_data
+    from synth.batch import batch_spec, shifted, region_fields
+    spec = batch_spec()
+    groups = {}
+    for i, (side, k, seed) in enumerate(spec):
+        groups.setdefault(k, []).append((i, side, seed))
+    width = 2.0
+    probs = []
+    t0 = time.perf_counter()
+    for k, mem in sorted(groups.items()):
+        meshes = [shifted(cartesian_quads(side), width * j) for j, (_, side, _) in enumerate(mem)]
+        fields = [problem_data(None, trig_series(2, seed), 2) for (_, _, seed) in mem]
+        U, fo, co = H.Mesh.union(meshes)
+        P = H.Problem(U, k, "v", precision=args.precision, coarse_rtol=args.coarse_rtol)
+        P.set_segments(fo, co)
+        P.set_data(*region_fields(fields, 2, width))
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            P.bind("cuda:0")
+            P.upload()
+        probs.append(dict(k=k, P=P, stream=stream, members=len(mem), cells=U.n_cells))
+        print(f"[bench] degree {k}: {len(mem)} members, {U.n_cells} cells, {P.level_size(0)} fine DOFs "
+              f"({time.perf_counter() - t0:.1f}s)", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    dofs = sum(g["P"].level_size(0) for g in probs)
+    cells = sum(g["cells"] for g in probs)
+
+    def run_group(g, out):
+        P = g["P"]
+        P.setup()
+        out[g["k"]] = P.solve()[1:]
+
+    def step():
+        out = {}
+        th = [threading.Thread(target=run_group, args=(g, out)) for g in probs]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        return out
+
+    for w in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        res = step()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    per = {}
+    worst_rel, max_its = 0.0, 0
+    for g in probs:
+        its, hist, rel, ok = res[g["k"]]
+        m_its, m_rel = g["P"].batch_results()
+        worst_rel = max(worst_rel, float(m_rel.max()))
+        max_its = max(max_its, int(m_its.max()))
+        per[f"k{g['k']}"] = {"members": g["members"], "fine_dofs": g["P"].level_size(0), "its_max": int(m_its.max()),
+                             "its_mean": round(float(m_its.mean()), 2), "ok": bool(ok),
+                             "phase_ms": {k: round(v, 2) for k, v in g["P"].timings().items()}}
+    out = {
+        "metric": METRIC, "value": round(dofs / dt / 1e9, 6), "unit": "GDOF/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32 V-cycle / f64 outer", "data": "synthetic",
+        "config": {"workload": "batch256", "problems": len(spec), "cells": cells, "fine_dofs": dofs, "rtol": 1e-8,
+                   "cond": "v", "groups": per},
+        "time_to_1e8_ms": round(dt * 1e3, 3), "fgmres_its_max": max_its, "final_rel_residual_max": worst_rel,
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="voronoi16384_k3_v", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="voronoi16384_k3_v", choices=sorted(WORKLOADS) + ["batch256"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--coarse-rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -199,6 +281,9 @@ def main():
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU sharding is a design, see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch256":
+        return run_batch(args)
 
     import torch
     import paper_2009_13840_amd as H

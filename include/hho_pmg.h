@@ -238,6 +238,33 @@ int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_m
  * [8] coarse iterations total.  n is the capacity of t. */
 int hho_get_timings(const hho_problem *p, double *t, int n);
 
+/* ---- batches of independent problems (not in the paper) ----
+ * n meshes become one mesh (their disjoint union; member i's faces and cells
+ * keep their order and follow those of members 0..i-1), a problem on it is told
+ * the member ranges with hho_problem_set_segments, and hho_solve then runs one
+ * flexible GMRES process per member: the V-cycle and the operator act on the
+ * whole union at once (block diagonal), while the Arnoldi dot products,
+ * Hessenberg columns, Givens rotations, restarts and the stopping test
+ * (true relative residual of each member <= rtol) are per member.  Members with
+ * a pure Dirichlet boundary have their own constant-pressure null vector. */
+
+/* Disjoint union of n meshes (host descriptors, copied).  face_offsets and
+ * cell_offsets (may be NULL, else n+1 entries) receive the first face / cell
+ * of every member and the totals. */
+int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int64_t *face_offsets,
+                          int64_t *cell_offsets);
+
+/* Declares the members of a union mesh: member i owns faces [face_ptr[i],
+ * face_ptr[i+1]) and cells [cell_ptr[i], cell_ptr[i+1]) (partitions, every
+ * cell's faces in its own member).  Call after hho_problem_create and before
+ * hho_problem_set_data.  A dense coarsest-level solver is refused when the
+ * members have a pressure null space (use AMG or GMRES). */
+int hho_problem_set_segments(hho_problem *p, int n, const int64_t *face_ptr, const int64_t *cell_ptr);
+
+/* After a batched hho_solve: FGMRES iterations and final true relative
+ * residual of every member (host arrays of n = number of members). */
+int hho_batch_results(const hho_problem *p, int *iters, double *rel, int n);
+
 /* ---- learned fine-level smoother (not in the paper) ----
  * Needs a problem created with options.learned = 1 and a bound workspace.
  * Per face F of level 0 a network maps a window of the residual r to a

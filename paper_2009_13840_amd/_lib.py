@@ -28,7 +28,8 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
-           "hho_learned_collect", "hho_learned_grad", "hho_learned_train"]
+           "hho_learned_collect", "hho_learned_grad", "hho_learned_train", "hho_mesh_create_union",
+           "hho_problem_set_segments", "hho_batch_results"]
 
 
 class HHOError(RuntimeError):
@@ -94,6 +95,9 @@ def load():
         "hho_time_kernel": ([P, I32, I32, I32, D], I32),
         "hho_coarse_prec_apply": ([P, P, P], I32),
         "hho_debug_copy": ([P, C.c_char_p, I32, D, I64, C.POINTER(I64)], I32),
+        "hho_mesh_create_union": ([C.POINTER(MeshDesc), I32, C.POINTER(P), C.POINTER(I64), C.POINTER(I64)], I32),
+        "hho_problem_set_segments": ([P, I32, C.POINTER(I64), C.POINTER(I64)], I32),
+        "hho_batch_results": ([P, C.POINTER(C.c_int), D, I32], I32),
         "hho_learned_dims": ([P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(I64)], I32),
         "hho_learned_set_params": ([P, C.POINTER(C.c_float), I64], I32),
         "hho_learned_get_params": ([P, C.POINTER(C.c_float), I64], I32),
@@ -121,31 +125,54 @@ def _dptr(a):
     return a.ctypes.data_as(C.POINTER(C.c_double))
 
 
+def _desc(m):
+    keep = [np.ascontiguousarray(m.verts, dtype=np.float64),
+            np.ascontiguousarray(m.face_ptr, dtype=np.int64),
+            np.ascontiguousarray(m.face_vtx, dtype=np.int64),
+            np.ascontiguousarray(m.cell_ptr, dtype=np.int64),
+            np.ascontiguousarray(m.cell_face, dtype=np.int64),
+            np.ascontiguousarray(m.face_bc, dtype=np.int8)]
+    v, fp, fv, cp, cf, bc = keep
+    desc = MeshDesc(int(m.dim), len(v), _dptr(v), len(fp) - 1, fp.ctypes.data_as(C.POINTER(C.c_int64)),
+                    fv.ctypes.data_as(C.POINTER(C.c_int64)), len(cp) - 1,
+                    cp.ctypes.data_as(C.POINTER(C.c_int64)), cf.ctypes.data_as(C.POINTER(C.c_int64)),
+                    bc.ctypes.data_as(C.POINTER(C.c_int8)))
+    return desc, keep
+
+
 class Mesh:
     """Library copy of a ``synth.Mesh``-like object (dim, verts, face_ptr, face_vtx,
     cell_ptr, cell_face, face_bc)."""
 
     def __init__(self, m):
         lib = load()
-        self._keep = [np.ascontiguousarray(m.verts, dtype=np.float64),
-                      np.ascontiguousarray(m.face_ptr, dtype=np.int64),
-                      np.ascontiguousarray(m.face_vtx, dtype=np.int64),
-                      np.ascontiguousarray(m.cell_ptr, dtype=np.int64),
-                      np.ascontiguousarray(m.cell_face, dtype=np.int64),
-                      np.ascontiguousarray(m.face_bc, dtype=np.int8)]
-        v, fp, fv, cp, cf, bc = self._keep
-        desc = MeshDesc(int(m.dim), len(v), _dptr(v), len(fp) - 1, fp.ctypes.data_as(C.POINTER(C.c_int64)),
-                        fv.ctypes.data_as(C.POINTER(C.c_int64)), len(cp) - 1,
-                        cp.ctypes.data_as(C.POINTER(C.c_int64)), cf.ctypes.data_as(C.POINTER(C.c_int64)),
-                        bc.ctypes.data_as(C.POINTER(C.c_int8)))
+        desc, keep = _desc(m)
+        self._keep = keep
         h = C.c_void_p()
         _check(lib.hho_mesh_create(C.byref(desc), C.byref(h)))
         self.h = h
         self.dim = int(m.dim)
-        self.n_cells = len(cp) - 1
-        self.n_faces = len(fp) - 1
-        self.cell_ptr = cp
-        self.cell_face = cf
+        self.n_faces = len(keep[1]) - 1
+        self.n_cells = len(keep[3]) - 1
+
+    @classmethod
+    def union(cls, meshes):
+        """Disjoint union of several meshes; returns (mesh, face_offsets, cell_offsets)."""
+        lib = load()
+        pairs = [_desc(m) for m in meshes]
+        arr = (MeshDesc * len(pairs))(*[d for d, _ in pairs])
+        fo = np.zeros(len(pairs) + 1, dtype=np.int64)
+        co = np.zeros(len(pairs) + 1, dtype=np.int64)
+        h = C.c_void_p()
+        _check(lib.hho_mesh_create_union(arr, len(pairs), C.byref(h), fo.ctypes.data_as(C.POINTER(C.c_int64)),
+                                         co.ctypes.data_as(C.POINTER(C.c_int64))))
+        self = cls.__new__(cls)
+        self._keep = []
+        self.h = h
+        self.dim = int(meshes[0].dim)
+        self.n_faces = int(fo[-1])
+        self.n_cells = int(co[-1])
+        return self, fo, co
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -203,7 +230,7 @@ class Problem:
         self.h = h
         self.ws = None
         self.nlev = len(degrees) if degrees is not None else k + 1
-        self.nfaces = len(mesh._keep[1]) - 1
+        self.nfaces = mesh.n_faces
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -318,6 +345,20 @@ class Problem:
         x = self._vec(self.level_size(0))
         _check(load().hho_vcycle_apply(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
         return x
+
+    # ---- batches (problem on a union mesh)
+    def set_segments(self, face_ptr, cell_ptr):
+        fp = np.ascontiguousarray(face_ptr, dtype=np.int64)
+        cp = np.ascontiguousarray(cell_ptr, dtype=np.int64)
+        self.nseg = len(fp) - 1
+        _check(load().hho_problem_set_segments(self.h, self.nseg, fp.ctypes.data_as(C.POINTER(C.c_int64)),
+                                               cp.ctypes.data_as(C.POINTER(C.c_int64))))
+
+    def batch_results(self):
+        its = np.zeros(self.nseg, dtype=np.int32)
+        rel = np.zeros(self.nseg)
+        _check(load().hho_batch_results(self.h, its.ctypes.data_as(C.POINTER(C.c_int)), _dptr(rel), self.nseg))
+        return its, rel
 
     # ---- learned fine-level smoother (problem created with learned=1)
     def learned_dims(self):

@@ -169,6 +169,35 @@ void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T
                 T *r, double *partial, double *y, hipStream_t s);
 void launch_sum_finish(int G, const double *partial, double *out, hipStream_t s);
 
+// ---- batched problems: per-problem (segment) Krylov state over a disjoint union
+// A segment's unknowns are its face entries [fo, fo + fl) and cell entries
+// [co, co + cl) of the level-0 vector; its "virtual" index e < fl + cl maps to
+// fo + e (e < fl) or co + e - fl.
+struct SegInfo {
+  int64_t fo, fl, co, cl;
+};
+struct SegChunk {  // kSegChunk consecutive virtual entries of one segment
+  int32_t p, e0, len, pad;
+};
+constexpr int kSegChunk = 4096;
+struct GmresState;
+void launch_seg_sumsq(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *r, double *partial,
+                      hipStream_t s);
+// |r_p| -> beta, (bnorm when which == 1), g = beta e1, done flags (sdone[p])
+void launch_seg_norm_finish(int np, const int32_t *chunk_ptr, int nchunks, const double *partial, GmresState *st,
+                            int *sdone, int which, hipStream_t s);
+void launch_seg_scale(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *x, const GmresState *st,
+                      double *y, hipStream_t s);
+void launch_seg_arnoldi(int mode, int nchunks, const SegChunk *ch, const SegInfo *seg, int np,
+                        const int32_t *chunk_ptr, int j, const double *V, int64_t ldv, double *w, double *partial,
+                        GmresState *st, int *sdone, int cgs2, hipStream_t s);
+void launch_seg_solve_ls(int np, GmresState *st, hipStream_t s);
+void launch_seg_combine(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *Z, int64_t ldz,
+                        const GmresState *st, double *x, hipStream_t s);
+// v_p -= (v_p . z_p / z_p . z_p) z_p for every segment
+void launch_seg_project(int np, const int32_t *chunk_ptr, int nchunks, const SegChunk *ch, const SegInfo *seg,
+                        const double *z, double *v, double *partial, double *ratio, hipStream_t s);
+
 // device-resident GMRES scalars
 struct GmresState {
   double H[(kMaxRestartH + 1) * kMaxRestartH];
@@ -183,7 +212,7 @@ struct GmresState {
   int j;              // current column
   int done;           // converged or broke down
   int nan;            // non-finite value met
-  int pad;
+  int its;           // Arnoldi steps taken (all cycles)
 };
 
 }  // namespace hho

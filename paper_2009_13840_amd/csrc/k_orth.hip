@@ -68,10 +68,10 @@ __device__ inline void block_multi_partial(double (&acc)[NV], int nv, double *pa
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   if ((lane & ((1 << shift) - 1)) == 0) red[wid][lane >> shift] = acc[0];
   __syncthreads();
+  const int nwv = blockDim.x / kWave;  // waves of this launch (<= kOrthThreads / kWave)
   for (int i = threadIdx.x; i < nv; i += blockDim.x) {
     double s = 0;
-#pragma unroll
-    for (int w_ = 0; w_ < kOrthThreads / kWave; ++w_) s += red[w_][i];
+    for (int w_ = 0; w_ < nwv; ++w_) s += red[w_][i];
     partial[(int64_t)i * gridDim.x + blockIdx.x] = s;
   }
 }
@@ -143,31 +143,18 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(int64_t n, int j, int E, 
   }
 }
 
-// One block: sums the partials of k_orth in a fixed order.  MODE 0/1 store h1/h2;
-// MODE 2 completes column j of the Hessenberg matrix, applies the Givens
-// rotations and updates the residual estimate and the convergence flag.
-template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const double *partial, GmresState *st,
-                                                        int cgs2) {
-  if (st->done) return;
-  __shared__ double hs[kMaxRestartH + 1];
-  const int nv = j + 1;
-  if (MODE != 2) {
-    reduce_partials(partial, G, nv, hs);
-    double *dst = (MODE == 0) ? st->h1 : st->h2;
-    for (int i = threadIdx.x; i < nv; i += blockDim.x) dst[i] = hs[i];
-    return;
-  }
-  // column j of H in LDS, previous rotations staged in LDS, then one thread
-  // applies them (a dependent chain, kept out of global memory)
+// Completes column j of the Hessenberg matrix (h1 (+ h2) above the diagonal,
+// sqrt(nn) below), applies the previous Givens rotations and the new one, and
+// updates the residual estimate and the convergence flag.  Whole block; the
+// column and rotations are staged in LDS and one thread runs the dependent chain.
+__device__ void givens_column(GmresState *st, int j, int cgs2, double nn) {
   __shared__ double col[kMaxRestartH + 1], cs[kMaxRestartH], sn[kMaxRestartH];
   for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = cgs2 ? st->h1[i] + st->h2[i] : st->h1[i];
   for (int i = threadIdx.x; i < j; i += blockDim.x) {
     cs[i] = st->cs[i];
     sn[i] = st->sn[i];
   }
-  reduce_partials(partial, G, 1, hs);  // ends with a barrier
-  const double nn = hs[0];
+  __syncthreads();
   const double hn = sqrt(nn);
   if (threadIdx.x == 0) {
     for (int i = 0; i < j; ++i) {
@@ -188,6 +175,7 @@ __global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const doub
     st->g[j + 1] = -s_ * gj;
     st->res = fabs(st->g[j + 1]);
     st->j = j + 1;
+    st->its += 1;
     st->inv_hnext = (hn > 0) ? 1.0 / hn : 0.0;
     if (!isfinite(nn) || !isfinite(st->res)) {
       st->nan = 1;
@@ -198,6 +186,25 @@ __global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const doub
   __syncthreads();
   const int R = kMaxRestartH;
   for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) st->H[i * R + j] = col[i];
+}
+
+// One block: sums the partials of k_orth in a fixed order.  MODE 0/1 store h1/h2;
+// MODE 2 completes column j of the Hessenberg matrix, applies the Givens
+// rotations and updates the residual estimate and the convergence flag.
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const double *partial, GmresState *st,
+                                                        int cgs2) {
+  if (st->done) return;
+  __shared__ double hs[kMaxRestartH + 1];
+  const int nv = j + 1;
+  if (MODE != 2) {
+    reduce_partials(partial, G, nv, hs);
+    double *dst = (MODE == 0) ? st->h1 : st->h2;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) dst[i] = hs[i];
+    return;
+  }
+  reduce_partials(partial, G, 1, hs);
+  givens_column(st, j, cgs2, hs[0]);
 }
 
 void orth_shape(int64_t n, int *grid, int *E) {
@@ -231,6 +238,234 @@ void launch_mode(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partia
   hipLaunchKernelGGL((k_orth_finish<MODE>), dim3(1), dim3(kBlock), 0, s, grid, j, (const double *)partial, st, cgs2);
 }
 
+// ---------------------------------------------------------------- batched problems
+// Chunk c covers kSegChunk consecutive virtual entries of segment ch[c].p; the
+// partials of a segment's chunks are summed (in chunk order) by one block per
+// segment.  Blocks of a converged segment return at once.
+__device__ inline int64_t seg_index(const SegInfo &g, int64_t e) { return e < g.fl ? g.fo + e : g.co + (e - g.fl); }
+
+constexpr int kSegThreads = 256;
+
+// Sum over chunks [c0, c1) of partial[k * G + c] for k < K (waves per sum, lanes split chunks).
+__device__ inline void reduce_range(const double *partial, int G, int c0, int c1, int K, double *out) {
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  for (int k = wid; k < K; k += nw) {
+    double s = 0;
+    for (int b = c0 + lane; b < c1; b += kWave) s += partial[(int64_t)k * G + b];
+    s = wave_sum(s);
+    if (lane == 0) out[k] = s;
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kSegThreads) k_seg_sumsq(const SegChunk *ch, const SegInfo *seg, const double *r,
+                                                            double *partial) {
+  __shared__ double red[16];
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  double acc = 0;
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const double v = r[seg_index(g, (int64_t)c.e0 + e)];
+    acc += v * v;
+  }
+  const double sm = block_sum(acc, red);
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm;
+}
+
+__global__ void __launch_bounds__(kBlock) k_seg_norm_finish(const int32_t *chunk_ptr, int G, const double *partial,
+                                                             GmresState *st_all, int *sdone, int which) {
+  const int p = blockIdx.x;
+  GmresState *st = st_all + p;
+  __shared__ double nsum[1];
+  if (which == 0 && st->done && st->nan) return;
+  reduce_range(partial, G, chunk_ptr[p], chunk_ptr[p + 1], 1, nsum);
+  if (threadIdx.x == 0) {
+    const double nn = nsum[0];
+    const double beta = sqrt(nn);
+    st->beta = beta;
+    if (which == 1) {
+      st->bnorm = beta;
+      st->its = 0;
+    }
+    for (int i = 0; i <= kMaxRestartH; ++i) st->g[i] = 0;
+    st->g[0] = beta;
+    st->res = beta;
+    st->j = 0;
+    st->inv_hnext = (beta > 0) ? 1.0 / beta : 0.0;
+    st->nan = !isfinite(nn);
+    st->done = (!(beta > 0) || st->nan || beta <= st->rtol * st->bnorm) ? 1 : 0;
+    sdone[p] = st->done;
+  }
+}
+
+__global__ void __launch_bounds__(kSegThreads) k_seg_scale(const SegChunk *ch, const SegInfo *seg, const double *x,
+                                                            const GmresState *st, double *y) {
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  const double a = st[c.p].inv_hnext;
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t i = seg_index(g, (int64_t)c.e0 + e);
+    y[i] = a * x[i];
+  }
+}
+
+// MODE 0: h1 = V^T w; 1: w -= V h1, h2 = V^T w; 2: w -= V h, |w|^2 (per segment, per chunk partials)
+template <int NV, int MODE>
+__global__ void __launch_bounds__(kSegThreads) k_seg_orth(const SegChunk *ch, const SegInfo *seg, int j,
+                                                           const double *__restrict__ V, int64_t ldv,
+                                                           double *__restrict__ w, double *partial,
+                                                           const GmresState *st_all, int cgs2) {
+  const SegChunk c = ch[blockIdx.x];
+  const GmresState *st = st_all + c.p;
+  const int nv = j + 1;
+  if (st->done) {  // converged segment: keep the partial layout defined
+    if (threadIdx.x < (MODE == 2 ? 1 : nv)) partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = 0.0;
+    return;
+  }
+  const SegInfo g = seg[c.p];
+  __shared__ double h[NV];
+  if (MODE != 0) {
+    const double *src = (MODE == 2 && cgs2) ? st->h2 : st->h1;
+    for (int i = threadIdx.x; i < NV; i += blockDim.x) h[i] = (i <= j) ? src[i] : 0.0;
+    __syncthreads();
+  }
+  double acc[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) acc[i] = 0;
+#pragma unroll 1
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t k = seg_index(g, (int64_t)c.e0 + e);
+    double wk = w[k];
+    const double *Vk = V + k;
+    if (MODE != 0) {
+#pragma unroll
+      for (int cc = 0; cc < NV / 8; ++cc) {
+        if (cc * 8 < nv) {
+          double v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = Vk[(int64_t)min(cc * 8 + q, nv - 1) * ldv];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) wk -= h[cc * 8 + q] * v[q];
+        }
+        asm volatile("" ::: "memory");
+      }
+      w[k] = wk;
+    }
+    if (MODE == 2) {
+      acc[0] += wk * wk;
+    } else {
+#pragma unroll
+      for (int cc = 0; cc < NV / 8; ++cc) {
+        if (cc * 8 < nv) {
+          double v[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) v[q] = Vk[(int64_t)min(cc * 8 + q, nv - 1) * ldv];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) acc[cc * 8 + q] += v[q] * wk;
+        }
+        asm volatile("" ::: "memory");
+      }
+    }
+  }
+  if (MODE == 2) {
+    __shared__ double red[16];
+    const double sm = block_sum(acc[0], red);
+    if (threadIdx.x == 0) partial[blockIdx.x] = sm;
+  } else {
+    block_multi_partial<NV>(acc, nv, partial);
+  }
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(kBlock) k_seg_orth_finish(const int32_t *chunk_ptr, int G, int j,
+                                                             const double *partial, GmresState *st_all, int *sdone,
+                                                             int cgs2) {
+  const int p = blockIdx.x;
+  GmresState *st = st_all + p;
+  if (st->done) return;
+  __shared__ double hs[kMaxRestartH + 1];
+  const int nv = j + 1;
+  if (MODE != 2) {
+    reduce_range(partial, G, chunk_ptr[p], chunk_ptr[p + 1], nv, hs);
+    double *dst = (MODE == 0) ? st->h1 : st->h2;
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) dst[i] = hs[i];
+    return;
+  }
+  reduce_range(partial, G, chunk_ptr[p], chunk_ptr[p + 1], 1, hs);
+  givens_column(st, j, cgs2, hs[0]);
+  if (threadIdx.x == 0) sdone[p] = st->done;
+}
+
+// y = H^{-1} g per segment (one thread each)
+__global__ void k_seg_solve_ls(int np, GmresState *st_all) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  GmresState *st = st_all + p;
+  const int R = kMaxRestartH;
+  const int jn = st->j;
+  for (int i = jn - 1; i >= 0; --i) {
+    double v = st->g[i];
+    for (int k = i + 1; k < jn; ++k) v -= st->H[i * R + k] * st->y[k];
+    const double hii = st->H[i * R + i];
+    st->y[i] = (hii != 0) ? v / hii : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(kSegThreads) k_seg_combine(const SegChunk *ch, const SegInfo *seg, const double *Z,
+                                                              int64_t ldz, const GmresState *st_all, double *x) {
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  const GmresState *st = st_all + c.p;
+  const int jn = st->j;
+  __shared__ double y[kMaxRestartH];
+  for (int i = threadIdx.x; i < jn; i += blockDim.x) y[i] = st->y[i];
+  __syncthreads();
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t k = seg_index(g, (int64_t)c.e0 + e);
+    double v = x[k];
+    for (int i = 0; i < jn; ++i) v += y[i] * Z[i * ldz + k];
+    x[k] = v;
+  }
+}
+
+__global__ void __launch_bounds__(kSegThreads) k_seg_dot2(const SegChunk *ch, const SegInfo *seg, const double *z,
+                                                           const double *v, double *partial) {
+  __shared__ double red[16];
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  double a = 0, b = 0;
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t k = seg_index(g, (int64_t)c.e0 + e);
+    a += v[k] * z[k];
+    b += z[k] * z[k];
+  }
+  const double sa = block_sum(a, red);
+  const double sb = block_sum(b, red);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = sa;
+    partial[(int64_t)gridDim.x + blockIdx.x] = sb;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock) k_seg_ratio(const int32_t *chunk_ptr, int G, const double *partial,
+                                                       double *ratio) {
+  const int p = blockIdx.x;
+  __shared__ double s2[2];
+  reduce_range(partial, G, chunk_ptr[p], chunk_ptr[p + 1], 2, s2);
+  if (threadIdx.x == 0) ratio[p] = s2[1] > 0 ? s2[0] / s2[1] : 0.0;
+}
+
+__global__ void __launch_bounds__(kSegThreads) k_seg_axpy(const SegChunk *ch, const SegInfo *seg, const double *ratio,
+                                                           const double *z, double *v) {
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  const double a = ratio[c.p];
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t k = seg_index(g, (int64_t)c.e0 + e);
+    v[k] -= a * z[k];
+  }
+}
+
 }  // namespace
 
 static_assert(kMaxRestartH <= 64, "orthogonalisation kernels handle at most 64 basis vectors");
@@ -247,6 +482,65 @@ void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, doub
     launch_mode<T, 1>(n, j, V, ldv, w, partial, st, cgs2, s);
   else
     launch_mode<T, 2>(n, j, V, ldv, w, partial, st, cgs2, s);
+}
+
+
+void launch_seg_sumsq(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *r, double *partial,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_sumsq, dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, r, partial);
+}
+void launch_seg_norm_finish(int np, const int32_t *chunk_ptr, int nchunks, const double *partial, GmresState *st,
+                            int *sdone, int which, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_norm_finish, dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, partial, st, sdone, which);
+}
+void launch_seg_scale(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *x, const GmresState *st,
+                      double *y, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_scale, dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, x, st, y);
+}
+void launch_seg_arnoldi(int mode, int nchunks, const SegChunk *ch, const SegInfo *seg, int np,
+                        const int32_t *chunk_ptr, int j, const double *V, int64_t ldv, double *w, double *partial,
+                        GmresState *st, int *sdone, int cgs2, hipStream_t s) {
+  const int nv = j + 1;
+#define HHO_SEG(NVC, M)                                                                                          \
+  hipLaunchKernelGGL((k_seg_orth<NVC, M>), dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, j, V, ldv, w, partial, \
+                     (const GmresState *)st, cgs2)
+#define HHO_SEG_NV(M)         \
+  if (nv <= 8)                \
+    HHO_SEG(8, M);            \
+  else if (nv <= 16)          \
+    HHO_SEG(16, M);           \
+  else if (nv <= 32)          \
+    HHO_SEG(32, M);           \
+  else                        \
+    HHO_SEG(64, M);
+  if (mode == 0) {
+    HHO_SEG_NV(0)
+    hipLaunchKernelGGL((k_seg_orth_finish<0>), dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, j,
+                       (const double *)partial, st, sdone, cgs2);
+  } else if (mode == 1) {
+    HHO_SEG_NV(1)
+    hipLaunchKernelGGL((k_seg_orth_finish<1>), dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, j,
+                       (const double *)partial, st, sdone, cgs2);
+  } else {
+    HHO_SEG_NV(2)
+    hipLaunchKernelGGL((k_seg_orth_finish<2>), dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, j,
+                       (const double *)partial, st, sdone, cgs2);
+  }
+#undef HHO_SEG_NV
+#undef HHO_SEG
+}
+void launch_seg_solve_ls(int np, GmresState *st, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_solve_ls, dim3((np + 63) / 64), dim3(64), 0, s, np, st);
+}
+void launch_seg_combine(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *Z, int64_t ldz,
+                        const GmresState *st, double *x, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_combine, dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, Z, ldz, st, x);
+}
+void launch_seg_project(int np, const int32_t *chunk_ptr, int nchunks, const SegChunk *ch, const SegInfo *seg,
+                        const double *z, double *v, double *partial, double *ratio, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_dot2, dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, z, (const double *)v, partial);
+  hipLaunchKernelGGL(k_seg_ratio, dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, (const double *)partial, ratio);
+  hipLaunchKernelGGL(k_seg_axpy, dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, (const double *)ratio, z, v);
 }
 
 #define HHO_INST(T)                                                                                              \

@@ -309,7 +309,10 @@ __global__ void __launch_bounds__(kBlock) k_norm_finish(int G, const double *par
     const double nn = nsum[0];
     const double beta = sqrt(nn);
     st->beta = beta;
-    if (which == 1) st->bnorm = beta;
+    if (which == 1) {
+      st->bnorm = beta;
+      st->its = 0;
+    }
     for (int i = 0; i <= kMaxRestartH; ++i) st->g[i] = 0;
     st->g[0] = beta;
     st->res = beta;

@@ -100,6 +100,7 @@ struct hho_problem {
   // host mirrors
   GmresState *h_st = nullptr;  // pinned
   double timings[16] = {0};
+  int64_t coarse_its = 0;  // coarse GMRES iterations of the current solve
   bool uploaded = false;
   // coarsest-level block preconditioner (smoothed aggregation)
   bool coarse_amg = false;
@@ -111,6 +112,20 @@ struct hho_problem {
   AmgDev amgd;
   std::vector<double> zhost;
   size_t lds_condense = 0, lds_patch = 0;
+  // batched problems (disjoint union): per-segment FGMRES state
+  int nseg = 0;
+  std::vector<SegInfo> hseg;
+  std::vector<SegChunk> hchunks;
+  std::vector<int32_t> hchunk_ptr;
+  std::vector<int64_t> seg_face_ptr, seg_cell_ptr;
+  SegInfo *dseg = nullptr;
+  SegChunk *dchunks = nullptr;
+  int32_t *dchunk_ptr = nullptr;
+  GmresState *sst = nullptr;
+  int *sdone = nullptr;
+  double *seg_partial = nullptr, *seg_ratio = nullptr;
+  std::vector<int> seg_its;
+  std::vector<double> seg_rel;
   // learned fine-level smoother
   MlpDims md{};
   bool learned_on = false, learned_ready = false;
@@ -263,6 +278,17 @@ static void plan(hho_problem *P, Arena &A) {
     }
     D.partial = A.take<double>(512);
     D.pw = A.take<double>(kAmgPowerSteps + 1);
+  }
+  // batched problems
+  if (P->nseg > 0) {
+    const int64_t G = (int64_t)P->hchunks.size();
+    P->dseg = A.take<SegInfo>(P->nseg);
+    P->dchunks = A.take<SegChunk>(G);
+    P->dchunk_ptr = A.take<int32_t>(P->nseg + 1);
+    P->sst = A.take<GmresState>(P->nseg);
+    P->sdone = A.take<int>(P->nseg);
+    P->seg_partial = A.take<double>(G * (kMaxRestartH + 2));
+    P->seg_ratio = A.take<double>(P->nseg);
   }
   // learned fine-level smoother
   if (P->opt.learned) {
@@ -439,16 +465,22 @@ static void init_levels(hho_problem *P) {
   P->border = P->mesh->has_neumann ? 0 : 1;
   const int64_t nd = LC.N + P->border;
   P->coarse_dense = (P->opt.coarse_mode == HHO_COARSE_DENSE) ||
-                    (P->opt.coarse_mode == HHO_COARSE_AUTO && nd <= 1024);
+                    (P->opt.coarse_mode == HHO_COARSE_AUTO && nd <= 1024 && !(P->nseg > 1 && P->border));
+  if (P->coarse_dense && P->nseg > 1 && P->border)
+    fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
   if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
   P->dense_n = nd;
   P->coarse_amg = !P->coarse_dense && (P->opt.coarse_mode == HHO_COARSE_AMG ||
                                        (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
   if (P->coarse_amg && LC.k != 0) fail(HHO_E_INVALID_ARG, "AMG coarse solver needs a coarsest degree of 0");
-  if (P->coarse_amg) {
-    amg_symbolic((int)P->mesh->nf, P->rowptr.data(), P->col.data(), kAmgCoarsest, &P->amgh);
-    if ((int)P->amgh.levels.size() > kMaxAmgLevels) fail(HHO_E_INVALID_ARG, "AMG hierarchy too deep");
-  }
+  P->amgh.levels.clear();  // built by amg_levels() once the problem's data are set
+}
+
+// symbolic smoothed-aggregation hierarchy of the coarsest level (topology only)
+static void amg_levels(hho_problem *P) {
+  if (!P->coarse_amg || !P->amgh.levels.empty()) return;
+  amg_symbolic((int)P->mesh->nf, P->rowptr.data(), P->col.data(), kAmgCoarsest, &P->amgh);
+  if ((int)P->amgh.levels.size() > kMaxAmgLevels) fail(HHO_E_INVALID_ARG, "AMG hierarchy too deep");
 }
 
 static void check_device_error(hho_problem *P, const char *what) {
@@ -483,6 +515,11 @@ static void device_upload(hho_problem *P) {
   if (P->border)
     for (int64_t c = 0; c < P->mesh->nc; ++c) P->zhost[L0.nface + c * L0.t] = P->zmean[c];
   h2d(P->zvec, P->zhost.data(), P->zhost.size() * 8);
+  if (P->nseg > 0) {
+    h2d(P->dseg, P->hseg.data(), P->hseg.size() * sizeof(SegInfo));
+    h2d(P->dchunks, P->hchunks.data(), P->hchunks.size() * sizeof(SegChunk));
+    h2d(P->dchunk_ptr, P->hchunk_ptr.data(), P->hchunk_ptr.size() * 4);
+  }
   if (P->coarse_amg) {
     h2d(P->d_fdiag, P->fdiag.data(), P->fdiag.size() * 4);
     for (int l = 0; l < P->amgd.nlev; ++l) {
@@ -668,7 +705,6 @@ static void set_rtol(hho_problem *P, GmresState *st, double rtol) {
 }
 
 // coarsest level: lev[Lc].v64.b -> lev[Lc].v64.w (FP64)
-static int64_t g_coarse_its = 0;
 static void coarse_solve(hho_problem *P) {
   hipStream_t s = P->stream;
   const int Lc = P->nlev - 1;
@@ -720,7 +756,7 @@ static void coarse_solve(hho_problem *P) {
     launch_scale<double>(n, P->cr, &st->inv_hnext, P->cV, s);
     read_state(P, st);
   }
-  g_coarse_its += its;
+  P->coarse_its += its;
 }
 
 // x = V-cycle(b) on level 0, b and x FP64 (device)
@@ -745,6 +781,125 @@ static void apply_vcycle(hho_problem *P, const double *b, double *x) {
 }
 
 // ------------------------------------------------------------ FGMRES
+// Flexible GMRES with one Krylov process per segment (problem) of a batch: the
+// V-cycle and the operator act on the whole disjoint union (block diagonal),
+// the Arnoldi reductions, Hessenberg columns, Givens rotations, restarts and
+// convergence tests are per segment.  Converged segments stop contributing.
+__global__ void k_seg_init(int np, GmresState *st, double rtol) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  st[p].rtol = rtol;
+  st[p].done = 0;
+  st[p].nan = 0;
+  st[p].its = 0;
+  st[p].j = 0;
+}
+
+static int read_seg_done(hho_problem *P) {
+  std::vector<int> d(P->nseg);
+  HIPCHK(hipMemcpyAsync(d.data(), P->sdone, P->nseg * sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  int nd = 0;
+  for (int x : d) nd += x != 0;
+  return nd;
+}
+
+static int fgmres_batched(hho_problem *P, double *x_out, int *iters, double *hist, int hist_cap,
+                          double *final_rel) {
+  hipStream_t s = P->stream;
+  const DLevel<double> D = dlev64(P, 0);
+  const int64_t n = D.N;
+  const int R = P->opt.restart, np = P->nseg, G = (int)P->hchunks.size();
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventRecord(e0, s));
+  P->coarse_its = 0;
+  launch_copy<double>(n, P->rhs, P->ob, s);
+  if (P->border)
+    launch_seg_project(np, P->dchunk_ptr, G, P->dchunks, P->dseg, P->zvec, P->ob, P->seg_partial, P->seg_ratio, s);
+  hipLaunchKernelGGL(k_seg_init, dim3((np + 63) / 64), dim3(64), 0, s, np, P->sst, P->opt.rtol);
+  launch_fill<double>(n, 0.0, P->ox, s);
+  launch_seg_sumsq(G, P->dchunks, P->dseg, P->ob, P->seg_partial, s);
+  launch_seg_norm_finish(np, P->dchunk_ptr, G, P->seg_partial, P->sst, P->sdone, 1, s);
+  launch_seg_scale(G, P->dchunks, P->dseg, P->ob, P->sst, P->oV, s);
+  int ndone = read_seg_done(P);
+  int its = 0, nvc = 0;
+  double vc_ms = 0;
+  std::vector<hipEvent_t> ev;  // V-cycle start/end pairs, read after the solve
+  if (hist && hist_cap > 0) hist[0] = 1.0;
+  while (ndone < np && its < P->opt.max_it) {
+    for (int j = 0; j < R && its < P->opt.max_it; ++j) {
+      double *vj = P->oV + (int64_t)j * n, *zj = P->oZ + (int64_t)j * n;
+      hipEvent_t va, vb;
+      HIPCHK(hipEventCreate(&va));
+      HIPCHK(hipEventCreate(&vb));
+      ev.push_back(va);
+      ev.push_back(vb);
+      HIPCHK(hipEventRecord(va, s));
+      apply_vcycle(P, vj, zj);
+      HIPCHK(hipEventRecord(vb, s));
+      ++nvc;
+      launch_spmv<double>(P->tp, D, zj, nullptr, nullptr, P->ow, s);
+      for (int mode = 0; mode < 3; ++mode)
+        launch_seg_arnoldi(mode, G, P->dchunks, P->dseg, np, P->dchunk_ptr, j, P->oV, n, P->ow, P->seg_partial,
+                           P->sst, P->sdone, 1, s);
+      launch_seg_scale(G, P->dchunks, P->dseg, P->ow, P->sst, P->oV + (int64_t)(j + 1) * n, s);
+      ++its;
+      ndone = read_seg_done(P);  // one small read per (batch-wide, heavy) iteration
+      if (ndone == np) break;
+    }
+    launch_seg_solve_ls(np, P->sst, s);
+    launch_seg_combine(G, P->dchunks, P->dseg, P->oZ, n, P->sst, P->ox, s);
+    // true residual per segment; restart the unconverged ones from it
+    launch_residual<double>(P->tp, D, P->ob, P->ox, P->or_, s);
+    launch_seg_sumsq(G, P->dchunks, P->dseg, P->or_, P->seg_partial, s);
+    launch_seg_norm_finish(np, P->dchunk_ptr, G, P->seg_partial, P->sst, P->sdone, 0, s);
+    launch_seg_scale(G, P->dchunks, P->dseg, P->or_, P->sst, P->oV, s);
+    ndone = read_seg_done(P);
+  }
+  if (P->border)
+    launch_seg_project(np, P->dchunk_ptr, G, P->dchunks, P->dseg, P->zvec, P->ox, P->seg_partial, P->seg_ratio, s);
+  if (x_out) launch_copy<double>(n, P->ox, x_out, s);
+  HIPCHK(hipEventRecord(e1, s));
+  // per-segment results
+  std::vector<GmresState> hs(np);
+  HIPCHK(hipMemcpyAsync(hs.data(), P->sst, np * sizeof(GmresState), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  P->seg_its.assign(np, 0);
+  P->seg_rel.assign(np, 0.0);
+  double worst = 0;
+  bool nan = false;
+  for (int q = 0; q < np; ++q) {
+    P->seg_its[q] = hs[q].its;
+    P->seg_rel[q] = hs[q].bnorm > 0 ? hs[q].beta / hs[q].bnorm : 0.0;
+    worst = std::max(worst, P->seg_rel[q]);
+    nan = nan || hs[q].nan;
+  }
+  if (nan) fail(HHO_E_BREAKDOWN, "batched FGMRES: non-finite value");
+  float ms;
+  HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+  for (size_t q = 0; q + 1 < ev.size(); q += 2) {
+    float vms;
+    HIPCHK(hipEventElapsedTime(&vms, ev[q], ev[q + 1]));
+    vc_ms += vms;
+  }
+  for (hipEvent_t e : ev) HIPCHK(hipEventDestroy(e));
+  P->timings[5] = ms;
+  P->timings[6] = vc_ms;
+  P->timings[7] = nvc;
+  P->timings[8] = (double)P->coarse_its;
+  HIPCHK(hipEventDestroy(e0));
+  HIPCHK(hipEventDestroy(e1));
+  check_device_error(P, "solve");
+  int its_max = 0;
+  for (int q = 0; q < np; ++q) its_max = std::max(its_max, P->seg_its[q]);
+  if (iters) *iters = its_max;
+  if (final_rel) *final_rel = worst;
+  if (hist && hist_cap > 1) hist[std::min(its_max, hist_cap - 1)] = worst;
+  return ndone == np ? HHO_OK : HHO_E_NOT_CONVERGED;
+}
+
 static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int hist_cap, double *final_rel) {
   hipStream_t s = P->stream;
   const DLevel<double> D = dlev64(P, 0);
@@ -755,7 +910,7 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   HIPCHK(hipEventRecord(e0, s));
-  g_coarse_its = 0;
+  P->coarse_its = 0;
   // b <- b - (b.z / z.z) z  (consistent right-hand side when the pressure is defined up to a constant)
   launch_copy<double>(n, P->rhs, P->ob, s);
   if (P->border) {
@@ -832,7 +987,7 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
   P->timings[7] = nvc;
   HIPCHK(hipEventDestroy(va));
   HIPCHK(hipEventDestroy(vb));
-  P->timings[8] = (double)g_coarse_its;
+  P->timings[8] = (double)P->coarse_its;
   HIPCHK(hipEventDestroy(e0));
   HIPCHK(hipEventDestroy(e1));
   check_device_error(P, "solve");
@@ -970,6 +1125,7 @@ int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_fi
   if (!p) hho::fail(HHO_E_INVALID_ARG, "set_data: NULL problem");
   int qdeg = 2 * p->k + 2 + std::max(0, p->opt.quad_extra);
   hho::build_local(p->mesh, p->k, p->eta, qdeg, f, gD, gN, ctx, &p->loc);
+  hho::amg_levels(p);
   p->have_data = true;
   p->setup_done = false;
   hho::Arena A;
@@ -1045,6 +1201,7 @@ static void need_setup(const hho_problem *p) {
 int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel) {
   ABI_BEGIN
   need_setup(p);
+  if (p->nseg > 0) return hho::fgmres_batched(p, x_dev, iters, hist, hist_cap, final_rel);
   return hho::fgmres(p, x_dev, iters, hist, hist_cap, final_rel);
   ABI_END
 }
@@ -1465,6 +1622,102 @@ int hho_learned_train(hho_problem *p, const float *X, const float *Tg, int64_t n
   }
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+// ------------------------------------------------------------ batches of problems
+int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int64_t *face_offsets,
+                          int64_t *cell_offsets) {
+  ABI_BEGIN
+  if (!descs || n < 1 || !out) hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: bad argument");
+  *out = nullptr;
+  const int dim = descs[0].dim;
+  std::vector<double> verts;
+  std::vector<int64_t> fptr(1, 0), fvtx, cptr(1, 0), cface;
+  std::vector<int8_t> fbc;
+  int64_t nv = 0, nf = 0, nc = 0;
+  for (int i = 0; i < n; ++i) {
+    const hho_mesh_desc &d = descs[i];
+    if (d.dim != dim) hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: meshes of different dimensions");
+    if (!d.verts || !d.face_ptr || !d.face_vtx || !d.cell_ptr || !d.cell_face || !d.face_bc || d.n_faces <= 0 ||
+        d.n_cells <= 0 || d.n_verts <= 0)
+      hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: empty or NULL member mesh");
+    if (face_offsets) face_offsets[i] = nf;
+    if (cell_offsets) cell_offsets[i] = nc;
+    verts.insert(verts.end(), d.verts, d.verts + d.n_verts * dim);
+    for (int64_t f = 0; f < d.n_faces; ++f) {
+      for (int64_t e = d.face_ptr[f]; e < d.face_ptr[f + 1]; ++e) fvtx.push_back(d.face_vtx[e] + nv);
+      fptr.push_back((int64_t)fvtx.size());
+    }
+    for (int64_t c = 0; c < d.n_cells; ++c) {
+      for (int64_t e = d.cell_ptr[c]; e < d.cell_ptr[c + 1]; ++e) cface.push_back(d.cell_face[e] + nf);
+      cptr.push_back((int64_t)cface.size());
+    }
+    fbc.insert(fbc.end(), d.face_bc, d.face_bc + d.n_faces);
+    nv += d.n_verts;
+    nf += d.n_faces;
+    nc += d.n_cells;
+  }
+  if (face_offsets) face_offsets[n] = nf;
+  if (cell_offsets) cell_offsets[n] = nc;
+  hho_mesh_desc u{dim, nv, verts.data(), nf, fptr.data(), fvtx.data(), nc, cptr.data(), cface.data(), fbc.data()};
+  auto m = std::make_unique<hho_mesh>();
+  hho::build_mesh(&u, m.get());
+  *out = m.release();
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_problem_set_segments(hho_problem *p, int n, const int64_t *face_ptr, const int64_t *cell_ptr) {
+  ABI_BEGIN
+  if (!p || n < 1 || !face_ptr || !cell_ptr) hho::fail(HHO_E_INVALID_ARG, "set_segments: bad argument");
+  if (p->have_data) hho::fail(HHO_E_INVALID_ARG, "set_segments: call before hho_problem_set_data");
+  const hho_mesh *m = p->mesh;
+  if (face_ptr[0] != 0 || cell_ptr[0] != 0 || face_ptr[n] != m->nf || cell_ptr[n] != m->nc)
+    hho::fail(HHO_E_INVALID_ARG, "set_segments: ranges must partition the faces and the cells");
+  std::vector<int32_t> fseg(m->nf, -1);
+  for (int i = 0; i < n; ++i) {
+    if (face_ptr[i + 1] <= face_ptr[i] || cell_ptr[i + 1] <= cell_ptr[i])
+      hho::fail(HHO_E_INVALID_ARG, "set_segments: empty or decreasing range");
+    for (int64_t f = face_ptr[i]; f < face_ptr[i + 1]; ++f) fseg[f] = i;
+  }
+  for (int i = 0; i < n; ++i)
+    for (int64_t c = cell_ptr[i]; c < cell_ptr[i + 1]; ++c)
+      for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e)
+        if (fseg[m->cface[e]] != i) hho::fail(HHO_E_INVALID_ARG, "set_segments: a cell and its faces lie in different segments");
+  p->nseg = n;
+  p->seg_face_ptr.assign(face_ptr, face_ptr + n + 1);
+  p->seg_cell_ptr.assign(cell_ptr, cell_ptr + n + 1);
+  hho::init_levels(p);  // the coarse solver choice depends on the segments
+  const hho::LevelInfo &L0 = p->lev[0];
+  const int64_t dp = (int64_t)p->d * L0.p;
+  p->hseg.resize(n);
+  p->hchunks.clear();
+  p->hchunk_ptr.assign(1, 0);
+  for (int i = 0; i < n; ++i) {
+    hho::SegInfo &g = p->hseg[i];
+    g.fo = face_ptr[i] * dp;
+    g.fl = (face_ptr[i + 1] - face_ptr[i]) * dp;
+    g.co = L0.nface + cell_ptr[i] * L0.t;
+    g.cl = (cell_ptr[i + 1] - cell_ptr[i]) * L0.t;
+    const int64_t len = g.fl + g.cl;
+    if (len > INT32_MAX) hho::fail(HHO_E_INVALID_ARG, "set_segments: segment too large");
+    for (int64_t e = 0; e < len; e += hho::kSegChunk)
+      p->hchunks.push_back({i, (int32_t)e, (int32_t)std::min<int64_t>(hho::kSegChunk, len - e), 0});
+    p->hchunk_ptr.push_back((int32_t)p->hchunks.size());
+  }
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_batch_results(const hho_problem *p, int *iters, double *rel, int n) {
+  ABI_BEGIN
+  if (!p || n != p->nseg || p->seg_its.empty()) hho::fail(HHO_E_INVALID_ARG, "batch_results: no batched solve");
+  for (int i = 0; i < n; ++i) {
+    if (iters) iters[i] = p->seg_its[i];
+    if (rel) rel[i] = p->seg_rel[i];
+  }
   return HHO_OK;
   ABI_END
 }

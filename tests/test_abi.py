@@ -99,3 +99,24 @@ def test_host_local_operators_match_oracle(mesh, k):
         assert np.abs(G["B"] - L.B).max() <= 1e-12 * np.abs(L.B).max()
         assert np.abs(G["rhs_u"] - L.rhs_u).max() <= 1e-12 * max(1.0, np.abs(L.rhs_u).max())
         assert np.abs(G["rhs_p"] - L.rhs_p).max() <= 1e-12 * max(1.0, np.abs(L.rhs_p).max())
+
+
+def test_union_mesh_and_segment_validation():
+    H, _ = _lib()
+    a, b = cartesian_quads(2), voronoi_lloyd(10, 1)
+    U, fo, co = H.Mesh.union([a, b])
+    assert list(fo) == [0, a.n_faces, a.n_faces + b.n_faces]
+    assert list(co) == [0, a.n_cells, a.n_cells + b.n_cells]
+    assert (U.n_faces, U.n_cells) == (fo[-1], co[-1])
+    P = H.Problem(U, 1, "v", coarse_mode="amg")
+    with pytest.raises(H.HHOError) as e:            # ranges that do not partition the faces
+        P.set_segments([0, 3, fo[-1] - 1], co)
+    assert e.value.code == -1
+    with pytest.raises(H.HHOError) as e:            # a cell whose faces lie in another member
+        P.set_segments([0, fo[1] + 1, fo[2]], co)
+    assert e.value.code == -1
+    P.set_segments(fo, co)
+    with pytest.raises(H.HHOError) as e:            # dense coarse solver with per-member null spaces
+        Q = H.Problem(U, 1, "v", coarse_mode="dense")
+        Q.set_segments(fo, co)
+    assert e.value.code == -1
