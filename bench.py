@@ -274,6 +274,8 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--learned", action="store_true",
                     help="train the learned fine-level smoother first (untimed) and solve with it")
+    ap.add_argument("--autotune", action="store_true",
+                    help="pick per-level launch shapes with the library's autotuner first (untimed)")
     ap.add_argument("--traffic-calibration", action="store_true",
                     help="run a plain 1 GiB device copy first (reference point for HBM byte counters)")
     args = ap.parse_args()
@@ -319,6 +321,11 @@ def main():
         P.setup()
         return P.solve()
 
+    tuned = None
+    if args.autotune:
+        P.setup()
+        tuned = P.autotune().tolist()
+        print(f"[bench] autotuned (operator block, patch threads) per level: {tuned}", file=sys.stderr, flush=True)
     learned_info = None
     if args.learned:
         learned_info = train_learned(P, n0)
@@ -382,6 +389,7 @@ def main():
         "phase_ms": {k: round(v, 3) for k, v in tm.items()},
         "roofline": roof,
         "learned": learned_info,
+        "autotune": tuned,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

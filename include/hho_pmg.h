@@ -232,6 +232,15 @@ int hho_vcycle_apply(hho_problem *p, const double *b_dev, double *x_dev);
  * 3 = one full V-cycle from level 0.  Inputs are fixed internal vectors. */
 int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_ms);
 
+/* Autotuner: times candidate launch shapes on the problem's own data (reps
+ * launches each) and keeps the fastest per level: threads per block of the
+ * operator kernels (64, 128, 256) and threads per cell of the smoother patch
+ * factorisation (64, 128, 256, 512).  choices (may be NULL) receives 2 ints per
+ * level (operator block, patch threads; 0 = level without a smoother).  The
+ * factorisations are recomputed while timing, so hho_setup must be called again
+ * before hho_solve. */
+int hho_autotune(hho_problem *p, int reps, int *choices);
+
 /* Phase timings of the last hho_setup / hho_solve in milliseconds (device
  * events): [0] condensation, [1] assembly, [2] levels, [3] smoother setup,
  * [4] coarse setup, [5] solve, [6] V-cycle total, [7] V-cycle count,

@@ -29,7 +29,7 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
            "hho_learned_collect", "hho_learned_grad", "hho_learned_train", "hho_mesh_create_union",
-           "hho_problem_set_segments", "hho_batch_results"]
+           "hho_problem_set_segments", "hho_batch_results", "hho_autotune"]
 
 
 class HHOError(RuntimeError):
@@ -98,6 +98,7 @@ def load():
         "hho_mesh_create_union": ([C.POINTER(MeshDesc), I32, C.POINTER(P), C.POINTER(I64), C.POINTER(I64)], I32),
         "hho_problem_set_segments": ([P, I32, C.POINTER(I64), C.POINTER(I64)], I32),
         "hho_batch_results": ([P, C.POINTER(C.c_int), D, I32], I32),
+        "hho_autotune": ([P, I32, C.POINTER(C.c_int)], I32),
         "hho_learned_dims": ([P, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(I64)], I32),
         "hho_learned_set_params": ([P, C.POINTER(C.c_float), I64], I32),
         "hho_learned_get_params": ([P, C.POINTER(C.c_float), I64], I32),
@@ -345,6 +346,13 @@ class Problem:
         x = self._vec(self.level_size(0))
         _check(load().hho_vcycle_apply(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
         return x
+
+    def autotune(self, reps=10):
+        """Fastest launch shapes per level (operator block, patch threads); re-runs setup."""
+        ch = np.zeros(2 * self.nlev, dtype=np.int32)
+        _check(load().hho_autotune(self.h, reps, ch.ctypes.data_as(C.POINTER(C.c_int))))
+        self.setup()
+        return ch.reshape(-1, 2)
 
     # ---- batches (problem on a union mesh)
     def set_segments(self, face_ptr, cell_ptr):

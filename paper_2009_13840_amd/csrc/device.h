@@ -46,6 +46,7 @@ struct DLevel {
   const T *sinv;  // v: [pairoff*p*p] s_P^{-1}; vp: [pairoff*(d p)^2] S_P^{-1}
   const T *xinv;  // v: [nc][t][t] pressure Schur inverse; vp: [cptr*d*p] g = S_P^{-1} b
   const T *sig;   // vp: [nc] 1 / (b^T S_P^{-1} b)
+  int block = 0;  // threads per block of the operator kernels (0: default), chosen by the autotuner
 };
 
 // ---- setup kernels (FP64)
@@ -58,9 +59,10 @@ void launch_assemble(const DTopo &tp, int cond, int nF, int64_t nnzb, const doub
                      const double *rhs_stage, double *rhs, hipStream_t s);
 void launch_extract(const DTopo &tp, int cond, int64_t nnzb, int p0, int t0, int p1, int t1, const double *bsr0,
                     const double *cpl0, const double *spp0, double *bsr1, double *cpl1, double *spp1, hipStream_t s);
+// threads: threads per cell of the LDS-resident variant (0: chosen from the patch size)
 void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *bsr, const double *cpl,
                         const double *spp, double *sinv, double *xinv, double *sig, double *scratch, int *err,
-                        hipStream_t s, size_t lds);
+                        hipStream_t s, size_t lds, int threads = 0);
 template <typename Tout, typename Tin>
 void launch_convert(const Tin *in, Tout *out, int64_t n, hipStream_t s);
 

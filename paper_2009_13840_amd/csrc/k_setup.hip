@@ -681,7 +681,7 @@ size_t patch_lds_packed_bytes(int d, int cond, int p, int t, int max_faces) {
 
 void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *bsr, const double *cpl,
                         const double *spp, double *sinv, double *xinv, double *sig, double *scratch, int *err,
-                        hipStream_t s, size_t lds) {
+                        hipStream_t s, size_t lds, int threads) {
   // LDS-resident factorisation when the packed patch fits the 160 KB of a CDNA4 CU
   const size_t packed = patch_lds_packed_bytes(tp.d, cond, p, t, tp.max_faces);
   const size_t budget = kMaxLdsBytes - 1024;  // leaves room for the kernel's static LDS
@@ -693,8 +693,11 @@ void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *b
         fail(HHO_E_DEVICE, "patch setup: cannot reserve 160 KB of LDS");
       attr_set = true;
     }
-    hipLaunchKernelGGL(k_patch_setup_lds, dim3(tp.nc), dim3(kPatchThreads), packed, s, tp, cond, p, t, bsr, cpl,
-                       spp, sinv, xinv, sig, err);
+    // threads per cell from the patch size (the kernel adapts to any multiple of 64 up to 512)
+    const int n = tp.max_faces * ((cond == 1) ? p : tp.d * p);
+    if (threads <= 0) threads = n <= 16 ? 64 : n <= 48 ? 128 : n <= 96 ? 256 : kPatchThreads;
+    hipLaunchKernelGGL(k_patch_setup_lds, dim3(tp.nc), dim3(threads), packed, s, tp, cond, p, t, bsr, cpl, spp, sinv,
+                       xinv, sig, err);
     return;
   }
   hipLaunchKernelGGL(k_patch_setup, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, p, t, bsr, cpl, spp, sinv, xinv,

@@ -146,14 +146,14 @@ bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T
   if (L.cond == 1) {
     if (L.t != TT) return false;
     const int64_t total = (int64_t)tp.nf * P + (int64_t)tp.nc * TT;
-    const int grid = (int)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(kBlock), 0, s, tp, L, x, xs1, xsum, b,
-                       y);
+    const int bs = L.block > 0 ? L.block : kBlock;
+    const int grid = (int)((total + bs - 1) / bs);
+    hipLaunchKernelGGL((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   } else {
     const int64_t total = (int64_t)tp.nf * D * P + tp.nc;
-    const int grid = (int)((total + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(kBlock), 0, s, tp, L, x, xs1, xsum, b,
-                       y);
+    const int bs = L.block > 0 ? L.block : kBlock;
+    const int grid = (int)((total + bs - 1) / bs);
+    hipLaunchKernelGGL((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   }
   return true;
 }

@@ -48,6 +48,7 @@ struct VBufs {  // V-cycle vectors of one level
 
 struct LevelInfo {
   int k, p, t, bs;
+  int spmv_block = 0, patch_threads = 0;  // autotuned launch shapes (0: defaults)
   int64_t nface, N;
   // FP64 operator and smoother
   double *bsr, *cpl, *spp, *sinv, *xinv, *sig;
@@ -337,6 +338,7 @@ static DLevel<double> dlev64(const hho_problem *P, int l) {
   D.sinv = L.sinv;
   D.xinv = L.xinv;
   D.sig = L.sig;
+  D.block = L.spmv_block;
   return D;
 }
 static DLevel<float> dlev32(const hho_problem *P, int l) {
@@ -353,6 +355,7 @@ static DLevel<float> dlev32(const hho_problem *P, int l) {
   D.sinv = L.sinv32;
   D.xinv = L.xinv32;
   D.sig = L.sig32;
+  D.block = L.spmv_block;
   return D;
 }
 template <typename T>
@@ -585,7 +588,7 @@ static void device_setup(hho_problem *P) {
     if (!L.sinv) continue;
     size_t lds = patch_lds_bytes(P->d, P->cond, L.p, L.t, P->max_faces);
     launch_patch_setup(P->tp, P->cond, L.p, L.t, L.bsr, L.cpl, L.spp, L.sinv, L.xinv, L.sig, P->stage, P->err + 1,
-                       s, lds);
+                       s, lds, L.patch_threads);
   }
   HIPCHK(hipEventRecord(ev[4], s));
   // coarse solver
@@ -1388,10 +1391,8 @@ int hho_upload(hho_problem *p) {
   ABI_END
 }
 
-int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_ms) {
-  ABI_BEGIN
-  need_setup(p);
-  if (level < 0 || level >= p->nlev || reps < 1 || !avg_ms) hho::fail(HHO_E_INVALID_ARG, "time_kernel: bad argument");
+static double time_kernel_ms(hho_problem *p, int kind, int level, int reps) {
+  if (level < 0 || level >= p->nlev || reps < 1) hho::fail(HHO_E_INVALID_ARG, "time_kernel: bad argument");
   hipStream_t s = p->stream;
   const hho::LevelInfo &L = p->lev[level];
   const bool mixed = p->opt.precision == HHO_PREC_FP32 && level < p->nlev - 1;
@@ -1445,7 +1446,64 @@ int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_m
   HIPCHK(hipEventDestroy(a));
   HIPCHK(hipEventDestroy(b));
   HIPCHK(hipGetLastError());
-  *avg_ms = ms / reps;
+  return ms / reps;
+}
+
+int hho_time_kernel(hho_problem *p, int kind, int level, int reps, double *avg_ms) {
+  ABI_BEGIN
+  need_setup(p);
+  if (!avg_ms) hho::fail(HHO_E_INVALID_ARG, "time_kernel: bad argument");
+  *avg_ms = time_kernel_ms(p, kind, level, reps);
+  return HHO_OK;
+  ABI_END
+}
+
+// Autotuner: the fastest launch shape of each level's operator kernel and patch
+// factorisation, measured on the problem's own data.
+int hho_autotune(hho_problem *p, int reps, int *choices) {
+  ABI_BEGIN
+  need_setup(p);
+  if (reps < 1) hho::fail(HHO_E_INVALID_ARG, "autotune: reps must be >= 1");
+  hipStream_t s = p->stream;
+  for (int l = 0; l < p->nlev; ++l) {
+    hho::LevelInfo &L = p->lev[l];
+    const int kind = L.sinv ? 2 : 0;
+    double best = 1e300;
+    int pick = 0;
+    for (int bs : {64, 128, 256}) {
+      L.spmv_block = bs;
+      const double ms = time_kernel_ms(p, kind, l, reps);
+      if (ms < best) best = ms, pick = bs;
+    }
+    L.spmv_block = pick;
+    int pick_patch = 0;
+    if (L.sinv) {
+      best = 1e300;
+      hipEvent_t a, b;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      for (int th : {64, 128, 256, 512}) {
+        const size_t lds = hho::patch_lds_bytes(p->d, p->cond, L.p, L.t, p->max_faces);
+        HIPCHK(hipEventRecord(a, s));
+        hho::launch_patch_setup(p->tp, p->cond, L.p, L.t, L.bsr, L.cpl, L.spp, L.sinv, L.xinv, L.sig, p->stage,
+                                p->err + 1, s, lds, th);
+        HIPCHK(hipEventRecord(b, s));
+        HIPCHK(hipEventSynchronize(b));
+        float ms;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        if (ms < best) best = ms, pick_patch = th;
+      }
+      HIPCHK(hipEventDestroy(a));
+      HIPCHK(hipEventDestroy(b));
+      L.patch_threads = pick_patch;
+    }
+    if (choices) {
+      choices[2 * l] = pick;
+      choices[2 * l + 1] = pick_patch;
+    }
+  }
+  p->setup_done = false;  // factors were recomputed while timing: run hho_setup again
+  HIPCHK(hipGetLastError());
   return HHO_OK;
   ABI_END
 }

@@ -158,3 +158,16 @@ def test_fgmres_solution(built, name, mk, k, cond, coarse):
     x = x.cpu().numpy()
     assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
     assert its <= 40 and hist[0] == 1.0
+
+
+def test_autotune_keeps_solution(built):
+    """The autotuner only changes launch shapes: the solve still reaches the direct solution."""
+    import oracle.solve as OS
+    name, mk, k, cond = CASES[2]
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="dense", rtol=1e-11)
+    ch = P.autotune(reps=3)
+    assert ch.shape == (len(O.S), 2)
+    assert set(ch[:, 0]) <= {64, 128, 256} and set(ch[:-1, 1]) <= {64, 128, 256, 512}
+    x, its, hist, rel, ok = P.solve()
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    assert ok and np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
