@@ -490,6 +490,187 @@ __global__ void __launch_bounds__(kPatchThreads) k_patch_setup_lds(DTopo tp, int
   if (tid == 0 && bad) atomicMax(err, T + 1);
 }
 
+// Patch inverse by the sweep operator (Gauss-Jordan elimination in place on a
+// symmetric positive definite matrix, pivots in order, no pivoting): sweeping
+// pivot k maps a_kk -> -1/a_kk, a_ik -> a_ik/a_kk, a_kj -> a_kj/a_kk and
+// a_ij -> a_ij - a_ik a_kj / a_kk; after all pivots the matrix is -S_P^{-1}.
+// The pivots are the diagonal entries of the successive Schur complements,
+// positive for an SPD patch.  The matrix lives in registers: thread t owns the
+// TILE x TILE tile (t / nt, t % nt) (nt = ceil(n / TILE) tiles a side); the
+// pivot column is broadcast through LDS (two barriers per pivot).  Padding rows
+// and columns (n..nt*TILE) never couple to the patch.
+template <int TILE>
+__global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p, int t, const double *bsr,
+                                                      const double *cpl, const double *spp, double *sinv,
+                                                      double *xinv, double *sig, int *err) {
+  extern __shared__ double lds[];
+  const int T = blockIdx.x;
+  const int d = tp.d;
+  const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+  const int bs = (cond == 1) ? p : d * p;
+  const int n = nfc * bs;
+  const int nt = (n + TILE - 1) / TILE;
+  const int np = nt * TILE;
+  const int tid = threadIdx.x;
+  const int tr = tid / nt, tc = tid % nt;
+  const bool own = tr < nt;
+  const int r0 = tr * TILE, c0 = tc * TILE;
+  double *cb = lds;                        // [np] pivot column
+  double *ext = cb + (np > 16 ? np : 16);  // post-processing space
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  const int32_t *pb = tp.pairblk + tp.pairoff[T];
+  double a[TILE][TILE];
+#pragma unroll
+  for (int q = 0; q < TILE; ++q)
+#pragma unroll
+    for (int w = 0; w < TILE; ++w) {
+      const int i = r0 + q, j = c0 + w;
+      double v = (i == j) ? 1.0 : 0.0;  // identity on the padding
+      if (own && i < n && j < n) {
+        const int64_t blk = pb[(i / bs) * nfc + (j / bs)];
+        v = bsr[blk * bs * bs + (int64_t)(i % bs) * bs + (j % bs)];
+      }
+      a[q][w] = v;
+    }
+  for (int k = 0; k < n; ++k) {  // scalar pivots; the pivot column goes through LDS
+    const int kt = k / TILE, kw = k % TILE;
+    if (own && tc == kt) {
+#pragma unroll
+      for (int q = 0; q < TILE; ++q)
+#pragma unroll
+        for (int w = 0; w < TILE; ++w)
+          if (w == kw) cb[r0 + q] = a[q][w];
+    }
+    __syncthreads();
+    double dk = cb[k];
+    if (!(dk > 0.0)) {
+      if (tid == 0) bad = 1;
+      dk = 1.0;
+    }
+    const double inv = 1.0 / dk;
+    if (own) {
+      double ci[TILE], cj[TILE];
+#pragma unroll
+      for (int q = 0; q < TILE; ++q) {
+        ci[q] = cb[r0 + q] * inv;
+        cj[q] = cb[c0 + q];
+      }
+      // every entry: a_ij -= (a_ik / a_kk) a_kj (one FMA); the pivot row and
+      // column, held by one tile row and one tile column, are fixed up after
+#pragma unroll
+      for (int q = 0; q < TILE; ++q)
+#pragma unroll
+        for (int w = 0; w < TILE; ++w) a[q][w] = fma(-ci[q], cj[w], a[q][w]);
+      if (tr == kt) {
+#pragma unroll
+        for (int q = 0; q < TILE; ++q)
+#pragma unroll
+          for (int w = 0; w < TILE; ++w)
+            if (q == kw) a[q][w] = cj[w] * inv;
+      }
+      if (tc == kt) {
+#pragma unroll
+        for (int q = 0; q < TILE; ++q)
+#pragma unroll
+          for (int w = 0; w < TILE; ++w)
+            if (w == kw) a[q][w] = (tr == kt && q == kw) ? -inv : ci[q];
+      }
+    }
+    __syncthreads();
+  }
+  // S_P^{-1} = -a
+  double *Si = sinv + tp.pairoff[T] * (int64_t)bs * bs;
+  if (own) {
+#pragma unroll
+    for (int q = 0; q < TILE; ++q)
+#pragma unroll
+      for (int w = 0; w < TILE; ++w) {
+        const int i = r0 + q, j = c0 + w;
+        if (i < n && j < n) Si[(int64_t)i * n + j] = -a[q][w];
+      }
+  }
+  const int64_t c0e = tp.cptr[T];
+  if (cond == 1) {
+    // the inverse in LDS (full square), then U = (s^{-1} (x) I) C and the pressure Schur complement
+    double *Sl = ext;                        // [n][n]
+    double *U = Sl + n * n;                  // [d*n][t]
+    double *X = U + (int64_t)d * n * t;      // [t][t]
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < TILE; ++q)
+#pragma unroll
+        for (int w = 0; w < TILE; ++w) {
+          const int i = r0 + q, j = c0 + w;
+          if (i < n && j < n) Sl[i * n + j] = -a[q][w];
+        }
+    }
+    __syncthreads();
+    const double *C = cpl + c0e * d * p * t;
+    for (int idx = tid; idx < d * n * t; idx += blockDim.x) {
+      const int row = idx / t, q = idx % t;
+      const int fi = row / (d * p), c = (row / p) % d, r = row % p;
+      const int i = fi * p + r;
+      double v = 0;
+      for (int fj = 0; fj < nfc; ++fj)
+        for (int r2 = 0; r2 < p; ++r2) v += Sl[i * n + fj * p + r2] * C[((fj * d + c) * p + r2) * t + q];
+      U[idx] = v;
+    }
+    __syncthreads();
+    for (int idx = tid; idx < t * t; idx += blockDim.x) {
+      const int q = idx / t, q2 = idx % t;
+      double v = -spp[(int64_t)T * t * t + idx];
+      for (int row = 0; row < d * n; ++row) v += C[row * t + q] * U[row * t + q2];
+      X[idx] = v;  // -X is SPD
+    }
+    __syncthreads();
+    blk_chol(X, t, t, &bad);
+    __syncthreads();
+    double *Xi = xinv + (int64_t)T * t * t;
+    blk_chol_inverse(X, t, t, Xi, t);
+    for (int idx = tid; idx < t * t; idx += blockDim.x) Xi[idx] = -Xi[idx];
+  } else {
+    // g = S_P^{-1} b: per-tile partial row sums, then summed over tile columns in order
+    const double *b = cpl + c0e * d * p;
+    double *part = ext;                      // [nt][np]
+    double *g = xinv + c0e * d * p;
+    if (own) {
+#pragma unroll
+      for (int q = 0; q < TILE; ++q) {
+        double sacc = 0;
+#pragma unroll
+        for (int w = 0; w < TILE; ++w)
+          if (c0 + w < n) sacc -= a[q][w] * b[c0 + w];
+        part[tc * np + r0 + q] = sacc;
+      }
+    }
+    __syncthreads();
+    double dot = 0;
+    for (int i = tid; i < n; i += blockDim.x) {
+      double gi = 0;
+      for (int c = 0; c < nt; ++c) gi += part[c * np + i];
+      g[i] = gi;
+      dot += b[i] * gi;
+    }
+    __syncthreads();
+    const double sdot = block_sum(dot, cb);
+    if (tid == 0) {
+      if (!(sdot > 0.0)) bad = 1;
+      sig[T] = (sdot > 0.0) ? 1.0 / sdot : 0.0;
+    }
+  }
+  __syncthreads();
+  if (tid == 0 && bad) atomicMax(err, T + 1);
+}
+
+size_t patch_sweep_lds_bytes(int d, int cond, int p, int t, int max_faces, int tile) {
+  const int64_t n = (int64_t)max_faces * ((cond == 1) ? p : d * p);
+  const int64_t nt = (n + tile - 1) / tile;
+  int64_t w = std::max<int64_t>(nt * tile, 16);
+  w += (cond == 1) ? n * n + (int64_t)d * n * t + (int64_t)t * t : nt * nt * tile;
+  return (size_t)w * sizeof(double);
+}
+
 template <typename Tout, typename Tin>
 __global__ void k_convert(const Tin *in, Tout *out, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
@@ -682,6 +863,40 @@ size_t patch_lds_packed_bytes(int d, int cond, int p, int t, int max_faces) {
 void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *bsr, const double *cpl,
                         const double *spp, double *sinv, double *xinv, double *sig, double *scratch, int *err,
                         hipStream_t s, size_t lds, int threads) {
+  // register-resident sweep when a tile of at most 7 x 7 per thread covers the patch
+  {
+    const int n = tp.max_faces * ((cond == 1) ? p : tp.d * p);
+    const int tile = (n + 31) / 32;  // 32 x 32 tiles at most (1024 threads)
+    const size_t lds_sw = tile <= 7 ? patch_sweep_lds_bytes(tp.d, cond, p, t, tp.max_faces, tile) : 0;
+    if (tile <= 7 && lds_sw <= kMaxLdsBytes - 1024 && threads == 0) {
+      const int nt = (n + tile - 1) / tile;
+      const int th = std::max(64, (nt * nt + 63) / 64 * 64);
+      static bool attr[8] = {false, false, false, false, false, false, false, false};
+#define HHO_SWEEP(TL)                                                                                            \
+  case TL:                                                                                                       \
+    if (!attr[TL]) {                                                                                             \
+      if (hipFuncSetAttribute((const void *)k_patch_sweep<TL>, hipFuncAttributeMaxDynamicSharedMemorySize,       \
+                              (int)(kMaxLdsBytes - 1024)) != hipSuccess)                                         \
+        fail(HHO_E_DEVICE, "patch setup: cannot reserve LDS");                                                   \
+      attr[TL] = true;                                                                                           \
+    }                                                                                                            \
+    hipLaunchKernelGGL((k_patch_sweep<TL>), dim3(tp.nc), dim3(th), lds_sw, s, tp, cond, p, t, bsr, cpl, spp, sinv, \
+                       xinv, sig, err);                                                                          \
+    return;
+      switch (tile) {
+        HHO_SWEEP(1)
+        HHO_SWEEP(2)
+        HHO_SWEEP(3)
+        HHO_SWEEP(4)
+        HHO_SWEEP(5)
+        HHO_SWEEP(6)
+        HHO_SWEEP(7)
+        default:
+          break;
+      }
+#undef HHO_SWEEP
+    }
+  }
   // LDS-resident factorisation when the packed patch fits the 160 KB of a CDNA4 CU
   const size_t packed = patch_lds_packed_bytes(tp.d, cond, p, t, tp.max_faces);
   const size_t budget = kMaxLdsBytes - 1024;  // leaves room for the kernel's static LDS

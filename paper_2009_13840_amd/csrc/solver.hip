@@ -1482,7 +1482,7 @@ int hho_autotune(hho_problem *p, int reps, int *choices) {
       hipEvent_t a, b;
       HIPCHK(hipEventCreate(&a));
       HIPCHK(hipEventCreate(&b));
-      for (int th : {64, 128, 256, 512}) {
+      for (int th : {0, 64, 128, 256, 512}) {  // 0: register sweep where it applies
         const size_t lds = hho::patch_lds_bytes(p->d, p->cond, L.p, L.t, p->max_faces);
         HIPCHK(hipEventRecord(a, s));
         hho::launch_patch_setup(p->tp, p->cond, L.p, L.t, L.bsr, L.cpl, L.spp, L.sinv, L.xinv, L.sig, p->stage,
