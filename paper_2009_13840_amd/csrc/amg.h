@@ -26,6 +26,7 @@ struct AmgHostLevel {
   std::vector<int32_t> ptp, pti, pte;    // P^T by coarse row: fine row, P entry
   std::vector<int32_t> brp, bci;         // B = A P pattern
   std::vector<int32_t> bpp, bpa, bpb;    // B pairs (A entry, P entry)
+  std::vector<int32_t> btp, bti, bte;    // B^T by coarse row: fine row, B entry
   std::vector<int32_t> cpp, cpa, cpb;    // next A pairs (P entry, B entry)
 };
 

@@ -150,6 +150,21 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
       L.brp.push_back((int32_t)L.bci.size());
     }
     L.bpp.push_back((int32_t)L.bpa.size());
+    // B^T (by coarse column): rows i and B entry indices, rows ascending
+    L.btp.assign(na + 1, 0);
+    for (size_t e = 0; e < L.bci.size(); ++e) ++L.btp[L.bci[e] + 1];
+    for (int I = 0; I < na; ++I) L.btp[I + 1] += L.btp[I];
+    L.bti.resize(L.bci.size());
+    L.bte.resize(L.bci.size());
+    {
+      std::vector<int32_t> fill(L.btp.begin(), L.btp.end() - 1);
+      for (int i = 0; i < n; ++i)
+        for (int e = L.brp[i]; e < L.brp[i + 1]; ++e) {
+          const int32_t q = fill[L.bci[e]]++;
+          L.bti[q] = i;
+          L.bte[q] = e;
+        }
+    }
     // A_next = P^T B : pattern + pairs (P entry, B entry)
     std::vector<int32_t> nrp(1, 0), nci;
     for (int I = 0; I < na; ++I) {

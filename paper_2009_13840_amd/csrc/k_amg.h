@@ -21,7 +21,10 @@ struct AmgDevLevel {
   double *pval = nullptr;
   const int32_t *ptp = nullptr, *pti = nullptr, *pte = nullptr;
   const int32_t *bpp = nullptr, *bpa = nullptr, *bpb = nullptr;
+  const int32_t *brp = nullptr, *bci = nullptr;              // B = A P by rows
+  const int32_t *btp = nullptr, *bti = nullptr, *bte = nullptr;  // B^T by coarse rows
   double *bval = nullptr;
+  double *ptval = nullptr, *btval = nullptr;  // P and B values in P^T / B^T order
   const int32_t *cpp = nullptr, *cpa = nullptr, *cpb = nullptr;
   double *x = nullptr, *r = nullptr, *res = nullptr, *tmp = nullptr;  // [n][d]
 };

@@ -156,15 +156,13 @@ __device__ inline double group_sum(double v) {
   return v;
 }
 
-// G lanes per row, all d (<= 3) components at once.
-// MODE 0: xout = xin + w D^{-1} (r - A xin); xin == null means xin = w D^{-1} r (a
-//         first sweep from zero folded in), so one launch gives two sweeps.
-// MODE 1: res = r - A xin (xin == null: xin = w D^{-1} r) and, if xout is set,
-//         xout = xin: the residual after the sweep(s) already taken.
-template <int MODE, int G>
+// Damped-Jacobi sweep xout = xin + w D^{-1} (r - A xin), G lanes per row, all d
+// (<= 3) components at once; xin == null means xin = w D^{-1} r (a first sweep
+// from zero folded in), so one launch gives two sweeps.
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_amg_rows(int n, int d, const int32_t *rp, const int32_t *ci,
                                                       const double *val, const double *dinv, const double *lam,
-                                                      const double *r, const double *xin, double *xout, double *res) {
+                                                      const double *r, const double *xin, double *xout) {
   const double w = kAmgOmegaJac / lam[0];
   const int lane = threadIdx.x % G;
   const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
@@ -201,32 +199,64 @@ __global__ void __launch_bounds__(kBlock) k_amg_rows(int n, int d, const int32_t
       y[c] = xin ? xin[i * d + c] : si * rc;
       q[c] = rc - q[c];
     }
-    for (int c = 0; c < d; ++c) {
-      if (MODE == 0) {
-        xout[i * d + c] = y[c] + si * q[c];
-      } else {
-        res[i * d + c] = q[c];
-        if (xout) xout[i * d + c] = y[c];
-      }
+    for (int c = 0; c < d; ++c) xout[i * d + c] = y[c] + si * q[c];
+  }
+}
+
+// dst[k] = src[idx[k]] (values of a matrix in the order of its transpose)
+__global__ void __launch_bounds__(kBlock) k_amg_gather(int64_t n, const int32_t *idx, const double *src,
+                                                        double *dst) {
+  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k < n) dst[k] = src[idx[k]];
+}
+
+// s += sign * sum over k in [beg, end) of v[k] * x(row[k]), the wavefront's lanes
+// taking every 64th entry, four entries in flight per lane.  With scale != null
+// the vector is x(i) = w scale[i] y[i] (a sweep from zero), else x(i) = y[i].
+template <int SIGN>
+__device__ inline void wave_gather(int beg, int end, const int32_t *row, const double *v, const double *y,
+                                   const double *scale, double w, int d, double &s0, double &s1, double &s2) {
+  const int lane = threadIdx.x % kWave;
+  for (int k = beg + lane; k < end; k += 4 * kWave) {
+    int ii[4];
+    double vv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int kk = k + u * kWave;
+      const bool in = kk < end;
+      ii[u] = in ? row[kk] : 0;
+      vv[u] = in ? v[kk] : 0.0;
+    }
+    if (scale) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) vv[u] *= w * scale[ii[u]];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double *yi = y + (int64_t)ii[u] * d;
+      s0 += SIGN * vv[u] * yi[0];
+      if (d > 1) s1 += SIGN * vv[u] * yi[1];
+      if (d > 2) s2 += SIGN * vv[u] * yi[2];
     }
   }
 }
 
-// rc = P^T res; one wavefront per coarse row, lanes split the row's entries
+// rc = P^T r - B^T x with B = A P: since A is symmetric, B^T x = P^T A x, so this
+// is the restriction of the residual r - A x after pre-smoothing, with no pass
+// that forms that residual.  x == null stands for x = w D^{-1} r (one sweep from
+// zero).  One wavefront per coarse row; lanes split the P^T and B^T entries.
 __global__ void __launch_bounds__(kBlock) k_amg_restrict(int nc, int d, const int32_t *ptp, const int32_t *pti,
-                                                          const int32_t *pte, const double *pval, const double *res,
-                                                          double *rc) {
+                                                          const double *ptval, const int32_t *btp,
+                                                          const int32_t *bti, const double *btval,
+                                                          const double *dinv, const double *lam, const double *r,
+                                                          const double *x, double *rc) {
+  const double w = kAmgOmegaJac / lam[0];
   const int lane = threadIdx.x % kWave;
   const int64_t nwave = (int64_t)gridDim.x * (blockDim.x / kWave);
   for (int64_t I = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; I < nc; I += nwave) {
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int k = ptp[I] + lane; k < ptp[I + 1]; k += kWave) {
-      const double pv = pval[pte[k]];
-      const double *rr = res + (int64_t)pti[k] * d;
-      s0 += pv * rr[0];
-      if (d > 1) s1 += pv * rr[1];
-      if (d > 2) s2 += pv * rr[2];
-    }
+    wave_gather<1>(ptp[I], ptp[I + 1], pti, ptval, r, nullptr, 0.0, d, s0, s1, s2);
+    wave_gather<-1>(btp[I], btp[I + 1], bti, btval, x ? x : r, x ? nullptr : dinv, w, d, s0, s1, s2);
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
@@ -238,28 +268,61 @@ __global__ void __launch_bounds__(kBlock) k_amg_restrict(int nc, int d, const in
   }
 }
 
-// xout = xin + P xc (xout may alias xin: every entry is read and written by one lane)
+// Prolongation and the first post-smoothing sweep in one pass: with
+// c = xin + P xc, xout = c + w D^{-1} (r - A c) is evaluated as
+// xin + P xc + w D^{-1} (r - A xin - B xc) (B = A P), so no row needs the
+// corrected values of its neighbours.  xin == null stands for xin = w D^{-1} r.
+// G lanes per row; xout must not alias xin.
 template <int G>
-__global__ void __launch_bounds__(kBlock) k_amg_prolong(int n, int d, const int32_t *prp, const int32_t *pci,
-                                                         const double *pval, const double *xc, const double *xin,
-                                                         double *xout) {
+__global__ void __launch_bounds__(kBlock) k_amg_prolong_sweep(int n, int d, const int32_t *rp, const int32_t *ci,
+                                                               const double *val, const double *dinv,
+                                                               const double *lam, const int32_t *prp,
+                                                               const int32_t *pci, const double *pval,
+                                                               const int32_t *brp, const int32_t *bci,
+                                                               const double *bval, const double *xc,
+                                                               const double *r, const double *xin, double *xout) {
+  const double w = kAmgOmegaJac / lam[0];
   const int lane = threadIdx.x % G;
   const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
   for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; i < n; i += ngroups) {
-    double s0 = 0, s1 = 0, s2 = 0;
+    double q0 = 0, q1 = 0, q2 = 0;  // (A xin + B xc)_i
+    double p0 = 0, p1 = 0, p2 = 0;  // (P xc)_i
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += G) {
+      const int j = ci[e];
+      double a = val[e];
+      const double *xj = xin ? xin + (int64_t)j * d : r + (int64_t)j * d;
+      if (!xin) a *= w * dinv[j];
+      q0 += a * xj[0];
+      if (d > 1) q1 += a * xj[1];
+      if (d > 2) q2 += a * xj[2];
+    }
+    for (int e = brp[i] + lane; e < brp[i + 1]; e += G) {
+      const double bv = bval[e];
+      const double *xj = xc + (int64_t)bci[e] * d;
+      q0 += bv * xj[0];
+      if (d > 1) q1 += bv * xj[1];
+      if (d > 2) q2 += bv * xj[2];
+    }
     for (int e = prp[i] + lane; e < prp[i + 1]; e += G) {
       const double pv = pval[e];
       const double *xj = xc + (int64_t)pci[e] * d;
-      s0 += pv * xj[0];
-      if (d > 1) s1 += pv * xj[1];
-      if (d > 2) s2 += pv * xj[2];
+      p0 += pv * xj[0];
+      if (d > 1) p1 += pv * xj[1];
+      if (d > 2) p2 += pv * xj[2];
     }
-    s0 = group_sum<G>(s0);
-    s1 = group_sum<G>(s1);
-    s2 = group_sum<G>(s2);
+    q0 = group_sum<G>(q0);
+    q1 = group_sum<G>(q1);
+    q2 = group_sum<G>(q2);
+    p0 = group_sum<G>(p0);
+    p1 = group_sum<G>(p1);
+    p2 = group_sum<G>(p2);
     if (lane != 0) continue;
-    const double s[3] = {s0, s1, s2};
-    for (int c = 0; c < d; ++c) xout[i * d + c] = xin[i * d + c] + s[c];
+    const double si = w * dinv[i], q[3] = {q0, q1, q2}, pp[3] = {p0, p1, p2};
+    for (int c = 0; c < d; ++c) {
+      const double rc = r[i * d + c];
+      const double y = xin ? xin[i * d + c] : si * rc;
+      xout[i * d + c] = y + pp[c] + si * (rc - q[c]);
+    }
   }
 }
 
@@ -321,6 +384,10 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
     const AmgDevLevel &N = A.lev[l + 1];
     hipLaunchKernelGGL(k_amg_pairs, dim3(grid_for(N.nnz)), dim3(kBlock), 0, s, N.nnz, L.cpp, L.cpa, L.cpb,
                        (const double *)L.pval, (const double *)L.bval, N.val);
+    hipLaunchKernelGGL(k_amg_gather, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.pte,
+                       (const double *)L.pval, L.ptval);
+    hipLaunchKernelGGL(k_amg_gather, dim3(grid_for(L.nbe)), dim3(kBlock), 0, s, L.nbe, L.bte,
+                       (const double *)L.bval, L.btval);
   }
 }
 
@@ -331,29 +398,32 @@ void bp_setup(const DTopo &tp, int cond, const int32_t *fdiag, const double *bsr
 
 // V-cycle on level l: x = AMG_l(r); x, r are [n_l][d].  nu damped-Jacobi sweeps
 // before and after the coarse correction (nu = 1 or 2).
-template <int MODE>
 static void rows(int G, int n, int d, const AmgDevLevel &L, const double *r, const double *xin, double *xout,
-                 double *res, hipStream_t s) {
+                 hipStream_t s) {
   const dim3 b(kBlock), g(grid_for((int64_t)n * G));
   const double *val = L.val, *dinv = L.dinv, *lam = L.lam;
   switch (G) {
-    case 64: hipLaunchKernelGGL((k_amg_rows<MODE, 64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
-    case 16: hipLaunchKernelGGL((k_amg_rows<MODE, 16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
-    case 4: hipLaunchKernelGGL((k_amg_rows<MODE, 4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
-    default: hipLaunchKernelGGL((k_amg_rows<MODE, 1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, res); break;
+    case 64: hipLaunchKernelGGL((k_amg_rows<64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
+    case 16: hipLaunchKernelGGL((k_amg_rows<16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
+    case 4: hipLaunchKernelGGL((k_amg_rows<4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
+    default: hipLaunchKernelGGL((k_amg_rows<1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
   }
 }
 
-static void prolong(int G, const AmgDevLevel &L, int d, const double *xc, const double *xin, double *xout,
-                    hipStream_t s) {
+static void prolong_sweep(int G, const AmgDevLevel &L, int d, const double *xc, const double *r, const double *xin,
+                          double *xout, hipStream_t s) {
   const dim3 b(kBlock), g(grid_for((int64_t)L.n * G));
-  const double *pv = L.pval;
+#define HHO_PS(GG)                                                                                             \
+  hipLaunchKernelGGL((k_amg_prolong_sweep<GG>), g, b, 0, s, L.n, d, L.rp, L.ci, (const double *)L.val,           \
+                     (const double *)L.dinv, (const double *)L.lam, L.prp, L.pci, (const double *)L.pval, L.brp, \
+                     L.bci, (const double *)L.bval, xc, r, xin, xout)
   switch (G) {
-    case 64: hipLaunchKernelGGL((k_amg_prolong<64>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
-    case 16: hipLaunchKernelGGL((k_amg_prolong<16>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
-    case 4: hipLaunchKernelGGL((k_amg_prolong<4>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
-    default: hipLaunchKernelGGL((k_amg_prolong<1>), g, b, 0, s, L.n, d, L.prp, L.pci, pv, xc, xin, xout); break;
+    case 64: HHO_PS(64); break;
+    case 16: HHO_PS(16); break;
+    case 4: HHO_PS(4); break;
+    default: HHO_PS(1); break;
   }
+#undef HHO_PS
 }
 
 // lanes per row for a given average row length
@@ -363,7 +433,6 @@ int amg_group(double avg) { return avg >= 48 ? 64 : avg >= 12 ? 16 : avg >= 3 ? 
 // before and after the coarse correction (nu = 1 or 2).
 static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, double *x, hipStream_t s) {
   const AmgDevLevel &L = A.lev[l];
-  const int64_t nd = (int64_t)L.n * d;
   if (l == A.nlev - 1) {
     if (A.ainv) {
       hipLaunchKernelGGL(k_amg_dense, dim3(grid_for((int64_t)L.n * kWave)), dim3(kBlock), 0, s, L.n, d,
@@ -374,35 +443,30 @@ static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, doubl
     const int GA = amg_group((double)L.nnz / L.n);
     constexpr int rest = kAmgCoarseSweeps - 2;
     double *cur = (rest % 2 == 1) ? L.tmp : x;
-    rows<0>(GA, L.n, d, L, r, nullptr, cur, nullptr, s);
+    rows(GA, L.n, d, L, r, nullptr, cur, s);
     for (int it = 0; it < rest; ++it) {
       double *nxt = (cur == x) ? L.tmp : x;
-      rows<0>(GA, L.n, d, L, r, cur, nxt, nullptr, s);
+      rows(GA, L.n, d, L, r, cur, nxt, s);
       cur = nxt;
     }
     return;
   }
-  (void)nd;
-  const int GA = amg_group((double)L.nnz / L.n), GP = amg_group((double)L.npe / L.n);
-  // pre-smoothing from zero and the residual after it
-  if (nu == 1) {
-    rows<1>(GA, L.n, d, L, r, nullptr, x, L.res, s);
-  } else {
-    rows<0>(GA, L.n, d, L, r, nullptr, x, nullptr, s);
-    rows<1>(GA, L.n, d, L, r, x, nullptr, L.res, s);
-  }
   const AmgDevLevel &N = A.lev[l + 1];
-  hipLaunchKernelGGL(k_amg_restrict, dim3(grid_for((int64_t)N.n * kWave)), dim3(kBlock), 0, s, N.n, d, L.ptp, L.pti,
-                     L.pte, (const double *)L.pval, (const double *)L.res, N.r);
-  vcycle(A, l + 1, d, nu, N.r, N.x, s);
-  // prolongation, then nu post-smoothing sweeps alternating between tmp and x, ending in x
-  double *cur = (nu % 2 == 1) ? L.tmp : x;
-  prolong(GP, L, d, N.x, x, cur, s);
-  for (int it = 0; it < nu; ++it) {
-    double *nxt = (cur == x) ? L.tmp : x;
-    rows<0>(GA, L.n, d, L, r, cur, nxt, nullptr, s);
-    cur = nxt;
+  const int GA = amg_group((double)L.nnz / L.n), GS = amg_group((double)std::max(L.nnz, L.nbe) / L.n);
+  // pre-smoothing from zero: for nu = 2 one launch takes both sweeps; for nu = 1
+  // the single sweep x = w D^{-1} r is formed where it is used
+  const double *xpre = nullptr;
+  if (nu == 2) {
+    rows(GA, L.n, d, L, r, nullptr, x, s);
+    xpre = x;
   }
+  hipLaunchKernelGGL(k_amg_restrict, dim3(grid_for((int64_t)N.n * kWave)), dim3(kBlock), 0, s, N.n, d, L.ptp, L.pti,
+                     (const double *)L.ptval, L.btp, L.bti, (const double *)L.btval, (const double *)L.dinv,
+                     (const double *)L.lam, r, xpre, N.r);
+  vcycle(A, l + 1, d, nu, N.r, N.x, s);
+  // prolongation with the first post-sweep (nu = 2: into tmp, then the second sweep into x)
+  prolong_sweep(GS, L, d, N.x, r, xpre, nu == 2 ? L.tmp : x, s);
+  if (nu == 2) rows(GA, L.n, d, L, r, L.tmp, x, s);
 }
 
 void bp_apply(const DTopo &tp, const AmgDev &A, int64_t nface, const double *cpl, const double *Sd, const double *v,

@@ -40,17 +40,30 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0;
     const int rb = tp.rowptr[f], re = tp.rowptr[f + 1];
-    for (int bi = rb; bi < re; ++bi) {
-      const int64_t fc = tp.col[bi];
-      const T *blk = L.bsr + (int64_t)tp.mirror[bi] * (P * P) + r;
-      T bv[P];
+    // U blocks in flight per step (small blocks: the loop is latency-bound);
+    // a 1 x 1 block is its own mirror
+    constexpr int U = DP <= 4 ? 4 : DP <= 8 ? 2 : 1;
+    for (int b0 = rb; b0 < re; b0 += U) {
+      int64_t fc[U], mb[U];
 #pragma unroll
-      for (int k = 0; k < P; ++k) bv[k] = blk[k * P];
-      const int64_t xo = fc * DP;
+      for (int u = 0; u < U; ++u) {
+        const bool in = b0 + u < re;
+        fc[u] = in ? tp.col[b0 + u] : 0;
+        mb[u] = in ? (P == 1 ? b0 + u : tp.mirror[b0 + u]) : -1;
+      }
 #pragma unroll
-      for (int c = 0; c < D; ++c)
+      for (int u = 0; u < U; ++u) {
+        if (mb[u] < 0) continue;
+        const T *blk = L.bsr + mb[u] * (P * P) + r;
+        T bv[P];
 #pragma unroll
-        for (int k = 0; k < P; ++k) acc[c] += bv[k] * xface<T, SPLIT>(x, xs1, xo + c * P + k);
+        for (int k = 0; k < P; ++k) bv[k] = blk[k * P];
+        const int64_t xo = fc[u] * DP;
+#pragma unroll
+        for (int c = 0; c < D; ++c)
+#pragma unroll
+          for (int k = 0; k < P; ++k) acc[c] += bv[k] * xface<T, SPLIT>(x, xs1, xo + c * P + k);
+      }
     }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {

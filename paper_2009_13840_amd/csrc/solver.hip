@@ -264,7 +264,14 @@ static void plan(hho_problem *P, Arena &A) {
         G.bpp = A.take<int32_t>(H.bpp.size());
         G.bpa = A.take<int32_t>(H.bpa.size());
         G.bpb = A.take<int32_t>(H.bpb.size());
+        G.brp = A.take<int32_t>(H.brp.size());
+        G.bci = A.take<int32_t>(H.bci.size());
+        G.btp = A.take<int32_t>(H.btp.size());
+        G.bti = A.take<int32_t>(H.bti.size());
+        G.bte = A.take<int32_t>(H.bte.size());
         G.bval = A.take<double>(G.nbe);
+        G.ptval = A.take<double>(G.npe);
+        G.btval = A.take<double>(G.nbe);
         G.cpp = A.take<int32_t>(H.cpp.size());
         G.cpa = A.take<int32_t>(H.cpa.size());
         G.cpb = A.take<int32_t>(H.cpb.size());
@@ -547,6 +554,11 @@ static void device_upload(hho_problem *P) {
         h2d((void *)G.bpp, H.bpp.data(), H.bpp.size() * 4);
         h2d((void *)G.bpa, H.bpa.data(), H.bpa.size() * 4);
         h2d((void *)G.bpb, H.bpb.data(), H.bpb.size() * 4);
+        h2d((void *)G.brp, H.brp.data(), H.brp.size() * 4);
+        h2d((void *)G.bci, H.bci.data(), H.bci.size() * 4);
+        h2d((void *)G.btp, H.btp.data(), H.btp.size() * 4);
+        h2d((void *)G.bti, H.bti.data(), H.bti.size() * 4);
+        h2d((void *)G.bte, H.bte.data(), H.bte.size() * 4);
         h2d((void *)G.cpp, H.cpp.data(), H.cpp.size() * 4);
         h2d((void *)G.cpa, H.cpa.data(), H.cpa.size() * 4);
         h2d((void *)G.cpb, H.cpb.data(), H.cpb.size() * 4);

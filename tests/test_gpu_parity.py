@@ -136,6 +136,20 @@ def test_coarse_block_preconditioner(built, name, mk, k, cond):
     assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
 
 
+@pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0], AMG_CASES[2]])
+def test_coarse_block_preconditioner_one_sweep(built, name, mk, k, cond):
+    """The same with one damped-Jacobi sweep before and after each coarse correction."""
+    import torch
+    from oracle.amg import BlockStokesPrec
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_sweeps=1)
+    L = len(O.S) - 1
+    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, nu=1)
+    rng = np.random.default_rng(4)
+    v = rng.standard_normal(O.S[L].shape[0])
+    z = P.coarse_prec_apply(torch.from_numpy(v).cuda()).cpu().numpy()
+    assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
+
+
 @pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
 def test_fgmres_solution_amg_coarse(built, name, mk, k, cond):
     import oracle.solve as OS
