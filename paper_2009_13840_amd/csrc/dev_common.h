@@ -17,6 +17,14 @@ __device__ inline double wave_sum(double v) {
   return v;
 }
 
+// Sum over the G lanes of a row group (G a power of two dividing 64); result in
+// the group's first lane.
+template <int G, typename T>
+__device__ inline T group_sum(T v) {
+  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
+  return v;
+}
+
 // Block-wide sum (blockDim.x a multiple of 64, <= 1024); result valid in thread 0.
 __device__ inline double block_sum(double v, double *lds /* >= 16 */) {
   v = wave_sum(v);

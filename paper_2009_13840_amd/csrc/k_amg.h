@@ -29,14 +29,21 @@ struct AmgDevLevel {
   double *x = nullptr, *r = nullptr, *res = nullptr, *tmp = nullptr;  // [n][d]
 };
 
+constexpr int kAmgExplicitMax = 4096;  // largest level replaced by its explicit V-cycle matrix
+
 struct AmgDev {
   int nlev = 0;
   AmgDevLevel lev[kMaxAmgLevels];
-  double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr, *pw = nullptr;
+  // explicit operator M of the V-cycle on level expl (-1: none), [n][n] row-major
+  // (it is cx[expl]), and the column blocks [n_l][n_expl] it is formed with
+  int expl = -1;
+  double *mexpl = nullptr;
+  double *cr[kMaxAmgLevels] = {}, *cx[kMaxAmgLevels] = {}, *ct[kMaxAmgLevels] = {};
+  double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr;  // partial: 2 x 256 power-step sums
 };
 
-void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int *err,
-                       hipStream_t s);
+void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int nu,
+                       int *err, hipStream_t s);
 void bp_setup(const DTopo &tp, int cond, const int32_t *fdiag, const double *bsr, const double *cpl, double *Sd,
               hipStream_t s);
 // z = block preconditioner applied to v (coarsest-level vectors in the global layout)

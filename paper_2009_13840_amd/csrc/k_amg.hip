@@ -41,23 +41,43 @@ __global__ void k_amg_diag(int n, const int32_t *diag, const double *val, double
   }
 }
 
-// one power-iteration step: vout = D^{-1} A (vin / lam_in), partial sums of |vout|^2
-// (lam_in == null: no scaling); k_amg_power_finish writes lam_out = safety * |vout|.
+// One power-iteration step for lambda ~ rho(D^{-1} A): vout = D^{-1} A vin / |vin|,
+// with |vin|^2 the sum of the nin partial sums pin (nin == 0: no scaling; every
+// block adds them in the same order), and this block's share of |vout|^2 in
+// pout[blockIdx.x].  G lanes per row.  k_amg_power_finish writes
+// lam_out = safety * |vout| after the last step.
+template <int G>
 __global__ void __launch_bounds__(kBlock) k_amg_power(int n, const int32_t *rp, const int32_t *ci, const double *val,
-                                                       const double *dinv, const double *vin, const double *lam_in,
-                                                       double *vout, double *partial) {
+                                                       const double *dinv, const double *vin, const double *pin,
+                                                       int nin, double *vout, double *pout) {
   __shared__ double red[16];
-  const double sc = lam_in ? 1.0 / lam_in[0] : 1.0;
+  __shared__ double scs;
+  double sc = 1.0;
+  if (nin > 0) {
+    if (threadIdx.x < kWave) {
+      double t = 0;
+      for (int b = threadIdx.x; b < nin; b += kWave) t += pin[b];
+      t = wave_sum(t);
+      if (threadIdx.x == 0) scs = 1.0 / sqrt(t);
+    }
+    __syncthreads();
+    sc = scs;
+  }
+  const int lane = threadIdx.x % G;
+  const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
   double acc = 0;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G; i < n; i += ngroups) {
     double t = 0;
-    for (int e = rp[i]; e < rp[i + 1]; ++e) t += val[e] * vin[ci[e]];
-    t *= sc * dinv[i];
-    vout[i] = t;
-    acc += t * t;
+    for (int e = rp[i] + lane; e < rp[i + 1]; e += G) t += val[e] * vin[ci[e]];
+    t = group_sum<G>(t);
+    if (lane == 0) {
+      t *= sc * dinv[i];
+      vout[i] = t;
+      acc += t * t;
+    }
   }
   const double s = block_sum(acc, red);
-  if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  if (threadIdx.x == 0) pout[blockIdx.x] = s;
 }
 
 __global__ void __launch_bounds__(kBlock) k_amg_power_finish(int G, const double *partial, double *lam_out,
@@ -87,6 +107,47 @@ __global__ void k_amg_pairs(int64_t nout, const int32_t *pp, const int32_t *pa, 
     for (int k = pp[e]; k < pp[e + 1]; ++k) s += X[pa[k]] * Y[pb[k]];
     out[e] = s;
   }
+}
+
+// coarsest level: dense inverse of the (small, SPD) CSR matrix by Gauss-Jordan
+// elimination without pivoting (the pivots of an SPD matrix are positive), the
+// matrix resident in LDS, one block of 1024 threads; n <= kAmgCoarsest.
+__global__ void __launch_bounds__(1024) k_amg_coarsest_lds(int n, const int32_t *rp, const int32_t *ci,
+                                                            const double *val, double *Ainv, int *err) {
+  extern __shared__ double lds[];
+  double *M = lds, *colk = lds + n * n, *rowk = colk + n;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) M[i] = 0.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    for (int e = rp[i]; e < rp[i + 1]; ++e) M[i * n + ci[e]] = val[e];
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = M[k * n + k];
+    if (!(piv > 0)) {
+      if (threadIdx.x == 0) bad = 1;
+      break;  // uniform: every thread reads the same pivot
+    }
+    const double ip = 1.0 / piv;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      colk[i] = M[i * n + k];
+      rowk[i] = M[k * n + i] * ip;
+    }
+    __syncthreads();
+    // M_ij -= M_ik M_kj / piv (i, j != k); row k scaled by 1/piv; column k = -M_ik / piv; M_kk = 1/piv
+    for (int o = threadIdx.x; o < n * n; o += blockDim.x) {
+      const int i = o / n, j = o % n;
+      double v;
+      if (i == k) v = (j == k) ? ip : rowk[j];
+      else if (j == k) v = -colk[i] * ip;
+      else v = M[o] - colk[i] * rowk[j];
+      M[o] = v;
+    }
+    __syncthreads();
+  }
+  for (int i = threadIdx.x; i < n * n; i += blockDim.x) Ainv[i] = M[i];
+  if (threadIdx.x == 0 && bad) atomicMax(err, 1);
 }
 
 // coarsest level: dense inverse of the (small, SPD) CSR matrix in one block
@@ -147,13 +208,6 @@ __global__ void k_bp_rhs(DTopo tp, int64_t nface, const double *cpl, const doubl
       z[o] = -v[o] / Sd[T];
     }
   }
-}
-
-// Sum over the G lanes of a row group (G a power of two dividing 64).
-template <int G>
-__device__ inline double group_sum(double v) {
-  for (int o = G / 2; o > 0; o >>= 1) v += __shfl_down(v, o, G);
-  return v;
 }
 
 // Damped-Jacobi sweep xout = xin + w D^{-1} (r - A xin), G lanes per row, all d
@@ -326,56 +380,219 @@ __global__ void __launch_bounds__(kBlock) k_amg_prolong_sweep(int n, int d, cons
   }
 }
 
-// x = Ainv r (dense, n <= 128), one wavefront per row
+// x = Ainv r (dense, row-major n x n): one block per row, every thread taking
+// every 256th entry, two in flight; waves combined through LDS
 __global__ void __launch_bounds__(kBlock) k_amg_dense(int n, int d, const double *Ainv, const double *r,
                                                        double *x) {
-  const int lane = threadIdx.x % kWave;
-  const int64_t nw = (int64_t)gridDim.x * (blockDim.x / kWave);
-  for (int64_t i = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave; i < n; i += nw) {
+  __shared__ double red[3][kBlock / kWave];
+  const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
+  for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
+    const double *row = Ainv + i * n;
     double s0 = 0, s1 = 0, s2 = 0;
-    for (int j = lane; j < n; j += kWave) {
-      const double a = Ainv[i * n + j];
-      s0 += a * r[(int64_t)j * d];
-      if (d > 1) s1 += a * r[(int64_t)j * d + 1];
-      if (d > 2) s2 += a * r[(int64_t)j * d + 2];
+    int j = threadIdx.x;
+    for (; j + kBlock < n; j += 2 * kBlock) {
+      const double a0 = row[j], a1 = row[j + kBlock];
+      const double *r0 = r + (int64_t)j * d, *r1 = r + (int64_t)(j + kBlock) * d;
+      s0 += a0 * r0[0] + a1 * r1[0];
+      if (d > 1) s1 += a0 * r0[1] + a1 * r1[1];
+      if (d > 2) s2 += a0 * r0[2] + a1 * r1[2];
+    }
+    if (j < n) {
+      const double a0 = row[j];
+      const double *r0 = r + (int64_t)j * d;
+      s0 += a0 * r0[0];
+      if (d > 1) s1 += a0 * r0[1];
+      if (d > 2) s2 += a0 * r0[2];
     }
     s0 = wave_sum(s0);
     s1 = wave_sum(s1);
     s2 = wave_sum(s2);
     if (lane == 0) {
-      x[i * d] = s0;
-      if (d > 1) x[i * d + 1] = s1;
-      if (d > 2) x[i * d + 2] = s2;
+      red[0][wid] = s0;
+      red[1][wid] = s1;
+      red[2][wid] = s2;
     }
+    __syncthreads();
+    if (threadIdx.x < d) {
+      double t = 0;
+      for (int w = 0; w < kBlock / kWave; ++w) t += red[threadIdx.x][w];
+      x[i * d + threadIdx.x] = t;
+    }
+    __syncthreads();
   }
+}
+
+// ---- explicit V-cycle operator: the V-cycle of a small level applied to the m
+// columns of the identity, the same steps as the vector path on [n][m] blocks
+// (row-major, one thread per entry), so that M[i][c] = (V e_c)_i.
+
+__global__ void __launch_bounds__(kBlock) k_cols_identity(int64_t n, double *R) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o < n * n) R[o] = (o / n == o % n) ? 1.0 : 0.0;
+}
+
+// Y = X + w D^{-1} (R - A X); X == null stands for X = w D^{-1} R (two sweeps
+// from zero in one pass); with half, Y = w D^{-1} R (one sweep from zero)
+__global__ void __launch_bounds__(kBlock) k_cols_sweep(int n, int m, const int32_t *rp, const int32_t *ci,
+                                                        const double *val, const double *dinv, const double *lam,
+                                                        const double *R, const double *X, double *Y, int half) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= (int64_t)n * m) return;
+  const int i = (int)(o / m), c = (int)(o % m);
+  const double w = kAmgOmegaJac / lam[0], si = w * dinv[i];
+  if (half) {
+    Y[o] = si * R[o];
+    return;
+  }
+  double q = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) {
+    const int64_t jc = (int64_t)ci[e] * m + c;
+    q += val[e] * (X ? X[jc] : w * dinv[ci[e]] * R[jc]);
+  }
+  Y[o] = (X ? X[o] : si * R[o]) + si * (R[o] - q);
+}
+
+// T = R - A X
+__global__ void __launch_bounds__(kBlock) k_cols_resid(int n, int m, const int32_t *rp, const int32_t *ci,
+                                                        const double *val, const double *R, const double *X,
+                                                        double *T) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= (int64_t)n * m) return;
+  const int i = (int)(o / m), c = (int)(o % m);
+  double q = 0;
+  for (int e = rp[i]; e < rp[i + 1]; ++e) q += val[e] * X[(int64_t)ci[e] * m + c];
+  T[o] = R[o] - q;
+}
+
+// Rc = P^T T (coarse row I gathers its P^T entries)
+__global__ void __launch_bounds__(kBlock) k_cols_restrict(int nc, int m, const int32_t *ptp, const int32_t *pti,
+                                                           const double *ptval, const double *T, double *Rc) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= (int64_t)nc * m) return;
+  const int I = (int)(o / m), c = (int)(o % m);
+  double q = 0;
+  for (int k = ptp[I]; k < ptp[I + 1]; ++k) q += ptval[k] * T[(int64_t)pti[k] * m + c];
+  Rc[o] = q;
+}
+
+// Y = X + P Xc (Y may be X)
+__global__ void __launch_bounds__(kBlock) k_cols_prolong(int n, int m, const int32_t *prp, const int32_t *pci,
+                                                          const double *pval, const double *Xc, const double *X,
+                                                          double *Y) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= (int64_t)n * m) return;
+  const int i = (int)(o / m), c = (int)(o % m);
+  double q = 0;
+  for (int e = prp[i]; e < prp[i + 1]; ++e) q += pval[e] * Xc[(int64_t)pci[e] * m + c];
+  Y[o] = X[o] + q;
+}
+
+// X = Ainv R (dense n x n times n x m)
+__global__ void __launch_bounds__(kBlock) k_cols_dense(int n, int m, const double *Ainv, const double *R,
+                                                        double *X) {
+  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (o >= (int64_t)n * m) return;
+  const int i = (int)(o / m), c = (int)(o % m);
+  double q = 0;
+  for (int j = 0; j < n; ++j) q += Ainv[(int64_t)i * n + j] * R[(int64_t)j * m + c];
+  X[o] = q;
 }
 
 }  // namespace
 
-void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int *err,
-                       hipStream_t s) {
+int amg_group(double avg);
+
+// Column-block V-cycle on level l: X_l = V_l(R_l) for the m columns of cr[l]
+// (result in cx[l]); the steps of the vector V-cycle.
+static void cols_vcycle(const AmgDev &A, int l, int m, int nu, hipStream_t s) {
+  const AmgDevLevel &L = A.lev[l];
+  const int n = L.n;
+  const dim3 b(kBlock), g(grid_for((int64_t)n * m));
+  double *R = A.cr[l], *X = A.cx[l], *T = A.ct[l];
+  auto sweep = [&](const double *xin, double *xout, int half) {
+    hipLaunchKernelGGL(k_cols_sweep, g, b, 0, s, n, m, L.rp, L.ci, (const double *)L.val, (const double *)L.dinv,
+                       (const double *)L.lam, (const double *)R, xin, xout, half);
+  };
+  if (l == A.nlev - 1) {
+    if (A.ainv) {
+      hipLaunchKernelGGL(k_cols_dense, g, b, 0, s, n, m, (const double *)A.ainv, (const double *)R, X);
+      return;
+    }
+    constexpr int rest = kAmgCoarseSweeps - 2;
+    double *cur = (rest % 2 == 1) ? T : X;
+    sweep(nullptr, cur, 0);
+    for (int it = 0; it < rest; ++it) {
+      double *nxt = (cur == X) ? T : X;
+      sweep(cur, nxt, 0);
+      cur = nxt;
+    }
+    return;
+  }
+  const AmgDevLevel &N = A.lev[l + 1];
+  sweep(nullptr, X, nu == 1);  // pre-smoothing from zero
+  hipLaunchKernelGGL(k_cols_resid, g, b, 0, s, n, m, L.rp, L.ci, (const double *)L.val, (const double *)R,
+                     (const double *)X, T);
+  hipLaunchKernelGGL(k_cols_restrict, dim3(grid_for((int64_t)N.n * m)), b, 0, s, N.n, m, L.ptp, L.pti,
+                     (const double *)L.ptval, (const double *)T, A.cr[l + 1]);
+  cols_vcycle(A, l + 1, m, nu, s);
+  // prolongation, then nu post-sweeps alternating between T and X, ending in X
+  double *cur = (nu % 2 == 1) ? T : X;
+  hipLaunchKernelGGL(k_cols_prolong, g, b, 0, s, n, m, L.prp, L.pci, (const double *)L.pval,
+                     (const double *)A.cx[l + 1], (const double *)X, cur);
+  for (int it = 0; it < nu; ++it) {
+    double *nxt = (cur == X) ? T : X;
+    sweep(cur, nxt, 0);
+    cur = nxt;
+  }
+}
+
+void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int nu,
+                       int *err, hipStream_t s) {
   hipLaunchKernelGGL(k_amg_extract0, dim3(grid_for(nnzb0)), dim3(kBlock), 0, s, nnzb0, bs, d, cond, bsr0,
                      A.lev[0].val);
   for (int l = 0; l < A.nlev; ++l) {
     const AmgDevLevel &L = A.lev[l];
     if (l == A.nlev - 1 && A.ainv) {
-      hipLaunchKernelGGL(k_amg_coarsest, dim3(1), dim3(kBlock), 0, s, L.n, L.rp, L.ci, L.val, A.dense_scratch,
-                         A.ainv, err);
+      const size_t lds = ((size_t)L.n * L.n + 2 * L.n) * sizeof(double);
+      static bool attr = false;
+      if (!attr) {
+        if (hipFuncSetAttribute((const void *)k_amg_coarsest_lds, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(kMaxLdsBytes - 1024)) != hipSuccess)
+          fail(HHO_E_DEVICE, "AMG coarsest: cannot reserve LDS");
+        attr = true;
+      }
+      if (lds <= kMaxLdsBytes - 1024)
+        hipLaunchKernelGGL(k_amg_coarsest_lds, dim3(1), dim3(1024), lds, s, L.n, L.rp, L.ci,
+                           (const double *)L.val, A.ainv, err);
+      else
+        hipLaunchKernelGGL(k_amg_coarsest, dim3(1), dim3(kBlock), 0, s, L.n, L.rp, L.ci, L.val, A.dense_scratch,
+                           A.ainv, err);
       break;
     }
-    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>((L.n + kBlock - 1) / kBlock, 256));
+    const int GA = amg_group((double)L.nnz / L.n);
+    const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(grid_for((int64_t)L.n * GA), 256));
     hipLaunchKernelGGL(k_amg_diag, dim3(grid_for(L.n)), dim3(kBlock), 0, s, L.n, L.diag, (const double *)L.val,
                        L.dinv, L.tmp);
-    // lambda ~ rho(D^{-1} A) by power iteration (ping-pong between tmp and res)
+    // lambda ~ rho(D^{-1} A) by power iteration (vectors ping-pong between tmp
+    // and res, partial sums between the two halves of the partial buffer)
     for (int k = 0; k < kAmgPowerSteps; ++k) {
       const double *vin = (k % 2 == 0) ? L.tmp : L.res;
       double *vout = (k % 2 == 0) ? L.res : L.tmp;
-      const bool last = k == kAmgPowerSteps - 1;
-      hipLaunchKernelGGL(k_amg_power, dim3(nb), dim3(kBlock), 0, s, L.n, L.rp, L.ci, (const double *)L.val,
-                         (const double *)L.dinv, vin, (const double *)(k ? A.pw + k - 1 : nullptr), vout, A.partial);
-      hipLaunchKernelGGL(k_amg_power_finish, dim3(1), dim3(kBlock), 0, s, nb, (const double *)A.partial,
-                         last ? L.lam : A.pw + k, last ? kAmgLambdaSafety : 1.0);
+      const double *pin = A.partial + ((k + 1) % 2) * 256;
+      double *pout = A.partial + (k % 2) * 256;
+#define HHO_PW(GG)                                                                                             \
+  hipLaunchKernelGGL((k_amg_power<GG>), dim3(nb), dim3(kBlock), 0, s, L.n, L.rp, L.ci, (const double *)L.val,   \
+                     (const double *)L.dinv, vin, pin, k ? nb : 0, vout, pout)
+      switch (GA) {
+        case 64: HHO_PW(64); break;
+        case 16: HHO_PW(16); break;
+        case 4: HHO_PW(4); break;
+        default: HHO_PW(1); break;
+      }
+#undef HHO_PW
     }
+    hipLaunchKernelGGL(k_amg_power_finish, dim3(1), dim3(kBlock), 0, s, nb,
+                       (const double *)(A.partial + ((kAmgPowerSteps - 1) % 2) * 256), L.lam, kAmgLambdaSafety);
     if (l == A.nlev - 1) break;  // large coarsest level: Jacobi sweeps only
     hipLaunchKernelGGL(k_amg_p, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.prow, L.pgp, L.pgi, L.pself,
                        L.val, L.dinv, L.lam, L.pval);
@@ -388,6 +605,12 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
                        (const double *)L.pval, L.ptval);
     hipLaunchKernelGGL(k_amg_gather, dim3(grid_for(L.nbe)), dim3(kBlock), 0, s, L.nbe, L.bte,
                        (const double *)L.bval, L.btval);
+  }
+  if (A.expl >= 0) {  // M = V_expl(I)
+    const int m = A.lev[A.expl].n;
+    hipLaunchKernelGGL(k_cols_identity, dim3(grid_for((int64_t)m * m)), dim3(kBlock), 0, s, (int64_t)m,
+                       A.cr[A.expl]);
+    cols_vcycle(A, A.expl, m, nu, s);  // M is cx[expl]
   }
 }
 
@@ -433,10 +656,13 @@ int amg_group(double avg) { return avg >= 48 ? 64 : avg >= 12 ? 16 : avg >= 3 ? 
 // before and after the coarse correction (nu = 1 or 2).
 static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, double *x, hipStream_t s) {
   const AmgDevLevel &L = A.lev[l];
+  if (l == A.expl) {  // this level and all coarser ones: the explicit operator
+    hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.mexpl, r, x);
+    return;
+  }
   if (l == A.nlev - 1) {
     if (A.ainv) {
-      hipLaunchKernelGGL(k_amg_dense, dim3(grid_for((int64_t)L.n * kWave)), dim3(kBlock), 0, s, L.n, d,
-                         (const double *)A.ainv, r, x);
+      hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.ainv, r, x);
       return;
     }
     // kAmgCoarseSweeps damped-Jacobi sweeps from zero (the first launch takes two)

@@ -107,6 +107,64 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
   }
 }
 
+// Lowest degree (k = 0, v-cond: one face mode, one pressure mode per cell): the
+// rows are short, so G lanes share a row (its blocks, its two cells, or its
+// cell's faces) and combine by shuffles; otherwise as k_spmv_v.
+template <typename T, int D, int G, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+                                                     const T *__restrict__ xs1, T *__restrict__ xsum,
+                                                     const T *__restrict__ b, T *__restrict__ y) {
+  const int64_t o = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (o >= (int64_t)tp.nf + tp.nc) return;  // uniform over the group
+  if (o < tp.nf) {
+    const int f = (int)o;
+    T acc[D];
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = 0;
+    for (int bi = tp.rowptr[f] + lane; bi < tp.rowptr[f + 1]; bi += G) {
+      const T a = L.bsr[bi];  // a 1 x 1 block is its own mirror
+      const int64_t xo = (int64_t)tp.col[bi] * D;
+#pragma unroll
+      for (int c = 0; c < D; ++c) acc[c] += a * xface<T, SPLIT>(x, xs1, xo + c);
+    }
+    if (lane < 2) {
+      const int Tc = tp.fcell[2 * f + lane];
+      if (Tc >= 0) {
+        const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + lane];
+        const T xc = x[L.nface + Tc];
+#pragma unroll
+        for (int c = 0; c < D; ++c) acc[c] += L.cpl[e * D + c] * xc;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) acc[c] = group_sum<G>(acc[c]);
+    if (lane == 0) {
+#pragma unroll
+      for (int c = 0; c < D; ++c) {
+        const int64_t i = (int64_t)f * D + c;
+        y[i] = (MODE == 1) ? (T)(b[i] - acc[c]) : acc[c];
+        if (SPLIT && xsum) xsum[i] = x[i] + xs1[i];
+      }
+    }
+  } else {
+    const int Tc = (int)(o - tp.nf);
+    T acc = 0;
+    for (int e = tp.cptr[Tc] + lane; e < tp.cptr[Tc + 1]; e += G) {
+      const int64_t xo = (int64_t)tp.cface[e] * D;
+#pragma unroll
+      for (int j = 0; j < D; ++j) acc += L.cpl[(int64_t)e * D + j] * xface<T, SPLIT>(x, xs1, xo + j);
+    }
+    if (lane == 0) acc += L.spp[Tc] * x[L.nface + Tc];
+    acc = group_sum<G>(acc);
+    if (lane == 0) {
+      const int64_t i = L.nface + Tc;
+      y[i] = (MODE == 1) ? (T)(b[i] - acc) : acc;
+      if (SPLIT && xsum) xsum[i] = x[i];
+    }
+  }
+}
+
 template <typename T, int BS, bool SPLIT, int MODE>
 __global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const T *__restrict__ x,
                                                      const T *__restrict__ xs1, T *__restrict__ xsum,
@@ -158,8 +216,15 @@ bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T
   if (tp.d != D || L.p != P) return false;
   if (L.cond == 1) {
     if (L.t != TT) return false;
-    const int64_t total = (int64_t)tp.nf * P + (int64_t)tp.nc * TT;
     const int bs = L.block > 0 ? L.block : kBlock;
+    if (K == 0) {
+      constexpr int G = 4;
+      const int64_t total = ((int64_t)tp.nf + tp.nc) * G;
+      const int grid = (int)((total + bs - 1) / bs);
+      hipLaunchKernelGGL((k_spmv_v0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+      return true;
+    }
+    const int64_t total = (int64_t)tp.nf * P + (int64_t)tp.nc * TT;
     const int grid = (int)((total + bs - 1) / bs);
     hipLaunchKernelGGL((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   } else {

@@ -277,6 +277,23 @@ static void plan(hho_problem *P, Arena &A) {
         G.cpb = A.take<int32_t>(H.cpb.size());
       }
     }
+    // explicit V-cycle operator from the first level with at most
+    // coarse_amg_explicit rows down (none if that is the dense coarsest level)
+    D.expl = -1;
+    for (int l = 0; l < D.nlev; ++l)
+      if (D.lev[l].n <= P->opt.coarse_amg_explicit) {
+        if (!(l == D.nlev - 1 && D.lev[l].n <= kAmgCoarsest)) D.expl = l;
+        break;
+      }
+    if (D.expl >= 0) {
+      const int64_t m = D.lev[D.expl].n;
+      for (int l = D.expl; l < D.nlev; ++l) {
+        D.cr[l] = A.take<double>(D.lev[l].n * m);
+        D.cx[l] = A.take<double>(D.lev[l].n * m);
+        D.ct[l] = A.take<double>(D.lev[l].n * m);
+      }
+      D.mexpl = D.cx[D.expl];
+    }
     const int nlast = P->amgh.levels.back().n;
     if (nlast <= kAmgCoarsest) {  // dense inverse of the coarsest level; Jacobi sweeps above that size
       D.ainv = A.take<double>((int64_t)nlast * nlast);
@@ -285,7 +302,6 @@ static void plan(hho_problem *P, Arena &A) {
       D.ainv = D.dense_scratch = nullptr;
     }
     D.partial = A.take<double>(512);
-    D.pw = A.take<double>(kAmgPowerSteps + 1);
   }
   // batched problems
   if (P->nseg > 0) {
@@ -614,7 +630,7 @@ static void device_setup(hho_problem *P) {
   if (P->coarse_amg) {
     const LevelInfo &LC = P->lev[Lc];
     bp_setup(P->tp, P->cond, P->d_fdiag, LC.bsr, LC.cpl, P->Sd, s);
-    amg_numeric_setup(P->amgd, P->cond, P->d, LC.bs, P->nnzb, LC.bsr, P->err + 3, s);
+    amg_numeric_setup(P->amgd, P->cond, P->d, LC.bs, P->nnzb, LC.bsr, P->amg_nu, P->err + 3, s);
   }
   // FP32 copies for the mixed-precision V-cycle
   if (P->opt.precision == HHO_PREC_FP32) {
@@ -1049,6 +1065,7 @@ void hho_options_default(hho_options *o) {
   o->quad_extra = 6;
   o->coarse_amg_sweeps = 2;
   o->learned = 0;
+  o->coarse_amg_explicit = 2048;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -1098,6 +1115,8 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.coarse_amg_sweeps < 1 || P->opt.coarse_amg_sweeps > 2)
     hho::fail(HHO_E_INVALID_ARG, "coarse_amg_sweeps must be 1 or 2");
   P->amg_nu = P->opt.coarse_amg_sweeps;
+  if (P->opt.coarse_amg_explicit < 0 || P->opt.coarse_amg_explicit > hho::kAmgExplicitMax)
+    hho::fail(HHO_E_INVALID_ARG, "coarse_amg_explicit must be in 0..4096");
   if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
   if (P->opt.learned != 0 && P->opt.learned != 1) hho::fail(HHO_E_INVALID_ARG, "learned must be 0 or 1");

@@ -120,13 +120,15 @@ AMG_CASES = [
 ]
 
 
+@pytest.mark.parametrize("explicit", [2048, 0])
 @pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
-def test_coarse_block_preconditioner(built, name, mk, k, cond):
+def test_coarse_block_preconditioner(built, name, mk, k, cond, explicit):
     """Coarsest-level block-triangular preconditioner with the smoothed-aggregation
-    velocity block: GPU vs the oracle's plain definition."""
+    velocity block: GPU vs the oracle's plain definition, with the small AMG levels
+    applied as their explicit V-cycle matrix (2048) and level by level (0)."""
     import torch
     from oracle.amg import BlockStokesPrec
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg")
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_explicit=explicit)
     L = len(O.S) - 1
     prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim)
     assert len(prec.amg.sizes) >= 2
@@ -136,12 +138,13 @@ def test_coarse_block_preconditioner(built, name, mk, k, cond):
     assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
 
 
-@pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0], AMG_CASES[2]])
-def test_coarse_block_preconditioner_one_sweep(built, name, mk, k, cond):
+@pytest.mark.parametrize("explicit", [2048, 0])
+@pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0], AMG_CASES[3]])
+def test_coarse_block_preconditioner_one_sweep(built, name, mk, k, cond, explicit):
     """The same with one damped-Jacobi sweep before and after each coarse correction."""
     import torch
     from oracle.amg import BlockStokesPrec
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_sweeps=1)
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_sweeps=1, coarse_amg_explicit=explicit)
     L = len(O.S) - 1
     prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, nu=1)
     rng = np.random.default_rng(4)
