@@ -25,6 +25,45 @@ __device__ inline T group_sum(T v) {
   return v;
 }
 
+// One butterfly exchange across lanes (lane ^ O): the lower lane keeps the first
+// H sums and the upper lane the second H, each adding its partner's copy.
+template <int NV, int H, int O, typename T>
+__device__ inline void halve(T (&acc)[NV], bool upper) {
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    const T send = upper ? acc[i] : acc[i + H];
+    const T keep = upper ? acc[i + H] : acc[i];
+    acc[i] = keep + __shfl_xor(send, O, kWave);
+  }
+}
+
+template <int NV, int LIVE, int O, typename T>
+__device__ inline void multi_sum_step(T (&acc)[NV], int lane) {
+  if constexpr (O >= 1) {
+    if constexpr (LIVE > 1) {
+      halve<NV, LIVE / 2, O>(acc, (lane & O) != 0);
+      multi_sum_step<NV, LIVE / 2, O / 2>(acc, lane);
+    } else {
+      acc[0] += __shfl_xor(acc[0], O, kWave);
+      multi_sum_step<NV, 1, O / 2>(acc, lane);
+    }
+  }
+}
+
+// Sum over the 64 lanes of a wave of acc[0..NV) (NV a power of two <= 64) in
+// NV - 1 + 6 - log2(NV) exchanges (a butterfly that halves the live sums per
+// exchange).  On return acc[0] holds, in every lane, the total of vector
+// (lane >> (6 - log2 NV)).
+template <int NV, typename T>
+__device__ inline void wave_multi_sum(T (&acc)[NV]) {
+  multi_sum_step<NV, NV, kWave / 2>(acc, threadIdx.x % kWave);
+}
+
+template <int NV>
+constexpr int log2i() {
+  return NV <= 1 ? 0 : 1 + log2i<NV / 2>();
+}
+
 // Block-wide sum (blockDim.x a multiple of 64, <= 1024); result valid in thread 0.
 __device__ inline double block_sum(double v, double *lds /* >= 16 */) {
   v = wave_sum(v);

@@ -29,6 +29,7 @@ struct DTopo {
   int max_faces;           // largest card(F_T)
 };
 
+constexpr int kPatchMaxRows = 256;  // face rows of a patch inverse (one component block for v-cond)
 constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one CDNA4 compute unit
 
 // One level of the operator: face-block rows plus cell-local couplings.
@@ -43,7 +44,8 @@ struct DLevel {
   int64_t nface, N;  // face-part length nf*d*p, total length
   const T *bsr, *cpl, *spp;
   // smoother patches
-  const T *sinv;  // v: [pairoff*p*p] s_P^{-1}; vp: [pairoff*(d p)^2] S_P^{-1}
+  const T *sinv;  // v: [pairoff*p*p] s_P^{-1}; vp: [pairoff*(d p)^2] S_P^{-1}; each cell's
+                  // slot holds the lower triangle packed by rows (i (i+1)/2 + j, i >= j)
   const T *xinv;  // v: [nc][t][t] pressure Schur inverse; vp: [cptr*d*p] g = S_P^{-1} b
   const T *sig;   // vp: [nc] 1 / (b^T S_P^{-1} b)
   int block = 0;  // threads per block of the operator kernels (0: default), chosen by the autotuner

@@ -262,6 +262,8 @@ __global__ void k_extract(DTopo tp, int cond, int64_t nnzb, int p0, int t0, int 
 //  v-cond: [[s_P (x) I_d, C], [C^T, S_TT]]: store s_P^{-1} and the inverse of the
 //          pressure Schur complement X = S_TT - C^T (s_P^{-1} (x) I_d) C.
 //  v&p:    [[S_P, b], [b^T, 0]]: store S_P^{-1}, g = S_P^{-1} b, 1/(b^T g).
+// The symmetric inverses are stored as their lower triangle packed by rows
+// (entry (i, j), i >= j, at i (i + 1) / 2 + j) at the start of the cell's slot.
 // The factor is formed in `scratch` (per-cell slots sized like s_P).
 __global__ void __launch_bounds__(kBlock) k_patch_setup(DTopo tp, int cond, int p, int t, const double *bsr,
                                                         const double *cpl, const double *spp, double *sinv,
@@ -332,6 +334,14 @@ __global__ void __launch_bounds__(kBlock) k_patch_setup(DTopo tp, int cond, int 
       if (!(s > 0.0)) bad = 1;
       sig[T] = (s > 0.0) ? 1.0 / s : 0.0;
     }
+  }
+  // keep S_P^{-1} as its lower triangle packed by rows (through a copy in the scratch slot)
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) Lm[idx] = Si[idx];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int i = idx / n, j = idx % n;
+    if (j <= i) Si[(int64_t)i * (i + 1) / 2 + j] = Lm[idx];
   }
   __syncthreads();
   if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
@@ -409,15 +419,14 @@ __global__ void __launch_bounds__(kPatchThreads) k_patch_setup_lds(DTopo tp, int
     }
     __syncthreads();
   }
-  // S_P^{-1}(i, k) = sum_{m >= max(i,k)} Linv(m, i) Linv(m, k), both triangles written
+  // S_P^{-1}(i, k) = sum_{m >= max(i,k)} Linv(m, i) Linv(m, k), lower triangle packed by rows
   double *Si = sinv + tp.pairoff[T] * (int64_t)bs * bs;
   for (int k = wid; k < n; k += nw)
     for (int i = k + lane; i < n; i += kWave) {
       double acc = 0;
       const double *ci = A + pk(n, i, i), *ck = A + pk(n, i, k);  // rows m >= i of columns i and k
       for (int m = 0; m < n - i; ++m) acc += ci[m] * ck[m];
-      Si[(int64_t)i * n + k] = acc;
-      Si[(int64_t)k * n + i] = acc;
+      Si[(int64_t)i * (i + 1) / 2 + k] = acc;
     }
   // y = S_P^{-1} v through the factor: u = Linv v, y = Linv^T u (columns of V strided by ld)
   auto apply = [&](const double *v, int64_t vs, double *u, double *y, int64_t ys) {
@@ -587,7 +596,7 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
 #pragma unroll
       for (int w = 0; w < TILE; ++w) {
         const int i = r0 + q, j = c0 + w;
-        if (i < n && j < n) Si[(int64_t)i * n + j] = -a[q][w];
+        if (i < n && j <= i) Si[(int64_t)i * (i + 1) / 2 + j] = -a[q][w];
       }
   }
   const int64_t c0e = tp.cptr[T];

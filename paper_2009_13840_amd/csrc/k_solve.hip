@@ -8,6 +8,7 @@
 
 #include "dev_common.h"
 #include "device.h"
+#include "internal.h"
 
 namespace hho {
 namespace {
@@ -95,11 +96,99 @@ __global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T 
   }
 }
 
+// y = (S (x) I_d) x for a symmetric m x m matrix S (m <= 64 SM) stored as its
+// lower triangle packed by rows (entry (i, j), i >= j, at i (i + 1) / 2 + j).
+// The vectors are in LDS in the patch order [(face, component, mode)] with p
+// modes per face and DC components (DC = 1, p = m: a plain product).  One
+// wavefront: every row j of the triangle is read once, coalesced; its strictly
+// lower entries add S_ji x_j to y_i (S_ij = S_ji, lane-local), and the whole row
+// gives y_j's dot product.  R rows are loaded together (R * SM loads in flight)
+// and their R * DC dot products are reduced across the wave together.
+template <typename T, int SM, int DC>
+__device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T *x, T *y, T *ydot) {
+  constexpr int DCP = DC == 1 ? 1 : DC == 2 ? 2 : 4;  // components padded to a power of two
+  constexpr int R = (SM >= 3 ? 4 : 8) / DCP > 0 ? (SM >= 3 ? 4 : 8) / DCP : 1;  // rows per group
+  constexpr int NV = R * DCP;                                                   // sums reduced together
+  constexpr int shift = 6 - log2i<NV>();
+  const int lane = threadIdx.x;
+  T acc[SM][DC], xi[SM][DC];
+#pragma unroll
+  for (int s = 0; s < SM; ++s) {
+    const int i = lane + s * kWave;
+    const int ib = (i < m) ? ((i / p) * DC) * p + i % p : 0;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+      acc[s][c] = 0;
+      xi[s][c] = (i < m) ? x[ib + c * p] : (T)0;
+    }
+  }
+  int jf = 0, jr = 0;  // j0 = jf p + jr
+  for (int j0 = 0; j0 < m; j0 += R) {
+    T v[R][SM];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = j0 + r;
+      const T *row = S + (int64_t)j * (j + 1) / 2;
+#pragma unroll
+      for (int s = 0; s < SM; ++s) {
+        const int i = lane + s * kWave;
+        v[r][s] = (j < m && i <= j) ? row[i] : (T)0;
+      }
+    }
+    T dot[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) dot[q] = 0;
+    int f = jf, rr = jr;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int j = j0 + r;
+      if (j < m) {
+        const int jb = (f * DC) * p + rr;
+#pragma unroll
+        for (int c = 0; c < DC; ++c) {
+          const T xj = x[jb + c * p];
+          T dsum = 0;
+#pragma unroll
+          for (int s = 0; s < SM; ++s) {
+            const int i = lane + s * kWave;
+            dsum += v[r][s] * xi[s][c];
+            acc[s][c] += ((i < j) ? v[r][s] : (T)0) * xj;
+          }
+          dot[r * DCP + c] = dsum;
+        }
+      }
+      if (++rr == p) {
+        rr = 0;
+        ++f;
+      }
+    }
+    jf = f;
+    jr = rr;
+    wave_multi_sum<NV>(dot);
+    if ((lane & ((1 << shift) - 1)) == 0) {
+      const int q = lane >> shift, r = q / DCP, c = q % DCP;
+      if (c < DC && j0 + r < m) ydot[c * m + j0 + r] = dot[0];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < SM; ++s) {
+    const int i = lane + s * kWave;
+    if (i < m) {
+      const int ib = ((i / p) * DC) * p + i % p;
+#pragma unroll
+      for (int c = 0; c < DC; ++c) y[ib + c * p] = acc[s][c] + ydot[c * m + i];
+    }
+  }
+  __syncthreads();
+}
+
 // Cell-patch Schwarz preconditioner; one 64-thread block per cell.  The
 // corrections of the face unknowns are weighted by 1/card(T_F) and written to the
 // slot of the face's side (slot 0: first cell of the face -> z, slot 1 -> zs1), so
 // that z_F = slot 0 + slot 1 with no write conflict.
-template <typename T>
+// SM, DC: as sym_packed_apply for the level's largest patch (DC = d for v-cond, 1 for v&p).
+template <typename T, int SM, int DC>
 __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const T *__restrict__ r,
                                                    const double *__restrict__ scale, T *__restrict__ v,
                                                    T *__restrict__ z, T *__restrict__ zs1) {
@@ -115,6 +204,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   T *wv = u1 + n;              // [max(n, t)]
   T *yp = wv + (n > t ? n : t);  // [t + 1]
   T *rpr = yp + t + 1;         // [t]
+  T *ydot = rpr + t;           // [n]
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int fi = i / dp, k = i % dp;
     const int f = tp.cface[eb + fi];
@@ -129,17 +219,10 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   }
   __syncthreads();
   if (L.cond == 1) {
-    const T *Si = L.sinv + tp.pairoff[Tc] * p * p;  // [m][m], symmetric
+    const T *Si = L.sinv + tp.pairoff[Tc] * p * p;  // s_P^{-1}, packed lower triangle
     const T *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
     // u1 = (s^{-1} (x) I) r_u
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int fi = i / dp, c = (i / p) % d, rr = i % p;
-      const int row = fi * p + rr;
-      T acc = 0;
-      for (int j = 0; j < m; ++j) acc += Si[(int64_t)j * m + row] * ru[((j / p) * d + c) * p + j % p];
-      u1[i] = acc;
-    }
-    __syncthreads();
+    sym_packed_apply<T, SM, DC>(Si, m, p, ru, u1, ydot);
     // y_p = X^{-1} (r_p - C^T u1)
     for (int q = threadIdx.x; q < t; q += blockDim.x) {
       T acc = rpr[q];
@@ -161,21 +244,11 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
       wv[i] = acc;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      const int fi = i / dp, c = (i / p) % d, rr = i % p;
-      const int row = fi * p + rr;
-      T acc = 0;
-      for (int j = 0; j < m; ++j) acc += Si[(int64_t)j * m + row] * wv[((j / p) * d + c) * p + j % p];
-      u1[i] = acc;
-    }
+    sym_packed_apply<T, SM, DC>(Si, m, p, wv, u1, ydot);
   } else {
-    const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)dp * dp;  // [n][n], symmetric
+    const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)dp * dp;  // S_P^{-1}, packed lower triangle
     const T *g = L.xinv + (int64_t)eb * dp;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      T acc = 0;
-      for (int j = 0; j < n; ++j) acc += Si[(int64_t)j * n + i] * ru[j];
-      u1[i] = acc;
-    }
+    sym_packed_apply<T, SM, DC>(Si, n, n, ru, u1, ydot);
     T part = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) part += g[i] * ru[i];
     // wave reduction (blockDim == 64)
@@ -414,13 +487,25 @@ void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x
 }
 size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem) {
   const int n = max_faces * d * p;
-  return (size_t)(2 * n + std::max(n, t) + 2 * t + 2) * elem;
+  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2) * elem;
 }
 template <typename T>
 void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
                     int max_faces, hipStream_t s) {
   const size_t lds = precond_lds_bytes(tp.d, L.cond, L.p, L.t, max_faces, sizeof(T));
-  hipLaunchKernelGGL((k_precond<T>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1);
+  const int rows = max_faces * ((L.cond == 1) ? L.p : tp.d * L.p);  // rows of the largest packed inverse
+  const int sm = (rows + kWave - 1) / kWave, dc = (L.cond == 1) ? tp.d : 1;
+  if (sm < 1 || sm > kPatchMaxRows / kWave) fail(HHO_E_INVALID_ARG, "precond: patch too large");
+#define HHO_PC(SM, DC)                                                                                         \
+  if (sm == SM && dc == DC) {                                                                                  \
+    hipLaunchKernelGGL((k_precond<T, SM, DC>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1); \
+    return;                                                                                                    \
+  }
+  HHO_PC(1, 1) HHO_PC(2, 1) HHO_PC(3, 1) HHO_PC(4, 1)
+  HHO_PC(1, 2) HHO_PC(2, 2) HHO_PC(3, 2) HHO_PC(4, 2)
+  HHO_PC(1, 3) HHO_PC(2, 3) HHO_PC(3, 3) HHO_PC(4, 3)
+#undef HHO_PC
+  fail(HHO_E_INVALID_ARG, "precond: no kernel for this patch shape");
 }
 template <typename T>
 void launch_combine(int64_t nface, const T *zs1, T *z, hipStream_t s) {

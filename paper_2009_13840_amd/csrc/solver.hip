@@ -1123,6 +1123,11 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
   if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol > 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
   const int d = P->d;
+  {  // the patch smoother keeps a cell's face unknowns (one component for v-cond) in one wavefront's registers
+    const int pk = (d == 2) ? k + 1 : (k + 1) * (k + 2) / 2;
+    if (P->deg.size() > 1 && (int64_t)mesh->max_faces * (cond == 1 ? pk : d * pk) > hho::kPatchMaxRows)
+      hho::fail(HHO_E_INVALID_ARG, "problem_create: a cell patch has more than 256 face unknowns per component block");
+  }
   P->eta = P->opt.eta > 0 ? P->opt.eta : 4.0 * (k + 1) * (k + d) / d * mesh->max_faces;
   hho::build_topology(P.get());
   hho::init_levels(P.get());
