@@ -183,6 +183,29 @@ __device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T 
   __syncthreads();
 }
 
+// The same product with the packed triangle already in LDS (patches of at most
+// 64 rows): one thread per output entry, no cross-lane reduction.
+template <typename T, int DC>
+__device__ void sym_lds_apply(const T *S, int m, int p, const T *x, T *y) {
+  const int n = m * DC;
+  for (int e = threadIdx.x; e < n; e += blockDim.x) {
+    const int fi = e / (DC * p), c = (e / p) % DC, rr = e % p;
+    const int i = fi * p + rr;
+    T acc = 0;
+    int jf = 0, jr = 0;
+    for (int j = 0; j < m; ++j) {
+      const int lo = j < i ? j : i, hi = j < i ? i : j;
+      acc += S[hi * (hi + 1) / 2 + lo] * x[(jf * DC + c) * p + jr];
+      if (++jr == p) {
+        jr = 0;
+        ++jf;
+      }
+    }
+    y[e] = acc;
+  }
+  __syncthreads();
+}
+
 // Cell-patch Schwarz preconditioner; one 64-thread block per cell.  The
 // corrections of the face unknowns are weighted by 1/card(T_F) and written to the
 // slot of the face's side (slot 0: first cell of the face -> z, slot 1 -> zs1), so
@@ -205,6 +228,13 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   T *yp = wv + (n > t ? n : t);  // [t + 1]
   T *rpr = yp + t + 1;         // [t]
   T *ydot = rpr + t;           // [n]
+  T *red = ydot + n;           // [64] partial sums
+  T *Sl = red + kWave;         // SM == 1, DC < 3: the packed patch inverse [rows (rows + 1) / 2]
+  const int rows = (L.cond == 1) ? m : n;
+  const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)((L.cond == 1) ? p * p : dp * dp);  // packed lower triangle
+  if constexpr (SM == 1 && DC < 3) {  // all of the (small) inverse in flight at once
+    for (int q = threadIdx.x; q < rows * (rows + 1) / 2; q += blockDim.x) Sl[q] = Si[q];
+  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int fi = i / dp, k = i % dp;
     const int f = tp.cface[eb + fi];
@@ -219,15 +249,30 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   }
   __syncthreads();
   if (L.cond == 1) {
-    const T *Si = L.sinv + tp.pairoff[Tc] * p * p;  // s_P^{-1}, packed lower triangle
     const T *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
     // u1 = (s^{-1} (x) I) r_u
-    sym_packed_apply<T, SM, DC>(Si, m, p, ru, u1, ydot);
-    // y_p = X^{-1} (r_p - C^T u1)
-    for (int q = threadIdx.x; q < t; q += blockDim.x) {
-      T acc = rpr[q];
-      for (int i = 0; i < n; ++i) acc -= C[(int64_t)i * t + q] * u1[i];
-      wv[q] = acc;
+    if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, m, p, ru, u1);
+    else sym_packed_apply<T, SM, DC>(Si, m, p, ru, u1, ydot);
+    // y_p = X^{-1} (r_p - C^T u1); C^T u1 by lanes (part, q), parts = 64 / t taking
+    // every parts-th row (coalesced rows of C), partials combined in order
+    if (t <= kWave) {
+      const int parts = kWave / t, q = threadIdx.x % t, part = threadIdx.x / t;
+      T acc = 0;
+      if (part < parts)
+        for (int i = part; i < n; i += parts) acc += C[(int64_t)i * t + q] * u1[i];
+      red[threadIdx.x] = acc;
+      __syncthreads();
+      if (threadIdx.x < t) {
+        T s = rpr[threadIdx.x];
+        for (int pp = 0; pp < parts; ++pp) s -= red[pp * t + threadIdx.x];
+        wv[threadIdx.x] = s;
+      }
+    } else {
+      for (int q = threadIdx.x; q < t; q += blockDim.x) {
+        T acc = rpr[q];
+        for (int i = 0; i < n; ++i) acc -= C[(int64_t)i * t + q] * u1[i];
+        wv[q] = acc;
+      }
     }
     __syncthreads();
     const T *Xi = L.xinv + (int64_t)Tc * t * t;
@@ -244,11 +289,12 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
       wv[i] = acc;
     }
     __syncthreads();
-    sym_packed_apply<T, SM, DC>(Si, m, p, wv, u1, ydot);
+    if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, m, p, wv, u1);
+    else sym_packed_apply<T, SM, DC>(Si, m, p, wv, u1, ydot);
   } else {
-    const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)dp * dp;  // S_P^{-1}, packed lower triangle
     const T *g = L.xinv + (int64_t)eb * dp;
-    sym_packed_apply<T, SM, DC>(Si, n, n, ru, u1, ydot);
+    if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, n, n, ru, u1);
+    else sym_packed_apply<T, SM, DC>(Si, n, n, ru, u1, ydot);
     T part = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) part += g[i] * ru[i];
     // wave reduction (blockDim == 64)
@@ -487,7 +533,9 @@ void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x
 }
 size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem) {
   const int n = max_faces * d * p;
-  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2) * elem;
+  const int rows = max_faces * ((cond == 1) ? p : d * p);  // of the packed patch inverse
+  const size_t staged = (rows <= 64 && !(cond == 1 && d == 3)) ? (size_t)rows * (rows + 1) / 2 : 0;
+  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2 + kWave + staged) * elem;
 }
 template <typename T>
 void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
