@@ -267,10 +267,14 @@ class Problem:
         return s.value
 
     # ---- device phase
-    def bind(self, device="cuda:0"):
+    def bind(self, device="cuda:0", fill=None):
+        """Allocate the workspace (optionally every byte set to `fill`) and bind it."""
         import torch
         n = self.workspace_size()
-        self.ws = torch.empty(n, dtype=torch.uint8, device=device)
+        if fill is None:
+            self.ws = torch.empty(n, dtype=torch.uint8, device=device)
+        else:
+            self.ws = torch.full((n,), fill, dtype=torch.uint8, device=device)
         _check(load().hho_bind_workspace(self.h, C.c_void_p(self.ws.data_ptr()), n))
         stream = torch.cuda.current_stream(self.ws.device).cuda_stream
         _check(load().hho_set_stream(self.h, C.c_void_p(stream)))

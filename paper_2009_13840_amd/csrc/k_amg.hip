@@ -260,8 +260,8 @@ __global__ void __launch_bounds__(kBlock) k_amg_rows(int n, int d, const int32_t
 // dst[k] = src[idx[k]] (values of a matrix in the order of its transpose)
 __global__ void __launch_bounds__(kBlock) k_amg_gather(int64_t n, const int32_t *idx, const double *src,
                                                         double *dst) {
-  const int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (k < n) dst[k] = src[idx[k]];
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] = src[idx[k]];
 }
 
 // s += sign * sum over k in [beg, end) of v[k] * x(row[k]), the wavefront's lanes
@@ -427,75 +427,82 @@ __global__ void __launch_bounds__(kBlock) k_amg_dense(int n, int d, const double
 // (row-major, one thread per entry), so that M[i][c] = (V e_c)_i.
 
 __global__ void __launch_bounds__(kBlock) k_cols_identity(int64_t n, double *R) {
-  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (o < n * n) R[o] = (o / n == o % n) ? 1.0 : 0.0;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < n * n; o += (int64_t)gridDim.x * blockDim.x)
+    R[o] = (o / n == o % n) ? 1.0 : 0.0;
 }
 
 // Y = X + w D^{-1} (R - A X); X == null stands for X = w D^{-1} R (two sweeps
-// from zero in one pass); with half, Y = w D^{-1} R (one sweep from zero)
+// from zero in one pass); with half, Y = w D^{-1} R (one sweep from zero).
+// These column-block kernels loop over their entries with a grid stride.
 __global__ void __launch_bounds__(kBlock) k_cols_sweep(int n, int m, const int32_t *rp, const int32_t *ci,
                                                         const double *val, const double *dinv, const double *lam,
                                                         const double *R, const double *X, double *Y, int half) {
-  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (o >= (int64_t)n * m) return;
-  const int i = (int)(o / m), c = (int)(o % m);
-  const double w = kAmgOmegaJac / lam[0], si = w * dinv[i];
-  if (half) {
-    Y[o] = si * R[o];
-    return;
+  const double w = kAmgOmegaJac / lam[0];
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < (int64_t)n * m;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(o / m), c = (int)(o % m);
+    const double si = w * dinv[i];
+    if (half) {
+      Y[o] = si * R[o];
+      continue;
+    }
+    double q = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) {
+      const int64_t jc = (int64_t)ci[e] * m + c;
+      q += val[e] * (X ? X[jc] : w * dinv[ci[e]] * R[jc]);
+    }
+    Y[o] = (X ? X[o] : si * R[o]) + si * (R[o] - q);
   }
-  double q = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) {
-    const int64_t jc = (int64_t)ci[e] * m + c;
-    q += val[e] * (X ? X[jc] : w * dinv[ci[e]] * R[jc]);
-  }
-  Y[o] = (X ? X[o] : si * R[o]) + si * (R[o] - q);
 }
 
 // T = R - A X
 __global__ void __launch_bounds__(kBlock) k_cols_resid(int n, int m, const int32_t *rp, const int32_t *ci,
                                                         const double *val, const double *R, const double *X,
                                                         double *T) {
-  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (o >= (int64_t)n * m) return;
-  const int i = (int)(o / m), c = (int)(o % m);
-  double q = 0;
-  for (int e = rp[i]; e < rp[i + 1]; ++e) q += val[e] * X[(int64_t)ci[e] * m + c];
-  T[o] = R[o] - q;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < (int64_t)n * m;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(o / m), c = (int)(o % m);
+    double q = 0;
+    for (int e = rp[i]; e < rp[i + 1]; ++e) q += val[e] * X[(int64_t)ci[e] * m + c];
+    T[o] = R[o] - q;
+  }
 }
 
 // Rc = P^T T (coarse row I gathers its P^T entries)
 __global__ void __launch_bounds__(kBlock) k_cols_restrict(int nc, int m, const int32_t *ptp, const int32_t *pti,
                                                            const double *ptval, const double *T, double *Rc) {
-  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (o >= (int64_t)nc * m) return;
-  const int I = (int)(o / m), c = (int)(o % m);
-  double q = 0;
-  for (int k = ptp[I]; k < ptp[I + 1]; ++k) q += ptval[k] * T[(int64_t)pti[k] * m + c];
-  Rc[o] = q;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < (int64_t)nc * m;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int I = (int)(o / m), c = (int)(o % m);
+    double q = 0;
+    for (int k = ptp[I]; k < ptp[I + 1]; ++k) q += ptval[k] * T[(int64_t)pti[k] * m + c];
+    Rc[o] = q;
+  }
 }
 
 // Y = X + P Xc (Y may be X)
 __global__ void __launch_bounds__(kBlock) k_cols_prolong(int n, int m, const int32_t *prp, const int32_t *pci,
                                                           const double *pval, const double *Xc, const double *X,
                                                           double *Y) {
-  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (o >= (int64_t)n * m) return;
-  const int i = (int)(o / m), c = (int)(o % m);
-  double q = 0;
-  for (int e = prp[i]; e < prp[i + 1]; ++e) q += pval[e] * Xc[(int64_t)pci[e] * m + c];
-  Y[o] = X[o] + q;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < (int64_t)n * m;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(o / m), c = (int)(o % m);
+    double q = 0;
+    for (int e = prp[i]; e < prp[i + 1]; ++e) q += pval[e] * Xc[(int64_t)pci[e] * m + c];
+    Y[o] = X[o] + q;
+  }
 }
 
 // X = Ainv R (dense n x n times n x m)
 __global__ void __launch_bounds__(kBlock) k_cols_dense(int n, int m, const double *Ainv, const double *R,
                                                         double *X) {
-  const int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (o >= (int64_t)n * m) return;
-  const int i = (int)(o / m), c = (int)(o % m);
-  double q = 0;
-  for (int j = 0; j < n; ++j) q += Ainv[(int64_t)i * n + j] * R[(int64_t)j * m + c];
-  X[o] = q;
+  for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < (int64_t)n * m;
+       o += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(o / m), c = (int)(o % m);
+    double q = 0;
+    for (int j = 0; j < n; ++j) q += Ainv[(int64_t)i * n + j] * R[(int64_t)j * m + c];
+    X[o] = q;
+  }
 }
 
 }  // namespace

@@ -138,6 +138,53 @@ def test_coarse_block_preconditioner(built, name, mk, k, cond, explicit):
     assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
 
 
+def test_coarse_block_preconditioner_explicit_several_levels():
+    """The explicit V-cycle matrix spanning several AMG levels, larger than one
+    launch's thread count (k = 0 on 4096 Voronoi cells: the first level with at
+    most 4096 rows is level 1, with levels below it): GPU vs the oracle."""
+    import torch
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    from oracle.amg import BlockStokesPrec
+    mesh = voronoi_lloyd(4096, 11)
+    data = problem_data(polynomial_stokes(2, 1, 3), None, 2)
+    P = H.Problem(H.Mesh(mesh), 0, "v", coarse_mode="amg", coarse_amg_explicit=4096)
+    P.set_data(*data)
+    P.bind("cuda:0", fill=0xFF)      # NaN bytes: a read of unwritten workspace shows up
+    P.setup()
+    O = OS.build(mesh, 0, "v", data, eta=None)
+    prec = BlockStokesPrec(O.S[0], O.lays[0].off, 2)
+    sizes = prec.amg.sizes
+    assert sizes[0] > 4096 and sizes[1] <= 4096 and sizes[1] ** 2 > 8192 * 256 and len(sizes) >= 4, sizes
+    rng = np.random.default_rng(6)
+    v = rng.standard_normal(O.S[0].shape[0])
+    z = P.coarse_prec_apply(torch.from_numpy(v).cuda()).cpu().numpy()
+    assert np.isfinite(z).all()
+    assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
+
+
+def test_coarse_preconditioner_independent_of_workspace_contents():
+    """Property at full size (3D, 32^3 hexahedra, k = 0: 101,376 faces, B = A P
+    with more entries than one launch has threads): the coarse preconditioner
+    reads only what the setup wrote, so a workspace prefilled with NaN bytes and
+    one prefilled with zeros give the same, finite result, bit for bit."""
+    import torch
+    import paper_2009_13840_amd as H
+    mesh = cartesian_hexes(32)
+    data = problem_data(polynomial_stokes(3, 1, 3), None, 3)
+    out = []
+    for fill in (0x00, 0xFF):
+        P = H.Problem(H.Mesh(mesh), 0, "v", coarse_mode="amg")
+        P.set_data(*data)
+        P.bind("cuda:0", fill=fill)
+        P.setup()
+        v = torch.from_numpy(np.random.default_rng(7).standard_normal(P.level_size(0))).cuda()
+        out.append(P.coarse_prec_apply(v).cpu().numpy())
+        del P
+    assert np.isfinite(out[0]).all() and np.isfinite(out[1]).all()
+    assert np.array_equal(out[0], out[1])
+
+
 @pytest.mark.parametrize("explicit", [2048, 0])
 @pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0], AMG_CASES[3]])
 def test_coarse_block_preconditioner_one_sweep(built, name, mk, k, cond, explicit):
