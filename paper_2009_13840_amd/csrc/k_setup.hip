@@ -875,7 +875,9 @@ void launch_patch_setup(const DTopo &tp, int cond, int p, int t, const double *b
   // register-resident sweep when a tile of at most 7 x 7 per thread covers the patch
   {
     const int n = tp.max_faces * ((cond == 1) ? p : tp.d * p);
-    const int tile = (n + 31) / 32;  // 32 x 32 tiles at most (1024 threads)
+    // one wavefront (8 x 8 tiles of at most 7 x 7) when the patch fits, so the
+    // two barriers per pivot are cheap; else 32 x 32 tiles at most (1024 threads)
+    const int tile = (n + 7) / 8 <= 7 ? (n + 7) / 8 : (n + 31) / 32;
     const size_t lds_sw = tile <= 7 ? patch_sweep_lds_bytes(tp.d, cond, p, t, tp.max_faces, tile) : 0;
     if (tile <= 7 && lds_sw <= kMaxLdsBytes - 1024 && threads == 0) {
       const int nt = (n + tile - 1) / tile;
