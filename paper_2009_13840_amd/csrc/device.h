@@ -128,6 +128,12 @@ void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, 
 template <typename T>
 void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partial, GmresState *st,
                            int pass, int cgs2, hipStream_t s);
+// Classical Gram-Schmidt once, fused: h1 = V^T w and |w|^2 in one pass, the
+// Hessenberg column (new norm |w|^2 - |h1|^2), Givens and residual estimate, then
+// V_{j+1} = (w - V h1) / h_{j+1,j} written in one more pass (3 launches).
+template <typename T>
+void launch_arnoldi_cgs1(int64_t n, int j, T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
+                         hipStream_t s);
 void launch_gmres_solve_ls(GmresState *st, hipStream_t s);
 template <typename T>
 void launch_gmres_combine(int64_t n, const T *Z, int64_t ldz, const GmresState *st, T *x, hipStream_t s);

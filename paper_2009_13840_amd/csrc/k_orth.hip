@@ -42,19 +42,23 @@ __device__ inline void block_multi_partial(double (&acc)[NV], int nv, double *pa
 // MODE 0: h1 = V^T w.
 // MODE 1: w -= V h1, then h2 = V^T w.
 // MODE 2: w -= V h (h = h2 if cgs2 else h1), then |w|^2 -> H column j, Givens, residual.
+// MODE 3: h1 = V^T w and |w|^2 in one pass (classical Gram-Schmidt once, the new
+//         norm by |w - V h1|^2 = |w|^2 - |h1|^2 for orthonormal V).
+// MODE 4: V_{j+1} = (w - V h1) / h_{j+1,j} (the Hessenberg column already complete).
 template <typename T, int NV, int MODE>
 __global__ void __launch_bounds__(kOrthThreads) k_orth(int64_t n, int j, int E, const T *__restrict__ V,
                                                         int64_t ldv, T *__restrict__ w, double *partial,
                                                         GmresState *st, int cgs2) {
   if (st->done) return;
   __shared__ double h[NV];
-  if (MODE != 0) {
+  if (MODE != 0 && MODE != 3) {
     const double *src = (MODE == 2 && cgs2) ? st->h2 : st->h1;
     for (int i = threadIdx.x; i < NV; i += blockDim.x) h[i] = (i <= j) ? src[i] : 0.0;
     __syncthreads();
   }
+  const double inv = (MODE == 4) ? st->inv_hnext : 1.0;
   const int nv = j + 1;
-  double acc[NV];
+  double acc[NV], ww = 0;
 #pragma unroll
   for (int i = 0; i < NV; ++i) acc[i] = 0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -66,7 +70,7 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(int64_t n, int j, int E, 
   for (int e = 0; e < E && k < n; ++e, k += stride) {
     double wk = (double)w[k];
     const T *Vk = V + k;
-    if (MODE != 0) {
+    if (MODE != 0 && MODE != 3) {
 #pragma unroll
       for (int c = 0; c < NV / 8; ++c) {
         if (c * 8 < nv) {
@@ -78,9 +82,14 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(int64_t n, int j, int E, 
         }
         asm volatile("" ::: "memory");
       }
+      if (MODE == 4) {
+        const_cast<T *>(V)[(int64_t)nv * ldv + k] = (T)(wk * inv);
+        continue;
+      }
       w[k] = (T)wk;
       wk = (double)(T)wk;
     }
+    if (MODE == 3) ww += wk * wk;
     if (MODE == 2) {
       acc[0] += wk * wk;
     } else {
@@ -97,10 +106,16 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(int64_t n, int j, int E, 
       }
     }
   }
+  if (MODE == 4) return;
   if (MODE == 2) {
     __shared__ double red[16];
     const double s = block_sum(acc[0], red);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
+  } else if (MODE == 3) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+      if (i == nv) acc[i] = ww;  // the slot after the dots (its dot sum is unused)
+    block_multi_partial<NV>(acc, nv + 1, partial);
   } else {
     block_multi_partial<NV>(acc, nv, partial);
   }
@@ -153,17 +168,31 @@ __device__ void givens_column(GmresState *st, int j, int cgs2, double nn) {
 
 // One block: sums the partials of k_orth in a fixed order.  MODE 0/1 store h1/h2;
 // MODE 2 completes column j of the Hessenberg matrix, applies the Givens
-// rotations and updates the residual estimate and the convergence flag.
+// rotations and updates the residual estimate and the convergence flag; MODE 3
+// stores h1 and completes the column with |w|^2 - |h1|^2 as the new norm squared.
 template <int MODE>
 __global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const double *partial, GmresState *st,
                                                         int cgs2) {
   if (st->done) return;
   __shared__ double hs[kMaxRestartH + 1];
   const int nv = j + 1;
-  if (MODE != 2) {
+  if (MODE == 0 || MODE == 1) {
     reduce_partials(partial, G, nv, hs);
     double *dst = (MODE == 0) ? st->h1 : st->h2;
     for (int i = threadIdx.x; i < nv; i += blockDim.x) dst[i] = hs[i];
+    return;
+  }
+  if (MODE == 3) {
+    reduce_partials(partial, G, nv + 1, hs);
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) st->h1[i] = hs[i];
+    __shared__ double nn;
+    if (threadIdx.x == 0) {
+      double hh = 0;
+      for (int i = 0; i < nv; ++i) hh += hs[i] * hs[i];
+      nn = fmax(hs[nv] - hh, 0.0);
+    }
+    __syncthreads();
+    givens_column(st, j, 0, nn);
     return;
   }
   reduce_partials(partial, G, 1, hs);
@@ -185,7 +214,7 @@ void launch_mode(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partia
                  hipStream_t s) {
   int grid, E;
   orth_shape(n, &grid, &E);
-  const int nv = j + 1;
+  const int nv = j + 1 + (MODE == 3 ? 1 : 0);  // sums per block (MODE 3: the dots and |w|^2)
 #define HHO_ORTH(NVC)                                                                                             \
   hipLaunchKernelGGL((k_orth<T, NVC, MODE>), dim3(grid), dim3(kOrthThreads), 0, s, n, j, E, V, ldv, w, partial, \
                      st, cgs2)
@@ -198,7 +227,9 @@ void launch_mode(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partia
   else
     HHO_ORTH(64);
 #undef HHO_ORTH
-  hipLaunchKernelGGL((k_orth_finish<MODE>), dim3(1), dim3(kBlock), 0, s, grid, j, (const double *)partial, st, cgs2);
+  if (MODE != 4)
+    hipLaunchKernelGGL((k_orth_finish<MODE>), dim3(1), dim3(kBlock), 0, s, grid, j, (const double *)partial, st,
+                       cgs2);
 }
 
 // ---------------------------------------------------------------- batched problems
@@ -439,6 +470,12 @@ void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, 
   launch_mode<T, 0>(n, j, V, ldv, const_cast<T *>(w), partial, st, 0, s);
 }
 template <typename T>
+void launch_arnoldi_cgs1(int64_t n, int j, T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
+                         hipStream_t s) {
+  launch_mode<T, 3>(n, j, V, ldv, const_cast<T *>(w), partial, st, 0, s);
+  launch_mode<T, 4>(n, j, V, ldv, const_cast<T *>(w), partial, st, 0, s);
+}
+template <typename T>
 void launch_arnoldi_update(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partial, GmresState *st,
                            int pass, int cgs2, hipStream_t s) {
   if (pass == 1)
@@ -510,7 +547,8 @@ void launch_seg_project(int np, const int32_t *chunk_ptr, int nchunks, const Seg
   template void launch_arnoldi_dots<T>(int64_t, int, const T *, int64_t, const T *, double *, GmresState *,     \
                                        hipStream_t);                                                           \
   template void launch_arnoldi_update<T>(int64_t, int, const T *, int64_t, T *, double *, GmresState *, int,    \
-                                         int, hipStream_t);
+                                         int, hipStream_t);                                                      \
+  template void launch_arnoldi_cgs1<T>(int64_t, int, T *, int64_t, const T *, double *, GmresState *, hipStream_t);
 HHO_INST(double)
 HHO_INST(float)
 #undef HHO_INST

@@ -767,10 +767,16 @@ static void coarse_solve(hho_problem *P) {
         launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
         launch_spmv<double>(P->tp, D, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
       }
-      // coarse GMRES: classical Gram-Schmidt once (its target is a 1e-3 reduction)
-      launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
-      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, 2, 0, s);
-      launch_scale<double>(n, P->cw, &st->inv_hnext, P->cV + (int64_t)(j + 1) * n, s);
+      // coarse GMRES: classical Gram-Schmidt once (its target is a 1e-3 reduction),
+      // the new norm from |w|^2 - |h|^2, the next basis vector written directly
+      // (while the j + 2 sums of the fused pass fit its 64 accumulators)
+      if (j + 2 <= 64) {
+        launch_arnoldi_cgs1<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
+      } else {
+        launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
+        launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, 2, 0, s);
+        launch_scale<double>(n, P->cw, &st->inv_hnext, P->cV + (int64_t)(j + 1) * n, s);
+      }
       if ((j + 1) % chunk == 0 || j + 1 == jmax) {
         read_state(P, st);
         if (P->h_st->done) break;

@@ -211,6 +211,21 @@ def test_fgmres_solution_amg_coarse(built, name, mk, k, cond):
     assert its <= 40
 
 
+@pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0]])
+def test_fgmres_solution_long_coarse_cycles(built, name, mk, k, cond):
+    """Coarse GMRES with 64-vector cycles run to a tight tolerance, so a cycle
+    reaches the columns past the fused one-pass Gram-Schmidt's 64 sums."""
+    import oracle.solve as OS
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="gmres", coarse_restart=64, coarse_rtol=1e-14,
+                          coarse_max_it=70, rtol=1e-11)
+    x, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-11
+    tm = P.timings()
+    assert tm["coarse_its"] > 63 * tm["vcycles"], tm     # every coarse solve ran past column 63
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
 @pytest.mark.parametrize("name,mk,k,cond", CASES)
 @pytest.mark.parametrize("coarse", ["dense", "gmres"])
 def test_fgmres_solution(built, name, mk, k, cond, coarse):
