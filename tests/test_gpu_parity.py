@@ -28,6 +28,14 @@ CASES = [
 ]
 
 
+# 3D at the highest degree the fixed-size kernels cover (face blocks of 30 rows for
+# v&p-cond, the widest patch inverses)
+CASES_3D_K3 = [
+    ("hex2_k3_vp", lambda: cartesian_hexes(2), 3, "vp"),
+    ("hex2_k3_v", lambda: cartesian_hexes(2), 3, "v"),
+]
+
+
 @pytest.fixture(scope="module")
 def built():
     import paper_2009_13840_amd as H
@@ -69,7 +77,7 @@ def test_condensed_cells_and_rhs(built, name, mk, k, cond):
     torch.cuda.synchronize()
 
 
-@pytest.mark.parametrize("name,mk,k,cond", CASES)
+@pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3)
 def test_level_operators(built, name, mk, k, cond):
     import torch
     mesh, M, P, O = built(name, mk, k, cond)
@@ -80,7 +88,7 @@ def test_level_operators(built, name, mk, k, cond):
         assert _rel(y, S @ x) < 1e-12, (l, _rel(y, S @ x))
 
 
-@pytest.mark.parametrize("name,mk,k,cond", CASES)
+@pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3)
 def test_smoother_preconditioner(built, name, mk, k, cond):
     import torch
     import oracle.multilevel as ML
@@ -93,7 +101,7 @@ def test_smoother_preconditioner(built, name, mk, k, cond):
         assert _rel(z, prec(r)) < 1e-10, (l, _rel(z, prec(r)))
 
 
-@pytest.mark.parametrize("name,mk,k,cond", CASES)
+@pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3)
 def test_vcycle_matches_oracle(built, name, mk, k, cond):
     import torch
     import oracle.solve as OS
