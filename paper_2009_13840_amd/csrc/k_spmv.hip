@@ -165,6 +165,68 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T> L, const
   }
 }
 
+// Lowest degree, v&p-cond (d x d face blocks, one mean pressure per cell): G lanes
+// share a face row block (its blocks, read whole by one lane, and its two cells)
+// or a cell row (its faces), combined by shuffles.
+template <typename T, int BS, int G, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_vp0(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+                                                      const T *__restrict__ xs1, T *__restrict__ xsum,
+                                                      const T *__restrict__ b, T *__restrict__ y) {
+  const int64_t o = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
+  const int lane = threadIdx.x % G;
+  if (o >= (int64_t)tp.nf + tp.nc) return;  // uniform over the group
+  if (o < tp.nf) {
+    const int f = (int)o;
+    T acc[BS];
+#pragma unroll
+    for (int i = 0; i < BS; ++i) acc[i] = 0;
+    for (int bi = tp.rowptr[f] + lane; bi < tp.rowptr[f + 1]; bi += G) {
+      const T *blk = L.bsr + (int64_t)bi * (BS * BS);
+      const int64_t xo = (int64_t)tp.col[bi] * BS;
+      T xv[BS];
+#pragma unroll
+      for (int k = 0; k < BS; ++k) xv[k] = xface<T, SPLIT>(x, xs1, xo + k);
+#pragma unroll
+      for (int i = 0; i < BS; ++i)
+#pragma unroll
+        for (int k = 0; k < BS; ++k) acc[i] += blk[i * BS + k] * xv[k];
+    }
+    if (lane < 2) {
+      const int Tc = tp.fcell[2 * f + lane];
+      if (Tc >= 0) {
+        const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + lane];
+        const T xc = x[L.nface + Tc];
+#pragma unroll
+        for (int i = 0; i < BS; ++i) acc[i] += L.cpl[e * BS + i] * xc;
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < BS; ++i) acc[i] = group_sum<G>(acc[i]);
+    if (lane == 0) {
+#pragma unroll
+      for (int i = 0; i < BS; ++i) {
+        const int64_t r = (int64_t)f * BS + i;
+        y[r] = (MODE == 1) ? (T)(b[r] - acc[i]) : acc[i];
+        if (SPLIT && xsum) xsum[r] = x[r] + xs1[r];
+      }
+    }
+  } else {
+    const int Tc = (int)(o - tp.nf);
+    T acc = 0;
+    for (int e = tp.cptr[Tc] + lane; e < tp.cptr[Tc + 1]; e += G) {
+      const int64_t xo = (int64_t)tp.cface[e] * BS;
+#pragma unroll
+      for (int k = 0; k < BS; ++k) acc += L.cpl[(int64_t)e * BS + k] * xface<T, SPLIT>(x, xs1, xo + k);
+    }
+    acc = group_sum<G>(acc);
+    if (lane == 0) {
+      const int64_t r = L.nface + Tc;
+      y[r] = (MODE == 1) ? (T)(b[r] - acc) : acc;
+      if (SPLIT && xsum) xsum[r] = x[r];
+    }
+  }
+}
+
 template <typename T, int BS, bool SPLIT, int MODE>
 __global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const T *__restrict__ x,
                                                      const T *__restrict__ xs1, T *__restrict__ xsum,
@@ -228,8 +290,15 @@ bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T
     const int grid = (int)((total + bs - 1) / bs);
     hipLaunchKernelGGL((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   } else {
-    const int64_t total = (int64_t)tp.nf * D * P + tp.nc;
     const int bs = L.block > 0 ? L.block : kBlock;
+    if (K == 0) {
+      constexpr int G = 4;
+      const int64_t total = ((int64_t)tp.nf + tp.nc) * G;
+      const int grid = (int)((total + bs - 1) / bs);
+      hipLaunchKernelGGL((k_spmv_vp0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+      return true;
+    }
+    const int64_t total = (int64_t)tp.nf * D * P + tp.nc;
     const int grid = (int)((total + bs - 1) / bs);
     hipLaunchKernelGGL((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   }
