@@ -118,6 +118,45 @@ def test_vcycle_matches_oracle(built, name, mk, k, cond):
     assert _rel(x, xo) < 1e-9, _rel(x, xo)
 
 
+MIXED_CASES = [CASES[0], CASES[3], CASES[5], CASES_3D_K3[0]]
+
+
+@pytest.mark.parametrize("name,mk,k,cond", MIXED_CASES)
+def test_mixed_precision_vcycle(built, name, mk, k, cond):
+    """FP32 V-cycle (levels above the coarsest in FP32, coarsest in FP64) against
+    the oracle's FP64 V-cycle.  Tolerance: every FP32 quantity (operator, patch
+    inverses, vectors) carries a relative rounding of 2^-24 = 6e-8; a V-cycle
+    applies some tens of them with local condition numbers below 1e2, so the
+    result agrees to ~1e-5 of its largest entry; the test allows 1e-4."""
+    import torch
+    import oracle.solve as OS
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="dense", precision="fp32")
+    H = OS.hierarchy(O, coarse="direct")
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(O.S[0].shape[0])
+    if O.z[0] is not None:
+        b = OS.project_out(O.z[0])(b)
+    x = P.vcycle_apply(torch.from_numpy(b).cuda()).cpu().numpy()
+    xo = H.vcycle(0, b)
+    if O.z[0] is not None:
+        x, xo = OS.project_out(O.z[0])(x), OS.project_out(O.z[0])(xo)
+    err = _rel(x, xo)
+    assert 1e-9 < err < 1e-4, err          # FP32 arithmetic is really used, and it is close
+
+
+@pytest.mark.parametrize("name,mk,k,cond", MIXED_CASES)
+def test_mixed_precision_fgmres_solution(built, name, mk, k, cond):
+    """FGMRES in FP64 preconditioned by the FP32 V-cycle reaches the FP64 direct
+    solution (the flexible outer iteration absorbs the FP32 preconditioner)."""
+    import oracle.solve as OS
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="dense", precision="fp32", rtol=1e-11)
+    x, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-11
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
+    assert its <= 40
+
+
 AMG_CASES = [
     ("vor120_k2_v", lambda: voronoi_lloyd(120, 7), 2, "v"),
     ("vor120_k2_vp", lambda: voronoi_lloyd(120, 7), 2, "vp"),
