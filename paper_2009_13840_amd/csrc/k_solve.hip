@@ -183,8 +183,9 @@ __device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T 
   __syncthreads();
 }
 
-// The same product with the packed triangle already in LDS (patches of at most
-// 64 rows): one thread per output entry, no cross-lane reduction.
+// The same product for patches of at most 64 rows, with the packed triangle in
+// LDS (staged) or read in place (it stays in the L1/L2 caches after its first
+// touch): one thread per output entry, no cross-lane reduction.
 template <typename T, int DC>
 __device__ void sym_lds_apply(const T *S, int m, int p, const T *x, T *y) {
   const int n = m * DC;
@@ -193,6 +194,7 @@ __device__ void sym_lds_apply(const T *S, int m, int p, const T *x, T *y) {
     const int i = fi * p + rr;
     T acc = 0;
     int jf = 0, jr = 0;
+#pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const int lo = j < i ? j : i, hi = j < i ? i : j;
       acc += S[hi * (hi + 1) / 2 + lo] * x[(jf * DC + c) * p + jr];
@@ -252,6 +254,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
     const T *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
     // u1 = (s^{-1} (x) I) r_u
     if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, m, p, ru, u1);
+    else if constexpr (SM == 1) sym_lds_apply<T, DC>(Si, m, p, ru, u1);  // rows through L1, no reductions
     else sym_packed_apply<T, SM, DC>(Si, m, p, ru, u1, ydot);
     // y_p = X^{-1} (r_p - C^T u1); C^T u1 by lanes (part, q), parts = 64 / t taking
     // every parts-th row (coalesced rows of C), partials combined in order
@@ -259,6 +262,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
       const int parts = kWave / t, q = threadIdx.x % t, part = threadIdx.x / t;
       T acc = 0;
       if (part < parts)
+#pragma unroll 8
         for (int i = part; i < n; i += parts) acc += C[(int64_t)i * t + q] * u1[i];
       red[threadIdx.x] = acc;
       __syncthreads();
@@ -285,11 +289,13 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
     // w = r_u - C y_p ; y_u = (s^{-1} (x) I) w
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
       T acc = ru[i];
+#pragma unroll 8
       for (int q = 0; q < t; ++q) acc -= C[(int64_t)i * t + q] * yp[q];
       wv[i] = acc;
     }
     __syncthreads();
     if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, m, p, wv, u1);
+    else if constexpr (SM == 1) sym_lds_apply<T, DC>(Si, m, p, wv, u1);
     else sym_packed_apply<T, SM, DC>(Si, m, p, wv, u1, ydot);
   } else {
     const T *g = L.xinv + (int64_t)eb * dp;
