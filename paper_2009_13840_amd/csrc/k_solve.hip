@@ -183,11 +183,11 @@ __device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T 
   __syncthreads();
 }
 
-// The same product for patches of at most 64 rows, with the packed triangle in
-// LDS (staged) or read in place (it stays in the L1/L2 caches after its first
-// touch): one thread per output entry, no cross-lane reduction.
+// The same product for patches of at most 64 rows: one thread per output entry
+// walks its whole row through the packed index (the triangle stays in the L1/L2
+// caches after its first touch), no cross-lane reduction.
 template <typename T, int DC>
-__device__ void sym_lds_apply(const T *S, int m, int p, const T *x, T *y) {
+__device__ void sym_row_apply(const T *__restrict__ S, int m, int p, const T *x, T *y) {
   const int n = m * DC;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int fi = e / (DC * p), c = (e / p) % DC, rr = e % p;
@@ -231,12 +231,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   T *rpr = yp + t + 1;         // [t]
   T *ydot = rpr + t;           // [n]
   T *red = ydot + n;           // [64] partial sums
-  T *Sl = red + kWave;         // SM == 1, DC < 3: the packed patch inverse [rows (rows + 1) / 2]
-  const int rows = (L.cond == 1) ? m : n;
   const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)((L.cond == 1) ? p * p : dp * dp);  // packed lower triangle
-  if constexpr (SM == 1 && DC < 3) {  // all of the (small) inverse in flight at once
-    for (int q = threadIdx.x; q < rows * (rows + 1) / 2; q += blockDim.x) Sl[q] = Si[q];
-  }
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int fi = i / dp, k = i % dp;
     const int f = tp.cface[eb + fi];
@@ -253,8 +248,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   if (L.cond == 1) {
     const T *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
     // u1 = (s^{-1} (x) I) r_u
-    if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, m, p, ru, u1);
-    else if constexpr (SM == 1) sym_lds_apply<T, DC>(Si, m, p, ru, u1);  // rows through L1, no reductions
+    if constexpr (SM == 1) sym_row_apply<T, DC>(Si, m, p, ru, u1);
     else sym_packed_apply<T, SM, DC>(Si, m, p, ru, u1, ydot);
     // y_p = X^{-1} (r_p - C^T u1); C^T u1 by lanes (part, q), parts = 64 / t taking
     // every parts-th row (coalesced rows of C), partials combined in order
@@ -294,12 +288,11 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
       wv[i] = acc;
     }
     __syncthreads();
-    if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, m, p, wv, u1);
-    else if constexpr (SM == 1) sym_lds_apply<T, DC>(Si, m, p, wv, u1);
+    if constexpr (SM == 1) sym_row_apply<T, DC>(Si, m, p, wv, u1);
     else sym_packed_apply<T, SM, DC>(Si, m, p, wv, u1, ydot);
   } else {
     const T *g = L.xinv + (int64_t)eb * dp;
-    if constexpr (SM == 1 && DC < 3) sym_lds_apply<T, DC>(Sl, n, n, ru, u1);
+    if constexpr (SM == 1) sym_row_apply<T, DC>(Si, n, n, ru, u1);
     else sym_packed_apply<T, SM, DC>(Si, n, n, ru, u1, ydot);
     T part = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) part += g[i] * ru[i];
@@ -539,9 +532,7 @@ void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x
 }
 size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem) {
   const int n = max_faces * d * p;
-  const int rows = max_faces * ((cond == 1) ? p : d * p);  // of the packed patch inverse
-  const size_t staged = (rows <= 64 && !(cond == 1 && d == 3)) ? (size_t)rows * (rows + 1) / 2 : 0;
-  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2 + kWave + staged) * elem;
+  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2 + kWave) * elem;
 }
 template <typename T>
 void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
