@@ -135,13 +135,17 @@ __device__ void givens_column(GmresState *st, int j, int cgs2, double nn) {
   __syncthreads();
   const double hn = sqrt(nn);
   if (threadIdx.x == 0) {
+    // previous rotations; the running entry is carried in a register so that the
+    // loads of col, cs, sn do not wait on the stores
+    double a = col[0];
     for (int i = 0; i < j; ++i) {
-      const double a = col[i], b = col[i + 1];
+      const double b = col[i + 1];
       col[i] = cs[i] * a + sn[i] * b;
-      col[i + 1] = -sn[i] * a + cs[i] * b;
+      a = -sn[i] * a + cs[i] * b;
     }
+    col[j] = a;
     col[j + 1] = hn;
-    const double a = col[j], b = hn;
+    const double b = hn;
     const double rr = sqrt(a * a + b * b);
     const double c = (rr > 0) ? a / rr : 1.0, s_ = (rr > 0) ? b / rr : 0.0;
     st->cs[j] = c;
@@ -171,8 +175,8 @@ __device__ void givens_column(GmresState *st, int j, int cgs2, double nn) {
 // rotations and updates the residual estimate and the convergence flag; MODE 3
 // stores h1 and completes the column with |w|^2 - |h1|^2 as the new norm squared.
 template <int MODE>
-__global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const double *partial, GmresState *st,
-                                                        int cgs2) {
+__global__ void __launch_bounds__(1024) k_orth_finish(int G, int j, const double *partial, GmresState *st,
+                                                      int cgs2) {
   if (st->done) return;
   __shared__ double hs[kMaxRestartH + 1];
   const int nv = j + 1;
@@ -186,10 +190,11 @@ __global__ void __launch_bounds__(kBlock) k_orth_finish(int G, int j, const doub
     reduce_partials(partial, G, nv + 1, hs);
     for (int i = threadIdx.x; i < nv; i += blockDim.x) st->h1[i] = hs[i];
     __shared__ double nn;
-    if (threadIdx.x == 0) {
+    if (threadIdx.x < kWave) {
       double hh = 0;
-      for (int i = 0; i < nv; ++i) hh += hs[i] * hs[i];
-      nn = fmax(hs[nv] - hh, 0.0);
+      for (int i = threadIdx.x; i < nv; i += kWave) hh += hs[i] * hs[i];
+      hh = wave_sum(hh);
+      if (threadIdx.x == 0) nn = fmax(hs[nv] - hh, 0.0);
     }
     __syncthreads();
     givens_column(st, j, 0, nn);
@@ -228,8 +233,8 @@ void launch_mode(int64_t n, int j, const T *V, int64_t ldv, T *w, double *partia
     HHO_ORTH(64);
 #undef HHO_ORTH
   if (MODE != 4)
-    hipLaunchKernelGGL((k_orth_finish<MODE>), dim3(1), dim3(kBlock), 0, s, grid, j, (const double *)partial, st,
-                       cgs2);
+    hipLaunchKernelGGL((k_orth_finish<MODE>), dim3(1), dim3(1024), 0, s, grid, j, (const double *)partial, st,
+                       cgs2);  // 16 waves: about two sums per wave
 }
 
 // ---------------------------------------------------------------- batched problems
