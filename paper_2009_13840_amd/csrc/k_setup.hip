@@ -524,8 +524,11 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
   const int tr = tid / nt, tc = tid % nt;
   const bool own = tr < nt;
   const int r0 = tr * TILE, c0 = tc * TILE;
-  double *cb = lds;                        // [np] pivot column
-  double *ext = cb + (np > 16 ? np : 16);  // post-processing space
+  // two pivot-column buffers [np + 1] (entry np: the pivot's reciprocal), used
+  // alternately so that one barrier per pivot suffices
+  const int cbw = np + 1;
+  double *cbuf = lds;
+  double *ext = cbuf + (2 * cbw > 16 ? 2 * cbw : 16);  // post-processing space
   __shared__ int bad;
   if (tid == 0) bad = 0;
   const int32_t *pb = tp.pairblk + tp.pairoff[T];
@@ -544,20 +547,23 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
     }
   for (int k = 0; k < n; ++k) {  // scalar pivots; the pivot column goes through LDS
     const int kt = k / TILE, kw = k % TILE;
+    double *cb = cbuf + (k & 1) * cbw;
     if (own && tc == kt) {
 #pragma unroll
       for (int q = 0; q < TILE; ++q)
 #pragma unroll
         for (int w = 0; w < TILE; ++w)
-          if (w == kw) cb[r0 + q] = a[q][w];
+          if (w == kw) {
+            cb[r0 + q] = a[q][w];
+            if (tr == kt && q == kw) {  // the diagonal's owner: the reciprocal, once
+              const double dk = a[q][w];
+              if (!(dk > 0.0)) bad = 1;
+              cb[np] = (dk > 0.0) ? 1.0 / dk : 1.0;
+            }
+          }
     }
     __syncthreads();
-    double dk = cb[k];
-    if (!(dk > 0.0)) {
-      if (tid == 0) bad = 1;
-      dk = 1.0;
-    }
-    const double inv = 1.0 / dk;
+    const double inv = cb[np];
     if (own) {
       double ci[TILE], cj[TILE];
 #pragma unroll
@@ -586,8 +592,10 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
             if (w == kw) a[q][w] = (tr == kt && q == kw) ? -inv : ci[q];
       }
     }
-    __syncthreads();
+    // no second barrier: the next pivot writes the other column buffer, and every
+    // thread has read this one before it passes the next pivot's barrier
   }
+  __syncthreads();
   // S_P^{-1} = -a
   double *Si = sinv + tp.pairoff[T] * (int64_t)bs * bs;
   if (own) {
@@ -662,7 +670,7 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
       dot += b[i] * gi;
     }
     __syncthreads();
-    const double sdot = block_sum(dot, cb);
+    const double sdot = block_sum(dot, cbuf);
     if (tid == 0) {
       if (!(sdot > 0.0)) bad = 1;
       sig[T] = (sdot > 0.0) ? 1.0 / sdot : 0.0;
@@ -675,7 +683,7 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
 size_t patch_sweep_lds_bytes(int d, int cond, int p, int t, int max_faces, int tile) {
   const int64_t n = (int64_t)max_faces * ((cond == 1) ? p : d * p);
   const int64_t nt = (n + tile - 1) / tile;
-  int64_t w = std::max<int64_t>(nt * tile, 16);
+  int64_t w = std::max<int64_t>(2 * (nt * tile + 1), 16);  // two pivot-column buffers
   w += (cond == 1) ? n * n + (int64_t)d * n * t + (int64_t)t * t : nt * nt * tile;
   return (size_t)w * sizeof(double);
 }
