@@ -545,55 +545,52 @@ __global__ void __launch_bounds__(1024) k_patch_sweep(DTopo tp, int cond, int p,
       }
       a[q][w] = v;
     }
-  for (int k = 0; k < n; ++k) {  // scalar pivots; the pivot column goes through LDS
-    const int kt = k / TILE, kw = k % TILE;
-    double *cb = cbuf + (k & 1) * cbw;
-    if (own && tc == kt) {
+  // pivots k = kt TILE + W: the inner loop over W is unrolled, so the pivot's
+  // place inside a tile is a compile-time index (direct register accesses, no
+  // per-entry selects)
+  for (int kt = 0; kt * TILE < n; ++kt) {
 #pragma unroll
-      for (int q = 0; q < TILE; ++q)
+    for (int W = 0; W < TILE; ++W) {
+      const int k = kt * TILE + W;
+      if (k >= n) break;  // uniform
+      double *cb = cbuf + (k & 1) * cbw;
+      if (own && tc == kt) {
 #pragma unroll
-        for (int w = 0; w < TILE; ++w)
-          if (w == kw) {
-            cb[r0 + q] = a[q][w];
-            if (tr == kt && q == kw) {  // the diagonal's owner: the reciprocal, once
-              const double dk = a[q][w];
-              if (!(dk > 0.0)) bad = 1;
-              cb[np] = (dk > 0.0) ? 1.0 / dk : 1.0;
-            }
-          }
-    }
-    __syncthreads();
-    const double inv = cb[np];
-    if (own) {
-      double ci[TILE], cj[TILE];
-#pragma unroll
-      for (int q = 0; q < TILE; ++q) {
-        ci[q] = cb[r0 + q] * inv;
-        cj[q] = cb[c0 + q];
+        for (int q = 0; q < TILE; ++q) cb[r0 + q] = a[q][W];
+        if (tr == kt) {  // the diagonal's owner: the reciprocal, once
+          const double dk = a[W][W];
+          if (!(dk > 0.0)) bad = 1;
+          cb[np] = (dk > 0.0) ? 1.0 / dk : 1.0;
+        }
       }
-      // every entry: a_ij -= (a_ik / a_kk) a_kj (one FMA); the pivot row and
-      // column, held by one tile row and one tile column, are fixed up after
+      __syncthreads();
+      const double inv = cb[np];
+      if (own) {
+        double ci[TILE], cj[TILE];
 #pragma unroll
-      for (int q = 0; q < TILE; ++q)
-#pragma unroll
-        for (int w = 0; w < TILE; ++w) a[q][w] = fma(-ci[q], cj[w], a[q][w]);
-      if (tr == kt) {
+        for (int q = 0; q < TILE; ++q) {
+          ci[q] = cb[r0 + q] * inv;
+          cj[q] = cb[c0 + q];
+        }
+        // every entry: a_ij -= (a_ik / a_kk) a_kj (one FMA); the pivot row and
+        // column, held by one tile row and one tile column, are fixed up after
 #pragma unroll
         for (int q = 0; q < TILE; ++q)
 #pragma unroll
-          for (int w = 0; w < TILE; ++w)
-            if (q == kw) a[q][w] = cj[w] * inv;
-      }
-      if (tc == kt) {
+          for (int w = 0; w < TILE; ++w) a[q][w] = fma(-ci[q], cj[w], a[q][w]);
+        if (tr == kt) {
 #pragma unroll
-        for (int q = 0; q < TILE; ++q)
+          for (int w = 0; w < TILE; ++w) a[W][w] = cj[w] * inv;
+        }
+        if (tc == kt) {
 #pragma unroll
-          for (int w = 0; w < TILE; ++w)
-            if (w == kw) a[q][w] = (tr == kt && q == kw) ? -inv : ci[q];
+          for (int q = 0; q < TILE; ++q) a[q][W] = ci[q];
+          if (tr == kt) a[W][W] = -inv;
+        }
       }
+      // no second barrier: the next pivot writes the other column buffer, and
+      // every thread has read this one before it passes the next pivot's barrier
     }
-    // no second barrier: the next pivot writes the other column buffer, and every
-    // thread has read this one before it passes the next pivot's barrier
   }
   __syncthreads();
   // S_P^{-1} = -a
