@@ -42,7 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
     const int rb = tp.rowptr[f], re = tp.rowptr[f + 1];
     // U blocks in flight per step (small blocks: the loop is latency-bound);
     // a 1 x 1 block is its own mirror
-    constexpr int U = DP <= 4 ? 4 : DP <= 8 ? 2 : 1;
+    constexpr int U = DP <= 8 ? 4 : DP <= 16 ? 2 : 1;
     for (int b0 = rb; b0 < re; b0 += U) {
       int64_t fc[U], mb[U];
 #pragma unroll
