@@ -3,6 +3,12 @@
 // (vectors stored [row][component]), and the pressure / velocity split of the
 // block-triangular Stokes preconditioner
 //   y = -g / S_T,   x = AMG(f - C y).
+// The V-cycle is evaluated with B = A P (formed by the Galerkin setup): the
+// restricted residual after pre-smoothing is P^T r - B^T x, and prolongation with
+// the first post-sweep is x + P x_c + w D^{-1} (r - A x - B x_c) (4 launches per
+// level).  The levels from the first one with at most coarse_amg_explicit rows
+// down are applied as the explicit matrix of their V-cycle, formed at setup by
+// running the V-cycle on the identity columns (column-block kernels k_cols_*).
 #include <algorithm>
 #include <cmath>
 
