@@ -124,6 +124,8 @@ typedef struct {
   int32_t learned;     /* 1: reserve the learned fine-level smoother (hho_learned_*); 0 (default): no */
   int32_t coarse_amg_explicit; /* AMG levels with at most this many rows are applied as the explicit
                                   matrix of their V-cycle, formed at setup (2048; 0 = never; at most 4096) */
+  int32_t coarse_amg_psmooth;  /* AMG prolongator smoothing steps, at most: P = (I - w D^-1 A)^s T (1; 1 or 2;
+                                  a level takes one step where two would make the next operator too dense) */
 } hho_options;
 
 /* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the

@@ -15,10 +15,12 @@ that preconditioner, used to check the GPU implementation:
   neighbours when their members are)
 * lambda: 15 power-iteration steps v <- D^{-1} A v / |.| from the start vector
   v_i = frac(i * 2654435761 / 2^32) - 1/2, times 1.05 (estimate of rho(D^{-1} A))
-* tentative prolongator T (0/1), P = T - (omega/lambda) D^{-1} A T with
-  omega = 4/3, A_next = P^T A P, down to <= 128 unknowns, then a dense inverse;
-  coarsening stops earlier when A_next would hold more than 160 entries per row
-  (structurally), and such a coarsest level gets 6 damped-Jacobi sweeps from zero
+* tentative prolongator T (0/1), P = (I - (omega/lambda) D^{-1} A)^s T with
+  omega = 4/3 and s prolongator smoothing steps: the most, up to 1 (the
+  default) or 2 (on request), for which A_next = P^T A P holds at most 160 entries
+  per row (structurally); down to <= 128 unknowns, then a dense inverse; when no
+  s >= 1 keeps A_next that sparse coarsening stops, and such a coarsest level
+  gets 6 damped-Jacobi sweeps from zero
 * V-cycle with nu (default 2) damped-Jacobi sweeps of weight 4/(3 lambda) before
   and after the coarse correction
 * pressure Schur approximation  S_T = sum_{(f,c)} C[(f,c),T]^2 / S[(f,c),(f,c)]
@@ -71,8 +73,10 @@ def aggregate(A: sp.csr_matrix) -> np.ndarray:
 
 
 class SA:
-    def __init__(self, A: sp.csr_matrix, nu: int = 2):
+    def __init__(self, A: sp.csr_matrix, nu: int = 2, p_steps: int = 1):
         self.nu = nu
+        self.p_steps = p_steps
+        self.steps = []   # smoothing steps taken per level
         self.levels = []
         self.lams = []
         A = sp.csr_matrix(A)
@@ -85,16 +89,28 @@ class SA:
             if na >= A.shape[0]:
                 break
             T = sp.csr_matrix((np.ones(A.shape[0]), (np.arange(A.shape[0]), agg)), shape=(A.shape[0], na))
-            # structural pattern of the next operator (P pattern = T + A T)
+            # smoothing steps of this level: the most (<= p_steps) whose next operator
+            # stays below the density bound (structurally; P pattern: T, then P + A P
+            # per step); none fits: this level is the coarsest
             Ab = A.copy()
             Ab.data[:] = 1.0
-            Pb = (T + Ab @ T).tocsr()
-            Pb.data[:] = 1.0
-            if (Pb.T @ Ab @ Pb).nnz > MAX_ROW_NNZ * na:
+            steps = 0
+            for st in range(p_steps, 0, -1):
+                Pb = T.copy()
+                for _ in range(st):
+                    Pb = (Pb + Ab @ Pb).tocsr()
+                    Pb.data[:] = 1.0
+                if (Pb.T @ Ab @ Pb).nnz <= MAX_ROW_NNZ * na:
+                    steps = st
+                    break
+            if steps == 0:
                 break
             D = A.diagonal()
             lam = spectral_radius_estimate(A)
-            P = (T - (OMEGA_SA / lam) * (sp.diags(1.0 / D) @ A @ T)).tocsr()
+            P = T
+            for _ in range(steps):
+                P = (P - (OMEGA_SA / lam) * (sp.diags(1.0 / D) @ (A @ P))).tocsr()
+            self.steps.append(steps)
             self.levels.append((A, P, 1.0 / D))
             self.lams.append(lam)
             A = (P.T @ A @ P).tocsr()
@@ -134,13 +150,13 @@ class SA:
 class BlockStokesPrec:
     """Block-triangular preconditioner of the coarsest (k = 0) level."""
 
-    def __init__(self, S: sp.csr_matrix, nface_dofs: int, d: int, nu: int = 2):
+    def __init__(self, S: sp.csr_matrix, nface_dofs: int, d: int, nu: int = 2, p_steps: int = 1):
         S = sp.csr_matrix(S)
         self.nf, self.d = nface_dofs, d
         nfaces = nface_dofs // d
         blocks = [S[c:nface_dofs:d][:, c:nface_dofs:d] for c in range(d)]
         s = sum(blocks[1:], blocks[0]) / d
-        self.amg = SA(s.tocsr(), nu)
+        self.amg = SA(s.tocsr(), nu, p_steps)
         C = S[:nface_dofs, nface_dofs:].tocsc()
         diagA = S.diagonal()[:nface_dofs]
         Sd = np.asarray((C.multiply(C)).T @ (1.0 / diagA)).ravel()

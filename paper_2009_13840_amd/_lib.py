@@ -50,7 +50,7 @@ class Options(C.Structure):
                 ("smooth_its", C.c_int32), ("precision", C.c_int32), ("coarse_mode", C.c_int32),
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_max_it", C.c_int32),
                 ("quad_extra", C.c_int32), ("coarse_amg_sweeps", C.c_int32), ("learned", C.c_int32),
-                ("coarse_amg_explicit", C.c_int32)]
+                ("coarse_amg_explicit", C.c_int32), ("coarse_amg_psmooth", C.c_int32)]
 
 
 FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),

@@ -23,6 +23,11 @@ struct AmgHostLevel {
   std::vector<int32_t> prp, pci;         // P pattern (n x nc)
   std::vector<int32_t> pgp, pgi;         // A entries summed into each P entry
   std::vector<int32_t> pself;            // 1 where the entry is the tentative injection
+  int np1 = 0;                           // two smoothing steps: entries of P_1 (the gathers
+                                         // above, pself, p1row refer to P_1), else 0
+  std::vector<int32_t> p1row;            // row of every P_1 entry
+  std::vector<int32_t> qpp, qpa, qpb;    // B_1 = A P_1 in the final P pattern: pairs (A entry, P_1 entry)
+  std::vector<int32_t> p2src;            // final P entry -> its P_1 entry, or -1
   std::vector<int32_t> ptp, pti, pte;    // P^T by coarse row: fine row, P entry
   std::vector<int32_t> brp, bci;         // B = A P pattern
   std::vector<int32_t> bpp, bpa, bpb;    // B pairs (A entry, P entry)
@@ -34,6 +39,6 @@ struct AmgHost {
   std::vector<AmgHostLevel> levels;
 };
 
-void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, AmgHost *H);
+void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, int p_steps, AmgHost *H);
 
 }  // namespace hho

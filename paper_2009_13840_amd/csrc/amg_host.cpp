@@ -7,8 +7,9 @@
 // unaggregated row in index order opens an aggregate holding itself and its
 // unaggregated neighbours in the aggregation graph G_l, with G_0 the pattern of
 // A_0 and G_{l+1} the pattern of T^T G_l T), the pattern of P = T - w D^{-1} A T (T the 0/1
-// aggregate injection), and the gather lists that evaluate
-//   P        (entries of A summed per (row, aggregate)),
+// aggregate injection; with two smoothing steps P = P_1 - w D^{-1} A P_1 from that
+// P_1), and the gather lists that evaluate
+//   P        (entries of A summed per (row, aggregate); second step: pairs of A P_1),
 //   B = A P  (pairs (A entry, P entry)),
 //   A_{l+1} = P^T B  (pairs (P entry, B entry)).
 #include <algorithm>
@@ -45,7 +46,7 @@ struct RowGroups {
   }
 };
 
-void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, AmgHost *H) {
+void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, int p_steps, AmgHost *H) {
   H->levels.clear();
   std::vector<int32_t> rp(rp0, rp0 + n0 + 1), ci(ci0, ci0 + rp0[n0]);
   std::vector<int32_t> grp = rp, gci = ci;  // aggregation graph (pattern of T^T G T)
@@ -97,13 +98,45 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
     L.pself.resize(L.pci.size());
     for (int i = 0; i < n; ++i)
       for (int e = L.prp[i]; e < L.prp[i + 1]; ++e) L.pself[e] = (L.pci[e] == L.agg[i]) ? 1 : 0;
+    // second smoothing step: with P_1 as above and B_1 = A P_1 (pairs (A entry,
+    // P_1 entry)), P = P_1 - w D^{-1} B_1 on the pattern of B_1, which holds that
+    // of P_1 (A has its diagonal); p2src gives each entry's P_1 entry or -1
+    auto second_step = [&]() {
+      L.np1 = (int)L.pci.size();
+      L.p1row.resize(L.np1);
+      for (int i = 0; i < n; ++i)
+        for (int e = L.prp[i]; e < L.prp[i + 1]; ++e) L.p1row[e] = i;
+      std::vector<int32_t> qrp(1, 0), qci;
+      L.qpp.clear();
+      L.qpa.clear();
+      L.qpb.clear();
+      for (int i = 0; i < n; ++i) {
+        for (int e = rp[i]; e < rp[i + 1]; ++e) {
+          const int j = ci[e];
+          for (int pe = L.prp[j]; pe < L.prp[j + 1]; ++pe) rg.add(L.pci[pe], e, pe);
+        }
+        rg.flush(qci, L.qpp, L.qpa, &L.qpb);
+        qrp.push_back((int32_t)qci.size());
+      }
+      L.qpp.push_back((int32_t)L.qpa.size());
+      L.p2src.assign(qci.size(), -1);
+      for (int i = 0; i < n; ++i) {  // both rows sorted by column
+        int e1 = L.prp[i];
+        for (int e = qrp[i]; e < qrp[i + 1]; ++e) {
+          while (e1 < L.prp[i + 1] && L.pci[e1] < qci[e]) ++e1;
+          if (e1 < L.prp[i + 1] && L.pci[e1] == qci[e]) L.p2src[e] = e1;
+        }
+      }
+      L.prp.swap(qrp);
+      L.pci.swap(qci);
+    };
     // P^T (by coarse column): rows i and P entry indices, rows ascending
-    L.ptp.assign(na + 1, 0);
-    for (size_t e = 0; e < L.pci.size(); ++e) ++L.ptp[L.pci[e] + 1];
-    for (int I = 0; I < na; ++I) L.ptp[I + 1] += L.ptp[I];
-    L.pti.resize(L.pci.size());
-    L.pte.resize(L.pci.size());
-    {
+    auto transpose_p = [&]() {
+      L.ptp.assign(na + 1, 0);
+      for (size_t e = 0; e < L.pci.size(); ++e) ++L.ptp[L.pci[e] + 1];
+      for (int I = 0; I < na; ++I) L.ptp[I + 1] += L.ptp[I];
+      L.pti.resize(L.pci.size());
+      L.pte.resize(L.pci.size());
       std::vector<int32_t> fill(L.ptp.begin(), L.ptp.end() - 1);
       for (int i = 0; i < n; ++i)
         for (int e = L.prp[i]; e < L.prp[i + 1]; ++e) {
@@ -111,11 +144,10 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
           L.pti[q] = i;
           L.pte[q] = e;
         }
-    }
-    // stop when the next operator would be nearly dense (three-dimensional
-    // meshes fill in quickly): this level becomes the coarsest, handled by
-    // Jacobi sweeps (or the dense inverse when small)
-    {
+    };
+    // the next operator P^T A P would be nearly dense (three-dimensional meshes
+    // fill in quickly), counted structurally
+    auto too_dense = [&]() {
       std::vector<int32_t> mark(na, -1);
       int64_t cnt = 0;
       for (int I = 0; I < na; ++I)
@@ -128,16 +160,42 @@ void amg_symbolic(int n0, const int32_t *rp0, const int32_t *ci0, int coarsest, 
                 ++cnt;
               }
         }
-      if (cnt > (int64_t)kAmgMaxRowNnz * na) {
-        AmgHostLevel C;
-        C.n = L.n;
-        C.nc = 0;
-        C.rp.swap(L.rp);
-        C.ci.swap(L.ci);
-        C.diag.swap(L.diag);
-        H->levels.push_back(std::move(C));
-        break;
+      return cnt > (int64_t)kAmgMaxRowNnz * na;
+    };
+    // the most smoothing steps (<= p_steps) that keep the next operator below
+    // the density bound; if even one step does not, this level becomes the
+    // coarsest (Jacobi sweeps, or the dense inverse when small)
+    L.np1 = 0;
+    bool dense = true;
+    if (p_steps == 2) {
+      const std::vector<int32_t> prp1 = L.prp, pci1 = L.pci;
+      second_step();
+      transpose_p();
+      dense = too_dense();
+      if (dense) {  // back to one step
+        L.prp = prp1;
+        L.pci = pci1;
+        L.np1 = 0;
+        L.p1row.clear();
+        L.qpp.clear();
+        L.qpa.clear();
+        L.qpb.clear();
+        L.p2src.clear();
       }
+    }
+    if (dense) {
+      transpose_p();
+      dense = too_dense();
+    }
+    if (dense) {
+      AmgHostLevel C;
+      C.n = L.n;
+      C.nc = 0;
+      C.rp.swap(L.rp);
+      C.ci.swap(L.ci);
+      C.diag.swap(L.diag);
+      H->levels.push_back(std::move(C));
+      break;
     }
     // B = A P : pattern + pairs (A entry, P entry)
     L.brp.assign(1, 0);

@@ -19,6 +19,12 @@ struct AmgDevLevel {
   double *val = nullptr, *dinv = nullptr, *lam = nullptr;
   const int32_t *prp = nullptr, *pci = nullptr, *prow = nullptr, *pgp = nullptr, *pgi = nullptr, *pself = nullptr;
   double *pval = nullptr;
+  // two prolongator smoothing steps (np1 > 0): P_1 (np1 entries, gathered by
+  // pgp/pgi/pself, rows p1row), B_1 = A P_1 on the final P pattern (pairs
+  // qpp/qpa/qpb), P = P_1 (via p2src) - w D^{-1} B_1
+  int np1 = 0;
+  const int32_t *p1row = nullptr, *qpp = nullptr, *qpa = nullptr, *qpb = nullptr, *p2src = nullptr;
+  double *pval1 = nullptr, *qval = nullptr;
   const int32_t *ptp = nullptr, *pti = nullptr, *pte = nullptr;
   const int32_t *bpp = nullptr, *bpa = nullptr, *bpb = nullptr;
   const int32_t *brp = nullptr, *bci = nullptr;              // B = A P by rows

@@ -93,6 +93,15 @@ __global__ void __launch_bounds__(kBlock) k_amg_power_finish(int G, const double
   if (threadIdx.x == 0) lam_out[0] = safety * sqrt(tot[0]);
 }
 
+// second smoothing step: P = P_1 - (omega / lambda) D^{-1} B_1 with B_1 = A P_1
+// on the final pattern (src: the entry's P_1 entry, or -1)
+__global__ void k_amg_p2(int64_t npe, const int32_t *src, const int32_t *prow, const double *p1, const double *b1,
+                         const double *dinv, const double *lam, double *pval) {
+  const double w = kAmgOmegaSA / lam[0];
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < npe; e += (int64_t)gridDim.x * blockDim.x)
+    pval[e] = (src[e] >= 0 ? p1[src[e]] : 0.0) - w * dinv[prow[e]] * b1[e];
+}
+
 // P = T - (omega / lambda) D^{-1} A T
 __global__ void k_amg_p(int64_t npe, const int32_t *prow, const int32_t *pgp, const int32_t *pgi,
                         const int32_t *pself, const double *val, const double *dinv, const double *lam,
@@ -607,8 +616,18 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
     hipLaunchKernelGGL(k_amg_power_finish, dim3(1), dim3(kBlock), 0, s, nb,
                        (const double *)(A.partial + ((kAmgPowerSteps - 1) % 2) * 256), L.lam, kAmgLambdaSafety);
     if (l == A.nlev - 1) break;  // large coarsest level: Jacobi sweeps only
-    hipLaunchKernelGGL(k_amg_p, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.prow, L.pgp, L.pgi, L.pself,
-                       L.val, L.dinv, L.lam, L.pval);
+    if (L.np1 > 0) {  // two smoothing steps
+      hipLaunchKernelGGL(k_amg_p, dim3(grid_for(L.np1)), dim3(kBlock), 0, s, (int64_t)L.np1, L.p1row, L.pgp, L.pgi,
+                         L.pself, L.val, L.dinv, L.lam, L.pval1);
+      hipLaunchKernelGGL(k_amg_pairs, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.qpp, L.qpa, L.qpb,
+                         (const double *)L.val, (const double *)L.pval1, L.qval);
+      hipLaunchKernelGGL(k_amg_p2, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.p2src, L.prow,
+                         (const double *)L.pval1, (const double *)L.qval, (const double *)L.dinv,
+                         (const double *)L.lam, L.pval);
+    } else {
+      hipLaunchKernelGGL(k_amg_p, dim3(grid_for(L.npe)), dim3(kBlock), 0, s, L.npe, L.prow, L.pgp, L.pgi, L.pself,
+                         L.val, L.dinv, L.lam, L.pval);
+    }
     hipLaunchKernelGGL(k_amg_pairs, dim3(grid_for(L.nbe)), dim3(kBlock), 0, s, L.nbe, L.bpp, L.bpa, L.bpb,
                        (const double *)L.val, (const double *)L.pval, L.bval);
     const AmgDevLevel &N = A.lev[l + 1];

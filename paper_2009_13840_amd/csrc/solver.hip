@@ -258,6 +258,16 @@ static void plan(hho_problem *P, Arena &A) {
         G.pgi = A.take<int32_t>(H.pgi.size());
         G.pself = A.take<int32_t>(H.pself.size());
         G.pval = A.take<double>(G.npe);
+        G.np1 = H.np1;
+        if (H.np1 > 0) {
+          G.p1row = A.take<int32_t>(H.p1row.size());
+          G.qpp = A.take<int32_t>(H.qpp.size());
+          G.qpa = A.take<int32_t>(H.qpa.size());
+          G.qpb = A.take<int32_t>(H.qpb.size());
+          G.p2src = A.take<int32_t>(H.p2src.size());
+          G.pval1 = A.take<double>(H.np1);
+          G.qval = A.take<double>(G.npe);
+        }
         G.ptp = A.take<int32_t>(H.ptp.size());
         G.pti = A.take<int32_t>(H.pti.size());
         G.pte = A.take<int32_t>(H.pte.size());
@@ -505,7 +515,8 @@ static void init_levels(hho_problem *P) {
 // symbolic smoothed-aggregation hierarchy of the coarsest level (topology only)
 static void amg_levels(hho_problem *P) {
   if (!P->coarse_amg || !P->amgh.levels.empty()) return;
-  amg_symbolic((int)P->mesh->nf, P->rowptr.data(), P->col.data(), kAmgCoarsest, &P->amgh);
+  amg_symbolic((int)P->mesh->nf, P->rowptr.data(), P->col.data(), kAmgCoarsest, P->opt.coarse_amg_psmooth,
+               &P->amgh);
   if ((int)P->amgh.levels.size() > kMaxAmgLevels) fail(HHO_E_INVALID_ARG, "AMG hierarchy too deep");
 }
 
@@ -564,6 +575,13 @@ static void device_upload(hho_problem *P) {
         h2d((void *)G.pgp, H.pgp.data(), H.pgp.size() * 4);
         h2d((void *)G.pgi, H.pgi.data(), H.pgi.size() * 4);
         h2d((void *)G.pself, H.pself.data(), H.pself.size() * 4);
+        if (H.np1 > 0) {
+          h2d((void *)G.p1row, H.p1row.data(), H.p1row.size() * 4);
+          h2d((void *)G.qpp, H.qpp.data(), H.qpp.size() * 4);
+          h2d((void *)G.qpa, H.qpa.data(), H.qpa.size() * 4);
+          h2d((void *)G.qpb, H.qpb.data(), H.qpb.size() * 4);
+          h2d((void *)G.p2src, H.p2src.data(), H.p2src.size() * 4);
+        }
         h2d((void *)G.ptp, H.ptp.data(), H.ptp.size() * 4);
         h2d((void *)G.pti, H.pti.data(), H.pti.size() * 4);
         h2d((void *)G.pte, H.pte.data(), H.pte.size() * 4);
@@ -1072,6 +1090,7 @@ void hho_options_default(hho_options *o) {
   o->coarse_amg_sweeps = 2;
   o->learned = 0;
   o->coarse_amg_explicit = 2048;
+  o->coarse_amg_psmooth = 1;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -1123,6 +1142,8 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   P->amg_nu = P->opt.coarse_amg_sweeps;
   if (P->opt.coarse_amg_explicit < 0 || P->opt.coarse_amg_explicit > hho::kAmgExplicitMax)
     hho::fail(HHO_E_INVALID_ARG, "coarse_amg_explicit must be in 0..4096");
+  if (P->opt.coarse_amg_psmooth < 1 || P->opt.coarse_amg_psmooth > 2)
+    hho::fail(HHO_E_INVALID_ARG, "coarse_amg_psmooth must be 1 or 2");
   if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
   if (P->opt.learned != 0 && P->opt.learned != 1) hho::fail(HHO_E_INVALID_ARG, "learned must be 0 or 1");

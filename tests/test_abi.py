@@ -56,7 +56,8 @@ def test_problem_argument_validation():
     M = H.Mesh(cartesian_quads(2))
     for kw in (dict(k=-1), dict(k=7), dict(k=2, degrees=[2, 2, 0]), dict(k=2, degrees=[1, 0]),
                dict(k=1, restart=0), dict(k=1, smooth_its=3), dict(k=1, coarse_amg_sweeps=3),
-               dict(k=1, coarse_amg_explicit=-1), dict(k=1, coarse_amg_explicit=4097)):
+               dict(k=1, coarse_amg_explicit=-1), dict(k=1, coarse_amg_explicit=4097),
+               dict(k=1, coarse_amg_psmooth=0), dict(k=1, coarse_amg_psmooth=3)):
         k = kw.pop("k")
         with pytest.raises(H.HHOError) as e:
             H.Problem(M, k, "v", **kw)

@@ -167,17 +167,20 @@ AMG_CASES = [
 ]
 
 
+@pytest.mark.parametrize("psmooth", [1, 2])
 @pytest.mark.parametrize("explicit", [2048, 0])
 @pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
-def test_coarse_block_preconditioner(built, name, mk, k, cond, explicit):
+def test_coarse_block_preconditioner(built, name, mk, k, cond, explicit, psmooth):
     """Coarsest-level block-triangular preconditioner with the smoothed-aggregation
     velocity block: GPU vs the oracle's plain definition, with the small AMG levels
-    applied as their explicit V-cycle matrix (2048) and level by level (0)."""
+    applied as their explicit V-cycle matrix (2048) and level by level (0), with
+    two prolongator smoothing steps (where the density bound allows) and one."""
     import torch
     from oracle.amg import BlockStokesPrec
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_explicit=explicit)
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_explicit=explicit,
+                          coarse_amg_psmooth=psmooth)
     L = len(O.S) - 1
-    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim)
+    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, p_steps=psmooth)
     assert len(prec.amg.sizes) >= 2
     rng = np.random.default_rng(3)
     v = rng.standard_normal(O.S[L].shape[0])

@@ -60,6 +60,42 @@ def _contraction(A, S, reps=6, seed=0):
 
 def test_vcycle_contracts_on_poisson():
     for A, bound in ((poisson(48, 2), 0.3), (poisson(16, 3), 0.35)):
-        S = AM.SA(A)
-        assert len(S.levels) >= 1
-        assert _contraction(A, S) < bound
+        for p_steps in (1, 2):
+            S = AM.SA(A, p_steps=p_steps)
+            assert len(S.levels) >= 1
+            assert _contraction(A, S) < bound, p_steps
+
+
+def test_second_smoothing_step_strengthens_the_cycle():
+    """A second prolongator smoothing step widens P by one ring of neighbours
+    (structurally, P_2 = pattern of P_1 + A P_1) and contracts faster on the 2D
+    model problem."""
+    A = poisson(48, 2)
+    S1, S2 = AM.SA(A, p_steps=1), AM.SA(A, p_steps=2)
+    assert S2.steps[0] == 2 and S1.steps[0] == 1
+    P1, P2 = S1.levels[0][1], S2.levels[0][1]
+    Ab = A.copy()
+    Ab.data[:] = 1.0
+    P1b = P1.copy()
+    P1b.data[:] = 1.0
+    pat = (P1b + Ab @ P1b).tocsr()
+    pat.data[:] = 1.0
+    P2b = P2.copy()
+    P2b.eliminate_zeros()
+    P2b.data[:] = 1.0
+    outside = (P2b - P2b.multiply(pat)).tocsr()
+    outside.eliminate_zeros()
+    assert outside.nnz == 0                     # P_2 lies within the widened pattern
+    assert P2b.nnz > P1.nnz
+    assert _contraction(A, S2) < _contraction(A, S1)
+
+
+def test_smoothing_steps_fall_back_before_a_dense_level():
+    """On 3D grids two smoothing steps would make the next operator too dense:
+    the level takes one step instead of stopping the coarsening."""
+    A = poisson(16, 3)
+    S = AM.SA(A, p_steps=2)
+    for Al, _, _ in S.levels[1:]:
+        assert Al.nnz <= AM.MAX_ROW_NNZ * Al.shape[0]
+    assert all(st in (1, 2) for st in S.steps)
+    assert len(S.levels) >= 1
