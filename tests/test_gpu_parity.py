@@ -289,6 +289,48 @@ def test_fgmres_solution(built, name, mk, k, cond, coarse):
     assert its <= 40 and hist[0] == 1.0
 
 
+DEGENERATE_CASES = [
+    ("quad1_k0_v", lambda: cartesian_quads(1), 0, "v"),       # one cell, one level (bordered dense solve)
+    ("hex1_k0_vp", lambda: cartesian_hexes(1), 0, "vp"),
+    ("quad4_k0_v", lambda: cartesian_quads(4), 0, "v"),       # one level: the V-cycle is the coarse solve
+    ("quad2_k2_vp", lambda: cartesian_quads(2), 2, "vp"),     # the smallest multilevel case (4 cells)
+    ("hex2_k1_v_two_levels", lambda: cartesian_hexes(2), 1, "v"),
+]
+
+
+@pytest.mark.parametrize("name,mk,k,cond", DEGENERATE_CASES)
+def test_degenerate_problems(built, name, mk, k, cond):
+    """Single-cell meshes, a single-level hierarchy and the smallest multilevel
+    meshes: level operators, and FGMRES reaching the direct solution."""
+    import torch
+    import oracle.solve as OS
+    mesh, M, P, O = built(name, mk, k, cond, rtol=1e-11)
+    rng = np.random.default_rng(9)
+    for l, S in enumerate(O.S):
+        x = rng.standard_normal(S.shape[0])
+        y = P.level_apply(l, torch.from_numpy(x).cuda()).cpu().numpy()
+        assert _rel(y, S @ x) < 1e-12, (l, _rel(y, S @ x))
+    x, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-11
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
+
+
+def test_single_cell_patch_holding_the_pressure_null_space_is_reported():
+    """With one cell and k >= 1 the only smoother patch holds the constant
+    pressure, the null space of the all-Dirichlet problem, so it is singular:
+    setup fails with HHO_E_LOCAL_SINGULAR instead of producing a garbage smoother."""
+    import paper_2009_13840_amd as H
+    mesh = cartesian_quads(1)
+    data = problem_data(polynomial_stokes(2, 2, 3), None, 2)
+    P = H.Problem(H.Mesh(mesh), 1, "v")
+    P.set_data(*data)
+    P.bind("cuda:0")
+    with pytest.raises(H.HHOError) as e:
+        P.setup()
+    assert "not invertible" in str(e.value)
+
+
 def test_autotune_keeps_solution(built):
     """The autotuner only changes launch shapes: the solve still reaches the direct solution."""
     import oracle.solve as OS
