@@ -189,6 +189,17 @@ int hho_level_size(const hho_problem *p, int level, int64_t *n);
  * Errors: HHO_E_NOT_CONVERGED (outputs written), HHO_E_BREAKDOWN, HHO_E_DEVICE. */
 int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel);
 
+/* Back-substitution of the cell unknowns eliminated by static condensation
+ * (Section 4.1.2): from the level-0 solution x_dev of hho_solve (device, global
+ * layout), cell_u_dev [n_cells x d*n_T] receives the cell velocity modes
+ * (component c, mode j at c*n_T + j), from the first block row of eq. def:HHOAB
+ * for v-cond; cell_p_dev [n_cells x n_T] the full cell pressure modes: for v-cond
+ * a copy of x's, for v&p-cond the kept mean mode and the non-mean modes from the
+ * eliminated block of eq. ST.2.  Device buffers, owned by the caller, on the
+ * problem's stream; returns after the kernel has finished.  Requires hho_setup.
+ * Errors: HHO_E_INVALID_ARG (NULL pointer, no setup), HHO_E_LOCAL_SINGULAR. */
+int hho_recover_cells(hho_problem *p, const double *x_dev, double *cell_u_dev, double *cell_p_dev);
+
 /* ---- inspection and kernel-level entry points (parity tests, benchmarks) ---- */
 
 /* Condensed right-hand side of level 0 (device, [level-0 size]). */

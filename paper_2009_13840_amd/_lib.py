@@ -29,7 +29,7 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
            "hho_learned_collect", "hho_learned_grad", "hho_learned_train", "hho_mesh_create_union",
-           "hho_problem_set_segments", "hho_batch_results", "hho_autotune"]
+           "hho_problem_set_segments", "hho_batch_results", "hho_autotune", "hho_recover_cells"]
 
 
 class HHOError(RuntimeError):
@@ -86,6 +86,7 @@ def load():
         "hho_level_size": ([P, I32, C.POINTER(I64)], I32),
         "hho_solve": ([P, P, C.POINTER(C.c_int), D, I32, D], I32),
         "hho_get_rhs": ([P, P], I32),
+        "hho_recover_cells": ([P, P, P, P], I32),
         "hho_get_condensed_cell": ([P, I64, D, D, I64, C.POINTER(I64)], I32),
         "hho_get_local_cell": ([P, I64, D, D, D, D, I64, C.POINTER(I64)], I32),
         "hho_level_apply": ([P, I32, P, P], I32),
@@ -316,6 +317,21 @@ class Problem:
         b = self._vec(self.level_size(0))
         _check(load().hho_get_rhs(self.h, C.c_void_p(b.data_ptr())))
         return b
+
+    def recover_cells(self, x):
+        """Cell velocities [n_cells, d*n_T] and full cell pressures [n_cells, n_T]
+        (device tensors) from the level-0 solution x."""
+        import torch
+        from math import comb
+        d = self.mesh.dim
+        nT = comb(self.k + d, d)
+        nc = self.mesh.n_cells
+        assert x.dtype == torch.float64 and x.is_contiguous() and x.numel() == self.level_size(0)
+        u = torch.empty((nc, d * nT), dtype=torch.float64, device=x.device)
+        p = torch.empty((nc, nT), dtype=torch.float64, device=x.device)
+        _check(load().hho_recover_cells(self.h, C.c_void_p(x.data_ptr()), C.c_void_p(u.data_ptr()),
+                                        C.c_void_p(p.data_ptr())))
+        return u, p
 
     def condensed_cell(self, c: int):
         n = C.c_int64()

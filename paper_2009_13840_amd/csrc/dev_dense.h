@@ -43,6 +43,18 @@ __device__ inline void blk_fwd(const double *L, int n, int lda, double *B, int n
   }
 }
 
+// Backward substitution L^T y = b on ncol columns of B (layout as blk_fwd).
+__device__ inline void blk_bwd(const double *L, int n, int lda, double *B, int ncol, int64_t cs, int64_t rs) {
+  for (int c = threadIdx.x; c < ncol; c += blockDim.x) {
+    double *b = B + c * cs;
+    for (int i = n - 1; i >= 0; --i) {
+      double v = b[i * rs];
+      for (int k = i + 1; k < n; ++k) v -= L[k * lda + i] * b[k * rs];
+      b[i * rs] = v / L[i * lda + i];
+    }
+  }
+}
+
 // X = (L L^T)^{-1} (n x n, leading dimension ldx), one column per thread.
 __device__ inline void blk_chol_inverse(const double *L, int n, int lda, double *X, int ldx) {
   for (int c = threadIdx.x; c < n; c += blockDim.x) {

@@ -57,6 +57,11 @@ size_t patch_lds_bytes(int d, int cond, int p, int t, int max_faces);
 void launch_condense(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
                      double *stage, double *cpl, double *spp, double *rhs_stage, double *rhs_p, int *err,
                      hipStream_t s, size_t lds);
+// Cell unknowns from the solved globally coupled ones x (level-0 layout):
+// cu [nc][d*nT] velocities (component-major), cp [nc][nT] full pressures.
+size_t recover_lds_bytes(int d, int nT, int nF, int max_faces);
+void launch_recover(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
+                    const double *x, double *cu, double *cp, int *err, hipStream_t s, size_t lds);
 void launch_assemble(const DTopo &tp, int cond, int nF, int64_t nnzb, const double *stage, double *bsr,
                      const double *rhs_stage, double *rhs, hipStream_t s);
 void launch_extract(const DTopo &tp, int cond, int64_t nnzb, int p0, int t0, int p1, int t1, const double *bsr0,

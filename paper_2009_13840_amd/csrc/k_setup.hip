@@ -172,6 +172,115 @@ __global__ void __launch_bounds__(kBlock) k_condense(DTopo tp, int cond, int nT,
   if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
 }
 
+// ------------------------------------------------------------ cell recovery
+// Back-substitution of the eliminated cell unknowns from the solved globally
+// coupled ones (Section 4.1.2), one block per cell, from the cell's record:
+//  v-cond, first block row of eq. def:HHOAB:
+//    a_TT U_T,c = f_c - a_Td U_dT,c - B_c,TT^T P_T.
+//  v&p-cond, the eliminated block of eq. ST.2 with the mean pressure Pbar known:
+//    r_c = f_c - a_Td U_dT,c - B_c,TT[0]^T Pbar,  s = rp[1:] - B~_d U_dT,
+//    with L the Cholesky factor of a_TT, Y_c = L^{-1} B_c,TT^T, g_c = L^{-1} r_c
+//    and Sigma = sum_c Y~_c^T Y~_c (non-mean columns), the non-mean pressures
+//    solve Sigma P~ = sum_c Y~_c^T g_c - s and U_T,c = L^{-T} (g_c - Y~_c P~).
+__global__ void __launch_bounds__(kBlock) k_recover(DTopo tp, int cond, int nT, int nF, const double *rec,
+                                                    const int64_t *roff, const double *x, double *cu, double *cp,
+                                                    int *err) {
+  extern __shared__ double lds[];
+  const int T = blockIdx.x;
+  const int d = tp.d;
+  const int64_t c0 = tp.cptr[T];
+  const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+  const int m = nfc * nF, nloc = nT + m, n1 = nT - 1;
+  const int np = (cond == 1) ? nT : 1;
+  const double *a = rec + roff[T];
+  const double *B = a + (int64_t)nloc * nloc;
+  const double *ru = B + (int64_t)d * nT * nloc;
+  const double *rp = ru + (int64_t)d * nloc;
+  const double *xp = x + (int64_t)tp.nf * d * nF + (int64_t)T * np;
+  // LDS: L [nT][nT], U [d][m] face unknowns per component, R [d][nT],
+  //      p [nT] pressures, Y [d][nT][nT], Sg [n1][n1], h [nT]
+  double *L = lds;
+  double *U = L + nT * nT;
+  double *R = U + d * m;
+  double *p = R + d * nT;
+  double *Y = p + nT;
+  double *Sg = Y + d * nT * nT;
+  double *h = Sg + n1 * n1;
+  __shared__ int bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int i = threadIdx.x; i < nT * nT; i += blockDim.x) L[i] = a[(int64_t)(i / nT) * nloc + i % nT];
+  for (int i = threadIdx.x; i < d * m; i += blockDim.x) {
+    const int c = i / m, j = i % m;
+    const int f = tp.cface[c0 + j / nF];
+    U[i] = x[((int64_t)f * d + c) * nF + j % nF];
+  }
+  for (int q = threadIdx.x; q < nT; q += blockDim.x) p[q] = (q < np) ? xp[q] : 0.0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < d * nT; i += blockDim.x) {
+    const int c = i / nT, t = i % nT;
+    const double *at = a + (int64_t)t * nloc + nT;
+    double v = ru[(int64_t)c * nloc + t];
+    for (int j = 0; j < m; ++j) v -= at[j] * U[c * m + j];
+    for (int q = 0; q < np; ++q) v -= B[((int64_t)c * nT + q) * nloc + t] * p[q];
+    R[i] = v;
+  }
+  if (cond != 1) {
+    for (int i = threadIdx.x; i < d * nT * nT; i += blockDim.x) {
+      const int c = i / (nT * nT), t = (i / nT) % nT, q = i % nT;
+      Y[i] = B[((int64_t)c * nT + q) * nloc + t];  // B_c,TT^T
+    }
+    for (int q = 1 + threadIdx.x; q < nT; q += blockDim.x) {
+      double v = rp[q];
+      for (int c = 0; c < d; ++c) {
+        const double *bq = B + ((int64_t)c * nT + q) * nloc + nT;
+        for (int j = 0; j < m; ++j) v -= bq[j] * U[c * m + j];
+      }
+      h[q] = v;
+    }
+  }
+  __syncthreads();
+  blk_chol(L, nT, nT, &bad);
+  __syncthreads();
+  blk_fwd(L, nT, nT, R, d, nT, 1);  // g_c
+  if (cond != 1)
+    for (int c = 0; c < d; ++c) blk_fwd(L, nT, nT, Y + c * nT * nT, nT, 1, nT);
+  __syncthreads();
+  if (cond != 1 && n1 > 0) {
+    for (int idx = threadIdx.x; idx < n1 * n1; idx += blockDim.x) {
+      const int q = 1 + idx / n1, q2 = 1 + idx % n1;
+      double v = 0;
+      for (int c = 0; c < d; ++c)
+        for (int t = 0; t < nT; ++t) v += Y[(c * nT + t) * nT + q] * Y[(c * nT + t) * nT + q2];
+      Sg[idx] = v;
+    }
+    for (int q = 1 + threadIdx.x; q < nT; q += blockDim.x) {
+      double v = -h[q];
+      for (int c = 0; c < d; ++c)
+        for (int t = 0; t < nT; ++t) v += Y[(c * nT + t) * nT + q] * R[c * nT + t];
+      p[q] = v;
+    }
+    __syncthreads();
+    blk_chol(Sg, n1, n1, &bad);
+    __syncthreads();
+    blk_fwd(Sg, n1, n1, p + 1, 1, 1, 1);
+    __syncthreads();
+    blk_bwd(Sg, n1, n1, p + 1, 1, 1, 1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < d * nT; i += blockDim.x) {
+      const int c = i / nT, t = i % nT;
+      double v = R[i];
+      for (int q = 1; q < nT; ++q) v -= Y[(c * nT + t) * nT + q] * p[q];
+      R[i] = v;
+    }
+    __syncthreads();
+  }
+  blk_bwd(L, nT, nT, R, d, nT, 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < d * nT; i += blockDim.x) cu[(int64_t)T * d * nT + i] = R[i];
+  for (int q = threadIdx.x; q < nT; q += blockDim.x) cp[(int64_t)T * nT + q] = p[q];
+  if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
+}
+
 // ------------------------------------------------------------ assembly
 // Every face block (F, F') is the sum of the <= 2 cell blocks (T, i, j) with
 // F_i = F and F_j = F' (deterministic gather, no atomics).
@@ -850,6 +959,17 @@ void launch_condense(const DTopo &tp, int cond, int nT, int nF, const double *re
                      hipStream_t s, size_t lds) {
   hipLaunchKernelGGL(k_condense, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, nT, nF, rec, roff, stage, cpl, spp,
                      rhs_stage, rhs_p, err);
+}
+size_t recover_lds_bytes(int d, int nT, int nF, int max_faces) {
+  const int m = max_faces * nF;
+  const size_t n = (size_t)nT * nT + (size_t)d * m + (size_t)d * nT + nT + (size_t)d * nT * nT +
+                   (size_t)(nT - 1) * (nT - 1) + nT;
+  return n * sizeof(double);
+}
+void launch_recover(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
+                    const double *x, double *cu, double *cp, int *err, hipStream_t s, size_t lds) {
+  if (tp.nc == 0) return;
+  hipLaunchKernelGGL(k_recover, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, nT, nF, rec, roff, x, cu, cp, err);
 }
 void launch_assemble(const DTopo &tp, int cond, int nF, int64_t nnzb, const double *stage, double *bsr,
                      const double *rhs_stage, double *rhs, hipStream_t s) {

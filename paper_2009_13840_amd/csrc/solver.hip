@@ -1272,6 +1272,25 @@ int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_
   ABI_END
 }
 
+int hho_recover_cells(hho_problem *p, const double *x_dev, double *cell_u_dev, double *cell_p_dev) {
+  ABI_BEGIN
+  need_setup(p);
+  if (!x_dev || !cell_u_dev || !cell_p_dev) hho::fail(HHO_E_INVALID_ARG, "recover_cells: NULL pointer");
+  const size_t lds = hho::recover_lds_bytes(p->d, p->loc.nT, p->loc.nF, p->max_faces);
+  if (lds > 64 * 1024) hho::fail(HHO_E_INVALID_ARG, "recover_cells: cell too large for the kernel's LDS budget");
+  hipStream_t s = p->stream;
+  HIPCHK(hipMemsetAsync(p->err, 0, sizeof(int), s));
+  hho::launch_recover(p->tp, p->cond, p->loc.nT, p->loc.nF, p->rec, p->roff, x_dev, cell_u_dev, cell_p_dev, p->err,
+                      s, lds);
+  HIPCHK(hipGetLastError());
+  int herr = 0;
+  HIPCHK(hipMemcpyAsync(&herr, p->err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (herr) hho::fail(HHO_E_LOCAL_SINGULAR, "recover_cells: local block not SPD in cell " + std::to_string(herr - 1));
+  return HHO_OK;
+  ABI_END
+}
+
 int hho_get_rhs(hho_problem *p, double *b_dev) {
   ABI_BEGIN
   need_setup(p);

@@ -289,6 +289,30 @@ def test_fgmres_solution(built, name, mk, k, cond, coarse):
     assert its <= 40 and hist[0] == 1.0
 
 
+@pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3 + [
+    ("quad4_k0_v", lambda: cartesian_quads(4), 0, "v"),
+    ("hex1_k0_vp", lambda: cartesian_hexes(1), 0, "vp"),      # one pressure mode: nothing to eliminate
+])
+def test_recover_cells(built, name, mk, k, cond):
+    """Cell unknowns eliminated by static condensation, recovered on the device
+    from a random vector and from the FGMRES solution, against the oracle's dense
+    local solves (v&p-cond also recovers the non-mean pressure modes)."""
+    import torch
+    import oracle.solve as OS
+    mesh, M, P, O = built(name, mk, k, cond, rtol=1e-11)
+    rng = np.random.default_rng(21)
+    xs = [rng.standard_normal(P.level_size(0))]
+    x, its, hist, rel, ok = P.solve()
+    assert ok
+    xs.append(x.cpu().numpy())
+    for x in xs:
+        u, p = P.recover_cells(torch.from_numpy(x).cuda())
+        uo, po = OS.recover(O, x)
+        assert u.shape == uo.shape and p.shape == po.shape
+        assert _rel(u.cpu().numpy(), uo) < 1e-11, _rel(u.cpu().numpy(), uo)
+        assert _rel(p.cpu().numpy(), po) < 1e-11, _rel(p.cpu().numpy(), po)
+
+
 DEGENERATE_CASES = [
     ("quad1_k0_v", lambda: cartesian_quads(1), 0, "v"),       # one cell, one level (bordered dense solve)
     ("hex1_k0_vp", lambda: cartesian_hexes(1), 0, "vp"),
