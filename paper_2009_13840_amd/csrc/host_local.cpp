@@ -380,14 +380,24 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
   out->N1 = N1;
   const int64_t nc = m->nc, nf = m->nf;
 
-  // quadrature rules
-  std::vector<Rule> crule(nc), frule(nf);
-  parallel_for(nc, [&](int64_t c) { cell_rule(m, c, qdeg, crule[c]); });
-  parallel_for(nf, [&](int64_t f) { face_rule(m, f, qdeg, frule[f]); });
+  // quadrature rules: the data integrals (f, g_D, g_N) use rules exact to qdeg;
+  // every other integrand (Gram matrices of the bases, stiffness, reconstruction
+  // right-hand side, trace projections, coupling) is a polynomial of degree at
+  // most 2k + 2, integrated exactly by the cheaper operator rules
+  const int odeg = std::min(qdeg, 2 * k + 2);
+  std::vector<Rule> crule(nc), frule(nf), corule(nc), forule(nf);
+  parallel_for(nc, [&](int64_t c) {
+    cell_rule(m, c, qdeg, crule[c]);
+    cell_rule(m, c, odeg, corule[c]);
+  });
+  parallel_for(nf, [&](int64_t f) {
+    face_rule(m, f, qdeg, frule[f]);
+    face_rule(m, f, odeg, forule[f]);
+  });
 
   // face bases (shared by the two cells of a face)
   std::vector<FaceBasis> fb(nf);
-  std::vector<std::vector<double>> fpsi(nf);
+  std::vector<std::vector<double>> fpsi(nf), fpsio(nf);  // values at the data / operator points
   const std::vector<int> EF = exponents(d - 1, k);
   parallel_for(nf, [&](int64_t f) {
     FaceBasis &B = fb[f];
@@ -400,7 +410,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
       B.t1[q] = m->ft1[3 * f + q];
       B.t2[q] = m->ft2[3 * f + q];
     }
-    const Rule &R = frule[f];
+    const Rule &R = forule[f];
     int nq = R.n();
     std::vector<double> xi((size_t)nq * B.nvar), M((size_t)nq * nF);
     for (int q = 0; q < nq; ++q) {
@@ -411,8 +421,10 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
     }
     eval_monomials(B.E, B.nvar, xi.data(), nq, M.data());
     gram_schmidt(M.data(), R.w.data(), nq, nF, B.C);
-    fpsi[f].resize((size_t)nq * nF);
-    B.values(R.x.data(), nq, fpsi[f].data());
+    fpsio[f].resize((size_t)nq * nF);
+    B.values(R.x.data(), nq, fpsio[f].data());
+    fpsi[f].resize((size_t)frule[f].n() * nF);
+    B.values(frule[f].x.data(), frule[f].n(), fpsi[f].data());
   });
 
   // data at the quadrature points: body force on cells, Dirichlet / Neumann data on faces
@@ -460,7 +472,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
   const std::vector<int> EC = exponents(d, k + 1);
 
   parallel_for(nc, [&](int64_t c) {
-    const Rule &R = crule[c];
+    const Rule &R = corule[c];
     const int nq = R.n();
     const int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
     const int nloc = nT + nfc * nF;
@@ -509,7 +521,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
       FaceLoc &L = FL[i];
       L.f = f;
       for (int q = 0; q < 3; ++q) L.n[q] = m->csign[e] * m->fnrm[3 * f + q];
-      const Rule &Rf = frule[f];
+      const Rule &Rf = forule[f];
       L.nq = Rf.n();
       L.phif.resize((size_t)L.nq * N1);
       L.gn.resize((size_t)L.nq * N1);
@@ -522,7 +534,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
           for (int a = 0; a < d; ++a) s += g[((size_t)q * N1 + t) * d + a] * L.n[a];
           L.gn[(size_t)q * N1 + t] = s;
         }
-      const double *psi = fpsi[f].data();
+      const double *psi = fpsio[f].data();
       for (int q = 0; q < L.nq; ++q) {
         double w = Rf.w[q];
         for (int t = 1; t < N1; ++t) {
@@ -570,8 +582,8 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
     for (int i = 0; i < nfc; ++i) {
       const FaceLoc &L = FL[i];
       const int64_t f = L.f;
-      const Rule &Rf = frule[f];
-      const double *psi = fpsi[f].data();
+      const Rule &Rf = forule[f];
+      const double *psi = fpsio[f].data();
       const double hF = m->fdiam[f];
       const int bc = m->fbc[f];
       // Pi[j][t] = (psi_j, phi_t)_F ; Nn[j][t] = (psi_j, grad phi_t . n)_F
@@ -619,14 +631,30 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
           }
           A[(size_t)r * nloc + r] += eta / hF;
         }
-        // data: -(g_D, n.grad P v) + eta/h (g_D, v_F); mass: (g_D . n, q)
+        // data: -(g_D, n.grad P v) + eta/h (g_D, v_F); mass: (g_D . n, q), at the
+        // data points
         const double *g = &dval[dof_[f] * d];
+        const Rule &Rd = frule[f];
+        const int nqd = Rd.n();
+        const double *psid = fpsi[f].data();
+        std::vector<double> phid((size_t)nqd * N1), gnd((size_t)nqd * N1);
+        {
+          std::vector<double> gd((size_t)nqd * N1 * d);
+          cb.values(Rd.x.data(), nqd, phid.data());
+          cb.grads(Rd.x.data(), nqd, gd.data());
+          for (int q = 0; q < nqd; ++q)
+            for (int t = 0; t < N1; ++t) {
+              double s = 0;
+              for (int a = 0; a < d; ++a) s += gd[((size_t)q * N1 + t) * d + a] * L.n[a];
+              gnd[(size_t)q * N1 + t] = s;
+            }
+        }
         for (int cc = 0; cc < d; ++cc) {
           std::vector<double> gt(N1, 0.0), gp(nF, 0.0);
-          for (int q = 0; q < L.nq; ++q) {
-            double wg = Rf.w[q] * g[q * d + cc];
-            for (int t = 0; t < N1; ++t) gt[t] += wg * L.gn[(size_t)q * N1 + t];
-            for (int j = 0; j < nF; ++j) gp[j] += wg * psi[(size_t)q * nF + j];
+          for (int q = 0; q < nqd; ++q) {
+            double wg = Rd.w[q] * g[q * d + cc];
+            for (int t = 0; t < N1; ++t) gt[t] += wg * gnd[(size_t)q * N1 + t];
+            for (int j = 0; j < nF; ++j) gp[j] += wg * psid[(size_t)q * nF + j];
           }
           for (int b = 0; b < nloc; ++b) {
             double s = 0;
@@ -635,16 +663,19 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
           }
           for (int j = 0; j < nF; ++j) ru[cc * nloc + nT + i * nF + j] += eta / hF * gp[j];
         }
-        for (int q = 0; q < L.nq; ++q) {
+        for (int q = 0; q < nqd; ++q) {
           double gn = 0;
           for (int a = 0; a < d; ++a) gn += g[q * d + a] * L.n[a];
-          for (int t = 0; t < nT; ++t) rp[t] += Rf.w[q] * gn * L.phif[(size_t)q * N1 + t];
+          for (int t = 0; t < nT; ++t) rp[t] += Rd.w[q] * gn * phid[(size_t)q * N1 + t];
         }
       } else if (bc == HHO_FACE_NEUMANN) {
         const double *g = &nval[nof[f] * d];
+        const Rule &Rd = frule[f];
+        const double *psid = fpsi[f].data();
         for (int cc = 0; cc < d; ++cc)
-          for (int q = 0; q < L.nq; ++q)
-            for (int j = 0; j < nF; ++j) ru[cc * nloc + nT + i * nF + j] += Rf.w[q] * g[q * d + cc] * psi[(size_t)q * nF + j];
+          for (int q = 0; q < Rd.n(); ++q)
+            for (int j = 0; j < nF; ++j)
+              ru[cc * nloc + nT + i * nF + j] += Rd.w[q] * g[q * d + cc] * psid[(size_t)q * nF + j];
       }
       // coupling, face part: -(v_F . n, q)_F on non-Dirichlet faces
       if (bc != HHO_FACE_DIRICHLET)
@@ -656,17 +687,26 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
               Bm[((size_t)cc * nT + t) * nloc + nT + i * nF + j] -= L.n[cc] * s;
             }
     }
-    // coupling, cell part: (v_T,c, d_c q)_T ; body force (f_c, v_T)
+    // coupling, cell part: (v_T,c, d_c q)_T
     for (int q = 0; q < nq; ++q) {
       double w = R.w[q];
-      for (int cc = 0; cc < d; ++cc) {
-        double fv = fval[(coff[c] + q) * d + cc];
+      for (int cc = 0; cc < d; ++cc)
         for (int j = 0; j < nT; ++j) {
           double pj = w * phi[(size_t)q * N1 + j];
-          ru[cc * nloc + j] += fv * pj;
           for (int t = 0; t < nT; ++t) Bm[((size_t)cc * nT + t) * nloc + j] += pj * gphi[((size_t)q * N1 + t) * d + cc];
         }
-      }
+    }
+    // body force (f_c, v_T) at the data points
+    {
+      const Rule &Rd = crule[c];
+      const int nqd = Rd.n();
+      std::vector<double> phid((size_t)nqd * N1);
+      cb.values(Rd.x.data(), nqd, phid.data());
+      for (int q = 0; q < nqd; ++q)
+        for (int cc = 0; cc < d; ++cc) {
+          const double fv = Rd.w[q] * fval[(coff[c] + q) * d + cc];
+          for (int j = 0; j < nT; ++j) ru[cc * nloc + j] += fv * phid[(size_t)q * N1 + j];
+        }
     }
   });
 }
