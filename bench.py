@@ -425,6 +425,9 @@ def main():
         "final_rel_residual": rel,
         "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
         "phase_ms": {k: round(v, 3) for k, v in tm.items()},
+        # outside the timed step: host-side local operators (incl. the data
+        # callbacks) and symbolic AMG hierarchy, before the upload
+        "host_set_data_s": round(t_host, 3),
         "roofline": roof,
         "roofline_smoother": roof_pc,
         "learned": learned_info,
