@@ -71,6 +71,18 @@ def test_problem_argument_validation():
     assert e.value.code == -1
 
 
+def test_recover_cells_requires_setup_and_buffers():
+    """Host-side checks of hho_recover_cells, taken before any device work."""
+    import ctypes as C
+    H, lib = _lib()
+    P = H.Problem(H.Mesh(cartesian_quads(2)), 1, "v")
+    P.set_data(*problem_data(polynomial_stokes(2, 1, 0), None, 2))
+    dummy = C.c_void_p(0x1000)
+    assert lib.hho_recover_cells(P.h, dummy, dummy, dummy) == -1      # no setup yet
+    assert b"hho_setup" in lib.hho_last_error()
+    assert lib.hho_recover_cells(None, dummy, dummy, dummy) == -1
+
+
 def test_workspace_capacity_error():
     import ctypes as C
     H, lib = _lib()
