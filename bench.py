@@ -311,7 +311,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU sharding is a design, see DESIGN.md)", file=sys.stderr)
+              "(the sharding across GPUs is a design only)", file=sys.stderr)
         sys.exit(2)
 
     if args.workload == "batch256":
