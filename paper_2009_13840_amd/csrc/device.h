@@ -49,6 +49,7 @@ struct DLevel {
   const T *xinv;  // v: [nc][t][t] pressure Schur inverse; vp: [cptr*d*p] g = S_P^{-1} b
   const T *sig;   // vp: [nc] 1 / (b^T S_P^{-1} b)
   int block = 0;  // threads per block of the operator kernels (0: default), chosen by the autotuner
+  const int *skip = nullptr;  // lowest-degree operator kernels return at once while *skip != 0 (device flag)
 };
 
 // ---- setup kernels (FP64)

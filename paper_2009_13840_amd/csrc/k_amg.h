@@ -52,8 +52,11 @@ void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, 
                        int *err, hipStream_t s);
 void bp_setup(const DTopo &tp, int cond, const int32_t *fdiag, const double *bsr, const double *cpl, double *Sd,
               hipStream_t s);
-// z = block preconditioner applied to v (coarsest-level vectors in the global layout)
+// z = block preconditioner applied to v (coarsest-level vectors in the global layout).
+// skip (device, may be null): when *skip is nonzero at launch time every kernel of
+// the application returns at once (a Krylov process that has already converged
+// inside a chunk of queued iterations).
 void bp_apply(const DTopo &tp, const AmgDev &A, int64_t nface, const double *cpl, const double *Sd, const double *v,
-              double *z, int nu, hipStream_t s);
+              double *z, int nu, hipStream_t s, const int *skip = nullptr);
 
 }  // namespace hho

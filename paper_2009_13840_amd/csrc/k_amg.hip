@@ -204,7 +204,8 @@ __global__ void k_bp_setup(DTopo tp, int cond, const int32_t *fdiag, const doubl
 // split of the block preconditioner: z_T = -v_T / S_T on cells; the AMG
 // right-hand side f - C y on faces ([face][component] = the k = 0 face layout)
 __global__ void k_bp_rhs(DTopo tp, int64_t nface, const double *cpl, const double *Sd, const double *v,
-                         double *rhs, double *z) {
+                         double *rhs, double *z, const int *skip) {
+  if (skip && *skip) return;
   const int d = tp.d;
   const int64_t total = nface + tp.nc;
   for (int64_t o = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; o < total; o += (int64_t)gridDim.x * blockDim.x) {
@@ -231,7 +232,9 @@ __global__ void k_bp_rhs(DTopo tp, int64_t nface, const double *cpl, const doubl
 template <int G>
 __global__ void __launch_bounds__(kBlock) k_amg_rows(int n, int d, const int32_t *rp, const int32_t *ci,
                                                       const double *val, const double *dinv, const double *lam,
-                                                      const double *r, const double *xin, double *xout) {
+                                                      const double *r, const double *xin, double *xout,
+                                                      const int *skip) {
+  if (skip && *skip) return;
   const double w = kAmgOmegaJac / lam[0];
   const int lane = threadIdx.x % G;
   const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
@@ -318,7 +321,8 @@ __global__ void __launch_bounds__(kBlock) k_amg_restrict(int nc, int d, const in
                                                           const double *ptval, const int32_t *btp,
                                                           const int32_t *bti, const double *btval,
                                                           const double *dinv, const double *lam, const double *r,
-                                                          const double *x, double *rc) {
+                                                          const double *x, double *rc, const int *skip) {
+  if (skip && *skip) return;
   const double w = kAmgOmegaJac / lam[0];
   const int lane = threadIdx.x % kWave;
   const int64_t nwave = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -349,7 +353,9 @@ __global__ void __launch_bounds__(kBlock) k_amg_prolong_sweep(int n, int d, cons
                                                                const int32_t *pci, const double *pval,
                                                                const int32_t *brp, const int32_t *bci,
                                                                const double *bval, const double *xc,
-                                                               const double *r, const double *xin, double *xout) {
+                                                               const double *r, const double *xin, double *xout,
+                                                               const int *skip) {
+  if (skip && *skip) return;
   const double w = kAmgOmegaJac / lam[0];
   const int lane = threadIdx.x % G;
   const int64_t ngroups = (int64_t)gridDim.x * (blockDim.x / G);
@@ -398,7 +404,8 @@ __global__ void __launch_bounds__(kBlock) k_amg_prolong_sweep(int n, int d, cons
 // x = Ainv r (dense, row-major n x n): one block per row, every thread taking
 // every 256th entry, two in flight; waves combined through LDS
 __global__ void __launch_bounds__(kBlock) k_amg_dense(int n, int d, const double *Ainv, const double *r,
-                                                       double *x) {
+                                                       double *x, const int *skip) {
+  if (skip && *skip) return;
   __shared__ double red[3][kBlock / kWave];
   const int lane = threadIdx.x % kWave, wid = threadIdx.x / kWave;
   for (int64_t i = blockIdx.x; i < n; i += gridDim.x) {
@@ -654,24 +661,24 @@ void bp_setup(const DTopo &tp, int cond, const int32_t *fdiag, const double *bsr
 // V-cycle on level l: x = AMG_l(r); x, r are [n_l][d].  nu damped-Jacobi sweeps
 // before and after the coarse correction (nu = 1 or 2).
 static void rows(int G, int n, int d, const AmgDevLevel &L, const double *r, const double *xin, double *xout,
-                 hipStream_t s) {
+                 hipStream_t s, const int *skip) {
   const dim3 b(kBlock), g(grid_for((int64_t)n * G));
   const double *val = L.val, *dinv = L.dinv, *lam = L.lam;
   switch (G) {
-    case 64: hipLaunchKernelGGL((k_amg_rows<64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
-    case 16: hipLaunchKernelGGL((k_amg_rows<16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
-    case 4: hipLaunchKernelGGL((k_amg_rows<4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
-    default: hipLaunchKernelGGL((k_amg_rows<1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout); break;
+    case 64: hipLaunchKernelGGL((k_amg_rows<64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    case 16: hipLaunchKernelGGL((k_amg_rows<16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    case 4: hipLaunchKernelGGL((k_amg_rows<4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    default: hipLaunchKernelGGL((k_amg_rows<1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
   }
 }
 
 static void prolong_sweep(int G, const AmgDevLevel &L, int d, const double *xc, const double *r, const double *xin,
-                          double *xout, hipStream_t s) {
+                          double *xout, hipStream_t s, const int *skip) {
   const dim3 b(kBlock), g(grid_for((int64_t)L.n * G));
 #define HHO_PS(GG)                                                                                             \
   hipLaunchKernelGGL((k_amg_prolong_sweep<GG>), g, b, 0, s, L.n, d, L.rp, L.ci, (const double *)L.val,           \
                      (const double *)L.dinv, (const double *)L.lam, L.prp, L.pci, (const double *)L.pval, L.brp, \
-                     L.bci, (const double *)L.bval, xc, r, xin, xout)
+                     L.bci, (const double *)L.bval, xc, r, xin, xout, skip)
   switch (G) {
     case 64: HHO_PS(64); break;
     case 16: HHO_PS(16); break;
@@ -686,25 +693,26 @@ int amg_group(double avg) { return avg >= 48 ? 64 : avg >= 12 ? 16 : avg >= 3 ? 
 
 // V-cycle on level l: x = AMG_l(r); x, r are [n_l][d].  nu damped-Jacobi sweeps
 // before and after the coarse correction (nu = 1 or 2).
-static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, double *x, hipStream_t s) {
+static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, double *x, hipStream_t s,
+                   const int *skip) {
   const AmgDevLevel &L = A.lev[l];
   if (l == A.expl) {  // this level and all coarser ones: the explicit operator
-    hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.mexpl, r, x);
+    hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.mexpl, r, x, skip);
     return;
   }
   if (l == A.nlev - 1) {
     if (A.ainv) {
-      hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.ainv, r, x);
+      hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.ainv, r, x, skip);
       return;
     }
     // kAmgCoarseSweeps damped-Jacobi sweeps from zero (the first launch takes two)
     const int GA = amg_group((double)L.nnz / L.n);
     constexpr int rest = kAmgCoarseSweeps - 2;
     double *cur = (rest % 2 == 1) ? L.tmp : x;
-    rows(GA, L.n, d, L, r, nullptr, cur, s);
+    rows(GA, L.n, d, L, r, nullptr, cur, s, skip);
     for (int it = 0; it < rest; ++it) {
       double *nxt = (cur == x) ? L.tmp : x;
-      rows(GA, L.n, d, L, r, cur, nxt, s);
+      rows(GA, L.n, d, L, r, cur, nxt, s, skip);
       cur = nxt;
     }
     return;
@@ -715,24 +723,24 @@ static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, doubl
   // the single sweep x = w D^{-1} r is formed where it is used
   const double *xpre = nullptr;
   if (nu == 2) {
-    rows(GA, L.n, d, L, r, nullptr, x, s);
+    rows(GA, L.n, d, L, r, nullptr, x, s, skip);
     xpre = x;
   }
   hipLaunchKernelGGL(k_amg_restrict, dim3(grid_for((int64_t)N.n * kWave)), dim3(kBlock), 0, s, N.n, d, L.ptp, L.pti,
                      (const double *)L.ptval, L.btp, L.bti, (const double *)L.btval, (const double *)L.dinv,
-                     (const double *)L.lam, r, xpre, N.r);
-  vcycle(A, l + 1, d, nu, N.r, N.x, s);
+                     (const double *)L.lam, r, xpre, N.r, skip);
+  vcycle(A, l + 1, d, nu, N.r, N.x, s, skip);
   // prolongation with the first post-sweep (nu = 2: into tmp, then the second sweep into x)
-  prolong_sweep(GS, L, d, N.x, r, xpre, nu == 2 ? L.tmp : x, s);
-  if (nu == 2) rows(GA, L.n, d, L, r, L.tmp, x, s);
+  prolong_sweep(GS, L, d, N.x, r, xpre, nu == 2 ? L.tmp : x, s, skip);
+  if (nu == 2) rows(GA, L.n, d, L, r, L.tmp, x, s, skip);
 }
 
 void bp_apply(const DTopo &tp, const AmgDev &A, int64_t nface, const double *cpl, const double *Sd, const double *v,
-              double *z, int nu, hipStream_t s) {
+              double *z, int nu, hipStream_t s, const int *skip) {
   const int d = tp.d;
   hipLaunchKernelGGL(k_bp_rhs, dim3(grid_for(nface + tp.nc)), dim3(kBlock), 0, s, tp, nface, cpl, Sd, v,
-                     A.lev[0].r, z);
-  vcycle(A, 0, d, nu, A.lev[0].r, z, s);
+                     A.lev[0].r, z, skip);
+  vcycle(A, 0, d, nu, A.lev[0].r, z, s, skip);
 }
 
 }  // namespace hho

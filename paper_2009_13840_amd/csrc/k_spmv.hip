@@ -114,6 +114,7 @@ template <typename T, int D, int G, bool SPLIT, int MODE>
 __global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T> L, const T *__restrict__ x,
                                                      const T *__restrict__ xs1, T *__restrict__ xsum,
                                                      const T *__restrict__ b, T *__restrict__ y) {
+  if (L.skip && *L.skip) return;
   const int64_t o = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   if (o >= (int64_t)tp.nf + tp.nc) return;  // uniform over the group
@@ -172,6 +173,7 @@ template <typename T, int BS, int G, bool SPLIT, int MODE>
 __global__ void __launch_bounds__(kBlock) k_spmv_vp0(DTopo tp, DLevel<T> L, const T *__restrict__ x,
                                                       const T *__restrict__ xs1, T *__restrict__ xsum,
                                                       const T *__restrict__ b, T *__restrict__ y) {
+  if (L.skip && *L.skip) return;
   const int64_t o = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / G;
   const int lane = threadIdx.x % G;
   if (o >= (int64_t)tp.nf + tp.nc) return;  // uniform over the group

@@ -767,6 +767,8 @@ static void coarse_solve(hho_problem *P) {
   const int64_t n = L.N;
   const int R = P->opt.coarse_restart;
   GmresState *st = P->cst;
+  DLevel<double> Dq = D;
+  Dq.skip = &st->done;
   launch_fill<double>(n, 0.0, V.w, s);
   launch_norm_init<double>(n, V.b, P->partial, st, 1, s);
   launch_scale<double>(n, V.b, &st->inv_hnext, P->cV, s);
@@ -778,12 +780,15 @@ static void coarse_solve(hho_problem *P) {
     const int jmax = std::min(R, P->opt.coarse_max_it - its);
     for (int j = 0; j < jmax; ++j) {
       double *vj = P->cV + (int64_t)j * n;
+      // once the process has converged inside the chunk, the remaining queued
+      // iterations' preconditioner and operator kernels return at once (the
+      // Arnoldi kernels test the same flag)
       if (P->coarse_amg) {
-        bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, P->cZ + (int64_t)j * n, P->amg_nu, s);
-        launch_spmv<double>(P->tp, D, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s);
+        bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, P->cZ + (int64_t)j * n, P->amg_nu, s, &st->done);
+        launch_spmv<double>(P->tp, Dq, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s);
       } else {
         launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
-        launch_spmv<double>(P->tp, D, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+        launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
       }
       // coarse GMRES: classical Gram-Schmidt once (its target is a 1e-3 reduction),
       // the new norm from |w|^2 - |h|^2, the next basis vector written directly
