@@ -20,28 +20,53 @@ namespace hho {
 
 // Entries (column, first source, second source) of one output row, grouped by
 // column: columns ascending and, within a column, the entries in the order they
-// were produced (the device sums them in that order).
+// were produced (the device sums them in that order).  Grouping counts the
+// entries per distinct column (a column -> slot map kept across rows) and sorts
+// only the distinct columns.
 struct RowGroups {
   struct E {
-    int32_t col, seq, a, b;
+    int32_t col, a, b;
   };
   std::vector<E> e;
-  void clear() { e.clear(); }
-  void add(int32_t col, int32_t a, int32_t b) { e.push_back({col, (int32_t)e.size(), a, b}); }
+  std::vector<int32_t> slot;  // column -> index in ucol, -1 when absent (grown on demand)
+  std::vector<int32_t> ucol, cnt, pos, order;
+  void add(int32_t col, int32_t a, int32_t b) { e.push_back({col, a, b}); }
   // appends the row to (cols, pair offsets, pair lists)
   // (skip_negative: entries whose first source is < 0 only create their column)
   void flush(std::vector<int32_t> &cols, std::vector<int32_t> &pp, std::vector<int32_t> &pa,
              std::vector<int32_t> *pb, bool skip_negative = false) {
-    std::sort(e.begin(), e.end(), [](const E &x, const E &y) { return x.col != y.col ? x.col < y.col : x.seq < y.seq; });
-    for (size_t i = 0; i < e.size(); ++i) {
-      if (i == 0 || e[i].col != e[i - 1].col) {
-        cols.push_back(e[i].col);
-        pp.push_back((int32_t)pa.size());
+    for (const E &x : e) {
+      if (x.col >= (int32_t)slot.size()) slot.resize((size_t)x.col + 1, -1);
+      int32_t &sl = slot[x.col];
+      if (sl < 0) {
+        sl = (int32_t)ucol.size();
+        ucol.push_back(x.col);
+        cnt.push_back(0);
       }
-      if (skip_negative && e[i].a < 0) continue;
-      pa.push_back(e[i].a);
-      if (pb) pb->push_back(e[i].b);
+      if (!(skip_negative && x.a < 0)) ++cnt[sl];
     }
+    order.resize(ucol.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = (int32_t)i;
+    std::sort(order.begin(), order.end(), [&](int32_t u, int32_t v) { return ucol[u] < ucol[v]; });
+    pos.resize(ucol.size());
+    int32_t base = (int32_t)pa.size();
+    for (int32_t o : order) {
+      cols.push_back(ucol[o]);
+      pp.push_back(base);
+      pos[o] = base;
+      base += cnt[o];
+    }
+    pa.resize(base);
+    if (pb) pb->resize(base);
+    for (const E &x : e) {
+      if (skip_negative && x.a < 0) continue;
+      const int32_t q = pos[slot[x.col]]++;
+      pa[q] = x.a;
+      if (pb) (*pb)[q] = x.b;
+    }
+    for (int32_t c : ucol) slot[c] = -1;
+    ucol.clear();
+    cnt.clear();
     e.clear();
   }
 };
