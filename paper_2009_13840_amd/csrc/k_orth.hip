@@ -121,6 +121,36 @@ __global__ void __launch_bounds__(kOrthThreads) k_orth(int64_t n, int j, int E, 
   }
 }
 
+// The sums of MODE 3 split over blocks: blockIdx.y takes the eight sums
+// 8 y .. 8 y + 7 of V_i^T w (i <= j) and w^T w (i = j + 1), so that a lane keeps
+// all of its loads in flight at once (more blocks, one short chain each) rather
+// than walking every basis vector; partial[i * gridDim.x + blockIdx.x] as MODE 3.
+template <typename T>
+__global__ void __launch_bounds__(kOrthThreads) k_orth_dots8(int64_t n, int j, int E, const T *__restrict__ V,
+                                                             int64_t ldv, const T *__restrict__ w, double *partial,
+                                                             const GmresState *st) {
+  if (st->done) return;
+  const int nv = j + 1;  // dot products; sum nv is |w|^2
+  const int i0 = blockIdx.y * 8;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  for (int e = 0; e < E && k < n; ++e, k += stride) {
+    const double wk = (double)w[k];
+    double v[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int i = i0 + q;
+      v[q] = (i < nv) ? (double)V[(int64_t)i * ldv + k] : wk;  // past sum nv: unused
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) acc[q] += v[q] * wk;
+  }
+  block_multi_partial<8>(acc, min(8, nv + 1 - i0), partial + (int64_t)i0 * gridDim.x);
+}
+
 // Completes column j of the Hessenberg matrix (h1 (+ h2) above the diagonal,
 // sqrt(nn) below), applies the previous Givens rotations and the new one, and
 // updates the residual estimate and the convergence flag.  Whole block; the
@@ -477,7 +507,12 @@ void launch_arnoldi_dots(int64_t n, int j, const T *V, int64_t ldv, const T *w, 
 template <typename T>
 void launch_arnoldi_cgs1(int64_t n, int j, T *V, int64_t ldv, const T *w, double *partial, GmresState *st,
                          hipStream_t s) {
-  launch_mode<T, 3>(n, j, V, ldv, const_cast<T *>(w), partial, st, 0, s);
+  int grid, E;
+  orth_shape(n, &grid, &E);
+  const int groups = (j + 2 + 7) / 8;  // j + 1 dot products and |w|^2
+  hipLaunchKernelGGL((k_orth_dots8<T>), dim3(grid, groups), dim3(kOrthThreads), 0, s, n, j, E, (const T *)V, ldv, w,
+                     partial, (const GmresState *)st);
+  hipLaunchKernelGGL((k_orth_finish<3>), dim3(1), dim3(1024), 0, s, grid, j, (const double *)partial, st, 0);
   launch_mode<T, 4>(n, j, V, ldv, const_cast<T *>(w), partial, st, 0, s);
 }
 template <typename T>
