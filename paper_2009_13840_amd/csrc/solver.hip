@@ -792,7 +792,7 @@ static void coarse_solve(hho_problem *P) {
       }
       // coarse GMRES: classical Gram-Schmidt once (its target is a 1e-3 reduction),
       // the new norm from |w|^2 - |h|^2, the next basis vector written directly
-      // (while the j + 2 sums of the fused pass fit its 64 accumulators)
+      // (while the j + 2 sums fit the 64 slots of the update pass)
       if (j + 2 <= 64) {
         launch_arnoldi_cgs1<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
       } else {
