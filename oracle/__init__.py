@@ -19,6 +19,7 @@ Modules, each written from the paper's definitions:
                     level hierarchy by Galerkin projection (Sec. 3.1-3.2, 4.2)
 * ``krylov``     -- GMRES smoother and flexible GMRES (Sec. 3.3)
 * ``multilevel`` -- cell-patch Schwarz preconditioner and the V-cycle (Sec. 3.3)
+* ``ilu``        -- zero-fill ILU, the paper's smoother preconditioner (Sec. 3.3, 5.2)
 * ``solve``      -- end-to-end driver and error norms (Sec. 5.2)
 * ``mlp``        -- reference network for the learned smoother (not in the paper)
 

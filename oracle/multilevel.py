@@ -1,8 +1,10 @@
 """p-multilevel V-cycle of Section 3.3 (test infrastructure; see package header).
 
 Smoother preconditioner.  The paper preconditions its smoothing GMRES
-iterations with ILU.  The GPU library replaces ILU by a cell-patch additive
-Schwarz preconditioner, and this module replays that choice exactly:
+iterations with ILU; ``oracle.ilu.ILU0`` is that preconditioner (zero fill,
+natural ordering) and ``oracle.solve.hierarchy(smoother="ilu")`` selects it.
+The GPU library's default replaces ILU by a cell-patch additive Schwarz
+preconditioner, and this module replays that choice exactly:
 for every cell T the patch holds the unknowns of the faces of T and the
 pressure unknowns of T at the current level; the patch matrix is the global
 level matrix restricted to the patch; the correction of the patch is solved

@@ -18,6 +18,7 @@ import scipy.sparse.linalg as spla
 from .bases import dim_poly
 from .condense import condense_v, condense_vp, recover_v, recover_vp
 from .hho import mesh_geometry, local_hho
+from .ilu import ILU0
 from .krylov import fgmres
 from .multilevel import Hierarchy, Schwarz
 from .system import (assemble_condensed, coarse_indices, face_dofs, layout, nullspace)
@@ -84,8 +85,15 @@ def solve_direct(P: Problem) -> np.ndarray:
 
 
 def hierarchy(P: Problem, smooth_its=2, coarse="direct", coarse_rtol=1e-3,
-              coarse_restart=30, coarse_maxit=500) -> Hierarchy:
-    precs = [Schwarz(S, P.mesh, lay) for S, lay in zip(P.S, P.lays)]
+              coarse_restart=30, coarse_maxit=500, smoother="schwarz") -> Hierarchy:
+    """smoother: "schwarz" (the cell-patch preconditioner the GPU library uses)
+    or "ilu" (zero-fill ILU in the natural ordering, the paper's, Section 3.3)."""
+    if smoother == "schwarz":
+        precs = [Schwarz(S, P.mesh, lay) for S, lay in zip(P.S, P.lays)]
+    elif smoother == "ilu":
+        precs = [ILU0(S) for S in P.S]
+    else:
+        raise ValueError(f"unknown smoother {smoother!r}")
     H = Hierarchy(P.S, P.idx, precs, P.z, smooth_its, coarse, coarse_rtol, coarse_restart, coarse_maxit)
     H.nface_dofs = [lay.off for lay in P.lays]
     H.dim = P.mesh.dim

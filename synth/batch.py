@@ -48,3 +48,25 @@ def region_fields(fields, dim: int, width: float):
             return out
         return cb
     return make(0), make(1), make(2)
+
+
+def disjoint_union(meshes):
+    """One mesh holding the given meshes side by side, unconnected (member i's
+    vertices, faces and cells follow those of members 0..i-1, in their order)."""
+    from .meshes import Mesh
+    dim = meshes[0].dim
+    verts, fptr, fvtx, cptr, cface, bc = [], [0], [], [0], [], []
+    nv = nf = 0
+    for m in meshes:
+        assert m.dim == dim
+        verts.append(m.verts)
+        fvtx.append(m.face_vtx + nv)
+        fptr.extend((m.face_ptr[1:] + fptr[-1]).tolist())
+        cface.append(m.cell_face + nf)
+        cptr.extend((m.cell_ptr[1:] + cptr[-1]).tolist())
+        bc.append(m.face_bc)
+        nv += len(m.verts)
+        nf += m.n_faces
+    return Mesh(dim, np.concatenate(verts), np.array(fptr, dtype=np.int64), np.concatenate(fvtx),
+                np.array(cptr, dtype=np.int64), np.concatenate(cface), np.concatenate(bc).astype(np.int8),
+                "union")
