@@ -369,8 +369,8 @@ void chol_solve(const double *L, int n, int lda, double *B, int nrhs, int ldb) {
 }  // namespace
 
 // ---------------------------------------------------------------- driver
-void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_fn, hho_field_fn gD_fn,
-                 hho_field_fn gN_fn, void *ctx, LocalData *out) {
+void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, int qdeg, hho_field_fn f_fn,
+                 hho_field_fn gD_fn, hho_field_fn gN_fn, void *ctx, LocalData *out) {
   const int d = m->dim;
   const int N1 = dim_poly(d, k + 1), nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
   out->k = k;
@@ -472,6 +472,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
   const std::vector<int> EC = exponents(d, k + 1);
 
   parallel_for(nc, [&](int64_t c) {
+    const double eta_c = cell_eta ? cell_eta[c] : eta;  // Nitsche penalty of this cell
     const Rule &R = corule[c];
     const int nq = R.n();
     const int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
@@ -629,7 +630,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
             A[(size_t)r * nloc + b] -= NR[(size_t)j * nloc + b];
             A[(size_t)b * nloc + r] -= NR[(size_t)j * nloc + b];
           }
-          A[(size_t)r * nloc + r] += eta / hF;
+          A[(size_t)r * nloc + r] += eta_c / hF;
         }
         // data: -(g_D, n.grad P v) + eta/h (g_D, v_F); mass: (g_D . n, q), at the
         // data points
@@ -661,7 +662,7 @@ void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_
             for (int t = 0; t < N1; ++t) s += Rm[(size_t)t * nloc + b] * gt[t];
             ru[cc * nloc + b] -= s;
           }
-          for (int j = 0; j < nF; ++j) ru[cc * nloc + nT + i * nF + j] += eta / hF * gp[j];
+          for (int j = 0; j < nF; ++j) ru[cc * nloc + nT + i * nF + j] += eta_c / hF * gp[j];
         }
         for (int q = 0; q < nqd; ++q) {
           double gn = 0;

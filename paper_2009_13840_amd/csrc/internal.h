@@ -63,6 +63,7 @@ struct LocalData {
   std::vector<int32_t> nloc;  // [nc]
   std::vector<double> rec;
 };
-void build_local(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f, hho_field_fn gD,
-                 hho_field_fn gN, void *ctx, LocalData *out);
+// eta: Nitsche penalty of every cell, or, when cell_eta is not NULL, cell_eta[c] per cell
+void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, int qdeg, hho_field_fn f,
+                 hho_field_fn gD, hho_field_fn gN, void *ctx, LocalData *out);
 }  // namespace hho

@@ -331,10 +331,14 @@ __global__ void __launch_bounds__(kSegThreads) k_seg_scale(const SegChunk *ch, c
                                                             const GmresState *st, double *y) {
   const SegChunk c = ch[blockIdx.x];
   const SegInfo g = seg[c.p];
+  // a converged member's next basis vector is zero: the V-cycle, which acts on
+  // the whole union, then sees nothing of it (its scalars and the coarse solve
+  // are formed over the union), and its slice cannot grow with a stale scale
+  const bool done = st[c.p].done != 0;
   const double a = st[c.p].inv_hnext;
   for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
     const int64_t i = seg_index(g, (int64_t)c.e0 + e);
-    y[i] = a * x[i];
+    y[i] = done ? 0.0 : a * x[i];
   }
 }
 

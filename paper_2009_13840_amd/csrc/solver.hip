@@ -119,6 +119,7 @@ struct hho_problem {
   std::vector<SegChunk> hchunks;
   std::vector<int32_t> hchunk_ptr;
   std::vector<int64_t> seg_face_ptr, seg_cell_ptr;
+  std::vector<double> cell_eta;  // per-cell Nitsche penalty of a batch (each member's own default)
   SegInfo *dseg = nullptr;
   SegChunk *dchunks = nullptr;
   int32_t *dchunk_ptr = nullptr;
@@ -1195,7 +1196,8 @@ int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_fi
   ABI_BEGIN
   if (!p) hho::fail(HHO_E_INVALID_ARG, "set_data: NULL problem");
   int qdeg = 2 * p->k + 2 + std::max(0, p->opt.quad_extra);
-  hho::build_local(p->mesh, p->k, p->eta, qdeg, f, gD, gN, ctx, &p->loc);
+  hho::build_local(p->mesh, p->k, p->eta, p->cell_eta.empty() ? nullptr : p->cell_eta.data(), qdeg, f, gD, gN,
+                   ctx, &p->loc);
   hho::amg_levels(p);
   p->have_data = true;
   p->setup_done = false;
@@ -1831,6 +1833,31 @@ int hho_problem_set_segments(hho_problem *p, int n, const int64_t *face_ptr, con
     for (int64_t c = cell_ptr[i]; c < cell_ptr[i + 1]; ++c)
       for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e)
         if (fseg[m->cface[e]] != i) hho::fail(HHO_E_INVALID_ARG, "set_segments: a cell and its faces lie in different segments");
+  // every member is the problem it would be alone: mixed boundary types would give
+  // some members a pressure null space and others none, which one border cannot
+  // express, so they are refused
+  {
+    int with_neumann = 0;
+    for (int i = 0; i < n; ++i) {
+      bool nm = false;
+      for (int64_t f = face_ptr[i]; f < face_ptr[i + 1] && !nm; ++f) nm = m->fbc[f] == HHO_FACE_NEUMANN;
+      with_neumann += nm;
+    }
+    if (with_neumann != 0 && with_neumann != n)
+      hho::fail(HHO_E_INVALID_ARG, "set_segments: either every member or none may have Neumann faces");
+  }
+  // the default penalty 4(k+1)(k+d)/d max card(F_T) is taken per member
+  p->cell_eta.clear();
+  if (!(p->opt.eta > 0)) {
+    const int d = p->d, k = p->k;
+    p->cell_eta.resize(m->nc);
+    for (int i = 0; i < n; ++i) {
+      int64_t mf = 0;
+      for (int64_t c = cell_ptr[i]; c < cell_ptr[i + 1]; ++c) mf = std::max<int64_t>(mf, m->cptr[c + 1] - m->cptr[c]);
+      const double eta_i = 4.0 * (k + 1) * (k + d) / d * (double)mf;
+      for (int64_t c = cell_ptr[i]; c < cell_ptr[i + 1]; ++c) p->cell_eta[c] = eta_i;
+    }
+  }
   p->nseg = n;
   p->seg_face_ptr.assign(face_ptr, face_ptr + n + 1);
   p->seg_cell_ptr.assign(cell_ptr, cell_ptr + n + 1);

@@ -134,3 +134,35 @@ def test_union_mesh_and_segment_validation():
         Q = H.Problem(U, 1, "v", coarse_mode="dense")
         Q.set_segments(fo, co)
     assert e.value.code == -1
+
+
+def test_batch_refuses_mixed_boundary_types():
+    """A batch is a set of independent problems: a member with Neumann faces beside
+    one without would need a pressure null space for some members only."""
+    H, _ = _lib()
+    from synth.batch import shifted
+    a = cartesian_quads(3)
+    b = shifted(cartesian_quads(3), 2.0).with_bc(lambda x: 2 if x[0] > 3 - 1e-12 else 1)
+    U, fo, co = H.Mesh.union([a, b])
+    P = H.Problem(U, 1, "v")
+    with pytest.raises(H.HHOError, match="Neumann"):
+        P.set_segments(fo, co)
+
+
+def test_batch_members_take_their_own_penalty():
+    """The default Nitsche penalty depends on max card(F_T); in a batch each member
+    takes its own (a quadrilateral member beside a Voronoi member keeps the
+    quadrilateral's penalty), so its local operators are those it has alone."""
+    H, _ = _lib()
+    from synth.batch import shifted, region_fields
+    quads, vor = cartesian_quads(3), voronoi_lloyd(20, 4)
+    fields = [problem_data(polynomial_stokes(2, 2, 5 + i), None, 2) for i in range(2)]
+    U, fo, co = H.Mesh.union([quads, shifted(vor, 2.0)])
+    P = H.Problem(U, 1, "v")
+    P.set_segments(fo, co)
+    P.set_data(*region_fields(fields, 2, 2.0))
+    A = H.Problem(H.Mesh(quads), 1, "v")
+    A.set_data(*fields[0])
+    for c in range(quads.n_cells):
+        u, a = P.local_cell(c), A.local_cell(c)
+        assert np.abs(u["a"] - a["a"]).max() <= 1e-12 * np.abs(a["a"]).max()

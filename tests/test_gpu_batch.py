@@ -39,10 +39,9 @@ def test_batched_members_match_oracle(dim, k, cond):
     lay_dp = None
     n0 = P.level_size(0)
     nface_total = int(fo[-1])
-    # the union has one penalty (its largest card(F_T) enters the default)
-    eta = max(OS.default_eta(m, k) for m in members)
+    # every member takes its own default penalty, as it would alone
     for i, mesh in enumerate(members):
-        O = OS.build(mesh, k, cond, fields[i], eta=eta)
+        O = OS.build(mesh, k, cond, fields[i], eta=None)
         xd = OS.normalise_pressure(O, OS.solve_direct(O))
         nF, nP = O.lays[0].nF, O.lays[0].nP
         dp = dim * nF
@@ -55,3 +54,39 @@ def test_batched_members_match_oracle(dim, k, cond):
         print(f"[member] {i}: its {m_its[i]} rel {m_rel[i]:.2e} |x - x_direct|/|x| {err:.2e}")
         assert err <= 1e-8, (i, err)
     assert n0 == nface_total * lay_dp + int(co[-1]) * nP
+
+
+def test_batched_restart_after_a_member_converged():
+    """Members of very different difficulty with a short restart: the easy member
+    converges while the hard one still restarts.  The converged member's basis
+    vectors must stay zero (they feed the union-wide V-cycle); every member
+    converges and no breakdown is reported."""
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    members = [cartesian_quads(2), voronoi_lloyd(60, 11), cartesian_quads(3), voronoi_lloyd(45, 12)]
+    fields = [problem_data(polynomial_stokes(2, 3, 70 + i), None, 2) for i in range(len(members))]
+    width = 2.0
+    U, fo, co = H.Mesh.union([shifted(m, width * i) for i, m in enumerate(members)])
+    print(f"[case] batch restart=4, {len(members)} members, {U.n_cells} cells", flush=True)
+    P = H.Problem(U, 2, "v", rtol=1e-10, restart=4, coarse_mode="gmres")
+    P.set_segments(fo, co)
+    P.set_data(*region_fields(fields, 2, width))
+    P.bind("cuda:0")
+    P.setup()
+    x, its, hist, rel, ok = P.solve()
+    m_its, m_rel = P.batch_results()
+    print(f"[members] its {m_its.tolist()} rel {m_rel.tolist()}")
+    assert ok and np.all(m_rel <= 1e-10), (m_its, m_rel)
+    assert m_its.min() < m_its.max()      # the members really converge at different times
+    assert m_its.max() > 4                # and the slowest restarts at least once
+    x = x.cpu().numpy()
+    nface_total = int(fo[-1])
+    for i, mesh in enumerate(members):
+        O = OS.build(mesh, 2, "v", fields[i])
+        xd = OS.normalise_pressure(O, OS.solve_direct(O))
+        dp, nP = 2 * O.lays[0].nF, O.lays[0].nP
+        xm = np.concatenate([x[fo[i] * dp:fo[i + 1] * dp],
+                             x[nface_total * dp + co[i] * nP:nface_total * dp + co[i + 1] * nP]])
+        err = np.linalg.norm(xm - xd) / np.linalg.norm(xd)
+        assert err <= 1e-7, (i, err)
+
