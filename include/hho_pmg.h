@@ -281,8 +281,12 @@ int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int
 /* Declares the members of a union mesh: member i owns faces [face_ptr[i],
  * face_ptr[i+1]) and cells [cell_ptr[i], cell_ptr[i+1]) (partitions, every
  * cell's faces in its own member).  Call after hho_problem_create and before
- * hho_problem_set_data.  A dense coarsest-level solver is refused when the
- * members have a pressure null space (use AMG or GMRES). */
+ * hho_problem_set_data.  Each member is the problem it would be alone: with the
+ * default penalty (options.eta <= 0) its cells take 4(k+1)(k+d)/d times the
+ * member's own max card(F_T).  Either every member or none may have Neumann
+ * faces (HHO_E_INVALID_ARG otherwise): a pure-Dirichlet member has its own
+ * constant-pressure null vector.  A dense coarsest-level solver is refused when
+ * the members have a pressure null space (use AMG or GMRES). */
 int hho_problem_set_segments(hho_problem *p, int n, const int64_t *face_ptr, const int64_t *cell_ptr);
 
 /* After a batched hho_solve: FGMRES iterations and final true relative
@@ -336,8 +340,10 @@ int hho_learned_grad(hho_problem *p, const float *X_dev, const float *T_dev, int
                      double *loss);
 
 /* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
- * batches of `batch` rows (<= 4096) drawn from the n rows of X, T with
- * SplitMix64 of (seed, step, i); loss_hist (host, may be NULL) receives the
+ * batches of `batch` rows (<= 4096) drawn from the n rows of X, T: row i of the
+ * batch of step s (counted from 0 since the last hho_learned_set_params, across
+ * calls) is SM(seed ^ SM((s << 32) | i)) mod n, SM the SplitMix64 output
+ * function (Steele, Lea & Flood 2014); loss_hist (host, may be NULL) receives the
  * batch loss of every step. */
 int hho_learned_train(hho_problem *p, const float *X_dev, const float *T_dev, int64_t n, int steps, int batch,
                       float lr, uint64_t seed, float *loss_hist);

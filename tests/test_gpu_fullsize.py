@@ -1,15 +1,15 @@
 """Parity at the full size of the workloads the benchmark times: the 2D Voronoi
 problem (16384 Lloyd-relaxed cells, seed 2, k = 3, levels 3-2-1-0, v-cond and
-v&p-cond, default options) and the 3D one (32^3 hexahedra, k = 3, v&p-cond, FP32
-V-cycle under FP64 FGMRES), with polynomial data so that both sides integrate
-exactly.
+v&p-cond, default options) and the 3D ones (32^3 hexahedra, k = 3, v&p-cond, FP32
+V-cycle under FP64 FGMRES; 32^3 hexahedra, k = 2, v&p-cond; 24^3 hexahedra,
+k = 3, v-cond), with polynomial data so that both sides integrate exactly.
 
 The oracle cannot assemble the whole system in seconds, so it builds the local
 operators only for the cells around a seeded sample (two rings of neighbours)
 and checks the library's outputs at the sample's rows, one row at a time:
 condensed cell blocks and right-hand side (eqs. ST.1 / ST.2), the fine operator
 (face rows are sums over the face's two cells, pressure rows belong to one
-cell), the cell-patch Schwarz smoother (a face's correction is the weighted sum
+cell) and every coarse operator at the sample's rows, the cell-patch Schwarz smoother (a face's correction is the weighted sum
 of its two patches' solutions), and, after a full FGMRES solve, the residual
 of the library's solution at the sampled face rows, formed from the oracle's own
 rows of the operator and right-hand side.  A CPU test checks the sampled row
@@ -155,6 +155,17 @@ def test_sampled_oracle_rows_match_full_assembly():
         assert _rel(so.rhs(rows), O.b[rows]) < 1e-12
         prec = ML.Schwarz(O.S[0], mesh, O.lays[0])
         assert _rel(so.schwarz(x, rows), prec(x)[rows]) < 1e-10
+        # coarse rows through the zero-padded fine vector
+        from oracle.system import coarse_indices
+        idx = np.arange(O.S[0].shape[0])
+        for l in range(1, len(O.S)):
+            idx = idx[coarse_indices(O.lays[l - 1], O.lays[l])]
+            xl = np.random.default_rng(3 + l).standard_normal(len(idx))
+            xf = np.zeros(O.S[0].shape[0])
+            xf[idx] = xl
+            sel = np.flatnonzero(np.isin(idx, rows))
+            assert len(sel) > 0
+            assert _rel(so.apply(xf, idx[sel]), (O.S[l] @ xl)[sel]) < 1e-12
 
 
 @pytest.fixture(scope="module")
@@ -179,17 +190,34 @@ def test_full_size_hex32_k3_vp_fp32_vcycle():
     _check_full_size(mesh, mesh.face_cells(), "vp", nsample=3, seed=6, precision="fp32")
 
 
-def _check_full_size(mesh, fc, cond, nsample, seed, **opts):
+@pytest.mark.gpu
+def test_full_size_hex32_k2_vp():
+    from synth import cartesian_hexes
+    mesh = cartesian_hexes(32)
+    print("[case] hex32 k=2 cond=vp", flush=True)
+    _check_full_size(mesh, mesh.face_cells(), "vp", nsample=3, seed=7, k=2)
+
+
+@pytest.mark.gpu
+def test_full_size_hex24_k3_v():
+    from synth import cartesian_hexes
+    mesh = cartesian_hexes(24)
+    print("[case] hex24 k=3 cond=v", flush=True)
+    _check_full_size(mesh, mesh.face_cells(), "v", nsample=3, seed=8)
+
+
+def _check_full_size(mesh, fc, cond, nsample, seed, k=K, **opts):
     import torch
     import paper_2009_13840_amd as H
+    from oracle.system import layout, coarse_indices
     d = mesh.dim
-    data = problem_data(polynomial_stokes(d, K + 1, 3), None, d)
-    P = H.Problem(H.Mesh(mesh), K, cond, **opts)
+    data = problem_data(polynomial_stokes(d, k + 1, 3), None, d)
+    P = H.Problem(H.Mesh(mesh), k, cond, **opts)
     P.set_data(*data)
     P.bind("cuda:0")
     P.setup()
     rng = np.random.default_rng(seed)
-    so = SampledOracle(mesh, K, cond, data, _sample(mesh, fc, rng, nsample))
+    so = SampledOracle(mesh, k, cond, data, _sample(mesh, fc, rng, nsample))
     rows, frows = so.rows()
     N = P.level_size(0)
     assert N == so.N
@@ -206,6 +234,21 @@ def _check_full_size(mesh, fc, cond, nsample, seed, **opts):
     y = P.level_apply(0, torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.isfinite(y).all()
     assert _rel(y[rows], so.apply(x, rows)) < 1e-11
+    # coarse operators k-1 ... 0 (sub-blocks of the fine one, Section 4.2): at the
+    # sample's rows S_l x_l equals the fine rows of S_0 (P x_l), P the zero-padding
+    lays = [layout(mesh, kl, cond) for kl in range(k, -1, -1)]
+    idx = np.arange(N)                       # fine index of every level-l unknown
+    for l in range(1, len(lays)):
+        idx = idx[coarse_indices(lays[l - 1], lays[l])]
+        assert P.level_size(l) == len(idx)
+        xl = rng.standard_normal(len(idx))
+        yl = P.level_apply(l, torch.from_numpy(xl).cuda()).cpu().numpy()
+        assert np.isfinite(yl).all()
+        sel = np.flatnonzero(np.isin(idx, rows))
+        assert len(sel) > 0
+        xf = np.zeros(N)
+        xf[idx] = xl
+        assert _rel(yl[sel], so.apply(xf, idx[sel])) < 1e-11, (l, _rel(yl[sel], so.apply(xf, idx[sel])))
     # patch smoother
     z = P.precond_apply(0, torch.from_numpy(x).cuda()).cpu().numpy()
     assert np.isfinite(z).all()

@@ -140,6 +140,60 @@ def test_learned_vcycle_matches_oracle(built, name, mk, k, cond):
         P.learned_enable(False)
 
 
+def _splitmix64(x):
+    """SplitMix64 output function (Steele, Lea & Flood, OOPSLA 2014)."""
+    M = (1 << 64) - 1
+    x = (x + 0x9E3779B97F4A7C15) & M
+    x = ((x ^ (x >> 30)) * 0xBF58476D1CE4E5B9) & M
+    x = ((x ^ (x >> 27)) * 0x94D049BB133111EB) & M
+    return x ^ (x >> 31)
+
+
+def _batch_rows(seed, step, B, n):
+    """Rows of training step `step` (from 0): SplitMix64(seed xor SplitMix64(step << 32 | i)) mod n."""
+    return np.array([_splitmix64(seed ^ _splitmix64((step << 32) | i)) % n for i in range(B)], dtype=np.int64)
+
+
+@pytest.mark.parametrize("name,mk,k,cond", CASES[:2])
+def test_adam_steps_match_oracle(built, name, mk, k, cond):
+    """Three training steps: the batch rows follow the documented SplitMix64 draw,
+    and the Adam kernel's parameters after each step equal the oracle's Adam
+    update (FP64, oracle.mlp.adam_step, bias-corrected moments from zero) applied
+    to the gradient the library computes for those rows at its current
+    parameters.  Tolerance: FP32 rounding of the update arithmetic, 1e-6 of a
+    parameter plus 1e-4 of the learning rate."""
+    import torch
+    mesh, P, O, L = built(name, mk, k, cond)
+    rng = np.random.default_rng(17)
+    th, flat = _params(rng, L.n_in, L.dp)
+    P.learned_set_params(flat)
+    n, B, lr, seed = 500, 96, 1e-3, 1234567
+    X = torch.from_numpy(rng.standard_normal((n, L.n_in)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((n, L.dp)).astype(np.float32)).cuda()
+    keys = ("W1", "b1", "W2", "b2")
+    m = {k_: np.zeros_like(th[k_]) for k_ in keys}
+    v = {k_: np.zeros_like(th[k_]) for k_ in keys}
+    tho = dict(th)
+    for step in range(3):
+        rows = torch.from_numpy(_batch_rows(seed, step, B, n)).cuda()
+        _, g = P.learned_grad(X[rows].contiguous(), T[rows].contiguous())
+        hist = P.learned_train(X, T, steps=1, batch=B, lr=lr, seed=seed)
+        assert np.isfinite(hist).all()
+        gd, off = {}, 0
+        for k_ in keys:
+            gd[k_] = g[off:off + th[k_].size].astype(np.float64).reshape(th[k_].shape)
+            off += th[k_].size
+        tho, m, v = mlp.adam_step(tho, gd, m, v, step + 1, lr)
+        want = np.concatenate([tho[k_].ravel() for k_ in keys])
+        got = P.learned_get_params().astype(np.float64)
+        err = np.abs(got - want) / (1e-6 * np.abs(want) + 1e-4 * lr)
+        print(f"[adam] {name} step {step + 1}: worst error / tolerance {err.max():.2f}")
+        assert err.max() <= 1.0, err.max()
+        # the step really moved the parameters (by about lr where the gradient is not zero)
+        moved = np.abs(got - np.concatenate([th[k_].ravel() for k_ in keys]))
+        assert moved.max() > 0.5 * lr
+
+
 def test_training_gain_over_plain_smoother():
     """Trains on V-cycle pairs of a 3D problem and reports the fine-level
     smoothing gain; the learned step can never lose to the plain one (it

@@ -1,8 +1,10 @@
 """GPU parity tests: the HIP library (through its C ABI) against the CPU oracle on
 the same seeded inputs.  Tolerances are relative to the largest entry of the
 compared quantity; all FP64 kernels are held to <= 1e-11 except the full V-cycle
-(1e-10, nested minimal-residual steps amplify rounding) and iterative solves
-(compared through the discrete solution they converge to)."""
+(1e-10, nested minimal-residual steps amplify rounding).  Iterative solves are
+compared iteration by iteration (FGMRES residual histories, 1e-8 per entry),
+through their final iterates (library and oracle FGMRES both run to a 1e-12
+relative residual agree to 1e-10) and against the exact discrete solution."""
 import numpy as np
 import pytest
 
@@ -115,7 +117,8 @@ def test_vcycle_matches_oracle(built, name, mk, k, cond):
     xo = H.vcycle(0, b)
     if O.z[0] is not None:   # the coarse correction is defined up to the constant pressure
         x, xo = OS.project_out(O.z[0])(x), OS.project_out(O.z[0])(xo)
-    assert _rel(x, xo) < 1e-9, _rel(x, xo)
+    print(f"[vcycle] {name}: {_rel(x, xo):.2e}")
+    assert _rel(x, xo) < 1e-10, _rel(x, xo)
 
 
 MIXED_CASES = [CASES[0], CASES[3], CASES[5], CASES_3D_K3[0]]
@@ -124,12 +127,16 @@ MIXED_CASES = [CASES[0], CASES[3], CASES[5], CASES_3D_K3[0]]
 @pytest.mark.parametrize("name,mk,k,cond", MIXED_CASES)
 def test_mixed_precision_vcycle(built, name, mk, k, cond):
     """FP32 V-cycle (levels above the coarsest in FP32, coarsest in FP64) against
-    the oracle's FP64 V-cycle.  Tolerance: every FP32 quantity (operator, patch
-    inverses, vectors) carries a relative rounding of 2^-24 = 6e-8; a V-cycle
-    applies some tens of them with local condition numbers below 1e2, so the
-    result agrees to ~1e-5 of its largest entry; the test allows 1e-4."""
+    the oracle's float32 emulation of the same V-cycle (oracle.mixed: FP64
+    operators and patch inverses rounded to float32, float32 vector arithmetic,
+    FP64 coarsest solve) at 1e-5 of the largest entry, and against the FP64
+    oracle V-cycle: it must differ from it by more than 1e-9 (FP32 is really
+    used).  Each FP32 quantity carries a relative rounding of 2^-24 = 6e-8; a
+    V-cycle composes some tens of them with local condition numbers below 1e2,
+    so both FP32 results lie within ~1e-6 of the FP64 one."""
     import torch
     import oracle.solve as OS
+    from oracle.mixed import Vcycle32
     mesh, M, P, O = built(name, mk, k, cond, coarse_mode="dense", precision="fp32")
     H = OS.hierarchy(O, coarse="direct")
     rng = np.random.default_rng(8)
@@ -138,10 +145,13 @@ def test_mixed_precision_vcycle(built, name, mk, k, cond):
         b = OS.project_out(O.z[0])(b)
     x = P.vcycle_apply(torch.from_numpy(b).cuda()).cpu().numpy()
     xo = H.vcycle(0, b)
+    x32 = Vcycle32(H)(b)
     if O.z[0] is not None:
-        x, xo = OS.project_out(O.z[0])(x), OS.project_out(O.z[0])(xo)
-    err = _rel(x, xo)
-    assert 1e-9 < err < 1e-4, err          # FP32 arithmetic is really used, and it is close
+        x, xo, x32 = (OS.project_out(O.z[0])(v) for v in (x, xo, x32))
+    err64, err32 = _rel(x, xo), _rel(x, x32)
+    print(f"[mixed vcycle] {name}: vs fp64 {err64:.2e}, vs fp32 emulation {err32:.2e}")
+    assert err64 > 1e-9, err64          # FP32 arithmetic is really used
+    assert err32 < 1e-5, err32
 
 
 @pytest.mark.parametrize("name,mk,k,cond", MIXED_CASES)
@@ -250,15 +260,29 @@ def test_coarse_block_preconditioner_one_sweep(built, name, mk, k, cond, explici
     assert _rel(z, prec(v)) < 1e-10, _rel(z, prec(v))
 
 
+def _solution_parity(O, P, coarse, tag, **hk):
+    """Library and oracle FGMRES, both to a 1e-12 relative residual with the same
+    coarse solver: final iterates agree to 1e-10; both reach the direct solution."""
+    import oracle.solve as OS
+    x, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-12, (its, rel)
+    x = x.cpu().numpy()
+    xo, its_o, hist_o, conv = OS.solve_fgmres(O, rtol=1e-12, coarse=coarse, **hk)
+    assert conv
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    e_o = np.linalg.norm(x - xo) / np.linalg.norm(xo)
+    e_d = np.linalg.norm(x - xd) / np.linalg.norm(xd)
+    print(f"[fgmres] {tag}: its {its} (oracle {its_o}), |x - x_oracle| {e_o:.2e}, |x - x_direct| {e_d:.2e}")
+    assert e_o <= 1e-10, e_o
+    assert e_d <= 1e-8, e_d
+    assert its <= 40 and hist[0] == 1.0
+    return its, its_o
+
+
 @pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
 def test_fgmres_solution_amg_coarse(built, name, mk, k, cond):
-    import oracle.solve as OS
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", rtol=1e-11)
-    x, its, hist, rel, ok = P.solve()
-    assert ok and rel <= 1e-11
-    xd = OS.normalise_pressure(O, OS.solve_direct(O))
-    assert np.linalg.norm(x.cpu().numpy() - xd) <= 1e-8 * np.linalg.norm(xd)
-    assert its <= 40
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", rtol=1e-12)
+    _solution_parity(O, P, "amg", name)
 
 
 @pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0]])
@@ -279,14 +303,33 @@ def test_fgmres_solution_long_coarse_cycles(built, name, mk, k, cond):
 @pytest.mark.parametrize("name,mk,k,cond", CASES)
 @pytest.mark.parametrize("coarse", ["dense", "gmres"])
 def test_fgmres_solution(built, name, mk, k, cond, coarse):
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode=coarse, rtol=1e-12)
+    its, its_o = _solution_parity(O, P, "direct" if coarse == "dense" else "gmres", f"{name} {coarse}")
+    if coarse == "dense":
+        assert its == its_o
+
+
+@pytest.mark.parametrize("restart", [30, 3])
+@pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3)
+def test_fgmres_history_matches_oracle(built, name, mk, k, cond, restart):
+    """Iteration-level parity of flexible GMRES (CGS2 Arnoldi, Givens rotations,
+    restarts from the true residual): with the exact coarsest solve the V-cycle is
+    the same linear map on both sides, so the library and the oracle take the
+    same number of iterations and their relative residual estimates agree to
+    1e-8 per entry while above 1e-8.  Restart 3 forces several restarts."""
     import oracle.solve as OS
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode=coarse, rtol=1e-11)
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="dense", rtol=1e-10, restart=restart)
     x, its, hist, rel, ok = P.solve()
-    assert ok and rel <= 1e-11
-    xd = OS.normalise_pressure(O, OS.solve_direct(O))
-    x = x.cpu().numpy()
-    assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
-    assert its <= 40 and hist[0] == 1.0
+    assert ok
+    xo, its_o, hist_o, conv = OS.solve_fgmres(O, rtol=1e-10, restart=restart, coarse="direct")
+    ho = np.asarray(hist_o)
+    print(f"[history] {name} restart {restart}: its {its} (oracle {its_o})")
+    assert its == its_o and len(hist) == len(ho)
+    sel = ho > 1e-8
+    assert sel.sum() >= 3
+    dev = np.abs(hist[sel] - ho[sel]) / ho[sel]
+    print(f"[history] {name} restart {restart}: max per-entry deviation {dev.max():.2e}")
+    assert dev.max() <= 1e-8, dev.max()
 
 
 @pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3 + [

@@ -307,3 +307,24 @@ def test_fgmres_with_ilu_smoother_reaches_the_direct_solution(cond):
     xd = OS.normalise_pressure(P, OS.solve_direct(P))
     assert conv and np.linalg.norm(x - xd) < 1e-8 * np.linalg.norm(xd)
     assert its <= 30
+
+
+# ---------------------------------------------------------------- float32 emulation of the V-cycle
+
+@pytest.mark.parametrize("cond", ["v", "vp"])
+def test_fp32_vcycle_emulation_is_float32_and_close(cond):
+    """The float32 emulation keeps float32 data above the coarsest level, and its
+    V-cycle lies within the float32 rounding bound (1e-5 of the largest entry) of
+    the FP64 V-cycle while differing from it (by more than 1e-9)."""
+    from oracle.mixed import Vcycle32
+    mesh = voronoi_lloyd(30, 12)
+    P = _build(mesh, 2, cond)
+    H = OS.hierarchy(P, coarse="direct")
+    V32 = Vcycle32(H)
+    assert all(S.dtype == np.float32 for S in V32.S)
+    assert all(A.dtype == np.float32 for M in V32.prec for A in M.inv)
+    b = OS.project_out(P.z[0])(np.random.default_rng(13).standard_normal(P.S[0].shape[0]))
+    x64 = OS.project_out(P.z[0])(H.vcycle(0, b))
+    x32 = OS.project_out(P.z[0])(V32(b))
+    err = np.abs(x32 - x64).max() / np.abs(x64).max()
+    assert 1e-9 < err < 1e-5, err
