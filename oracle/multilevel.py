@@ -123,7 +123,10 @@ class Hierarchy:
         return gmres_steps(A, self.prec[l], w, r, self.smooth_its)
 
     def vcycle(self, l, b, w=None):
-        """MG_V(l, b, w) of the algorithm in Section 3.3."""
+        """MG_V(l, b, w) of the algorithm in Section 3.3.  On the coarsest level the
+        algorithm solves (so a one-level hierarchy is its coarsest solve)."""
+        if l == self.L:
+            return self.coarse_solve(b)
         S = self.S[l]
         w = np.zeros_like(b) if w is None else w
         w = self.smooth(l, b, w)                                           # pre-smoothing

@@ -328,3 +328,17 @@ def test_fp32_vcycle_emulation_is_float32_and_close(cond):
     x32 = OS.project_out(P.z[0])(V32(b))
     err = np.abs(x32 - x64).max() / np.abs(x64).max()
     assert 1e-9 < err < 1e-5, err
+
+
+def test_one_level_vcycle_is_the_coarsest_solve():
+    """With a single level (k = 0, no coarser degree) the V-cycle is the coarsest
+    solve itself; FGMRES preconditioned by it converges at once."""
+    mesh = _neumann_right(voronoi_lloyd(16, 14))
+    P = _build(mesh, 0, "v")
+    assert len(P.S) == 1
+    H = OS.hierarchy(P, coarse="direct")
+    b = np.random.default_rng(15).standard_normal(P.S[0].shape[0])
+    x = spla.spsolve(P.S[0].tocsc(), b)
+    assert np.abs(H.vcycle(0, b) - x).max() < 1e-12 * np.abs(x).max()
+    xs, its, hist, conv = OS.solve_fgmres(P, rtol=1e-12, coarse="direct")
+    assert conv and its == 1
