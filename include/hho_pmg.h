@@ -339,6 +339,21 @@ int hho_learned_collect(hho_problem *p, const double *x_true_dev, int cycles, fl
 int hho_learned_grad(hho_problem *p, const float *X_dev, const float *T_dev, int64_t n, float *grad,
                      double *loss);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid allocation): the same loss and gradient
+ * as hho_learned_grad, with the same kernels in the same order (so the results
+ * are identical), but the work arrays -- hidden activations and outputs of the
+ * batch and their gradients, the parameter gradient, the loss partial sums --
+ * live in a fixed device array of the library (about 10 MiB per device, held
+ * until the process ends) instead of the problem's workspace.  The call itself
+ * allocates nothing.  Limits: 1 <= n <= 4096 rows, n_out <= 128 outputs,
+ * n_params <= 2^20; beyond them it returns HHO_E_CAPACITY.  The device of the
+ * problem's workspace must be current (HHO_E_INVALID_ARG otherwise).  Every
+ * call on one device shares that array: calls that overlap on one device (other
+ * host threads, other streams) race and must be serialised by the caller. */
+int hho_learned_grad_noalloc(hho_problem *p, const float *X_dev, const float *T_dev, int64_t n, float *grad,
+                             double *loss);
+
 /* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on
  * batches of `batch` rows (<= 4096) drawn from the n rows of X, T: row i of the
  * batch of step s (counted from 0 since the last hho_learned_set_params, across

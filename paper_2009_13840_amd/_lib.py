@@ -28,7 +28,7 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
-           "hho_learned_collect", "hho_learned_grad", "hho_learned_train", "hho_mesh_create_union",
+           "hho_learned_collect", "hho_learned_grad", "hho_learned_grad_noalloc", "hho_learned_train", "hho_mesh_create_union",
            "hho_problem_set_segments", "hho_batch_results", "hho_autotune", "hho_recover_cells"]
 
 
@@ -108,6 +108,7 @@ def load():
         "hho_learned_apply": ([P, P, P], I32),
         "hho_learned_collect": ([P, P, I32, P, P, I64, C.POINTER(I64)], I32),
         "hho_learned_grad": ([P, P, P, I64, C.POINTER(C.c_float), D], I32),
+        "hho_learned_grad_noalloc": ([P, P, P, I64, C.POINTER(C.c_float), D], I32),
         "hho_learned_train": ([P, P, P, I64, I32, I32, C.c_float, C.c_uint64, C.POINTER(C.c_float)], I32),
     }
     for name, (args, res) in sig.items():
@@ -423,11 +424,15 @@ class Problem:
                                           C.c_void_p(T.data_ptr()), cap, C.byref(n)))
         return X[:n.value], T[:n.value]
 
-    def learned_grad(self, X, T):
+    def learned_grad(self, X, T, noalloc=False):
+        """Loss and parameter gradient over the rows of X, T (device FP32);
+        noalloc=True calls the variant whose work arrays live in the library's
+        fixed device array instead of the workspace."""
         g = np.zeros(self.learned_dims()["n_params"], dtype=np.float32)
         loss = C.c_double()
-        _check(load().hho_learned_grad(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), X.shape[0],
-                                       g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
+        fn = load().hho_learned_grad_noalloc if noalloc else load().hho_learned_grad
+        _check(fn(self.h, C.c_void_p(X.data_ptr()), C.c_void_p(T.data_ptr()), X.shape[0],
+                  g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)))
         return loss.value, g
 
     def learned_train(self, X, T, steps, batch=1024, lr=1e-3, seed=0):

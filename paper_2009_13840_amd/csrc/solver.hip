@@ -5,6 +5,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1717,14 +1718,26 @@ int hho_learned_collect(hho_problem *p, const double *x_true, int cycles, float 
   ABI_END
 }
 
-// loss and gradient of the batch rows (rows == null: rows 0..B-1) at the current parameters
-static double mlp_loss_grad(hho_problem *p, const float *X, const float *Tg, const int *rows, int B, double *loss_dev) {
+// work arrays of one loss-and-gradient evaluation over at most kMlpMaxBatch rows
+struct MlpWork {
+  float *Z, *Y, *dY, *dZ, *g;  // hidden activations, outputs, their gradients, parameter gradient
+  double *partial;             // per-block partial sums of the squared errors
+};
+
+static MlpWork mlp_work(hho_problem *p) {
+  return {p->mlp_Z, p->mlp_Yb, p->mlp_dY, p->mlp_dZ, p->mlp_g, p->partial};
+}
+
+// loss and gradient (into w.g) of the batch rows (rows == null: rows 0..B-1) at the
+// current parameters; the summed squared error goes to loss_dev
+static double mlp_loss_grad(hho_problem *p, const MlpWork &w, const float *X, const float *Tg, const int *rows, int B,
+                            double *loss_dev) {
   const hho::MlpDims &md = p->md;
   hipStream_t s = p->stream;
-  hho::launch_mlp_forward(B, md.n_in, md.n_out, X, rows, p->mlp_prm, p->mlp_Z, p->mlp_Yb, s);
-  const int G = hho::launch_mlp_backward(B, md.n_in, md.n_out, X, rows, Tg, p->mlp_prm, p->mlp_Z, p->mlp_Yb,
-                                         p->mlp_dY, p->mlp_dZ, p->mlp_g, p->partial, s);
-  hho::launch_sum_finish(G, p->partial, loss_dev, s);
+  hho::launch_mlp_forward(B, md.n_in, md.n_out, X, rows, p->mlp_prm, w.Z, w.Y, s);
+  const int G = hho::launch_mlp_backward(B, md.n_in, md.n_out, X, rows, Tg, p->mlp_prm, w.Z, w.Y, w.dY, w.dZ, w.g,
+                                         w.partial, s);
+  hho::launch_sum_finish(G, w.partial, loss_dev, s);
   return 0.5 / B;  // factor turning the summed squares into the loss
 }
 
@@ -1734,12 +1747,89 @@ int hho_learned_grad(hho_problem *p, const float *X, const float *Tg, int64_t n,
   if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_grad: no parameters set");
   if (!X || !Tg || !grad || !loss || n < 1 || n > hho::kMlpMaxBatch)
     hho::fail(HHO_E_INVALID_ARG, "learned_grad: bad argument (1 <= n <= 4096)");
-  const double f = mlp_loss_grad(p, X, Tg, nullptr, (int)n, p->mlp_loss);
+  const double f = mlp_loss_grad(p, mlp_work(p), X, Tg, nullptr, (int)n, p->mlp_loss);
   const int64_t np = hho::mlp_param_count(p->md);
   double ls = 0;
   HIPCHK(hipMemcpyAsync(grad, p->mlp_g, np * sizeof(float), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipMemcpyAsync(&ls, p->mlp_loss, sizeof(double), hipMemcpyDeviceToHost, p->stream));
   HIPCHK(hipStreamSynchronize(p->stream));
+  *loss = f * ls;
+  return HHO_OK;
+  ABI_END
+}
+
+// ------------------------------------------------------------ allocation-free gradient
+// hho_learned_grad_noalloc keeps its work arrays in this file-scope device array
+// instead of the problem's workspace: hidden activations and their gradients
+// (kMlpMaxBatch x kMlpHidden floats each), outputs and their gradients
+// (kMlpMaxBatch x kNoallocMaxOut floats each), the parameter gradient
+// (kNoallocMaxParams floats), the per-block loss partials and the summed loss.
+// Every array is written before it is read within one call, so nothing is
+// cleared.  Each device holds its own copy; host code reaches it only through
+// the address hipGetSymbolAddress returns on that device.
+namespace hho {
+constexpr int64_t kNoallocMaxOut = 128;
+constexpr int64_t kNoallocMaxParams = int64_t(1) << 20;
+constexpr int64_t kNoallocPartials = 512;
+constexpr int64_t kNoallocZ = (int64_t)kMlpMaxBatch * kMlpHidden * sizeof(float);
+constexpr int64_t kNoallocY = (int64_t)kMlpMaxBatch * kNoallocMaxOut * sizeof(float);
+constexpr int64_t kNoallocG = kNoallocMaxParams * sizeof(float);
+constexpr int64_t kNoallocBytes = 2 * kNoallocZ + 2 * kNoallocY + kNoallocG + (kNoallocPartials + 256) * sizeof(double);
+constexpr int kNoallocMaxDevices = 64;
+}  // namespace hho
+
+static __device__ __align__(256) unsigned char scratch[hho::kNoallocBytes];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[hho::kNoallocMaxDevices];
+
+// device address of `scratch` on the current device, looked up once per device
+static char *noalloc_scratch(hho_problem *p) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= hho::kNoallocMaxDevices) hho::fail(HHO_E_DEVICE, "learned_grad_noalloc: device ordinal out of range");
+  hipPointerAttribute_t attr{};
+  HIPCHK(hipPointerGetAttributes(&attr, p->ws));
+  if (attr.device != dev)
+    hho::fail(HHO_E_INVALID_ARG, "learned_grad_noalloc: make the device of the problem's workspace current first");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    if (!ptr) hho::fail(HHO_E_DEVICE, "learned_grad_noalloc: no device address for the scratch array");
+    g_scratch_ptr[dev] = ptr;
+  }
+  return (char *)g_scratch_ptr[dev];
+}
+
+int hho_learned_grad_noalloc(hho_problem *p, const float *X, const float *Tg, int64_t n, float *grad, double *loss) {
+  ABI_BEGIN
+  need_learned(p);
+  if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_grad_noalloc: no parameters set");
+  if (!X || !Tg || !grad || !loss || n < 1) hho::fail(HHO_E_INVALID_ARG, "learned_grad_noalloc: bad argument");
+  const hho::MlpDims &md = p->md;
+  const int64_t np = hho::mlp_param_count(md);
+  if (n > hho::kMlpMaxBatch || md.n_out > hho::kNoallocMaxOut || np > hho::kNoallocMaxParams) {
+    hho::set_error("learned_grad_noalloc: beyond the scratch limits (rows <= " + std::to_string(hho::kMlpMaxBatch) +
+                   ", outputs <= " + std::to_string(hho::kNoallocMaxOut) + ", parameters <= " +
+                   std::to_string(hho::kNoallocMaxParams) + ")");
+    return HHO_E_CAPACITY;
+  }
+  char *base = noalloc_scratch(p);
+  MlpWork w;
+  w.Z = (float *)base;
+  w.dZ = (float *)(base + hho::kNoallocZ);
+  w.Y = (float *)(base + 2 * hho::kNoallocZ);
+  w.dY = (float *)(base + 2 * hho::kNoallocZ + hho::kNoallocY);
+  w.g = (float *)(base + 2 * hho::kNoallocZ + 2 * hho::kNoallocY);
+  w.partial = (double *)(base + 2 * hho::kNoallocZ + 2 * hho::kNoallocY + hho::kNoallocG);
+  double *ls_dev = w.partial + hho::kNoallocPartials;
+  const double f = mlp_loss_grad(p, w, X, Tg, nullptr, (int)n, ls_dev);
+  double ls = 0;
+  HIPCHK(hipMemcpyAsync(grad, w.g, np * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(&ls, ls_dev, sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipGetLastError());
   *loss = f * ls;
   return HHO_OK;
   ABI_END
@@ -1758,7 +1848,7 @@ int hho_learned_train(hho_problem *p, const float *X, const float *Tg, int64_t n
   double f = 0;
   for (int it = 0; it < steps; ++it) {
     hho::launch_mlp_rows(batch, n, seed, p->adam_step, p->mlp_rows, s);
-    f = mlp_loss_grad(p, X, Tg, p->mlp_rows, batch, p->mlp_loss + it);
+    f = mlp_loss_grad(p, mlp_work(p), X, Tg, p->mlp_rows, batch, p->mlp_loss + it);
     hho::launch_mlp_adam(np, p->mlp_prm, p->mlp_g, p->mlp_m, p->mlp_v, lr, ++p->adam_step, s);
   }
   if (loss_hist) {
