@@ -28,12 +28,13 @@ METRIC = "time-to-1e-8 residual & V-cycle GDOF/s: mixed/learned vs plain FP64, 1
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 30
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
+PROBE_STRIDE = 16
 
 
 def kernel_source_digest():
     import hashlib
     h = hashlib.sha256()
-    for f in ("k_spmv.hip", "k_solve.hip", "device.h", "dev_common.h"):
+    for f in ("k_spmv.hip", "k_solve.hip", "k_amg.hip", "device.h", "dev_common.h"):
         with open(os.path.join(ROOT, "paper_2009_13840_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -183,31 +184,102 @@ def train_learned(P, n0, forcings=8, cycles=3, steps=1500, batch=2048, lr=1e-3):
             "loss_zero_predictor": base, "fgmres_its_plain": its_plain}
 
 
-def cpu_baseline(spec, sample_cells=1024):
-    """The oracle as it stands, end to end (local operators, condensation,
-    assembly, levels, Schwarz setup, FGMRES to 1e-8), on a smaller mesh of the
-    same family; reported in the metric's unit (fine DOFs solved per second)."""
-    from threadpoolctl import threadpool_limits
+_POOL_INPUT = None  # (mesh, geo, eta, data) of the CPU baseline, inherited by forked workers
+
+
+def _oracle_local(cells):
+    """Worker of the untimed host phase of the CPU baseline: the oracle's local
+    operators of some cells (the same call its build step makes)."""
+    from oracle.hho import local_hho
+    mesh, geo, eta, data = _POOL_INPUT
+    return [local_hho(mesh, geo, c, eta, *data) for c in cells]
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(spec, sample_cells=4096):
+    """The oracle as it stands, on a bounded sample of the workload's family (the
+    same mesh generator and seed, fewer cells; same degree, variant and solver
+    settings: cell-patch Schwarz GMRES(2) smoothing, coarsest level by GMRES to
+    1e-3 with the block-triangular AMG preconditioner, FGMRES to 1e-8).  Timed:
+    the phases of the GPU step -- condensation, assembly, coarse operators,
+    smoother and coarse-solver setup, FGMRES.  Untimed: the mesh and the local
+    HHO operators (the GPU step takes them as input too), the latter spread over
+    a process pool.  Reported in the metric's unit, fine DOFs solved per second."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    from threadpoolctl import threadpool_info
     import oracle.solve as OS
-    from synth import voronoi_lloyd, cartesian_quads, cartesian_hexes
+    from oracle.hho import mesh_geometry
+    from oracle.condense import condense_v, condense_vp
+    from oracle.system import assemble_condensed, coarse_indices, layout, nullspace
+    from synth import voronoi_lloyd, cartesian_hexes
     if spec["mesh"] == "voronoi":
         mesh = voronoi_lloyd(sample_cells, spec["seed"])
         name = f"voronoi{sample_cells}_k{spec['k']}_{spec['cond']}"
     elif spec["mesh"] == "hex":
-        mesh = cartesian_hexes(4)
-        name = f"hex4_k{spec['k']}_{spec['cond']}"
+        n = 6
+        mesh = cartesian_hexes(n)
+        name = f"hex{n}_k{spec['k']}_{spec['cond']}"
     else:
-        mesh = cartesian_quads(spec["n"])
+        mesh = make_mesh(spec)
         name = f"quad{spec['n']}_k{spec['k']}_{spec['cond']}"
     data = make_data(spec, mesh.dim)
-    with threadpool_limits(limits=1):
-        t0 = time.perf_counter()
-        P = OS.build(mesh, spec["k"], spec["cond"], data)
-        x, its, hist, conv = OS.solve_fgmres(P, rtol=1e-8, coarse="gmres", coarse_rtol=1e-3)
-        dt = time.perf_counter() - t0
-    n0 = P.S[0].shape[0]
-    return {"value": n0 / dt / 1e9, "unit": "GDOF/s", "cores": 1, "kind": "oracle",
-            "sample": f"{name}: {n0} fine DOFs, {its} FGMRES its, {dt:.1f} s single-thread (NumPy/SciPy FP64)"}
+    k, cond = spec["k"], spec["cond"]
+    degrees = list(range(k, -1, -1))
+    eta = OS.default_eta(mesh, k)
+    t_host = time.perf_counter()
+    geo = mesh_geometry(mesh, k, None)
+    workers = max(1, min(16, os.cpu_count() or 1))
+    chunks = [list(range(i, mesh.n_cells, workers)) for i in range(workers)]
+    global _POOL_INPUT
+    _POOL_INPUT = (mesh, geo, eta, data)
+    # forked workers (run before this process touches the GPU) inherit the inputs
+    with ProcessPoolExecutor(workers, mp_context=mp.get_context("fork")) as ex:
+        parts = list(ex.map(_oracle_local, chunks))
+    _POOL_INPUT = None
+    locs = [None] * mesh.n_cells
+    for ch, part in zip(chunks, parts):
+        for c, L in zip(ch, part):
+            locs[c] = L
+    t_host = time.perf_counter() - t_host
+    threads = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    t0 = time.perf_counter()
+    cfun = condense_v if cond == "v" else condense_vp
+    blocks = [cfun(L) for L in locs]
+    lays = [layout(mesh, kl, cond) for kl in degrees]
+    S0, b = assemble_condensed(mesh, blocks, mesh.dim, lays[0].nF, lays[0].nP)
+    S, idx = [S0], []
+    for l in range(len(degrees) - 1):
+        ii = coarse_indices(lays[l], lays[l + 1])
+        idx.append(ii)
+        S.append(S[-1][ii][:, ii].tocsr())
+    z = [nullspace(mesh, geo, lay) for lay in lays]
+    P = OS.Problem(mesh, geo, k, cond, degrees, eta, locs, blocks, lays, S, b, idx, z)
+    t1 = time.perf_counter()
+    H = OS.hierarchy(P, coarse="amg", coarse_rtol=1e-3)
+    x, its, hist, conv = OS.solve_fgmres(P, rtol=1e-8, H=H)
+    t2 = time.perf_counter()
+    dt = t2 - t0
+    n0 = S0.shape[0]
+    return {"value": n0 / dt / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
+            "sample": (f"{name}: {n0} fine DOFs, FGMRES {its} its to 1e-8 ({'converged' if conv else 'NOT converged'}), "
+                       f"{sum(H.coarse_its)} coarse its; timed {dt:.1f} s = condensation/assembly/levels "
+                       f"{t1 - t0:.1f} s + smoother/coarse setup and FGMRES {t2 - t1:.1f} s (NumPy/SciPy FP64: "
+                       f"dense products on up to {threads} BLAS threads, per-cell loops and sparse products on one); "
+                       f"untimed local operators {t_host:.1f} s on {workers} processes"),
+            "phases_s": {"condense_assemble_levels": round(t1 - t0, 3), "setup_and_fgmres": round(t2 - t1, 3),
+                         "local_operators_untimed": round(t_host, 3)}}
 
 
 def run_batch(args):
@@ -292,18 +364,240 @@ def run_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _amg_bytes(kind, L, N, d):
+    """Algorithmic bytes of one launch of an AMG kernel class on the level with
+    sizes L (rows n, next-level rows nc, entries of A, P, B = A P) and the next
+    level N: every matrix entry (8-byte value + 4-byte index) and row pointer
+    once, every vector read once and written once."""
+    n, nc = L["n"], L["nc"]
+    vec = n * d * 8
+    if kind == "amg_restrict":   # rc = P^T r - B^T x
+        return 2 * (nc + 1) * 4 + 12 * (L["nnz_p"] + L["nnz_b"]) + 2 * vec + n * 8 + nc * d * 8
+    if kind == "amg_sweep":      # x_out = x_in + w D^-1 (r - A x_in)
+        return (n + 1) * 4 + 12 * L["nnz_a"] + n * 8 + 3 * vec
+    if kind == "amg_prolong":    # x_out = x_in + P x_c + w D^-1 (r - A x_in - B x_c)
+        return 3 * (n + 1) * 4 + 12 * (L["nnz_a"] + L["nnz_b"] + L["nnz_p"]) + n * 8 + 3 * vec + nc * d * 8
+    if kind == "amg_dense":      # x = M r, M explicit n x n
+        return n * n * 8 + 2 * vec
+    raise ValueError(kind)
+
+
+class ByteModel:
+    """Algorithmic bytes per launch of every probed kernel class, by level."""
+
+    def __init__(self, P, mesh, spec, precision):
+        self.mesh, self.spec, self.P = mesh, spec, P
+        self.k, self.cond = spec["k"], spec["cond"]
+        self.degrees = list(range(self.k, -1, -1))
+        self.nlev = len(self.degrees)
+        self.elem = [4 if (precision == "fp32" and l < self.nlev - 1) else 8 for l in range(self.nlev)]
+        self._spmv = {}
+        self.amg = []
+        try:
+            lv0 = P.amg_level_info(0)
+            self.amg = [P.amg_level_info(l) for l in range(lv0["levels"])]
+        except Exception:
+            self.amg = []
+
+    def spmv(self, level, elem):
+        key = (level, elem)
+        if key not in self._spmv:
+            self._spmv[key] = spmv_bytes(self.mesh, self.k, self.cond, self.degrees[level], elem)
+        return self._spmv[key]
+
+    def bytes(self, kind, level):
+        d = self.mesh.dim
+        if kind == "operator":       # two-slot input form: one more vector read
+            b, info = self.spmv(level, self.elem[level])
+            return b + info["N"] * self.elem[level]
+        if kind == "smoother":
+            return precond_bytes(self.mesh, self.degrees[level], self.cond, self.elem[level])
+        if kind == "coarse_operator":
+            return self.spmv(self.nlev - 1, 8)[0]
+        if kind == "outer_operator":
+            return self.spmv(0, 8)[0]
+        L = self.amg[level]
+        N = self.amg[level + 1] if level + 1 < len(self.amg) else None
+        return _amg_bytes(kind, L, N, d)
+
+    def levels(self, kind):
+        if kind in ("operator", "smoother"):
+            return range(self.nlev - 1)
+        if kind == "coarse_operator":
+            return [self.nlev - 1]
+        if kind == "outer_operator":
+            return [0]
+        return range(len(self.amg))
+
+
+def kernel_label(kind, mesh, spec, model, level):
+    """Kernel name of a probed class on a level, as rocprofv3 lists it."""
+    from math import comb
+    d = mesh.dim
+    if kind in ("operator", "smoother"):
+        k = model.degrees[level]
+        T = "float" if model.elem[level] == 4 else "double"
+        if kind == "operator":
+            return fine_kernel_name(d, k, spec["cond"], "fp32" if T == "float" else "fp64")
+        p = comb(k + d - 1, d - 1)
+        rows = int(np.diff(np.asarray(mesh.cell_ptr)).max()) * (p if spec["cond"] == "v" else d * p)
+        return f"k_precond<{T}, {(rows + 63) // 64}, {d if spec['cond'] == 'v' else 1}>"
+    return {"amg_restrict": "k_amg_restrict", "amg_sweep": "k_amg_rows<G>", "amg_prolong": "k_amg_prolong_sweep<G>",
+            "amg_dense": "k_amg_dense", "coarse_operator": "k = 0 operator (k_spmv_v0 / k_spmv_vp)",
+            "outer_operator": "level-0 operator, one-slot form"}[kind]
+
+
+def probe_table(P, model):
+    """Launches, time and algorithmic bytes of every armed class, per level."""
+    import paper_2009_13840_amd as H
+    out = {}
+    for kind, bit in H.PROBE.items():
+        rows = []
+        for l in model.levels(kind):
+            n, ms, alln = P.probe_read(bit, l)
+            if n:
+                rows.append({"level": l, "launches": n, "ms": ms, "all_launches": alln,
+                             "bytes_per_launch": int(model.bytes(kind, l))})
+        if rows:
+            out[kind] = rows
+    return out
+
+
+def roofline_from(table, kind, label, workload):
+    rows = table[kind]
+    launches = sum(r["launches"] for r in rows)
+    all_launches = sum(r["all_launches"] for r in rows)
+    ms = sum(r["ms"] for r in rows)
+    nbytes = sum(r["launches"] * r["bytes_per_launch"] for r in rows)
+    achieved = nbytes / (ms / 1e3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(workload, label),
+            "kernel": label, "class": kind, "timed_launches": launches, "launches": all_launches,
+            "avg_launch_ms": round(ms / launches, 5),
+            "bytes_per_launch": int(nbytes / launches),
+            "levels": [{"level": r["level"], "launches": r["launches"], "avg_us": round(1e3 * r["ms"] / r["launches"], 2),
+                        "bytes_per_launch": r["bytes_per_launch"],
+                        "frac": round(r["bytes_per_launch"] / (r["ms"] / r["launches"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+                       for r in rows]}
+
+
+def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=None, probe=True):
+    """One configuration of the solver on the workload: host phase and upload
+    (untimed), optional training of the learned smoother (untimed), warmup steps,
+    then `args.steps` timed steps (setup + solve to 1e-8), each checked for
+    convergence.  With probe=True an untimed step first times every probed kernel
+    class; the class with the most time is then the only one armed during the
+    timed steps (its launches bracketed by events on the library's stream)."""
+    import torch
+    import paper_2009_13840_amd as H
+    M = H.Mesh(mesh)
+    P = H.Problem(M, spec["k"], spec["cond"], precision=precision, coarse_rtol=args.coarse_rtol,
+                  learned=1 if learned else 0)
+    t_host = time.perf_counter()
+    P.set_data(*data)
+    t_host = time.perf_counter() - t_host
+    P.bind("cuda:0")
+    P.upload()
+    torch.cuda.synchronize()
+    n0 = P.level_size(0)
+    tag = f"{workload} {precision}{' learned' if learned else ''}"
+    print(f"[bench] {tag}: host phase {t_host:.2f}s, workspace {P.workspace_size() / 2**30:.2f} GiB, "
+          f"fine DOFs {n0}", file=sys.stderr, flush=True)
+    learned_info = train_learned(P, n0) if learned else None
+    failures = []
+
+    def step(label):
+        P.setup()
+        x, its, hist, rel, ok = P.solve()
+        if not ok or not rel <= 1e-8:
+            failures.append(f"{label}: its={its} rel={rel:.3e} converged={ok}")
+        return x, its, hist, rel, ok
+
+    if args.autotune and probe:
+        P.setup()
+        print(f"[bench] {tag} autotuned (operator block, patch threads) per level: {P.autotune().tolist()}",
+              file=sys.stderr, flush=True)
+    for w in range(args.warmup):
+        _, its, _, rel, ok = step(f"warmup {w}")
+        print(f"[bench] {tag} warmup {w}: its={its} rel={rel:.2e} ok={ok}", file=sys.stderr, flush=True)
+    model = ByteModel(P, mesh, spec, precision)
+    table_all, dominant = None, None
+    if probe:
+        P.probe_arm(sum(H.PROBE.values()))
+        step("probe step")
+        table_all = probe_table(P, model)
+        P.probe_arm(0)
+        dominant = max(table_all, key=lambda kk: sum(r["ms"] for r in table_all[kk]))
+        # one launch in PROBE_STRIDE of the dominant class is timed during the
+        # timed steps (the host's event calls would otherwise slow short launches)
+        P.probe_arm(H.PROBE[dominant], PROBE_STRIDE)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for st in range(args.steps):
+        x, its, hist, rel, ok = step(f"step {st}")
+        results.append((its, rel, ok, P.timings()))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    roof = None
+    if probe:
+        table_timed = probe_table(P, model)
+        P.probe_arm(0)
+        top = max(table_timed[dominant], key=lambda r: r["ms"])["level"]
+        label = kernel_label(dominant, mesh, spec, model, top)
+        roof = roofline_from(table_timed, dominant, label, workload)
+    for st, (its, rel, ok, tm) in enumerate(results):
+        print(f"[bench] {tag} step {st}: its={its} rel={rel:.2e} ok={ok} "
+              f"{json.dumps({kk: round(v, 3) for kk, v in tm.items()})}", file=sys.stderr, flush=True)
+    its, rel, ok, tm = results[-1]
+    vc_gdofs = n0 * tm["vcycles"] / (tm["vcycle_ms"] / 1e3) / 1e9 if tm["vcycle_ms"] > 0 else None
+    rec = {"precision": precision, "learned": learned, "time_to_1e8_ms": round(dt * 1e3, 3),
+           "gdof_s": round(n0 / dt / 1e9, 6), "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
+           "fgmres_its": its, "final_rel_residual": rel, "converged": not failures, "failures": failures,
+           "phase_ms": {kk: round(v, 3) for kk, v in tm.items()}, "host_set_data_s": round(t_host, 3)}
+    if learned_info:
+        rec["training"] = learned_info
+    # V-cycle roofline: algorithmic bytes of every probed launch of the probe step
+    # that belongs to the V-cycle, against the V-cycle time of the last timed step
+    if table_all:
+        vc_kinds = [kk for kk in table_all if kk != "outer_operator"]
+        vc_bytes = sum(r["launches"] * r["bytes_per_launch"] for kk in vc_kinds for r in table_all[kk])
+        vc_ms_probed = sum(r["ms"] for kk in vc_kinds for r in table_all[kk])
+        rec["vcycle_roofline"] = {
+            "bytes_per_vcycle": int(vc_bytes / max(tm["vcycles"], 1)),
+            "vcycle_ms": round(tm["vcycle_ms"] / max(tm["vcycles"], 1), 4),
+            "achieved": round(vc_bytes / max(tm["vcycles"], 1) / (tm["vcycle_ms"] / max(tm["vcycles"], 1) / 1e3) / 1e9, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(vc_bytes / (tm["vcycle_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+            "note": "bytes: the probed kernel classes of one untimed step (operator, smoother, coarse operator, "
+                    "AMG) per V-cycle; time: the V-cycle's events of the last timed step; Krylov vector "
+                    "traffic is not counted in the bytes",
+            "probed_kernel_ms_share": round(vc_ms_probed / tm["vcycle_ms"] / 1.0, 4) if tm["vcycle_ms"] else None,
+            "classes": {kk: {"launches": sum(r["launches"] for r in table_all[kk]),
+                             "ms": round(sum(r["ms"] for r in table_all[kk]), 3),
+                             "gbytes": round(sum(r["launches"] * r["bytes_per_launch"] for r in table_all[kk]) / 1e9, 4)}
+                        for kk in table_all}}
+    if x_ref is not None:
+        rec["err_vs_fp64_reference"] = float(torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref))
+    return P, x, rec, roof
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="voronoi16384_k3_v", choices=sorted(WORKLOADS) + ["batch256"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the headline run (the other modes are reported beside it)")
     ap.add_argument("--coarse-rtol", type=float, default=1e-3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--kernel-reps", type=int, default=50)
-    ap.add_argument("--learned", action="store_true",
-                    help="train the learned fine-level smoother first (untimed) and solve with it")
+    ap.add_argument("--modes", default="fp64,fp32,learned",
+                    help="comma list of the solver forms timed on the workload: fp64, fp32, learned")
+    ap.add_argument("--largest", default="hex32_k3_vp",
+                    help="second workload timed in FP64 and FP32 beside the headline ('none' to skip)")
+    ap.add_argument("--cpu-sample-cells", type=int, default=4096)
+    ap.add_argument("--learned", action="store_true", help="headline run with the learned smoother")
     ap.add_argument("--autotune", action="store_true",
                     help="pick per-level launch shapes with the library's autotuner first (untimed)")
     ap.add_argument("--traffic-calibration", action="store_true",
@@ -317,25 +611,18 @@ def main():
     if args.workload == "batch256":
         return run_batch(args)
 
-    import torch
-    import paper_2009_13840_amd as H
+    # the CPU baseline first: its host-phase workers are forked before this
+    # process initialises the GPU
+    cpu = None
+    if not args.no_cpu_baseline:
+        try:
+            cpu = cpu_baseline(WORKLOADS[args.workload], args.cpu_sample_cells)
+        except Exception as e:  # pragma: no cover
+            cpu = {"error": repr(e)}
+        print(f"[bench] cpu baseline: {json.dumps(cpu)}", file=sys.stderr, flush=True)
 
-    spec = WORKLOADS[args.workload]
-    t_mesh = time.perf_counter()
-    mesh = make_mesh(spec)
-    data = make_data(spec, mesh.dim)
-    t_mesh = time.perf_counter() - t_mesh
-    print(f"[bench] workload {args.workload}: {mesh.n_cells} cells, {mesh.n_faces} faces "
-          f"(mesh {t_mesh:.1f}s)", file=sys.stderr, flush=True)
-    M = H.Mesh(mesh)
-    P = H.Problem(M, spec["k"], spec["cond"], precision=args.precision, coarse_rtol=args.coarse_rtol,
-                  learned=1 if args.learned else 0)
-    t_host = time.perf_counter()
-    P.set_data(*data)
-    t_host = time.perf_counter() - t_host
-    P.bind("cuda:0")
-    P.upload()
-    torch.cuda.synchronize()
+    import torch
+
     if args.traffic_calibration:
         src = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device="cuda:0")
         dst = torch.empty_like(src)
@@ -343,106 +630,128 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+
+    def workload_inputs(name):
+        spec = WORKLOADS[name]
+        t = time.perf_counter()
+        mesh = make_mesh(spec)
+        data = make_data(spec, mesh.dim)
+        print(f"[bench] workload {name}: {mesh.n_cells} cells, {mesh.n_faces} faces "
+              f"(mesh {time.perf_counter() - t:.1f}s)", file=sys.stderr, flush=True)
+        return spec, mesh, data
+
+    spec, mesh, data = workload_inputs(args.workload)
+    modes = [m for m in args.modes.split(",") if m]
+    head_mode = "learned" if args.learned else args.precision
+    if head_mode not in modes:
+        modes.insert(0, head_mode)
+    # headline first, so the reference solution comes from it when it is FP64
+    modes.sort(key=lambda m: (m != head_mode, m != "fp64"))
+    records, head = {}, None
+    x_ref = None
+    for m in modes:
+        prec = "fp64" if m in ("fp64", "learned") else "fp32"
+        P, x, rec, roof = run_mode(mesh, data, spec, args.workload, prec, args, learned=(m == "learned"),
+                                   x_ref=x_ref, probe=(m == head_mode))
+        if x_ref is None:
+            # FP64 reference for the error of every form: this problem solved again to 1e-12 (untimed)
+            P.set_tolerances(1e-12, 1000, args.coarse_rtol, 300)
+            P.setup()
+            x_ref, its_ref, _, rel_ref, ok_ref = P.solve()
+            x_ref = x_ref.clone()
+            rec["err_vs_fp64_reference"] = float(torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref))
+            ref_info = {"rtol": 1e-12, "fgmres_its": its_ref, "final_rel_residual": rel_ref, "converged": ok_ref,
+                        "from": m}
+        if m == head_mode:
+            head = (P, x, rec, roof)
+        else:
+            del P
+        records[m] = rec
+        torch.cuda.synchronize()
+    P, x, rec, roof = head
     n0 = P.level_size(0)
-    print(f"[bench] host local operators {t_host:.2f}s, workspace {P.workspace_size() / 2**30:.2f} GiB, "
-          f"fine DOFs {n0}", file=sys.stderr, flush=True)
-
-    def step():
-        P.setup()
-        return P.solve()
-
-    tuned = None
-    if args.autotune:
-        P.setup()
-        tuned = P.autotune().tolist()
-        print(f"[bench] autotuned (operator block, patch threads) per level: {tuned}", file=sys.stderr, flush=True)
-    learned_info = None
-    if args.learned:
-        learned_info = train_learned(P, n0)
-
-    for w in range(args.warmup):
-        _, its, _, rel, ok = step()
-        print(f"[bench] warmup {w}: its={its} rel={rel:.2e} ok={ok}", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for s in range(args.steps):
-        x, its, hist, rel, ok = step()
-        results.append((its, rel, ok, P.timings()))
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    for s, (its, rel, ok, tm) in enumerate(results):
-        print(f"[bench] step {s}: its={its} rel={rel:.2e} ok={ok} {json.dumps({k: round(v, 3) for k, v in tm.items()})}",
-              file=sys.stderr, flush=True)
-    its, rel, ok, tm = results[-1]
-    vc_gdofs = n0 * tm["vcycles"] / (tm["vcycle_ms"] / 1e3) / 1e9 if tm["vcycle_ms"] > 0 else None
-    # back-substitution of the cell unknowns from the last solution (outside the
-    # step): wall time of the call, which returns after its kernel has finished
+    # back-substitution of the cell unknowns from the headline solution (outside the step)
     rec_ms = []
     for _ in range(3):
         t1 = time.perf_counter()
         P.recover_cells(x)
         rec_ms.append((time.perf_counter() - t1) * 1e3)
+    base = records.get("fp64")
+    for m, r in records.items():
+        if base and m != "fp64" and r["converged"] and base["converged"]:
+            r["speedup_vs_fp64"] = round(base["time_to_1e8_ms"] / r["time_to_1e8_ms"], 4)
+            if r.get("vcycle_gdof_s") and base.get("vcycle_gdof_s"):
+                r["vcycle_speedup_vs_fp64"] = round(r["vcycle_gdof_s"] / base["vcycle_gdof_s"], 4)
+    del P, head
+    torch.cuda.empty_cache()
 
-    # roofline of the dominant memory-bound kernel: the fine-level operator application
-    kind = 2  # the V-cycle's operator application (two-slot input) on level 0
-    avg_ms = P.time_kernel(kind, 0, args.kernel_reps)
-    elem = 4 if args.precision == "fp32" else 8
-    nbytes, info = spmv_bytes(mesh, spec["k"], spec["cond"], spec["k"], elem)
-    nbytes += info["N"] * elem  # second slot of the input face part + combined write of the input
-    achieved = nbytes / (avg_ms / 1e3) / 1e9
-    kname = fine_kernel_name(mesh.dim, spec["k"], spec["cond"], args.precision)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(args.workload, kname),
-            "kernel": kname, "bytes_per_launch": int(nbytes), "avg_launch_ms": round(avg_ms, 5)}
-    # the fine-level patch smoother (FP64), the other bandwidth-bound kernel of the V-cycle
-    pc_ms = P.time_kernel(1, 0, args.kernel_reps)
-    pc_bytes = precond_bytes(mesh, spec["k"], spec["cond"])
-    pc_name = precond_kernel_name(mesh, spec["k"], spec["cond"])
-    roof_pc = {"bound": "hbm", "achieved": round(pc_bytes / (pc_ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-               "unit": "GB/s", "frac": round(pc_bytes / (pc_ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
-               "traffic": measured_traffic(args.workload, pc_name), "kernel": pc_name,
-               "bytes_per_launch": int(pc_bytes), "avg_launch_ms": round(pc_ms, 5)}
+    largest = None
+    if args.largest and args.largest != "none" and args.largest != args.workload:
+        lspec, lmesh, ldata = workload_inputs(args.largest)
+        largest = {"workload": args.largest, "cells": lmesh.n_cells, "faces": lmesh.n_faces, "k": lspec["k"],
+                   "cond": lspec["cond"]}
+        lref = None
+        for prec in ("fp64", "fp32"):
+            LP, lx, lrec, lroof = run_mode(lmesh, ldata, lspec, args.largest, prec, args, x_ref=lref,
+                                           probe=(prec == "fp64"))
+            if prec == "fp64":
+                lref = lx.clone()
+                largest["fine_dofs"] = LP.level_size(0)
+                largest["roofline"] = lroof
+            lrec["err_vs_fp64_reference"] = float(torch.linalg.norm(lx - lref) / torch.linalg.norm(lref))
+            largest[prec] = lrec
+            del LP, lx
+            torch.cuda.empty_cache()
+        if largest["fp64"]["converged"] and largest["fp32"]["converged"]:
+            largest["fp32"]["speedup_vs_fp64"] = round(largest["fp64"]["time_to_1e8_ms"] /
+                                                       largest["fp32"]["time_to_1e8_ms"], 4)
+            if largest["fp32"].get("vcycle_gdof_s") and largest["fp64"].get("vcycle_gdof_s"):
+                largest["fp32"]["vcycle_speedup_vs_fp64"] = round(largest["fp32"]["vcycle_gdof_s"] /
+                                                                  largest["fp64"]["vcycle_gdof_s"], 4)
+        largest["note"] = ("err_vs_fp64_reference: relative difference from the FP64 solution of the same problem "
+                           "(both to 1e-8)")
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        try:
-            cpu = cpu_baseline(spec)
-        except Exception as e:  # pragma: no cover
-            cpu = {"error": repr(e)}
-
+    converged = rec["converged"]
     out = {
         "metric": METRIC,
-        "value": round(n0 / dt / 1e9, 6),
+        "value": round(n0 / (rec["time_to_1e8_ms"] / 1e3) / 1e9, 6) if converged else None,
         "unit": "GDOF/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(dt * 1e3, 3),
+        "ms_per_step": rec["time_to_1e8_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": ("f64" if args.precision == "fp64" else "f32 V-cycle / f64 outer") + (" + f32 MLP" if args.learned else ""),
+        "dtype": ("f64" if rec["precision"] == "fp64" else "f32 V-cycle / f64 outer") +
+                 (" + f32 MLP" if rec["learned"] else ""),
         "data": "synthetic",
         "config": {"workload": args.workload, "cells": mesh.n_cells, "faces": mesh.n_faces, "k": spec["k"],
                    "cond": spec["cond"], "levels": list(range(spec["k"], -1, -1)), "fine_dofs": n0,
-                   "rtol": 1e-8, "coarse": "gmres 1e-3" if n0 > 4096 else "dense"},
-        "time_to_1e8_ms": round(dt * 1e3, 3),
-        "fgmres_its": its,
-        "final_rel_residual": rel,
-        "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
-        "phase_ms": {k: round(v, 3) for k, v in tm.items()},
-        # outside the timed step: host-side local operators (incl. the data
-        # callbacks) and symbolic AMG hierarchy, before the upload
-        "host_set_data_s": round(t_host, 3),
+                   "rtol": 1e-8,
+                   "coarse": (f"GMRES to {args.coarse_rtol:g} preconditioned by a block-triangular Stokes "
+                              "preconditioner with a smoothed-aggregation AMG velocity block"
+                              if n0 > 4096 else "bordered dense inverse"),
+                   "smoother": "GMRES(2), right-preconditioned by cell-patch additive Schwarz"},
+        "converged": converged,
+        "failures": rec["failures"],
+        "time_to_1e8_ms": rec["time_to_1e8_ms"],
+        "fgmres_its": rec["fgmres_its"],
+        "final_rel_residual": rec["final_rel_residual"],
+        "vcycle_gdof_s": rec["vcycle_gdof_s"],
+        "phase_ms": rec["phase_ms"],
+        "modes": records,
+        "fp64_reference": ref_info,
+        "host_set_data_s": rec["host_set_data_s"],
         "recover_cells_ms": round(min(rec_ms), 3),
         "roofline": roof,
-        "roofline_smoother": roof_pc,
-        "learned": learned_info,
-        "autotune": tuned,
+        "roofline_vcycle": rec.get("vcycle_roofline"),
+        "largest_single_gpu": largest,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if not converged:
+        sys.exit(1)
 
 
 if __name__ == "__main__":

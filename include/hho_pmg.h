@@ -82,6 +82,13 @@ extern "C" {
 #define HHO_COARSE_AMG    3   /* GMRES to coarse_rtol, block-triangular Stokes preconditioner
                                  with a smoothed-aggregation velocity block (k_L = 0 only)     */
 
+/* smoother preconditioner of the V-cycle's GMRES(smooth_its) steps (Section 3.3) */
+#define HHO_SMOOTHER_SCHWARZ  0   /* cell-patch additive Schwarz (the only one on the GPU) */
+
+/* treatment of the constant-pressure null space */
+#define HHO_NULLSPACE_AUTO  0   /* projected out when the boundary has no Neumann face */
+#define HHO_NULLSPACE_NONE  1   /* never projected (the caller's right-hand side must be consistent) */
+
 /* face boundary flags in hho_mesh_desc.face_bc */
 #define HHO_FACE_INTERIOR   0
 #define HHO_FACE_DIRICHLET  1
@@ -126,6 +133,8 @@ typedef struct {
                                   matrix of their V-cycle, formed at setup (2048; 0 = never; at most 4096) */
   int32_t coarse_amg_psmooth;  /* AMG prolongator smoothing steps, at most: P = (I - w D^-1 A)^s T (1; 1 or 2;
                                   a level takes one step where two would make the next operator too dense) */
+  int32_t smoother;    /* HHO_SMOOTHER_* (SCHWARZ) */
+  int32_t nullspace;   /* HHO_NULLSPACE_* (AUTO) */
 } hho_options;
 
 /* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the
@@ -158,6 +167,20 @@ void hho_problem_destroy(hho_problem *p);
  * HHO_E_LOCAL_SINGULAR (reconstruction matrix not SPD). */
 int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_field_fn gN, void *ctx);
 
+/* Right-hand sides given directly as moments, replacing the data terms that
+ * hho_problem_set_data integrated (for instance moments computed elsewhere in
+ * the library's bases).  Per cell T, in mesh order: rhs_u holds d*nloc_T values,
+ * component c then local unknown i at c*nloc_T + i, the local unknowns being the
+ * n_T cell modes followed by the n_F modes of each face of T in T's face order
+ * (nloc_T = n_T + card(F_T) n_F); rhs_p holds n_T values per cell: the
+ * momentum and mass right-hand sides of the local problem of Section 2.3.1
+ * (data terms of eq. def:HHOAB, with the Dirichlet datum loading cell rows as
+ * well).  The local operators stay; the next hho_setup copies the records
+ * again.  Needs hho_problem_set_data first (NULL fields build the operators
+ * with zero data).  hho_moments_size gives the two lengths. */
+int hho_moments_size(const hho_problem *p, int64_t *n_u, int64_t *n_p);
+int hho_set_moments(hho_problem *p, const double *rhs_u, const double *rhs_p);
+
 /* Device workspace (see conventions).  hho_bind_workspace fails with
  * HHO_E_CAPACITY if bytes < hho_workspace_size(). */
 int hho_workspace_size(const hho_problem *p, size_t *bytes);
@@ -181,13 +204,32 @@ int hho_setup(hho_problem *p);
 /* Number of unknowns of level l in the global layout. */
 int hho_level_size(const hho_problem *p, int level, int64_t *n);
 
-/* FGMRES + V-cycle solve from x = 0.  x_dev (device, [level-0 size]) receives
- * the solution with the pressure normalised to zero mean when the boundary is
- * all Dirichlet.  iters receives the iteration count; hist (host, may be NULL)
- * receives min(hist_cap, iters+1) relative residual estimates, hist[0] = 1;
- * final_rel (may be NULL) the explicitly recomputed true relative residual.
- * Errors: HHO_E_NOT_CONVERGED (outputs written), HHO_E_BREAKDOWN, HHO_E_DEVICE. */
-int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel);
+/* FGMRES + V-cycle solve from x = 0 (Section 3.3), outputs in caller-owned
+ * host buffers: face_out [face_n] the face velocity modes in the global layout
+ * (face f, component c, mode j at (f*d + c)*n_F + j), cell_p_out [p_n] the cell
+ * pressure modes kept by the condensation (cell T, mode q at T*n_P + q: every
+ * mode of P^k for v-cond, the mean for v&p-cond), with face_n, p_n from
+ * hho_solution_sizes; the pressure has zero mean when the boundary is all
+ * Dirichlet.  iters receives the iteration count; hist (may be NULL) receives
+ * min(hist_cap, iters+1) relative residual estimates, hist[0] = 1; final_rel
+ * (may be NULL) the explicitly recomputed true relative residual.
+ * Errors: HHO_E_CAPACITY (face_cap < face_n or p_cap < p_n; nothing solved),
+ * HHO_E_NOT_CONVERGED (outputs written), HHO_E_BREAKDOWN, HHO_E_DEVICE. */
+int hho_solve(hho_problem *p, double *face_out, int64_t face_cap, double *cell_p_out, int64_t p_cap, int *iters,
+              double *hist, int hist_cap, double *final_rel);
+
+/* Sizes of hho_solve's outputs: face_n = n_faces*d*n_F, p_n = n_cells*n_P (level 0). */
+int hho_solution_sizes(const hho_problem *p, int64_t *face_n, int64_t *p_n);
+
+/* hho_solve with the whole level-0 solution written to x_dev (device,
+ * [level-0 size], global layout: face part then pressure part) on the problem's
+ * stream instead of host buffers. */
+int hho_solve_device(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel);
+
+/* Changes the stopping rules of later hho_solve calls (options.rtol, max_it,
+ * coarse_rtol, coarse_max_it; the restart lengths size the workspace and stay).
+ * Errors: HHO_E_INVALID_ARG (rtol or coarse_rtol outside (0, 1), limits < 1). */
+int hho_set_tolerances(hho_problem *p, double rtol, int max_it, double coarse_rtol, int coarse_max_it);
 
 /* Back-substitution of the cell unknowns eliminated by static condensation
  * (Section 4.1.2): from the level-0 solution x_dev of hho_solve (device, global
@@ -262,6 +304,42 @@ int hho_autotune(hho_problem *p, int reps, int *choices);
  * [8] coarse iterations total.  n is the capacity of t. */
 int hho_get_timings(const hho_problem *p, double *t, int n);
 
+/* ---- live kernel timing (measurement) ----
+ * Classes of kernel launches that hho_solve can time while it runs: each armed
+ * launch is bracketed by two HIP events recorded on the problem's stream (the
+ * stream the kernel runs on), and hho_probe_read sums the elapsed times.  The
+ * events add a few microseconds of ordering between launches; disarm (mask 0)
+ * for untimed runs.  "level" is the V-cycle level for the first three classes,
+ * the level of the coarse preconditioner's aggregation hierarchy for the AMG
+ * classes (Section 5.2's iterative coarsest-level solve, preconditioned). */
+#define HHO_PROBE_OPERATOR         1   /* operator application of a smoothing step (Section 3.3), level l */
+#define HHO_PROBE_SMOOTHER         2   /* cell-patch Schwarz preconditioner of a smoothing step, level l   */
+#define HHO_PROBE_COARSE_OPERATOR  4   /* coarsest-level operator inside the coarse GMRES                  */
+#define HHO_PROBE_OUTER_OPERATOR   8   /* FP64 level-0 operator of each FGMRES iteration                   */
+#define HHO_PROBE_AMG_RESTRICT    16   /* AMG restriction of the pre-smoothed residual, AMG level l         */
+#define HHO_PROBE_AMG_SWEEP       32   /* AMG damped-Jacobi sweeps, AMG level l                             */
+#define HHO_PROBE_AMG_PROLONG     64   /* AMG prolongation with the first post-sweep, AMG level l           */
+#define HHO_PROBE_AMG_DENSE      128   /* AMG explicit small-level operator or dense coarsest inverse       */
+#define HHO_PROBE_ALL            255
+
+/* Arms the classes of `mask` (0 disarms) and discards recorded launches; every
+ * stride-th launch (>= 1) of each armed class and level is timed, the first one
+ * included, so that the event calls do not hold up a stream of short launches. */
+int hho_probe_arm(hho_problem *p, unsigned mask, int stride);
+/* Timed launches of class `kind` (one HHO_PROBE_* bit) on `level` (-1: every
+ * level) and their summed duration in ms, since the last arm/clear; launches
+ * (may be NULL) receives every launch of that class and level, timed or not.
+ * Synchronises the problem's stream.  HHO_E_DEVICE if an event failed. */
+int hho_probe_read(hho_problem *p, int kind, int level, int64_t *timed, double *total_ms, int64_t *launches);
+/* Discards recorded launches (the armed classes stay armed). */
+int hho_probe_clear(hho_problem *p);
+/* Sizes of level `level` of the coarse preconditioner's aggregation hierarchy
+ * (problems whose coarsest solver is HHO_COARSE_AMG, after hho_problem_set_data):
+ * info[0] rows n, [1] coarse rows of the next level (0 on the last), [2] entries
+ * of A, [3] of the prolongator P, [4] of B = A P, [5] the first level applied as
+ * an explicit matrix (-1: none; set by the workspace plan), [6] number of levels. */
+int hho_amg_level_info(const hho_problem *p, int level, int64_t *info);
+
 /* ---- batches of independent problems (not in the paper) ----
  * n meshes become one mesh (their disjoint union; member i's faces and cells
  * keep their order and follow those of members 0..i-1), a problem on it is told
@@ -293,6 +371,31 @@ int hho_problem_set_segments(hho_problem *p, int n, const int64_t *face_ptr, con
  * residual of every member (host arrays of n = number of members). */
 int hho_batch_results(const hho_problem *p, int *iters, double *rel, int n);
 
+/* Batches built from separately created problems (the same combined problem as
+ * above, assembled by the library): n problems with equal dimension, degree
+ * schedule, condensation variant and solver options (the penalty eta may
+ * differ), each after hho_problem_set_data.  The batch copies the meshes and
+ * local operators (members may be destroyed afterwards) and owns one combined
+ * problem, returned by hho_batch_problem: query its workspace size, bind a
+ * workspace and stream, and call hho_setup on it as on any problem. */
+typedef struct hho_batch hho_batch;
+int hho_batch_create(hho_problem *const *ps, int n, hho_batch **out);
+void hho_batch_destroy(hho_batch *b);
+int hho_batch_problem(hho_batch *b, hho_problem **p);
+/* face_n[i], p_n[i]: hho_solve's output sizes of member i (host arrays of n). */
+int hho_batch_sizes(const hho_batch *b, int64_t *face_n, int64_t *p_n);
+/* Solves every member (one flexible GMRES process each, one V-cycle over the
+ * union).  Member i's face modes go to face_out[face_off[i] .. face_off[i+1]),
+ * its cell pressure modes to p_out[p_off[i] .. p_off[i+1]) (host, layouts as in
+ * hho_solve; ranges at least hho_batch_sizes long, else HHO_E_CAPACITY before
+ * any work).  Host arrays of n (may be NULL): iters, final_rel (true relative
+ * residual), status (HHO_OK or HHO_E_NOT_CONVERGED); hist with hist_off (n+1
+ * entries; may be NULL) receives member i's relative residual estimates, entry 0
+ * = 1, one per Arnoldi step it took, truncated to its range.  Returns HHO_OK
+ * when every member converged, else HHO_E_NOT_CONVERGED. */
+int hho_batch_solve(hho_batch *b, double *face_out, const int64_t *face_off, double *p_out, const int64_t *p_off,
+                    int *iters, double *hist, const int64_t *hist_off, double *final_rel, int *status);
+
 /* ---- learned fine-level smoother (not in the paper) ----
  * Needs a problem created with options.learned = 1 and a bound workspace.
  * Per face F of level 0 a network maps a window of the residual r to a
@@ -318,6 +421,15 @@ int hho_learned_set_params(hho_problem *p, const float *params, int64_t n);
 
 /* Copy the current parameters out (host, exactly n_params floats). */
 int hho_learned_get_params(const hho_problem *p, float *params, int64_t n);
+
+/* Parameters as bytes: a 32-byte header (magic "HHOMLP01", int32 n_in, n_out,
+ * hidden, 0, int64 n_params) followed by the n_params FP32 values in the layout
+ * above, host byte order.  hho_learned_save writes them to buf (host, cap
+ * bytes; *need receives the size, buf may be NULL to query it: HHO_E_CAPACITY);
+ * hho_learned_load reads them back (HHO_E_INVALID_ARG when the sizes differ
+ * from the problem's network) and resets the Adam moments. */
+int hho_learned_save(const hho_problem *p, void *buf, size_t cap, size_t *need);
+int hho_learned_load(hho_problem *p, const void *buf, size_t n);
 
 /* Use (on = 1) or stop using (0) the learned direction in level-0 smoothing. */
 int hho_learned_enable(hho_problem *p, int on);

@@ -19,17 +19,22 @@ HHO_OK = 0
 ERRORS = {-1: "HHO_E_INVALID_ARG", -2: "HHO_E_MESH", -3: "HHO_E_LOCAL_SINGULAR", -4: "HHO_E_NOT_CONVERGED",
           -5: "HHO_E_BREAKDOWN", -6: "HHO_E_DEVICE", -7: "HHO_E_CAPACITY", -8: "HHO_E_OOM"}
 COND = {"v": 1, "vp": 2}
+PROBE = {"operator": 1, "smoother": 2, "coarse_operator": 4, "outer_operator": 8, "amg_restrict": 16,
+         "amg_sweep": 32, "amg_prolong": 64, "amg_dense": 128}
 PREC = {"fp64": 0, "fp32": 1}
 COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
-           "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_get_rhs", "hho_get_condensed_cell",
+           "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_solve_device", "hho_solution_sizes",
+           "hho_moments_size", "hho_set_moments", "hho_batch_create", "hho_batch_destroy", "hho_batch_problem",
+           "hho_batch_sizes", "hho_batch_solve", "hho_learned_save", "hho_learned_load", "hho_get_rhs", "hho_get_condensed_cell",
            "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
            "hho_learned_collect", "hho_learned_grad", "hho_learned_grad_noalloc", "hho_learned_train", "hho_mesh_create_union",
-           "hho_problem_set_segments", "hho_batch_results", "hho_autotune", "hho_recover_cells"]
+           "hho_problem_set_segments", "hho_batch_results", "hho_autotune", "hho_recover_cells",
+           "hho_set_tolerances", "hho_probe_arm", "hho_probe_read", "hho_probe_clear", "hho_amg_level_info"]
 
 
 class HHOError(RuntimeError):
@@ -50,7 +55,8 @@ class Options(C.Structure):
                 ("smooth_its", C.c_int32), ("precision", C.c_int32), ("coarse_mode", C.c_int32),
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_max_it", C.c_int32),
                 ("quad_extra", C.c_int32), ("coarse_amg_sweeps", C.c_int32), ("learned", C.c_int32),
-                ("coarse_amg_explicit", C.c_int32), ("coarse_amg_psmooth", C.c_int32)]
+                ("coarse_amg_explicit", C.c_int32), ("coarse_amg_psmooth", C.c_int32), ("smoother", C.c_int32),
+                ("nullspace", C.c_int32)]
 
 
 FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -84,7 +90,19 @@ def load():
         "hho_set_stream": ([P, P], I32),
         "hho_setup": ([P], I32),
         "hho_level_size": ([P, I32, C.POINTER(I64)], I32),
-        "hho_solve": ([P, P, C.POINTER(C.c_int), D, I32, D], I32),
+        "hho_solve": ([P, D, I64, D, I64, C.POINTER(C.c_int), D, I32, D], I32),
+        "hho_solve_device": ([P, P, C.POINTER(C.c_int), D, I32, D], I32),
+        "hho_solution_sizes": ([P, C.POINTER(I64), C.POINTER(I64)], I32),
+        "hho_moments_size": ([P, C.POINTER(I64), C.POINTER(I64)], I32),
+        "hho_set_moments": ([P, D, D], I32),
+        "hho_batch_create": ([C.POINTER(P), I32, C.POINTER(P)], I32),
+        "hho_batch_destroy": ([P], None),
+        "hho_batch_problem": ([P, C.POINTER(P)], I32),
+        "hho_batch_sizes": ([P, C.POINTER(I64), C.POINTER(I64)], I32),
+        "hho_batch_solve": ([P, D, C.POINTER(I64), D, C.POINTER(I64), C.POINTER(C.c_int), D, C.POINTER(I64), D,
+                             C.POINTER(C.c_int)], I32),
+        "hho_learned_save": ([P, P, C.c_size_t, C.POINTER(C.c_size_t)], I32),
+        "hho_learned_load": ([P, P, C.c_size_t], I32),
         "hho_get_rhs": ([P, P], I32),
         "hho_recover_cells": ([P, P, P, P], I32),
         "hho_get_condensed_cell": ([P, I64, D, D, I64, C.POINTER(I64)], I32),
@@ -109,6 +127,11 @@ def load():
         "hho_learned_collect": ([P, P, I32, P, P, I64, C.POINTER(I64)], I32),
         "hho_learned_grad": ([P, P, P, I64, C.POINTER(C.c_float), D], I32),
         "hho_learned_grad_noalloc": ([P, P, P, I64, C.POINTER(C.c_float), D], I32),
+        "hho_set_tolerances": ([P, C.c_double, I32, C.c_double, I32], I32),
+        "hho_probe_arm": ([P, C.c_uint, I32], I32),
+        "hho_probe_read": ([P, I32, I32, C.POINTER(I64), D, C.POINTER(I64)], I32),
+        "hho_probe_clear": ([P], I32),
+        "hho_amg_level_info": ([P, I32, C.POINTER(I64)], I32),
         "hho_learned_train": ([P, P, P, I64, I32, I32, C.c_float, C.c_uint64, C.POINTER(C.c_float)], I32),
     }
     for name, (args, res) in sig.items():
@@ -237,7 +260,8 @@ class Problem:
         self.nfaces = mesh.n_faces
 
     def __del__(self):
-        if getattr(self, "h", None) and _lib is not None:
+        # a batch's combined problem belongs to the batch (hho_batch_destroy frees it)
+        if getattr(self, "h", None) and _lib is not None and not getattr(self, "_borrowed", False):
             _lib.hho_problem_destroy(self.h)
             self.h = None
 
@@ -293,6 +317,29 @@ class Problem:
         _check(load().hho_time_kernel(self.h, kind, level, reps, C.byref(ms)))
         return ms.value
 
+    def set_tolerances(self, rtol, max_it=1000, coarse_rtol=1e-3, coarse_max_it=300):
+        _check(load().hho_set_tolerances(self.h, rtol, max_it, coarse_rtol, coarse_max_it))
+
+    # ---- live kernel timing
+    def probe_arm(self, mask: int, stride: int = 1):
+        _check(load().hho_probe_arm(self.h, mask, stride))
+
+    def probe_clear(self):
+        _check(load().hho_probe_clear(self.h))
+
+    def probe_read(self, kind: int, level: int = -1):
+        """(timed launches, their total ms, all launches) of the armed class
+        `kind` on `level` (-1: all levels)."""
+        n, ms, alln = C.c_int64(), C.c_double(), C.c_int64()
+        _check(load().hho_probe_read(self.h, kind, level, C.byref(n), C.byref(ms), C.byref(alln)))
+        return n.value, ms.value, alln.value
+
+    def amg_level_info(self, level: int):
+        info = (C.c_int64 * 7)()
+        _check(load().hho_amg_level_info(self.h, level, info))
+        keys = ("n", "nc", "nnz_a", "nnz_p", "nnz_b", "explicit_from", "levels")
+        return dict(zip(keys, list(info)))
+
     def level_size(self, l: int) -> int:
         n = C.c_int64()
         _check(load().hho_level_size(self.h, l, C.byref(n)))
@@ -307,12 +354,59 @@ class Problem:
         it = C.c_int()
         hist = np.zeros(hist_cap)
         rel = C.c_double()
-        code = load().hho_solve(self.h, C.c_void_p(x.data_ptr()), C.byref(it), _dptr(hist), hist_cap,
+        code = load().hho_solve_device(self.h, C.c_void_p(x.data_ptr()), C.byref(it), _dptr(hist), hist_cap,
                                 C.byref(rel))
         if code not in (HHO_OK, -4):
             _check(code)
         n = min(it.value + 1, hist_cap)
         return x, it.value, hist[:n].copy(), rel.value, code == HHO_OK
+
+    def solution_sizes(self):
+        fn, pn = C.c_int64(), C.c_int64()
+        _check(load().hho_solution_sizes(self.h, C.byref(fn), C.byref(pn)))
+        return fn.value, pn.value
+
+    def solve_host(self, face_cap=None, p_cap=None, hist_cap: int = 1001):
+        """hho_solve into host arrays: (face modes, cell pressure modes, iterations,
+        residual history, final relative residual, converged)."""
+        fn, pn = self.solution_sizes()
+        face = np.zeros(fn if face_cap is None else face_cap)
+        pres = np.zeros(pn if p_cap is None else p_cap)
+        it = C.c_int()
+        hist = np.zeros(hist_cap)
+        rel = C.c_double()
+        code = load().hho_solve(self.h, _dptr(face), face.size, _dptr(pres), pres.size, C.byref(it), _dptr(hist),
+                                hist_cap, C.byref(rel))
+        if code not in (HHO_OK, -4):
+            _check(code)
+        n = min(it.value + 1, hist_cap)
+        return face[:fn], pres[:pn], it.value, hist[:n].copy(), rel.value, code == HHO_OK
+
+    def moments_size(self):
+        nu, npp = C.c_int64(), C.c_int64()
+        _check(load().hho_moments_size(self.h, C.byref(nu), C.byref(npp)))
+        return nu.value, npp.value
+
+    def set_moments(self, rhs_u, rhs_p):
+        nu, npp = self.moments_size()
+        ru = np.ascontiguousarray(rhs_u, dtype=np.float64)
+        rp = np.ascontiguousarray(rhs_p, dtype=np.float64)
+        if ru.size != nu or rp.size != npp:
+            raise ValueError(f"set_moments: need {nu} and {npp} values, got {ru.size} and {rp.size}")
+        _check(load().hho_set_moments(self.h, _dptr(ru), _dptr(rp)))
+
+    def learned_save(self) -> bytes:
+        need = C.c_size_t()
+        code = load().hho_learned_save(self.h, None, 0, C.byref(need))
+        if code != -7:
+            _check(code)
+        buf = C.create_string_buffer(need.value)
+        _check(load().hho_learned_save(self.h, C.cast(buf, C.c_void_p), need.value, C.byref(need)))
+        return buf.raw
+
+    def learned_load(self, data: bytes):
+        buf = C.create_string_buffer(data, len(data))
+        _check(load().hho_learned_load(self.h, C.cast(buf, C.c_void_p), len(data)))
 
     def rhs(self):
         b = self._vec(self.level_size(0))
@@ -447,3 +541,63 @@ class Problem:
         keys = ["condense_ms", "assemble_ms", "levels_ms", "smoother_setup_ms", "coarse_setup_ms", "solve_ms",
                 "vcycle_ms", "vcycles", "coarse_its"]
         return dict(zip(keys, t[:len(keys)]))
+
+
+class Batch:
+    """hho_batch_create over separately created problems (each after set_data);
+    ``problem`` is the combined problem to bind, set up and time."""
+
+    def __init__(self, problems):
+        lib = load()
+        arr = (C.c_void_p * len(problems))(*[q.h for q in problems])
+        h = C.c_void_p()
+        _check(lib.hho_batch_create(arr, len(problems), C.byref(h)))
+        self.h = h
+        self.n = len(problems)
+        ph = C.c_void_p()
+        _check(lib.hho_batch_problem(self.h, C.byref(ph)))
+        P = Problem.__new__(Problem)
+        P.h, P.mesh, P.k, P.cond, P.ws = ph, problems[0].mesh, problems[0].k, problems[0].cond, None
+        P.nlev, P.opts, P._owner = problems[0].nlev, problems[0].opts, self
+        P._borrowed = True
+        P.nfaces = None
+        self.problem = P
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.hho_batch_destroy(self.h)
+            self.h = None
+
+    def sizes(self):
+        fn = np.zeros(self.n, dtype=np.int64)
+        pn = np.zeros(self.n, dtype=np.int64)
+        _check(load().hho_batch_sizes(self.h, fn.ctypes.data_as(C.POINTER(C.c_int64)),
+                                      pn.ctypes.data_as(C.POINTER(C.c_int64))))
+        return fn, pn
+
+    def solve(self, hist_cap: int = 200):
+        """Per member: (face modes, cell pressure modes, iterations, history,
+        final relative residual, status)."""
+        fn, pn = self.sizes()
+        foff = np.concatenate([[0], np.cumsum(fn)]).astype(np.int64)
+        poff = np.concatenate([[0], np.cumsum(pn)]).astype(np.int64)
+        hoff = (np.arange(self.n + 1) * hist_cap).astype(np.int64)
+        face = np.zeros(int(foff[-1]))
+        pres = np.zeros(int(poff[-1]))
+        its = np.zeros(self.n, dtype=np.int32)
+        hist = np.full(int(hoff[-1]), np.nan)
+        rel = np.zeros(self.n)
+        st = np.zeros(self.n, dtype=np.int32)
+        i64 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int64))  # noqa: E731
+        i32 = lambda a: a.ctypes.data_as(C.POINTER(C.c_int))  # noqa: E731
+        code = load().hho_batch_solve(self.h, _dptr(face), i64(foff), _dptr(pres), i64(poff), i32(its), _dptr(hist),
+                                      i64(hoff), _dptr(rel), i32(st))
+        if code not in (HHO_OK, -4):
+            _check(code)
+        out = []
+        for i in range(self.n):
+            h = hist[hoff[i]:hoff[i + 1]]
+            out.append((face[foff[i]:foff[i + 1]], pres[poff[i]:poff[i + 1]], int(its[i]),
+                        h[~np.isnan(h)], float(rel[i]), int(st[i])))
+        return out
+

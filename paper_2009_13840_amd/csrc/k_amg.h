@@ -1,6 +1,8 @@
 // Device-side smoothed-aggregation hierarchy (pointers into the workspace).
 #pragma once
 
+#include "probe.h"
+
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -46,6 +48,7 @@ struct AmgDev {
   double *mexpl = nullptr;
   double *cr[kMaxAmgLevels] = {}, *cx[kMaxAmgLevels] = {}, *ct[kMaxAmgLevels] = {};
   double *ainv = nullptr, *dense_scratch = nullptr, *partial = nullptr;  // partial: 2 x 256 power-step sums
+  KernelProbe *probe = nullptr;  // live timing of armed kernel classes (may be null)
 };
 
 void amg_numeric_setup(const AmgDev &A, int cond, int d, int bs, int64_t nnzb0, const double *bsr0, int nu,

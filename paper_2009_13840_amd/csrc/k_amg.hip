@@ -665,10 +665,10 @@ static void rows(int G, int n, int d, const AmgDevLevel &L, const double *r, con
   const dim3 b(kBlock), g(grid_for((int64_t)n * G));
   const double *val = L.val, *dinv = L.dinv, *lam = L.lam;
   switch (G) {
-    case 64: hipLaunchKernelGGL((k_amg_rows<64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
-    case 16: hipLaunchKernelGGL((k_amg_rows<16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
-    case 4: hipLaunchKernelGGL((k_amg_rows<4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
-    default: hipLaunchKernelGGL((k_amg_rows<1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    case 64: HHO_LAUNCH((k_amg_rows<64>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    case 16: HHO_LAUNCH((k_amg_rows<16>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    case 4: HHO_LAUNCH((k_amg_rows<4>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
+    default: HHO_LAUNCH((k_amg_rows<1>), g, b, 0, s, n, d, L.rp, L.ci, val, dinv, lam, r, xin, xout, skip); break;
   }
 }
 
@@ -676,7 +676,7 @@ static void prolong_sweep(int G, const AmgDevLevel &L, int d, const double *xc, 
                           double *xout, hipStream_t s, const int *skip) {
   const dim3 b(kBlock), g(grid_for((int64_t)L.n * G));
 #define HHO_PS(GG)                                                                                             \
-  hipLaunchKernelGGL((k_amg_prolong_sweep<GG>), g, b, 0, s, L.n, d, L.rp, L.ci, (const double *)L.val,           \
+  HHO_LAUNCH((k_amg_prolong_sweep<GG>), g, b, 0, s, L.n, d, L.rp, L.ci, (const double *)L.val,           \
                      (const double *)L.dinv, (const double *)L.lam, L.prp, L.pci, (const double *)L.pval, L.brp, \
                      L.bci, (const double *)L.bval, xc, r, xin, xout, skip)
   switch (G) {
@@ -697,22 +697,24 @@ static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, doubl
                    const int *skip) {
   const AmgDevLevel &L = A.lev[l];
   if (l == A.expl) {  // this level and all coarser ones: the explicit operator
-    hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.mexpl, r, x, skip);
+    HHO_PROBED(A.probe, HHO_PROBE_AMG_DENSE, l, s,
+               HHO_LAUNCH(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.mexpl, r, x, skip));
     return;
   }
   if (l == A.nlev - 1) {
     if (A.ainv) {
-      hipLaunchKernelGGL(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.ainv, r, x, skip);
+      HHO_PROBED(A.probe, HHO_PROBE_AMG_DENSE, l, s,
+                 HHO_LAUNCH(k_amg_dense, dim3(L.n), dim3(kBlock), 0, s, L.n, d, (const double *)A.ainv, r, x, skip));
       return;
     }
     // kAmgCoarseSweeps damped-Jacobi sweeps from zero (the first launch takes two)
     const int GA = amg_group((double)L.nnz / L.n);
     constexpr int rest = kAmgCoarseSweeps - 2;
     double *cur = (rest % 2 == 1) ? L.tmp : x;
-    rows(GA, L.n, d, L, r, nullptr, cur, s, skip);
+    HHO_PROBED(A.probe, HHO_PROBE_AMG_SWEEP, l, s, rows(GA, L.n, d, L, r, nullptr, cur, s, skip));
     for (int it = 0; it < rest; ++it) {
       double *nxt = (cur == x) ? L.tmp : x;
-      rows(GA, L.n, d, L, r, cur, nxt, s, skip);
+      HHO_PROBED(A.probe, HHO_PROBE_AMG_SWEEP, l, s, rows(GA, L.n, d, L, r, cur, nxt, s, skip));
       cur = nxt;
     }
     return;
@@ -723,16 +725,17 @@ static void vcycle(const AmgDev &A, int l, int d, int nu, const double *r, doubl
   // the single sweep x = w D^{-1} r is formed where it is used
   const double *xpre = nullptr;
   if (nu == 2) {
-    rows(GA, L.n, d, L, r, nullptr, x, s, skip);
+    HHO_PROBED(A.probe, HHO_PROBE_AMG_SWEEP, l, s, rows(GA, L.n, d, L, r, nullptr, x, s, skip));
     xpre = x;
   }
-  hipLaunchKernelGGL(k_amg_restrict, dim3(grid_for((int64_t)N.n * kWave)), dim3(kBlock), 0, s, N.n, d, L.ptp, L.pti,
-                     (const double *)L.ptval, L.btp, L.bti, (const double *)L.btval, (const double *)L.dinv,
-                     (const double *)L.lam, r, xpre, N.r, skip);
+  HHO_PROBED(A.probe, HHO_PROBE_AMG_RESTRICT, l, s,
+             HHO_LAUNCH(k_amg_restrict, dim3(grid_for((int64_t)N.n * kWave)), dim3(kBlock), 0, s, N.n, d,
+                                L.ptp, L.pti, (const double *)L.ptval, L.btp, L.bti, (const double *)L.btval,
+                                (const double *)L.dinv, (const double *)L.lam, r, xpre, N.r, skip));
   vcycle(A, l + 1, d, nu, N.r, N.x, s, skip);
   // prolongation with the first post-sweep (nu = 2: into tmp, then the second sweep into x)
-  prolong_sweep(GS, L, d, N.x, r, xpre, nu == 2 ? L.tmp : x, s, skip);
-  if (nu == 2) rows(GA, L.n, d, L, r, L.tmp, x, s, skip);
+  HHO_PROBED(A.probe, HHO_PROBE_AMG_PROLONG, l, s, prolong_sweep(GS, L, d, N.x, r, xpre, nu == 2 ? L.tmp : x, s, skip));
+  if (nu == 2) HHO_PROBED(A.probe, HHO_PROBE_AMG_SWEEP, l, s, rows(GA, L.n, d, L, r, L.tmp, x, s, skip));
 }
 
 void bp_apply(const DTopo &tp, const AmgDev &A, int64_t nface, const double *cpl, const double *Sd, const double *v,

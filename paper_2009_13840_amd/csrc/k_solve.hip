@@ -8,6 +8,7 @@
 
 #include "dev_common.h"
 #include "device.h"
+#include "probe.h"
 #include "internal.h"
 
 namespace hho {
@@ -518,10 +519,10 @@ template <typename T>
 void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s) {
   if (launch_spmv_fixed<T>(tp, L, x, xs1, xsum, nullptr, y, s)) return;
   if (xs1)
-    hipLaunchKernelGGL((k_spmv<T, true, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
+    HHO_LAUNCH((k_spmv<T, true, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
                        (const T *)nullptr, y);
   else
-    hipLaunchKernelGGL((k_spmv<T, false, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
+    HHO_LAUNCH((k_spmv<T, false, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
                        (const T *)nullptr, y);
 }
 template <typename T>
@@ -543,7 +544,7 @@ void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const doubl
   if (sm < 1 || sm > kPatchMaxRows / kWave) fail(HHO_E_INVALID_ARG, "precond: patch too large");
 #define HHO_PC(SM, DC)                                                                                         \
   if (sm == SM && dc == DC) {                                                                                  \
-    hipLaunchKernelGGL((k_precond<T, SM, DC>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1); \
+    HHO_LAUNCH((k_precond<T, SM, DC>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1); \
     return;                                                                                                    \
   }
   HHO_PC(1, 1) HHO_PC(2, 1) HHO_PC(3, 1) HHO_PC(4, 1)

@@ -16,6 +16,7 @@
 // (Schwarz output), and xsum (if not null) receives that sum.
 #include "dev_common.h"
 #include "device.h"
+#include "probe.h"
 
 namespace hho {
 namespace {
@@ -285,24 +286,24 @@ bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T
       constexpr int G = 4;
       const int64_t total = ((int64_t)tp.nf + tp.nc) * G;
       const int grid = (int)((total + bs - 1) / bs);
-      hipLaunchKernelGGL((k_spmv_v0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+      HHO_LAUNCH((k_spmv_v0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
       return true;
     }
     const int64_t total = (int64_t)tp.nf * P + (int64_t)tp.nc * TT;
     const int grid = (int)((total + bs - 1) / bs);
-    hipLaunchKernelGGL((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+    HHO_LAUNCH((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   } else {
     const int bs = L.block > 0 ? L.block : kBlock;
     if (K == 0) {
       constexpr int G = 4;
       const int64_t total = ((int64_t)tp.nf + tp.nc) * G;
       const int grid = (int)((total + bs - 1) / bs);
-      hipLaunchKernelGGL((k_spmv_vp0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+      HHO_LAUNCH((k_spmv_vp0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
       return true;
     }
     const int64_t total = (int64_t)tp.nf * D * P + tp.nc;
     const int grid = (int)((total + bs - 1) / bs);
-    hipLaunchKernelGGL((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+    HHO_LAUNCH((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   }
   return true;
 }

@@ -13,6 +13,7 @@
 #include "device.h"
 #include "internal.h"
 #include "k_amg.h"
+#include "probe.h"
 
 namespace hho {
 
@@ -126,8 +127,10 @@ struct hho_problem {
   int32_t *dchunk_ptr = nullptr;
   GmresState *sst = nullptr;
   int *sdone = nullptr;
-  double *seg_partial = nullptr, *seg_ratio = nullptr;
+  double *seg_partial = nullptr, *seg_ratio = nullptr, *seg_hist = nullptr;
   std::vector<int> seg_its;
+  std::vector<std::vector<double>> seg_hist_h;  // per-member residual estimates of the last batched solve
+  bool opt_seg_hist = false;                     // record them (hho_batch_solve with histories)
   std::vector<double> seg_rel;
   // learned fine-level smoother
   MlpDims md{};
@@ -137,6 +140,8 @@ struct hho_problem {
         *mlp_Y = nullptr, *mlp_Z = nullptr, *mlp_dZ = nullptr, *mlp_Yb = nullptr, *mlp_dY = nullptr;
   int *mlp_rows = nullptr;
   double *mlp_loss = nullptr;
+  // live timing of armed kernel classes (hho_probe_arm / hho_probe_read)
+  KernelProbe probe;
 };
 
 namespace hho {
@@ -233,6 +238,7 @@ static void plan(hho_problem *P, Arena &A) {
     P->d_fdiag = A.take<int32_t>(nf);
     P->Sd = A.take<double>(nc);
     AmgDev &D = P->amgd;
+    D.probe = &P->probe;
     D.nlev = (int)P->amgh.levels.size();
     for (int l = 0; l < D.nlev; ++l) {
       const AmgHostLevel &H = P->amgh.levels[l];
@@ -325,6 +331,7 @@ static void plan(hho_problem *P, Arena &A) {
     P->sdone = A.take<int>(P->nseg);
     P->seg_partial = A.take<double>(G * (kMaxRestartH + 2));
     P->seg_ratio = A.take<double>(P->nseg);
+    P->seg_hist = A.take<double>(2 * P->nseg);
   }
   // learned fine-level smoother
   if (P->opt.learned) {
@@ -500,7 +507,7 @@ static void init_levels(hho_problem *P) {
     L.N = L.nface + P->mesh->nc * L.t;
   }
   const LevelInfo &LC = P->lev[P->nlev - 1];
-  P->border = P->mesh->has_neumann ? 0 : 1;
+  P->border = (P->mesh->has_neumann || P->opt.nullspace == HHO_NULLSPACE_NONE) ? 0 : 1;
   const int64_t nd = LC.N + P->border;
   P->coarse_dense = (P->opt.coarse_mode == HHO_COARSE_DENSE) ||
                     (P->opt.coarse_mode == HHO_COARSE_AUTO && nd <= 1024 && !(P->nseg > 1 && P->border));
@@ -703,11 +710,12 @@ static void smooth(hho_problem *P, int l) {
     launch_mlp_scatter<T>(md.nface, n, md.dp, P->mlp_Y, P->mlp_sc, V.z3, s);
     launch_spmv<T>(P->tp, D, V.z3, nullptr, nullptr, V.w3, s);
   }
-  launch_precond<T>(P->tp, D, V.r, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
-  launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z1, V.w1, s);
+  KernelProbe *pr = &P->probe;
+  HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.r, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
+  HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z1, V.w1, s));
   if (m == 2) {
-    launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s);
-    launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s);
+    HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
+    HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s));
   }
   if (learned) {
     launch_mr3<T>(n, m, V.z1, V.z2, V.z3, V.w1, V.w2, V.w3, V.w, V.r, P->partial, P->lev[l].y, s);
@@ -787,7 +795,8 @@ static void coarse_solve(hho_problem *P) {
       // Arnoldi kernels test the same flag)
       if (P->coarse_amg) {
         bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, P->cZ + (int64_t)j * n, P->amg_nu, s, &st->done);
-        launch_spmv<double>(P->tp, Dq, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s);
+        HHO_PROBED(&P->probe, HHO_PROBE_COARSE_OPERATOR, Lc, s,
+                   launch_spmv<double>(P->tp, Dq, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s));
       } else {
         launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
         launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
@@ -857,6 +866,30 @@ __global__ void k_seg_init(int np, GmresState *st, double rtol) {
   st[p].j = 0;
 }
 
+// relative residual estimate and Arnoldi step count of every segment
+__global__ void k_seg_hist(int np, const GmresState *st, double *out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  const double bn = st[p].bnorm;
+  out[2 * p] = bn > 0 ? st[p].res / bn : 0.0;
+  out[2 * p + 1] = (double)st[p].its;
+}
+
+// appends the estimate of every segment that took an Arnoldi step since the last call
+static void record_seg_hist(hho_problem *P, std::vector<int> &last_its) {
+  const int np = P->nseg;
+  hipLaunchKernelGGL(k_seg_hist, dim3((np + 63) / 64), dim3(64), 0, P->stream, np, (const GmresState *)P->sst,
+                     P->seg_hist);
+  std::vector<double> h(2 * np);
+  HIPCHK(hipMemcpyAsync(h.data(), P->seg_hist, h.size() * sizeof(double), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  for (int q = 0; q < np; ++q) {
+    const int its = (int)h[2 * q + 1];
+    if (its > last_its[q]) P->seg_hist_h[q].push_back(h[2 * q]);
+    last_its[q] = its;
+  }
+}
+
 static int read_seg_done(hho_problem *P) {
   std::vector<int> d(P->nseg);
   HIPCHK(hipMemcpyAsync(d.data(), P->sdone, P->nseg * sizeof(int), hipMemcpyDeviceToHost, P->stream));
@@ -890,6 +923,8 @@ static int fgmres_batched(hho_problem *P, double *x_out, int *iters, double *his
   double vc_ms = 0;
   std::vector<hipEvent_t> ev;  // V-cycle start/end pairs, read after the solve
   if (hist && hist_cap > 0) hist[0] = 1.0;
+  P->seg_hist_h.assign(np, std::vector<double>(1, 1.0));
+  std::vector<int> last_its(np, 0);
   while (ndone < np && its < P->opt.max_it) {
     for (int j = 0; j < R && its < P->opt.max_it; ++j) {
       double *vj = P->oV + (int64_t)j * n, *zj = P->oZ + (int64_t)j * n;
@@ -908,6 +943,7 @@ static int fgmres_batched(hho_problem *P, double *x_out, int *iters, double *his
                            P->sst, P->sdone, 1, s);
       launch_seg_scale(G, P->dchunks, P->dseg, P->ow, P->sst, P->oV + (int64_t)(j + 1) * n, s);
       ++its;
+      if (P->opt_seg_hist) record_seg_hist(P, last_its);
       ndone = read_seg_done(P);  // one small read per (batch-wide, heavy) iteration
       if (ndone == np) break;
     }
@@ -1003,7 +1039,7 @@ static int fgmres(hho_problem *P, double *x_out, int *iters, double *hist, int h
       apply_vcycle(P, vj, zj);
       HIPCHK(hipEventRecord(vb, s));
       ++nvc;
-      launch_spmv<double>(P->tp, D, zj, nullptr, nullptr, P->ow, s);
+      HHO_PROBED(&P->probe, HHO_PROBE_OUTER_OPERATOR, 0, s, launch_spmv<double>(P->tp, D, zj, nullptr, nullptr, P->ow, s));
       launch_arnoldi_dots<double>(n, j, P->oV, n, P->ow, P->partial, st, s);
       launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, 1, 1, s);
       launch_arnoldi_update<double>(n, j, P->oV, n, P->ow, P->partial, st, 2, 1, s);
@@ -1098,6 +1134,8 @@ void hho_options_default(hho_options *o) {
   o->learned = 0;
   o->coarse_amg_explicit = 2048;
   o->coarse_amg_psmooth = 1;
+  o->smoother = HHO_SMOOTHER_SCHWARZ;
+  o->nullspace = HHO_NULLSPACE_AUTO;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -1154,6 +1192,9 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
   if (P->opt.learned != 0 && P->opt.learned != 1) hho::fail(HHO_E_INVALID_ARG, "learned must be 0 or 1");
+  if (P->opt.smoother != HHO_SMOOTHER_SCHWARZ) hho::fail(HHO_E_INVALID_ARG, "smoother: only HHO_SMOOTHER_SCHWARZ");
+  if (P->opt.nullspace != HHO_NULLSPACE_AUTO && P->opt.nullspace != HHO_NULLSPACE_NONE)
+    hho::fail(HHO_E_INVALID_ARG, "nullspace must be HHO_NULLSPACE_AUTO or HHO_NULLSPACE_NONE");
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
   if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol > 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
   const int d = P->d;
@@ -1272,11 +1313,42 @@ static void need_setup(const hho_problem *p) {
   if (!p->setup_done) hho::fail(HHO_E_INVALID_ARG, "call hho_setup first");
 }
 
-int hho_solve(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel) {
+int hho_solve_device(hho_problem *p, double *x_dev, int *iters, double *hist, int hist_cap, double *final_rel) {
   ABI_BEGIN
   need_setup(p);
   if (p->nseg > 0) return hho::fgmres_batched(p, x_dev, iters, hist, hist_cap, final_rel);
   return hho::fgmres(p, x_dev, iters, hist, hist_cap, final_rel);
+  ABI_END
+}
+
+int hho_solution_sizes(const hho_problem *p, int64_t *face_n, int64_t *p_n) {
+  ABI_BEGIN
+  if (!p || !face_n || !p_n) hho::fail(HHO_E_INVALID_ARG, "solution_sizes: NULL");
+  const hho::LevelInfo &L0 = p->lev[0];
+  *face_n = L0.nface;
+  *p_n = L0.N - L0.nface;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_solve(hho_problem *p, double *face_out, int64_t face_cap, double *cell_p_out, int64_t p_cap, int *iters,
+              double *hist, int hist_cap, double *final_rel) {
+  ABI_BEGIN
+  need_setup(p);
+  const hho::LevelInfo &L0 = p->lev[0];
+  const int64_t nfv = L0.nface, npv = L0.N - L0.nface;
+  if (!face_out || !cell_p_out) hho::fail(HHO_E_INVALID_ARG, "solve: NULL output buffer");
+  if (face_cap < nfv || p_cap < npv) {
+    hho::set_error("solve: output buffers too small: face_cap >= " + std::to_string(nfv) + " and p_cap >= " +
+                   std::to_string(npv) + " are needed");
+    return HHO_E_CAPACITY;
+  }
+  const int rc = p->nseg > 0 ? hho::fgmres_batched(p, nullptr, iters, hist, hist_cap, final_rel)
+                             : hho::fgmres(p, nullptr, iters, hist, hist_cap, final_rel);
+  HIPCHK(hipMemcpyAsync(face_out, p->ox, nfv * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipMemcpyAsync(cell_p_out, p->ox + nfv, npv * sizeof(double), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return rc;
   ABI_END
 }
 
@@ -1598,6 +1670,87 @@ int hho_autotune(hho_problem *p, int reps, int *choices) {
   ABI_END
 }
 
+int hho_set_tolerances(hho_problem *p, double rtol, int max_it, double coarse_rtol, int coarse_max_it) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "set_tolerances: NULL problem");
+  if (!(rtol > 0 && rtol < 1) || max_it < 1 || !(coarse_rtol > 0 && coarse_rtol < 1) || coarse_max_it < 1)
+    hho::fail(HHO_E_INVALID_ARG, "set_tolerances: need 0 < rtol, coarse_rtol < 1 and positive iteration limits");
+  p->opt.rtol = rtol;
+  p->opt.max_it = max_it;
+  p->opt.coarse_rtol = coarse_rtol;
+  p->opt.coarse_max_it = coarse_max_it;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_probe_arm(hho_problem *p, unsigned mask, int stride) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "probe_arm: NULL problem");
+  if (mask & ~(unsigned)HHO_PROBE_ALL) hho::fail(HHO_E_INVALID_ARG, "probe_arm: unknown class bit");
+  if (stride < 1) hho::fail(HHO_E_INVALID_ARG, "probe_arm: stride must be >= 1");
+  if (p->bound) HIPCHK(hipStreamSynchronize(p->stream));
+  p->probe.mask = mask;
+  p->probe.stride = stride;
+  p->probe.reset();
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_probe_read(hho_problem *p, int kind, int level, int64_t *timed, double *total_ms, int64_t *launches) {
+  ABI_BEGIN
+  if (!p || !timed || !total_ms) hho::fail(HHO_E_INVALID_ARG, "probe_read: NULL");
+  const int ci = hho::KernelProbe::class_index(kind);
+  if (ci >= hho::kProbeClasses || (kind & (kind - 1))) hho::fail(HHO_E_INVALID_ARG, "probe_read: kind must be one class bit");
+  if (level >= hho::kProbeLevels) hho::fail(HHO_E_INVALID_ARG, "probe_read: level out of range");
+  if (p->bound) HIPCHK(hipStreamSynchronize(p->stream));
+  if (p->probe.failed) hho::fail(HHO_E_DEVICE, "probe_read: an event could not be created or recorded");
+  int64_t cnt = 0;
+  double ms = 0;
+  for (const hho::KernelProbe::Rec &r : p->probe.recs) {
+    if (r.kind != kind || (level >= 0 && r.level != level)) continue;
+    float t;
+    HIPCHK(hipEventElapsedTime(&t, r.a, r.b));
+    ms += t;
+    ++cnt;
+  }
+  *timed = cnt;
+  *total_ms = ms;
+  if (launches) {
+    int64_t all = 0;
+    for (int l = 0; l < hho::kProbeLevels; ++l)
+      if (level < 0 || l == level) all += p->probe.seen[ci][l];
+    *launches = all;
+  }
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_probe_clear(hho_problem *p) {
+  ABI_BEGIN
+  if (!p) hho::fail(HHO_E_INVALID_ARG, "probe_clear: NULL");
+  if (p->bound) HIPCHK(hipStreamSynchronize(p->stream));
+  p->probe.reset();
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_amg_level_info(const hho_problem *p, int level, int64_t *info) {
+  ABI_BEGIN
+  if (!p || !info) hho::fail(HHO_E_INVALID_ARG, "amg_level_info: NULL");
+  if (!p->coarse_amg || level < 0 || level >= (int)p->amgh.levels.size())
+    hho::fail(HHO_E_INVALID_ARG, "amg_level_info: no such AMG level");
+  const hho::AmgHostLevel &H = p->amgh.levels[level];
+  info[0] = H.n;
+  info[1] = H.nc;
+  info[2] = (int64_t)H.ci.size();
+  info[3] = (int64_t)H.pci.size();
+  info[4] = (int64_t)H.bci.size();
+  info[5] = (int64_t)p->amgd.expl;
+  info[6] = (int64_t)p->amgh.levels.size();
+  return HHO_OK;
+  ABI_END
+}
+
 int hho_get_timings(const hho_problem *p, double *t, int n) {
   ABI_BEGIN
   if (!p || !t) hho::fail(HHO_E_INVALID_ARG, "get_timings: NULL");
@@ -1864,11 +2017,10 @@ int hho_learned_train(hho_problem *p, const float *X, const float *Tg, int64_t n
 }
 
 // ------------------------------------------------------------ batches of problems
-int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int64_t *face_offsets,
-                          int64_t *cell_offsets) {
-  ABI_BEGIN
-  if (!descs || n < 1 || !out) hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: bad argument");
-  *out = nullptr;
+// disjoint union of n mesh descriptors (member i's faces and cells follow those
+// of members 0..i-1); face_offsets / cell_offsets (may be null) get n+1 entries
+static void build_union_mesh(const hho_mesh_desc *descs, int n, hho_mesh *m, int64_t *face_offsets,
+                             int64_t *cell_offsets) {
   const int dim = descs[0].dim;
   std::vector<double> verts;
   std::vector<int64_t> fptr(1, 0), fvtx, cptr(1, 0), cface;
@@ -1876,10 +2028,10 @@ int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int
   int64_t nv = 0, nf = 0, nc = 0;
   for (int i = 0; i < n; ++i) {
     const hho_mesh_desc &d = descs[i];
-    if (d.dim != dim) hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: meshes of different dimensions");
+    if (d.dim != dim) hho::fail(HHO_E_INVALID_ARG, "mesh union: meshes of different dimensions");
     if (!d.verts || !d.face_ptr || !d.face_vtx || !d.cell_ptr || !d.cell_face || !d.face_bc || d.n_faces <= 0 ||
         d.n_cells <= 0 || d.n_verts <= 0)
-      hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: empty or NULL member mesh");
+      hho::fail(HHO_E_INVALID_ARG, "mesh union: empty or NULL member mesh");
     if (face_offsets) face_offsets[i] = nf;
     if (cell_offsets) cell_offsets[i] = nc;
     verts.insert(verts.end(), d.verts, d.verts + d.n_verts * dim);
@@ -1899,8 +2051,16 @@ int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int
   if (face_offsets) face_offsets[n] = nf;
   if (cell_offsets) cell_offsets[n] = nc;
   hho_mesh_desc u{dim, nv, verts.data(), nf, fptr.data(), fvtx.data(), nc, cptr.data(), cface.data(), fbc.data()};
+  hho::build_mesh(&u, m);
+}
+
+int hho_mesh_create_union(const hho_mesh_desc *descs, int n, hho_mesh **out, int64_t *face_offsets,
+                          int64_t *cell_offsets) {
+  ABI_BEGIN
+  if (!descs || n < 1 || !out) hho::fail(HHO_E_INVALID_ARG, "mesh_create_union: bad argument");
+  *out = nullptr;
   auto m = std::make_unique<hho_mesh>();
-  hho::build_mesh(&u, m.get());
+  build_union_mesh(descs, n, m.get(), face_offsets, cell_offsets);
   *out = m.release();
   return HHO_OK;
   ABI_END
@@ -1983,3 +2143,237 @@ int hho_batch_results(const hho_problem *p, int *iters, double *rel, int n) {
   return HHO_OK;
   ABI_END
 }
+
+// ------------------------------------------------------------ batches built from separate problems
+struct hho_batch {
+  std::unique_ptr<hho_mesh> mesh;  // disjoint union of the members' meshes
+  hho_problem *P = nullptr;        // the combined problem (owned)
+  int n = 0;
+  std::vector<int64_t> foff, coff;  // first face / cell of every member in the union, n+1 entries
+  ~hho_batch() { hho_problem_destroy(P); }
+};
+
+static bool same_solver_options(const hho_options &a, const hho_options &b) {
+  return a.rtol == b.rtol && a.max_it == b.max_it && a.restart == b.restart && a.smooth_its == b.smooth_its &&
+         a.precision == b.precision && a.coarse_mode == b.coarse_mode && a.coarse_rtol == b.coarse_rtol &&
+         a.coarse_restart == b.coarse_restart && a.coarse_max_it == b.coarse_max_it && a.quad_extra == b.quad_extra &&
+         a.coarse_amg_sweeps == b.coarse_amg_sweeps && a.learned == b.learned &&
+         a.coarse_amg_explicit == b.coarse_amg_explicit && a.coarse_amg_psmooth == b.coarse_amg_psmooth &&
+         a.smoother == b.smoother && a.nullspace == b.nullspace;
+}
+
+int hho_batch_create(hho_problem *const *ps, int n, hho_batch **out) {
+  ABI_BEGIN
+  if (!ps || n < 1 || !out) hho::fail(HHO_E_INVALID_ARG, "batch_create: bad argument");
+  *out = nullptr;
+  const hho_problem *p0 = ps[0];
+  for (int i = 0; i < n; ++i) {
+    const hho_problem *q = ps[i];
+    if (!q) hho::fail(HHO_E_INVALID_ARG, "batch_create: NULL member");
+    if (!q->have_data) hho::fail(HHO_E_INVALID_ARG, "batch_create: every member needs hho_problem_set_data first");
+    if (q->nseg > 0) hho::fail(HHO_E_INVALID_ARG, "batch_create: a member is itself a batch");
+    if (q->d != p0->d || q->k != p0->k || q->cond != p0->cond || q->deg != p0->deg)
+      hho::fail(HHO_E_INVALID_ARG, "batch_create: members differ in dimension, degree schedule or condensation");
+    if (!same_solver_options(q->opt, p0->opt))
+      hho::fail(HHO_E_INVALID_ARG, "batch_create: members differ in solver options (only eta may differ)");
+  }
+  auto B = std::make_unique<hho_batch>();
+  B->n = n;
+  B->foff.resize(n + 1);
+  B->coff.resize(n + 1);
+  std::vector<hho_mesh_desc> descs(n);
+  for (int i = 0; i < n; ++i) {
+    const hho_mesh *m = ps[i]->mesh;
+    descs[i] = hho_mesh_desc{m->dim, m->nv, m->verts.data(), m->nf, m->fptr.data(), m->fvtx.data(),
+                             m->nc, m->cptr.data(), m->cface.data(), m->fbc.data()};
+  }
+  B->mesh = std::make_unique<hho_mesh>();
+  build_union_mesh(descs.data(), n, B->mesh.get(), B->foff.data(), B->coff.data());
+  hho_options opt = p0->opt;
+  opt.eta = 1.0;  // the members' local operators are copied below, each with its own penalty
+  hho_problem *P = nullptr;
+  int rc = hho_problem_create(B->mesh.get(), p0->k, p0->cond, p0->nlev, p0->deg.data(), &opt, &P);
+  if (rc != HHO_OK) return rc;
+  B->P = P;
+  rc = hho_problem_set_segments(P, n, B->foff.data(), B->coff.data());
+  if (rc != HHO_OK) return rc;
+  // local operators: the members' records, concatenated in union cell order
+  hho::LocalData &L = P->loc;
+  L = hho::LocalData{};
+  const hho::LocalData &L0 = p0->loc;
+  L.k = L0.k;
+  L.d = L0.d;
+  L.nT = L0.nT;
+  L.nF = L0.nF;
+  L.N1 = L0.N1;
+  L.off.assign(1, 0);
+  for (int i = 0; i < n; ++i) {
+    const hho::LocalData &Li = ps[i]->loc;
+    const int64_t base = (int64_t)L.rec.size();
+    L.rec.insert(L.rec.end(), Li.rec.begin(), Li.rec.end());
+    L.nloc.insert(L.nloc.end(), Li.nloc.begin(), Li.nloc.end());
+    for (size_t c = 1; c < Li.off.size(); ++c) L.off.push_back(base + Li.off[c]);
+  }
+  P->opt.eta = p0->opt.eta;
+  P->cell_eta.clear();
+  hho::amg_levels(P);
+  P->have_data = true;
+  P->setup_done = false;
+  hho::Arena A;
+  hho::plan(P, A);
+  P->need = A.off + 256;
+  *out = B.release();
+  return HHO_OK;
+  ABI_END
+}
+
+void hho_batch_destroy(hho_batch *b) { delete b; }
+
+int hho_batch_problem(hho_batch *b, hho_problem **p) {
+  ABI_BEGIN
+  if (!b || !p) hho::fail(HHO_E_INVALID_ARG, "batch_problem: NULL");
+  *p = b->P;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_batch_sizes(const hho_batch *b, int64_t *face_n, int64_t *p_n) {
+  ABI_BEGIN
+  if (!b || !face_n || !p_n) hho::fail(HHO_E_INVALID_ARG, "batch_sizes: NULL");
+  const hho::LevelInfo &L0 = b->P->lev[0];
+  const int64_t fdof = L0.nface / b->mesh->nf;  // d * n_F per face
+  for (int i = 0; i < b->n; ++i) {
+    face_n[i] = (b->foff[i + 1] - b->foff[i]) * fdof;
+    p_n[i] = (b->coff[i + 1] - b->coff[i]) * L0.t;
+  }
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_batch_solve(hho_batch *b, double *face_out, const int64_t *face_off, double *p_out, const int64_t *p_off,
+                    int *iters, double *hist, const int64_t *hist_off, double *final_rel, int *status) {
+  ABI_BEGIN
+  if (!b || !face_out || !face_off || !p_out || !p_off) hho::fail(HHO_E_INVALID_ARG, "batch_solve: NULL argument");
+  hho_problem *P = b->P;
+  need_setup(P);
+  const int n = b->n;
+  const hho::LevelInfo &L0 = P->lev[0];
+  const int64_t fdof = L0.nface / b->mesh->nf;
+  for (int i = 0; i < n; ++i) {
+    const int64_t fn = (b->foff[i + 1] - b->foff[i]) * fdof, pn = (b->coff[i + 1] - b->coff[i]) * L0.t;
+    if (face_off[i + 1] - face_off[i] < fn || p_off[i + 1] - p_off[i] < pn) {
+      hho::set_error("batch_solve: output range of member " + std::to_string(i) + " too small: " +
+                     std::to_string(fn) + " face and " + std::to_string(pn) + " pressure values are needed");
+      return HHO_E_CAPACITY;
+    }
+    if (hist_off && hist_off[i + 1] < hist_off[i]) hho::fail(HHO_E_INVALID_ARG, "batch_solve: decreasing hist_off");
+  }
+  P->opt_seg_hist = hist && hist_off;
+  int its = 0;
+  double rel = 0;
+  const int rc = hho::fgmres_batched(P, nullptr, &its, nullptr, 0, &rel);
+  P->opt_seg_hist = false;
+  for (int i = 0; i < n; ++i) {
+    const int64_t fn = (b->foff[i + 1] - b->foff[i]) * fdof, pn = (b->coff[i + 1] - b->coff[i]) * L0.t;
+    HIPCHK(hipMemcpyAsync(face_out + face_off[i], P->ox + b->foff[i] * fdof, fn * sizeof(double),
+                          hipMemcpyDeviceToHost, P->stream));
+    HIPCHK(hipMemcpyAsync(p_out + p_off[i], P->ox + L0.nface + b->coff[i] * L0.t, pn * sizeof(double),
+                          hipMemcpyDeviceToHost, P->stream));
+  }
+  HIPCHK(hipStreamSynchronize(P->stream));
+  for (int i = 0; i < n; ++i) {
+    if (iters) iters[i] = P->seg_its[i];
+    if (final_rel) final_rel[i] = P->seg_rel[i];
+    if (status) status[i] = P->seg_rel[i] <= P->opt.rtol ? HHO_OK : HHO_E_NOT_CONVERGED;
+    if (hist && hist_off) {
+      const std::vector<double> &h = P->seg_hist_h[i];
+      const int64_t cap = hist_off[i + 1] - hist_off[i];
+      for (int64_t e = 0; e < cap && e < (int64_t)h.size(); ++e) hist[hist_off[i] + e] = h[e];
+    }
+  }
+  return rc;
+  ABI_END
+}
+
+// ------------------------------------------------------------ learned parameters as bytes
+namespace {
+constexpr char kMlpMagic[8] = {'H', 'H', 'O', 'M', 'L', 'P', '0', '1'};
+struct MlpFileHeader {
+  char magic[8];
+  int32_t n_in, n_out, hidden, reserved;
+  int64_t n_params;
+};
+}  // namespace
+
+int hho_learned_save(const hho_problem *p, void *buf, size_t cap, size_t *need) {
+  ABI_BEGIN
+  need_learned(p);
+  if (!p->learned_ready) hho::fail(HHO_E_INVALID_ARG, "learned_save: no parameters set");
+  const int64_t np = hho::mlp_param_count(p->md);
+  const size_t bytes = sizeof(MlpFileHeader) + (size_t)np * sizeof(float);
+  if (need) *need = bytes;
+  if (!buf || cap < bytes) {
+    hho::set_error("learned_save: the buffer needs " + std::to_string(bytes) + " bytes");
+    return HHO_E_CAPACITY;
+  }
+  MlpFileHeader h{};
+  std::memcpy(h.magic, kMlpMagic, 8);
+  h.n_in = p->md.n_in;
+  h.n_out = p->md.n_out;
+  h.hidden = hho::kMlpHidden;
+  h.n_params = np;
+  std::memcpy(buf, &h, sizeof(h));
+  HIPCHK(hipMemcpyAsync((char *)buf + sizeof(h), p->mlp_prm, np * sizeof(float), hipMemcpyDeviceToHost, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_learned_load(hho_problem *p, const void *buf, size_t n) {
+  ABI_BEGIN
+  need_learned(p);
+  if (!buf || n < sizeof(MlpFileHeader)) hho::fail(HHO_E_INVALID_ARG, "learned_load: buffer too short");
+  MlpFileHeader h;
+  std::memcpy(&h, buf, sizeof(h));
+  const int64_t np = hho::mlp_param_count(p->md);
+  if (std::memcmp(h.magic, kMlpMagic, 8) != 0) hho::fail(HHO_E_INVALID_ARG, "learned_load: not a saved network");
+  if (h.n_in != p->md.n_in || h.n_out != p->md.n_out || h.hidden != hho::kMlpHidden || h.n_params != np)
+    hho::fail(HHO_E_INVALID_ARG, "learned_load: the network's sizes differ from this problem's");
+  if (n < sizeof(h) + (size_t)np * sizeof(float)) hho::fail(HHO_E_INVALID_ARG, "learned_load: buffer too short");
+  return hho_learned_set_params(p, (const float *)((const char *)buf + sizeof(h)), np);
+  ABI_END
+}
+
+// ------------------------------------------------------------ right-hand sides given as moments
+int hho_moments_size(const hho_problem *p, int64_t *n_u, int64_t *n_p) {
+  ABI_BEGIN
+  if (!p || !n_u || !n_p) hho::fail(HHO_E_INVALID_ARG, "moments_size: NULL");
+  if (!p->have_data) hho::fail(HHO_E_INVALID_ARG, "moments_size: call hho_problem_set_data first");
+  int64_t nu = 0;
+  for (int32_t v : p->loc.nloc) nu += (int64_t)p->d * v;
+  *n_u = nu;
+  *n_p = (int64_t)p->mesh->nc * p->loc.nT;
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_set_moments(hho_problem *p, const double *rhs_u, const double *rhs_p) {
+  ABI_BEGIN
+  if (!p || !rhs_u || !rhs_p) hho::fail(HHO_E_INVALID_ARG, "set_moments: NULL");
+  if (!p->have_data) hho::fail(HHO_E_INVALID_ARG, "set_moments: call hho_problem_set_data first");
+  hho::LocalData &L = p->loc;
+  const int d = p->d, nT = L.nT;
+  int64_t ou = 0;
+  for (int64_t c = 0; c < p->mesh->nc; ++c) {
+    const int64_t nl = L.nloc[c];
+    double *r = L.rec.data() + L.off[c] + nl * nl + (int64_t)d * nT * nl;  // [rhs_u (d*nloc) | rhs_p (nT)]
+    std::memcpy(r, rhs_u + ou, sizeof(double) * d * nl);
+    std::memcpy(r + d * nl, rhs_p + c * nT, sizeof(double) * nT);
+    ou += d * nl;
+  }
+  p->uploaded = false;  // the next hho_setup copies the records again
+  p->setup_done = false;
+  return HHO_OK;
+  ABI_END
+}
+

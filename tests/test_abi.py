@@ -166,3 +166,85 @@ def test_batch_members_take_their_own_penalty():
     for c in range(quads.n_cells):
         u, a = P.local_cell(c), A.local_cell(c)
         assert np.abs(u["a"] - a["a"]).max() <= 1e-12 * np.abs(a["a"]).max()
+
+
+def test_option_fields_smoother_and_nullspace():
+    H, _ = _lib()
+    M = H.Mesh(cartesian_quads(2))
+    for kw in (dict(smoother=1), dict(nullspace=2), dict(nullspace=-1)):
+        with pytest.raises(H.HHOError) as e:
+            H.Problem(M, 1, "v", **kw)
+        assert e.value.code == -1, kw
+    H.Problem(M, 1, "v", smoother=0, nullspace=1)
+
+
+def test_moments_replace_the_local_right_hand_sides():
+    """hho_set_moments writes the data part of every cell record (layout of the
+    header: per cell d*nloc_T momentum then n_T mass values); the operators stay."""
+    H, _ = _lib()
+    mesh = voronoi_lloyd(12, 3)
+    k = 2
+    P = H.Problem(H.Mesh(mesh), k, "v")
+    P.set_data(None, None, None)
+    before = [P.local_cell(c) for c in range(mesh.n_cells)]
+    nu, npp = P.moments_size()
+    nT = (k + 1) * (k + 2) // 2
+    nloc = [nT + (mesh.cell_ptr[c + 1] - mesh.cell_ptr[c]) * (k + 1) for c in range(mesh.n_cells)]
+    assert nu == 2 * sum(nloc) and npp == mesh.n_cells * nT
+    rng = np.random.default_rng(3)
+    ru, rp = rng.standard_normal(nu), rng.standard_normal(npp)
+    P.set_moments(ru, rp)
+    off = 0
+    for c in range(mesh.n_cells):
+        G = P.local_cell(c)
+        assert np.array_equal(G["rhs_u"].ravel(), ru[off:off + 2 * nloc[c]])
+        assert np.array_equal(G["rhs_p"], rp[c * nT:(c + 1) * nT])
+        assert np.array_equal(G["a"], before[c]["a"]) and np.array_equal(G["B"], before[c]["B"])
+        off += 2 * nloc[c]
+    with pytest.raises(ValueError):
+        P.set_moments(ru[:-1], rp)
+    Q = H.Problem(H.Mesh(mesh), k, "v")
+    with pytest.raises(H.HHOError):                 # operators not built yet
+        Q.moments_size()
+
+
+def test_batch_from_separate_problems_validation_and_sizes():
+    """hho_batch_create takes problems with equal degree schedule, variant and
+    options (the penalty may differ); the output sizes are the members' own."""
+    H, _ = _lib()
+    meshes = [cartesian_quads(3), voronoi_lloyd(20, 4), cartesian_quads(2)]
+    probs = []
+    for i, m in enumerate(meshes):
+        Q = H.Problem(H.Mesh(m), 2, "v", coarse_mode="amg")
+        Q.set_data(*problem_data(polynomial_stokes(2, 2, i), None, 2))
+        probs.append(Q)
+    B = H.Batch(probs)
+    fn, pn = B.sizes()
+    assert list(fn) == [m.n_faces * 2 * 3 for m in meshes]
+    assert list(pn) == [m.n_cells * 6 for m in meshes]
+    assert B.problem.workspace_size() > 0
+    # the combined problem's local operators are the members' (each with its own penalty)
+    c1 = meshes[0].n_cells + 5
+    u, a = B.problem.local_cell(c1), probs[1].local_cell(5)
+    assert np.array_equal(u["a"], a["a"]) and np.array_equal(u["rhs_u"], a["rhs_u"])
+    other = H.Problem(H.Mesh(cartesian_quads(2)), 1, "v", coarse_mode="amg")
+    other.set_data(*problem_data(polynomial_stokes(2, 1, 0), None, 2))
+    with pytest.raises(H.HHOError) as e:            # different degree
+        H.Batch([probs[0], other])
+    assert e.value.code == -1
+    nodata = H.Problem(H.Mesh(cartesian_quads(2)), 2, "v", coarse_mode="amg")
+    with pytest.raises(H.HHOError):                 # member without local operators
+        H.Batch([probs[0], nodata])
+    diffopt = H.Problem(H.Mesh(cartesian_quads(2)), 2, "v", coarse_mode="amg", rtol=1e-6)
+    diffopt.set_data(*problem_data(polynomial_stokes(2, 2, 0), None, 2))
+    with pytest.raises(H.HHOError):                 # different solver options
+        H.Batch([probs[0], diffopt])
+
+
+def test_solution_sizes():
+    H, _ = _lib()
+    mesh = cartesian_quads(3)
+    P = H.Problem(H.Mesh(mesh), 2, "vp")
+    assert P.solution_sizes() == (mesh.n_faces * 2 * 3, mesh.n_cells)
+    Q = H.Problem(H.Mesh(mesh), 2, "v")
+    assert Q.solution_sizes() == (mesh.n_faces * 2 * 3, mesh.n_cells * 6)
