@@ -73,7 +73,10 @@ extern "C" {
 
 /* precision of the V-cycle (the outer FGMRES is always FP64) */
 #define HHO_PREC_FP64   0
-#define HHO_PREC_FP32   1
+#define HHO_PREC_FP32   1   /* levels above the coarsest: FP32 values, vectors and arithmetic */
+#define HHO_PREC_BF16   2   /* levels above the coarsest: operator values stored as bfloat16
+                               (rounded to nearest even from FP32), smoother factors FP32,
+                               FP32 vectors and arithmetic */
 
 /* coarsest-level solver */
 #define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns, else AMG when k_L = 0, else GMRES */
@@ -123,7 +126,7 @@ typedef struct {
   int32_t smooth_its;  /* GMRES iterations per pre/post smoothing (2, at most 2) */
   int32_t precision;   /* HHO_PREC_* (FP64) */
   int32_t coarse_mode; /* HHO_COARSE_* (AUTO) */
-  double coarse_rtol;  /* coarse GMRES relative residual (1e-3) */
+  double coarse_rtol;  /* coarse GMRES relative residual (0: 1e-3 in 3D, 1e-2 in 2D) */
   int32_t coarse_restart; /* coarse GMRES restart (30, at most 64) */
   int32_t coarse_max_it;  /* coarse GMRES iterations (300) */
   int32_t quad_extra;  /* quadrature exact to degree 2k+2+quad_extra (6) */
@@ -262,6 +265,13 @@ int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B,
 
 /* y = S_l x on level l in FP64 (device vectors in the global layout). */
 int hho_level_apply(hho_problem *p, int level, const double *x_dev, double *y_dev);
+
+/* The level-l operator (which = 0: y = S_l x) or smoother preconditioner
+ * (which = 1: y = M_l x) in the V-cycle's own precision: on levels above the
+ * coarsest of an HHO_PREC_FP32/BF16 problem, x is rounded to FP32, the stored
+ * FP32/bfloat16 values are applied in FP32 arithmetic and y is widened back to
+ * FP64; otherwise as hho_level_apply / hho_precond_apply (device vectors). */
+int hho_vcycle_level_apply(hho_problem *p, int level, int which, const double *x_dev, double *y_dev);
 
 /* z = M_l r: the level-l smoother preconditioner (cell-patch Schwarz), FP64. */
 int hho_precond_apply(hho_problem *p, int level, const double *r_dev, double *z_dev);

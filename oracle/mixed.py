@@ -19,12 +19,33 @@ This module replays that with NumPy float32 arithmetic:
   float32 before it is added.
 
 The V-cycle's steps are those of ``oracle.multilevel.Hierarchy.vcycle``.
+
+``round_bf16`` gives the bfloat16 storage of the 16-bit mode: a bfloat16 number
+is an IEEE binary32 number whose 16 low significand bits are zero, and a float32
+value is stored as the nearest such number, ties to the one whose lowest kept
+bit is zero (round to nearest even); values keep float32 arithmetic after that.
 """
 from __future__ import annotations
 
 import numpy as np
 
 F32 = np.float32
+
+
+def round_bf16(a):
+    """Nearest bfloat16 numbers (ties to even) of the float32 values of ``a``,
+    as float32.  Written from the definition: the two bfloat16 neighbours of x
+    are x with its 16 low bits cleared (towards zero) and the next bfloat16 away
+    from zero; the nearer wins, an exact tie goes to the one with an even kept
+    significand.  NaN and infinities are left as they are."""
+    x = np.asarray(a, dtype=F32)
+    bits = x.view(np.uint32)
+    lo = bits & np.uint32(0xFFFF0000)                       # truncated towards zero
+    hi = (lo.astype(np.uint64) + 0x10000).astype(np.uint32)  # next one away from zero
+    rest = bits & np.uint32(0xFFFF)                          # distance to lo in units of 2^-16 ulp
+    up = (rest > 0x8000) | ((rest == 0x8000) & ((lo >> 16) & 1 == 1))
+    out = np.where(up, hi, lo).astype(np.uint32).view(F32)
+    return np.where(np.isfinite(x), out, x).astype(F32)
 
 
 class Schwarz32:

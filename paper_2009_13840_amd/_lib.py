@@ -21,7 +21,7 @@ ERRORS = {-1: "HHO_E_INVALID_ARG", -2: "HHO_E_MESH", -3: "HHO_E_LOCAL_SINGULAR",
 COND = {"v": 1, "vp": 2}
 PROBE = {"operator": 1, "smoother": 2, "coarse_operator": 4, "outer_operator": 8, "amg_restrict": 16,
          "amg_sweep": 32, "amg_prolong": 64, "amg_dense": 128}
-PREC = {"fp64": 0, "fp32": 1}
+PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
@@ -29,7 +29,7 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_solve_device", "hho_solution_sizes",
            "hho_moments_size", "hho_set_moments", "hho_batch_create", "hho_batch_destroy", "hho_batch_problem",
            "hho_batch_sizes", "hho_batch_solve", "hho_learned_save", "hho_learned_load", "hho_get_rhs", "hho_get_condensed_cell",
-           "hho_get_local_cell", "hho_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
+           "hho_get_local_cell", "hho_level_apply", "hho_vcycle_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
            "hho_learned_collect", "hho_learned_grad", "hho_learned_grad_noalloc", "hho_learned_train", "hho_mesh_create_union",
@@ -109,6 +109,7 @@ def load():
         "hho_get_local_cell": ([P, I64, D, D, D, D, I64, C.POINTER(I64)], I32),
         "hho_level_apply": ([P, I32, P, P], I32),
         "hho_precond_apply": ([P, I32, P, P], I32),
+        "hho_vcycle_level_apply": ([P, I32, I32, P, P], I32),
         "hho_vcycle_apply": ([P, P, P], I32),
         "hho_get_timings": ([P, D, I32], I32),
         "hho_upload": ([P], I32),
@@ -440,6 +441,12 @@ class Problem:
     def level_apply(self, l, x):
         y = self._vec(self.level_size(l))
         _check(load().hho_level_apply(self.h, l, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
+        return y
+
+    def vcycle_level_apply(self, l, x, which: int = 0):
+        """y = S_l x (which 0) or M_l x (which 1) in the V-cycle's precision."""
+        y = self._vec(self.level_size(l))
+        _check(load().hho_vcycle_level_apply(self.h, l, which, C.c_void_p(x.data_ptr()), C.c_void_p(y.data_ptr())))
         return y
 
     def precond_apply(self, l, r):

@@ -7,6 +7,32 @@
 
 namespace hho {
 
+// bfloat16 storage of operator and smoother values (the 16 high bits of an IEEE
+// binary32): read as float, arithmetic in float.  Rounding from float is to the
+// nearest, ties to even (add 0x7fff plus the lowest kept bit, drop 16 bits; NaN
+// stays a quiet NaN).
+struct bf16 {
+  uint16_t bits;
+  __host__ __device__ operator float() const { return __builtin_bit_cast(float, (uint32_t)bits << 16); }
+};
+__host__ __device__ inline bf16 to_bf16(float f) {
+  uint32_t u = __builtin_bit_cast(uint32_t, f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)((u >> 16) | 0x40u)};  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return bf16{(uint16_t)(u >> 16)};
+}
+// value conversion to a storage type (double -> float -> bf16 for bf16)
+template <typename To>
+struct StoreAs {
+  template <typename From>
+  __host__ __device__ static To from(From v) { return (To)v; }
+};
+template <>
+struct StoreAs<bf16> {
+  template <typename From>
+  __host__ __device__ static bf16 from(From v) { return to_bf16((float)v); }
+};
+
 constexpr int kWave = 64;
 constexpr int kBlock = 256;
 constexpr int kMaxRestart = 64;

@@ -37,17 +37,19 @@ constexpr size_t kMaxLdsBytes = 160 * 1024;  // LDS of one CDNA4 compute unit
 //            cpl  [cptr*d*p*t] cell coupling S_dT, rows (face i, comp c, mode r), cols q,
 //            spp  [nc][t][t]   S_TT.
 //  v&p-cond: bsr  [nnzb][d*p][d*p] full blocks, cpl [cptr*d*p] mean-pressure coupling, spp unused.
-template <typename T>
+// Operator values are stored as Sto and the smoother's factors as StoP (T; or
+// bf16 with T = float: read as float).
+template <typename T, typename Sto = T, typename StoP = Sto>
 struct DLevel {
   int cond;  // 1 v, 2 vp
   int p, t;  // face modes, pressure modes per cell
   int64_t nface, N;  // face-part length nf*d*p, total length
-  const T *bsr, *cpl, *spp;
+  const Sto *bsr, *cpl, *spp;
   // smoother patches
-  const T *sinv;  // v: [pairoff*p*p] s_P^{-1}; vp: [pairoff*(d p)^2] S_P^{-1}; each cell's
+  const StoP *sinv;  // v: [pairoff*p*p] s_P^{-1}; vp: [pairoff*(d p)^2] S_P^{-1}; each cell's
                   // slot holds the lower triangle packed by rows (i (i+1)/2 + j, i >= j)
-  const T *xinv;  // v: [nc][t][t] pressure Schur inverse; vp: [cptr*d*p] g = S_P^{-1} b
-  const T *sig;   // vp: [nc] 1 / (b^T S_P^{-1} b)
+  const StoP *xinv;  // v: [nc][t][t] pressure Schur inverse; vp: [cptr*d*p] g = S_P^{-1} b
+  const StoP *sig;   // vp: [nc] 1 / (b^T S_P^{-1} b)
   int block = 0;  // threads per block of the operator kernels (0: default), chosen by the autotuner
   const int *skip = nullptr;  // lowest-degree operator kernels return at once while *skip != 0 (device flag)
 };
@@ -86,20 +88,20 @@ size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t el
 int reduce_blocks(int64_t n);
 // y = S x (face rows and cell rows); if xs1 != null the face part of x is the sum of
 // two slot vectors x (slot 0) and xs1 (slot 1), and xsum (if not null) receives it.
-template <typename T>
-void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s);
+template <typename T, typename Sto, typename StoP>
+void launch_spmv(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s);
 // Compile-time-sized variants of the two calls above (b != null: residual form);
 // false when no variant matches the level's block sizes.
-template <typename T>
-bool launch_spmv_fixed(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+template <typename T, typename Sto, typename StoP>
+bool launch_spmv_fixed(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
                        hipStream_t s);
 // r = b - S x
-template <typename T>
-void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x, T *r, hipStream_t s);
+template <typename T, typename Sto, typename StoP>
+void launch_residual(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *b, const T *x, T *r, hipStream_t s);
 // Schwarz preconditioner: face part in two slots (z: slot 0, zs1: slot 1), cells in z.
 // If scale != null the input is scale[0]*r and v (if not null) receives that scaled vector.
-template <typename T>
-void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
+template <typename T, typename Sto, typename StoP>
+void launch_precond(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
                     int max_faces, hipStream_t s);
 template <typename T>
 void launch_combine(int64_t nface, const T *zs1, T *z, hipStream_t s);

@@ -797,7 +797,7 @@ size_t patch_sweep_lds_bytes(int d, int cond, int p, int t, int max_faces, int t
 template <typename Tout, typename Tin>
 __global__ void k_convert(const Tin *in, Tout *out, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = (Tout)in[i];
+    out[i] = StoreAs<Tout>::from(in[i]);
 }
 
 // ------------------------------------------------------------ dense coarse level
@@ -1060,6 +1060,7 @@ void launch_convert(const Tin *in, Tout *out, int64_t n, hipStream_t s) {
 }
 template void launch_convert<float, double>(const double *, float *, int64_t, hipStream_t);
 template void launch_convert<double, float>(const float *, double *, int64_t, hipStream_t);
+template void launch_convert<bf16, double>(const double *, bf16 *, int64_t, hipStream_t);
 
 void launch_densify(const DTopo &tp, const DLevel<double> &L, int border, double *D, int64_t ld, hipStream_t s) {
   const int bs = (L.cond == 1) ? L.p : tp.d * L.p;

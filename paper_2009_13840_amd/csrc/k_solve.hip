@@ -29,8 +29,8 @@ __device__ inline T xface(const T *x, const T *xs1, int64_t i) {
 
 // y = S x  (MODE 0)   or   y = b - S x  (MODE 1).  One thread per output entry:
 // face rows first (f, c, r), then cell rows (T, q).
-template <typename T, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+template <typename T, typename Sto, typename StoP, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T, Sto, StoP> L, const T *__restrict__ x,
                                                   const T *__restrict__ xs1, T *__restrict__ xsum,
                                                   const T *__restrict__ b, T *__restrict__ y) {
   const int d = tp.d, p = L.p, t = L.t;
@@ -45,7 +45,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T 
       if (L.cond == 1) {
         const int c = cr / p, r = cr % p;
         for (int b = rb; b < re; ++b) {
-          const T *blk = L.bsr + (int64_t)b * p * p + r * p;
+          const Sto *blk = L.bsr + (int64_t)b * p * p + r * p;
           const int64_t xo = ((int64_t)tp.col[b] * d + c) * p;
           for (int k = 0; k < p; ++k) acc += blk[k] * xface<T, SPLIT>(x, xs1, xo + k);
         }
@@ -53,13 +53,13 @@ __global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T 
           const int Tc = tp.fcell[2 * f + s];
           if (Tc < 0) continue;
           const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + s];
-          const T *cp = L.cpl + ((e * d + c) * p + r) * t;
+          const Sto *cp = L.cpl + ((e * d + c) * p + r) * t;
           const T *xp = x + L.nface + (int64_t)Tc * t;
           for (int q = 0; q < t; ++q) acc += cp[q] * xp[q];
         }
       } else {
         for (int b = rb; b < re; ++b) {
-          const T *blk = L.bsr + (int64_t)b * dp * dp + (int64_t)cr * dp;
+          const Sto *blk = L.bsr + (int64_t)b * dp * dp + (int64_t)cr * dp;
           const int64_t xo = (int64_t)tp.col[b] * dp;
           for (int k = 0; k < dp; ++k) acc += blk[k] * xface<T, SPLIT>(x, xs1, xo + k);
         }
@@ -78,16 +78,16 @@ __global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T 
       if (L.cond == 1) {
         for (int e = eb; e < ee; ++e) {
           const int64_t xo = (int64_t)tp.cface[e] * dp;
-          const T *cp = L.cpl + (int64_t)e * dp * t + q;
+          const Sto *cp = L.cpl + (int64_t)e * dp * t + q;
           for (int k = 0; k < dp; ++k) acc += cp[(int64_t)k * t] * xface<T, SPLIT>(x, xs1, xo + k);
         }
-        const T *sp = L.spp + ((int64_t)Tc * t + q) * t;
+        const Sto *sp = L.spp + ((int64_t)Tc * t + q) * t;
         const T *xp = x + L.nface + (int64_t)Tc * t;
         for (int q2 = 0; q2 < t; ++q2) acc += sp[q2] * xp[q2];
       } else {
         for (int e = eb; e < ee; ++e) {
           const int64_t xo = (int64_t)tp.cface[e] * dp;
-          const T *cp = L.cpl + (int64_t)e * dp;
+          const Sto *cp = L.cpl + (int64_t)e * dp;
           for (int k = 0; k < dp; ++k) acc += cp[k] * xface<T, SPLIT>(x, xs1, xo + k);
         }
       }
@@ -105,8 +105,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv(DTopo tp, DLevel<T> L, const T 
 // lower entries add S_ji x_j to y_i (S_ij = S_ji, lane-local), and the whole row
 // gives y_j's dot product.  R rows are loaded together (R * SM loads in flight)
 // and their R * DC dot products are reduced across the wave together.
-template <typename T, int SM, int DC>
-__device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T *x, T *y, T *ydot) {
+template <typename T, typename Sto, int SM, int DC>
+__device__ void sym_packed_apply(const Sto *__restrict__ S, int m, int p, const T *x, T *y, T *ydot) {
   constexpr int DCP = DC == 1 ? 1 : DC == 2 ? 2 : 4;  // components padded to a power of two
   constexpr int R = (SM >= 3 ? 4 : 8) / DCP > 0 ? (SM >= 3 ? 4 : 8) / DCP : 1;  // rows per group
   constexpr int NV = R * DCP;                                                   // sums reduced together
@@ -129,11 +129,11 @@ __device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T 
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const int j = j0 + r;
-      const T *row = S + (int64_t)j * (j + 1) / 2;
+      const Sto *row = S + (int64_t)j * (j + 1) / 2;
 #pragma unroll
       for (int s = 0; s < SM; ++s) {
         const int i = lane + s * kWave;
-        v[r][s] = (j < m && i <= j) ? row[i] : (T)0;
+        v[r][s] = (j < m && i <= j) ? (T)row[i] : (T)0;
       }
     }
     T dot[NV];
@@ -187,8 +187,8 @@ __device__ void sym_packed_apply(const T *__restrict__ S, int m, int p, const T 
 // The same product for patches of at most 64 rows: one thread per output entry
 // walks its whole row through the packed index (the triangle stays in the L1/L2
 // caches after its first touch), no cross-lane reduction.
-template <typename T, int DC>
-__device__ void sym_row_apply(const T *__restrict__ S, int m, int p, const T *x, T *y) {
+template <typename T, typename Sto, int DC>
+__device__ void sym_row_apply(const Sto *__restrict__ S, int m, int p, const T *x, T *y) {
   const int n = m * DC;
   for (int e = threadIdx.x; e < n; e += blockDim.x) {
     const int fi = e / (DC * p), c = (e / p) % DC, rr = e % p;
@@ -198,7 +198,7 @@ __device__ void sym_row_apply(const T *__restrict__ S, int m, int p, const T *x,
 #pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const int lo = j < i ? j : i, hi = j < i ? i : j;
-      acc += S[hi * (hi + 1) / 2 + lo] * x[(jf * DC + c) * p + jr];
+      acc += (T)S[hi * (hi + 1) / 2 + lo] * x[(jf * DC + c) * p + jr];
       if (++jr == p) {
         jr = 0;
         ++jf;
@@ -214,8 +214,8 @@ __device__ void sym_row_apply(const T *__restrict__ S, int m, int p, const T *x,
 // slot of the face's side (slot 0: first cell of the face -> z, slot 1 -> zs1), so
 // that z_F = slot 0 + slot 1 with no write conflict.
 // SM, DC: as sym_packed_apply for the level's largest patch (DC = d for v-cond, 1 for v&p).
-template <typename T, int SM, int DC>
-__global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const T *__restrict__ r,
+template <typename T, typename Sto, typename StoP, int SM, int DC>
+__global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T, Sto, StoP> L, const T *__restrict__ r,
                                                    const double *__restrict__ scale, T *__restrict__ v,
                                                    T *__restrict__ z, T *__restrict__ zs1) {
   extern __shared__ unsigned char smem[];
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   T *rpr = yp + t + 1;         // [t]
   T *ydot = rpr + t;           // [n]
   T *red = ydot + n;           // [64] partial sums
-  const T *Si = L.sinv + tp.pairoff[Tc] * (int64_t)((L.cond == 1) ? p * p : dp * dp);  // packed lower triangle
+  const StoP *Si = L.sinv + tp.pairoff[Tc] * (int64_t)((L.cond == 1) ? p * p : dp * dp);  // packed lower triangle
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int fi = i / dp, k = i % dp;
     const int f = tp.cface[eb + fi];
@@ -247,10 +247,10 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
   }
   __syncthreads();
   if (L.cond == 1) {
-    const T *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
+    const Sto *C = L.cpl + (int64_t)eb * dp * t;      // [n][t]
     // u1 = (s^{-1} (x) I) r_u
-    if constexpr (SM == 1) sym_row_apply<T, DC>(Si, m, p, ru, u1);
-    else sym_packed_apply<T, SM, DC>(Si, m, p, ru, u1, ydot);
+    if constexpr (SM == 1) sym_row_apply<T, StoP, DC>(Si, m, p, ru, u1);
+    else sym_packed_apply<T, StoP, SM, DC>(Si, m, p, ru, u1, ydot);
     // y_p = X^{-1} (r_p - C^T u1); C^T u1 by lanes (part, q), parts = 64 / t taking
     // every parts-th row (coalesced rows of C), partials combined in order
     if (t <= kWave) {
@@ -274,7 +274,7 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
       }
     }
     __syncthreads();
-    const T *Xi = L.xinv + (int64_t)Tc * t * t;
+    const StoP *Xi = L.xinv + (int64_t)Tc * t * t;
     for (int q = threadIdx.x; q < t; q += blockDim.x) {
       T acc = 0;
       for (int q2 = 0; q2 < t; ++q2) acc += Xi[q * t + q2] * wv[q2];
@@ -289,17 +289,17 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T> L, const 
       wv[i] = acc;
     }
     __syncthreads();
-    if constexpr (SM == 1) sym_row_apply<T, DC>(Si, m, p, wv, u1);
-    else sym_packed_apply<T, SM, DC>(Si, m, p, wv, u1, ydot);
+    if constexpr (SM == 1) sym_row_apply<T, StoP, DC>(Si, m, p, wv, u1);
+    else sym_packed_apply<T, StoP, SM, DC>(Si, m, p, wv, u1, ydot);
   } else {
-    const T *g = L.xinv + (int64_t)eb * dp;
-    if constexpr (SM == 1) sym_row_apply<T, DC>(Si, n, n, ru, u1);
-    else sym_packed_apply<T, SM, DC>(Si, n, n, ru, u1, ydot);
+    const StoP *g = L.xinv + (int64_t)eb * dp;
+    if constexpr (SM == 1) sym_row_apply<T, StoP, DC>(Si, n, n, ru, u1);
+    else sym_packed_apply<T, StoP, SM, DC>(Si, n, n, ru, u1, ydot);
     T part = 0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) part += g[i] * ru[i];
     // wave reduction (blockDim == 64)
     double pd = wave_sum((double)part);
-    if (threadIdx.x == 0) yp[0] = (T)((pd - (double)rpr[0]) * (double)L.sig[Tc]);
+    if (threadIdx.x == 0) yp[0] = (T)((pd - (double)rpr[0]) * (double)(T)L.sig[Tc]);
     __syncthreads();
     const T ypv = yp[0];
     for (int i = threadIdx.x; i < n; i += blockDim.x) u1[i] -= g[i] * ypv;
@@ -515,28 +515,28 @@ int reduce_blocks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 256));
 }
 
-template <typename T>
-void launch_spmv(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s) {
-  if (launch_spmv_fixed<T>(tp, L, x, xs1, xsum, nullptr, y, s)) return;
+template <typename T, typename Sto, typename StoP>
+void launch_spmv(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *x, const T *xs1, T *xsum, T *y, hipStream_t s) {
+  if (launch_spmv_fixed<T, Sto, StoP>(tp, L, x, xs1, xsum, nullptr, y, s)) return;
   if (xs1)
-    HHO_LAUNCH((k_spmv<T, true, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
+    HHO_LAUNCH((k_spmv<T, Sto, StoP, true, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
                        (const T *)nullptr, y);
   else
-    HHO_LAUNCH((k_spmv<T, false, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
+    HHO_LAUNCH((k_spmv<T, Sto, StoP, false, 0>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, xs1, xsum,
                        (const T *)nullptr, y);
 }
-template <typename T>
-void launch_residual(const DTopo &tp, const DLevel<T> &L, const T *b, const T *x, T *r, hipStream_t s) {
-  if (launch_spmv_fixed<T>(tp, L, x, nullptr, nullptr, b, r, s)) return;
-  hipLaunchKernelGGL((k_spmv<T, false, 1>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, (const T *)nullptr,
+template <typename T, typename Sto, typename StoP>
+void launch_residual(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *b, const T *x, T *r, hipStream_t s) {
+  if (launch_spmv_fixed<T, Sto, StoP>(tp, L, x, nullptr, nullptr, b, r, s)) return;
+  hipLaunchKernelGGL((k_spmv<T, Sto, StoP, false, 1>), dim3(grid_for(L.N)), dim3(kBlock), 0, s, tp, L, x, (const T *)nullptr,
                      (T *)nullptr, b, r);
 }
 size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem) {
   const int n = max_faces * d * p;
   return (size_t)(3 * n + std::max(n, t) + 2 * t + 2 + kWave) * elem;
 }
-template <typename T>
-void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
+template <typename T, typename Sto, typename StoP>
+void launch_precond(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
                     int max_faces, hipStream_t s) {
   const size_t lds = precond_lds_bytes(tp.d, L.cond, L.p, L.t, max_faces, sizeof(T));
   const int rows = max_faces * ((L.cond == 1) ? L.p : tp.d * L.p);  // rows of the largest packed inverse
@@ -544,7 +544,7 @@ void launch_precond(const DTopo &tp, const DLevel<T> &L, const T *r, const doubl
   if (sm < 1 || sm > kPatchMaxRows / kWave) fail(HHO_E_INVALID_ARG, "precond: patch too large");
 #define HHO_PC(SM, DC)                                                                                         \
   if (sm == SM && dc == DC) {                                                                                  \
-    HHO_LAUNCH((k_precond<T, SM, DC>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1); \
+    HHO_LAUNCH((k_precond<T, Sto, StoP, SM, DC>), dim3(tp.nc), dim3(kWave), lds, s, tp, L, r, scale, v, z, zs1); \
     return;                                                                                                    \
   }
   HHO_PC(1, 1) HHO_PC(2, 1) HHO_PC(3, 1) HHO_PC(4, 1)
@@ -621,11 +621,19 @@ void launch_copy(int64_t n, const T *x, T *y, hipStream_t s) {
   hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(kBlock), 0, s, n, x, y);
 }
 
+#define HHO_INST_OP(T, Sto, StoP)                                                                               \
+  template void launch_spmv<T, Sto, StoP>(const DTopo &, const DLevel<T, Sto, StoP> &, const T *, const T *, T *, \
+                                          T *, hipStream_t);                                                     \
+  template void launch_residual<T, Sto, StoP>(const DTopo &, const DLevel<T, Sto, StoP> &, const T *, const T *,  \
+                                              T *, hipStream_t);                                                 \
+  template void launch_precond<T, Sto, StoP>(const DTopo &, const DLevel<T, Sto, StoP> &, const T *,             \
+                                             const double *, T *, T *, T *, int, hipStream_t);
+HHO_INST_OP(double, double, double)
+HHO_INST_OP(float, float, float)
+HHO_INST_OP(float, bf16, float)
+#undef HHO_INST_OP
+
 #define HHO_INST(T)                                                                                              \
-  template void launch_spmv<T>(const DTopo &, const DLevel<T> &, const T *, const T *, T *, T *, hipStream_t);  \
-  template void launch_residual<T>(const DTopo &, const DLevel<T> &, const T *, const T *, T *, hipStream_t);   \
-  template void launch_precond<T>(const DTopo &, const DLevel<T> &, const T *, const double *, T *, T *, T *,   \
-                                  int, hipStream_t);                                                           \
   template void launch_combine<T>(int64_t, const T *, T *, hipStream_t);                                        \
   template void launch_mr2_dots<T>(int64_t, int, const T *, const T *, const T *, double *, double *,           \
                                    hipStream_t);                                                               \

@@ -27,8 +27,8 @@ __device__ inline T xface(const T *__restrict__ x, const T *__restrict__ xs1, in
   return x[i];
 }
 
-template <typename T, int D, int P, int TT, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+template <typename T, typename Sto, typename StoP, int D, int P, int TT, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T, Sto, StoP> L, const T *__restrict__ x,
                                                     const T *__restrict__ xs1, T *__restrict__ xsum,
                                                     const T *__restrict__ b, T *__restrict__ y) {
   constexpr int DP = D * P;
@@ -55,7 +55,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if (mb[u] < 0) continue;
-        const T *blk = L.bsr + mb[u] * (P * P) + r;
+        const Sto *blk = L.bsr + mb[u] * (P * P) + r;
         T bv[P];
 #pragma unroll
         for (int k = 0; k < P; ++k) bv[k] = blk[k * P];
@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
       const int Tc = tp.fcell[2 * f + s];
       if (Tc < 0) continue;
       const int64_t e = (int64_t)tp.cptr[Tc] + tp.floc[2 * f + s];
-      const T *cp = L.cpl + (e * DP + r) * TT;
+      const Sto *cp = L.cpl + (e * DP + r) * TT;
       const T *xp = x + L.nface + (int64_t)Tc * TT;
       T xv[TT];
 #pragma unroll
@@ -94,11 +94,11 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
     const int eb = tp.cptr[Tc], ee = tp.cptr[Tc + 1];
     for (int e = eb; e < ee; ++e) {
       const int64_t xo = (int64_t)tp.cface[e] * DP;
-      const T *cp = L.cpl + (int64_t)e * DP * TT + q;
+      const Sto *cp = L.cpl + (int64_t)e * DP * TT + q;
 #pragma unroll
       for (int j = 0; j < DP; ++j) acc += cp[j * TT] * xface<T, SPLIT>(x, xs1, xo + j);
     }
-    const T *sp = L.spp + (int64_t)Tc * TT * TT + q;
+    const Sto *sp = L.spp + (int64_t)Tc * TT * TT + q;
     const T *xp = x + L.nface + (int64_t)Tc * TT;
 #pragma unroll
     for (int q2 = 0; q2 < TT; ++q2) acc += sp[q2 * TT] * xp[q2];
@@ -111,8 +111,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v(DTopo tp, DLevel<T> L, const 
 // Lowest degree (k = 0, v-cond: one face mode, one pressure mode per cell): the
 // rows are short, so G lanes share a row (its blocks, its two cells, or its
 // cell's faces) and combine by shuffles; otherwise as k_spmv_v.
-template <typename T, int D, int G, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+template <typename T, typename Sto, typename StoP, int D, int G, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T, Sto, StoP> L, const T *__restrict__ x,
                                                      const T *__restrict__ xs1, T *__restrict__ xsum,
                                                      const T *__restrict__ b, T *__restrict__ y) {
   if (L.skip && *L.skip) return;
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T> L, const
 #pragma unroll
     for (int c = 0; c < D; ++c) acc[c] = 0;
     for (int bi = tp.rowptr[f] + lane; bi < tp.rowptr[f + 1]; bi += G) {
-      const T a = L.bsr[bi];  // a 1 x 1 block is its own mirror
+      const T a = (T)L.bsr[bi];  // a 1 x 1 block is its own mirror
       const int64_t xo = (int64_t)tp.col[bi] * D;
 #pragma unroll
       for (int c = 0; c < D; ++c) acc[c] += a * xface<T, SPLIT>(x, xs1, xo + c);
@@ -170,8 +170,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv_v0(DTopo tp, DLevel<T> L, const
 // Lowest degree, v&p-cond (d x d face blocks, one mean pressure per cell): G lanes
 // share a face row block (its blocks, read whole by one lane, and its two cells)
 // or a cell row (its faces), combined by shuffles.
-template <typename T, int BS, int G, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv_vp0(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+template <typename T, typename Sto, typename StoP, int BS, int G, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_vp0(DTopo tp, DLevel<T, Sto, StoP> L, const T *__restrict__ x,
                                                       const T *__restrict__ xs1, T *__restrict__ xsum,
                                                       const T *__restrict__ b, T *__restrict__ y) {
   if (L.skip && *L.skip) return;
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_vp0(DTopo tp, DLevel<T> L, cons
 #pragma unroll
     for (int i = 0; i < BS; ++i) acc[i] = 0;
     for (int bi = tp.rowptr[f] + lane; bi < tp.rowptr[f + 1]; bi += G) {
-      const T *blk = L.bsr + (int64_t)bi * (BS * BS);
+      const Sto *blk = L.bsr + (int64_t)bi * (BS * BS);
       const int64_t xo = (int64_t)tp.col[bi] * BS;
       T xv[BS];
 #pragma unroll
@@ -230,8 +230,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv_vp0(DTopo tp, DLevel<T> L, cons
   }
 }
 
-template <typename T, int BS, bool SPLIT, int MODE>
-__global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const T *__restrict__ x,
+template <typename T, typename Sto, typename StoP, int BS, bool SPLIT, int MODE>
+__global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T, Sto, StoP> L, const T *__restrict__ x,
                                                      const T *__restrict__ xs1, T *__restrict__ xsum,
                                                      const T *__restrict__ b, T *__restrict__ y) {
   const int64_t nfr = (int64_t)tp.nf * BS;
@@ -243,7 +243,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const
     const int rb = tp.rowptr[f], re = tp.rowptr[f + 1];
     for (int bi = rb; bi < re; ++bi) {
       const int64_t xo = (int64_t)tp.col[bi] * BS;
-      const T *blk = L.bsr + (int64_t)tp.mirror[bi] * (BS * BS) + i;
+      const Sto *blk = L.bsr + (int64_t)tp.mirror[bi] * (BS * BS) + i;
 #pragma unroll
       for (int k = 0; k < BS; ++k) acc += blk[k * BS] * xface<T, SPLIT>(x, xs1, xo + k);
     }
@@ -262,7 +262,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const
     const int eb = tp.cptr[Tc], ee = tp.cptr[Tc + 1];
     for (int e = eb; e < ee; ++e) {
       const int64_t xo = (int64_t)tp.cface[e] * BS;
-      const T *cp = L.cpl + (int64_t)e * BS;
+      const Sto *cp = L.cpl + (int64_t)e * BS;
 #pragma unroll
       for (int k = 0; k < BS; ++k) acc += cp[k] * xface<T, SPLIT>(x, xs1, xo + k);
     }
@@ -274,8 +274,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv_vp(DTopo tp, DLevel<T> L, const
 constexpr int dimP(int d, int k) { return d == 2 ? k + 1 : (k + 1) * (k + 2) / 2; }
 constexpr int dimT(int d, int k) { return d == 2 ? (k + 1) * (k + 2) / 2 : (k + 1) * (k + 2) * (k + 3) / 6; }
 
-template <typename T, bool SPLIT, int MODE, int D, int K>
-bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+template <typename T, typename Sto, typename StoP, bool SPLIT, int MODE, int D, int K>
+bool try_launch(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
                 hipStream_t s) {
   constexpr int P = dimP(D, K), TT = dimT(D, K);
   if (tp.d != D || L.p != P) return false;
@@ -286,56 +286,60 @@ bool try_launch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T
       constexpr int G = 4;
       const int64_t total = ((int64_t)tp.nf + tp.nc) * G;
       const int grid = (int)((total + bs - 1) / bs);
-      HHO_LAUNCH((k_spmv_v0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+      HHO_LAUNCH((k_spmv_v0<T, Sto, StoP, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
       return true;
     }
     const int64_t total = (int64_t)tp.nf * P + (int64_t)tp.nc * TT;
     const int grid = (int)((total + bs - 1) / bs);
-    HHO_LAUNCH((k_spmv_v<T, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+    HHO_LAUNCH((k_spmv_v<T, Sto, StoP, D, P, TT, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   } else {
     const int bs = L.block > 0 ? L.block : kBlock;
     if (K == 0) {
       constexpr int G = 4;
       const int64_t total = ((int64_t)tp.nf + tp.nc) * G;
       const int grid = (int)((total + bs - 1) / bs);
-      HHO_LAUNCH((k_spmv_vp0<T, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+      HHO_LAUNCH((k_spmv_vp0<T, Sto, StoP, D, G, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
       return true;
     }
     const int64_t total = (int64_t)tp.nf * D * P + tp.nc;
     const int grid = (int)((total + bs - 1) / bs);
-    HHO_LAUNCH((k_spmv_vp<T, D * P, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
+    HHO_LAUNCH((k_spmv_vp<T, Sto, StoP, D * P, SPLIT, MODE>), dim3(grid), dim3(bs), 0, s, tp, L, x, xs1, xsum, b, y);
   }
   return true;
 }
 
-template <typename T, bool SPLIT, int MODE>
-bool dispatch(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+template <typename T, typename Sto, typename StoP, bool SPLIT, int MODE>
+bool dispatch(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
               hipStream_t s) {
-  return try_launch<T, SPLIT, MODE, 2, 0>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 2, 1>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 2, 2>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 2, 3>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 2, 4>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 3, 0>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 3, 1>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 3, 2>(tp, L, x, xs1, xsum, b, y, s) ||
-         try_launch<T, SPLIT, MODE, 3, 3>(tp, L, x, xs1, xsum, b, y, s);
+  return try_launch<T, Sto, StoP, SPLIT, MODE, 2, 0>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 2, 1>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 2, 2>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 2, 3>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 2, 4>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 3, 0>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 3, 1>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 3, 2>(tp, L, x, xs1, xsum, b, y, s) ||
+         try_launch<T, Sto, StoP, SPLIT, MODE, 3, 3>(tp, L, x, xs1, xsum, b, y, s);
 }
 
 }  // namespace
 
-template <typename T>
-bool launch_spmv_fixed(const DTopo &tp, const DLevel<T> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
+template <typename T, typename Sto, typename StoP>
+bool launch_spmv_fixed(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *x, const T *xs1, T *xsum, const T *b, T *y,
                        hipStream_t s) {
   if (tp.nf == 0 && tp.nc == 0) return true;
-  if (b) return dispatch<T, false, 1>(tp, L, x, nullptr, nullptr, b, y, s);
-  if (xs1) return dispatch<T, true, 0>(tp, L, x, xs1, xsum, nullptr, y, s);
-  return dispatch<T, false, 0>(tp, L, x, nullptr, nullptr, nullptr, y, s);
+  if (b) return dispatch<T, Sto, StoP, false, 1>(tp, L, x, nullptr, nullptr, b, y, s);
+  if (xs1) return dispatch<T, Sto, StoP, true, 0>(tp, L, x, xs1, xsum, nullptr, y, s);
+  return dispatch<T, Sto, StoP, false, 0>(tp, L, x, nullptr, nullptr, nullptr, y, s);
 }
 
-template bool launch_spmv_fixed<double>(const DTopo &, const DLevel<double> &, const double *, const double *,
-                                        double *, const double *, double *, hipStream_t);
-template bool launch_spmv_fixed<float>(const DTopo &, const DLevel<float> &, const float *, const float *, float *,
-                                       const float *, float *, hipStream_t);
+template bool launch_spmv_fixed<double, double, double>(const DTopo &, const DLevel<double> &, const double *,
+                                                        const double *, double *, const double *, double *,
+                                                        hipStream_t);
+template bool launch_spmv_fixed<float, float, float>(const DTopo &, const DLevel<float> &, const float *,
+                                                     const float *, float *, const float *, float *, hipStream_t);
+template bool launch_spmv_fixed<float, bf16, float>(const DTopo &, const DLevel<float, bf16, float> &,
+                                                    const float *, const float *, float *, const float *, float *,
+                                                    hipStream_t);
 
 }  // namespace hho

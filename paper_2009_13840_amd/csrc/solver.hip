@@ -56,6 +56,8 @@ struct LevelInfo {
   double *bsr, *cpl, *spp, *sinv, *xinv, *sig;
   // FP32 copies (mixed V-cycle)
   float *bsr32, *cpl32, *spp32, *sinv32, *xinv32, *sig32;
+  // bfloat16 copies of the operator (V-cycle with 16-bit operator storage, FP32 arithmetic)
+  bf16 *bsr16, *cpl16, *spp16;
   VBufs<double> v64;
   VBufs<float> v32;
   double *y;  // smoother coefficients
@@ -153,7 +155,9 @@ static int level_t(const hho_problem *P, int k) { return P->cond == HHO_COND_V ?
 static void plan(hho_problem *P, Arena &A) {
   const int d = P->d;
   const int64_t nc = P->mesh->nc, nf = P->mesh->nf;
-  const bool mixed = P->opt.precision == HHO_PREC_FP32;
+  // levels above the coarsest run in FP32 arithmetic (FP32 or bfloat16 storage)
+  const bool mixed = P->opt.precision != HHO_PREC_FP64;
+  const bool b16 = P->opt.precision == HHO_PREC_BF16;
   // topology
   P->tp.cptr = A.take<int32_t>(nc + 1);
   P->tp.cface = A.take<int32_t>(P->ncf);
@@ -191,9 +195,17 @@ static void plan(hho_problem *P, Arena &A) {
     L.sig = need_smoother ? A.take<double>(nc) : nullptr;
     L.y = A.take<double>(4);
     if (mixed && l < Lc) {
-      L.bsr32 = A.take<float>(nbsr);
-      L.cpl32 = A.take<float>(ncpl);
-      L.spp32 = A.take<float>(nspp);
+      // bfloat16 mode: operator values in 16 bits; the smoother's factors stay FP32
+      // (its packed-row loads are bound by their count, not their width)
+      if (b16) {
+        L.bsr16 = A.take<bf16>(nbsr);
+        L.cpl16 = A.take<bf16>(ncpl);
+        L.spp16 = A.take<bf16>(nspp);
+      } else {
+        L.bsr32 = A.take<float>(nbsr);
+        L.cpl32 = A.take<float>(ncpl);
+        L.spp32 = A.take<float>(nspp);
+      }
       L.sinv32 = A.take<float>(nsinv);
       L.xinv32 = A.take<float>(nxinv);
       L.sig32 = A.take<float>(nc);
@@ -400,16 +412,37 @@ static DLevel<float> dlev32(const hho_problem *P, int l) {
   D.block = L.spmv_block;
   return D;
 }
-template <typename T>
-struct LevSel;
-template <>
-struct LevSel<double> {
+static DLevel<float, bf16, float> dlev16(const hho_problem *P, int l) {
+  const LevelInfo &L = P->lev[l];
+  DLevel<float, bf16, float> D;
+  D.cond = P->cond;
+  D.p = L.p;
+  D.t = L.t;
+  D.nface = L.nface;
+  D.N = L.N;
+  D.bsr = L.bsr16;
+  D.cpl = L.cpl16;
+  D.spp = L.spp16;
+  D.sinv = L.sinv32;
+  D.xinv = L.xinv32;
+  D.sig = L.sig32;
+  D.block = L.spmv_block;
+  return D;
+}
+// V-cycle precisions: vector/arithmetic type T and value storage Sto
+struct PrecF64 {
+  using T = double;
   static DLevel<double> op(const hho_problem *P, int l) { return dlev64(P, l); }
   static VBufs<double> &vb(hho_problem *P, int l) { return P->lev[l].v64; }
 };
-template <>
-struct LevSel<float> {
+struct PrecF32 {
+  using T = float;
   static DLevel<float> op(const hho_problem *P, int l) { return dlev32(P, l); }
+  static VBufs<float> &vb(hho_problem *P, int l) { return P->lev[l].v32; }
+};
+struct PrecB16 {
+  using T = float;
+  static DLevel<float, bf16, float> op(const hho_problem *P, int l) { return dlev16(P, l); }
   static VBufs<float> &vb(hho_problem *P, int l) { return P->lev[l].v32; }
 };
 
@@ -659,8 +692,8 @@ static void device_setup(hho_problem *P) {
     bp_setup(P->tp, P->cond, P->d_fdiag, LC.bsr, LC.cpl, P->Sd, s);
     amg_numeric_setup(P->amgd, P->cond, P->d, LC.bs, P->nnzb, LC.bsr, P->amg_nu, P->err + 3, s);
   }
-  // FP32 copies for the mixed-precision V-cycle
-  if (P->opt.precision == HHO_PREC_FP32) {
+  // FP32 or bfloat16 copies for the mixed-precision V-cycle
+  if (P->opt.precision != HHO_PREC_FP64) {
     for (int l = 0; l < Lc; ++l) {
       LevelInfo &L = P->lev[l];
       const int d = P->d;
@@ -669,9 +702,15 @@ static void device_setup(hho_problem *P) {
       const int64_t nspp = P->cond == HHO_COND_V ? nc * L.t * L.t : 1;
       const int64_t nsinv = P->pairoff[nc] * L.bs * L.bs;
       const int64_t nxinv = P->cond == HHO_COND_V ? nc * L.t * L.t : P->ncf * d * L.p;
-      launch_convert<float, double>(L.bsr, L.bsr32, nbsr, s);
-      launch_convert<float, double>(L.cpl, L.cpl32, ncpl, s);
-      if (P->cond == HHO_COND_V) launch_convert<float, double>(L.spp, L.spp32, nspp, s);
+      if (P->opt.precision == HHO_PREC_BF16) {
+        launch_convert<bf16, double>(L.bsr, L.bsr16, nbsr, s);
+        launch_convert<bf16, double>(L.cpl, L.cpl16, ncpl, s);
+        if (P->cond == HHO_COND_V) launch_convert<bf16, double>(L.spp, L.spp16, nspp, s);
+      } else {
+        launch_convert<float, double>(L.bsr, L.bsr32, nbsr, s);
+        launch_convert<float, double>(L.cpl, L.cpl32, ncpl, s);
+        if (P->cond == HHO_COND_V) launch_convert<float, double>(L.spp, L.spp32, nspp, s);
+      }
       launch_convert<float, double>(L.sinv, L.sinv32, nsinv, s);
       launch_convert<float, double>(L.xinv, L.xinv32, nxinv, s);
       if (P->cond != HHO_COND_V) launch_convert<float, double>(L.sig, L.sig32, nc, s);
@@ -695,11 +734,12 @@ static void device_setup(hho_problem *P) {
 }
 
 // ------------------------------------------------------------ V-cycle
-template <typename T>
+template <typename Prec>
 static void smooth(hho_problem *P, int l) {
+  using T = typename Prec::T;
   hipStream_t s = P->stream;
-  const DLevel<T> D = LevSel<T>::op(P, l);
-  VBufs<T> &V = LevSel<T>::vb(P, l);
+  const auto D = Prec::op(P, l);
+  VBufs<T> &V = Prec::vb(P, l);
   const int m = P->opt.smooth_its;
   const int64_t n = D.N;
   const bool learned = l == 0 && P->learned_on;
@@ -728,29 +768,30 @@ static void smooth(hho_problem *P, int l) {
 static void coarse_solve(hho_problem *P);
 
 // MG_V(l, b, 0): input lev[l] b, output lev[l] w
-template <typename T>
+template <typename Prec>
 static void vcycle(hho_problem *P, int l) {
+  using T = typename Prec::T;
   hipStream_t s = P->stream;
   const int Lc = P->nlev - 1;
-  const DLevel<T> D = LevSel<T>::op(P, l);
-  VBufs<T> &V = LevSel<T>::vb(P, l);
+  const auto D = Prec::op(P, l);
+  VBufs<T> &V = Prec::vb(P, l);
   const LevelInfo &A = P->lev[l], &B = P->lev[l + 1];
   const int d = P->d, nf = (int)P->mesh->nf, nc = (int)P->mesh->nc;
   launch_fill<T>(D.N, (T)0, V.w, s);
   launch_copy<T>(D.N, V.b, V.r, s);
-  smooth<T>(P, l);
+  smooth<Prec>(P, l);
   if (l + 1 == Lc) {
     launch_restrict<double, T>(d, nf, nc, A.p, A.t, B.p, B.t, V.r, P->lev[Lc].v64.b, s);
     coarse_solve(P);
     launch_prolong_add<double, T>(d, nf, nc, A.p, A.t, B.p, B.t, P->lev[Lc].v64.w, V.w, s);
   } else {
-    VBufs<T> &W = LevSel<T>::vb(P, l + 1);
+    VBufs<T> &W = Prec::vb(P, l + 1);
     launch_restrict<T, T>(d, nf, nc, A.p, A.t, B.p, B.t, V.r, W.b, s);
-    vcycle<T>(P, l + 1);
+    vcycle<Prec>(P, l + 1);
     launch_prolong_add<T, T>(d, nf, nc, A.p, A.t, B.p, B.t, W.w, V.w, s);
   }
   launch_residual<T>(P->tp, D, V.b, V.w, V.r, s);
-  smooth<T>(P, l);
+  smooth<Prec>(P, l);
 }
 
 static void read_state(hho_problem *P, GmresState *dst) {
@@ -840,13 +881,16 @@ static void apply_vcycle(hho_problem *P, const double *b, double *x) {
     launch_copy<double>(L0.N, L0.v64.w, x, s);
     return;
   }
-  if (P->opt.precision == HHO_PREC_FP32) {
+  if (P->opt.precision != HHO_PREC_FP64) {
     launch_convert<float, double>(b, L0.v32.b, L0.N, s);
-    vcycle<float>(P, 0);
+    if (P->opt.precision == HHO_PREC_BF16)
+      vcycle<PrecB16>(P, 0);
+    else
+      vcycle<PrecF32>(P, 0);
     launch_convert<double, float>(L0.v32.w, x, L0.N, s);
   } else {
     launch_copy<double>(L0.N, b, L0.v64.b, s);
-    vcycle<double>(P, 0);
+    vcycle<PrecF64>(P, 0);
     launch_copy<double>(L0.N, L0.v64.w, x, s);
   }
 }
@@ -1126,7 +1170,7 @@ void hho_options_default(hho_options *o) {
   o->smooth_its = 2;
   o->precision = HHO_PREC_FP64;
   o->coarse_mode = HHO_COARSE_AUTO;
-  o->coarse_rtol = 1e-3;
+  o->coarse_rtol = 0.0;  // resolved per dimension at problem creation
   o->coarse_restart = 30;
   o->coarse_max_it = 300;
   o->quad_extra = 6;
@@ -1189,15 +1233,19 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
     hho::fail(HHO_E_INVALID_ARG, "coarse_amg_explicit must be in 0..4096");
   if (P->opt.coarse_amg_psmooth < 1 || P->opt.coarse_amg_psmooth > 2)
     hho::fail(HHO_E_INVALID_ARG, "coarse_amg_psmooth must be 1 or 2");
-  if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32)
+  if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32 && P->opt.precision != HHO_PREC_BF16)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
   if (P->opt.learned != 0 && P->opt.learned != 1) hho::fail(HHO_E_INVALID_ARG, "learned must be 0 or 1");
   if (P->opt.smoother != HHO_SMOOTHER_SCHWARZ) hho::fail(HHO_E_INVALID_ARG, "smoother: only HHO_SMOOTHER_SCHWARZ");
   if (P->opt.nullspace != HHO_NULLSPACE_AUTO && P->opt.nullspace != HHO_NULLSPACE_NONE)
     hho::fail(HHO_E_INVALID_ARG, "nullspace must be HHO_NULLSPACE_AUTO or HHO_NULLSPACE_NONE");
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
-  if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol > 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
+  if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol >= 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
   const int d = P->d;
+  // coarsest-level tolerance: the paper's 1e-3 for its iterative coarse solve in
+  // 3D; in 2D, where the paper solves the coarsest level exactly, 1e-2 keeps the
+  // exact solve's outer iteration count
+  if (P->opt.coarse_rtol == 0) P->opt.coarse_rtol = d == 3 ? 1e-3 : 1e-2;
   {  // the patch smoother keeps a cell's face unknowns (one component for v-cond) in one wavefront's registers
     const int pk = (d == 2) ? k + 1 : (k + 1) * (k + 2) / 2;
     if (P->deg.size() > 1 && (int64_t)mesh->max_faces * (cond == 1 ? pk : d * pk) > hho::kPatchMaxRows)
@@ -1478,6 +1526,48 @@ int hho_level_apply(hho_problem *p, int level, const double *x, double *y) {
   ABI_END
 }
 
+int hho_vcycle_level_apply(hho_problem *p, int level, int which, const double *x, double *y) {
+  ABI_BEGIN
+  need_setup(p);
+  if (level < 0 || level >= p->nlev || !x || !y || (which != 0 && which != 1))
+    hho::fail(HHO_E_INVALID_ARG, "vcycle_level_apply: bad argument");
+  const hho::LevelInfo &L = p->lev[level];
+  if (which == 1 && !L.sinv) hho::fail(HHO_E_INVALID_ARG, "vcycle_level_apply: this level has no smoother");
+  hipStream_t s = p->stream;
+  const bool mixed = p->opt.precision != HHO_PREC_FP64 && level < p->nlev - 1;
+  if (!mixed) {
+    if (which == 0) {
+      hho::launch_spmv<double>(p->tp, hho::dlev64(p, level), x, nullptr, nullptr, y, s);
+    } else {
+      double *zs1 = p->ow;
+      hho::launch_precond<double>(p->tp, hho::dlev64(p, level), x, nullptr, nullptr, y, zs1, p->max_faces, s);
+      hho::launch_combine<double>(L.nface, zs1, y, s);
+    }
+  } else {
+    // the level's own FP32 V-cycle vectors serve as input and output
+    const hho::VBufs<float> &V = p->lev[level].v32;
+    hho::launch_convert<float, double>(x, V.z1, L.N, s);
+    const bool b16 = p->opt.precision == HHO_PREC_BF16;
+    if (which == 0) {
+      if (b16)
+        hho::launch_spmv<float>(p->tp, hho::dlev16(p, level), V.z1, nullptr, nullptr, V.w1, s);
+      else
+        hho::launch_spmv<float>(p->tp, hho::dlev32(p, level), V.z1, nullptr, nullptr, V.w1, s);
+    } else {
+      if (b16)
+        hho::launch_precond<float>(p->tp, hho::dlev16(p, level), V.z1, nullptr, nullptr, V.w1, V.zs1, p->max_faces, s);
+      else
+        hho::launch_precond<float>(p->tp, hho::dlev32(p, level), V.z1, nullptr, nullptr, V.w1, V.zs1, p->max_faces, s);
+      hho::launch_combine<float>(L.nface, V.zs1, V.w1, s);
+    }
+    hho::launch_convert<double, float>(V.w1, y, L.N, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
 int hho_precond_apply(hho_problem *p, int level, const double *r, double *z) {
   ABI_BEGIN
   need_setup(p);
@@ -1557,7 +1647,8 @@ static double time_kernel_ms(hho_problem *p, int kind, int level, int reps) {
   if (level < 0 || level >= p->nlev || reps < 1) hho::fail(HHO_E_INVALID_ARG, "time_kernel: bad argument");
   hipStream_t s = p->stream;
   const hho::LevelInfo &L = p->lev[level];
-  const bool mixed = p->opt.precision == HHO_PREC_FP32 && level < p->nlev - 1;
+  const bool mixed = p->opt.precision != HHO_PREC_FP64 && level < p->nlev - 1;
+  const bool b16 = p->opt.precision == HHO_PREC_BF16;
   if ((kind == 1 || kind == 2) && !L.sinv) hho::fail(HHO_E_INVALID_ARG, "time_kernel: level has no smoother");
   // inputs: the level's operator applied to the outer solver's scratch vectors
   hho::launch_fill<double>(L.N, 1.0, p->ox, s);
@@ -1573,7 +1664,10 @@ static double time_kernel_ms(hho_problem *p, int kind, int level, int reps) {
       case 2:
         if (mixed) {
           const hho::VBufs<float> &V = p->lev[level].v32;
-          hho::launch_spmv<float>(p->tp, hho::dlev32(p, level), V.zs0, V.zs1, V.z1, V.w1, s);
+          if (b16)
+            hho::launch_spmv<float>(p->tp, hho::dlev16(p, level), V.zs0, V.zs1, V.z1, V.w1, s);
+          else
+            hho::launch_spmv<float>(p->tp, hho::dlev32(p, level), V.zs0, V.zs1, V.z1, V.w1, s);
         } else {
           const hho::VBufs<double> &V = p->lev[level].v64;
           hho::launch_spmv<double>(p->tp, hho::dlev64(p, level), V.zs0, V.zs1, V.z1, V.w1, s);

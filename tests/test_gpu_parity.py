@@ -267,6 +267,8 @@ def _solution_parity(O, P, coarse, tag, **hk):
     x, its, hist, rel, ok = P.solve()
     assert ok and rel <= 1e-12, (its, rel)
     x = x.cpu().numpy()
+    if coarse != "direct":   # the library's default coarse tolerance: 1e-3 in 3D, 1e-2 in 2D
+        hk.setdefault("coarse_rtol", 1e-3 if O.mesh.dim == 3 else 1e-2)
     xo, its_o, hist_o, conv = OS.solve_fgmres(O, rtol=1e-12, coarse=coarse, **hk)
     assert conv
     xd = OS.normalise_pressure(O, OS.solve_direct(O))

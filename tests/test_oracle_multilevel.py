@@ -342,3 +342,38 @@ def test_one_level_vcycle_is_the_coarsest_solve():
     assert np.abs(H.vcycle(0, b) - x).max() < 1e-12 * np.abs(x).max()
     xs, its, hist, conv = OS.solve_fgmres(P, rtol=1e-12, coarse="direct")
     assert conv and its == 1
+
+
+def test_bfloat16_rounding_definition():
+    """round_bf16 against values fixed by the definition of round-to-nearest-even
+    on the bfloat16 grid (8 significand bits) and against a brute-force nearest
+    search on random float32 values."""
+    import numpy as np
+    from oracle.mixed import round_bf16
+    u = 2.0 ** -7                       # bfloat16 spacing on [1, 2)
+    cases = {1.0: 1.0, 1.0 + u: 1.0 + u, 1.0 + u / 2: 1.0,                 # tie -> even (1.0)
+             1.0 + 3 * u / 2: 1.0 + 2 * u,                                  # tie -> even (1 + 2u)
+             1.0 + u / 2 + 2.0 ** -20: 1.0 + u, -(1.0 + 3 * u / 2): -(1.0 + 2 * u),
+             2.0 ** -130: 2.0 ** -130, 0.0: 0.0, 3.0: 3.0, 1e38: None}
+    for x, want in cases.items():
+        got = float(round_bf16(np.float32(x)))
+        if want is None:
+            assert np.isfinite(got) and abs(got - 1e38) <= 2.0 ** -8 * 1e38
+        else:
+            assert got == want, (x, got, want)
+    assert np.isnan(round_bf16(np.float32(np.nan)))
+    assert round_bf16(np.float32(np.inf)) == np.inf
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(20000) * 10.0 ** rng.uniform(-6, 6, 20000)).astype(np.float32)
+    r = round_bf16(x)
+    assert np.array_equal(round_bf16(r), r)                        # idempotent
+    assert np.all((r.view(np.uint32) & 0xFFFF) == 0)               # on the bfloat16 grid
+    # nearest of the grid neighbours (brute force over the two candidates)
+    e = np.floor(np.log2(np.abs(x.astype(np.float64))))
+    step = 2.0 ** (e - 7)
+    lo = np.trunc(x.astype(np.float64) / step) * step
+    hi = lo + np.sign(x) * step
+    d_lo, d_hi = np.abs(x - lo), np.abs(x - hi)
+    best = np.where(d_lo < d_hi, lo, hi)
+    ties = d_lo == d_hi
+    assert np.array_equal(r[~ties].astype(np.float64), best[~ties])
