@@ -482,7 +482,7 @@ def roofline_from(table, kind, label, workload):
                        for r in rows]}
 
 
-def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=None, probe=True):
+def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=None, probe=True, copy="convert"):
     """One configuration of the solver on the workload: host phase and upload
     (untimed), optional training of the learned smoother (untimed), warmup steps,
     then `args.steps` timed steps (setup + solve to 1e-8), each checked for
@@ -493,7 +493,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
     import paper_2009_13840_amd as H
     M = H.Mesh(mesh)
     P = H.Problem(M, spec["k"], spec["cond"], precision=precision, coarse_rtol=args.coarse_rtol,
-                  learned=1 if learned else 0)
+                  learned=1 if learned else 0, vcycle_copy=copy)
     t_host = time.perf_counter()
     P.set_data(*data)
     t_host = time.perf_counter() - t_host
@@ -501,7 +501,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
     P.upload()
     torch.cuda.synchronize()
     n0 = P.level_size(0)
-    tag = f"{workload} {precision}{' learned' if learned else ''}"
+    tag = f"{workload} {precision}{' learned' if learned else ''}{' product copy' if copy == 'product' else ''}"
     print(f"[bench] {tag}: host phase {t_host:.2f}s, workspace {P.workspace_size() / 2**30:.2f} GiB, "
           f"fine DOFs {n0}", file=sys.stderr, flush=True)
     learned_info = train_learned(P, n0) if learned else None
@@ -552,7 +552,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
               f"{json.dumps({kk: round(v, 3) for kk, v in tm.items()})}", file=sys.stderr, flush=True)
     its, rel, ok, tm = results[-1]
     vc_gdofs = n0 * tm["vcycles"] / (tm["vcycle_ms"] / 1e3) / 1e9 if tm["vcycle_ms"] > 0 else None
-    rec = {"precision": precision, "learned": learned, "time_to_1e8_ms": round(dt * 1e3, 3),
+    rec = {"precision": precision, "learned": learned, "vcycle_copy": copy, "time_to_1e8_ms": round(dt * 1e3, 3),
            "gdof_s": round(n0 / dt / 1e9, 6), "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
            "fgmres_its": its, "final_rel_residual": rel, "converged": not failures, "failures": failures,
            "phase_ms": {kk: round(v, 3) for kk, v in tm.items()}, "host_set_data_s": round(t_host, 3)}
@@ -693,17 +693,19 @@ def main():
         largest = {"workload": args.largest, "cells": lmesh.n_cells, "faces": lmesh.n_faces, "k": lspec["k"],
                    "cond": lspec["cond"]}
         lref = None
-        for prec in ("fp64", "fp32", "bf16"):
-            LP, lx, lrec, lroof = run_mode(lmesh, ldata, lspec, args.largest, prec, args, x_ref=lref, probe=True)
-            if prec == "fp64":
+        for form in ("fp64", "fp32", "bf16", "bf16_product"):
+            prec = form.split("_")[0]
+            LP, lx, lrec, lroof = run_mode(lmesh, ldata, lspec, args.largest, prec, args, x_ref=lref, probe=True,
+                                           copy="product" if form.endswith("product") else "convert")
+            if form == "fp64":
                 lref = lx.clone()
                 largest["fine_dofs"] = LP.level_size(0)
                 largest["roofline"] = lroof
             lrec["err_vs_fp64_reference"] = float(torch.linalg.norm(lx - lref) / torch.linalg.norm(lref))
-            largest[prec] = lrec
+            largest[form] = lrec
             del LP, lx
             torch.cuda.empty_cache()
-        for prec in ("fp32", "bf16"):
+        for prec in ("fp32", "bf16", "bf16_product"):
             if largest["fp64"]["converged"] and largest[prec]["converged"]:
                 largest[prec]["speedup_vs_fp64"] = round(largest["fp64"]["time_to_1e8_ms"] /
                                                          largest[prec]["time_to_1e8_ms"], 4)

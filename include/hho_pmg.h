@@ -85,6 +85,12 @@ extern "C" {
 #define HHO_COARSE_AMG    3   /* GMRES to coarse_rtol, block-triangular Stokes preconditioner
                                  with a smoothed-aggregation velocity block (k_L = 0 only)     */
 
+/* how the face blocks of the V-cycle's level-0 copy are formed (FP32/BF16 V-cycles) */
+#define HHO_COPY_CONVERT  0   /* the FP64 operator rounded to the copy's precision */
+#define HHO_COPY_PRODUCT  1   /* each cell's Schur complement formed again from its FP64 factors,
+                                 rounded to bfloat16 and multiplied on the matrix cores with
+                                 FP32 accumulation (couplings and coarser levels: rounded) */
+
 /* smoother preconditioner of the V-cycle's GMRES(smooth_its) steps (Section 3.3) */
 #define HHO_SMOOTHER_SCHWARZ  0   /* cell-patch additive Schwarz (the only one on the GPU) */
 
@@ -138,6 +144,7 @@ typedef struct {
                                   a level takes one step where two would make the next operator too dense) */
   int32_t smoother;    /* HHO_SMOOTHER_* (SCHWARZ) */
   int32_t nullspace;   /* HHO_NULLSPACE_* (AUTO) */
+  int32_t vcycle_copy; /* HHO_COPY_* (CONVERT); PRODUCT needs precision FP32 or BF16 */
 } hho_options;
 
 /* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the

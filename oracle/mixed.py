@@ -20,6 +20,14 @@ This module replays that with NumPy float32 arithmetic:
 
 The V-cycle's steps are those of ``oracle.multilevel.Hierarchy.vcycle``.
 
+``product_copy_block`` gives a cell's face block of the V-cycle copy formed by
+the matrix-core product (not in the paper): the elimination of eq. ST.1 (and
+ST.2) in factored form, Cholesky factor L of the cell block A_TT, W = L^{-1} A_Td,
+and for v&p-cond Y = L^{-1} B_T^T, C = B_d^T - W^T Y, Sigma = the non-mean block
+of Y^T Y with Cholesky factor L_s and Z = L_s^{-1} C~^T; the factors are rounded
+to bfloat16 and the face block is A_dd (rounded to float32) - W^T W (+ Z^T Z for
+v&p-cond), here with exact products and sums of the rounded values.
+
 ``round_bf16`` gives the bfloat16 storage of the 16-bit mode: a bfloat16 number
 is an IEEE binary32 number whose 16 low significand bits are zero, and a float32
 value is stored as the nearest such number, ties to the one whose lowest kept
@@ -122,3 +130,30 @@ class Vcycle32:
 
     def __call__(self, b):
         return self._v(0, np.asarray(b).astype(F32)).astype(np.float64)
+
+
+def product_copy_block(L, cond):
+    """(block, bound): the face block of one cell's Schur complement as the
+    matrix-core product forms it (see the module header), in the vector unknown
+    order (face, component, mode), and |left| |right| summed over the product,
+    the scale of its single-precision accumulation error."""
+    from scipy.linalg import solve_triangular
+    from .hho import vector_system
+    A_TT, A_Td, A_dd, B_T, B_d, _, _, _ = vector_system(L)
+    Lc = np.linalg.cholesky(A_TT)
+    W = solve_triangular(Lc, A_Td, lower=True)
+    Wb = round_bf16(W.astype(F32)).astype(np.float64)
+    base = A_dd.astype(F32).astype(np.float64)
+    block = base - Wb.T @ Wb
+    bound = np.abs(Wb).T @ np.abs(Wb)
+    if cond == "vp":
+        Y = solve_triangular(Lc, B_T.T, lower=True)          # [d nT, nT]
+        C = B_d.T - W.T @ Y                                 # [d m, nT]
+        Sg = Y[:, 1:].T @ Y[:, 1:]
+        Ls = np.linalg.cholesky(Sg)
+        Z = solve_triangular(Ls, C[:, 1:].T, lower=True)     # [nT - 1, d m]
+        Zb = round_bf16(Z.astype(F32)).astype(np.float64)
+        block = block + Zb.T @ Zb
+        bound = bound + np.abs(Zb).T @ np.abs(Zb)
+    return block, bound
+

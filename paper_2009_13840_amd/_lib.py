@@ -23,6 +23,7 @@ PROBE = {"operator": 1, "smoother": 2, "coarse_operator": 4, "outer_operator": 8
          "amg_sweep": 32, "amg_prolong": 64, "amg_dense": 128}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
+COPY = {"convert": 0, "product": 1}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
@@ -56,7 +57,7 @@ class Options(C.Structure):
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_max_it", C.c_int32),
                 ("quad_extra", C.c_int32), ("coarse_amg_sweeps", C.c_int32), ("learned", C.c_int32),
                 ("coarse_amg_explicit", C.c_int32), ("coarse_amg_psmooth", C.c_int32), ("smoother", C.c_int32),
-                ("nullspace", C.c_int32)]
+                ("nullspace", C.c_int32), ("vcycle_copy", C.c_int32)]
 
 
 FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -219,6 +220,8 @@ def options(**kw) -> Options:
             v = PREC[v] if isinstance(v, str) else v
         if k == "coarse_mode":
             v = COARSE[v] if isinstance(v, str) else v
+        if k == "vcycle_copy":
+            v = COPY[v] if isinstance(v, str) else v
         setattr(o, k, v)
     return o
 

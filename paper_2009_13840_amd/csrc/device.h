@@ -57,9 +57,15 @@ struct DLevel {
 // ---- setup kernels (FP64)
 size_t condense_lds_bytes(int d, int cond, int nT, int nF, int max_faces);
 size_t patch_lds_bytes(int d, int cond, int p, int t, int max_faces);
+// stage32 (may be null): the V-cycle copy's face blocks formed by the matrix-core
+// bfloat16 product (FP32, laid out as stage)
 void launch_condense(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
                      double *stage, double *cpl, double *spp, double *rhs_stage, double *rhs_p, int *err,
-                     hipStream_t s, size_t lds);
+                     hipStream_t s, size_t lds, float *stage32 = nullptr);
+// face blocks of the V-cycle copy from stage32 (sum of <= 2 cell blocks in FP32)
+template <typename Tout>
+void launch_assemble32(const DTopo &tp, int cond, int nF, int64_t nnzb, const float *stage32, Tout *bsr,
+                       hipStream_t s);
 // Cell unknowns from the solved globally coupled ones x (level-0 layout):
 // cu [nc][d*nT] velocities (component-major), cp [nc][nT] full pressures.
 size_t recover_lds_bytes(int d, int nT, int nF, int max_faces);

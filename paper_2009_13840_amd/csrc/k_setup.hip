@@ -12,6 +12,78 @@
 namespace hho {
 namespace {
 
+// ------------------------------------------------------------ V-cycle copy by a matrix-core product
+typedef short v4bf __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+
+__device__ inline short bf16_bits(double v) { return (short)to_bf16((float)v).bits; }
+
+// The face-block Schur complement of one cell formed a second time, for the
+// V-cycle's single-precision copy only: the FP64 factors already in LDS are
+// rounded to bfloat16 and multiplied on the matrix cores (16x16x16 bfloat16
+// products, FP32 accumulation); the outer operator keeps the FP64 product.
+//   v-cond:   out = a_dd - W^T W                                   (m x m, K = nT)
+//   v&p-cond: out = [c = c'] a_dd - sum_c [c = c'] W^T W + Z^T Z   (dm x dm)
+// For v&p-cond one product runs over K = n1 + d nT: the n1 rows of Z, then the
+// nT rows of W once per component, that part with a minus sign on the right
+// factor and zero where the row's or column's component differs.  W[t][i] is
+// W[t * ldw + i] (i a face unknown of one component), Z[t][row] is Z[t * dm + row].
+// Wave w of the block takes the 16 x 16 output tiles w, w + nw, ...; out is the
+// cell's n x n block, row-major.
+__device__ void schur_product_bf16(int cond, int d, int nT, int nF, int nfc, const double *a, int nloc,
+                                   const double *W, int ldw, const double *Z, int n1, float *out) {
+  const int m = nfc * nF, dm = d * m;
+  const int n = (cond == 1) ? m : dm;
+  const int K = (cond == 1) ? nT : n1 + d * nT;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+  const int nt = (n + 15) / 16, kt = (K + 15) / 16;
+  // entry (row, k) of the left factor and (k, col) of the right one
+  auto left = [&](int row, int k) -> double {
+    if (cond == 1) return W[k * ldw + row];
+    if (k < n1) return Z[k * dm + row];
+    const int kk = k - n1, c = kk / nT, t = kk % nT;
+    if ((row / nF) % d != c) return 0.0;
+    return W[t * ldw + (row / (d * nF)) * nF + row % nF];
+  };
+  auto right = [&](int k, int col) -> double {
+    if (cond == 1) return W[k * ldw + col];
+    if (k < n1) return Z[k * dm + col];
+    const int kk = k - n1, c = kk / nT, t = kk % nT;
+    if ((col / nF) % d != c) return 0.0;
+    return -W[t * ldw + (col / (d * nF)) * nF + col % nF];
+  };
+  for (int tile = wave; tile < nt * nt; tile += nw) {  // uniform over the wave: every lane takes part
+    const int ti = tile / nt, tj = tile % nt;
+    const int r = ti * 16 + lane % 16, c = tj * 16 + lane % 16;
+    v4f32 acc = {0.f, 0.f, 0.f, 0.f};
+    for (int kb = 0; kb < kt; ++kb) {
+      v4bf af, bf;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = kb * 16 + 4 * (lane / 16) + v;
+        af[v] = (r < n && k < K) ? bf16_bits(left(r, k)) : (short)0;
+        bf[v] = (c < n && k < K) ? bf16_bits(right(k, c)) : (short)0;
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(af, bf, acc, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = ti * 16 + 4 * (lane / 16) + v, col = c;
+      if (row >= n || col >= n) continue;
+      float base;
+      if (cond == 1) {
+        base = (float)a[(int64_t)(nT + row) * nloc + nT + col];
+      } else {
+        const int ci = (row / nF) % d, cj = (col / nF) % d;
+        const int i = (row / (d * nF)) * nF + row % nF, j = (col / (d * nF)) * nF + col % nF;
+        base = (ci == cj) ? (float)a[(int64_t)(nT + i) * nloc + nT + j] : 0.f;
+      }
+      // v-cond: the product is W^T W, subtracted; v&p: signs are in the factors
+      out[(int64_t)row * n + col] = (cond == 1) ? base - acc[v] : base + acc[v];
+    }
+  }
+}
+
 // ------------------------------------------------------------ static condensation
 // One block per cell.  Record of the cell (host-built, eq. def:HHOAB):
 //   a [nloc][nloc] scalar viscous matrix (cell modes first, then faces),
@@ -27,7 +99,8 @@ namespace {
 // the mean pressure is C[:,0].
 __global__ void __launch_bounds__(kBlock) k_condense(DTopo tp, int cond, int nT, int nF, const double *rec,
                                                      const int64_t *roff, double *stage, double *cpl,
-                                                     double *spp, double *rhs_stage, double *rhs_p, int *err) {
+                                                     double *spp, double *rhs_stage, double *rhs_p, int *err,
+                                                     float *stage32) {
   extern __shared__ double lds[];
   const int T = blockIdx.x;
   const int d = tp.d;
@@ -101,6 +174,9 @@ __global__ void __launch_bounds__(kBlock) k_condense(DTopo tp, int cond, int nT,
         for (int t = 0; t < nT; ++t) v -= Y[(c * nT + t) * nT + q] * G[c * nT + t];
       rhs_p[(int64_t)T * nT + q] = v;
     }
+    if (stage32)
+      schur_product_bf16(cond, d, nT, nF, nfc, a, nloc, W, nloc, nullptr, 0,
+                         stage32 + tp.pairoff[T] * nF * nF);
   } else {
     // ext: Ct [nT][d*m] (C transposed), Sg [(nT-1)^2], rP [nT], h [nT-1]
     const int dm = d * m, n1 = nT - 1;
@@ -167,6 +243,9 @@ __global__ void __launch_bounds__(kBlock) k_condense(DTopo tp, int cond, int nT,
       rs[row] = v;
     }
     if (threadIdx.x == 0) rhs_p[T] = rP[0];
+    if (stage32)
+      schur_product_bf16(cond, d, nT, nF, nfc, a, nloc, W, nloc, Z, n1,
+                         stage32 + tp.pairoff[T] * (int64_t)(d * nF) * (d * nF));
   }
   __syncthreads();
   if (threadIdx.x == 0 && bad) atomicMax(err, T + 1);
@@ -302,6 +381,30 @@ __global__ void k_assemble(DTopo tp, int cond, int nF, int64_t nnzb, const doubl
       v += S[(i * bs + rr) * dim + j * bs + cc];
     }
     bsr[e] = v;
+  }
+}
+
+// The same gather for the V-cycle's copy: FP32 cell blocks summed in FP32 and
+// stored as Tout (float or bf16).
+template <typename Tout>
+__global__ void k_assemble32(DTopo tp, int cond, int nF, int64_t nnzb, const float *stage, Tout *bsr) {
+  const int d = tp.d;
+  const int bs = (cond == 1) ? nF : d * nF;
+  const int64_t total = nnzb * bs * bs;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t b = e / (bs * bs);
+    const int rr = (int)(e % (bs * bs)) / bs, cc = (int)(e % bs);
+    float v = 0;
+    for (int s = 0; s < 2; ++s) {
+      const int T = tp.blksrc[6 * b + 3 * s];
+      if (T < 0) continue;
+      const int i = tp.blksrc[6 * b + 3 * s + 1], j = tp.blksrc[6 * b + 3 * s + 2];
+      const int nfc = tp.cptr[T + 1] - tp.cptr[T];
+      const int64_t dim = (int64_t)nfc * bs;
+      const float *S = stage + tp.pairoff[T] * bs * bs;
+      v += S[(i * bs + rr) * dim + j * bs + cc];
+    }
+    bsr[e] = StoreAs<Tout>::from(v);
   }
 }
 
@@ -956,10 +1059,19 @@ size_t patch_lds_bytes(int d, int cond, int p, int t, int max_faces) {
 
 void launch_condense(const DTopo &tp, int cond, int nT, int nF, const double *rec, const int64_t *roff,
                      double *stage, double *cpl, double *spp, double *rhs_stage, double *rhs_p, int *err,
-                     hipStream_t s, size_t lds) {
+                     hipStream_t s, size_t lds, float *stage32) {
   hipLaunchKernelGGL(k_condense, dim3(tp.nc), dim3(kBlock), lds, s, tp, cond, nT, nF, rec, roff, stage, cpl, spp,
-                     rhs_stage, rhs_p, err);
+                     rhs_stage, rhs_p, err, stage32);
 }
+template <typename Tout>
+void launch_assemble32(const DTopo &tp, int cond, int nF, int64_t nnzb, const float *stage32, Tout *bsr,
+                       hipStream_t s) {
+  const int bs = (cond == 1) ? nF : tp.d * nF;
+  hipLaunchKernelGGL((k_assemble32<Tout>), dim3(grid_for(nnzb * bs * bs)), dim3(kBlock), 0, s, tp, cond, nF, nnzb,
+                     stage32, bsr);
+}
+template void launch_assemble32<float>(const DTopo &, int, int, int64_t, const float *, float *, hipStream_t);
+template void launch_assemble32<bf16>(const DTopo &, int, int, int64_t, const float *, bf16 *, hipStream_t);
 size_t recover_lds_bytes(int d, int nT, int nF, int max_faces) {
   const int m = max_faces * nF;
   const size_t n = (size_t)nT * nT + (size_t)d * m + (size_t)d * nT + nT + (size_t)d * nT * nT +

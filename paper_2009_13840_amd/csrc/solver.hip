@@ -94,6 +94,7 @@ struct hho_problem {
   double *rec = nullptr;
   int64_t *roff = nullptr;
   double *stage = nullptr, *rhs_stage = nullptr, *rhs = nullptr, *zvec = nullptr;
+  float *stage32 = nullptr;  // V-cycle copy's cell blocks by the matrix-core product (HHO_COPY_PRODUCT)
   double *dense = nullptr, *colbuf = nullptr;
   // outer FGMRES (FP64, level 0) and coarse GMRES (FP64, level L)
   double *oV = nullptr, *oZ = nullptr, *ow = nullptr, *ox = nullptr, *or_ = nullptr, *ob = nullptr;
@@ -175,6 +176,7 @@ static void plan(hho_problem *P, Arena &A) {
   P->roff = A.take<int64_t>(nc + 1);
   const LevelInfo &L0 = P->lev[0];
   P->stage = A.take<double>(P->pairoff[nc] * L0.bs * L0.bs);
+  P->stage32 = P->opt.vcycle_copy == HHO_COPY_PRODUCT ? A.take<float>(P->pairoff[nc] * L0.bs * L0.bs) : nullptr;
   P->rhs_stage = A.take<double>(P->ncf * d * L0.p);
   P->rhs = A.take<double>(L0.N);
   P->zvec = A.take<double>(L0.N);
@@ -657,7 +659,7 @@ static void device_setup(hho_problem *P) {
   LevelInfo &L0 = P->lev[0];
   // static condensation
   launch_condense(P->tp, P->cond, P->loc.nT, P->loc.nF, P->rec, P->roff, P->stage, L0.cpl, L0.spp, P->rhs_stage,
-                  P->rhs + L0.nface, P->err, s, P->lds_condense);
+                  P->rhs + L0.nface, P->err, s, P->lds_condense, P->stage32);
   HIPCHK(hipEventRecord(ev[1], s));
   // assembly
   launch_assemble(P->tp, P->cond, L0.p, P->nnzb, P->stage, L0.bsr, P->rhs_stage, P->rhs, s);
@@ -702,12 +704,19 @@ static void device_setup(hho_problem *P) {
       const int64_t nspp = P->cond == HHO_COND_V ? nc * L.t * L.t : 1;
       const int64_t nsinv = P->pairoff[nc] * L.bs * L.bs;
       const int64_t nxinv = P->cond == HHO_COND_V ? nc * L.t * L.t : P->ncf * d * L.p;
+      const bool product = l == 0 && P->stage32;  // level-0 face blocks by the matrix-core product
       if (P->opt.precision == HHO_PREC_BF16) {
-        launch_convert<bf16, double>(L.bsr, L.bsr16, nbsr, s);
+        if (product)
+          launch_assemble32<bf16>(P->tp, P->cond, L.p, P->nnzb, P->stage32, L.bsr16, s);
+        else
+          launch_convert<bf16, double>(L.bsr, L.bsr16, nbsr, s);
         launch_convert<bf16, double>(L.cpl, L.cpl16, ncpl, s);
         if (P->cond == HHO_COND_V) launch_convert<bf16, double>(L.spp, L.spp16, nspp, s);
       } else {
-        launch_convert<float, double>(L.bsr, L.bsr32, nbsr, s);
+        if (product)
+          launch_assemble32<float>(P->tp, P->cond, L.p, P->nnzb, P->stage32, L.bsr32, s);
+        else
+          launch_convert<float, double>(L.bsr, L.bsr32, nbsr, s);
         launch_convert<float, double>(L.cpl, L.cpl32, ncpl, s);
         if (P->cond == HHO_COND_V) launch_convert<float, double>(L.spp, L.spp32, nspp, s);
       }
@@ -1180,6 +1189,7 @@ void hho_options_default(hho_options *o) {
   o->coarse_amg_psmooth = 1;
   o->smoother = HHO_SMOOTHER_SCHWARZ;
   o->nullspace = HHO_NULLSPACE_AUTO;
+  o->vcycle_copy = HHO_COPY_CONVERT;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -1239,6 +1249,10 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.smoother != HHO_SMOOTHER_SCHWARZ) hho::fail(HHO_E_INVALID_ARG, "smoother: only HHO_SMOOTHER_SCHWARZ");
   if (P->opt.nullspace != HHO_NULLSPACE_AUTO && P->opt.nullspace != HHO_NULLSPACE_NONE)
     hho::fail(HHO_E_INVALID_ARG, "nullspace must be HHO_NULLSPACE_AUTO or HHO_NULLSPACE_NONE");
+  if (P->opt.vcycle_copy != HHO_COPY_CONVERT && P->opt.vcycle_copy != HHO_COPY_PRODUCT)
+    hho::fail(HHO_E_INVALID_ARG, "vcycle_copy must be HHO_COPY_CONVERT or HHO_COPY_PRODUCT");
+  if (P->opt.vcycle_copy == HHO_COPY_PRODUCT && (P->opt.precision == HHO_PREC_FP64 || P->deg.size() < 2))
+    hho::fail(HHO_E_INVALID_ARG, "vcycle_copy PRODUCT needs an FP32 or BF16 V-cycle with at least two levels");
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
   if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol >= 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
   const int d = P->d;

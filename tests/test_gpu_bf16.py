@@ -117,3 +117,93 @@ def test_bf16_fgmres_reaches_the_direct_solution(built, name, mk, k, cond):
     ef = np.linalg.norm(x[:nf] - xd[:nf]) / np.linalg.norm(xd[:nf])
     print(f"[bf16 fgmres] {name}: its {its}, rel {rel:.2e}, face error vs direct {ef:.2e}")
     assert ef <= 1e-9
+
+
+PRODUCT_CASES = [CASES[0], CASES[1], CASES[2]]
+
+
+@pytest.mark.parametrize("name,mk,k,cond", PRODUCT_CASES)
+def test_product_copy_operator_matches_oracle_definition(name, mk, k, cond):
+    """Level-0 operator of the V-cycle copy formed by the matrix-core product
+    (options.vcycle_copy = PRODUCT, FP32 storage): its face blocks against the
+    oracle's definition (oracle.mixed.product_copy_block: FP64 factors rounded to
+    bfloat16, exact products), its couplings against the FP64 operator rounded
+    to float32.  Entry by entry the difference is the FP32 accumulation of the
+    cell products (at most 1e-5 of their |left||right| sums) and of the
+    application (1e-5 of |S| |x|)."""
+    import torch
+    import scipy.sparse as sp
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    from oracle.mixed import product_copy_block
+    from oracle.system import assemble_condensed
+    from oracle.condense import condense_v, condense_vp
+    mesh = mk()
+    data = problem_data(polynomial_stokes(mesh.dim, k + 1, 3), None, mesh.dim)
+    print(f"[case] product copy {name}", flush=True)
+    P = H.Problem(H.Mesh(mesh), k, cond, precision="fp32", vcycle_copy="product", coarse_mode="dense",
+                  rtol=1e-10)
+    P.set_data(*data)
+    P.bind("cuda:0")
+    P.setup()
+    O = OS.build(mesh, k, cond, data, eta=None)
+    d, nF, nP = mesh.dim, O.lays[0].nF, O.lays[0].nP
+    cfun = condense_v if cond == "v" else condense_vp
+    face_blocks, bound_blocks, rest_blocks = [], [], []
+    for L in O.locs:
+        S, r = cfun(L)
+        n = L.nfaces * d * nF
+        blk, bnd = product_copy_block(L, cond)
+        F = np.zeros_like(S)
+        F[:n, :n] = blk
+        Bd = np.zeros_like(S)
+        Bd[:n, :n] = bnd
+        R = S.copy()
+        R[:n, :n] = 0.0
+        face_blocks.append((F, r))
+        bound_blocks.append((Bd, r))
+        rest_blocks.append((R, r))
+    Sf = assemble_condensed(mesh, face_blocks, d, nF, nP)[0]
+    Sb = assemble_condensed(mesh, bound_blocks, d, nF, nP)[0]
+    Sr = assemble_condensed(mesh, rest_blocks, d, nF, nP)[0]
+    S_emul = (Sf + Sr).tocsr()
+    S_emul.data = S_emul.data.astype(np.float32).astype(np.float64)
+    rng = np.random.default_rng(41)
+    x = rng.standard_normal(S_emul.shape[0])
+    x32 = x.astype(np.float32).astype(np.float64)
+    want = S_emul @ x32
+    bound = 1e-5 * (abs(S_emul) @ np.abs(x32)) + 1e-5 * (abs(Sb) @ np.abs(x32))
+    got = P.vcycle_level_apply(0, torch.from_numpy(x).cuda()).cpu().numpy()
+    err = np.abs(got - want)
+    print(f"[product copy] {name}: max err / bound {(err / np.maximum(bound, 1e-300)).max():.2e}")
+    assert np.all(err <= bound)
+    # the copy is really the product one: it differs from the FP32-rounded FP64 operator
+    S32 = O.S[0].copy()
+    S32.data = S32.data.astype(np.float32).astype(np.float64)
+    assert np.abs(got - S32 @ x32).max() > 1e-4 * np.abs(want).max()
+    # and FGMRES preconditioned by it reaches the direct solution
+    P.set_tolerances(1e-12)
+    xs, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-12
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    nfv = O.lays[0].off
+    assert np.linalg.norm(xs.cpu().numpy()[:nfv] - xd[:nfv]) <= 1e-9 * np.linalg.norm(xd[:nfv])
+
+
+def test_product_copy_with_bf16_storage_converges():
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    mesh = cartesian_hexes(2)
+    k, cond = 3, "vp"
+    data = problem_data(polynomial_stokes(3, k + 1, 3), None, 3)
+    print("[case] product copy, bf16 storage, hex2 k=3 vp", flush=True)
+    P = H.Problem(H.Mesh(mesh), k, cond, precision="bf16", vcycle_copy="product", coarse_mode="dense", rtol=1e-12)
+    P.set_data(*data)
+    P.bind("cuda:0")
+    P.setup()
+    xs, its, hist, rel, ok = P.solve()
+    assert ok and rel <= 1e-12
+    O = OS.build(mesh, k, cond, data, eta=None)
+    xd = OS.normalise_pressure(O, OS.solve_direct(O))
+    nfv = O.lays[0].off
+    assert np.linalg.norm(xs.cpu().numpy()[:nfv] - xd[:nfv]) <= 1e-9 * np.linalg.norm(xd[:nfv])

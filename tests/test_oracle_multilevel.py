@@ -377,3 +377,33 @@ def test_bfloat16_rounding_definition():
     best = np.where(d_lo < d_hi, lo, hi)
     ties = d_lo == d_hi
     assert np.array_equal(r[~ties].astype(np.float64), best[~ties])
+
+
+def test_product_copy_block_is_the_schur_complement_up_to_rounding():
+    """The product copy's face block, with the bfloat16 rounding removed, is the
+    face block of the Schur complement of eqs. ST.1 / ST.2 (checked against the
+    oracle's dense-solve condensation), and with it differs by at most the
+    rounding of its factors."""
+    import numpy as np
+    from unittest import mock
+    import oracle.mixed as MX
+    import oracle.solve as OS
+    from oracle.condense import condense_v, condense_vp
+    from synth import voronoi_lloyd, cartesian_hexes, polynomial_stokes
+    from synth.fields import problem_data
+    for mesh, k in ((voronoi_lloyd(12, 2), 2), (cartesian_hexes(1), 2)):
+        data = problem_data(polynomial_stokes(mesh.dim, k + 1, 1), None, mesh.dim)
+        P = OS.build(mesh, k, "v", data)
+        for cond, cfun in (("v", condense_v), ("vp", condense_vp)):
+            for L in P.locs[:4]:
+                S = cfun(L)[0]
+                n = L.nfaces * L.d * L.nF
+                exact = S[:n, :n]
+                with mock.patch.object(MX, "round_bf16", lambda a: np.asarray(a, dtype=np.float64)), \
+                        mock.patch.object(MX, "F32", np.float64):
+                    blk, _ = MX.product_copy_block(L, cond)
+                assert np.abs(blk - exact).max() <= 1e-11 * np.abs(exact).max()
+                blk16, bound = MX.product_copy_block(L, cond)
+                err = np.abs(blk16 - exact)
+                assert err.max() > 0
+                assert np.all(err <= 2.0 ** -7 * (bound + np.abs(exact)) + 1e-12 * np.abs(exact).max())
