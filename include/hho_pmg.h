@@ -416,7 +416,8 @@ int hho_batch_solve(hho_batch *b, double *face_out, const int64_t *face_off, dou
 /* ---- learned fine-level smoother (not in the paper) ----
  * Needs a problem created with options.learned = 1 and a bound workspace.
  * Per face F of level 0 a network maps a window of the residual r to a
- * correction of F's d*n_F velocity unknowns:
+ * correction of F's d*n_F velocity unknowns and of the n_P pressure unknowns of
+ * each of F's cells:
  *   window: for the cells T_0 < T_1 of F (T_1 absent on the boundary), the
  *     residual blocks of T_s's faces in its face order, zero padded to Fm (the
  *     largest card(F_T) of the mesh), then T_s's pressure residual; then one-hots
@@ -424,8 +425,14 @@ int hho_batch_solve(hho_batch *b, double *face_out, const int64_t *face_off, dou
  *     n_in = 2 (Fm d n_F + n_P) + 2 Fm entries;
  *   scale s_F = root mean square of the residual part (over 2 (Fm d n_F + n_P)
  *     entries), which is divided by s_F;
- *   h = relu(W1 x + b1) (64 units), y = W2 h + b2 (n_out = d n_F), correction s_F y.
- * Parameters are FP32, flat: [W1 (64 x n_in, row-major) | b1 | W2 (n_out x 64) | b2].
+ *   h = relu(W1 x + b1) (64 units), y = W2 h + b2 (n_out = d n_F + 2 n_P);
+ *   correction: s_F y[0 .. d n_F) on F's velocity unknowns; each cell T takes
+ *     the mean over its faces F of s_F y[d n_F + side n_P ..] (side = T's
+ *     position in F's cell pair) on its pressure unknowns.
+ * The products run on bfloat16 x, W1, h and W2 (rounded to nearest even) with
+ * FP32 sums on the matrix cores; biases, outputs and the master parameters are
+ * FP32: [W1 (64 x n_in, row-major) | b1 | W2 (n_out x 64) | b2].  Gradients are
+ * those of this network with the roundings taken as the identity.
  * When enabled, every level-0 smoothing step minimises the residual over the
  * Schwarz directions plus this correction, so its residual never exceeds the
  * plain step's: the plain smoother is both the fallback and the yardstick. */
@@ -457,8 +464,9 @@ int hho_learned_apply(hho_problem *p, const double *r_dev, double *z_dev);
 
 /* Training pairs from the plain V-cycle: with b = S_0 x_true and x = 0, for
  * each of `cycles` iterations the windows of r = b - S_0 x and the targets
- * (x_true - x)_F / s_F of every face are written (rows cycle*n_faces + F of
- * X [cap x n_in] and T [cap x n_out], device FP32), then x += MG_V(r).
+ * ((x_true - x) on F, on T_0, on T_1) / s_F of every face (0 for an absent T_1)
+ * are written (rows cycle*n_faces + F of X [cap x n_in] and T [cap x n_out],
+ * device FP32), then x += MG_V(r).
  * *n_out = cycles * n_faces; HHO_E_CAPACITY if cap is smaller. */
 int hho_learned_collect(hho_problem *p, const double *x_true_dev, int cycles, float *X_dev, float *T_dev,
                         int64_t cap, int64_t *n_out);
@@ -473,9 +481,9 @@ int hho_learned_grad(hho_problem *p, const float *X_dev, const float *T_dev, int
  * as hho_learned_grad, with the same kernels in the same order (so the results
  * are identical), but the work arrays -- hidden activations and outputs of the
  * batch and their gradients, the parameter gradient, the loss partial sums --
- * live in a fixed device array of the library (about 10 MiB per device, held
+ * live in a fixed device array of the library (about 14 MiB per device, held
  * until the process ends) instead of the problem's workspace.  The call itself
- * allocates nothing.  Limits: 1 <= n <= 4096 rows, n_out <= 128 outputs,
+ * allocates nothing.  Limits: 1 <= n <= 4096 rows, n_out <= 256 outputs,
  * n_params <= 2^20; beyond them it returns HHO_E_CAPACITY.  The device of the
  * problem's workspace must be current (HHO_E_INVALID_ARG otherwise).  Every
  * call on one device shares that array: calls that overlap on one device (other

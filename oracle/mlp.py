@@ -15,13 +15,23 @@ residual r to a correction of F's velocity unknowns:
 * scale: s_F = sqrt(mean of the squared residual entries of the window, the
   zero padding included, i.e. over 2 (Fm d p + t) entries); the residual part
   is divided by s_F, the one-hot part is not;
-* network: h = relu(W1 x + b1) (64 hidden units), y = W2 h + b2 (d p outputs);
-* correction: delta_F = s_F y (0 when s_F = 0); cell unknowns get no correction.
+* network: h = relu(W1 x + b1) (64 hidden units), y = W2 h + b2 with
+  d p + 2 t outputs: the correction of F's velocity unknowns, then of the
+  pressure unknowns of T_0 and of T_1 (the pressure head);
+* correction: delta_F = s_F y[:d p] (0 when s_F = 0); every cell T takes the
+  mean over its faces F of s_F y_F[d p + side t : d p + (side + 1) t], side the
+  position of T in F's cell pair.
+* precision: the network runs on bfloat16 weights and activations with sums
+  kept exact here (FP32 on the GPU): x, W1, W2 and h are rounded to bfloat16
+  (``round_bf16`` of oracle.mixed, from float32), biases and outputs are not;
+  the gradients are those of this network with each rounding taken as the
+  identity.  ``quantize=False`` gives the unrounded FP64 network.
 
 Training data are pairs (window of r, e_F / s_F) with e the error of the
-current iterate; the loss is 1/(2B) sum_i |y_i - t_i|^2 over a batch of B
-samples; parameters are updated with Adam (Kingma & Ba 2015: beta1 = 0.9,
-beta2 = 0.999, eps = 1e-8, bias-corrected moments).
+current iterate (its velocity block on F, then its pressure blocks on T_0 and
+T_1, 0 for an absent T_1); the loss is 1/(2B) sum_i |y_i - t_i|^2 over a batch of
+B samples; parameters are updated with Adam (Kingma & Ba 2015: beta1 = 0.9,
+beta2 = 0.999, eps = 1e-8, bias-corrected moments) on FP32 master values.
 
 Inside the V-cycle the correction is one more search direction of the
 fine-level smoothing step: the step minimises the residual over
@@ -55,6 +65,10 @@ class Layout:
     @property
     def n_in(self):
         return self.n_res + 2 * self.Fm
+
+    @property
+    def n_out(self):
+        return self.dp + 2 * self.t
 
 
 def layout(mesh, d: int, p: int, t: int) -> Layout:
@@ -95,23 +109,32 @@ def init_params(n_in: int, n_out: int, u1: np.ndarray, u2: np.ndarray):
     return dict(W1=W1, b1=np.zeros(HIDDEN), W2=W2, b2=np.zeros(n_out))
 
 
-def forward(th, X):
-    Z = X @ th["W1"].T + th["b1"]
-    H = np.maximum(Z, 0.0)
-    return H @ th["W2"].T + th["b2"], Z, H
+def _bf(a):
+    from .mixed import round_bf16
+    return round_bf16(np.asarray(a, dtype=np.float32)).astype(np.float64)
 
 
-def loss_and_grad(th, X, T):
-    """Loss 1/(2B) sum |Y - T|^2 and its gradient (backpropagation written out)."""
+def forward(th, X, quantize=True):
+    """Y, Z (pre-activations), H (activations as the second layer reads them)."""
+    q = _bf if quantize else (lambda a: a)
+    Z = q(X) @ q(th["W1"]).T + th["b1"]
+    H = q(np.maximum(Z, 0.0))
+    return H @ q(th["W2"]).T + th["b2"], Z, H
+
+
+def loss_and_grad(th, X, T, quantize=True):
+    """Loss 1/(2B) sum |Y - T|^2 and its gradient (backpropagation written out;
+    the bfloat16 roundings are taken as the identity)."""
+    q = _bf if quantize else (lambda a: a)
     B = X.shape[0]
-    Y, Z, H = forward(th, X)
+    Y, Z, H = forward(th, X, quantize)
     D = Y - T
     loss = 0.5 * np.sum(D * D) / B
     dY = D / B
     gW2 = dY.T @ H
     gb2 = dY.sum(axis=0)
-    dZ = (dY @ th["W2"]) * (Z > 0)
-    gW1 = dZ.T @ X
+    dZ = (dY @ q(th["W2"])) * (Z > 0)
+    gW1 = dZ.T @ q(X)
     gb1 = dZ.sum(axis=0)
     return loss, dict(W1=gW1, b1=gb1, W2=gW2, b2=gb2)
 
@@ -128,13 +151,38 @@ def adam_step(th, g, m, v, step: int, lr: float, b1=0.9, b2=0.999, eps=1e-8):
     return th2, m2, v2
 
 
-def apply(th, mesh, L: Layout, r: np.ndarray) -> np.ndarray:
-    """Level-0 vector: delta_F on every face block, zero cell part."""
+def apply(th, mesh, L: Layout, r: np.ndarray, quantize=True) -> np.ndarray:
+    """Level-0 vector: delta_F on every face block, the mean of the pressure
+    outputs of a cell's faces on its pressure block."""
     X, s = windows(mesh, L, r)
-    Y, _, _ = forward(th, X)
+    Y, _, _ = forward(th, X, quantize)
     z = np.zeros_like(r)
-    z[:L.nface] = (s[:, None] * Y).ravel()
+    z[:L.nface] = (s[:, None] * Y[:, :L.dp]).ravel()
+    fc = mesh.face_cells()
+    for c in range(mesh.n_cells):
+        faces = list(mesh.cell_faces(c))
+        acc = np.zeros(L.t)
+        for f in faces:
+            side = 0 if fc[f, 0] == c else 1
+            acc += s[f] * Y[f, L.dp + side * L.t:L.dp + (side + 1) * L.t]
+        z[L.nface + c * L.t:L.nface + (c + 1) * L.t] = acc / len(faces)
     return z
+
+
+def targets(mesh, L: Layout, e: np.ndarray, s: np.ndarray) -> np.ndarray:
+    """Training targets of every face: (e_F, e_T0, e_T1) / s_F (0 where s_F = 0
+    and for an absent T_1)."""
+    fc = mesh.face_cells()
+    T = np.zeros((mesh.n_faces, L.n_out))
+    for f in range(mesh.n_faces):
+        if s[f] <= 0:
+            continue
+        T[f, :L.dp] = e[f * L.dp:(f + 1) * L.dp] / s[f]
+        for side in range(2):
+            c = fc[f, side]
+            if c >= 0:
+                T[f, L.dp + side * L.t:L.dp + (side + 1) * L.t] = e[L.nface + c * L.t:L.nface + (c + 1) * L.t] / s[f]
+    return T
 
 
 def mr_step(A, dirs, x, r):

@@ -166,25 +166,30 @@ constexpr int kMlpHidden = 64;
 constexpr int kMlpMaxBatch = 4096;
 constexpr int kMlpMaxSteps = 100000;
 struct MlpDims {
-  int d, p, t, Fm, dp, n_res, n_in, n_out;
+  int d, p, t, Fm, dp, n_res, n_in, n_out;  // n_out = d p + 2 t: face velocity, then the two cells' pressures
+  int n_in16, n_out16;                      // n_in, n_out rounded up to multiples of 16 (matrix-core tiles)
   int64_t nface;  // offset of the cell part of a level-0 vector
 };
 int64_t mlp_param_count(const MlpDims &md);
 // window of every face of r -> X [nf][n_in] (FP32, scaled), sc [nf] (scales)
 template <typename T>
 void launch_mlp_windows(const DTopo &tp, const MlpDims &md, const T *r, float *X, float *sc, hipStream_t s);
-// targets (xt - x)_F / s_F -> Tg [nf][dp]
-void launch_mlp_targets(int nf, int dp, const double *xt, const double *x, const float *sc, float *Tg, hipStream_t s);
-// Z (pre-activations, optional) and Y of the rows of X (rows == null: rows 0..n-1)
-void launch_mlp_forward(int n, int n_in, int n_out, const float *X, const int *rows, const float *prm, float *Z,
-                        float *Y, hipStream_t s);
-// z = s_F y_F on face blocks, 0 on cells
+// targets (xt - x) on F, T_0, T_1, divided by s_F -> Tg [nf][n_out]
+void launch_mlp_targets(const DTopo &tp, const MlpDims &md, const double *xt, const double *x, const float *sc,
+                        float *Tg, hipStream_t s);
+// bfloat16 copies W1b [64][n_in16], W2b [n_out16][64] of the FP32 parameters
+void launch_mlp_pack(const MlpDims &md, const float *prm, uint16_t *W1b, uint16_t *W2b, hipStream_t s);
+// Z (pre-activations, optional) and Y of the rows of X (rows == null: rows 0..n-1), on the matrix cores
+void launch_mlp_forward(int n, const MlpDims &md, const float *X, const int *rows, const float *prm,
+                        const uint16_t *W1b, const uint16_t *W2b, float *Z, float *Y, hipStream_t s);
+// z = s_F y_F[:dp] on face blocks; cells: mean over their faces of the pressure outputs
 template <typename T>
-void launch_mlp_scatter(int64_t nface, int64_t N, int dp, const float *Y, const float *sc, T *z, hipStream_t s);
-// gradient g of 1/(2B) sum |Y - T|^2; returns the number of loss partials written
-int launch_mlp_backward(int B, int n_in, int n_out, const float *X, const int *rows, const float *Tg, const float *prm,
-                        const float *Z, const float *Y, float *dY, float *dZ, float *g, double *partial,
+void launch_mlp_scatter(const DTopo &tp, const MlpDims &md, int64_t N, const float *Y, const float *sc, T *z,
                         hipStream_t s);
+// gradient g of 1/(2B) sum |Y - T|^2; returns the number of loss partials written
+int launch_mlp_backward(int B, int n_in, int n_out, const float *X, const int *rows, const float *Tg,
+                        const uint16_t *W2b, const float *Z, const float *Y, float *dY, float *dZ, float *g,
+                        double *partial, hipStream_t s);
 void launch_mlp_adam(int64_t n, float *prm, const float *g, float *m, float *v, float lr, int step, hipStream_t s);
 void launch_mlp_rows(int B, int64_t n, uint64_t seed, int step, int *rows, hipStream_t s);
 // minimal residual over {z1, z2 (if m == 2), z3}: x += Z y, r -= W y

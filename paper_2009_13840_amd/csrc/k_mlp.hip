@@ -1,15 +1,19 @@
 // Learned fine-level smoother (not in the paper): a two-layer network per face
 // block maps a window of the residual to a correction of the face's velocity
-// unknowns; it enters the smoothing step as one more search direction of the
-// minimal-residual update, next to the Schwarz directions.
+// unknowns and of the pressure unknowns of its two cells (a cell takes the mean
+// of its faces' predictions); it enters the smoothing step as one more search
+// direction of the minimal-residual update, next to the Schwarz directions.
 //
 // Window of face F (n_in entries): for each side s of F (cells T_0 < T_1) the
 // residual blocks of T_s's faces in the cell's face order, zero padded to Fm
 // faces, then T_s's pressure residual; then a one-hot of F's position in T_0's
 // and in T_1's face list.  The residual part is divided by its root mean square
 // s_F (over 2 (Fm d p + t) entries) and the output is multiplied by s_F.
-// Network: h = relu(W1 x + b1) (64 units), y = W2 h + b2 (d p outputs).
-// Parameters are FP32 [W1 | b1 | W2 | b2]; all products accumulate in FP32.
+// Network: h = relu(W1 x + b1) (64 units), y = W2 h + b2 (d p + 2 t outputs),
+// run on bfloat16 x, W1, h, W2 (rounded to nearest even) with FP32 sums on the
+// matrix cores; biases and outputs FP32.  Master parameters are FP32
+// [W1 | b1 | W2 | b2] (Adam updates them); their bfloat16 copies W1b [64][n_in16]
+// and W2b [n_out16][64] (zero padded to multiples of 16) feed the products.
 #include <algorithm>
 
 #include "dev_common.h"
@@ -18,8 +22,6 @@
 namespace hho {
 namespace {
 
-constexpr int kRows = 32;   // samples per forward tile
-constexpr int kChunk = 64;  // K chunk of the first layer
 
 // one wavefront per face: gathers the window, its scale, and writes the scaled row
 template <typename T>
@@ -64,81 +66,138 @@ __global__ void __launch_bounds__(kWave) k_mlp_windows(DTopo tp, MlpDims md, con
   if (lane == 0) sc[f] = (float)s;
 }
 
-// targets e_F / s_F (0 when s_F = 0)
-__global__ void k_mlp_targets(int nf, int dp, const double *xt, const double *x, const float *sc, float *Tg) {
-  const int64_t n = (int64_t)nf * dp;
+// targets (e_F, e_T0, e_T1) / s_F, e = xt - x (0 when s_F = 0 and for an absent T1)
+__global__ void k_mlp_targets(DTopo tp, MlpDims md, const double *xt, const double *x, const float *sc, float *Tg) {
+  const int64_t n = (int64_t)tp.nf * md.n_out;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float s = sc[i / dp];
-    Tg[i] = s > 0 ? (float)((xt[i] - x[i]) / (double)s) : 0.0f;
+    const int f = (int)(i / md.n_out), o = (int)(i % md.n_out);
+    const float s = sc[f];
+    int64_t src = -1;
+    if (o < md.dp) {
+      src = (int64_t)f * md.dp + o;
+    } else {
+      const int side = (o - md.dp) / md.t, q = (o - md.dp) % md.t;
+      const int c = tp.fcell[2 * f + side];
+      if (c >= 0) src = md.nface + (int64_t)c * md.t + q;
+    }
+    Tg[i] = (s > 0 && src >= 0) ? (float)((xt[src] - x[src]) / (double)s) : 0.0f;
   }
 }
 
-// Z = X W1^T + b1, H = relu(Z), Y = H W2^T + b2 for kRows rows per block.
-// rows (optional) maps the tile's row i to the row of X it reads.
-__global__ void __launch_bounds__(256) k_mlp_forward(int n, int n_in, int n_out, const float *__restrict__ X,
-                                                      const int *__restrict__ rows, const float *__restrict__ prm,
-                                                      float *__restrict__ Zout, float *__restrict__ Y) {
-  __shared__ float Xs[kRows][kChunk + 1];
-  __shared__ float Ws[kMlpHidden][kChunk + 1];
-  __shared__ float Hs[kRows][kMlpHidden + 1];
-  const float *W1 = prm, *b1 = W1 + (int64_t)kMlpHidden * n_in, *W2 = b1 + kMlpHidden, *b2 = W2 + n_out * kMlpHidden;
-  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;  // hidden 4tx..4tx+3, rows 2ty, 2ty+1
-  const int r0 = blockIdx.x * kRows;
-  float acc[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  for (int k0 = 0; k0 < n_in; k0 += kChunk) {
-    for (int idx = tid; idx < kRows * kChunk; idx += blockDim.x) {
-      const int i = idx / kChunk, k = idx % kChunk;
-      const int gi = r0 + i;
-      float v = 0;
-      if (gi < n && k0 + k < n_in) {
-        const int64_t src = rows ? rows[gi] : gi;
-        v = X[src * n_in + k0 + k];
-      }
-      Xs[i][k] = v;
+// bfloat16 copies of the weights for the matrix-core products
+__global__ void k_mlp_pack(int n_in, int n_in16, int n_out, int n_out16, const float *prm, uint16_t *W1b,
+                           uint16_t *W2b) {
+  const float *W1 = prm, *W2 = W1 + (int64_t)kMlpHidden * n_in + kMlpHidden;
+  const int64_t n1 = (int64_t)kMlpHidden * n_in16, n2 = (int64_t)n_out16 * kMlpHidden;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n1 + n2; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < n1) {
+      const int h = (int)(i / n_in16), k = (int)(i % n_in16);
+      W1b[i] = k < n_in ? to_bf16(W1[(int64_t)h * n_in + k]).bits : (uint16_t)0;
+    } else {
+      const int64_t j = i - n1;
+      const int o = (int)(j / kMlpHidden), h = (int)(j % kMlpHidden);
+      W2b[j] = o < n_out ? to_bf16(W2[(int64_t)o * kMlpHidden + h]).bits : (uint16_t)0;
     }
-    for (int idx = tid; idx < kMlpHidden * kChunk; idx += blockDim.x) {
-      const int h = idx / kChunk, k = idx % kChunk;
-      Ws[h][k] = (k0 + k < n_in) ? W1[(int64_t)h * n_in + k0 + k] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < kChunk; ++k) {
-      const float a0 = Xs[2 * ty][k], a1 = Xs[2 * ty + 1][k];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const float w = Ws[4 * tx + q][k];
-        acc[0][q] += a0 * w;
-        acc[1][q] += a1 * w;
-      }
-    }
-    __syncthreads();
   }
+}
+
+typedef short v4bf16 __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+constexpr int kMfmaRows = 64;  // rows per block: 16 per wavefront
+
+// Forward pass on the matrix cores (16x16x16 bfloat16 products, FP32 sums):
+// each wavefront takes 16 rows; layer 1 gives its 16 x 64 pre-activations Z
+// (+ b1; written to Zout if not null), h = bf16(relu(Z)) goes through LDS to
+// layer 2, Y = h W2^T + b2 for the 16 rows.  rows (optional) maps a row of the
+// tile to the row of X it reads.
+__global__ void __launch_bounds__(256) k_mlp_forward_mfma(int n, int n_in, int n_in16, int n_out, int n_out16,
+                                                           const float *__restrict__ X, const int *__restrict__ rows,
+                                                           const float *__restrict__ prm,
+                                                           const uint16_t *__restrict__ W1b,
+                                                           const uint16_t *__restrict__ W2b,
+                                                           float *__restrict__ Zout, float *__restrict__ Y) {
+  __shared__ uint16_t Hs[kMfmaRows][kMlpHidden + 4];
+  const float *b1 = prm + (int64_t)kMlpHidden * n_in, *b2 = b1 + kMlpHidden + (int64_t)n_out * kMlpHidden;
+  const int lane = threadIdx.x % kWave, wave = threadIdx.x / kWave;
+  const int r16 = wave * 16;                          // the wave's rows in the block
+  const int gi = blockIdx.x * kMfmaRows + r16 + lane % 16;  // row of the A fragment
+  const int64_t src = gi < n ? (rows ? rows[gi] : gi) : -1;
+  const float *xrow = src >= 0 ? X + src * n_in : nullptr;
+  v4f acc[4];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int t = 0; t < 4; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int kb = 0; kb < n_in16; kb += 16) {
+    const int k0 = kb + 4 * (lane / 16);
+    v4bf16 a;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = 2 * ty + a, h = 4 * tx + q;
-      const float z = acc[a][q] + b1[h];
-      Hs[i][h] = z > 0 ? z : 0.0f;
-      if (Zout && r0 + i < n) Zout[(int64_t)(r0 + i) * kMlpHidden + h] = z;
+    for (int v = 0; v < 4; ++v) {
+      const int k = k0 + v;
+      a[v] = (xrow && k < n_in) ? (short)to_bf16(xrow[k]).bits : (short)0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {  // hidden units 16 t .. 16 t + 15
+      const uint16_t *w = W1b + (int64_t)(16 * t + lane % 16) * n_in16 + k0;
+      v4bf16 b;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = (short)w[v];
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    }
+  }
+  // D layout: lane holds column lane % 16, rows 4 (lane / 16) + v
+#pragma unroll
+  for (int t = 0; t < 4; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int row = r16 + 4 * (lane / 16) + v, h = 16 * t + lane % 16;
+      const float z = acc[t][v] + b1[h];
+      const int64_t g = (int64_t)blockIdx.x * kMfmaRows + row;
+      if (Zout && g < n) Zout[g * kMlpHidden + h] = z;
+      Hs[row][h] = to_bf16(z > 0.f ? z : 0.f).bits;
     }
   __syncthreads();
-  for (int idx = tid; idx < kRows * n_out; idx += blockDim.x) {
-    const int i = idx / n_out, o = idx % n_out;
-    if (r0 + i >= n) continue;
-    float y = b2[o];
-    const float *w = W2 + o * kMlpHidden;
-#pragma unroll 8
-    for (int h = 0; h < kMlpHidden; ++h) y += Hs[i][h] * w[h];
-    Y[(int64_t)(r0 + i) * n_out + o] = y;
+  for (int ob = 0; ob < n_out16; ob += 16) {
+    v4f y = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kb = 0; kb < kMlpHidden; kb += 16) {
+      const int k0 = kb + 4 * (lane / 16);
+      v4bf16 a, b;
+      const uint16_t *w = W2b + (int64_t)(ob + lane % 16) * kMlpHidden + k0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        a[v] = (short)Hs[r16 + lane % 16][k0 + v];
+        b[v] = (short)w[v];
+      }
+      y = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, y, 0, 0, 0);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t g = (int64_t)blockIdx.x * kMfmaRows + r16 + 4 * (lane / 16) + v;
+      const int o = ob + lane % 16;
+      if (g < n && o < n_out) Y[g * n_out + o] = y[v] + b2[o];
+    }
   }
 }
 
-// z (level 0 layout) = s_F * y_F on faces, 0 on cells
+// z (level 0 layout): s_F y_F[:dp] on faces; on a cell T the mean over its faces
+// F of s_F y_F[dp + side t + q], side = T's position in F's cell pair
 template <typename T>
-__global__ void k_mlp_scatter(int64_t nface, int64_t N, int dp, const float *Y, const float *sc, T *z) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x)
-    z[i] = i < nface ? (T)(sc[i / dp] * Y[i]) : (T)0;
+__global__ void k_mlp_scatter(DTopo tp, MlpDims md, int64_t N, const float *Y, const float *sc, T *z) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < N; i += (int64_t)gridDim.x * blockDim.x) {
+    if (i < md.nface) {
+      const int64_t f = i / md.dp;
+      z[i] = (T)(sc[f] * Y[f * md.n_out + i % md.dp]);
+    } else {
+      const int c = (int)((i - md.nface) / md.t), q = (int)((i - md.nface) % md.t);
+      const int e0 = tp.cptr[c], e1 = tp.cptr[c + 1];
+      float acc = 0;
+      for (int e = e0; e < e1; ++e) {
+        const int f = tp.cface[e];
+        const int side = tp.fcell[2 * f] == c ? 0 : 1;
+        acc += sc[f] * Y[(int64_t)f * md.n_out + md.dp + side * md.t + q];
+      }
+      z[i] = (T)(acc / (float)(e1 - e0));
+    }
+  }
 }
 
 // dY = (Y - T[rows]) / B and per-block partial sums of |Y - T|^2
@@ -158,19 +217,21 @@ __global__ void __launch_bounds__(kBlock) k_mlp_dy(int B, int n_out, const float
   if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-// dZ = (dY W2) .* (Z > 0)
-__global__ void k_mlp_dz(int B, int n_out, const float *dY, const float *Z, const float *prm, int n_in, float *dZ) {
-  const float *W2 = prm + (int64_t)kMlpHidden * n_in + kMlpHidden;
+__device__ inline float bf16_value(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// dZ = (dY W2b) .* (Z > 0), W2b the bfloat16 weights the forward pass used
+__global__ void k_mlp_dz(int B, int n_out, const float *dY, const float *Z, const uint16_t *W2b, float *dZ) {
   const int64_t n = (int64_t)B * kMlpHidden;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t b = i / kMlpHidden, h = i % kMlpHidden;
     float s = 0;
-    for (int o = 0; o < n_out; ++o) s += dY[b * n_out + o] * W2[o * kMlpHidden + h];
+    for (int o = 0; o < n_out; ++o) s += dY[b * n_out + o] * bf16_value(W2b[o * kMlpHidden + h]);
     dZ[i] = Z[i] > 0 ? s : 0.0f;
   }
 }
 
-// gradient of every parameter: one thread per parameter, sum over the batch in order
+// gradient of every parameter: one thread per parameter, sum over the batch in
+// order, on the bfloat16-rounded inputs and activations the forward pass used
 __global__ void k_mlp_wgrad(int B, int n_in, int n_out, const float *X, const int *rows, const float *Z,
                             const float *dZ, const float *dY, float *g) {
   const int64_t nW1 = (int64_t)kMlpHidden * n_in, nb1 = kMlpHidden, nW2 = (int64_t)n_out * kMlpHidden;
@@ -181,7 +242,7 @@ __global__ void k_mlp_wgrad(int B, int n_in, int n_out, const float *X, const in
       const int h = (int)(p / n_in), k = (int)(p % n_in);
       for (int b = 0; b < B; ++b) {
         const int64_t src = rows ? rows[b] : b;
-        s += dZ[(int64_t)b * kMlpHidden + h] * X[src * n_in + k];
+        s += dZ[(int64_t)b * kMlpHidden + h] * (float)to_bf16(X[src * n_in + k]);
       }
     } else if (p < nW1 + nb1) {
       const int h = (int)(p - nW1);
@@ -191,7 +252,7 @@ __global__ void k_mlp_wgrad(int B, int n_in, int n_out, const float *X, const in
       const int o = (int)(q / kMlpHidden), h = (int)(q % kMlpHidden);
       for (int b = 0; b < B; ++b) {
         const float z = Z[(int64_t)b * kMlpHidden + h];
-        s += dY[(int64_t)b * n_out + o] * (z > 0 ? z : 0.0f);
+        s += dY[(int64_t)b * n_out + o] * (float)to_bf16(z > 0 ? z : 0.0f);
       }
     } else {
       const int o = (int)(p - nW1 - nb1 - nW2);
@@ -319,26 +380,34 @@ void launch_mlp_windows(const DTopo &tp, const MlpDims &md, const T *r, float *X
   if (tp.nf == 0) return;
   hipLaunchKernelGGL((k_mlp_windows<T>), dim3(tp.nf), dim3(kWave), 0, s, tp, md, r, X, sc);
 }
-void launch_mlp_targets(int nf, int dp, const double *xt, const double *x, const float *sc, float *Tg, hipStream_t s) {
-  hipLaunchKernelGGL(k_mlp_targets, dim3(blocks_for((int64_t)nf * dp)), dim3(kBlock), 0, s, nf, dp, xt, x, sc, Tg);
+void launch_mlp_targets(const DTopo &tp, const MlpDims &md, const double *xt, const double *x, const float *sc,
+                        float *Tg, hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_targets, dim3(blocks_for((int64_t)tp.nf * md.n_out)), dim3(kBlock), 0, s, tp, md, xt, x,
+                     sc, Tg);
 }
-void launch_mlp_forward(int n, int n_in, int n_out, const float *X, const int *rows, const float *prm, float *Z,
-                        float *Y, hipStream_t s) {
+void launch_mlp_pack(const MlpDims &md, const float *prm, uint16_t *W1b, uint16_t *W2b, hipStream_t s) {
+  const int64_t n = (int64_t)kMlpHidden * md.n_in16 + (int64_t)md.n_out16 * kMlpHidden;
+  hipLaunchKernelGGL(k_mlp_pack, dim3(blocks_for(n)), dim3(kBlock), 0, s, md.n_in, md.n_in16, md.n_out, md.n_out16,
+                     prm, W1b, W2b);
+}
+void launch_mlp_forward(int n, const MlpDims &md, const float *X, const int *rows, const float *prm,
+                        const uint16_t *W1b, const uint16_t *W2b, float *Z, float *Y, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(k_mlp_forward, dim3((n + kRows - 1) / kRows), dim3(256), 0, s, n, n_in, n_out, X, rows, prm, Z,
-                     Y);
+  hipLaunchKernelGGL(k_mlp_forward_mfma, dim3((n + kMfmaRows - 1) / kMfmaRows), dim3(256), 0, s, n, md.n_in, md.n_in16,
+                     md.n_out, md.n_out16, X, rows, prm, W1b, W2b, Z, Y);
 }
 template <typename T>
-void launch_mlp_scatter(int64_t nface, int64_t N, int dp, const float *Y, const float *sc, T *z, hipStream_t s) {
-  hipLaunchKernelGGL((k_mlp_scatter<T>), dim3(blocks_for(N)), dim3(kBlock), 0, s, nface, N, dp, Y, sc, z);
-}
-int launch_mlp_backward(int B, int n_in, int n_out, const float *X, const int *rows, const float *Tg, const float *prm,
-                        const float *Z, const float *Y, float *dY, float *dZ, float *g, double *partial,
+void launch_mlp_scatter(const DTopo &tp, const MlpDims &md, int64_t N, const float *Y, const float *sc, T *z,
                         hipStream_t s) {
+  hipLaunchKernelGGL((k_mlp_scatter<T>), dim3(blocks_for(N)), dim3(kBlock), 0, s, tp, md, N, Y, sc, z);
+}
+int launch_mlp_backward(int B, int n_in, int n_out, const float *X, const int *rows, const float *Tg,
+                        const uint16_t *W2b, const float *Z, const float *Y, float *dY, float *dZ, float *g,
+                        double *partial, hipStream_t s) {
   const int G = std::min(256, blocks_for((int64_t)B * n_out));
   hipLaunchKernelGGL(k_mlp_dy, dim3(G), dim3(kBlock), 0, s, B, n_out, Y, Tg, rows, dY, partial);
   hipLaunchKernelGGL(k_mlp_dz, dim3(blocks_for((int64_t)B * kMlpHidden)), dim3(kBlock), 0, s, B, n_out,
-                     (const float *)dY, Z, prm, n_in, dZ);
+                     (const float *)dY, Z, W2b, dZ);
   const int64_t np = (int64_t)kMlpHidden * n_in + kMlpHidden + (int64_t)n_out * kMlpHidden + n_out;
   hipLaunchKernelGGL(k_mlp_wgrad, dim3(blocks_for(np)), dim3(kBlock), 0, s, B, n_in, n_out, X, rows, Z,
                      (const float *)dZ, (const float *)dY, g);
@@ -364,7 +433,8 @@ void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T
 
 #define HHO_INST(T)                                                                                             \
   template void launch_mlp_windows<T>(const DTopo &, const MlpDims &, const T *, float *, float *, hipStream_t); \
-  template void launch_mlp_scatter<T>(int64_t, int64_t, int, const float *, const float *, T *, hipStream_t);    \
+  template void launch_mlp_scatter<T>(const DTopo &, const MlpDims &, int64_t, const float *, const float *, T *, \
+                                      hipStream_t);                                                               \
   template void launch_mr3<T>(int64_t, int, const T *, const T *, const T *, const T *, const T *, const T *, T *, \
                               T *, double *, double *, hipStream_t);
 HHO_INST(double)

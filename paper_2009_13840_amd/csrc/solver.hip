@@ -139,6 +139,7 @@ struct hho_problem {
   MlpDims md{};
   bool learned_on = false, learned_ready = false;
   int adam_step = 0;
+  uint16_t *mlp_w1b = nullptr, *mlp_w2b = nullptr;  // bfloat16 copies of the weights
   float *mlp_prm = nullptr, *mlp_g = nullptr, *mlp_m = nullptr, *mlp_v = nullptr, *mlp_X = nullptr, *mlp_sc = nullptr,
         *mlp_Y = nullptr, *mlp_Z = nullptr, *mlp_dZ = nullptr, *mlp_Yb = nullptr, *mlp_dY = nullptr;
   int *mlp_rows = nullptr;
@@ -352,6 +353,8 @@ static void plan(hho_problem *P, Arena &A) {
     const MlpDims &md = P->md;
     const int64_t np = mlp_param_count(md);
     P->mlp_prm = A.take<float>(np);
+    P->mlp_w1b = A.take<uint16_t>((int64_t)kMlpHidden * md.n_in16);
+    P->mlp_w2b = A.take<uint16_t>((int64_t)md.n_out16 * kMlpHidden);
     P->mlp_g = A.take<float>(np);
     P->mlp_m = A.take<float>(np);
     P->mlp_v = A.take<float>(np);
@@ -755,8 +758,8 @@ static void smooth(hho_problem *P, int l) {
   if (learned) {  // learned direction from the residual at the start of the step
     const MlpDims &md = P->md;
     launch_mlp_windows<T>(P->tp, md, V.r, P->mlp_X, P->mlp_sc, s);
-    launch_mlp_forward(P->tp.nf, md.n_in, md.n_out, P->mlp_X, nullptr, P->mlp_prm, nullptr, P->mlp_Y, s);
-    launch_mlp_scatter<T>(md.nface, n, md.dp, P->mlp_Y, P->mlp_sc, V.z3, s);
+    launch_mlp_forward(P->tp.nf, md, P->mlp_X, nullptr, P->mlp_prm, P->mlp_w1b, P->mlp_w2b, nullptr, P->mlp_Y, s);
+    launch_mlp_scatter<T>(P->tp, md, n, P->mlp_Y, P->mlp_sc, V.z3, s);
     launch_spmv<T>(P->tp, D, V.z3, nullptr, nullptr, V.w3, s);
   }
   KernelProbe *pr = &P->probe;
@@ -1278,7 +1281,9 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
     md.dp = d * L0.p;
     md.n_res = 2 * (md.Fm * md.dp + md.t);
     md.n_in = md.n_res + 2 * md.Fm;
-    md.n_out = md.dp;
+    md.n_out = md.dp + 2 * md.t;
+    md.n_in16 = (md.n_in + 15) / 16 * 16;
+    md.n_out16 = (md.n_out + 15) / 16 * 16;
     md.nface = L0.nface;
   }
   const int nT = hho::dim_poly(d, k), nF = hho::dim_poly(d - 1, k);
@@ -1893,6 +1898,7 @@ int hho_learned_set_params(hho_problem *p, const float *prm, int64_t n) {
   const int64_t np = hho::mlp_param_count(p->md);
   if (!prm || n != np) hho::fail(HHO_E_INVALID_ARG, "learned_set_params: need exactly n_params values");
   HIPCHK(hipMemcpyAsync(p->mlp_prm, prm, np * sizeof(float), hipMemcpyHostToDevice, p->stream));
+  hho::launch_mlp_pack(p->md, p->mlp_prm, p->mlp_w1b, p->mlp_w2b, p->stream);
   hho::launch_fill<float>(np, 0.0f, p->mlp_m, p->stream);
   hho::launch_fill<float>(np, 0.0f, p->mlp_v, p->stream);
   HIPCHK(hipStreamSynchronize(p->stream));
@@ -1932,8 +1938,8 @@ int hho_learned_apply(hho_problem *p, const double *r, double *z) {
   const hho::MlpDims &md = p->md;
   hipStream_t s = p->stream;
   hho::launch_mlp_windows<double>(p->tp, md, r, p->mlp_X, p->mlp_sc, s);
-  hho::launch_mlp_forward(p->tp.nf, md.n_in, md.n_out, p->mlp_X, nullptr, p->mlp_prm, nullptr, p->mlp_Y, s);
-  hho::launch_mlp_scatter<double>(md.nface, p->lev[0].N, md.dp, p->mlp_Y, p->mlp_sc, z, s);
+  hho::launch_mlp_forward(p->tp.nf, md, p->mlp_X, nullptr, p->mlp_prm, p->mlp_w1b, p->mlp_w2b, nullptr, p->mlp_Y, s);
+  hho::launch_mlp_scatter<double>(p->tp, md, p->lev[0].N, p->mlp_Y, p->mlp_sc, z, s);
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
   return HHO_OK;
@@ -1965,7 +1971,7 @@ int hho_learned_collect(hho_problem *p, const double *x_true, int cycles, float 
     hho::launch_residual<double>(p->tp, D, p->ob, p->ox, p->or_, s);
     float *Xc = X + (int64_t)c * nf * md.n_in;
     hho::launch_mlp_windows<double>(p->tp, md, p->or_, Xc, p->mlp_sc, s);
-    hho::launch_mlp_targets((int)nf, md.dp, x_true, p->ox, p->mlp_sc, Tg + (int64_t)c * nf * md.n_out, s);
+    hho::launch_mlp_targets(p->tp, md, x_true, p->ox, p->mlp_sc, Tg + (int64_t)c * nf * md.n_out, s);
     if (c + 1 < cycles) {
       hho::apply_vcycle(p, p->or_, p->ow);
       hho::launch_axpy_ratio<double>(n, p->scal + 2, 1.0, p->ow, p->ox, s);  // x += V(r)
@@ -1995,8 +2001,8 @@ static double mlp_loss_grad(hho_problem *p, const MlpWork &w, const float *X, co
                             double *loss_dev) {
   const hho::MlpDims &md = p->md;
   hipStream_t s = p->stream;
-  hho::launch_mlp_forward(B, md.n_in, md.n_out, X, rows, p->mlp_prm, w.Z, w.Y, s);
-  const int G = hho::launch_mlp_backward(B, md.n_in, md.n_out, X, rows, Tg, p->mlp_prm, w.Z, w.Y, w.dY, w.dZ, w.g,
+  hho::launch_mlp_forward(B, md, X, rows, p->mlp_prm, p->mlp_w1b, p->mlp_w2b, w.Z, w.Y, s);
+  const int G = hho::launch_mlp_backward(B, md.n_in, md.n_out, X, rows, Tg, p->mlp_w2b, w.Z, w.Y, w.dY, w.dZ, w.g,
                                          w.partial, s);
   hho::launch_sum_finish(G, w.partial, loss_dev, s);
   return 0.5 / B;  // factor turning the summed squares into the loss
@@ -2029,7 +2035,7 @@ int hho_learned_grad(hho_problem *p, const float *X, const float *Tg, int64_t n,
 // cleared.  Each device holds its own copy; host code reaches it only through
 // the address hipGetSymbolAddress returns on that device.
 namespace hho {
-constexpr int64_t kNoallocMaxOut = 128;
+constexpr int64_t kNoallocMaxOut = 256;
 constexpr int64_t kNoallocMaxParams = int64_t(1) << 20;
 constexpr int64_t kNoallocPartials = 512;
 constexpr int64_t kNoallocZ = (int64_t)kMlpMaxBatch * kMlpHidden * sizeof(float);
@@ -2111,6 +2117,7 @@ int hho_learned_train(hho_problem *p, const float *X, const float *Tg, int64_t n
     hho::launch_mlp_rows(batch, n, seed, p->adam_step, p->mlp_rows, s);
     f = mlp_loss_grad(p, mlp_work(p), X, Tg, p->mlp_rows, batch, p->mlp_loss + it);
     hho::launch_mlp_adam(np, p->mlp_prm, p->mlp_g, p->mlp_m, p->mlp_v, lr, ++p->adam_step, s);
+    hho::launch_mlp_pack(p->md, p->mlp_prm, p->mlp_w1b, p->mlp_w2b, s);
   }
   if (loss_hist) {
     std::vector<double> tmp(steps);

@@ -2,9 +2,12 @@
 training-pair collection, loss gradient and the learned V-cycle against the
 CPU oracle (oracle/mlp.py), and what training gains over the plain smoother.
 
-Tolerances: the network runs in FP32 on the GPU and in FP64 in the oracle (on
-the same FP32 parameters and inputs), so agreement is to FP32 rounding of
-sums of a few hundred terms: 2e-5 relative to the largest entry."""
+Tolerances: the network runs on bfloat16 inputs, weights and activations with
+FP32 sums on the GPU, and on the same bfloat16-rounded values with exact sums in
+the oracle (oracle.mlp, quantize=True); the two differ by FP32 rounding, and
+where an FP32 pre-activation and its exact value round to different bfloat16
+neighbours, by one bfloat16 step of that activation: 1e-2 relative to the
+largest entry (the P13 bound), 1e-3 for the loss."""
 import numpy as np
 import pytest
 
@@ -61,8 +64,8 @@ def built():
 def test_dims_match_window_definition(built, name, mk, k, cond):
     mesh, P, O, L = built(name, mk, k, cond)
     dm = P.learned_dims()
-    assert (dm["n_in"], dm["n_out"], dm["hidden"]) == (L.n_in, L.dp, mlp.HIDDEN)
-    assert dm["n_params"] == mlp.HIDDEN * L.n_in + mlp.HIDDEN + L.dp * mlp.HIDDEN + L.dp
+    assert (dm["n_in"], dm["n_out"], dm["hidden"]) == (L.n_in, L.n_out, mlp.HIDDEN)
+    assert dm["n_params"] == mlp.HIDDEN * L.n_in + mlp.HIDDEN + L.n_out * mlp.HIDDEN + L.n_out
 
 
 @pytest.mark.parametrize("name,mk,k,cond", CASES)
@@ -70,14 +73,16 @@ def test_inference_matches_oracle(built, name, mk, k, cond):
     import torch
     mesh, P, O, L = built(name, mk, k, cond)
     rng = np.random.default_rng(11)
-    th, flat = _params(rng, L.n_in, L.dp)
+    th, flat = _params(rng, L.n_in, L.n_out)
     P.learned_set_params(flat)
     assert np.array_equal(P.learned_get_params(), flat)
     r = rng.standard_normal(O.S[0].shape[0])
     z = P.learned_apply(torch.from_numpy(r).cuda()).cpu().numpy()
     zo = mlp.apply(th, mesh, L, r.astype(np.float32).astype(np.float64))
-    assert _rel(z, zo) < 2e-5, _rel(z, zo)
-    assert np.all(z[L.nface:] == 0)
+    print(f"[inference] {name}: faces {_rel(z[:L.nface], zo[:L.nface]):.2e} cells {_rel(z[L.nface:], zo[L.nface:]):.2e}")
+    assert _rel(z[:L.nface], zo[:L.nface]) < 1e-2
+    assert _rel(z[L.nface:], zo[L.nface:]) < 1e-2
+    assert np.abs(z[L.nface:]).max() > 0          # the pressure head corrects the cells
 
 
 @pytest.mark.parametrize("name,mk,k,cond", CASES)
@@ -89,7 +94,7 @@ def test_collect_first_cycle_matches_oracle(built, name, mk, k, cond):
     xt = rng.standard_normal(O.S[0].shape[0])
     X, T = P.learned_collect(torch.from_numpy(xt).cuda(), 1)
     Xo, so = mlp.windows(mesh, L, O.S[0] @ xt)
-    To = np.where(so[:, None] > 0, xt[:L.nface].reshape(-1, L.dp) / np.where(so > 0, so, 1)[:, None], 0.0)
+    To = mlp.targets(mesh, L, xt, so)
     assert X.shape == Xo.shape and T.shape == To.shape
     assert _rel(X.cpu().numpy(), Xo) < 1e-6, _rel(X.cpu().numpy(), Xo)
     assert _rel(T.cpu().numpy(), To) < 1e-6, _rel(T.cpu().numpy(), To)
@@ -100,18 +105,19 @@ def test_gradient_matches_oracle(built, name, mk, k, cond):
     import torch
     mesh, P, O, L = built(name, mk, k, cond)
     rng = np.random.default_rng(13)
-    th, flat = _params(rng, L.n_in, L.dp)
+    th, flat = _params(rng, L.n_in, L.n_out)
     P.learned_set_params(flat)
     n = 300
     X = rng.standard_normal((n, L.n_in)).astype(np.float32)
-    T = rng.standard_normal((n, L.dp)).astype(np.float32)
+    T = rng.standard_normal((n, L.n_out)).astype(np.float32)
     loss, g = P.learned_grad(torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda())
     lo, go = mlp.loss_and_grad(th, X.astype(np.float64), T.astype(np.float64))
-    assert abs(loss - lo) <= 1e-5 * lo
+    assert abs(loss - lo) <= 1e-3 * lo
     off = 0
     for key in ("W1", "b1", "W2", "b2"):
         sz = go[key].size
-        assert _rel(g[off:off + sz], go[key].ravel()) < 2e-5, (key, _rel(g[off:off + sz], go[key].ravel()))
+        print(f"[grad] {name} {key}: {_rel(g[off:off + sz], go[key].ravel()):.2e}")
+        assert _rel(g[off:off + sz], go[key].ravel()) < 1e-2, (key, _rel(g[off:off + sz], go[key].ravel()))
         off += sz
     assert off == g.size
 
@@ -122,7 +128,7 @@ def test_learned_vcycle_matches_oracle(built, name, mk, k, cond):
     import oracle.solve as OS
     mesh, P, O, L = built(name, mk, k, cond)
     rng = np.random.default_rng(14)
-    th, flat = _params(rng, L.n_in, L.dp)
+    th, flat = _params(rng, L.n_in, L.n_out)
     P.learned_set_params(flat)
     P.learned_enable(True)
     try:
@@ -135,7 +141,8 @@ def test_learned_vcycle_matches_oracle(built, name, mk, k, cond):
         xo = H.vcycle(0, b)
         if O.z[0] is not None:
             x, xo = OS.project_out(O.z[0])(x), OS.project_out(O.z[0])(xo)
-        assert _rel(x, xo) < 1e-4, _rel(x, xo)
+        print(f"[learned vcycle] {name}: {_rel(x, xo):.2e}")
+        assert _rel(x, xo) < 1e-2, _rel(x, xo)
     finally:
         P.learned_enable(False)
 
@@ -165,11 +172,11 @@ def test_adam_steps_match_oracle(built, name, mk, k, cond):
     import torch
     mesh, P, O, L = built(name, mk, k, cond)
     rng = np.random.default_rng(17)
-    th, flat = _params(rng, L.n_in, L.dp)
+    th, flat = _params(rng, L.n_in, L.n_out)
     P.learned_set_params(flat)
     n, B, lr, seed = 500, 96, 1e-3, 1234567
     X = torch.from_numpy(rng.standard_normal((n, L.n_in)).astype(np.float32)).cuda()
-    T = torch.from_numpy(rng.standard_normal((n, L.dp)).astype(np.float32)).cuda()
+    T = torch.from_numpy(rng.standard_normal((n, L.n_out)).astype(np.float32)).cuda()
     keys = ("W1", "b1", "W2", "b2")
     m = {k_: np.zeros_like(th[k_]) for k_ in keys}
     v = {k_: np.zeros_like(th[k_]) for k_ in keys}

@@ -20,7 +20,7 @@ def test_gradient_matches_finite_differences():
     n_in, n_out, B = 9, 4, 7
     th = _net(rng, n_in, n_out)
     X, T = rng.standard_normal((B, n_in)), rng.standard_normal((B, n_out))
-    _, g = mlp.loss_and_grad(th, X, T)
+    _, g = mlp.loss_and_grad(th, X, T, quantize=False)
     h = 1e-6
     for k in th:
         flat = th[k].ravel()
@@ -29,7 +29,7 @@ def test_gradient_matches_finite_differences():
             tm = {q: v.copy() for q, v in th.items()}
             tp[k].ravel()[idx] += h
             tm[k].ravel()[idx] -= h
-            fd = (mlp.loss_and_grad(tp, X, T)[0] - mlp.loss_and_grad(tm, X, T)[0]) / (2 * h)
+            fd = (mlp.loss_and_grad(tp, X, T, quantize=False)[0] - mlp.loss_and_grad(tm, X, T, quantize=False)[0]) / (2 * h)
             assert abs(fd - g[k].ravel()[idx]) <= 1e-6 * max(1.0, abs(fd)), (k, idx)
 
 
@@ -74,12 +74,68 @@ def test_correction_is_positively_homogeneous():
     rng = np.random.default_rng(2)
     mesh = cartesian_quads(3)
     L = mlp.layout(mesh, 2, 2, 3)
-    th = _net(rng, L.n_in, L.dp)
+    th = _net(rng, L.n_in, L.n_out)
     r = rng.standard_normal(L.nface + mesh.n_cells * L.t)
-    z1 = mlp.apply(th, mesh, L, r)
-    z2 = mlp.apply(th, mesh, L, 7.5 * r)
+    z1 = mlp.apply(th, mesh, L, r, quantize=False)
+    z2 = mlp.apply(th, mesh, L, 7.5 * r, quantize=False)
     assert np.allclose(z2, 7.5 * z1, rtol=1e-12, atol=0)
-    assert np.all(z1[L.nface:] == 0)
+
+
+def test_pressure_head_is_the_mean_over_the_cell_faces():
+    """With W2 = 0 the outputs are b2: face blocks get s_F b2[:dp], and a cell
+    the mean over its faces F of s_F times the b2 slice of its side of F."""
+    rng = np.random.default_rng(5)
+    mesh = cartesian_quads(2)
+    L = mlp.layout(mesh, 2, 1, 2)
+    th = _net(rng, L.n_in, L.n_out)
+    th["W2"][:] = 0.0
+    th["b2"] = np.arange(1.0, L.n_out + 1.0)         # [1, 2 | 3, 4 | 5, 6]
+    r = rng.standard_normal(L.nface + mesh.n_cells * L.t)
+    z = mlp.apply(th, mesh, L, r, quantize=False)
+    _, s = mlp.windows(mesh, L, r)
+    fc = mesh.face_cells()
+    for f in range(mesh.n_faces):
+        assert np.allclose(z[2 * f:2 * f + 2], s[f] * np.array([1.0, 2.0]))
+    c = 0
+    want = np.zeros(2)
+    for f in mesh.cell_faces(c):
+        want += s[f] * (np.array([3.0, 4.0]) if fc[f, 0] == c else np.array([5.0, 6.0]))
+    assert np.allclose(z[L.nface:L.nface + 2], want / 4)
+
+
+def test_targets_carry_face_and_both_cells():
+    mesh = cartesian_quads(2)
+    L = mlp.layout(mesh, 2, 1, 1)
+    e = np.arange(1.0, L.nface + mesh.n_cells + 1.0)
+    s = np.full(mesh.n_faces, 2.0)
+    s[0] = 0.0
+    T = mlp.targets(mesh, L, e, s)
+    fc = mesh.face_cells()
+    assert np.all(T[0] == 0)
+    f = int(np.flatnonzero(fc[:, 1] >= 0)[0])
+    assert np.allclose(T[f], np.array([e[2 * f], e[2 * f + 1], e[L.nface + fc[f, 0]], e[L.nface + fc[f, 1]]]) / 2)
+    fb = int(np.flatnonzero((fc[:, 1] < 0) & (np.arange(mesh.n_faces) > 0))[0])
+    assert T[fb, 3] == 0
+
+
+def test_bfloat16_network_definition():
+    """On values of the bfloat16 grid whose products and sums stay on it, the
+    rounded network equals the unrounded one; on general values the two differ
+    by the rounding of x, W1, W2 and h (2^-8 relative each)."""
+    rng = np.random.default_rng(6)
+    n_in, n_out, B = 8, 3, 5
+    th = {"W1": rng.integers(-3, 4, (mlp.HIDDEN, n_in)).astype(float), "b1": np.zeros(mlp.HIDDEN),
+          "W2": rng.integers(-3, 4, (n_out, mlp.HIDDEN)) / 4.0, "b2": np.full(n_out, 0.1)}
+    X = rng.integers(-2, 3, (B, n_in)).astype(float)
+    assert np.array_equal(mlp.forward(th, X, True)[0], mlp.forward(th, X, False)[0])
+    th = _net(rng, n_in, n_out)
+    X = rng.standard_normal((B, n_in))
+    Yq, Y = mlp.forward(th, X, True)[0], mlp.forward(th, X, False)[0]
+    assert 0 < np.abs(Yq - Y).max() <= 4 * 2.0 ** -8 * np.abs(Y).max() + 1e-3
+    g_q = mlp.loss_and_grad(th, X, np.zeros((B, n_out)), True)[1]
+    g = mlp.loss_and_grad(th, X, np.zeros((B, n_out)), False)[1]
+    for k in g:
+        assert np.abs(g_q[k] - g[k]).max() <= 0.05 * np.abs(g[k]).max() + 1e-12
 
 
 def test_mr_step_minimises_over_directions():

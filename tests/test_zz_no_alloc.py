@@ -1,8 +1,9 @@
 """GPU test of the allocation-free loss-and-gradient entry point
 (hho_learned_grad_noalloc) through the C ABI: two calls in a row, the second
 with fewer rows, each identical to hho_learned_grad (same kernels, same fixed
-summation order, only the work arrays live elsewhere) and within FP32 rounding
-of the oracle's FP64 network; sizes beyond the fixed array are refused."""
+summation order, only the work arrays live elsewhere) and within the bfloat16
+network's bound of the oracle's network; sizes beyond the fixed array are
+refused."""
 import numpy as np
 import pytest
 
@@ -33,16 +34,16 @@ def test_noalloc_gradient_matches_workspace_gradient():
     O = OS.build(mesh, k, cond, data, eta=None)
     L = mlp.layout(mesh, mesh.dim, O.lays[0].nF, O.lays[0].nP)
     rng = np.random.default_rng(21)
-    th = mlp.init_params(L.n_in, L.dp, rng.random(mlp.HIDDEN * L.n_in), rng.random(L.dp * mlp.HIDDEN))
+    th = mlp.init_params(L.n_in, L.n_out, rng.random(mlp.HIDDEN * L.n_in), rng.random(L.n_out * mlp.HIDDEN))
     th["b1"] = 0.05 * rng.standard_normal(mlp.HIDDEN)
-    th["b2"] = 0.05 * rng.standard_normal(L.dp)
+    th["b2"] = 0.05 * rng.standard_normal(L.n_out)
     th = {kk: v.astype(np.float32).astype(np.float64) for kk, v in th.items()}
     flat = np.concatenate([th["W1"].ravel(), th["b1"], th["W2"].ravel(), th["b2"]]).astype(np.float32)
     P.learned_set_params(flat)
     results = []
     for n in (4096, 1000):   # the second call is smaller: stale rows of the first must not leak in
         X = rng.standard_normal((n, L.n_in)).astype(np.float32)
-        T = rng.standard_normal((n, L.dp)).astype(np.float32)
+        T = rng.standard_normal((n, L.n_out)).astype(np.float32)
         Xd, Td = torch.from_numpy(X).cuda(), torch.from_numpy(T).cuda()
         print(f"[call] noalloc gradient over {n} rows", flush=True)
         loss_na, g_na = P.learned_grad(Xd, Td, noalloc=True)
@@ -50,14 +51,14 @@ def test_noalloc_gradient_matches_workspace_gradient():
         assert loss_na == loss_ws
         assert np.array_equal(g_na, g_ws)
         lo, go = mlp.loss_and_grad(th, X.astype(np.float64), T.astype(np.float64))
-        assert abs(loss_na - lo) <= 1e-5 * lo
+        assert abs(loss_na - lo) <= 1e-3 * lo          # bfloat16 network: see test_gpu_learned
         gflat = np.concatenate([go[kk].ravel() for kk in ("W1", "b1", "W2", "b2")])
-        assert _rel(g_na, gflat) < 2e-5, _rel(g_na, gflat)
+        assert _rel(g_na, gflat) < 1e-2, _rel(g_na, gflat)
         results.append(g_na)
     assert not np.array_equal(results[0], results[1])
     # beyond the fixed array: refused before any device work
     X = torch.zeros((4097, L.n_in), dtype=torch.float32, device="cuda:0")
-    T = torch.zeros((4097, L.dp), dtype=torch.float32, device="cuda:0")
+    T = torch.zeros((4097, L.n_out), dtype=torch.float32, device="cuda:0")
     with pytest.raises(H.HHOError) as e:
         P.learned_grad(X, T, noalloc=True)
     assert e.value.code == -7
