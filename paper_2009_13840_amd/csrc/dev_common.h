@@ -120,6 +120,70 @@ __device__ inline void reduce_partials(const double *partial, int G, int K, doub
   __syncthreads();
 }
 
+// Coefficients of the smoothing step's minimal-residual update (Section 3.3: the
+// GMRES(2) iterate started from zero is the minimal-residual combination of the
+// first two preconditioned directions).  S holds the Gram sums of the operator
+// images w_i and their products with the residual:
+//   two directions  S = {w1.w1, w1.w2, w2.w2, w1.r, w2.r}            (m = 1: w1 only)
+//   three           S = {a11, a12, a13, a22, a23, a33, g1, g2, g3}   (m = 1: w2 dropped)
+// A direction that is numerically dependent on the earlier ones gets a zero
+// coefficient; non-finite results give zero coefficients.
+__device__ inline void mr2_solve(const double *S, int m, double *y) {
+  double y1 = 0, y2 = 0;
+  const double det = S[0] * S[2] - S[1] * S[1];
+  if (m == 2 && det > 1e-14 * S[0] * S[2]) {
+    y1 = (S[2] * S[3] - S[1] * S[4]) / det;
+    y2 = (S[0] * S[4] - S[1] * S[3]) / det;
+  } else if (S[0] > 0) {
+    y1 = S[3] / S[0];
+  }
+  if (!isfinite(y1) || !isfinite(y2)) y1 = y2 = 0;
+  y[0] = y1;
+  y[1] = y2;
+}
+
+// The three-direction normal equations by Cholesky; a direction whose pivot is
+// not clearly positive is dropped.
+__device__ inline void mr3_solve(const double *S, int m, double *y) {
+  double A[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
+  double g[3] = {S[6], S[7], S[8]};
+  bool use[3] = {true, m == 2, true};
+  double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int j = 0; j < 3; ++j) {
+    if (!use[j]) continue;
+    double dj = A[j][j];
+    for (int k = 0; k < j; ++k)
+      if (use[k]) dj -= L[j][k] * L[j][k];
+    if (!(dj > 1e-12 * A[j][j]) || !(A[j][j] > 0)) {
+      use[j] = false;
+      continue;
+    }
+    L[j][j] = sqrt(dj);
+    for (int i = j + 1; i < 3; ++i) {
+      double s = A[i][j];
+      for (int k = 0; k < j; ++k)
+        if (use[k]) s -= L[i][k] * L[j][k];
+      L[i][j] = s / L[j][j];
+    }
+  }
+  double z[3] = {0, 0, 0}, x[3] = {0, 0, 0};
+  for (int i = 0; i < 3; ++i) {
+    if (!use[i]) continue;
+    double s = g[i];
+    for (int k = 0; k < i; ++k)
+      if (use[k]) s -= L[i][k] * z[k];
+    z[i] = s / L[i][i];
+  }
+  for (int i = 2; i >= 0; --i) {
+    if (!use[i]) continue;
+    double s = z[i];
+    for (int k = i + 1; k < 3; ++k)
+      if (use[k]) s -= L[k][i] * x[k];
+    x[i] = s / L[i][i];
+  }
+  for (int i = 0; i < 3; ++i) y[i] = isfinite(x[i]) ? x[i] : 0.0;
+}
+
 __device__ inline double wave_max(double v) {
   for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, kWave));
   return v;

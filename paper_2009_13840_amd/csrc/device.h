@@ -212,7 +212,8 @@ constexpr int kSegChunk = 4096;
 struct GmresState;
 void launch_seg_sumsq(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *r, double *partial,
                       hipStream_t s);
-// |r_p| -> beta, (bnorm when which == 1), g = beta e1, done flags (sdone[p])
+// |r_p| -> beta, (bnorm when which == 1), g = beta e1, done flags (sdone[p]);
+// which == 2 leaves a segment that is already done untouched
 void launch_seg_norm_finish(int np, const int32_t *chunk_ptr, int nchunks, const double *partial, GmresState *st,
                             int *sdone, int which, hipStream_t s);
 void launch_seg_scale(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *x, const GmresState *st,
@@ -223,6 +224,15 @@ void launch_seg_arnoldi(int mode, int nchunks, const SegChunk *ch, const SegInfo
 void launch_seg_solve_ls(int np, GmresState *st, hipStream_t s);
 void launch_seg_combine(int nchunks, const SegChunk *ch, const SegInfo *seg, const double *Z, int64_t ldz,
                         const GmresState *st, double *x, hipStream_t s);
+// smoothing step of every segment with its own minimal-residual coefficients
+// (y: 3 per segment): x += Z y_p, r -= W y_p over the segment's entries; z3/w3
+// null for the two-direction step, m = 1 for one Schwarz direction
+template <typename T>
+void launch_seg_mr(int nchunks, const SegChunk *ch, const SegInfo *seg, int np, const int32_t *chunk_ptr, int m,
+                   const T *z1, const T *z2, const T *z3, const T *w1, const T *w2, const T *w3, T *x, T *r,
+                   double *partial, double *y, hipStream_t s);
+// *flag = 1 when every sdone[p] is set
+void launch_seg_all_done(int np, const int *sdone, int *flag, hipStream_t s);
 // v_p -= (v_p . z_p / z_p . z_p) z_p for every segment
 void launch_seg_project(int np, const int32_t *chunk_ptr, int nchunks, const SegChunk *ch, const SegInfo *seg,
                         const double *z, double *v, double *partial, double *ratio, hipStream_t s);

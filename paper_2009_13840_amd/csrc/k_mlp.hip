@@ -312,48 +312,10 @@ __global__ void __launch_bounds__(kBlock) k_mr3_dots(int64_t n, const T *w1, con
 }
 
 // Solves the 3x3 (or 2x2 without the second Schwarz direction) normal equations
-// by Cholesky; a direction whose pivot is not clearly positive is dropped.
 __global__ void __launch_bounds__(kBlock) k_mr3_finish(int G, int m, const double *partial, double *y) {
   __shared__ double S[9];
   reduce_partials(partial, G, 9, S);
-  if (threadIdx.x != 0) return;
-  double A[3][3] = {{S[0], S[1], S[2]}, {S[1], S[3], S[4]}, {S[2], S[4], S[5]}};
-  double g[3] = {S[6], S[7], S[8]};
-  bool use[3] = {true, m == 2, true};
-  double L[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-  for (int j = 0; j < 3; ++j) {
-    if (!use[j]) continue;
-    double dj = A[j][j];
-    for (int k = 0; k < j; ++k)
-      if (use[k]) dj -= L[j][k] * L[j][k];
-    if (!(dj > 1e-12 * A[j][j]) || !(A[j][j] > 0)) {
-      use[j] = false;
-      continue;
-    }
-    L[j][j] = sqrt(dj);
-    for (int i = j + 1; i < 3; ++i) {
-      double s = A[i][j];
-      for (int k = 0; k < j; ++k)
-        if (use[k]) s -= L[i][k] * L[j][k];
-      L[i][j] = s / L[j][j];
-    }
-  }
-  double z[3] = {0, 0, 0}, x[3] = {0, 0, 0};
-  for (int i = 0; i < 3; ++i) {
-    if (!use[i]) continue;
-    double s = g[i];
-    for (int k = 0; k < i; ++k)
-      if (use[k]) s -= L[i][k] * z[k];
-    z[i] = s / L[i][i];
-  }
-  for (int i = 2; i >= 0; --i) {
-    if (!use[i]) continue;
-    double s = z[i];
-    for (int k = i + 1; k < 3; ++k)
-      if (use[k]) s -= L[k][i] * x[k];
-    x[i] = s / L[i][i];
-  }
-  for (int i = 0; i < 3; ++i) y[i] = isfinite(x[i]) ? x[i] : 0.0;
+  if (threadIdx.x == 0) mr3_solve(S, m, y);
 }
 
 template <typename T>

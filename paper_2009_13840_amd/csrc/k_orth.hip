@@ -307,6 +307,10 @@ __global__ void __launch_bounds__(kBlock) k_seg_norm_finish(const int32_t *chunk
   GmresState *st = st_all + p;
   __shared__ double nsum[1];
   if (which == 0 && st->done && st->nan) return;
+  if (which == 2 && st->done) {  // its correction is in x already: no columns in the next cycle
+    if (threadIdx.x == 0) st->j = 0;
+    return;
+  }
   reduce_range(partial, G, chunk_ptr[p], chunk_ptr[p + 1], 1, nsum);
   if (threadIdx.x == 0) {
     const double nn = nsum[0];
@@ -331,9 +335,9 @@ __global__ void __launch_bounds__(kSegThreads) k_seg_scale(const SegChunk *ch, c
                                                             const GmresState *st, double *y) {
   const SegChunk c = ch[blockIdx.x];
   const SegInfo g = seg[c.p];
-  // a converged member's next basis vector is zero: the V-cycle, which acts on
-  // the whole union, then sees nothing of it (its scalars and the coarse solve
-  // are formed over the union), and its slice cannot grow with a stale scale
+  // a converged member's next basis vector is zero: the V-cycle and the
+  // operator, which act on the whole union, then carry only zeros in its slice,
+  // and the slice cannot grow with a stale scale
   const bool done = st[c.p].done != 0;
   const double a = st[c.p].inv_hnext;
   for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
@@ -499,6 +503,103 @@ __global__ void __launch_bounds__(kSegThreads) k_seg_axpy(const SegChunk *ch, co
   }
 }
 
+// ---- smoothing step of every segment on its own (batched problems)
+// Per chunk: the Gram sums of the step's directions, NS = 5 for two directions
+// (w2 may be null: one direction), NS = 9 for three (layouts of mr2_solve and
+// mr3_solve).
+template <typename T, int NS>
+__global__ void __launch_bounds__(kSegThreads) k_seg_mr_dots(const SegChunk *ch, const SegInfo *seg, const T *w1,
+                                                              const T *w2, const T *w3, const T *r,
+                                                              double *partial) {
+  __shared__ double red[16];
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  double v[NS];
+#pragma unroll
+  for (int k = 0; k < NS; ++k) v[k] = 0;
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t i = seg_index(g, (int64_t)c.e0 + e);
+    const double x1 = w1[i], x2 = w2 ? (double)w2[i] : 0.0, rr = r[i];
+    if constexpr (NS == 5) {
+      v[0] += x1 * x1;
+      v[1] += x1 * x2;
+      v[2] += x2 * x2;
+      v[3] += x1 * rr;
+      v[4] += x2 * rr;
+    } else {
+      const double x3 = w3[i];
+      v[0] += x1 * x1;
+      v[1] += x1 * x2;
+      v[2] += x1 * x3;
+      v[3] += x2 * x2;
+      v[4] += x2 * x3;
+      v[5] += x3 * x3;
+      v[6] += x1 * rr;
+      v[7] += x2 * rr;
+      v[8] += x3 * rr;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < NS; ++k) {
+    const double sm = block_sum(v[k], red);
+    if (threadIdx.x == 0) partial[(int64_t)k * gridDim.x + blockIdx.x] = sm;
+  }
+}
+
+// one block per segment: its coefficients y[3p .. 3p + 2]
+template <int NS>
+__global__ void __launch_bounds__(kBlock) k_seg_mr_finish(const int32_t *chunk_ptr, int G, int m,
+                                                           const double *partial, double *y) {
+  const int p = blockIdx.x;
+  __shared__ double S[NS];
+  reduce_range(partial, G, chunk_ptr[p], chunk_ptr[p + 1], NS, S);
+  if (threadIdx.x == 0) {
+    double yy[3] = {0, 0, 0};
+    if constexpr (NS == 5)
+      mr2_solve(S, m, yy);
+    else
+      mr3_solve(S, m, yy);
+    y[3 * p] = yy[0];
+    y[3 * p + 1] = yy[1];
+    y[3 * p + 2] = yy[2];
+  }
+}
+
+// x += Z y_p, r -= W y_p on every chunk, with its segment's coefficients (z2/w2
+// null: one Schwarz direction; z3/w3 null: no third direction)
+template <typename T>
+__global__ void __launch_bounds__(kSegThreads) k_seg_mr_update(const SegChunk *ch, const SegInfo *seg,
+                                                                const double *y, const T *z1, const T *z2,
+                                                                const T *z3, const T *w1, const T *w2, const T *w3,
+                                                                T *x, T *r) {
+  const SegChunk c = ch[blockIdx.x];
+  const SegInfo g = seg[c.p];
+  const T y1 = (T)y[3 * c.p], y2 = (T)y[3 * c.p + 1], y3 = (T)y[3 * c.p + 2];
+  for (int e = threadIdx.x; e < c.len; e += blockDim.x) {
+    const int64_t i = seg_index(g, (int64_t)c.e0 + e);
+    if (z3) {
+      const T a2 = z2 ? z2[i] : (T)0, b2 = w2 ? w2[i] : (T)0;
+      x[i] += y1 * z1[i] + y2 * a2 + y3 * z3[i];
+      r[i] -= y1 * w1[i] + y2 * b2 + y3 * w3[i];
+    } else if (z2) {
+      x[i] += y1 * z1[i] + y2 * z2[i];
+      r[i] -= y1 * w1[i] + y2 * w2[i];
+    } else {
+      x[i] += y1 * z1[i];
+      r[i] -= y1 * w1[i];
+    }
+  }
+}
+
+// flag = 1 when every segment's done flag is set (one block)
+__global__ void __launch_bounds__(kBlock) k_seg_all_done(int np, const int *sdone, int *flag) {
+  __shared__ double red[16];
+  double c = 0;
+  for (int p = threadIdx.x; p < np; p += blockDim.x) c += sdone[p] ? 1.0 : 0.0;
+  c = block_sum(c, red);
+  if (threadIdx.x == 0) *flag = (c == (double)np) ? 1 : 0;
+}
+
 }  // namespace
 
 static_assert(kMaxRestartH <= 64, "orthogonalisation kernels handle at most 64 basis vectors");
@@ -587,12 +688,37 @@ void launch_seg_project(int np, const int32_t *chunk_ptr, int nchunks, const Seg
   hipLaunchKernelGGL(k_seg_axpy, dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, (const double *)ratio, z, v);
 }
 
+template <typename T>
+void launch_seg_mr(int nchunks, const SegChunk *ch, const SegInfo *seg, int np, const int32_t *chunk_ptr, int m,
+                   const T *z1, const T *z2, const T *z3, const T *w1, const T *w2, const T *w3, T *x, T *r,
+                   double *partial, double *y, hipStream_t s) {
+  if (m != 2) z2 = w2 = nullptr;
+  if (z3) {
+    hipLaunchKernelGGL((k_seg_mr_dots<T, 9>), dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, w1, w2, w3, r, partial);
+    hipLaunchKernelGGL((k_seg_mr_finish<9>), dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, m,
+                       (const double *)partial, y);
+  } else {
+    hipLaunchKernelGGL((k_seg_mr_dots<T, 5>), dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, w1, w2,
+                       (const T *)nullptr, r, partial);
+    hipLaunchKernelGGL((k_seg_mr_finish<5>), dim3(np), dim3(kBlock), 0, s, chunk_ptr, nchunks, m,
+                       (const double *)partial, y);
+  }
+  hipLaunchKernelGGL((k_seg_mr_update<T>), dim3(nchunks), dim3(kSegThreads), 0, s, ch, seg, (const double *)y, z1, z2,
+                     z3, w1, w2, w3, x, r);
+}
+void launch_seg_all_done(int np, const int *sdone, int *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_seg_all_done, dim3(1), dim3(kBlock), 0, s, np, sdone, flag);
+}
+
 #define HHO_INST(T)                                                                                              \
   template void launch_arnoldi_dots<T>(int64_t, int, const T *, int64_t, const T *, double *, GmresState *,     \
                                        hipStream_t);                                                           \
   template void launch_arnoldi_update<T>(int64_t, int, const T *, int64_t, T *, double *, GmresState *, int,    \
                                          int, hipStream_t);                                                      \
-  template void launch_arnoldi_cgs1<T>(int64_t, int, T *, int64_t, const T *, double *, GmresState *, hipStream_t);
+  template void launch_arnoldi_cgs1<T>(int64_t, int, T *, int64_t, const T *, double *, GmresState *, hipStream_t); \
+  template void launch_seg_mr<T>(int, const SegChunk *, const SegInfo *, int, const int32_t *, int, const T *,     \
+                                 const T *, const T *, const T *, const T *, const T *, T *, T *, double *, double *, \
+                                 hipStream_t);
 HHO_INST(double)
 HHO_INST(float)
 #undef HHO_INST

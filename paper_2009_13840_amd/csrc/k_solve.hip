@@ -377,19 +377,7 @@ __global__ void __launch_bounds__(kBlock) k_mr2_dots(int64_t n, int m, const T *
 __global__ void __launch_bounds__(kBlock) k_mr2_finish(int G, int m, const double *partial, double *y) {
   __shared__ double S[5];
   reduce_partials(partial, G, 5, S);
-  if (threadIdx.x == 0) {
-    double y1 = 0, y2 = 0;
-    const double det = S[0] * S[2] - S[1] * S[1];
-    if (m == 2 && det > 1e-14 * S[0] * S[2]) {
-      y1 = (S[2] * S[3] - S[1] * S[4]) / det;
-      y2 = (S[0] * S[4] - S[1] * S[3]) / det;
-    } else if (S[0] > 0) {
-      y1 = S[3] / S[0];
-    }
-    if (!isfinite(y1) || !isfinite(y2)) y1 = y2 = 0;
-    y[0] = y1;
-    y[1] = y2;
-  }
+  if (threadIdx.x == 0) mr2_solve(S, m, y);
 }
 
 template <typename T>

@@ -63,6 +63,18 @@ struct LevelInfo {
   double *y;  // smoother coefficients
 };
 
+// one level's segment table of a batch (the level's vector layout: faces with
+// that level's degree, then cells)
+struct SegLevel {
+  std::vector<SegInfo> hseg;
+  std::vector<SegChunk> hch;
+  std::vector<int32_t> hptr;
+  SegInfo *seg = nullptr;
+  SegChunk *ch = nullptr;
+  int32_t *ptr = nullptr;
+  int G() const { return (int)hch.size(); }
+};
+
 }  // namespace hho
 
 using namespace hho;
@@ -131,6 +143,12 @@ struct hho_problem {
   GmresState *sst = nullptr;
   int *sdone = nullptr;
   double *seg_partial = nullptr, *seg_ratio = nullptr, *seg_hist = nullptr;
+  // per-member scalars inside the V-cycle: segment tables of every level, the
+  // smoothing steps' coefficients (3 per member) and the coarse GMRES state
+  std::vector<SegLevel> segl;
+  double *seg_y = nullptr;
+  GmresState *csst = nullptr;
+  int *csdone = nullptr, *call_done = nullptr;
   std::vector<int> seg_its;
   std::vector<std::vector<double>> seg_hist_h;  // per-member residual estimates of the last batched solve
   bool opt_seg_hist = false;                     // record them (hho_batch_solve with histories)
@@ -347,6 +365,22 @@ static void plan(hho_problem *P, Arena &A) {
     P->seg_partial = A.take<double>(G * (kMaxRestartH + 2));
     P->seg_ratio = A.take<double>(P->nseg);
     P->seg_hist = A.take<double>(2 * P->nseg);
+    for (int l = 0; l < P->nlev; ++l) {
+      SegLevel &S = P->segl[l];
+      if (l == 0) {
+        S.seg = P->dseg;
+        S.ch = P->dchunks;
+        S.ptr = P->dchunk_ptr;
+      } else {
+        S.seg = A.take<SegInfo>(P->nseg);
+        S.ch = A.take<SegChunk>(S.G());
+        S.ptr = A.take<int32_t>(P->nseg + 1);
+      }
+    }
+    P->seg_y = A.take<double>(3 * P->nseg);
+    P->csst = A.take<GmresState>(P->nseg);
+    P->csdone = A.take<int>(P->nseg);
+    P->call_done = A.take<int>(1);
   }
   // learned fine-level smoother
   if (P->opt.learned) {
@@ -603,6 +637,12 @@ static void device_upload(hho_problem *P) {
     h2d(P->dseg, P->hseg.data(), P->hseg.size() * sizeof(SegInfo));
     h2d(P->dchunks, P->hchunks.data(), P->hchunks.size() * sizeof(SegChunk));
     h2d(P->dchunk_ptr, P->hchunk_ptr.data(), P->hchunk_ptr.size() * 4);
+    for (int l = 1; l < P->nlev; ++l) {
+      const SegLevel &S = P->segl[l];
+      h2d(S.seg, S.hseg.data(), S.hseg.size() * sizeof(SegInfo));
+      h2d(S.ch, S.hch.data(), S.hch.size() * sizeof(SegChunk));
+      h2d(S.ptr, S.hptr.data(), S.hptr.size() * 4);
+    }
   }
   if (P->coarse_amg) {
     h2d(P->d_fdiag, P->fdiag.data(), P->fdiag.size() * 4);
@@ -769,6 +809,12 @@ static void smooth(hho_problem *P, int l) {
     HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
     HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s));
   }
+  if (P->nseg > 0) {  // batch: every member takes its own minimal-residual step
+    const SegLevel &S = P->segl[l];
+    launch_seg_mr<T>(S.G(), S.ch, S.seg, P->nseg, S.ptr, m, V.z1, V.z2, learned ? V.z3 : nullptr, V.w1, V.w2,
+                     learned ? V.w3 : nullptr, V.w, V.r, P->seg_partial, P->seg_y, s);
+    return;
+  }
   if (learned) {
     launch_mr3<T>(n, m, V.z1, V.z2, V.z3, V.w1, V.w2, V.w3, V.w, V.r, P->partial, P->lev[l].y, s);
     return;
@@ -816,6 +862,92 @@ static void set_rtol(hho_problem *P, GmresState *st, double rtol) {
   HIPCHK(hipStreamSynchronize(P->stream));
 }
 
+// GMRES state of every segment reset, with its tolerance
+__global__ void k_seg_init(int np, GmresState *st, double rtol) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= np) return;
+  st[p].rtol = rtol;
+  st[p].done = 0;
+  st[p].nan = 0;
+  st[p].its = 0;
+  st[p].j = 0;
+}
+
+static bool read_flag(hho_problem *P, const int *flag) {
+  int h = 0;
+  HIPCHK(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return h != 0;
+}
+
+// The coarse GMRES of a batch: one Krylov process per member over its slice of
+// the coarsest level (the same steps as coarse_solve: classical Gram-Schmidt once
+// with the new norm taken after the subtraction, restarts from the true
+// residual), so no member's coarse correction depends on another member's
+// residual.  The preconditioner acts on the whole union, which is block
+// diagonal; once every member has converged the queued operator kernels return
+// at once.
+static void coarse_solve_seg(hho_problem *P) {
+  hipStream_t s = P->stream;
+  const int Lc = P->nlev - 1, np = P->nseg;
+  LevelInfo &L = P->lev[Lc];
+  VBufs<double> &V = L.v64;
+  const SegLevel &S = P->segl[Lc];
+  const int G = S.G();
+  const DLevel<double> D = dlev64(P, Lc);
+  const int64_t n = L.N;
+  const int R = P->opt.coarse_restart;
+  GmresState *st = P->csst;
+  DLevel<double> Dq = D;
+  Dq.skip = P->call_done;
+  launch_fill<double>(n, 0.0, V.w, s);
+  hipLaunchKernelGGL(k_seg_init, dim3((np + 63) / 64), dim3(64), 0, s, np, st, P->opt.coarse_rtol);
+  launch_seg_sumsq(G, S.ch, S.seg, V.b, P->seg_partial, s);
+  launch_seg_norm_finish(np, S.ptr, G, P->seg_partial, st, P->csdone, 1, s);
+  launch_seg_scale(G, S.ch, S.seg, V.b, st, P->cV, s);
+  launch_seg_all_done(np, P->csdone, P->call_done, s);
+  bool all = read_flag(P, P->call_done);
+  int its = 0;
+  const int chunk = 6;
+  while (!all && its < P->opt.coarse_max_it) {
+    const int jmax = std::min(R, P->opt.coarse_max_it - its);
+    int jn = 0;
+    for (int j = 0; j < jmax; ++j) {
+      double *vj = P->cV + (int64_t)j * n, *zj = P->cZ + (int64_t)j * n;
+      if (P->coarse_amg) {
+        bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, zj, P->amg_nu, s, P->call_done);
+        HHO_PROBED(&P->probe, HHO_PROBE_COARSE_OPERATOR, Lc, s,
+                   launch_spmv<double>(P->tp, Dq, zj, nullptr, nullptr, P->cw, s));
+      } else {
+        launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
+        launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, zj, P->cw, s);
+      }
+      launch_seg_arnoldi(0, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
+      launch_seg_arnoldi(2, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
+      launch_seg_scale(G, S.ch, S.seg, P->cw, st, P->cV + (int64_t)(j + 1) * n, s);
+      launch_seg_all_done(np, P->csdone, P->call_done, s);
+      jn = j + 1;
+      if ((j + 1) % chunk == 0 || j + 1 == jmax) {
+        all = read_flag(P, P->call_done);
+        if (all) break;
+      }
+    }
+    its += jn;
+    launch_seg_solve_ls(np, st, s);
+    launch_seg_combine(G, S.ch, S.seg, P->cZ, n, st, V.w, s);
+    if (all || its >= P->opt.coarse_max_it) break;
+    // restart the unconverged members from their true residuals; a converged one
+    // stays done, as a single problem's coarse solve stops at its estimate
+    launch_residual<double>(P->tp, D, V.b, V.w, P->cr, s);
+    launch_seg_sumsq(G, S.ch, S.seg, P->cr, P->seg_partial, s);
+    launch_seg_norm_finish(np, S.ptr, G, P->seg_partial, st, P->csdone, 2, s);
+    launch_seg_scale(G, S.ch, S.seg, P->cr, st, P->cV, s);
+    launch_seg_all_done(np, P->csdone, P->call_done, s);
+    all = read_flag(P, P->call_done);
+  }
+  P->coarse_its += its;
+}
+
 // coarsest level: lev[Lc].v64.b -> lev[Lc].v64.w (FP64)
 static void coarse_solve(hho_problem *P) {
   hipStream_t s = P->stream;
@@ -824,6 +956,10 @@ static void coarse_solve(hho_problem *P) {
   VBufs<double> &V = L.v64;
   if (P->coarse_dense) {
     launch_dense_matvec(P->dense, P->dense_n, 2 * P->dense_n, P->border, V.b, V.w, s);
+    return;
+  }
+  if (P->nseg > 0) {
+    coarse_solve_seg(P);
     return;
   }
   const DLevel<double> D = dlev64(P, Lc);
@@ -912,15 +1048,6 @@ static void apply_vcycle(hho_problem *P, const double *b, double *x) {
 // V-cycle and the operator act on the whole disjoint union (block diagonal),
 // the Arnoldi reductions, Hessenberg columns, Givens rotations, restarts and
 // convergence tests are per segment.  Converged segments stop contributing.
-__global__ void k_seg_init(int np, GmresState *st, double rtol) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= np) return;
-  st[p].rtol = rtol;
-  st[p].done = 0;
-  st[p].nan = 0;
-  st[p].its = 0;
-  st[p].j = 0;
-}
 
 // relative residual estimate and Arnoldi step count of every segment
 __global__ void k_seg_hist(int np, const GmresState *st, double *out) {
@@ -2227,23 +2354,29 @@ int hho_problem_set_segments(hho_problem *p, int n, const int64_t *face_ptr, con
   p->seg_face_ptr.assign(face_ptr, face_ptr + n + 1);
   p->seg_cell_ptr.assign(cell_ptr, cell_ptr + n + 1);
   hho::init_levels(p);  // the coarse solver choice depends on the segments
-  const hho::LevelInfo &L0 = p->lev[0];
-  const int64_t dp = (int64_t)p->d * L0.p;
-  p->hseg.resize(n);
-  p->hchunks.clear();
-  p->hchunk_ptr.assign(1, 0);
-  for (int i = 0; i < n; ++i) {
-    hho::SegInfo &g = p->hseg[i];
-    g.fo = face_ptr[i] * dp;
-    g.fl = (face_ptr[i + 1] - face_ptr[i]) * dp;
-    g.co = L0.nface + cell_ptr[i] * L0.t;
-    g.cl = (cell_ptr[i + 1] - cell_ptr[i]) * L0.t;
-    const int64_t len = g.fl + g.cl;
-    if (len > INT32_MAX) hho::fail(HHO_E_INVALID_ARG, "set_segments: segment too large");
-    for (int64_t e = 0; e < len; e += hho::kSegChunk)
-      p->hchunks.push_back({i, (int32_t)e, (int32_t)std::min<int64_t>(hho::kSegChunk, len - e), 0});
-    p->hchunk_ptr.push_back((int32_t)p->hchunks.size());
+  p->segl.assign(p->nlev, hho::SegLevel{});
+  for (int l = 0; l < p->nlev; ++l) {
+    const hho::LevelInfo &L = p->lev[l];
+    const int64_t dp = (int64_t)p->d * L.p;
+    hho::SegLevel &S = p->segl[l];
+    S.hseg.resize(n);
+    S.hptr.assign(1, 0);
+    for (int i = 0; i < n; ++i) {
+      hho::SegInfo &g = S.hseg[i];
+      g.fo = face_ptr[i] * dp;
+      g.fl = (face_ptr[i + 1] - face_ptr[i]) * dp;
+      g.co = L.nface + cell_ptr[i] * L.t;
+      g.cl = (cell_ptr[i + 1] - cell_ptr[i]) * L.t;
+      const int64_t len = g.fl + g.cl;
+      if (len > INT32_MAX) hho::fail(HHO_E_INVALID_ARG, "set_segments: segment too large");
+      for (int64_t e = 0; e < len; e += hho::kSegChunk)
+        S.hch.push_back({i, (int32_t)e, (int32_t)std::min<int64_t>(hho::kSegChunk, len - e), 0});
+      S.hptr.push_back((int32_t)S.hch.size());
+    }
   }
+  p->hseg = p->segl[0].hseg;
+  p->hchunks = p->segl[0].hch;
+  p->hchunk_ptr = p->segl[0].hptr;
   return HHO_OK;
   ABI_END
 }

@@ -90,3 +90,58 @@ def test_batched_restart_after_a_member_converged():
         err = np.linalg.norm(xm - xd) / np.linalg.norm(xd)
         assert err <= 1e-7, (i, err)
 
+
+
+def _batch_run(meshes, fields, k, cond, **opts):
+    import paper_2009_13840_amd as H
+    probs = []
+    for m, f in zip(meshes, fields):
+        Q = H.Problem(H.Mesh(m), k, cond, **opts)
+        Q.set_data(*f)
+        probs.append(Q)
+    B = H.Batch(probs)
+    B.problem.bind("cuda:0")
+    B.problem.setup()
+    return B.solve(hist_cap=400)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_member_does_not_depend_on_its_companions(precision):
+    """Inside the V-cycle every member takes its own minimal-residual smoothing
+    coefficients and runs its own coarse GMRES (Section 3.3's V-cycle per
+    member), as the outer FGMRES already does: with a preconditioner that has no
+    union-wide quantity (Schwarz-preconditioned coarse GMRES), a member's
+    iteration count, residual history and solution are the same whichever
+    problems share its batch and at whatever position; alone (the
+    single-problem kernels sum in another order) it takes the same iterations
+    and its history agrees while above the tolerance."""
+    import paper_2009_13840_amd as H
+    k, cond = 2, "v"
+    A = voronoi_lloyd(30, 3)
+    others = [cartesian_quads(6), voronoi_lloyd(45, 5), cartesian_quads(3)]
+    fA = problem_data(polynomial_stokes(2, k + 1, 81), None, 2)
+    fo = [problem_data(polynomial_stokes(2, k + 1, 82 + i), None, 2) for i in range(3)]
+    opts = dict(rtol=1e-10, coarse_mode="gmres", precision=precision)
+    print(f"[case] member independence, precision={precision}", flush=True)
+    r1 = _batch_run([A, others[0]], [fA, fo[0]], k, cond, **opts)[0]
+    r2 = _batch_run([others[1], A, others[2]], [fo[1], fA, fo[2]], k, cond, **opts)[1]
+    face1, pres1, its1, h1, rel1, st1 = r1
+    face2, pres2, its2, h2, rel2, st2 = r2
+    dh = np.max(np.abs(np.asarray(h1) - np.asarray(h2)) / np.asarray(h1))
+    print(f"[member A] its {its1} / {its2}, history max rel diff {dh:.2e}")
+    assert st1 == 0 and st2 == 0
+    assert its1 == its2 and dh <= 1e-12
+    assert np.linalg.norm(face1 - face2) <= 1e-13 * np.linalg.norm(face1)
+    # alone
+    P = H.Problem(H.Mesh(A), k, cond, **opts)
+    P.set_data(*fA)
+    P.bind("cuda:0")
+    P.setup()
+    x, its, hist, rel, ok = P.solve(hist_cap=400)
+    hist = np.asarray(hist)
+    print(f"[member A alone] its {its}")
+    assert ok and its == its1
+    above = hist > 1e-8
+    assert np.all(np.abs(hist[above] - np.asarray(h1)[above]) <= 1e-6 * hist[above])
+    nf = face1.size
+    assert np.linalg.norm(x.cpu().numpy()[:nf] - face1) <= 1e-8 * np.linalg.norm(face1)
