@@ -98,6 +98,12 @@ extern "C" {
 #define HHO_NULLSPACE_AUTO  0   /* projected out when the boundary has no Neumann face */
 #define HHO_NULLSPACE_NONE  1   /* never projected (the caller's right-hand side must be consistent) */
 
+/* where the local operators of Sections 2.2-2.3 are built (hho_problem_set_data) */
+#define HHO_LOCAL_AUTO    0   /* on the device when its limits hold (a cell's velocity unknowns d*nloc <= 256,
+                                 its work arrays within the LDS), on the host otherwise */
+#define HHO_LOCAL_HOST    1   /* on the host, at hho_problem_set_data */
+#define HHO_LOCAL_DEVICE  2   /* on the device, at hho_setup; set_data fails if the limits do not hold */
+
 /* face boundary flags in hho_mesh_desc.face_bc */
 #define HHO_FACE_INTERIOR   0
 #define HHO_FACE_DIRICHLET  1
@@ -145,6 +151,9 @@ typedef struct {
   int32_t smoother;    /* HHO_SMOOTHER_* (SCHWARZ) */
   int32_t nullspace;   /* HHO_NULLSPACE_* (AUTO) */
   int32_t vcycle_copy; /* HHO_COPY_* (CONVERT); PRODUCT needs precision FP32 or BF16 */
+  int32_t local_build; /* HHO_LOCAL_* (AUTO): with the device build, hho_problem_set_data only
+                          integrates the data (the callbacks run there) and hho_setup builds every
+                          cell's operators on the device before the condensation */
 } hho_options;
 
 /* Scalar or vector field evaluated at n points x [n*dim]; nrm [n*dim] holds the
@@ -186,8 +195,9 @@ int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_fi
  * momentum and mass right-hand sides of the local problem of Section 2.3.1
  * (data terms of eq. def:HHOAB, with the Dirichlet datum loading cell rows as
  * well).  The local operators stay; the next hho_setup copies the records
- * again.  Needs hho_problem_set_data first (NULL fields build the operators
- * with zero data).  hho_moments_size gives the two lengths. */
+ * again (with the device build, writes these moments over the ones it forms).
+ * Needs hho_problem_set_data first (NULL fields build the operators with zero
+ * data).  hho_moments_size gives the two lengths. */
 int hho_moments_size(const hho_problem *p, int64_t *n_u, int64_t *n_p);
 int hho_set_moments(hho_problem *p, const double *rhs_u, const double *rhs_p);
 
@@ -266,7 +276,9 @@ int hho_get_condensed_cell(hho_problem *p, int64_t cell, double *S, double *rhs,
 
 /* Host copies of the local HHO operators of one cell before condensation:
  * a [nloc x nloc] scalar viscous matrix (cell modes first, then faces in mesh
- * order), B [d x n_T x nloc], rhs_u [d x nloc], rhs_p [n_T]. */
+ * order), B [d x n_T x nloc], rhs_u [d x nloc], rhs_p [n_T].  With the device
+ * build (options.local_build) the records exist after hho_setup, which this
+ * call then needs. */
 int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B, double *rhs_u,
                        double *rhs_p, int64_t cap, int64_t *nloc_out);
 

@@ -24,6 +24,7 @@ PROBE = {"operator": 1, "smoother": 2, "coarse_operator": 4, "outer_operator": 8
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
 COPY = {"convert": 0, "product": 1}
+LOCAL = {"auto": 0, "host": 1, "device": 2}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
@@ -57,7 +58,7 @@ class Options(C.Structure):
                 ("coarse_rtol", C.c_double), ("coarse_restart", C.c_int32), ("coarse_max_it", C.c_int32),
                 ("quad_extra", C.c_int32), ("coarse_amg_sweeps", C.c_int32), ("learned", C.c_int32),
                 ("coarse_amg_explicit", C.c_int32), ("coarse_amg_psmooth", C.c_int32), ("smoother", C.c_int32),
-                ("nullspace", C.c_int32), ("vcycle_copy", C.c_int32)]
+                ("nullspace", C.c_int32), ("vcycle_copy", C.c_int32), ("local_build", C.c_int32)]
 
 
 FIELD_FN = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -222,6 +223,8 @@ def options(**kw) -> Options:
             v = COARSE[v] if isinstance(v, str) else v
         if k == "vcycle_copy":
             v = COPY[v] if isinstance(v, str) else v
+        if k == "local_build":
+            v = LOCAL[v] if isinstance(v, str) else v
         setattr(o, k, v)
     return o
 
@@ -549,7 +552,7 @@ class Problem:
         t = np.zeros(16)
         _check(load().hho_get_timings(self.h, _dptr(t), 16))
         keys = ["condense_ms", "assemble_ms", "levels_ms", "smoother_setup_ms", "coarse_setup_ms", "solve_ms",
-                "vcycle_ms", "vcycles", "coarse_its"]
+                "vcycle_ms", "vcycles", "coarse_its", "local_ms"]
         return dict(zip(keys, t[:len(keys)]))
 
 

@@ -198,6 +198,36 @@ void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T
                 T *r, double *partial, double *y, hipStream_t s);
 void launch_sum_finish(int G, const double *partial, double *out, hipStream_t s);
 
+// ---- local HHO operators on the device (one workgroup per cell)
+constexpr int kGlTable = 16;  // Gauss-Legendre table stride: n = 1 .. 15 points
+struct LocalGeom {
+  int d, k, N1, nT, nF, odeg;
+  const int32_t *cptr, *cface;  // cell -> faces (the topology's)
+  const double *csign;          // [cptr[nc]] +1 if n_F points out of the cell
+  const int64_t *fptr, *fvtx;   // face vertices (2D: the two end points)
+  const double *verts;          // [nv][d]
+  const int64_t *rptr, *ring;   // 2D: counter-clockwise vertex ring of every cell
+  const uint8_t *cbox;          // 3D: axis-aligned box cells
+  const double *clo, *chi, *apex;
+  const double *ccen, *cdiam, *fcen, *fdiam, *fnrm, *ft1, *ft2;
+  const int8_t *fbc;
+  const double *eta;            // [nc] Nitsche penalty
+  const double *glt, *glw;      // [n][kGlTable] nodes and weights on [0, 1]
+  const int32_t *EC, *EF;       // exponents of the cell (degree k+1) and face (degree k) monomials
+  const double *mf, *fd;        // data against the monomials (see the host's DataMoments)
+  const int64_t *foff;
+  const int64_t *roff;          // record offsets
+  double *rec;                  // records [a | B | rhs_u | rhs_p] (output)
+  int *err;                     // cell + 1 of a degenerate basis or a non-SPD stiffness
+};
+struct LocalLds {  // LDS layout of the local build (offsets in doubles)
+  int C, K, Bc, G, Pi, Nn, gpo, red, rv, gto, scr;
+  int max_nq, max_nqf, nloc_max, chunk;
+  size_t bytes;
+};
+LocalLds local_lds(int d, int k, int max_faces, int max_nq, int max_nqf);
+void launch_local(const LocalGeom &g, const LocalLds &L, int nc, hipStream_t s);
+
 // ---- batched problems: per-problem (segment) Krylov state over a disjoint union
 // A segment's unknowns are its face entries [fo, fo + fl) and cell entries
 // [co, co + cl) of the level-0 vector; its "virtual" index e < fl + cl maps to

@@ -712,4 +712,206 @@ void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, i
   });
 }
 
+void build_data_moments(const hho_mesh *m, int k, int qdeg, hho_field_fn f_fn, hho_field_fn gD_fn,
+                        hho_field_fn gN_fn, void *ctx, DataMoments *out, LocalData *lay) {
+  const int d = m->dim;
+  const int N1 = dim_poly(d, k + 1), nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
+  const int64_t nc = m->nc, nf = m->nf;
+  lay->k = k;
+  lay->d = d;
+  lay->nT = nT;
+  lay->nF = nF;
+  lay->N1 = N1;
+  lay->off.assign(nc + 1, 0);
+  lay->nloc.assign(nc, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int nloc = nT + (int)(m->cptr[c + 1] - m->cptr[c]) * nF;
+    lay->nloc[c] = nloc;
+    lay->off[c + 1] = lay->off[c] + (int64_t)nloc * nloc + (int64_t)d * nT * nloc + (int64_t)d * nloc + nT;
+  }
+  lay->rec.clear();
+
+  std::vector<Rule> crule(nc), frule(nf);
+  parallel_for(nc, [&](int64_t c) { cell_rule(m, c, qdeg, crule[c]); });
+  parallel_for(nf, [&](int64_t f) {
+    if (m->fbc[f] != HHO_FACE_INTERIOR) face_rule(m, f, qdeg, frule[f]);
+  });
+  // data at the points
+  std::vector<int64_t> coff(nc + 1, 0), boff(nf + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + crule[c].n();
+  for (int64_t f = 0; f < nf; ++f) boff[f + 1] = boff[f] + frule[f].n();
+  std::vector<double> fx(coff[nc] * d), fval(coff[nc] * d, 0.0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int q = 0; q < crule[c].n(); ++q)
+      for (int a = 0; a < d; ++a) fx[(coff[c] + q) * d + a] = crule[c].x[3 * q + a];
+  if (f_fn && coff[nc]) f_fn(fx.data(), coff[nc], nullptr, fval.data(), ctx);
+  std::vector<double> nrm(nf * 3, 0.0);
+  std::vector<int64_t> dsel, nsel;  // Dirichlet / Neumann faces
+  for (int64_t f = 0; f < nf; ++f) {
+    if (m->fbc[f] == HHO_FACE_INTERIOR) continue;
+    const int64_t c = m->fcell[0][f];
+    const double sg = m->csign[m->cptr[c] + m->flocal[0][f]];
+    for (int a = 0; a < 3; ++a) nrm[3 * f + a] = sg * m->fnrm[3 * f + a];
+    (m->fbc[f] == HHO_FACE_DIRICHLET ? dsel : nsel).push_back(f);
+  }
+  auto gather = [&](const std::vector<int64_t> &sel, hho_field_fn fn, bool need, std::vector<double> &val,
+                    std::vector<int64_t> &at) {
+    int64_t n = 0;
+    at.assign(nf, -1);
+    for (int64_t f : sel) {
+      at[f] = n;
+      n += frule[f].n();
+    }
+    std::vector<double> x(n * d), nn(n * d);
+    val.assign(n * d, 0.0);
+    for (int64_t f : sel)
+      for (int q = 0; q < frule[f].n(); ++q)
+        for (int a = 0; a < d; ++a) {
+          x[(at[f] + q) * d + a] = frule[f].x[3 * q + a];
+          nn[(at[f] + q) * d + a] = nrm[3 * f + a];
+        }
+    if (n && !fn && need) fail(HHO_E_INVALID_ARG, "set_data: the mesh has Neumann faces but gN is NULL");
+    if (n && fn) fn(x.data(), n, nn.data(), val.data(), ctx);
+  };
+  std::vector<double> dval, nval;
+  std::vector<int64_t> dat, nat;
+  gather(dsel, gD_fn, false, dval, dat);
+  gather(nsel, gN_fn, true, nval, nat);
+
+  // record offsets of the face data
+  out->foff.assign(nf, -1);
+  int64_t nfd = 0;
+  for (int64_t f = 0; f < nf; ++f) {
+    if (m->fbc[f] == HHO_FACE_DIRICHLET) {
+      out->foff[f] = nfd;
+      nfd += (int64_t)d * N1 + (int64_t)d * nF + nT;
+    } else if (m->fbc[f] == HHO_FACE_NEUMANN) {
+      out->foff[f] = nfd;
+      nfd += (int64_t)d * nF;
+    }
+  }
+  out->fd.assign(nfd, 0.0);
+  out->mf.assign(nc * d * nT, 0.0);
+  const std::vector<int> EC = exponents(d, k + 1), EF = exponents(d - 1, k);
+  // cells: (f_a, M_j)_T
+  parallel_for(nc, [&](int64_t c) {
+    const Rule &R = crule[c];
+    const int nq = R.n();
+    const double h = m->cdiam[c], *x0 = &m->ccen[3 * c];
+    std::vector<double> xi((size_t)nq * d), M((size_t)nq * N1);
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a) xi[q * d + a] = (R.x[3 * q + a] - x0[a]) / h;
+    eval_monomials(EC, d, xi.data(), nq, M.data());
+    double *o = &out->mf[c * d * nT];
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a) {
+        const double wf = R.w[q] * fval[(coff[c] + q) * d + a];
+        for (int j = 0; j < nT; ++j) o[a * nT + j] += wf * M[(size_t)q * N1 + j];
+      }
+  });
+  // boundary faces
+  parallel_for(nf, [&](int64_t f) {
+    if (m->fbc[f] == HHO_FACE_INTERIOR) return;
+    const bool isD = m->fbc[f] == HHO_FACE_DIRICHLET;
+    const Rule &R = frule[f];
+    const int nq = R.n();
+    const double *g = isD ? &dval[dat[f] * d] : &nval[nat[f] * d];
+    double *o = &out->fd[out->foff[f]];
+    // face monomials
+    const double hF = m->fdiam[f], *xf = &m->fcen[3 * f], *t1 = &m->ft1[3 * f], *t2 = &m->ft2[3 * f];
+    const int nv = d - 1;
+    std::vector<double> xi((size_t)nq * nv), Mf((size_t)nq * nF);
+    for (int q = 0; q < nq; ++q) {
+      const double r[3] = {R.x[3 * q] - xf[0], R.x[3 * q + 1] - xf[1], R.x[3 * q + 2] - xf[2]};
+      xi[q * nv] = (r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2]) / hF;
+      if (nv == 2) xi[q * nv + 1] = (r[0] * t2[0] + r[1] * t2[1] + r[2] * t2[2]) / hF;
+    }
+    eval_monomials(EF, nv, xi.data(), nq, Mf.data());
+    double *gp = isD ? o + (int64_t)d * N1 : o;
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a)
+        for (int j = 0; j < nF; ++j) gp[a * nF + j] += R.w[q] * g[q * d + a] * Mf[(size_t)q * nF + j];
+    if (!isD) return;
+    // cell monomials of the face's cell and their normal derivatives
+    const int64_t c = m->fcell[0][f];
+    const double h = m->cdiam[c], *x0 = &m->ccen[3 * c], *n = &nrm[3 * f];
+    std::vector<double> xc((size_t)nq * d), M((size_t)nq * N1);
+    for (int q = 0; q < nq; ++q)
+      for (int a = 0; a < d; ++a) xc[q * d + a] = (R.x[3 * q + a] - x0[a]) / h;
+    eval_monomials(EC, d, xc.data(), nq, M.data());
+    double *gt = o, *gn = o + (int64_t)d * N1 + (int64_t)d * nF;
+    for (int q = 0; q < nq; ++q) {
+      double gdotn = 0;
+      for (int a = 0; a < d; ++a) gdotn += g[q * d + a] * n[a];
+      for (int t = 0; t < N1; ++t) {
+        // n . grad M_t = sum_b n_b E_tb / h prod_c xi_c^(E_tc - [c == b])
+        double dn = 0;
+        for (int b = 0; b < d; ++b) {
+          const int eb = EC[t * d + b];
+          if (eb == 0) continue;
+          double v = eb / h;
+          for (int cc = 0; cc < d; ++cc) v *= ipow(xc[q * d + cc], EC[t * d + cc] - (cc == b ? 1 : 0));
+          dn += n[b] * v;
+        }
+        for (int a = 0; a < d; ++a) gt[a * N1 + t] += R.w[q] * g[q * d + a] * dn;
+      }
+      for (int t = 0; t < nT; ++t) gn[t] += R.w[q] * gdotn * M[(size_t)q * N1 + t];
+    }
+  });
+}
+
+void build_local_geometry(const hho_mesh *m, int k, int qdeg, LocalGeomHost *g) {
+  const int d = m->dim;
+  const int64_t nc = m->nc, nf = m->nf;
+  g->odeg = std::min(qdeg, 2 * k + 2);
+  const int od = g->odeg;
+  g->rptr.assign(1, 0);
+  g->ring.clear();
+  g->apex.assign(3 * nc, 0.0);
+  int max_nq = 0, max_nqf = 0;
+  const int n2 = (od + 3) / 2, n3b = (od + 2) / 2, n3t = (od + 4) / 2, nseg = (od + 2) / 2;
+  if (n2 >= kGlMax || n3t >= kGlMax) fail(HHO_E_INVALID_ARG, "device local build: quadrature degree too high");
+  for (int64_t c = 0; c < nc; ++c) {
+    int nq = 0;
+    if (d == 2) {
+      const auto &r = m->cring[c];
+      g->ring.insert(g->ring.end(), r.begin(), r.end());
+      nq = (int)(r.size() - 2) * n2 * n2;
+    } else if (m->cbox[c]) {
+      nq = n3b * n3b * n3b;
+    } else {
+      std::vector<int64_t> vs;
+      for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e) {
+        const int64_t f = m->cface[e];
+        for (int64_t t = m->fptr[f]; t < m->fptr[f + 1]; ++t) vs.push_back(m->fvtx[t]);
+        nq += (int)(m->fptr[f + 1] - m->fptr[f] - 2) * n3t * n3t * n3t;
+      }
+      std::sort(vs.begin(), vs.end());
+      vs.erase(std::unique(vs.begin(), vs.end()), vs.end());
+      for (int64_t v : vs)
+        for (int q = 0; q < 3; ++q) g->apex[3 * c + q] += m->verts[v * 3 + q] / vs.size();
+    }
+    g->rptr.push_back((int64_t)g->ring.size());
+    max_nq = std::max(max_nq, nq);
+  }
+  for (int64_t f = 0; f < nf; ++f) {
+    const int nvf = (int)(m->fptr[f + 1] - m->fptr[f]);
+    max_nqf = std::max(max_nqf, d == 2 ? nseg : (nvf - 2) * n2 * n2);
+  }
+  g->max_nq = max_nq;
+  g->max_nqf = max_nqf;
+  g->glt.assign(kGlMax * kGlMax, 0.0);
+  g->glw.assign(kGlMax * kGlMax, 0.0);
+  for (int n = 1; n < kGlMax; ++n) {
+    const GL &r = gl(n);
+    for (int i = 0; i < n; ++i) {
+      g->glt[n * kGlMax + i] = r.t[i];
+      g->glw[n * kGlMax + i] = r.w[i];
+    }
+  }
+  const std::vector<int> EC = exponents(d, k + 1), EF = exponents(d - 1, k);
+  g->EC.assign(EC.begin(), EC.end());
+  g->EF.assign(EF.begin(), EF.end());
+}
+
 }  // namespace hho

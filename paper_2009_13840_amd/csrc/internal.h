@@ -66,4 +66,34 @@ struct LocalData {
 // eta: Nitsche penalty of every cell, or, when cell_eta is not NULL, cell_eta[c] per cell
 void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, int qdeg, hho_field_fn f,
                  hho_field_fn gD, hho_field_fn gN, void *ctx, LocalData *out);
+
+// The data of the device build of the local operators: integrals of the data
+// against scaled monomials, which the device maps onto the orthonormal bases.
+//   mf   [nc][d][nT]   (f_a, M_j)_T, M_j the cell monomials of degree <= k at
+//                      (x - x_T) / h_T in the graded order of the cell basis
+//   fd   per boundary face f from foff[f] (-1: interior face); n the outward
+//        normal of the face's cell T:
+//        Dirichlet: [d][N1] (g_a, n . grad M_t)_F, t < N1 (monomials of T)
+//                   [d][nF] (g_a, m_j)_F, m_j the face monomials
+//                   [nT]    (g . n, M_t)_F
+//        Neumann:   [d][nF] (g_a, m_j)_F
+// Also fills the record layout of `lay` (off, nloc and the sizes; no records).
+struct DataMoments {
+  std::vector<double> mf, fd;
+  std::vector<int64_t> foff;
+};
+void build_data_moments(const hho_mesh *m, int k, int qdeg, hho_field_fn f, hho_field_fn gD, hho_field_fn gN,
+                        void *ctx, DataMoments *out, LocalData *lay);
+// Geometry tables of the device build: counter-clockwise vertex rings of 2D
+// cells (CSR), the vertex mean of every 3D cell (apex of its tetrahedra),
+// Gauss-Legendre nodes and weights on [0, 1] for n = 1 .. kGlMax - 1 points
+// ([n][i], stride kGlMax), and the point counts of the operator rules.
+constexpr int kGlMax = 16;
+struct LocalGeomHost {
+  std::vector<int64_t> rptr, ring;
+  std::vector<double> apex, glt, glw;
+  std::vector<int32_t> EC, EF;
+  int odeg = 0, max_nq = 0, max_nqf = 0;
+};
+void build_local_geometry(const hho_mesh *m, int k, int qdeg, LocalGeomHost *g);
 }  // namespace hho

@@ -153,6 +153,17 @@ struct hho_problem {
   std::vector<std::vector<double>> seg_hist_h;  // per-member residual estimates of the last batched solve
   bool opt_seg_hist = false;                     // record them (hho_batch_solve with histories)
   std::vector<double> seg_rel;
+  // local operators built on the device (options.local_build)
+  bool local_dev = false;
+  DataMoments dmom;
+  LocalGeomHost lgeo;
+  LocalLds llds{};
+  LocalGeom lg{};
+  double *d_user_rhs = nullptr;          // hho_set_moments with the device build: [rhs_u | rhs_p] per cell
+  int64_t *d_user_off = nullptr;         // [nc+1] offsets of those packed records
+  std::vector<double> user_rhs;          // empty: the device build's own right-hand side
+  std::vector<int64_t> user_off;
+  std::vector<double> cell_eta_dev;      // penalty of every cell for the device build
   // learned fine-level smoother
   MlpDims md{};
   bool learned_on = false, learned_ready = false;
@@ -193,6 +204,51 @@ static void plan(hho_problem *P, Arena &A) {
   // local records and condensation staging
   P->rec = A.take<double>(P->loc.off.empty() ? 1 : P->loc.off[nc]);
   P->roff = A.take<int64_t>(nc + 1);
+  if (P->local_dev) {
+    const hho_mesh *m = P->mesh;
+    LocalGeom &g = P->lg;
+    g.d = d;
+    g.k = P->k;
+    g.N1 = P->loc.N1;
+    g.nT = P->loc.nT;
+    g.nF = P->loc.nF;
+    g.odeg = P->lgeo.odeg;
+    g.cptr = P->tp.cptr;
+    g.cface = P->tp.cface;
+    g.csign = A.take<double>(m->csign.size());
+    g.fptr = A.take<int64_t>(m->fptr.size());
+    g.fvtx = A.take<int64_t>(m->fvtx.size());
+    g.verts = A.take<double>(m->verts.size());
+    g.rptr = A.take<int64_t>(P->lgeo.rptr.size());
+    g.ring = A.take<int64_t>(std::max<size_t>(1, P->lgeo.ring.size()));
+    g.cbox = A.take<uint8_t>(std::max<size_t>(1, m->cbox.size()));
+    g.clo = A.take<double>(std::max<size_t>(1, m->clo.size()));
+    g.chi = A.take<double>(std::max<size_t>(1, m->chi.size()));
+    g.apex = A.take<double>(P->lgeo.apex.size());
+    g.ccen = A.take<double>(m->ccen.size());
+    g.cdiam = A.take<double>(m->cdiam.size());
+    g.fcen = A.take<double>(m->fcen.size());
+    g.fdiam = A.take<double>(m->fdiam.size());
+    g.fnrm = A.take<double>(m->fnrm.size());
+    g.ft1 = A.take<double>(m->ft1.size());
+    g.ft2 = A.take<double>(m->ft2.size());
+    g.fbc = A.take<int8_t>(m->fbc.size());
+    g.eta = A.take<double>(nc);
+    g.glt = A.take<double>(P->lgeo.glt.size());
+    g.glw = A.take<double>(P->lgeo.glw.size());
+    g.EC = A.take<int32_t>(P->lgeo.EC.size());
+    g.EF = A.take<int32_t>(std::max<size_t>(1, P->lgeo.EF.size()));
+    g.mf = A.take<double>(std::max<size_t>(1, P->dmom.mf.size()));
+    g.fd = A.take<double>(std::max<size_t>(1, P->dmom.fd.size()));
+    g.foff = A.take<int64_t>(P->dmom.foff.size());
+    g.roff = P->roff;
+    g.rec = P->rec;
+    g.err = nullptr;  // set below, once the error slots are placed
+    int64_t nu = 0;
+    for (int32_t v : P->loc.nloc) nu += (int64_t)d * v + P->loc.nT;
+    P->d_user_rhs = A.take<double>(std::max<int64_t>(1, nu));
+    P->d_user_off = A.take<int64_t>(nc + 1);
+  }
   const LevelInfo &L0 = P->lev[0];
   P->stage = A.take<double>(P->pairoff[nc] * L0.bs * L0.bs);
   P->stage32 = P->opt.vcycle_copy == HHO_COPY_PRODUCT ? A.take<float>(P->pairoff[nc] * L0.bs * L0.bs) : nullptr;
@@ -414,7 +470,8 @@ static void plan(hho_problem *P, Arena &A) {
   P->cst = A.take<GmresState>(1);
   P->partial = A.take<double>(512 * (kMaxRestartH + 2));
   P->scal = A.take<double>(16);
-  P->err = A.take<int>(4);
+  P->err = A.take<int>(8);
+  if (P->local_dev) P->lg.err = P->err + 4;
 }
 
 static DLevel<double> dlev64(const hho_problem *P, int l) {
@@ -624,9 +681,44 @@ static void device_upload(hho_problem *P) {
   h2d((void *)P->tp.pairoff, P->pairoff.data(), P->pairoff.size() * 8);
   h2d((void *)P->tp.pairblk, P->pairblk.data(), P->pairblk.size() * 4);
   h2d((void *)P->tp.zmean, P->zmean.data(), P->zmean.size() * 8);
-  h2d(P->rec, P->loc.rec.data(), P->loc.rec.size() * 8);
+  if (!P->local_dev) h2d(P->rec, P->loc.rec.data(), P->loc.rec.size() * 8);
   h2d(P->roff, P->loc.off.data(), P->loc.off.size() * 8);
-  HIPCHK(hipMemsetAsync(P->err, 0, 4 * sizeof(int), s));
+  if (P->local_dev) {
+    const hho_mesh *m = P->mesh;
+    const LocalGeom &g = P->lg;
+    const LocalGeomHost &H = P->lgeo;
+    h2d((void *)g.csign, m->csign.data(), m->csign.size() * 8);
+    h2d((void *)g.fptr, m->fptr.data(), m->fptr.size() * 8);
+    h2d((void *)g.fvtx, m->fvtx.data(), m->fvtx.size() * 8);
+    h2d((void *)g.verts, m->verts.data(), m->verts.size() * 8);
+    h2d((void *)g.rptr, H.rptr.data(), H.rptr.size() * 8);
+    h2d((void *)g.ring, H.ring.data(), H.ring.size() * 8);
+    h2d((void *)g.cbox, m->cbox.data(), m->cbox.size());
+    h2d((void *)g.clo, m->clo.data(), m->clo.size() * 8);
+    h2d((void *)g.chi, m->chi.data(), m->chi.size() * 8);
+    h2d((void *)g.apex, H.apex.data(), H.apex.size() * 8);
+    h2d((void *)g.ccen, m->ccen.data(), m->ccen.size() * 8);
+    h2d((void *)g.cdiam, m->cdiam.data(), m->cdiam.size() * 8);
+    h2d((void *)g.fcen, m->fcen.data(), m->fcen.size() * 8);
+    h2d((void *)g.fdiam, m->fdiam.data(), m->fdiam.size() * 8);
+    h2d((void *)g.fnrm, m->fnrm.data(), m->fnrm.size() * 8);
+    h2d((void *)g.ft1, m->ft1.data(), m->ft1.size() * 8);
+    h2d((void *)g.ft2, m->ft2.data(), m->ft2.size() * 8);
+    h2d((void *)g.fbc, m->fbc.data(), m->fbc.size());
+    h2d((void *)g.eta, P->cell_eta_dev.data(), P->cell_eta_dev.size() * 8);
+    h2d((void *)g.glt, H.glt.data(), H.glt.size() * 8);
+    h2d((void *)g.glw, H.glw.data(), H.glw.size() * 8);
+    h2d((void *)g.EC, H.EC.data(), H.EC.size() * 4);
+    h2d((void *)g.EF, H.EF.data(), H.EF.size() * 4);
+    h2d((void *)g.mf, P->dmom.mf.data(), P->dmom.mf.size() * 8);
+    h2d((void *)g.fd, P->dmom.fd.data(), P->dmom.fd.size() * 8);
+    h2d((void *)g.foff, P->dmom.foff.data(), P->dmom.foff.size() * 8);
+    if (!P->user_rhs.empty()) {
+      h2d(P->d_user_rhs, P->user_rhs.data(), P->user_rhs.size() * 8);
+      h2d(P->d_user_off, P->user_off.data(), P->user_off.size() * 8);
+    }
+  }
+  HIPCHK(hipMemsetAsync(P->err, 0, 8 * sizeof(int), s));
   // nullspace vector (constant pressure on the level-0 mean modes)
   const LevelInfo &L0 = P->lev[0];
   P->zhost.assign(L0.N, 0.0);
@@ -690,14 +782,55 @@ static void device_upload(hho_problem *P) {
   P->uploaded = true;
 }
 
+// the caller's right-hand-side moments (hho_set_moments) over the device build's
+__global__ void k_user_rhs(int d, int nT, const int64_t *roff, const int64_t *uoff, const double *u, double *rec) {
+  const int64_t c = blockIdx.x;
+  const int64_t len = uoff[c + 1] - uoff[c];       // d nloc + nT
+  const int64_t nloc = (len - nT) / d;
+  double *dst = rec + roff[c] + nloc * nloc + (int64_t)d * nT * nloc;
+  for (int64_t e = threadIdx.x; e < len; e += blockDim.x) dst[e] = u[uoff[c] + e];
+}
+
+// Whether the local operators are built on the device: options.local_build, and
+// for AUTO the device build's limits (every rhs_u entry of a cell on its own
+// thread, the cell's work arrays within the compute unit's LDS, quadrature
+// within the node table).
+static bool choose_local_device(hho_problem *P, int qdeg) {
+  const int mode = P->opt.local_build;
+  if (mode == HHO_LOCAL_HOST) return false;
+  const int d = P->d, k = P->k;
+  const int odeg = std::min(qdeg, 2 * k + 2);
+  const int nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
+  const int nloc_max = nT + P->mesh->max_faces * nF;
+  std::string why;
+  if ((odeg + 4) / 2 >= kGlTable) why = "quadrature degree above the node table";
+  if (why.empty() && d * nloc_max > 256) why = "more than 256 velocity unknowns in a cell";
+  if (why.empty()) {
+    build_local_geometry(P->mesh, k, qdeg, &P->lgeo);
+    P->llds = local_lds(d, k, P->mesh->max_faces, P->lgeo.max_nq, P->lgeo.max_nqf);
+    if (P->llds.bytes > kMaxLdsBytes - 2048) why = "a cell's work arrays exceed the LDS";
+  }
+  if (why.empty()) return true;
+  if (mode == HHO_LOCAL_DEVICE) fail(HHO_E_INVALID_ARG, "local_build DEVICE: " + why);
+  return false;
+}
+
 static void device_setup(hho_problem *P) {
   hipStream_t s = P->stream;
   const hho_mesh *m = P->mesh;
   const int64_t nc = m->nc;
   if (!P->uploaded) device_upload(P);
-  HIPCHK(hipMemsetAsync(P->err, 0, 4 * sizeof(int), s));
-  hipEvent_t ev[8];
+  HIPCHK(hipMemsetAsync(P->err, 0, 8 * sizeof(int), s));
+  hipEvent_t ev[8], evl;
   for (auto &e : ev) HIPCHK(hipEventCreate(&e));
+  HIPCHK(hipEventCreate(&evl));
+  HIPCHK(hipEventRecord(evl, s));
+  if (P->local_dev) {  // local operators of every cell, then the caller's moments if any
+    launch_local(P->lg, P->llds, (int)nc, s);
+    if (!P->user_rhs.empty())
+      hipLaunchKernelGGL(k_user_rhs, dim3((unsigned)nc), dim3(256), 0, s, P->d, P->loc.nT, P->roff,
+                         (const int64_t *)P->d_user_off, (const double *)P->d_user_rhs, P->rec);
+  }
   HIPCHK(hipEventRecord(ev[0], s));
   LevelInfo &L0 = P->lev[0];
   // static condensation
@@ -776,9 +909,15 @@ static void device_setup(hho_problem *P) {
     HIPCHK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
     P->timings[i] = ms;
   }
+  HIPCHK(hipEventElapsedTime(&ms, evl, ev[0]));
+  P->timings[9] = ms;
   for (auto &e : ev) HIPCHK(hipEventDestroy(e));
-  int herr[4];
+  HIPCHK(hipEventDestroy(evl));
+  int herr[8];
   HIPCHK(hipMemcpy(herr, P->err, sizeof(herr), hipMemcpyDeviceToHost));
+  if (herr[4])
+    fail(HHO_E_LOCAL_SINGULAR, "local build: degenerate basis or non-SPD reconstruction stiffness in cell " +
+                                   std::to_string(herr[4] - 1));
   if (herr[0]) fail(HHO_E_LOCAL_SINGULAR, "static condensation: local block not SPD in cell " + std::to_string(herr[0] - 1));
   if (herr[1]) fail(HHO_E_LOCAL_SINGULAR, "smoother patch not invertible in cell " + std::to_string(herr[1] - 1));
   if (herr[2]) fail(HHO_E_LOCAL_SINGULAR, "coarsest-level matrix is singular");
@@ -1320,6 +1459,7 @@ void hho_options_default(hho_options *o) {
   o->smoother = HHO_SMOOTHER_SCHWARZ;
   o->nullspace = HHO_NULLSPACE_AUTO;
   o->vcycle_copy = HHO_COPY_CONVERT;
+  o->local_build = HHO_LOCAL_AUTO;
 }
 
 int hho_mesh_create(const hho_mesh_desc *desc, hho_mesh **out) {
@@ -1383,6 +1523,9 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
     hho::fail(HHO_E_INVALID_ARG, "vcycle_copy must be HHO_COPY_CONVERT or HHO_COPY_PRODUCT");
   if (P->opt.vcycle_copy == HHO_COPY_PRODUCT && (P->opt.precision == HHO_PREC_FP64 || P->deg.size() < 2))
     hho::fail(HHO_E_INVALID_ARG, "vcycle_copy PRODUCT needs an FP32 or BF16 V-cycle with at least two levels");
+  if (P->opt.local_build != HHO_LOCAL_AUTO && P->opt.local_build != HHO_LOCAL_HOST &&
+      P->opt.local_build != HHO_LOCAL_DEVICE)
+    hho::fail(HHO_E_INVALID_ARG, "local_build must be HHO_LOCAL_AUTO, HHO_LOCAL_HOST or HHO_LOCAL_DEVICE");
   if (P->opt.max_it < 1 || P->opt.coarse_max_it < 1) hho::fail(HHO_E_INVALID_ARG, "iteration limits must be >= 1");
   if (!(P->opt.rtol > 0) || !(P->opt.coarse_rtol >= 0)) hho::fail(HHO_E_INVALID_ARG, "tolerances must be > 0");
   const int d = P->d;
@@ -1432,8 +1575,16 @@ int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_fi
   ABI_BEGIN
   if (!p) hho::fail(HHO_E_INVALID_ARG, "set_data: NULL problem");
   int qdeg = 2 * p->k + 2 + std::max(0, p->opt.quad_extra);
-  hho::build_local(p->mesh, p->k, p->eta, p->cell_eta.empty() ? nullptr : p->cell_eta.data(), qdeg, f, gD, gN,
-                   ctx, &p->loc);
+  p->user_rhs.clear();
+  p->user_off.clear();
+  p->local_dev = hho::choose_local_device(p, qdeg);
+  if (p->local_dev) {
+    hho::build_data_moments(p->mesh, p->k, qdeg, f, gD, gN, ctx, &p->dmom, &p->loc);
+    p->cell_eta_dev = p->cell_eta.empty() ? std::vector<double>(p->mesh->nc, p->eta) : p->cell_eta;
+  } else {
+    hho::build_local(p->mesh, p->k, p->eta, p->cell_eta.empty() ? nullptr : p->cell_eta.data(), qdeg, f, gD, gN,
+                     ctx, &p->loc);
+  }
   hho::amg_levels(p);
   p->have_data = true;
   p->setup_done = false;
@@ -1586,7 +1737,17 @@ int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B,
     hho::set_error("get_local_cell: capacity too small");
     return HHO_E_CAPACITY;
   }
-  const double *r = &p->loc.rec[p->loc.off[cell]];
+  std::vector<double> dev;
+  const double *r;
+  if (p->local_dev) {  // the record the device built (after hho_setup)
+    if (!p->setup_done) hho::fail(HHO_E_INVALID_ARG, "get_local_cell: the device builds the records in hho_setup");
+    dev.resize(p->loc.off[cell + 1] - p->loc.off[cell]);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipMemcpy(dev.data(), p->rec + p->loc.off[cell], dev.size() * 8, hipMemcpyDeviceToHost));
+    r = dev.data();
+  } else {
+    r = &p->loc.rec[p->loc.off[cell]];
+  }
   if (a) std::memcpy(a, r, sizeof(double) * nloc * nloc);
   r += (int64_t)nloc * nloc;
   if (B) std::memcpy(B, r, sizeof(double) * d * nT * nloc);
@@ -2407,7 +2568,8 @@ static bool same_solver_options(const hho_options &a, const hho_options &b) {
          a.coarse_restart == b.coarse_restart && a.coarse_max_it == b.coarse_max_it && a.quad_extra == b.quad_extra &&
          a.coarse_amg_sweeps == b.coarse_amg_sweeps && a.learned == b.learned &&
          a.coarse_amg_explicit == b.coarse_amg_explicit && a.coarse_amg_psmooth == b.coarse_amg_psmooth &&
-         a.smoother == b.smoother && a.nullspace == b.nullspace;
+         a.smoother == b.smoother && a.nullspace == b.nullspace && a.vcycle_copy == b.vcycle_copy &&
+         a.local_build == b.local_build;
 }
 
 int hho_batch_create(hho_problem *const *ps, int n, hho_batch **out) {
@@ -2445,7 +2607,32 @@ int hho_batch_create(hho_problem *const *ps, int n, hho_batch **out) {
   B->P = P;
   rc = hho_problem_set_segments(P, n, B->foff.data(), B->coff.data());
   if (rc != HHO_OK) return rc;
-  // local operators: the members' records, concatenated in union cell order
+  // local operators: the members' records (or, for the device build, their data
+  // moments and penalties), concatenated in union cell order
+  for (int i = 0; i < n; ++i)
+    if (ps[i]->local_dev != p0->local_dev)
+      hho::fail(HHO_E_INVALID_ARG, "batch_create: members differ in where their local operators are built");
+  P->local_dev = p0->local_dev;
+  if (P->local_dev) {
+    const int64_t nfu = B->mesh->nf;
+    hho::DataMoments &D = P->dmom;
+    D = hho::DataMoments{};
+    D.foff.assign(nfu, -1);
+    P->cell_eta_dev.clear();
+    for (int i = 0; i < n; ++i) {
+      const hho_problem *q = ps[i];
+      const int64_t base = (int64_t)D.fd.size();
+      D.mf.insert(D.mf.end(), q->dmom.mf.begin(), q->dmom.mf.end());
+      D.fd.insert(D.fd.end(), q->dmom.fd.begin(), q->dmom.fd.end());
+      for (int64_t f = 0; f < q->mesh->nf; ++f)
+        if (q->dmom.foff[f] >= 0) D.foff[B->foff[i] + f] = base + q->dmom.foff[f];
+      P->cell_eta_dev.insert(P->cell_eta_dev.end(), q->cell_eta_dev.begin(), q->cell_eta_dev.end());
+      if (!q->user_rhs.empty()) hho::fail(HHO_E_INVALID_ARG, "batch_create: a member has hho_set_moments data");
+    }
+    const int qdeg = 2 * p0->k + 2 + std::max(0, p0->opt.quad_extra);
+    if (!hho::choose_local_device(P, qdeg))
+      hho::fail(HHO_E_INVALID_ARG, "batch_create: the union cannot use the device build of its members");
+  }
   hho::LocalData &L = P->loc;
   L = hho::LocalData{};
   const hho::LocalData &L0 = p0->loc;
@@ -2457,7 +2644,7 @@ int hho_batch_create(hho_problem *const *ps, int n, hho_batch **out) {
   L.off.assign(1, 0);
   for (int i = 0; i < n; ++i) {
     const hho::LocalData &Li = ps[i]->loc;
-    const int64_t base = (int64_t)L.rec.size();
+    const int64_t base = L.off.back();
     L.rec.insert(L.rec.end(), Li.rec.begin(), Li.rec.end());
     L.nloc.insert(L.nloc.end(), Li.nloc.begin(), Li.nloc.end());
     for (size_t c = 1; c < Li.off.size(); ++c) L.off.push_back(base + Li.off[c]);
@@ -2612,6 +2799,21 @@ int hho_set_moments(hho_problem *p, const double *rhs_u, const double *rhs_p) {
   hho::LocalData &L = p->loc;
   const int d = p->d, nT = L.nT;
   int64_t ou = 0;
+  if (p->local_dev) {  // kept on the host, written over the device-built records at hho_setup
+    const int64_t nc = p->mesh->nc;
+    p->user_off.assign(nc + 1, 0);
+    for (int64_t c = 0; c < nc; ++c) p->user_off[c + 1] = p->user_off[c] + (int64_t)d * L.nloc[c] + nT;
+    p->user_rhs.resize(p->user_off[nc]);
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t nl = L.nloc[c];
+      std::memcpy(&p->user_rhs[p->user_off[c]], rhs_u + ou, sizeof(double) * d * nl);
+      std::memcpy(&p->user_rhs[p->user_off[c] + d * nl], rhs_p + c * nT, sizeof(double) * nT);
+      ou += d * nl;
+    }
+    p->uploaded = false;
+    p->setup_done = false;
+    return HHO_OK;
+  }
   for (int64_t c = 0; c < p->mesh->nc; ++c) {
     const int64_t nl = L.nloc[c];
     double *r = L.rec.data() + L.off[c] + nl * nl + (int64_t)d * nT * nl;  // [rhs_u (d*nloc) | rhs_p (nT)]

@@ -103,7 +103,7 @@ def test_host_local_operators_match_oracle(mesh, k):
     from oracle.hho import mesh_geometry, local_hho
     from oracle.solve import default_eta
     data = problem_data(polynomial_stokes(mesh.dim, k, 5), None, mesh.dim)
-    P = H.Problem(H.Mesh(mesh), k, "v")
+    P = H.Problem(H.Mesh(mesh), k, "v", local_build="host")
     P.set_data(*data)
     geo = mesh_geometry(mesh, k)
     for c in range(mesh.n_cells):
@@ -158,10 +158,10 @@ def test_batch_members_take_their_own_penalty():
     quads, vor = cartesian_quads(3), voronoi_lloyd(20, 4)
     fields = [problem_data(polynomial_stokes(2, 2, 5 + i), None, 2) for i in range(2)]
     U, fo, co = H.Mesh.union([quads, shifted(vor, 2.0)])
-    P = H.Problem(U, 1, "v")
+    P = H.Problem(U, 1, "v", local_build="host")
     P.set_segments(fo, co)
     P.set_data(*region_fields(fields, 2, 2.0))
-    A = H.Problem(H.Mesh(quads), 1, "v")
+    A = H.Problem(H.Mesh(quads), 1, "v", local_build="host")
     A.set_data(*fields[0])
     for c in range(quads.n_cells):
         u, a = P.local_cell(c), A.local_cell(c)
@@ -184,7 +184,7 @@ def test_moments_replace_the_local_right_hand_sides():
     H, _ = _lib()
     mesh = voronoi_lloyd(12, 3)
     k = 2
-    P = H.Problem(H.Mesh(mesh), k, "v")
+    P = H.Problem(H.Mesh(mesh), k, "v", local_build="host")
     P.set_data(None, None, None)
     before = [P.local_cell(c) for c in range(mesh.n_cells)]
     nu, npp = P.moments_size()
@@ -203,7 +203,7 @@ def test_moments_replace_the_local_right_hand_sides():
         off += 2 * nloc[c]
     with pytest.raises(ValueError):
         P.set_moments(ru[:-1], rp)
-    Q = H.Problem(H.Mesh(mesh), k, "v")
+    Q = H.Problem(H.Mesh(mesh), k, "v", local_build="host")
     with pytest.raises(H.HHOError):                 # operators not built yet
         Q.moments_size()
 
@@ -215,7 +215,7 @@ def test_batch_from_separate_problems_validation_and_sizes():
     meshes = [cartesian_quads(3), voronoi_lloyd(20, 4), cartesian_quads(2)]
     probs = []
     for i, m in enumerate(meshes):
-        Q = H.Problem(H.Mesh(m), 2, "v", coarse_mode="amg")
+        Q = H.Problem(H.Mesh(m), 2, "v", coarse_mode="amg", local_build="host")
         Q.set_data(*problem_data(polynomial_stokes(2, 2, i), None, 2))
         probs.append(Q)
     B = H.Batch(probs)
