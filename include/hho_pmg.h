@@ -99,7 +99,7 @@ extern "C" {
 #define HHO_NULLSPACE_NONE  1   /* never projected (the caller's right-hand side must be consistent) */
 
 /* where the local operators of Sections 2.2-2.3 are built (hho_problem_set_data) */
-#define HHO_LOCAL_AUTO    0   /* on the device when its limits hold (a cell's velocity unknowns d*nloc <= 256,
+#define HHO_LOCAL_AUTO    0   /* on the device when its limits hold (a cell's velocity unknowns d*nloc <= 1024,
                                  its work arrays within the LDS), on the host otherwise */
 #define HHO_LOCAL_HOST    1   /* on the host, at hho_problem_set_data */
 #define HHO_LOCAL_DEVICE  2   /* on the device, at hho_setup; set_data fails if the limits do not hold */

@@ -199,7 +199,8 @@ void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T
 void launch_sum_finish(int G, const double *partial, double *out, hipStream_t s);
 
 // ---- local HHO operators on the device (one workgroup per cell)
-constexpr int kGlTable = 16;  // Gauss-Legendre table stride: n = 1 .. 15 points
+constexpr int kGlTable = 16;       // Gauss-Legendre table stride: n = 1 .. 15 points
+constexpr int kLocalThreads = 1024;  // most threads of a cell's workgroup (every rhs_u entry has its own)
 struct LocalGeom {
   int d, k, N1, nT, nF, odeg;
   const int32_t *cptr, *cface;  // cell -> faces (the topology's)
@@ -222,7 +223,7 @@ struct LocalGeom {
 };
 struct LocalLds {  // LDS layout of the local build (offsets in doubles)
   int C, K, Bc, G, Pi, Nn, gpo, red, rv, gto, scr;
-  int max_nq, max_nqf, nloc_max, chunk;
+  int max_nq, max_nqf, nloc_max, chunk, threads;
   size_t bytes;
 };
 LocalLds local_lds(int d, int k, int max_faces, int max_nq, int max_nqf);

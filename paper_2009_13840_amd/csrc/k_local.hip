@@ -25,7 +25,6 @@
 namespace hho {
 namespace {
 
-constexpr int kLocalThreads = 256;
 
 __device__ inline void lvtx(const LocalGeom &g, int64_t v, double p[3]) {
   for (int q = 0; q < 3; ++q) p[q] = q < g.d ? g.verts[v * g.d + q] : 0.0;
@@ -52,12 +51,13 @@ __device__ inline double dmono(const int32_t *E, int d, const double *xi, double
   return v;
 }
 
-// block-wide sum returned to every thread (red: 16 doubles; slot 15 carries the result)
+// block-wide sum returned to every thread (red: 32 doubles; slots 0..15 take the
+// waves' partials, slot 31 carries the result)
 __device__ inline double lsum(double v, double *red) {
   const double r = block_sum(v, red);
-  if (threadIdx.x == 0) red[15] = r;
+  if (threadIdx.x == 0) red[31] = r;
   __syncthreads();
-  return red[15];
+  return red[31];
 }
 
 // Operator quadrature point q of cell c: position and weight (the rules of the
@@ -246,7 +246,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
 
   // ---- cell phase: points, orthonormal cell basis, stiffness and the cell part of the coupling
   const int nq = cell_npoints(g, c);
-  double *X = S, *W = X + 3 * L.max_nq, *M = W + L.max_nq, *GB = M + (int64_t)L.max_nq * N1;
+  double *X = S, *W = X + 3 * L.max_nq, *M = W + L.max_nq, *GBm = M + (int64_t)L.max_nq * N1,
+         *GB = GBm + (int64_t)L.chunk * N1 * d;
   for (int q = threadIdx.x; q < nq; q += blockDim.x) {
     double x[3], w;
     cell_point(g, c, q, x, &w);
@@ -274,22 +275,25 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
   const int P = L.chunk;
   for (int q0 = 0; q0 < nq; q0 += P) {
     const int np = min(P, nq - q0);
-    // monomial gradients, then in place (descending in i) the basis gradients
+    // monomial gradients, then the basis gradients (every thread takes entries)
     for (int e = threadIdx.x; e < np * N1 * d; e += blockDim.x) {
       const int qq = e / (N1 * d), j = (e / d) % N1, a = e % d;
       double xi[3];
       for (int b = 0; b < d; ++b) xi[b] = (X[3 * (q0 + qq) + b] - x0[b]) / h;
-      GB[e] = dmono(g.EC, d, xi, h, j, a);
+      GBm[e] = dmono(g.EC, d, xi, h, j, a);
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < np * d; e += blockDim.x) {
-      const int qq = e / d, a = e % d;
-      double *row = GB + (int64_t)qq * N1 * d + a;
-      for (int i = N1 - 1; i >= 0; --i) {
-        double s = 0;
-        for (int m = 0; m <= i; ++m) s += Cc[i * N1 + m] * row[m * d];
-        row[i * d] = s;
+    for (int e = threadIdx.x; e < np * N1 * d; e += blockDim.x) {
+      const int qq = e / (N1 * d), i = (e / d) % N1, a = e % d;
+      const double *row = GBm + (int64_t)qq * N1 * d + a, *ci = Cc + i * N1;
+      double s0 = 0, s1 = 0;
+      int m = 0;
+      for (; m + 1 <= i; m += 2) {
+        s0 += ci[m] * row[m * d];
+        s1 += ci[m + 1] * row[(m + 1) * d];
       }
+      if (m <= i) s0 += ci[m] * row[m * d];
+      GB[e] = s0 + s1;
     }
     __syncthreads();
     for (int e = threadIdx.x; e < N1 * N1; e += blockDim.x) {
@@ -328,7 +332,8 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
     for (int a = 0; a < 3; ++a) n[a] = sg * g.fnrm[3 * f + a];
     const int nqf = face_npoints(g, f);
     double *Xf = S, *Wf = Xf + 3 * L.max_nqf, *Psi = Wf + L.max_nqf, *Phf = Psi + (int64_t)L.max_nqf * nF,
-           *Gn = Phf + (int64_t)L.max_nqf * N1, *CF = Gn + (int64_t)L.max_nqf * N1;
+           *Gn = Phf + (int64_t)L.max_nqf * N1, *CF = Gn + (int64_t)L.max_nqf * N1, *Mm = CF + nF * nF,
+           *Dmm = Mm + (int64_t)L.max_nqf * N1;
     const double hF = g.fdiam[f];
     double xF[3], t1[3], t2[3];
     for (int a = 0; a < 3; ++a) {
@@ -346,31 +351,36 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
     }
     __syncthreads();
     // face monomials, cell monomials and their normal derivatives at the face points
-    for (int q = threadIdx.x; q < nqf; q += blockDim.x) {
-      const double r[3] = {Xf[3 * q] - xF[0], Xf[3 * q + 1] - xF[1], Xf[3 * q + 2] - xF[2]};
-      double xi[2];
-      xi[0] = (r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2]) / hF;
-      xi[1] = (r[0] * t2[0] + r[1] * t2[1] + r[2] * t2[2]) / hF;
-      for (int j = 0; j < nF; ++j) Psi[q * nF + j] = mono(g.EF, d - 1, xi, j);
-      double xc[3];
-      for (int a = 0; a < d; ++a) xc[a] = (Xf[3 * q + a] - x0[a]) / h;
-      double *ph = Phf + (int64_t)q * N1, *gn = Gn + (int64_t)q * N1;
-      for (int t = 0; t < N1; ++t) {
-        ph[t] = mono(g.EC, d, xc, t);
+    for (int e2 = threadIdx.x; e2 < nqf * (nF + N1); e2 += blockDim.x) {
+      const int q = e2 / (nF + N1), j = e2 % (nF + N1);
+      if (j < nF) {
+        const double r[3] = {Xf[3 * q] - xF[0], Xf[3 * q + 1] - xF[1], Xf[3 * q + 2] - xF[2]};
+        double xi[2];
+        xi[0] = (r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2]) / hF;
+        xi[1] = (r[0] * t2[0] + r[1] * t2[1] + r[2] * t2[2]) / hF;
+        Psi[q * nF + j] = mono(g.EF, d - 1, xi, j);
+      } else {
+        const int t = j - nF;
+        double xc[3];
+        for (int a = 0; a < d; ++a) xc[a] = (Xf[3 * q + a] - x0[a]) / h;
+        Mm[(int64_t)q * N1 + t] = mono(g.EC, d, xc, t);
         double dn = 0;
         for (int b = 0; b < d; ++b) dn += n[b] * dmono(g.EC, d, xc, h, t, b);
-        gn[t] = dn;
+        Dmm[(int64_t)q * N1 + t] = dn;
       }
-      // to the orthonormal cell basis, in place (row t needs the monomials m <= t)
-      for (int t = N1 - 1; t >= 0; --t) {
-        double s1 = 0, s2 = 0;
-        for (int m = 0; m <= t; ++m) {
-          s1 += Cc[t * N1 + m] * ph[m];
-          s2 += Cc[t * N1 + m] * gn[m];
-        }
-        ph[t] = s1;
-        gn[t] = s2;
+    }
+    __syncthreads();
+    // the cell basis and its normal derivative at the face points
+    for (int e2 = threadIdx.x; e2 < nqf * N1; e2 += blockDim.x) {
+      const int q = e2 / N1, t = e2 % N1;
+      const double *ct = Cc + t * N1, *mq = Mm + (int64_t)q * N1, *dq = Dmm + (int64_t)q * N1;
+      double s1 = 0, s2 = 0;
+      for (int m = 0; m <= t; ++m) {
+        s1 += ct[m] * mq[m];
+        s2 += ct[m] * dq[m];
       }
+      Phf[e2] = s1;
+      Gn[e2] = s2;
     }
     __syncthreads();
     if (!cgs2(Psi, nF, Wf, nqf, nF, CF, rv, red)) {
@@ -451,12 +461,13 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
     }
   }
   __syncthreads();
-  // consistency term (grad R u, grad R v)_T = Y^T Y
+  // consistency term (grad R u, grad R v)_T = Y^T Y, kept in LDS until the record is written
+  double *Al = S + 2LL * nF * L.nloc_max;
   for (int e = threadIdx.x; e < nloc * nloc; e += blockDim.x) {
     const int a = e / nloc, b = e % nloc;
     double s = 0;
     for (int t = 1; t < N1; ++t) s += G[t * nloc + a] * G[t * nloc + b];
-    A[e] = s;
+    Al[e] = s;
   }
   __syncthreads();
   // R = L^{-T} Y; the constant function's row is e_0
@@ -511,14 +522,14 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
       const int a = e2 / nloc, b = e2 % nloc;
       double s = 0;
       for (int j = 0; j < nF; ++j) s += Dm[j * nloc + a] * Dm[j * nloc + b];
-      double v = A[e2] + s / hF;
+      double v = Al[e2] + s / hF;
       if (bc == HHO_FACE_DIRICHLET) {
         const int fa = a - nT - fi * nF, fb = b - nT - fi * nF;
         if (fa >= 0 && fa < nF) v -= NR[fa * nloc + b];
         if (fb >= 0 && fb < nF) v -= NR[fb * nloc + a];
         if (fa >= 0 && fa < nF && a == b) v += eta * ih;
       }
-      A[e2] = v;
+      Al[e2] = v;
     }
     if (threadIdx.x < d * nloc) {
       const int fj = ub - nT - fi * nF;
@@ -540,6 +551,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
   }
   if (threadIdx.x < d * nloc) ru[threadIdx.x] = acc_u;
   if (threadIdx.x < nT) rp[threadIdx.x] = acc_p;
+  for (int e = threadIdx.x; e < nloc * nloc; e += blockDim.x) A[e] = Al[e];
 
   // ---- coupling: cell part (v_T,cc, d_cc q)_T, face part -(v_F . n, q)_F off Dirichlet faces
   for (int e = threadIdx.x; e < d * nT * nloc; e += blockDim.x) {
@@ -568,7 +580,7 @@ void launch_local(const LocalGeom &g, const LocalLds &L, int nc, hipStream_t s) 
                                (int)(kMaxLdsBytes - 1024));
   });
   if (attr != hipSuccess) fail(HHO_E_DEVICE, "local build: cannot reserve LDS");
-  hipLaunchKernelGGL(k_local, dim3(nc), dim3(kLocalThreads), L.bytes, s, g, L);
+  hipLaunchKernelGGL(k_local, dim3(nc), dim3(L.threads), L.bytes, s, g, L);
 }
 
 static int64_t choose(int n, int k) {
@@ -599,14 +611,21 @@ LocalLds local_lds(int d, int k, int max_faces, int max_nq, int max_nqf) {
   L.Pi = take((int64_t)max_faces * nF * N1);
   L.Nn = take((int64_t)max_faces * nF * N1);
   L.gpo = take((int64_t)max_faces * d * nF);
-  L.red = take(16);
+  L.red = take(32);
   L.rv = take(N1);
   L.gto = take((int64_t)d * N1);
-  const int64_t cell = 4LL * max_nq + (int64_t)max_nq * N1 + (int64_t)L.chunk * N1 * d;
-  const int64_t face = 4LL * max_nqf + (int64_t)max_nqf * nF + 2LL * max_nqf * N1 + (int64_t)nF * nF;
-  const int64_t stab = 2LL * nF * nlocmax;
+  const int64_t cell = 4LL * max_nq + (int64_t)max_nq * N1 + 2LL * L.chunk * N1 * d;
+  const int64_t face = 4LL * max_nqf + (int64_t)max_nqf * nF + 4LL * max_nqf * N1 + (int64_t)nF * nF;
+  const int64_t stab = 2LL * nF * nlocmax + (int64_t)nlocmax * nlocmax;
   L.scr = take(std::max(cell, std::max(face, stab)));
   L.bytes = (size_t)o * sizeof(double);
+  // Latency decides the speed (every phase is a chain of short LDS-bound loops):
+  // a cell whose work arrays leave room for a second workgroup on the compute
+  // unit runs with 256 threads, two or more cells per unit; a cell that takes the
+  // unit alone gets 1024 threads (16 waves) to hide the latency itself.  Every
+  // rhs_u entry needs its own thread.
+  L.threads = L.bytes > kMaxLdsBytes / 2 ? 1024 : 256;
+  while (L.threads < d * nlocmax && L.threads < kLocalThreads) L.threads *= 2;
   return L;
 }
 

@@ -793,7 +793,7 @@ __global__ void k_user_rhs(int d, int nT, const int64_t *roff, const int64_t *uo
 
 // Whether the local operators are built on the device: options.local_build, and
 // for AUTO the device build's limits (every rhs_u entry of a cell on its own
-// thread, the cell's work arrays within the compute unit's LDS, quadrature
+// thread of its workgroup, the cell's work arrays within the compute unit's LDS, quadrature
 // within the node table).
 static bool choose_local_device(hho_problem *P, int qdeg) {
   const int mode = P->opt.local_build;
@@ -804,7 +804,7 @@ static bool choose_local_device(hho_problem *P, int qdeg) {
   const int nloc_max = nT + P->mesh->max_faces * nF;
   std::string why;
   if ((odeg + 4) / 2 >= kGlTable) why = "quadrature degree above the node table";
-  if (why.empty() && d * nloc_max > 256) why = "more than 256 velocity unknowns in a cell";
+  if (why.empty() && d * nloc_max > kLocalThreads) why = "more velocity unknowns in a cell than threads";
   if (why.empty()) {
     build_local_geometry(P->mesh, k, qdeg, &P->lgeo);
     P->llds = local_lds(d, k, P->mesh->max_faces, P->lgeo.max_nq, P->lgeo.max_nqf);

@@ -11,6 +11,7 @@ normals ``nrm`` [n, d]) and returns an [n, d] (vector) or [n] (scalar) array.
 """
 from __future__ import annotations
 
+import os
 from dataclasses import dataclass
 from itertools import product
 from typing import Callable, Optional
@@ -37,15 +38,26 @@ class TrigSeries:
         # coefficients reshape to [out, m, ..., m] and the sum contracts one axis at a time
         A = self.a.reshape((-1,) + (m,) * d)
         B = self.b.reshape((-1,) + (m,) * d)
-        for s0 in range(0, n, 1 << 16):              # bounded temporaries
-            ang = (np.pi * x[s0:s0 + (1 << 16)])[:, :, None] * freq  # [p, d, m]
+
+        def block(s0):
+            ang = (np.pi * x[s0:s0 + (1 << 15)])[:, :, None] * freq  # [p, d, m]
             ct, st = np.cos(ang), np.sin(ang)
-            rc = np.einsum("pk,o...k->po...", ct[:, d - 1], A)
-            rs = np.einsum("pk,o...k->po...", st[:, d - 1], B)
+            rc = np.tensordot(ct[:, d - 1], A, axes=([1], [A.ndim - 1]))   # [p, out, m, ..., m]
+            rs = np.tensordot(st[:, d - 1], B, axes=([1], [B.ndim - 1]))
             for j in range(d - 2, -1, -1):
-                rc = np.einsum("pk,po...k->po...", ct[:, j], rc)
-                rs = np.einsum("pk,po...k->po...", st[:, j], rs)
+                shape = (ang.shape[0],) + (1,) * (rc.ndim - 2) + (m,)
+                rc = (rc * ct[:, j].reshape(shape)).sum(axis=-1)
+                rs = (rs * st[:, j].reshape(shape)).sum(axis=-1)
             out[s0:s0 + ang.shape[0]] = rc + rs
+
+        starts = range(0, n, 1 << 15)                 # bounded temporaries, blocks on threads
+        if n > (1 << 17):
+            from concurrent.futures import ThreadPoolExecutor
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(block, starts))
+        else:
+            for s0 in starts:
+                block(s0)
         return out
 
 

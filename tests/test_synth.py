@@ -44,3 +44,20 @@ def test_batch_spec_reproducible_and_bounded():
     ks = np.array([k for _, k, _ in s1])
     assert sides.min() >= 16 and sides.max() <= 96 and ks.min() >= 1 and ks.max() <= 4
     assert len({seed for _, _, seed in s1}) == 256
+
+
+def test_trig_series_matches_its_definition():
+    """The contracted evaluation equals the sum over alpha written out, in 2D and 3D,
+    on enough points to take the threaded blocks."""
+    rng = np.random.default_rng(5)
+    for dim in (2, 3):
+        T = trig_series(dim, 11)
+        x = rng.random((300_000, dim))
+        y = T(x)
+        idx = rng.integers(0, x.shape[0], 64)
+        xs = x[idx]
+        ref = np.zeros((64, dim))
+        for i, al in enumerate(T.alphas):
+            ref += np.outer(np.prod(np.cos(np.pi * al * xs), axis=1), T.a[:, i])
+            ref += np.outer(np.prod(np.sin(np.pi * al * xs), axis=1), T.b[:, i])
+        assert np.abs(y[idx] - ref).max() <= 1e-12 * np.abs(ref).max()
