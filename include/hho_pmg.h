@@ -186,6 +186,18 @@ void hho_problem_destroy(hho_problem *p);
  * HHO_E_LOCAL_SINGULAR (reconstruction matrix not SPD). */
 int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_field_fn gN, void *ctx);
 
+/* enable = 1: every V-cycle of hho_solve (and of the calls that apply it) is
+ * replayed from a HIP graph captured at its first use (captured again after
+ * hho_bind_workspace or a change of precision, smoothing steps, learned
+ * smoother or coarse limits).  Inside the graph the coarse GMRES takes at most
+ * min(coarse_restart, coarse_max_it) columns per V-cycle with no restart and
+ * tests convergence on the device, so the host issues one launch per V-cycle
+ * and reads nothing during it; while the eager coarse solve needs no restart,
+ * both give the same iterates.  enable = 0 (default): eager launches.  The
+ * graph reads the workspace, so hho_setup with new data keeps it valid; the
+ * coarse iteration count of hho_get_timings omits the captured iterations. */
+int hho_set_graph(hho_problem *p, int enable);
+
 /* Right-hand sides given directly as moments, replacing the data terms that
  * hho_problem_set_data integrated (for instance moments computed elsewhere in
  * the library's bases).  Per cell T, in mesh order: rhs_u holds d*nloc_T values,

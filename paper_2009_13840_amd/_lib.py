@@ -28,7 +28,7 @@ LOCAL = {"auto": 0, "host": 1, "device": 2}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
-           "hho_set_stream", "hho_setup", "hho_level_size", "hho_solve", "hho_solve_device", "hho_solution_sizes",
+           "hho_set_stream", "hho_set_graph", "hho_setup", "hho_level_size", "hho_solve", "hho_solve_device", "hho_solution_sizes",
            "hho_moments_size", "hho_set_moments", "hho_batch_create", "hho_batch_destroy", "hho_batch_problem",
            "hho_batch_sizes", "hho_batch_solve", "hho_learned_save", "hho_learned_load", "hho_get_rhs", "hho_get_condensed_cell",
            "hho_get_local_cell", "hho_level_apply", "hho_vcycle_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
@@ -90,6 +90,7 @@ def load():
         "hho_workspace_size": ([P, C.POINTER(C.c_size_t)], I32),
         "hho_bind_workspace": ([P, P, C.c_size_t], I32),
         "hho_set_stream": ([P, P], I32),
+        "hho_set_graph": ([P, I32], I32),
         "hho_setup": ([P], I32),
         "hho_level_size": ([P, I32, C.POINTER(I64)], I32),
         "hho_solve": ([P, D, I64, D, I64, C.POINTER(C.c_int), D, I32, D], I32),
@@ -293,6 +294,10 @@ class Problem:
         nT = comb(self.k + d, d)
         return {"a": a[:n * n].reshape(n, n).copy(), "B": B[:d * nT * n].reshape(d, nT, n).copy(),
                 "rhs_u": ru[:d * n].reshape(d, n).copy(), "rhs_p": rp[:nT].copy()}
+
+    def set_graph(self, on: bool = True):
+        """Replay every V-cycle from a captured HIP graph (hho_set_graph)."""
+        _check(load().hho_set_graph(self.h, 1 if on else 0))
 
     def workspace_size(self) -> int:
         s = C.c_size_t()

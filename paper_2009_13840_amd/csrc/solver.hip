@@ -153,6 +153,12 @@ struct hho_problem {
   std::vector<std::vector<double>> seg_hist_h;  // per-member residual estimates of the last batched solve
   bool opt_seg_hist = false;                     // record them (hho_batch_solve with histories)
   std::vector<double> seg_rel;
+  // the V-cycle as a replayed HIP graph (hho_set_graph)
+  bool graph_on = false, in_capture = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  int64_t gkey = -1;
+  hipStream_t cap_stream = nullptr;  // captures (the caller's stream may be the legacy one)
   // local operators built on the device (options.local_build)
   bool local_dev = false;
   DataMoments dmom;
@@ -1087,6 +1093,76 @@ static void coarse_solve_seg(hho_problem *P) {
   P->coarse_its += its;
 }
 
+// The coarse GMRES inside a captured V-cycle: one cycle of at most
+// coarse_restart columns with no host read and no restart; once the process (or,
+// in a batch, every member's) has converged the remaining columns' kernels return
+// at once on the device, and the correction is formed from the columns taken.
+// While the eager solve does not restart, the two take the same steps.
+static void coarse_solve_fixed(hho_problem *P) {
+  hipStream_t s = P->stream;
+  const int Lc = P->nlev - 1;
+  LevelInfo &L = P->lev[Lc];
+  VBufs<double> &V = L.v64;
+  const DLevel<double> D = dlev64(P, Lc);
+  const int64_t n = L.N;
+  const int R = std::min(P->opt.coarse_restart, P->opt.coarse_max_it);
+  launch_fill<double>(n, 0.0, V.w, s);
+  if (P->nseg > 0) {
+    const int np = P->nseg;
+    const SegLevel &S = P->segl[Lc];
+    const int G = S.G();
+    GmresState *st = P->csst;
+    DLevel<double> Dq = D;
+    Dq.skip = P->call_done;
+    hipLaunchKernelGGL(k_seg_init, dim3((np + 63) / 64), dim3(64), 0, s, np, st, P->opt.coarse_rtol);
+    launch_seg_sumsq(G, S.ch, S.seg, V.b, P->seg_partial, s);
+    launch_seg_norm_finish(np, S.ptr, G, P->seg_partial, st, P->csdone, 1, s);
+    launch_seg_scale(G, S.ch, S.seg, V.b, st, P->cV, s);
+    launch_seg_all_done(np, P->csdone, P->call_done, s);
+    for (int j = 0; j < R; ++j) {
+      double *vj = P->cV + (int64_t)j * n, *zj = P->cZ + (int64_t)j * n;
+      if (P->coarse_amg) {
+        bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, zj, P->amg_nu, s, P->call_done);
+        launch_spmv<double>(P->tp, Dq, zj, nullptr, nullptr, P->cw, s);
+      } else {
+        launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
+        launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, zj, P->cw, s);
+      }
+      launch_seg_arnoldi(0, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
+      launch_seg_arnoldi(2, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
+      launch_seg_scale(G, S.ch, S.seg, P->cw, st, P->cV + (int64_t)(j + 1) * n, s);
+      launch_seg_all_done(np, P->csdone, P->call_done, s);
+    }
+    launch_seg_solve_ls(np, st, s);
+    launch_seg_combine(G, S.ch, S.seg, P->cZ, n, st, V.w, s);
+    return;
+  }
+  GmresState *st = P->cst;
+  DLevel<double> Dq = D;
+  Dq.skip = &st->done;
+  launch_norm_init<double>(n, V.b, P->partial, st, 1, s);
+  launch_scale<double>(n, V.b, &st->inv_hnext, P->cV, s);
+  for (int j = 0; j < R; ++j) {
+    double *vj = P->cV + (int64_t)j * n;
+    if (P->coarse_amg) {
+      bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, P->cZ + (int64_t)j * n, P->amg_nu, s, &st->done);
+      launch_spmv<double>(P->tp, Dq, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s);
+    } else {
+      launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
+      launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+    }
+    if (j + 2 <= 64) {
+      launch_arnoldi_cgs1<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
+    } else {
+      launch_arnoldi_dots<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
+      launch_arnoldi_update<double>(n, j, P->cV, n, P->cw, P->partial, st, 2, 0, s);
+      launch_scale<double>(n, P->cw, &st->inv_hnext, P->cV + (int64_t)(j + 1) * n, s);
+    }
+  }
+  launch_gmres_solve_ls(st, s);
+  launch_gmres_combine<double>(n, P->cZ, n, st, V.w, s);
+}
+
 // coarsest level: lev[Lc].v64.b -> lev[Lc].v64.w (FP64)
 static void coarse_solve(hho_problem *P) {
   hipStream_t s = P->stream;
@@ -1095,6 +1171,10 @@ static void coarse_solve(hho_problem *P) {
   VBufs<double> &V = L.v64;
   if (P->coarse_dense) {
     launch_dense_matvec(P->dense, P->dense_n, 2 * P->dense_n, P->border, V.b, V.w, s);
+    return;
+  }
+  if (P->in_capture) {
+    coarse_solve_fixed(P);
     return;
   }
   if (P->nseg > 0) {
@@ -1158,28 +1238,78 @@ static void coarse_solve(hho_problem *P) {
   P->coarse_its += its;
 }
 
+// The V-cycle from lev[0]'s input vector (v64.b, or v32.b below FP64) to its
+// output (.w); the part of apply_vcycle that a HIP graph captures.
+static void vcycle_body(hho_problem *P) {
+  if (P->nlev == 1)
+    coarse_solve(P);
+  else if (P->opt.precision == HHO_PREC_BF16)
+    vcycle<PrecB16>(P, 0);
+  else if (P->opt.precision == HHO_PREC_FP32)
+    vcycle<PrecF32>(P, 0);
+  else
+    vcycle<PrecF64>(P, 0);
+}
+
+void drop_graph(hho_problem *P) {
+  if (P->gexec) (void)hipGraphExecDestroy(P->gexec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  P->gexec = nullptr;
+  P->graph = nullptr;
+  P->gkey = -1;
+}
+
+// what the captured kernels depend on besides the workspace addresses
+static int64_t graph_key(const hho_problem *P) {
+  return (((((int64_t)P->opt.precision * 2 + (P->learned_on ? 1 : 0)) * 4 + P->opt.smooth_its) * 128 +
+           P->opt.coarse_restart) * 4096 + P->opt.coarse_max_it) * 4 + P->amg_nu;
+}
+
+// Replays the captured V-cycle on the library's stream, capturing it first
+// (again after an option that changes its kernels).  The capture records every
+// launch of the V-cycle from a stream of the library's own (the caller's may be
+// the legacy stream, which cannot be captured); probes are off while capturing.
+static void vcycle_graph(hho_problem *P) {
+  hipStream_t s = P->stream;
+  if (!P->gexec || P->gkey != graph_key(P)) {
+    drop_graph(P);
+    if (!P->cap_stream) HIPCHK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+    const unsigned mask = P->probe.mask;
+    P->probe.mask = 0;
+    P->in_capture = true;
+    P->stream = P->cap_stream;
+    hipError_t e = hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+      vcycle_body(P);
+      e = hipStreamEndCapture(P->cap_stream, &P->graph);
+    }
+    P->stream = s;
+    P->in_capture = false;
+    P->probe.mask = mask;
+    HIPCHK(e);
+    HIPCHK(hipGraphInstantiate(&P->gexec, P->graph, nullptr, nullptr, 0));
+    P->gkey = graph_key(P);
+  }
+  HIPCHK(hipGraphLaunch(P->gexec, s));
+}
+
 // x = V-cycle(b) on level 0, b and x FP64 (device)
 static void apply_vcycle(hho_problem *P, const double *b, double *x) {
   hipStream_t s = P->stream;
   LevelInfo &L0 = P->lev[0];
-  if (P->nlev == 1) {
-    launch_copy<double>(L0.N, b, L0.v64.b, s);
-    coarse_solve(P);
-    launch_copy<double>(L0.N, L0.v64.w, x, s);
-    return;
-  }
-  if (P->opt.precision != HHO_PREC_FP64) {
+  const bool low = P->nlev > 1 && P->opt.precision != HHO_PREC_FP64;
+  if (low)
     launch_convert<float, double>(b, L0.v32.b, L0.N, s);
-    if (P->opt.precision == HHO_PREC_BF16)
-      vcycle<PrecB16>(P, 0);
-    else
-      vcycle<PrecF32>(P, 0);
-    launch_convert<double, float>(L0.v32.w, x, L0.N, s);
-  } else {
+  else
     launch_copy<double>(L0.N, b, L0.v64.b, s);
-    vcycle<PrecF64>(P, 0);
+  if (P->graph_on)
+    vcycle_graph(P);
+  else
+    vcycle_body(P);
+  if (low)
+    launch_convert<double, float>(L0.v32.w, x, L0.N, s);
+  else
     launch_copy<double>(L0.N, L0.v64.w, x, s);
-  }
 }
 
 // ------------------------------------------------------------ FGMRES
@@ -1567,6 +1697,8 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
 
 void hho_problem_destroy(hho_problem *p) {
   if (!p) return;
+  hho::drop_graph(p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   if (p->h_st) (void)hipHostFree(p->h_st);
   delete p;
 }
@@ -1614,12 +1746,22 @@ int hho_bind_workspace(hho_problem *p, void *dev_ptr, size_t bytes) {
   }
   hho::Arena A;
   A.base = (char *)(((uintptr_t)dev_ptr + 255) & ~(uintptr_t)255);
+  hho::drop_graph(p);  // captured addresses change with the workspace
   hho::plan(p, A);
   p->ws = (char *)dev_ptr;
   p->ws_bytes = bytes;
   p->bound = true;
   p->setup_done = false;
   if (!p->h_st) HIPCHK(hipHostMalloc((void **)&p->h_st, sizeof(hho::GmresState)));
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_set_graph(hho_problem *p, int enable) {
+  ABI_BEGIN
+  if (!p || (enable != 0 && enable != 1)) hho::fail(HHO_E_INVALID_ARG, "set_graph: bad argument");
+  p->graph_on = enable == 1;
+  if (!p->graph_on) hho::drop_graph(p);
   return HHO_OK;
   ABI_END
 }

@@ -38,13 +38,16 @@ def region_fields(fields, dim: int, width: float):
         def cb(x, *rest):
             out = np.zeros((x.shape[0], dim))
             idx = np.clip(np.floor(x[:, 0] / width + 1e-9).astype(int), 0, nmem - 1)
-            for i in np.unique(idx):
-                sel = idx == i
+            order = np.argsort(idx, kind="stable")        # the points of each member, contiguous
+            bounds = np.searchsorted(idx[order], np.arange(nmem + 1))
+            for i in range(nmem):
                 fn = fields[i][kind]
-                if fn is not None:
-                    y = x[sel].copy()
-                    y[:, 0] -= width * i
-                    out[sel] = fn(y, *[r[sel] for r in rest])
+                sel = order[bounds[i]:bounds[i + 1]]
+                if fn is None or sel.size == 0:
+                    continue
+                y = x[sel]
+                y[:, 0] -= width * i
+                out[sel] = fn(y, *[r[sel] for r in rest])
             return out
         return cb
     return make(0), make(1), make(2)

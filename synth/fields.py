@@ -33,15 +33,24 @@ class TrigSeries:
         deg = int(self.alphas.max())
         m = deg + 1
         out = np.empty((n, self.a.shape[0]))
-        freq = np.arange(m, dtype=np.float64)
         # alphas enumerate the full tensor grid {0..deg}^d with alpha_0 slowest, so the
         # coefficients reshape to [out, m, ..., m] and the sum contracts one axis at a time
         A = self.a.reshape((-1,) + (m,) * d)
         B = self.b.reshape((-1,) + (m,) * d)
 
         def block(s0):
-            ang = (np.pi * x[s0:s0 + (1 << 15)])[:, :, None] * freq  # [p, d, m]
-            ct, st = np.cos(ang), np.sin(ang)
+            th = np.pi * x[s0:s0 + (1 << 15)]                        # [p, d]
+            # cos / sin of alpha * theta for alpha = 0..deg by the angle-addition recurrences
+            ct = np.empty(th.shape + (m,))
+            st = np.empty(th.shape + (m,))
+            ct[..., 0], st[..., 0] = 1.0, 0.0
+            if m > 1:
+                c1, s1 = np.cos(th), np.sin(th)
+                ct[..., 1], st[..., 1] = c1, s1
+                for a in range(2, m):
+                    ct[..., a] = 2.0 * c1 * ct[..., a - 1] - ct[..., a - 2]
+                    st[..., a] = 2.0 * c1 * st[..., a - 1] - st[..., a - 2]
+            ang = ct
             rc = np.tensordot(ct[:, d - 1], A, axes=([1], [A.ndim - 1]))   # [p, out, m, ..., m]
             rs = np.tensordot(st[:, d - 1], B, axes=([1], [B.ndim - 1]))
             for j in range(d - 2, -1, -1):
