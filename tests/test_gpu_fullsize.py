@@ -259,3 +259,48 @@ def _check_full_size(mesh, fc, cond, nsample, seed, k=K, **opts):
     xs = xs.cpu().numpy()
     res = so.rhs(frows) - so.apply(xs, frows)
     assert np.abs(res).max() <= 2e-8 * np.linalg.norm(b), (np.abs(res).max(), np.linalg.norm(b))
+
+
+@pytest.mark.gpu
+def test_batch256_sampled_members_match_oracle():
+    """The benchmark's batch at full scale: 256 problems (Cartesian sides 16..96,
+    k 1..4, trig-series forcing seeds 4000+i), one disjoint-union problem per
+    degree with per-member FGMRES, V-cycle coefficients and coarse GMRES, FP32
+    V-cycle, solved to 1e-12.  In every degree group the two smallest members are
+    compared with the oracle's direct solve of that member alone (faces to 1e-8:
+    the member's local operators are formed on its shifted copy, which moves
+    them at rounding level), and every member meets the tolerance."""
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    from synth import cartesian_quads, trig_series
+    from synth.batch import batch_spec, shifted, region_fields
+    spec = batch_spec()
+    groups = {}
+    for i, (side, k, seed) in enumerate(spec):
+        groups.setdefault(k, []).append((i, side, seed))
+    width = 2.0
+    for k, mem in sorted(groups.items()):
+        print(f"[case] batch256 degree {k}: {len(mem)} members", flush=True)
+        meshes = [cartesian_quads(side) for (_, side, _) in mem]
+        fields = [problem_data(None, trig_series(2, seed), 2) for (_, _, seed) in mem]
+        U, fo, co = H.Mesh.union([shifted(m, width * j) for j, m in enumerate(meshes)])
+        P = H.Problem(U, k, "v", precision="fp32", rtol=1e-12)
+        P.set_segments(fo, co)
+        P.set_data(*region_fields(fields, 2, width))
+        P.bind("cuda:0")
+        P.setup()
+        x, its, hist, rel, ok = P.solve()
+        m_its, m_rel = P.batch_results()
+        assert ok and np.all(m_rel <= 1e-12), (k, m_rel.max())
+        x = x.cpu().numpy()
+        nface_total = int(fo[-1])
+        for j in sorted(range(len(mem)), key=lambda j: mem[j][1])[:2]:
+            O = OS.build(meshes[j], k, "v", fields[j], eta=None)
+            xd = OS.normalise_pressure(O, OS.solve_direct(O))
+            dp = 2 * O.lays[0].nF
+            xf = x[fo[j] * dp:fo[j + 1] * dp]
+            err = np.linalg.norm(xf - xd[:xf.size]) / np.linalg.norm(xd[:xf.size])
+            print(f"[batch256] degree {k} member {mem[j][0]} (side {mem[j][1]}): its {m_its[j]}, "
+                  f"face error vs direct {err:.1e}", flush=True)
+            assert err <= 1e-8, (k, j, err)
+        del P
