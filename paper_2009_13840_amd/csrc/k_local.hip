@@ -228,6 +228,63 @@ __device__ bool cgs2(double *V, int ldv, const double *W, int nq, int N, double 
   return true;
 }
 
+// Orders the LDS accesses of one wave's lanes: what a lane wrote before is seen by
+// every lane's later reads (a wave runs in order; this keeps the compiler's order).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// cgs2 for a small basis on few points (a face's): the first wave does it alone,
+// lane j forming the product with column j, so the column steps need no
+// workgroup barrier; one barrier publishes the result.  N <= 64.  `flag` is an
+// LDS int; returns false (on every thread) if a column is numerically zero.
+__device__ bool cgs2_wave(double *V, int ldv, const double *W, int nq, int N, double *C, double *r, int *flag) {
+  if (threadIdx.x < kWave) {
+    const int lane = threadIdx.x;
+    for (int e = lane; e < N * N; e += kWave) C[e] = (e / N == e % N) ? 1.0 : 0.0;
+    wave_sync();
+    int bad = 0;
+    for (int i = 0; i < N; ++i) {
+      for (int pass = 0; pass < 2 && i > 0; ++pass) {
+        if (lane < i) {  // r_j = (v, V_j)_W
+          double s = 0;
+          for (int q = 0; q < nq; ++q) s += W[q] * V[q * ldv + i] * V[q * ldv + lane];
+          r[lane] = s;
+        }
+        wave_sync();
+        for (int q = lane; q < nq; q += kWave) {
+          double v = V[q * ldv + i];
+          for (int j = 0; j < i; ++j) v -= r[j] * V[q * ldv + j];
+          V[q * ldv + i] = v;
+        }
+        if (lane < N) {
+          double v = C[i * N + lane];
+          for (int j = 0; j < i; ++j) v -= r[j] * C[j * N + lane];
+          C[i * N + lane] = v;
+        }
+        wave_sync();
+      }
+      double s = 0;
+      for (int q = lane; q < nq; q += kWave) s += W[q] * V[q * ldv + i] * V[q * ldv + i];
+      s = __shfl(wave_sum(s), 0, kWave);
+      const double nv = sqrt(s);
+      if (!(nv > 0)) {
+        bad = 1;
+        break;
+      }
+      const double inv = 1.0 / nv;
+      for (int q = lane; q < nq; q += kWave) V[q * ldv + i] *= inv;
+      if (lane < N) C[i * N + lane] *= inv;
+      wave_sync();
+    }
+    if (lane == 0) *flag = bad;
+  }
+  __syncthreads();
+  return *flag == 0;
+}
+
 __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L) {
   extern __shared__ double lds[];
   const int c = blockIdx.x;
@@ -383,7 +440,10 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
       Gn[e2] = s2;
     }
     __syncthreads();
-    if (!cgs2(Psi, nF, Wf, nqf, nF, CF, rv, red)) {
+    // a face of few points (2D segments) takes its basis in one wave, a larger one block-wide
+    const bool ok = nqf <= 16 ? cgs2_wave(Psi, nF, Wf, nqf, nF, CF, rv, &fail_flag)
+                              : cgs2(Psi, nF, Wf, nqf, nF, CF, rv, red);
+    if (!ok) {
       if (threadIdx.x == 0) g.err[0] = c + 1;
       return;
     }
