@@ -83,9 +83,10 @@ def make_data(spec, dim):
     return problem_data(None, trig_series(dim, spec["seed"]), dim)
 
 
-def spmv_bytes(mesh, k, cond, level_k, dtype_bytes=8):
+def spmv_bytes(mesh, k, cond, level_k, dtype_bytes=8, value_bytes=None):
     """Algorithmic bytes of one application of the level operator: every stored
-    value once, the int32 block structure, x read once and y written once."""
+    value once (value_bytes each, default the vectors' dtype_bytes), the int32
+    block structure, x read once and y written once."""
     from math import comb
     d = mesh.dim
     p = comb(level_k + d - 1, d - 1)
@@ -103,7 +104,8 @@ def spmv_bytes(mesh, k, cond, level_k, dtype_bytes=8):
     vals = nnzb * bs * bs + ncf * d * p * (t if cond == "v" else 1) + (mesh.n_cells * t * t if cond == "v" else 0)
     N = mesh.n_faces * d * p + mesh.n_cells * t
     idx = 4 * (nnzb + mesh.n_faces + 1 + ncf + mesh.n_cells + 1 + 4 * mesh.n_faces)
-    return vals * dtype_bytes + idx + 2 * N * dtype_bytes, dict(nnzb=nnzb, N=N, values=vals)
+    vb = dtype_bytes if value_bytes is None else value_bytes
+    return vals * vb + idx + 2 * N * dtype_bytes, dict(nnzb=nnzb, N=N, values=vals)
 
 
 def precond_bytes(mesh, k, cond, dtype_bytes=8):
@@ -136,10 +138,14 @@ def precond_kernel_name(mesh, k, cond):
     return f"k_precond<double, {(rows + 63) // 64}, {d if cond == 'v' else 1}>"
 
 
+STORAGE_TYPES = {"fp64": "double, double, double", "fp32": "float, float, float", "bf16": "float, hho::bf16, float"}
+
+
 def fine_kernel_name(d, k, cond, precision):
-    """Name of the fine-level operator kernel in its V-cycle (two-slot input) form."""
+    """Name of a level's operator kernel in its V-cycle (two-slot input) form, as
+    rocprofv3 lists it (arithmetic type, operator storage, smoother storage)."""
     from math import comb
-    T = "float" if precision == "fp32" else "double"
+    T = STORAGE_TYPES[precision]
     p = comb(k + d - 1, d - 1)
     if cond == "v":
         return f"k_spmv_v<{T}, {d}, {p}, {comb(k + d, d)}, true, 0>"
@@ -420,6 +426,41 @@ def _amg_bytes(kind, L, N, d):
     raise ValueError(kind)
 
 
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def local_flops(mesh, spec):
+    """Algorithmic FP64 flops of one device build of the local operators (k_local)
+    on the mesh: per cell the orthonormal basis by Gram-Schmidt twice (4 nq N1^2),
+    the basis gradients (d nq N1^2), stiffness and cell coupling (2 d nq (N1^2 +
+    nT^2)), per face the traces of the basis and its normal derivative (2 nqf
+    N1^2), the face basis (4 nqf nF^2), the reconstruction right-hand side and the
+    face mass products (2 nqf N1 (nF + nT) + 4 nqf nF N1), the Cholesky factor and
+    the two triangular solves (n1^3 / 3 + 2 n1^2 nloc), the consistency term
+    (2 n1 nloc^2) and per face the stabilisation (2 nF nloc (N1 - nT) + 2 nF
+    nloc^2); the rules are those of the device build (operator degree 2k + 2;
+    boxes for the 3D meshes used here)."""
+    from math import comb
+    d, k = mesh.dim, spec["k"]
+    N1, nT, nF = comb(k + 1 + d, d), comb(k + d, d), comb(k + d - 1, d - 1)
+    n1 = N1 - 1
+    od = 2 * k + 2
+    cptr = np.asarray(mesh.cell_ptr)
+    nfc = np.diff(cptr)
+    if d == 2:
+        nq = (nfc - 2) * ((od + 3) // 2) ** 2          # polygon fan (as many vertices as faces)
+        nqf = np.full_like(nfc, (od + 2) // 2)
+    else:
+        nq = np.full_like(nfc, ((od + 2) // 2) ** 3)   # boxes
+        nqf = np.full_like(nfc, 2 * ((od + 3) // 2) ** 2)  # quadrilateral faces: two triangles
+    nloc = nT + nfc * nF
+    f = (4 * nq * N1 ** 2 + d * nq * N1 ** 2 + 2 * d * nq * (N1 ** 2 + nT ** 2)
+         + nfc * (2 * nqf * N1 ** 2 + 4 * nqf * nF ** 2 + 2 * nqf * N1 * (nF + nT) + 4 * nqf * nF * N1)
+         + n1 ** 3 / 3 + 2 * n1 ** 2 * nloc + 2 * n1 * nloc ** 2
+         + nfc * (2 * nF * nloc * (N1 - nT) + 2 * nF * nloc ** 2))
+    return float(f.sum())
+
+
 class ByteModel:
     """Algorithmic bytes per launch of every probed kernel class, by level."""
 
@@ -428,7 +469,11 @@ class ByteModel:
         self.k, self.cond = spec["k"], spec["cond"]
         self.degrees = list(range(self.k, -1, -1))
         self.nlev = len(self.degrees)
-        self.elem = [4 if (precision == "fp32" and l < self.nlev - 1) else 8 for l in range(self.nlev)]
+        low = precision in ("fp32", "bf16")
+        self.precision = precision
+        # vectors (and smoother factors) and the operator's stored values, per level
+        self.elem = [4 if (low and l < self.nlev - 1) else 8 for l in range(self.nlev)]
+        self.val = [2 if (precision == "bf16" and l < self.nlev - 1) else self.elem[l] for l in range(self.nlev)]
         self._spmv = {}
         self.amg = []
         try:
@@ -437,16 +482,16 @@ class ByteModel:
         except Exception:
             self.amg = []
 
-    def spmv(self, level, elem):
-        key = (level, elem)
+    def spmv(self, level, elem, val=None):
+        key = (level, elem, val)
         if key not in self._spmv:
-            self._spmv[key] = spmv_bytes(self.mesh, self.k, self.cond, self.degrees[level], elem)
+            self._spmv[key] = spmv_bytes(self.mesh, self.k, self.cond, self.degrees[level], elem, val)
         return self._spmv[key]
 
     def bytes(self, kind, level):
         d = self.mesh.dim
         if kind == "operator":       # two-slot input form: one more vector read
-            b, info = self.spmv(level, self.elem[level])
+            b, info = self.spmv(level, self.elem[level], self.val[level])
             return b + info["N"] * self.elem[level]
         if kind == "smoother":
             return precond_bytes(self.mesh, self.degrees[level], self.cond, self.elem[level])
@@ -474,9 +519,10 @@ def kernel_label(kind, mesh, spec, model, level):
     d = mesh.dim
     if kind in ("operator", "smoother"):
         k = model.degrees[level]
-        T = "float" if model.elem[level] == 4 else "double"
+        form = model.precision if model.elem[level] == 4 else "fp64"
+        T = STORAGE_TYPES[form if form in STORAGE_TYPES else "fp64"]
         if kind == "operator":
-            return fine_kernel_name(d, k, spec["cond"], "fp32" if T == "float" else "fp64")
+            return fine_kernel_name(d, k, spec["cond"], form)
         p = comb(k + d - 1, d - 1)
         rows = int(np.diff(np.asarray(mesh.cell_ptr)).max()) * (p if spec["cond"] == "v" else d * p)
         return f"k_precond<{T}, {(rows + 63) // 64}, {d if spec['cond'] == 'v' else 1}>"
@@ -575,7 +621,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
         # a stride that shares a factor with the solver's periodic pattern (two
         # sweeps per coarse iteration, a host read every six) would sample one
         # phase of it, e.g. only the launches right after a host synchronisation
-        P.probe_arm(H.PROBE[dominant], PROBE_STRIDE)
+        P.probe_arm(H.PROBE[dominant], args.probe_stride)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
@@ -588,9 +634,18 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
     if probe:
         table_timed = probe_table(P, model)
         P.probe_arm(0)
-        top = max(table_timed[dominant], key=lambda r: r["ms"])["level"]
+        top = max(table_all[dominant], key=lambda r: r["ms"])["level"]
         label = kernel_label(dominant, mesh, spec, model, top)
-        roof = roofline_from(table_timed, dominant, label, workload)
+        # Per-launch durations from the step with every launch of every class
+        # stamped: they agree with the rocprofv3 trace to a few per cent.  With only
+        # the dominant class stamped (the timed steps) its launches read 1-1.5 us
+        # longer (the stamped launch's start is taken while the unstamped launch
+        # before it still drains), which the sampled record beside it shows.
+        roof = roofline_from(table_all, dominant, label, workload)
+        samp = roofline_from(table_timed, dominant, label, workload)
+        roof["measured_in"] = "untimed step with every launch of every probed class stamped"
+        roof["timed_steps_sampled"] = {kk: samp[kk] for kk in ("achieved", "frac", "timed_launches", "launches",
+                                                             "avg_launch_ms", "levels")}
     for st, (its, rel, ok, tm) in enumerate(results):
         print(f"[bench] {tag} step {st}: its={its} rel={rel:.2e} ok={ok} "
               f"{json.dumps({kk: round(v, 3) for kk, v in tm.items()})}", file=sys.stderr, flush=True)
@@ -603,6 +658,16 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
            "phase_ms": {kk: round(v, 3) for kk, v in tm.items()}, "host_set_data_s": round(t_host, 3)}
     if learned_info:
         rec["training"] = learned_info
+    if tm.get("local_ms", 0) > 0:
+        fl = local_flops(mesh, spec)
+        ach = fl / (tm["local_ms"] / 1e3) / 1e12
+        rec["roofline_local"] = {
+            "kernel": "k_local", "bound": "alu", "achieved": round(ach, 3), "peak": FP64_VECTOR_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(ach / FP64_VECTOR_PEAK_TFLOPS, 4), "flops_per_launch": int(fl),
+            "avg_launch_ms": round(tm["local_ms"], 4),
+            "note": "one launch per step (the local operators of every cell), timed by the library's events "
+                    "around it in the last timed step; the kernel is latency-bound (chains of short LDS loops "
+                    "between workgroup barriers), not ALU-bound"}
     # V-cycle roofline: algorithmic bytes of every probed launch of the probe step
     # that belongs to the V-cycle, against the V-cycle time of the last timed step
     if table_all:
@@ -640,6 +705,8 @@ def main():
                     help="coarsest-level GMRES tolerance (0: the library's default, 1e-3 in 3D and 1e-2 in 2D)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch of 256 problems in the default run")
+    ap.add_argument("--probe-stride", type=int, default=PROBE_STRIDE,
+                    help="time one launch in this many of the dominant kernel class during the timed steps")
     ap.add_argument("--modes", default="fp64,fp32,bf16,learned,graph",
                     help="comma list of the solver forms timed on the workload: fp64, fp32, bf16, learned")
     ap.add_argument("--largest", default="hex32_k3_vp",
@@ -801,6 +868,7 @@ def main():
         "recover_cells_ms": round(min(rec_ms), 3),
         "roofline": roof,
         "roofline_vcycle": rec.get("vcycle_roofline"),
+        "roofline_local": rec.get("roofline_local"),
         "largest_single_gpu": largest,
         "batch256": batch,
         "cpu_baseline": cpu,
