@@ -566,7 +566,7 @@ def roofline_from(table, kind, label, workload):
 
 
 def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=None, probe=True, copy="convert",
-             graph=False):
+             graph=False, smoother="schwarz"):
     """One configuration of the solver on the workload: host phase and upload
     (untimed), optional training of the learned smoother (untimed), warmup steps,
     then `args.steps` timed steps (setup + solve to 1e-8), each checked for
@@ -577,7 +577,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
     import paper_2009_13840_amd as H
     M = H.Mesh(mesh)
     P = H.Problem(M, spec["k"], spec["cond"], precision=precision, coarse_rtol=args.coarse_rtol,
-                  learned=1 if learned else 0, vcycle_copy=copy)
+                  learned=1 if learned else 0, vcycle_copy=copy, smoother=smoother)
     t_host = time.perf_counter()
     P.set_data(*data)
     t_host = time.perf_counter() - t_host
@@ -588,7 +588,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
     torch.cuda.synchronize()
     n0 = P.level_size(0)
     tag = (f"{workload} {precision}{' learned' if learned else ''}{' product copy' if copy == 'product' else ''}"
-           f"{' graph' if graph else ''}")
+           f"{' graph' if graph else ''}{' ilu' if smoother == 'ilu' else ''}")
     print(f"[bench] {tag}: host phase {t_host:.2f}s, workspace {P.workspace_size() / 2**30:.2f} GiB, "
           f"fine DOFs {n0}", file=sys.stderr, flush=True)
     learned_info = train_learned(P, n0) if learned else None
@@ -651,7 +651,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
               f"{json.dumps({kk: round(v, 3) for kk, v in tm.items()})}", file=sys.stderr, flush=True)
     its, rel, ok, tm = results[-1]
     vc_gdofs = n0 * tm["vcycles"] / (tm["vcycle_ms"] / 1e3) / 1e9 if tm["vcycle_ms"] > 0 else None
-    rec = {"precision": precision, "learned": learned, "vcycle_copy": copy, "graph": graph,
+    rec = {"precision": precision, "learned": learned, "vcycle_copy": copy, "graph": graph, "smoother": smoother,
            "time_to_1e8_ms": round(dt * 1e3, 3),
            "gdof_s": round(n0 / dt / 1e9, 6), "vcycle_gdof_s": round(vc_gdofs, 4) if vc_gdofs else None,
            "fgmres_its": its, "final_rel_residual": rel, "converged": not failures, "failures": failures,
@@ -707,8 +707,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batch of 256 problems in the default run")
     ap.add_argument("--probe-stride", type=int, default=PROBE_STRIDE,
                     help="time one launch in this many of the dominant kernel class during the timed steps")
-    ap.add_argument("--modes", default="fp64,fp32,bf16,learned,graph",
-                    help="comma list of the solver forms timed on the workload: fp64, fp32, bf16, learned")
+    ap.add_argument("--modes", default="fp64,fp32,bf16,learned,graph,ilu",
+                    help="comma list of the solver forms timed on the workload: fp64, fp32, bf16, learned, graph "
+                         "(V-cycle replayed from a HIP graph), ilu (the paper's ILU(0)-GMRES(2) smoother)")
     ap.add_argument("--largest", default="hex32_k3_vp",
                     help="second workload timed in FP64 and FP32 beside the headline ('none' to skip)")
     ap.add_argument("--cpu-sample-cells", type=int, default=4096)
@@ -765,9 +766,10 @@ def main():
     records, head = {}, None
     x_ref = None
     for m in modes:
-        prec = "fp64" if m in ("fp64", "learned", "graph") else m
+        prec = "fp64" if m in ("fp64", "learned", "graph", "ilu") else m
         P, x, rec, roof = run_mode(mesh, data, spec, args.workload, prec, args, learned=(m == "learned"),
-                                   x_ref=x_ref, probe=(m == head_mode), graph=(m == "graph"))
+                                   x_ref=x_ref, probe=(m == head_mode), graph=(m == "graph"),
+                                   smoother="ilu" if m == "ilu" else "schwarz")
         if x_ref is None:
             # FP64 reference for the error of every form: this problem solved again to 1e-12 (untimed)
             P.set_tolerances(1e-12, 1000, args.coarse_rtol or (1e-3 if mesh.dim == 3 else 1e-2), 300)

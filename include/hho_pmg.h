@@ -92,7 +92,11 @@ extern "C" {
                                  FP32 accumulation (couplings and coarser levels: rounded) */
 
 /* smoother preconditioner of the V-cycle's GMRES(smooth_its) steps (Section 3.3) */
-#define HHO_SMOOTHER_SCHWARZ  0   /* cell-patch additive Schwarz (the only one on the GPU) */
+#define HHO_SMOOTHER_SCHWARZ  0   /* cell-patch additive Schwarz (default) */
+#define HHO_SMOOTHER_ILU      1   /* the paper's (Section 3.3): zero-fill ILU of the level operator in the
+                                     natural ordering of its unknowns, exact, level-scheduled; FP64 V-cycle
+                                     only, no learned smoother; also preconditions the coarse GMRES
+                                     when the coarsest level is solved by it (coarse_mode GMRES) */
 
 /* treatment of the constant-pressure null space */
 #define HHO_NULLSPACE_AUTO  0   /* projected out when the boundary has no Neumann face */

@@ -25,6 +25,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
 COPY = {"convert": 0, "product": 1}
 LOCAL = {"auto": 0, "host": 1, "device": 2}
+SMOOTHER = {"schwarz": 0, "ilu": 1}
 
 EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh_destroy", "hho_problem_create",
            "hho_problem_destroy", "hho_problem_set_data", "hho_workspace_size", "hho_bind_workspace",
@@ -226,6 +227,8 @@ def options(**kw) -> Options:
             v = COPY[v] if isinstance(v, str) else v
         if k == "local_build":
             v = LOCAL[v] if isinstance(v, str) else v
+        if k == "smoother":
+            v = SMOOTHER[v] if isinstance(v, str) else v
         setattr(o, k, v)
     return o
 

@@ -198,6 +198,28 @@ void launch_mr3(int64_t n, int m, const T *z1, const T *z2, const T *z3, const T
                 T *r, double *partial, double *y, hipStream_t s);
 void launch_sum_finish(int G, const double *partial, double *out, hipStream_t s);
 
+// ---- zero-fill ILU of a level operator (natural ordering, structural pattern)
+// Rows of one face (group f) or one cell (group n_f + T) share the column list
+// gcol[gptr[g], gptr[g+1]) (sorted); row i's values start at LU[voff[i]], its
+// diagonal at LU[diag[i]]; L (unit lower) and U share the array.
+struct IluDev {
+  int64_t N, nface;
+  int d, p, t, cond;
+  const int64_t *gptr;
+  const int32_t *gcol;
+  const int64_t *voff, *diag;
+  double *LU;
+};
+// LU = the level operator's values on the pattern
+void launch_ilu_fill(const DTopo &tp, const DLevel<double> &L, const IluDev &I, hipStream_t s);
+// in-place factorisation, one launch per dependency level (lptr: host prefix of
+// the level sizes, lrows: device rows grouped by level); err = row + 1 of a zero pivot
+void launch_ilu_factor(const IluDev &I, const int32_t *lrows, const int32_t *lptr, int nlev, int maxrow, int *err,
+                       hipStream_t s);
+// z = U^{-1} L^{-1} r (forward levels lrows/lptr, backward levels urows/uptr)
+void launch_ilu_apply(const IluDev &I, const int32_t *lrows, const int32_t *lptr, int nlevL, const int32_t *urows,
+                      const int32_t *uptr, int nlevU, const double *r, double *z, hipStream_t s);
+
 // ---- local HHO operators on the device (one workgroup per cell)
 constexpr int kGlTable = 16;       // Gauss-Legendre table stride: n = 1 .. 15 points
 constexpr int kLocalThreads = 1024;  // most threads of a cell's workgroup (every rhs_u entry has its own)

@@ -1,6 +1,7 @@
 // Problem object, device workspace, setup pipeline, V-cycle, coarse solver,
 // flexible GMRES, and the C ABI entry points.
 #include <algorithm>
+#include <type_traits>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -61,6 +62,17 @@ struct LevelInfo {
   VBufs<double> v64;
   VBufs<float> v32;
   double *y;  // smoother coefficients
+};
+
+// one level's zero-fill ILU (the paper's smoother): the pattern's column list
+// per face and per cell, row offsets and diagonals, and the forward (lptr,
+// lrows) and backward (uptr, urows) dependency levels
+struct IluHost {
+  std::vector<int64_t> gptr, voff, diag;
+  std::vector<int32_t> gcol, lrows, lptr, urows, uptr;
+  int maxrow = 0;
+  IluDev dev{};
+  int32_t *d_lrows = nullptr, *d_urows = nullptr;
 };
 
 // one level's segment table of a batch (the level's vector layout: faces with
@@ -153,6 +165,9 @@ struct hho_problem {
   std::vector<std::vector<double>> seg_hist_h;  // per-member residual estimates of the last batched solve
   bool opt_seg_hist = false;                     // record them (hho_batch_solve with histories)
   std::vector<double> seg_rel;
+  // the paper's smoother: zero-fill ILU per level (options.smoother = ILU)
+  bool ilu_on = false;
+  std::vector<IluHost> ilu;  // per level; empty pattern where the level takes none
   // the V-cycle as a replayed HIP graph (hho_set_graph)
   bool graph_on = false, in_capture = false;
   hipGraph_t graph = nullptr;
@@ -189,6 +204,102 @@ static int level_t(const hho_problem *P, int k) { return P->cond == HHO_COND_V ?
 
 // Every device array of the problem, in one place: run once to size the
 // workspace (base == null) and once to hand out pointers.
+// The level takes the ILU smoother: every smoothed level, and the coarsest
+// when its solve is GMRES preconditioned by the smoother's preconditioner.
+static bool ilu_level(const hho_problem *P, int l) {
+  if (!P->ilu_on) return false;
+  const int Lc = P->nlev - 1;
+  return l < Lc || (!P->coarse_dense && !P->coarse_amg);
+}
+
+// Pattern of the level operator in the natural ordering: a face's rows share
+// the unknowns of its (at most two) cells, a cell's rows its own unknowns.
+static void build_ilu_level(hho_problem *P, int l, IluHost &H) {
+  const LevelInfo &L = P->lev[l];
+  const int d = P->d, p = L.p, t = L.t, dp = d * p;
+  const int64_t nf = P->mesh->nf, nc = P->mesh->nc, nface = L.nface, N = L.N;
+  if (N >= INT32_MAX) fail(HHO_E_INVALID_ARG, "ILU smoother: level too large");
+  H = IluHost{};
+  H.gptr.assign(1, 0);
+  std::vector<int32_t> faces;
+  std::vector<int32_t> cells;
+  auto emit = [&]() {
+    std::sort(faces.begin(), faces.end());
+    faces.erase(std::unique(faces.begin(), faces.end()), faces.end());
+    std::sort(cells.begin(), cells.end());
+    for (int32_t g : faces)
+      for (int r = 0; r < dp; ++r) H.gcol.push_back((int32_t)((int64_t)g * dp + r));
+    for (int32_t T : cells)
+      for (int q = 0; q < t; ++q) H.gcol.push_back((int32_t)(nface + (int64_t)T * t + q));
+    H.gptr.push_back((int64_t)H.gcol.size());
+  };
+  for (int64_t f = 0; f < nf; ++f) {
+    faces.clear();
+    cells.clear();
+    for (int sd = 0; sd < 2; ++sd) {
+      const int T = P->fcell[2 * f + sd];
+      if (T < 0) continue;
+      cells.push_back(T);
+      for (int e = P->cptr[T]; e < P->cptr[T + 1]; ++e) faces.push_back(P->cface[e]);
+    }
+    emit();
+  }
+  for (int64_t T = 0; T < nc; ++T) {
+    faces.assign(P->cface.begin() + P->cptr[T], P->cface.begin() + P->cptr[T + 1]);
+    cells.assign(1, (int32_t)T);
+    emit();
+  }
+  auto group = [&](int64_t i) { return i < nface ? i / dp : nf + (i - nface) / t; };
+  H.voff.assign(N + 1, 0);
+  H.diag.assign(N, 0);
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t g = group(i), b = H.gptr[g], len = H.gptr[g + 1] - b;
+    H.maxrow = std::max<int>(H.maxrow, (int)len);
+    H.voff[i + 1] = H.voff[i] + len;
+    const int32_t *c = H.gcol.data() + b;
+    const int64_t pos = std::lower_bound(c, c + len, (int32_t)i) - c;
+    if (pos >= len || c[pos] != i) fail(HHO_E_INVALID_ARG, "ILU smoother: row without its diagonal");
+    H.diag[i] = H.voff[i] + pos;
+  }
+  // dependency levels: forward over the columns left of the diagonal, backward right of it
+  std::vector<int32_t> lf(N, 0), lb(N, 0);
+  int nlf = 0, nlb = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    const int64_t g = group(i), b = H.gptr[g];
+    const int64_t dl = H.diag[i] - H.voff[i];
+    int m = 0;
+    for (int64_t e = 0; e < dl; ++e) m = std::max(m, lf[H.gcol[b + e]]);
+    lf[i] = m + 1;
+    nlf = std::max(nlf, m + 1);
+  }
+  for (int64_t i = N - 1; i >= 0; --i) {
+    const int64_t g = group(i), b = H.gptr[g], len = H.gptr[g + 1] - b;
+    const int64_t dl = H.diag[i] - H.voff[i];
+    int m = 0;
+    for (int64_t e = dl + 1; e < len; ++e) m = std::max(m, lb[H.gcol[b + e]]);
+    lb[i] = m + 1;
+    nlb = std::max(nlb, m + 1);
+  }
+  auto bucket = [&](const std::vector<int32_t> &lv, int nl, std::vector<int32_t> &ptr, std::vector<int32_t> &rows) {
+    ptr.assign(nl + 1, 0);
+    for (int64_t i = 0; i < N; ++i) ++ptr[lv[i]];
+    for (int k = 0; k < nl; ++k) ptr[k + 1] += ptr[k];  // level k + 1 (1-based) holds rows [ptr[k], ptr[k+1])
+    rows.assign(N, 0);
+    std::vector<int32_t> at(ptr.begin(), ptr.end() - 1);
+    for (int64_t i = 0; i < N; ++i) rows[at[lv[i] - 1]++] = (int32_t)i;
+  };
+  bucket(lf, nlf, H.lptr, H.lrows);
+  bucket(lb, nlb, H.uptr, H.urows);
+  if (H.maxrow * 4 * (int64_t)sizeof(double) > (int64_t)kMaxLdsBytes - 1024)
+    fail(HHO_E_INVALID_ARG, "ILU smoother: a row of the pattern exceeds the LDS staging");
+  H.dev.N = N;
+  H.dev.nface = nface;
+  H.dev.d = d;
+  H.dev.p = p;
+  H.dev.t = t;
+  H.dev.cond = P->cond;
+}
+
 static void plan(hho_problem *P, Arena &A) {
   const int d = P->d;
   const int64_t nc = P->mesh->nc, nf = P->mesh->nf;
@@ -443,6 +554,23 @@ static void plan(hho_problem *P, Arena &A) {
     P->csst = A.take<GmresState>(P->nseg);
     P->csdone = A.take<int>(P->nseg);
     P->call_done = A.take<int>(1);
+  }
+  // the paper's smoother: ILU patterns (built once) and factors
+  if (P->ilu_on) {
+    if (P->ilu.size() != (size_t)P->nlev) P->ilu.assign(P->nlev, IluHost{});
+    for (int l = 0; l < P->nlev; ++l) {
+      if (!ilu_level(P, l)) continue;
+      IluHost &H = P->ilu[l];
+      if (H.gptr.empty()) build_ilu_level(P, l, H);
+      const int64_t N = P->lev[l].N;
+      H.dev.gptr = A.take<int64_t>(H.gptr.size());
+      H.dev.gcol = A.take<int32_t>(H.gcol.size());
+      H.dev.voff = A.take<int64_t>(N + 1);
+      H.dev.diag = A.take<int64_t>(N);
+      H.dev.LU = A.take<double>(H.voff[N]);
+      H.d_lrows = A.take<int32_t>(N);
+      H.d_urows = A.take<int32_t>(N);
+    }
   }
   // learned fine-level smoother
   if (P->opt.learned) {
@@ -742,6 +870,17 @@ static void device_upload(hho_problem *P) {
       h2d(S.ptr, S.hptr.data(), S.hptr.size() * 4);
     }
   }
+  if (P->ilu_on)
+    for (int l = 0; l < P->nlev; ++l) {
+      if (!ilu_level(P, l)) continue;
+      const IluHost &H = P->ilu[l];
+      h2d((void *)H.dev.gptr, H.gptr.data(), H.gptr.size() * 8);
+      h2d((void *)H.dev.gcol, H.gcol.data(), H.gcol.size() * 4);
+      h2d((void *)H.dev.voff, H.voff.data(), H.voff.size() * 8);
+      h2d((void *)H.dev.diag, H.diag.data(), H.diag.size() * 8);
+      h2d(H.d_lrows, H.lrows.data(), H.lrows.size() * 4);
+      h2d(H.d_urows, H.urows.data(), H.urows.size() * 4);
+    }
   if (P->coarse_amg) {
     h2d(P->d_fdiag, P->fdiag.data(), P->fdiag.size() * 4);
     for (int l = 0; l < P->amgd.nlev; ++l) {
@@ -857,10 +996,16 @@ static void device_setup(hho_problem *P) {
   const int Lc = P->nlev - 1;
   for (int l = 0; l < P->nlev; ++l) {
     LevelInfo &L = P->lev[l];
-    if (!L.sinv) continue;
+    if (!L.sinv || P->ilu_on) continue;
     size_t lds = patch_lds_bytes(P->d, P->cond, L.p, L.t, P->max_faces);
     launch_patch_setup(P->tp, P->cond, L.p, L.t, L.bsr, L.cpl, L.spp, L.sinv, L.xinv, L.sig, P->stage, P->err + 1,
                        s, lds, L.patch_threads);
+  }
+  for (int l = 0; l < P->nlev; ++l) {  // the paper's smoother: incomplete factors of the level operators
+    if (!ilu_level(P, l)) continue;
+    IluHost &H = P->ilu[l];
+    launch_ilu_fill(P->tp, dlev64(P, l), H.dev, s);
+    launch_ilu_factor(H.dev, H.d_lrows, H.lptr.data(), (int)H.lptr.size() - 1, H.maxrow, P->err + 5, s);
   }
   HIPCHK(hipEventRecord(ev[4], s));
   // coarse solver
@@ -928,9 +1073,29 @@ static void device_setup(hho_problem *P) {
   if (herr[1]) fail(HHO_E_LOCAL_SINGULAR, "smoother patch not invertible in cell " + std::to_string(herr[1] - 1));
   if (herr[2]) fail(HHO_E_LOCAL_SINGULAR, "coarsest-level matrix is singular");
   if (herr[3]) fail(HHO_E_LOCAL_SINGULAR, "AMG coarsest matrix is not SPD");
+  if (herr[5]) fail(HHO_E_LOCAL_SINGULAR, "ILU smoother: zero pivot in row " + std::to_string(herr[5] - 1));
 }
 
 // ------------------------------------------------------------ V-cycle
+// z = (L U)^{-1} r with level l's incomplete factors
+static void ilu_apply(hho_problem *P, int l, const double *r, double *z) {
+  const IluHost &H = P->ilu[l];
+  launch_ilu_apply(H.dev, H.d_lrows, H.lptr.data(), (int)H.lptr.size() - 1, H.d_urows, H.uptr.data(),
+                   (int)H.uptr.size() - 1, r, z, P->stream);
+}
+
+// z_j = M v_j and w = S z_j on the coarsest level (M its smoother's preconditioner)
+static void coarse_precond(hho_problem *P, const DLevel<double> &D, const DLevel<double> &Dq, const double *vj,
+                           double *zj) {
+  if (P->ilu_on) {
+    ilu_apply(P, P->nlev - 1, vj, zj);
+    launch_spmv<double>(P->tp, Dq, zj, nullptr, nullptr, P->cw, P->stream);
+    return;
+  }
+  launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, P->stream);
+  launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, zj, P->cw, P->stream);
+}
+
 template <typename Prec>
 static void smooth(hho_problem *P, int l) {
   using T = typename Prec::T;
@@ -948,11 +1113,25 @@ static void smooth(hho_problem *P, int l) {
     launch_spmv<T>(P->tp, D, V.z3, nullptr, nullptr, V.w3, s);
   }
   KernelProbe *pr = &P->probe;
-  HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.r, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
-  HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z1, V.w1, s));
-  if (m == 2) {
-    HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
-    HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s));
+  bool ilu = false;
+  if constexpr (std::is_same<T, double>::value) {
+    if (P->ilu_on) {  // the paper's smoother: GMRES(2) right-preconditioned by the level's ILU
+      ilu = true;
+      ilu_apply(P, l, V.r, V.z1);
+      HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.z1, nullptr, nullptr, V.w1, s));
+      if (m == 2) {
+        ilu_apply(P, l, V.w1, V.z2);
+        HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.z2, nullptr, nullptr, V.w2, s));
+      }
+    }
+  }
+  if (!ilu) {
+    HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.r, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
+    HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z1, V.w1, s));
+    if (m == 2) {
+      HHO_PROBED(pr, HHO_PROBE_SMOOTHER, l, s, launch_precond<T>(P->tp, D, V.w1, nullptr, nullptr, V.zs0, V.zs1, P->max_faces, s));
+      HHO_PROBED(pr, HHO_PROBE_OPERATOR, l, s, launch_spmv<T>(P->tp, D, V.zs0, V.zs1, V.z2, V.w2, s));
+    }
   }
   if (P->nseg > 0) {  // batch: every member takes its own minimal-residual step
     const SegLevel &S = P->segl[l];
@@ -1064,8 +1243,7 @@ static void coarse_solve_seg(hho_problem *P) {
         HHO_PROBED(&P->probe, HHO_PROBE_COARSE_OPERATOR, Lc, s,
                    launch_spmv<double>(P->tp, Dq, zj, nullptr, nullptr, P->cw, s));
       } else {
-        launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
-        launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, zj, P->cw, s);
+        coarse_precond(P, D, Dq, vj, zj);
       }
       launch_seg_arnoldi(0, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
       launch_seg_arnoldi(2, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
@@ -1125,8 +1303,7 @@ static void coarse_solve_fixed(hho_problem *P) {
         bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, zj, P->amg_nu, s, P->call_done);
         launch_spmv<double>(P->tp, Dq, zj, nullptr, nullptr, P->cw, s);
       } else {
-        launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
-        launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, zj, P->cw, s);
+        coarse_precond(P, D, Dq, vj, zj);
       }
       launch_seg_arnoldi(0, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
       launch_seg_arnoldi(2, G, S.ch, S.seg, np, S.ptr, j, P->cV, n, P->cw, P->seg_partial, st, P->csdone, 0, s);
@@ -1148,8 +1325,7 @@ static void coarse_solve_fixed(hho_problem *P) {
       bp_apply(P->tp, P->amgd, L.nface, L.cpl, P->Sd, vj, P->cZ + (int64_t)j * n, P->amg_nu, s, &st->done);
       launch_spmv<double>(P->tp, Dq, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s);
     } else {
-      launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
-      launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+      coarse_precond(P, D, Dq, vj, P->cZ + (int64_t)j * n);
     }
     if (j + 2 <= 64) {
       launch_arnoldi_cgs1<double>(n, j, P->cV, n, P->cw, P->partial, st, s);
@@ -1206,8 +1382,7 @@ static void coarse_solve(hho_problem *P) {
         HHO_PROBED(&P->probe, HHO_PROBE_COARSE_OPERATOR, Lc, s,
                    launch_spmv<double>(P->tp, Dq, P->cZ + (int64_t)j * n, nullptr, nullptr, P->cw, s));
       } else {
-        launch_precond<double>(P->tp, D, vj, nullptr, nullptr, P->czs0, P->czs1, P->max_faces, s);
-        launch_spmv<double>(P->tp, Dq, P->czs0, P->czs1, P->cZ + (int64_t)j * n, P->cw, s);
+        coarse_precond(P, D, Dq, vj, P->cZ + (int64_t)j * n);
       }
       // coarse GMRES: classical Gram-Schmidt once (its target is a 1e-3 reduction),
       // the new norm from |w|^2 - |h|^2, the next basis vector written directly
@@ -1646,7 +1821,11 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.precision != HHO_PREC_FP64 && P->opt.precision != HHO_PREC_FP32 && P->opt.precision != HHO_PREC_BF16)
     hho::fail(HHO_E_INVALID_ARG, "bad precision");
   if (P->opt.learned != 0 && P->opt.learned != 1) hho::fail(HHO_E_INVALID_ARG, "learned must be 0 or 1");
-  if (P->opt.smoother != HHO_SMOOTHER_SCHWARZ) hho::fail(HHO_E_INVALID_ARG, "smoother: only HHO_SMOOTHER_SCHWARZ");
+  if (P->opt.smoother != HHO_SMOOTHER_SCHWARZ && P->opt.smoother != HHO_SMOOTHER_ILU)
+    hho::fail(HHO_E_INVALID_ARG, "smoother must be HHO_SMOOTHER_SCHWARZ or HHO_SMOOTHER_ILU");
+  if (P->opt.smoother == HHO_SMOOTHER_ILU && (P->opt.precision != HHO_PREC_FP64 || P->opt.learned))
+    hho::fail(HHO_E_INVALID_ARG, "smoother ILU: FP64 V-cycle without the learned smoother");
+  P->ilu_on = P->opt.smoother == HHO_SMOOTHER_ILU;
   if (P->opt.nullspace != HHO_NULLSPACE_AUTO && P->opt.nullspace != HHO_NULLSPACE_NONE)
     hho::fail(HHO_E_INVALID_ARG, "nullspace must be HHO_NULLSPACE_AUTO or HHO_NULLSPACE_NONE");
   if (P->opt.vcycle_copy != HHO_COPY_CONVERT && P->opt.vcycle_copy != HHO_COPY_PRODUCT)
@@ -2022,6 +2201,13 @@ int hho_precond_apply(hho_problem *p, int level, const double *r, double *z) {
   need_setup(p);
   if (level < 0 || level >= p->nlev || !r || !z) hho::fail(HHO_E_INVALID_ARG, "precond_apply: bad argument");
   const hho::LevelInfo &L = p->lev[level];
+  if (p->ilu_on) {
+    if (!hho::ilu_level(p, level)) hho::fail(HHO_E_INVALID_ARG, "precond_apply: this level has no smoother");
+    hho::ilu_apply(p, level, r, z);
+    HIPCHK(hipStreamSynchronize(p->stream));
+    HIPCHK(hipGetLastError());
+    return HHO_OK;
+  }
   if (!L.sinv) hho::fail(HHO_E_INVALID_ARG, "precond_apply: this level has no smoother (dense coarse level)");
   double *zs1 = p->ow;  // level-0 length covers the face part of every level
   hho::launch_precond<double>(p->tp, hho::dlev64(p, level), r, nullptr, nullptr, z, zs1, p->max_faces, p->stream);

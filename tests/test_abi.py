@@ -171,11 +171,13 @@ def test_batch_members_take_their_own_penalty():
 def test_option_fields_smoother_and_nullspace():
     H, _ = _lib()
     M = H.Mesh(cartesian_quads(2))
-    for kw in (dict(smoother=1), dict(nullspace=2), dict(nullspace=-1)):
+    for kw in (dict(smoother=2), dict(nullspace=2), dict(nullspace=-1), dict(smoother="ilu", precision="fp32"),
+               dict(smoother="ilu", learned=1)):
         with pytest.raises(H.HHOError) as e:
             H.Problem(M, 1, "v", **kw)
         assert e.value.code == -1, kw
     H.Problem(M, 1, "v", smoother=0, nullspace=1)
+    H.Problem(M, 1, "v", smoother="ilu")
 
 
 def test_moments_replace_the_local_right_hand_sides():
