@@ -224,7 +224,7 @@ void launch_ilu_apply(const IluDev &I, const int32_t *lrows, const int32_t *lptr
 constexpr int kGlTable = 16;       // Gauss-Legendre table stride: n = 1 .. 15 points
 constexpr int kLocalThreads = 1024;  // most threads of a cell's workgroup (every rhs_u entry has its own)
 struct LocalGeom {
-  int d, k, N1, nT, nF, odeg;
+  int d, k, N1, nT, nF, odeg, nf;
   const int32_t *cptr, *cface;  // cell -> faces (the topology's)
   const double *csign;          // [cptr[nc]] +1 if n_F points out of the cell
   const int64_t *fptr, *fvtx;   // face vertices (2D: the two end points)
@@ -241,7 +241,9 @@ struct LocalGeom {
   const int64_t *foff;
   const int64_t *roff;          // record offsets
   double *rec;                  // records [a | B | rhs_u | rhs_p] (output)
-  int *err;                     // cell + 1 of a degenerate basis or a non-SPD stiffness
+  double *CF;                   // [nf][nF][nF] face bases on the face monomials (formed first)
+  int *err;                     // cell + 1 of a degenerate basis or a non-SPD stiffness, -(face + 1)
+                                // of a degenerate face basis
 };
 struct LocalLds {  // LDS layout of the local build (offsets in doubles)
   int C, K, Bc, G, Pi, Nn, gpo, red, rv, gto, scr;

@@ -7,8 +7,10 @@
 // enter as integrals against scaled monomials (computed with the user's
 // callbacks on the host); the bases' coefficients map them onto the bases.
 //
-// Differences from the host build, all within rounding: the bases come from
-// classical Gram-Schmidt applied twice (the host uses the modified form twice;
+// The face bases are formed first, one wave per face (k_face_bases), and read by
+// both cells of a face.  Differences from the host build, all within rounding:
+// the bases come from classical Gram-Schmidt applied twice (the host uses the
+// modified form twice;
 // both give the unique lower-triangular orthonormalisation of the graded
 // monomials), the consistency term is Y^T Y with Y = L^{-1} G (L the Cholesky
 // factor of the stiffness on the non-constant functions) instead of the
@@ -236,13 +238,11 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// cgs2 for a small basis on few points (a face's): the first wave does it alone,
-// lane j forming the product with column j, so the column steps need no
-// workgroup barrier; one barrier publishes the result.  N <= 64.  `flag` is an
-// LDS int; returns false (on every thread) if a column is numerically zero.
-__device__ bool cgs2_wave(double *V, int ldv, const double *W, int nq, int N, double *C, double *r, int *flag) {
-  if (threadIdx.x < kWave) {
-    const int lane = threadIdx.x;
+// cgs2 for a small basis on few points (a face's) by one wave alone, lane j
+// forming the product with column j, so the column steps need no workgroup
+// barrier; N <= 64.  Every lane returns false if a column is numerically zero.
+__device__ bool cgs2_one_wave(double *V, int ldv, const double *W, int nq, int N, double *C, double *r, int lane) {
+  {
     for (int e = lane; e < N * N; e += kWave) C[e] = (e / N == e % N) ? 1.0 : 0.0;
     wave_sync();
     int bad = 0;
@@ -279,10 +279,49 @@ __device__ bool cgs2_wave(double *V, int ldv, const double *W, int nq, int N, do
       if (lane < N) C[i * N + lane] *= inv;
       wave_sync();
     }
-    if (lane == 0) *flag = bad;
+    return bad == 0;
   }
-  __syncthreads();
-  return *flag == 0;
+}
+
+// Orthonormal basis of every face (its coefficients on the face monomials,
+// CF[f][j][m], lower triangular), one wave per face: a face's basis is shared by
+// its two cells, so it is formed once, here, with many faces in flight.
+constexpr int kFaceWaves = 4;
+__global__ void __launch_bounds__(kFaceWaves * kWave) k_face_bases(LocalGeom g, int max_nqf, double *CFall) {
+  extern __shared__ double lds[];
+  const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+  const int f = blockIdx.x * kFaceWaves + w;
+  const int nF = g.nF;
+  const int per = 4 * max_nqf + max_nqf * nF + nF * nF + nF + 1;
+  double *X = lds + (int64_t)w * per, *W = X + 3 * max_nqf, *V = W + max_nqf, *C = V + (int64_t)max_nqf * nF,
+         *r = C + nF * nF;
+  if (f >= g.nf) return;
+  const int nqf = face_npoints(g, f);
+  for (int q = lane; q < nqf; q += kWave) {
+    double x[3], wq;
+    face_point(g, f, q, x, &wq);
+    X[3 * q] = x[0];
+    X[3 * q + 1] = x[1];
+    X[3 * q + 2] = x[2];
+    W[q] = wq;
+  }
+  wave_sync();
+  const double hF = g.fdiam[f];
+  for (int e = lane; e < nqf * nF; e += kWave) {
+    const int q = e / nF, j = e % nF;
+    const double rr[3] = {X[3 * q] - g.fcen[3 * f], X[3 * q + 1] - g.fcen[3 * f + 1], X[3 * q + 2] - g.fcen[3 * f + 2]};
+    double xi[2];
+    xi[0] = (rr[0] * g.ft1[3 * f] + rr[1] * g.ft1[3 * f + 1] + rr[2] * g.ft1[3 * f + 2]) / hF;
+    xi[1] = (rr[0] * g.ft2[3 * f] + rr[1] * g.ft2[3 * f + 1] + rr[2] * g.ft2[3 * f + 2]) / hF;
+    V[e] = mono(g.EF, g.d - 1, xi, j);
+  }
+  wave_sync();
+  if (!cgs2_one_wave(V, nF, W, nqf, nF, C, r, lane)) {
+    if (lane == 0) g.err[0] = -(f + 1);
+    return;
+  }
+  double *out = CFall + (int64_t)f * nF * nF;
+  for (int e = lane; e < nF * nF; e += kWave) out[e] = C[e];
 }
 
 __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L) {
@@ -389,8 +428,9 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
     for (int a = 0; a < 3; ++a) n[a] = sg * g.fnrm[3 * f + a];
     const int nqf = face_npoints(g, f);
     double *Xf = S, *Wf = Xf + 3 * L.max_nqf, *Psi = Wf + L.max_nqf, *Phf = Psi + (int64_t)L.max_nqf * nF,
-           *Gn = Phf + (int64_t)L.max_nqf * N1, *CF = Gn + (int64_t)L.max_nqf * N1, *Mm = CF + nF * nF,
-           *Dmm = Mm + (int64_t)L.max_nqf * N1;
+           *Gn = Phf + (int64_t)L.max_nqf * N1, *Mf = Gn + (int64_t)L.max_nqf * N1,
+           *Mm = Mf + (int64_t)L.max_nqf * nF, *Dmm = Mm + (int64_t)L.max_nqf * N1;
+    const double *CF = g.CF + (int64_t)f * nF * nF;  // the face's basis (k_face_bases)
     const double hF = g.fdiam[f];
     double xF[3], t1[3], t2[3];
     for (int a = 0; a < 3; ++a) {
@@ -415,7 +455,7 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
         double xi[2];
         xi[0] = (r[0] * t1[0] + r[1] * t1[1] + r[2] * t1[2]) / hF;
         xi[1] = (r[0] * t2[0] + r[1] * t2[1] + r[2] * t2[2]) / hF;
-        Psi[q * nF + j] = mono(g.EF, d - 1, xi, j);
+        Mf[q * nF + j] = mono(g.EF, d - 1, xi, j);
       } else {
         const int t = j - nF;
         double xc[3];
@@ -427,6 +467,13 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
       }
     }
     __syncthreads();
+    // the face basis at the face points
+    for (int e2 = threadIdx.x; e2 < nqf * nF; e2 += blockDim.x) {
+      const int q = e2 / nF, j = e2 % nF;
+      double s1 = 0;
+      for (int m = 0; m <= j; ++m) s1 += CF[j * nF + m] * Mf[q * nF + m];
+      Psi[e2] = s1;
+    }
     // the cell basis and its normal derivative at the face points
     for (int e2 = threadIdx.x; e2 < nqf * N1; e2 += blockDim.x) {
       const int q = e2 / N1, t = e2 % N1;
@@ -440,13 +487,6 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
       Gn[e2] = s2;
     }
     __syncthreads();
-    // a face of few points (2D segments) takes its basis in one wave, a larger one block-wide
-    const bool ok = nqf <= 16 ? cgs2_wave(Psi, nF, Wf, nqf, nF, CF, rv, &fail_flag)
-                              : cgs2(Psi, nF, Wf, nqf, nF, CF, rv, red);
-    if (!ok) {
-      if (threadIdx.x == 0) g.err[0] = c + 1;
-      return;
-    }
     // G[t][F_j] += (grad phi_t . n, psi_j)_F ; G[t][j'] -= (grad phi_t . n, phi_j')_F  (t >= 1)
     for (int e2 = threadIdx.x; e2 < N1 * (nF + nT); e2 += blockDim.x) {
       const int t = e2 / (nF + nT), col = e2 % (nF + nT);
@@ -633,6 +673,12 @@ __global__ void __launch_bounds__(kLocalThreads) k_local(LocalGeom g, LocalLds L
 
 void launch_local(const LocalGeom &g, const LocalLds &L, int nc, hipStream_t s) {
   if (nc <= 0) return;
+  if (g.nf > 0) {  // the faces' bases first (read by every cell's face phase)
+    const int per = 4 * L.max_nqf + L.max_nqf * g.nF + g.nF * g.nF + g.nF + 1;
+    const size_t lds = (size_t)kFaceWaves * per * sizeof(double);
+    hipLaunchKernelGGL(k_face_bases, dim3((g.nf + kFaceWaves - 1) / kFaceWaves), dim3(kFaceWaves * kWave), lds, s, g,
+                       L.max_nqf, g.CF);
+  }
   static std::once_flag once;
   static hipError_t attr = hipSuccess;
   std::call_once(once, [] {
@@ -675,7 +721,7 @@ LocalLds local_lds(int d, int k, int max_faces, int max_nq, int max_nqf) {
   L.rv = take(N1);
   L.gto = take((int64_t)d * N1);
   const int64_t cell = 4LL * max_nq + (int64_t)max_nq * N1 + 2LL * L.chunk * N1 * d;
-  const int64_t face = 4LL * max_nqf + (int64_t)max_nqf * nF + 4LL * max_nqf * N1 + (int64_t)nF * nF;
+  const int64_t face = 4LL * max_nqf + 2LL * max_nqf * nF + 4LL * max_nqf * N1;
   const int64_t stab = 2LL * nF * nlocmax + (int64_t)nlocmax * nlocmax;
   L.scr = take(std::max(cell, std::max(face, stab)));
   L.bytes = (size_t)o * sizeof(double);

@@ -330,6 +330,7 @@ static void plan(hho_problem *P, Arena &A) {
     g.nT = P->loc.nT;
     g.nF = P->loc.nF;
     g.odeg = P->lgeo.odeg;
+    g.nf = (int)P->mesh->nf;
     g.cptr = P->tp.cptr;
     g.cface = P->tp.cface;
     g.csign = A.take<double>(m->csign.size());
@@ -363,6 +364,7 @@ static void plan(hho_problem *P, Arena &A) {
     g.err = nullptr;  // set below, once the error slots are placed
     int64_t nu = 0;
     for (int32_t v : P->loc.nloc) nu += (int64_t)d * v + P->loc.nT;
+    g.CF = A.take<double>(std::max<int64_t>(1, (int64_t)P->mesh->nf * g.nF * g.nF));
     P->d_user_rhs = A.take<double>(std::max<int64_t>(1, nu));
     P->d_user_off = A.take<int64_t>(nc + 1);
   }
@@ -1066,9 +1068,10 @@ static void device_setup(hho_problem *P) {
   HIPCHK(hipEventDestroy(evl));
   int herr[8];
   HIPCHK(hipMemcpy(herr, P->err, sizeof(herr), hipMemcpyDeviceToHost));
-  if (herr[4])
+  if (herr[4] > 0)
     fail(HHO_E_LOCAL_SINGULAR, "local build: degenerate basis or non-SPD reconstruction stiffness in cell " +
                                    std::to_string(herr[4] - 1));
+  if (herr[4] < 0) fail(HHO_E_LOCAL_SINGULAR, "local build: degenerate basis of face " + std::to_string(-herr[4] - 1));
   if (herr[0]) fail(HHO_E_LOCAL_SINGULAR, "static condensation: local block not SPD in cell " + std::to_string(herr[0] - 1));
   if (herr[1]) fail(HHO_E_LOCAL_SINGULAR, "smoother patch not invertible in cell " + std::to_string(herr[1] - 1));
   if (herr[2]) fail(HHO_E_LOCAL_SINGULAR, "coarsest-level matrix is singular");
