@@ -282,6 +282,7 @@ def cpu_baseline(spec, sample_cells=4096):
     P = OS.Problem(mesh, geo, k, cond, degrees, eta, locs, blocks, lays, S, b, idx, z)
     t1 = time.perf_counter()
     H = OS.hierarchy(P, coarse="amg", coarse_rtol=1e-3 if mesh.dim == 3 else 1e-2)
+    H.amg_nu = 1        # the library's default: one damped-Jacobi sweep per AMG level
     x, its, hist, conv = OS.solve_fgmres(P, rtol=1e-8, H=H)
     t2 = time.perf_counter()
     dt = t2 - t0

@@ -146,7 +146,7 @@ typedef struct {
   int32_t coarse_restart; /* coarse GMRES restart (30, at most 64) */
   int32_t coarse_max_it;  /* coarse GMRES iterations (300) */
   int32_t quad_extra;  /* quadrature exact to degree 2k+2+quad_extra (6) */
-  int32_t coarse_amg_sweeps; /* damped-Jacobi sweeps before/after the AMG coarse correction (2; 1 or 2) */
+  int32_t coarse_amg_sweeps; /* damped-Jacobi sweeps before/after the AMG coarse correction (1; 1 or 2) */
   int32_t learned;     /* 1: reserve the learned fine-level smoother (hho_learned_*); 0 (default): no */
   int32_t coarse_amg_explicit; /* AMG levels with at most this many rows are applied as the explicit
                                   matrix of their V-cycle, formed at setup (2048; 0 = never; at most 4096) */

@@ -1760,7 +1760,7 @@ void hho_options_default(hho_options *o) {
   o->coarse_restart = 30;
   o->coarse_max_it = 300;
   o->quad_extra = 6;
-  o->coarse_amg_sweeps = 2;
+  o->coarse_amg_sweeps = 1;
   o->learned = 0;
   o->coarse_amg_explicit = 2048;
   o->coarse_amg_psmooth = 1;

@@ -182,15 +182,17 @@ AMG_CASES = [
 @pytest.mark.parametrize("name,mk,k,cond", AMG_CASES)
 def test_coarse_block_preconditioner(built, name, mk, k, cond, explicit, psmooth):
     """Coarsest-level block-triangular preconditioner with the smoothed-aggregation
-    velocity block: GPU vs the oracle's plain definition, with the small AMG levels
-    applied as their explicit V-cycle matrix (2048) and level by level (0), with
-    two prolongator smoothing steps (where the density bound allows) and one."""
+    velocity block (one damped-Jacobi sweep before and after each coarse
+    correction, the library's default): GPU vs the oracle's plain definition,
+    with the small AMG levels applied as their explicit V-cycle matrix (2048)
+    and level by level (0), with two prolongator smoothing steps (where the
+    density bound allows) and one."""
     import torch
     from oracle.amg import BlockStokesPrec
     mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_explicit=explicit,
                           coarse_amg_psmooth=psmooth)
     L = len(O.S) - 1
-    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, p_steps=psmooth)
+    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, nu=1, p_steps=psmooth)
     assert len(prec.amg.sizes) >= 2
     rng = np.random.default_rng(3)
     v = rng.standard_normal(O.S[L].shape[0])
@@ -213,7 +215,7 @@ def test_coarse_block_preconditioner_explicit_several_levels():
     P.bind("cuda:0", fill=0xFF)      # NaN bytes: a read of unwritten workspace shows up
     P.setup()
     O = OS.build(mesh, 0, "v", data, eta=None)
-    prec = BlockStokesPrec(O.S[0], O.lays[0].off, 2)
+    prec = BlockStokesPrec(O.S[0], O.lays[0].off, 2, nu=1)
     sizes = prec.amg.sizes
     assert sizes[0] > 4096 and sizes[1] <= 4096 and sizes[1] ** 2 > 8192 * 256 and len(sizes) >= 4, sizes
     rng = np.random.default_rng(6)
@@ -247,13 +249,13 @@ def test_coarse_preconditioner_independent_of_workspace_contents():
 
 @pytest.mark.parametrize("explicit", [2048, 0])
 @pytest.mark.parametrize("name,mk,k,cond", [AMG_CASES[0], AMG_CASES[3]])
-def test_coarse_block_preconditioner_one_sweep(built, name, mk, k, cond, explicit):
-    """The same with one damped-Jacobi sweep before and after each coarse correction."""
+def test_coarse_block_preconditioner_two_sweeps(built, name, mk, k, cond, explicit):
+    """The same with two damped-Jacobi sweeps before and after each coarse correction."""
     import torch
     from oracle.amg import BlockStokesPrec
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_sweeps=1, coarse_amg_explicit=explicit)
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="amg", coarse_amg_sweeps=2, coarse_amg_explicit=explicit)
     L = len(O.S) - 1
-    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, nu=1)
+    prec = BlockStokesPrec(O.S[L], O.lays[L].off, mesh.dim, nu=2)
     rng = np.random.default_rng(4)
     v = rng.standard_normal(O.S[L].shape[0])
     z = P.coarse_prec_apply(torch.from_numpy(v).cuda()).cpu().numpy()
