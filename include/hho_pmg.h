@@ -84,6 +84,10 @@ extern "C" {
 #define HHO_COARSE_GMRES  2   /* GMRES to coarse_rtol, cell-patch Schwarz preconditioner      */
 #define HHO_COARSE_AMG    3   /* GMRES to coarse_rtol, block-triangular Stokes preconditioner
                                  with a smoothed-aggregation velocity block (k_L = 0 only)     */
+#define HHO_COARSE_DIRECT 4   /* sparse direct solve (Section 5.2: the 2D coarse solver is a
+                                 direct factorisation): multifrontal elimination in a nested
+                                 dissection order, factorised at setup (k_L = 0 only; single
+                                 problems, or batches without a pressure null space)          */
 
 /* how the face blocks of the V-cycle's level-0 copy are formed (FP32/BF16 V-cycles) */
 #define HHO_COPY_CONVERT  0   /* the FP64 operator rounded to the copy's precision */
@@ -317,6 +321,23 @@ int hho_precond_apply(hho_problem *p, int level, const double *r_dev, double *z_
  * one smoothed-aggregation V-cycle on v_f - C y per component.  Only when the
  * problem uses HHO_COARSE_AMG (explicitly or through AUTO). */
 int hho_coarse_prec_apply(hho_problem *p, const double *v, double *z);
+
+/* x = the coarsest level's solver applied to b (device vectors of the
+ * coarsest level's size, FP64), as inside the V-cycle: the bordered dense
+ * inverse, the sparse direct solve (x orthogonal to the constant-pressure null
+ * vector when there is one, b first made so), or GMRES to coarse_rtol. */
+int hho_coarse_solve_apply(hho_problem *p, const double *b, double *x);
+
+/* The sparse direct solver's symbolic phase (host arrays, as int64), after
+ * hho_problem_set_data with HHO_COARSE_DIRECT: "m", "nfs" (unknowns of each front
+ * and how many it eliminates), "child" (2 per front, -1 if none), "dofoff",
+ * "dof" (the unknowns of each front: its own first, then its update part in
+ * elimination order), "cmap" (2 per front position: position in child 0/1's
+ * update part, -1 if absent), "hptr"/"hfront" (fronts by tree height), "pinned"
+ * (the unknown fixed to zero, or -1), "sizes" (fronts, heights, front entries,
+ * factor entries used by the solves, largest front).  cap: room in out;
+ * *n_out receives the length (HHO_E_CAPACITY when it exceeds cap). */
+int hho_direct_info(const hho_problem *p, const char *name, int64_t *out, int64_t cap, int64_t *n_out);
 
 /* Host copy of an internal device array for inspection: name "amg_val",
  * "amg_pval", "amg_dinv", "amg_lam", "amg_ainv" (AMG level `level`) or "sd"

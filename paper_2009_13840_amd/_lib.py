@@ -22,7 +22,7 @@ COND = {"v": 1, "vp": 2}
 PROBE = {"operator": 1, "smoother": 2, "coarse_operator": 4, "outer_operator": 8, "amg_restrict": 16,
          "amg_sweep": 32, "amg_prolong": 64, "amg_dense": 128}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
-COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3}
+COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3, "direct": 4}
 COPY = {"convert": 0, "product": 1}
 LOCAL = {"auto": 0, "host": 1, "device": 2}
 SMOOTHER = {"schwarz": 0, "ilu": 1}
@@ -33,7 +33,7 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_moments_size", "hho_set_moments", "hho_batch_create", "hho_batch_destroy", "hho_batch_problem",
            "hho_batch_sizes", "hho_batch_solve", "hho_learned_save", "hho_learned_load", "hho_get_rhs", "hho_get_condensed_cell",
            "hho_get_local_cell", "hho_level_apply", "hho_vcycle_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
-           "hho_time_kernel", "hho_coarse_prec_apply", "hho_debug_copy", "hho_learned_dims",
+           "hho_time_kernel", "hho_coarse_prec_apply", "hho_coarse_solve_apply", "hho_direct_info", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
            "hho_learned_collect", "hho_learned_grad", "hho_learned_grad_noalloc", "hho_learned_train", "hho_mesh_create_union",
            "hho_problem_set_segments", "hho_batch_results", "hho_autotune", "hho_recover_cells",
@@ -119,6 +119,8 @@ def load():
         "hho_upload": ([P], I32),
         "hho_time_kernel": ([P, I32, I32, I32, D], I32),
         "hho_coarse_prec_apply": ([P, P, P], I32),
+        "hho_coarse_solve_apply": ([P, P, P], I32),
+        "hho_direct_info": ([P, C.c_char_p, P, C.c_int64, P], I32),
         "hho_debug_copy": ([P, C.c_char_p, I32, D, I64, C.POINTER(I64)], I32),
         "hho_mesh_create_union": ([C.POINTER(MeshDesc), I32, C.POINTER(P), C.POINTER(I64), C.POINTER(I64)], I32),
         "hho_problem_set_segments": ([P, I32, C.POINTER(I64), C.POINTER(I64)], I32),
@@ -478,6 +480,21 @@ class Problem:
         z = self._vec(self.level_size(self.nlev - 1))
         _check(load().hho_coarse_prec_apply(self.h, C.c_void_p(v.data_ptr()), C.c_void_p(z.data_ptr())))
         return z
+
+    def direct_info(self, name: str):
+        """The sparse direct coarse solver's symbolic arrays (hho_direct_info)."""
+        n = C.c_int64()
+        st = load().hho_direct_info(self.h, name.encode(), None, 0, C.byref(n))
+        if st != -7:
+            _check(st)
+        out = np.zeros(max(n.value, 1), dtype=np.int64)
+        _check(load().hho_direct_info(self.h, name.encode(), out.ctypes.data_as(C.c_void_p), out.size, C.byref(n)))
+        return out[:n.value].copy()
+
+    def coarse_solve_apply(self, b):
+        x = self._vec(self.level_size(self.nlev - 1))
+        _check(load().hho_coarse_solve_apply(self.h, C.c_void_p(b.data_ptr()), C.c_void_p(x.data_ptr())))
+        return x
 
     def vcycle_apply(self, b):
         x = self._vec(self.level_size(0))

@@ -16,8 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhho_pmg.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
 
-HOST_SRC = ["host_mesh.cpp", "host_local.cpp", "amg_host.cpp"]
-HIP_SRC = ["k_setup.hip", "k_solve.hip", "k_spmv.hip", "k_orth.hip", "k_amg.hip", "k_mlp.hip", "k_local.hip", "k_ilu.hip", "solver.hip"]
+HOST_SRC = ["host_mesh.cpp", "host_local.cpp", "amg_host.cpp", "nd_host.cpp"]
+HIP_SRC = ["k_setup.hip", "k_solve.hip", "k_spmv.hip", "k_orth.hip", "k_amg.hip", "k_mlp.hip", "k_local.hip", "k_ilu.hip", "k_direct.hip", "solver.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("HHO_OFFLOAD_ARCH", "gfx950")
 HIP_FLAGS = ["-std=c++17", "-O3", "-fPIC", f"--offload-arch={ARCH}",

@@ -14,6 +14,7 @@
 #include "device.h"
 #include "internal.h"
 #include "k_amg.h"
+#include "k_direct.h"
 #include "probe.h"
 
 namespace hho {
@@ -140,6 +141,11 @@ struct hho_problem {
   double *Sd = nullptr;
   AmgHost amgh;
   AmgDev amgd;
+  // coarsest-level sparse direct solver (HHO_COARSE_DIRECT)
+  bool coarse_direct = false;
+  NdHost nd;
+  NdDev ndd;
+  double nd_zz = 0;  // squared norm of the constant-pressure null vector
   std::vector<double> zhost;
   size_t lds_condense = 0, lds_patch = 0;
   // batched problems (disjoint union): per-segment FGMRES state
@@ -209,7 +215,7 @@ static int level_t(const hho_problem *P, int k) { return P->cond == HHO_COND_V ?
 static bool ilu_level(const hho_problem *P, int l) {
   if (!P->ilu_on) return false;
   const int Lc = P->nlev - 1;
-  return l < Lc || (!P->coarse_dense && !P->coarse_amg);
+  return l < Lc || (!P->coarse_dense && !P->coarse_amg && !P->coarse_direct);
 }
 
 // Pattern of the level operator in the natural ordering: a face's rows share
@@ -385,7 +391,7 @@ static void plan(hho_problem *P, Arena &A) {
     L.bsr = A.take<double>(nbsr);
     L.cpl = A.take<double>(ncpl);
     L.spp = A.take<double>(nspp);
-    const bool need_smoother = (l < Lc) || !P->coarse_dense;
+    const bool need_smoother = (l < Lc) || !(P->coarse_dense || P->coarse_direct);
     L.sinv = need_smoother ? A.take<double>(nsinv) : nullptr;
     L.xinv = need_smoother ? A.take<double>(nxinv) : nullptr;
     L.sig = need_smoother ? A.take<double>(nc) : nullptr;
@@ -432,6 +438,33 @@ static void plan(hho_problem *P, Arena &A) {
   if (P->coarse_dense) {
     P->dense = A.take<double>(P->dense_n * 2 * P->dense_n);
     P->colbuf = A.take<double>(P->dense_n);
+  } else if (P->coarse_direct) {
+    NdHost &H = P->nd;
+    if (H.m.empty())
+      nd_symbolic(P->mesh, d, LC.p, LC.t, P->cond, P->border != 0, P->rowptr, P->col, &H);
+    if ((int64_t)H.maxm * (int64_t)sizeof(double) > (int64_t)kMaxLdsBytes - 1024)
+      fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: a front exceeds the LDS of one compute unit");
+    NdDev &D = P->ndd;
+    const int nn = H.nfront;
+    D.m = A.take<int32_t>(nn);
+    D.nfs = A.take<int32_t>(nn);
+    D.child = A.take<int32_t>(2 * nn);
+    D.off = A.take<int64_t>(nn + 1);
+    D.voff = A.take<int64_t>(nn + 1);
+    D.dofoff = A.take<int64_t>(nn + 1);
+    D.soff = A.take<int64_t>(nn);
+    D.dof = A.take<int32_t>(H.dof.size());
+    D.cmap = A.take<int32_t>(H.cmap.size());
+    D.npair = (int64_t)H.src.size();
+    D.src = A.take<int64_t>(H.src.size());
+    D.dst = A.take<int64_t>(H.dst.size());
+    D.hfront = A.take<int32_t>(H.hfront.size());
+    D.tiles = A.take<int32_t>(H.tiles.size());
+    D.chunks = A.take<int32_t>(H.chunks.size());
+    D.F = A.take<double>(H.total);
+    D.V = A.take<double>(H.vtotal);
+    D.S = A.take<double>(H.stotal);
+    D.coef = A.take<double>(1);
   } else {
     const int R = P->opt.coarse_restart;
     P->cV = A.take<double>((int64_t)(R + 1) * LC.N);
@@ -780,8 +813,13 @@ static void init_levels(hho_problem *P) {
     fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
   if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
   P->dense_n = nd;
-  P->coarse_amg = !P->coarse_dense && (P->opt.coarse_mode == HHO_COARSE_AMG ||
-                                       (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
+  P->coarse_direct = !P->coarse_dense && P->opt.coarse_mode == HHO_COARSE_DIRECT;
+  if (P->coarse_direct && LC.k != 0) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver needs a coarsest degree of 0");
+  if (P->coarse_direct && P->nseg > 1 && P->border)
+    fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
+  P->nd = NdHost{};  // built when the workspace is planned
+  P->coarse_amg = !P->coarse_dense && !P->coarse_direct &&
+                  (P->opt.coarse_mode == HHO_COARSE_AMG || (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
   if (P->coarse_amg && LC.k != 0) fail(HHO_E_INVALID_ARG, "AMG coarse solver needs a coarsest degree of 0");
   P->amgh.levels.clear();  // built by amg_levels() once the problem's data are set
 }
@@ -883,6 +921,26 @@ static void device_upload(hho_problem *P) {
       h2d(H.d_lrows, H.lrows.data(), H.lrows.size() * 4);
       h2d(H.d_urows, H.urows.data(), H.urows.size() * 4);
     }
+  if (P->coarse_direct) {
+    const NdHost &H = P->nd;
+    const NdDev &D = P->ndd;
+    h2d((void *)D.m, H.m.data(), H.m.size() * 4);
+    h2d((void *)D.nfs, H.nfs.data(), H.nfs.size() * 4);
+    h2d((void *)D.child, H.child.data(), H.child.size() * 4);
+    h2d((void *)D.off, H.off.data(), H.off.size() * 8);
+    h2d((void *)D.voff, H.voff.data(), H.voff.size() * 8);
+    h2d((void *)D.dofoff, H.dofoff.data(), H.dofoff.size() * 8);
+    h2d((void *)D.soff, H.soff.data(), H.soff.size() * 8);
+    h2d((void *)D.dof, H.dof.data(), H.dof.size() * 4);
+    h2d((void *)D.cmap, H.cmap.data(), H.cmap.size() * 4);
+    h2d((void *)D.src, H.src.data(), H.src.size() * 8);
+    h2d((void *)D.dst, H.dst.data(), H.dst.size() * 8);
+    h2d((void *)D.hfront, H.hfront.data(), H.hfront.size() * 4);
+    if (!H.tiles.empty()) h2d((void *)D.tiles, H.tiles.data(), H.tiles.size() * 4);
+    h2d((void *)D.chunks, H.chunks.data(), H.chunks.size() * 4);
+    P->nd_zz = 0;
+    for (double z : P->zmean) P->nd_zz += z * z;
+  }
   if (P->coarse_amg) {
     h2d(P->d_fdiag, P->fdiag.data(), P->fdiag.size() * 4);
     for (int l = 0; l < P->amgd.nlev; ++l) {
@@ -1018,6 +1076,11 @@ static void device_setup(hho_problem *P) {
     launch_eye_right(P->dense, n, 2 * n, s);
     for (int64_t kk = 0; kk < n; ++kk) launch_gj_step(P->dense, n, 2 * n, kk, P->colbuf, P->err + 2, s);
   }
+  if (P->coarse_direct) {
+    const LevelInfo &LC = P->lev[Lc];
+    const int bs = LC.bs;
+    launch_nd_factor(P->nd, P->ndd, dlev64(P, Lc), P->nnzb * bs * bs, P->ncf * P->d * LC.p * LC.t, P->err + 6, s);
+  }
   if (P->coarse_amg) {
     const LevelInfo &LC = P->lev[Lc];
     bp_setup(P->tp, P->cond, P->d_fdiag, LC.bsr, LC.cpl, P->Sd, s);
@@ -1077,6 +1140,8 @@ static void device_setup(hho_problem *P) {
   if (herr[2]) fail(HHO_E_LOCAL_SINGULAR, "coarsest-level matrix is singular");
   if (herr[3]) fail(HHO_E_LOCAL_SINGULAR, "AMG coarsest matrix is not SPD");
   if (herr[5]) fail(HHO_E_LOCAL_SINGULAR, "ILU smoother: zero pivot in row " + std::to_string(herr[5] - 1));
+  if (herr[6])
+    fail(HHO_E_LOCAL_SINGULAR, "sparse direct coarse solver: zero pivot in front " + std::to_string(herr[6] - 1));
 }
 
 // ------------------------------------------------------------ V-cycle
@@ -1350,6 +1415,10 @@ static void coarse_solve(hho_problem *P) {
   VBufs<double> &V = L.v64;
   if (P->coarse_dense) {
     launch_dense_matvec(P->dense, P->dense_n, 2 * P->dense_n, P->border, V.b, V.w, s);
+    return;
+  }
+  if (P->coarse_direct) {
+    launch_nd_solve(P->nd, P->ndd, L.nface, L.t, (int)P->mesh->nc, P->tp.zmean, P->nd_zz, V.b, V.w, s);
     return;
   }
   if (P->in_capture) {
@@ -1814,6 +1883,8 @@ int hho_problem_create(const hho_mesh *mesh, int k, int cond, int nlev, const in
   if (P->opt.coarse_restart < 1 || P->opt.coarse_restart > hho::kMaxRestartH)
     hho::fail(HHO_E_INVALID_ARG, "coarse_restart must be in 1..64");
   if (P->opt.smooth_its < 1 || P->opt.smooth_its > 2) hho::fail(HHO_E_INVALID_ARG, "smooth_its must be 1 or 2");
+  if (P->opt.coarse_mode < HHO_COARSE_AUTO || P->opt.coarse_mode > HHO_COARSE_DIRECT)
+    hho::fail(HHO_E_INVALID_ARG, "bad coarse_mode");
   if (P->opt.coarse_amg_sweeps < 1 || P->opt.coarse_amg_sweeps > 2)
     hho::fail(HHO_E_INVALID_ARG, "coarse_amg_sweeps must be 1 or 2");
   P->amg_nu = P->opt.coarse_amg_sweeps;
@@ -2269,6 +2340,48 @@ int hho_coarse_prec_apply(hho_problem *p, const double *v, double *z) {
   hho::bp_apply(p->tp, p->amgd, L.nface, L.cpl, p->Sd, v, z, p->amg_nu, p->stream);
   HIPCHK(hipStreamSynchronize(p->stream));
   HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_coarse_solve_apply(hho_problem *p, const double *b, double *x) {
+  ABI_BEGIN
+  need_setup(p);
+  if (!b || !x) hho::fail(HHO_E_INVALID_ARG, "coarse_solve_apply: NULL");
+  hho::LevelInfo &L = p->lev[p->nlev - 1];
+  HIPCHK(hipMemcpyAsync(L.v64.b, b, L.N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  p->coarse_its = 0;
+  hho::coarse_solve(p);
+  HIPCHK(hipMemcpyAsync(x, L.v64.w, L.N * sizeof(double), hipMemcpyDeviceToDevice, p->stream));
+  HIPCHK(hipStreamSynchronize(p->stream));
+  HIPCHK(hipGetLastError());
+  return HHO_OK;
+  ABI_END
+}
+
+int hho_direct_info(const hho_problem *p, const char *name, int64_t *out, int64_t cap, int64_t *n_out) {
+  ABI_BEGIN
+  if (!p || !name || !n_out) hho::fail(HHO_E_INVALID_ARG, "direct_info: NULL");
+  if (!p->coarse_direct || p->nd.m.empty())
+    hho::fail(HHO_E_INVALID_ARG, "direct_info: the problem has no sparse direct coarse solver (or no data yet)");
+  const hho::NdHost &H = p->nd;
+  const std::string n(name);
+  std::vector<int64_t> v;
+  auto put = [&](const auto &src) { v.assign(src.begin(), src.end()); };
+  if (n == "m") put(H.m);
+  else if (n == "nfs") put(H.nfs);
+  else if (n == "child") put(H.child);
+  else if (n == "dofoff") put(H.dofoff);
+  else if (n == "dof") put(H.dof);
+  else if (n == "cmap") put(H.cmap);
+  else if (n == "hptr") put(H.hptr);
+  else if (n == "hfront") put(H.hfront);
+  else if (n == "pinned") v = {H.pinned};
+  else if (n == "sizes") v = {H.nfront, H.nheight, H.total, H.factor_entries, H.maxm};
+  else hho::fail(HHO_E_INVALID_ARG, "direct_info: unknown name " + n);
+  *n_out = (int64_t)v.size();
+  if ((int64_t)v.size() > cap) hho::fail(HHO_E_CAPACITY, "direct_info: buffer too small");
+  if (out) std::copy(v.begin(), v.end(), out);
   return HHO_OK;
   ABI_END
 }

@@ -1,0 +1,123 @@
+"""Host logic of the sparse direct coarse solver (options.coarse_mode = "direct";
+the paper solves its 2D coarse problems directly, Section 5.2): the symbolic
+phase's nested dissection, pressure placement and index maps, read back through
+hho_direct_info, drive an independent NumPy elimination of the fronts in the
+order the device uses (sweep operator on each front's own unknowns, updates
+passed to the parent through the child maps, forward and backward passes).
+That elimination must reproduce the bordered direct solution of the oracle's
+coarsest operator (np.linalg.solve of [S z; z^T 0]) to rounding, which fails if
+a front misses an unknown, a child map is wrong, an operator entry is assembled
+into the wrong front or twice, or a pressure is eliminated before the velocity
+unknowns that make its pivot nonzero (a zero pivot).  No GPU is used."""
+import numpy as np
+import pytest
+
+from synth import voronoi_lloyd, polynomial_stokes, cartesian_quads, cartesian_hexes
+from synth.fields import problem_data
+
+NAMES = ["m", "nfs", "child", "dofoff", "dof", "cmap", "hptr", "hfront", "pinned", "sizes"]
+
+
+def _eliminate(S, z, I, b):
+    m, nfs, child, dofoff, dof, cmap = (I[n] for n in NAMES[:6])
+    nn, N = len(m), S.shape[0]
+    pinned = int(I["pinned"][0])
+    # fronts are numbered children first; each eliminates its first nfs unknowns
+    ekey = np.full(N, np.iinfo(np.int64).max)
+    front_of = np.full(N, -1)
+    key = 0
+    for f in range(nn):
+        own = dof[dofoff[f]:dofoff[f] + nfs[f]]
+        ekey[own] = np.arange(key, key + nfs[f])
+        front_of[own] = f
+        key += nfs[f]
+    assert key == N - (pinned >= 0)
+    assert (front_of >= 0).sum() == key and (pinned < 0 or front_of[pinned] < 0)
+    fronts = []
+    for f in range(nn):
+        d = dof[dofoff[f]:dofoff[f + 1]]
+        assert len(set(d.tolist())) == m[f]
+        # an operator entry belongs to the front of its earlier-eliminated unknown
+        owner = np.where(ekey[d][:, None] < ekey[d][None, :], front_of[d][:, None], front_of[d][None, :])
+        M = np.where(owner == f, S[np.ix_(d, d)], 0.0)
+        for s in range(2):
+            c = child[2 * f + s]
+            if c < 0:
+                continue
+            cm = cmap[2 * dofoff[f]:2 * dofoff[f + 1]][s::2]
+            idx = np.where(cm >= 0)[0]
+            assert len(idx) == m[c] - nfs[c]          # every update of the child has a place
+            U = fronts[c][nfs[c]:, nfs[c]:]
+            M[np.ix_(idx, idx)] += U[np.ix_(cm[idx], cm[idx])]
+        for k in range(nfs[f]):
+            a = M[k, k]
+            assert a != 0.0 and np.isfinite(a), (f, k)
+            r, col = M[k, :].copy(), M[:, k].copy()
+            M -= np.outer(col, r) / a
+            M[k, :], M[:, k] = r / a, col / a
+            M[k, k] = -1.0 / a
+        fronts.append(M)
+    coef = (z @ b) / (z @ z) if pinned >= 0 else 0.0
+    bp = b - coef * z if pinned >= 0 else b
+    V = []
+    for f in range(nn):
+        d = dof[dofoff[f]:dofoff[f + 1]]
+        v = np.zeros(m[f])
+        v[:nfs[f]] = bp[d[:nfs[f]]]
+        for s in range(2):
+            c = child[2 * f + s]
+            if c >= 0:
+                cm = cmap[2 * dofoff[f]:2 * dofoff[f + 1]][s::2]
+                idx = np.where(cm >= 0)[0]
+                v[idx] += V[c][nfs[c]:][cm[idx]]
+        u = v.copy()
+        u[nfs[f]:] -= fronts[f][nfs[f]:, :nfs[f]] @ v[:nfs[f]]
+        V.append(u)
+    x = np.zeros(N)
+    for f in reversed(range(nn)):
+        d = dof[dofoff[f]:dofoff[f + 1]]
+        y = np.concatenate([V[f][:nfs[f]], x[d[nfs[f]:]]])
+        x[d[:nfs[f]]] = -(fronts[f][:nfs[f], :] @ y)
+    if pinned >= 0:
+        x[pinned] = 0.0
+        x -= (z @ x) / (z @ z) * z
+    return x
+
+
+@pytest.mark.parametrize("name,mk,k,cond", [
+    ("vor60_k2_v", lambda: voronoi_lloyd(60, 2), 2, "v"),
+    ("vor60_k2_vp", lambda: voronoi_lloyd(60, 2), 2, "vp"),
+    ("vor200_k3_v", lambda: voronoi_lloyd(200, 5), 3, "v"),
+    ("quad6_k1_v_neumann", lambda: cartesian_quads(6).with_bc(lambda x: 2 if x[0] > 1 - 1e-12 else 1), 1, "v"),
+    ("hex3_k1_vp", lambda: cartesian_hexes(3), 1, "vp"),
+    ("hex4_k1_v", lambda: cartesian_hexes(4), 1, "v"),
+])
+def test_fronts_reproduce_the_bordered_direct_solution(name, mk, k, cond):
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    mesh = mk()
+    data = problem_data(polynomial_stokes(mesh.dim, k + 1, 3), None, mesh.dim)
+    P = H.Problem(H.Mesh(mesh), k, cond, coarse_mode="direct")
+    P.set_data(*data)
+    I = {n: P.direct_info(n) for n in NAMES}
+    O = OS.build(mesh, k, cond, data, eta=None)
+    S, z = O.S[-1].toarray(), O.z[-1]
+    N = S.shape[0]
+    b = np.random.default_rng(1).standard_normal(N)
+    x = _eliminate(S, z, I, b)
+    if z is not None:
+        xd = np.linalg.solve(np.block([[S, z[:, None]], [z[None, :], np.zeros((1, 1))]]), np.append(b, 0.0))[:N]
+        assert I["pinned"][0] >= 0
+    else:
+        xd = np.linalg.solve(S, b)
+        assert I["pinned"][0] < 0
+    err = np.abs(x - xd).max() / np.abs(xd).max()
+    nfront, nheight = I["sizes"][:2]
+    print(f"[direct symbolic] {name}: {N} unknowns, {nfront} fronts, {nheight} heights, err {err:.1e}")
+    assert nheight >= 2 and err <= 1e-11
+
+
+def test_direct_mode_rejects_what_it_cannot_solve():
+    import paper_2009_13840_amd as H
+    with pytest.raises(H.HHOError):
+        H.Problem(H.Mesh(cartesian_quads(2)), 1, "v", coarse_mode="direct", degrees=[1])  # coarsest degree 1

@@ -39,6 +39,7 @@ def _same(a, b):
     ("vor60_k3_vp_fp32", lambda: voronoi_lloyd(60, 2), 3, "vp", dict(coarse_mode="amg", precision="fp32")),
     ("quad4_k2_v_dense", lambda: cartesian_quads(4), 2, "v", dict(coarse_mode="dense")),
     ("hex3_k2_vp_gmres", lambda: cartesian_hexes(3), 2, "vp", dict(coarse_mode="gmres")),
+    ("vor60_k3_v_direct", lambda: voronoi_lloyd(60, 2), 3, "v", dict(coarse_mode="direct")),
 ])
 def test_graph_replays_equal_eager_solve(name, mk, k, cond, opts):
     import torch

@@ -305,34 +305,37 @@ def test_fgmres_solution_long_coarse_cycles(built, name, mk, k, cond):
 
 
 @pytest.mark.parametrize("name,mk,k,cond", CASES)
-@pytest.mark.parametrize("coarse", ["dense", "gmres"])
+@pytest.mark.parametrize("coarse", ["dense", "gmres", "direct"])
 def test_fgmres_solution(built, name, mk, k, cond, coarse):
     mesh, M, P, O = built(name, mk, k, cond, coarse_mode=coarse, rtol=1e-12)
-    its, its_o = _solution_parity(O, P, "direct" if coarse == "dense" else "gmres", f"{name} {coarse}")
-    if coarse == "dense":
+    exact = coarse in ("dense", "direct")     # both solve the coarsest level exactly
+    its, its_o = _solution_parity(O, P, "direct" if exact else "gmres", f"{name} {coarse}")
+    if exact:
         assert its == its_o
 
 
+@pytest.mark.parametrize("coarse", ["dense", "direct"])
 @pytest.mark.parametrize("restart", [30, 3])
 @pytest.mark.parametrize("name,mk,k,cond", CASES + CASES_3D_K3)
-def test_fgmres_history_matches_oracle(built, name, mk, k, cond, restart):
+def test_fgmres_history_matches_oracle(built, name, mk, k, cond, restart, coarse):
     """Iteration-level parity of flexible GMRES (CGS2 Arnoldi, Givens rotations,
-    restarts from the true residual): with the exact coarsest solve the V-cycle is
-    the same linear map on both sides, so the library and the oracle take the
-    same number of iterations and their relative residual estimates agree to
-    1e-8 per entry while above 1e-8.  Restart 3 forces several restarts."""
+    restarts from the true residual): with the exact coarsest solve (bordered
+    dense inverse, or the sparse direct solver) the V-cycle is the same linear
+    map on both sides, so the library and the oracle take the same number of
+    iterations and their relative residual estimates agree to 1e-8 per entry
+    while above 1e-8.  Restart 3 forces several restarts."""
     import oracle.solve as OS
-    mesh, M, P, O = built(name, mk, k, cond, coarse_mode="dense", rtol=1e-10, restart=restart)
+    mesh, M, P, O = built(name, mk, k, cond, coarse_mode=coarse, rtol=1e-10, restart=restart)
     x, its, hist, rel, ok = P.solve()
     assert ok
     xo, its_o, hist_o, conv = OS.solve_fgmres(O, rtol=1e-10, restart=restart, coarse="direct")
     ho = np.asarray(hist_o)
-    print(f"[history] {name} restart {restart}: its {its} (oracle {its_o})")
+    print(f"[history] {name} {coarse} restart {restart}: its {its} (oracle {its_o})")
     assert its == its_o and len(hist) == len(ho)
     sel = ho > 1e-8
     assert sel.sum() >= 3
     dev = np.abs(hist[sel] - ho[sel]) / ho[sel]
-    print(f"[history] {name} restart {restart}: max per-entry deviation {dev.max():.2e}")
+    print(f"[history] {name} {coarse} restart {restart}: max per-entry deviation {dev.max():.2e}")
     assert dev.max() <= 1e-8, dev.max()
 
 
