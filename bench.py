@@ -220,7 +220,7 @@ def cpu_model():
     return "unknown"
 
 
-def cpu_baseline(spec, sample_cells=4096):
+def cpu_baseline(spec, sample_cells=4096, coarse="amg"):
     """The oracle as it stands, on a bounded sample of the workload's family (the
     same mesh generator and seed, fewer cells; same degree, variant and solver
     settings: cell-patch Schwarz GMRES(2) smoothing, coarsest level by GMRES to
@@ -281,8 +281,11 @@ def cpu_baseline(spec, sample_cells=4096):
     z = [nullspace(mesh, geo, lay) for lay in lays]
     P = OS.Problem(mesh, geo, k, cond, degrees, eta, locs, blocks, lays, S, b, idx, z)
     t1 = time.perf_counter()
-    H = OS.hierarchy(P, coarse="amg", coarse_rtol=1e-3 if mesh.dim == 3 else 1e-2)
-    H.amg_nu = 1        # the library's default: one damped-Jacobi sweep per AMG level
+    if coarse == "direct":   # the coarsest level solved exactly (sparse LU of the bordered operator)
+        H = OS.hierarchy(P, coarse="direct")
+    else:
+        H = OS.hierarchy(P, coarse="amg", coarse_rtol=1e-3 if mesh.dim == 3 else 1e-2)
+        H.amg_nu = 1        # the library's default: one damped-Jacobi sweep per AMG level
     x, its, hist, conv = OS.solve_fgmres(P, rtol=1e-8, H=H)
     t2 = time.perf_counter()
     dt = t2 - t0
@@ -290,7 +293,9 @@ def cpu_baseline(spec, sample_cells=4096):
     return {"value": n0 / dt / 1e9, "unit": "GDOF/s", "cores": threads, "kind": "oracle",
             "cpu_model": cpu_model(), "cpu_count": os.cpu_count(),
             "sample": (f"{name}: {n0} fine DOFs, FGMRES {its} its to 1e-8 ({'converged' if conv else 'NOT converged'}), "
-                       f"{sum(H.coarse_its)} coarse its; timed {dt:.1f} s = condensation/assembly/levels "
+                       + (f"coarsest level by a sparse LU (SciPy SuperLU) of the bordered operator; "
+                          if coarse == "direct" else f"{sum(H.coarse_its)} coarse its; ")
+                       + f"timed {dt:.1f} s = condensation/assembly/levels "
                        f"{t1 - t0:.1f} s + smoother/coarse setup and FGMRES {t2 - t1:.1f} s (NumPy/SciPy FP64: "
                        f"dense products on up to {threads} BLAS threads, per-cell loops and sparse products on one); "
                        f"untimed local operators {t_host:.1f} s on {workers} processes"),
@@ -482,6 +487,12 @@ class ByteModel:
             self.amg = [P.amg_level_info(l) for l in range(lv0["levels"])]
         except Exception:
             self.amg = []
+        self.direct = {}  # sparse direct coarse solve: per tree height (front entries read, front unknowns)
+        try:
+            for kind in ("fwd", "bwd"):
+                self.direct[kind] = P.direct_info("h" + kind).reshape(-1, 2)
+        except Exception:
+            self.direct = {}
 
     def spmv(self, level, elem, val=None):
         key = (level, elem, val)
@@ -500,6 +511,12 @@ class ByteModel:
             return self.spmv(self.nlev - 1, 8)[0]
         if kind == "outer_operator":
             return self.spmv(0, 8)[0]
+        if kind in ("direct_fwd", "direct_bwd"):
+            # every front entry the pass reads once (8 bytes), its fronts' vectors:
+            # forward gathers b and the children's updates and writes v and u,
+            # backward gathers [v1; x2] and writes x1 (about three vectors each)
+            ent, unk = self.direct[kind[7:]][level]
+            return 8 * int(ent) + 3 * 8 * int(unk)
         L = self.amg[level]
         N = self.amg[level + 1] if level + 1 < len(self.amg) else None
         return _amg_bytes(kind, L, N, d)
@@ -511,6 +528,8 @@ class ByteModel:
             return [self.nlev - 1]
         if kind == "outer_operator":
             return [0]
+        if kind in ("direct_fwd", "direct_bwd"):
+            return range(len(self.direct.get(kind[7:], [])))
         return range(len(self.amg))
 
 
@@ -529,7 +548,8 @@ def kernel_label(kind, mesh, spec, model, level):
         return f"k_precond<{T}, {(rows + 63) // 64}, {d if spec['cond'] == 'v' else 1}>"
     return {"amg_restrict": "k_amg_restrict", "amg_sweep": "k_amg_rows<G>", "amg_prolong": "k_amg_prolong_sweep<G>",
             "amg_dense": "k_amg_dense", "coarse_operator": "k = 0 operator (k_spmv_v0 / k_spmv_vp)",
-            "outer_operator": "level-0 operator, one-slot form"}[kind]
+            "outer_operator": "level-0 operator, one-slot form", "direct_fwd": "k_nd_fwd",
+            "direct_bwd": "k_nd_bwd"}[kind]
 
 
 def probe_table(P, model):
@@ -566,6 +586,22 @@ def roofline_from(table, kind, label, workload):
                        for r in rows]}
 
 
+def coarse_label(P, dim, args):
+    """What the problem's coarsest-level solver is (the option, or what AUTO chose)."""
+    try:
+        sizes = P.direct_info("sizes")
+        return (f"sparse direct solve (nested dissection, multifrontal elimination on the device: "
+                f"{sizes[0]} fronts, {sizes[1]} tree heights, largest front {sizes[4]})")
+    except Exception:
+        pass
+    try:
+        P.amg_level_info(0)
+        return (f"GMRES to {args.coarse_rtol or (1e-3 if dim == 3 else 1e-2):g} preconditioned by a block-triangular "
+                "Stokes preconditioner with a smoothed-aggregation AMG velocity block")
+    except Exception:
+        return "bordered dense inverse" if args.coarse in ("auto", "dense") else f"coarse_mode {args.coarse}"
+
+
 def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=None, probe=True, copy="convert",
              graph=False, smoother="schwarz"):
     """One configuration of the solver on the workload: host phase and upload
@@ -578,7 +614,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
     import paper_2009_13840_amd as H
     M = H.Mesh(mesh)
     P = H.Problem(M, spec["k"], spec["cond"], precision=precision, coarse_rtol=args.coarse_rtol,
-                  learned=1 if learned else 0, vcycle_copy=copy, smoother=smoother)
+                  learned=1 if learned else 0, vcycle_copy=copy, smoother=smoother, coarse_mode=args.coarse)
     t_host = time.perf_counter()
     P.set_data(*data)
     t_host = time.perf_counter() - t_host
@@ -682,7 +718,7 @@ def run_mode(mesh, data, spec, workload, precision, args, learned=False, x_ref=N
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(vc_bytes / (tm["vcycle_ms"] / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
             "note": "bytes: the probed kernel classes of one untimed step (operator, smoother, coarse operator, "
-                    "AMG) per V-cycle; time: the V-cycle's events of the last timed step; Krylov vector "
+                    "AMG or the direct solve's passes) per V-cycle; time: the V-cycle's events of the last timed step; Krylov vector "
                     "traffic is not counted in the bytes",
             "probed_kernel_ms_share": round(vc_ms_probed / tm["vcycle_ms"] / 1.0, 4) if tm["vcycle_ms"] else None,
             "classes": {kk: {"launches": sum(r["launches"] for r in table_all[kk]),
@@ -704,6 +740,9 @@ def main():
                     help="precision of the headline run (the other modes are reported beside it)")
     ap.add_argument("--coarse-rtol", type=float, default=0.0,
                     help="coarsest-level GMRES tolerance (0: the library's default, 1e-3 in 3D and 1e-2 in 2D)")
+    ap.add_argument("--coarse", default="auto", choices=["auto", "direct", "amg", "gmres", "dense"],
+                    help="coarsest-level solver (auto: the sparse direct solve for a single 2D problem, "
+                         "AMG-preconditioned GMRES in 3D and for batches)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch of 256 problems in the default run")
     ap.add_argument("--probe-stride", type=int, default=PROBE_STRIDE,
@@ -733,7 +772,9 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         try:
-            cpu = cpu_baseline(WORKLOADS[args.workload], args.cpu_sample_cells)
+            spec0 = WORKLOADS[args.workload]
+            direct = args.coarse == "direct" or (args.coarse == "auto" and spec0["mesh"] != "hex")
+            cpu = cpu_baseline(spec0, args.cpu_sample_cells, coarse="direct" if direct else "amg")
         except Exception as e:  # pragma: no cover
             cpu = {"error": repr(e)}
         print(f"[bench] cpu baseline: {json.dumps(cpu)}", file=sys.stderr, flush=True)
@@ -788,6 +829,7 @@ def main():
         torch.cuda.synchronize()
     P, x, rec, roof = head
     n0 = P.level_size(0)
+    coarse_desc = coarse_label(P, mesh.dim, args)
     # back-substitution of the cell unknowns from the headline solution (outside the step)
     rec_ms = []
     for _ in range(3):
@@ -816,6 +858,7 @@ def main():
             if form == "fp64":
                 lref = lx.clone()
                 largest["fine_dofs"] = LP.level_size(0)
+                largest["coarse"] = coarse_label(LP, lmesh.dim, args)
                 largest["roofline"] = lroof
             lrec["err_vs_fp64_reference"] = float(torch.linalg.norm(lx - lref) / torch.linalg.norm(lref))
             largest[form] = lrec
@@ -854,9 +897,7 @@ def main():
         "config": {"workload": args.workload, "cells": mesh.n_cells, "faces": mesh.n_faces, "k": spec["k"],
                    "cond": spec["cond"], "levels": list(range(spec["k"], -1, -1)), "fine_dofs": n0,
                    "rtol": 1e-8,
-                   "coarse": (f"GMRES to {args.coarse_rtol or (1e-3 if mesh.dim == 3 else 1e-2):g} preconditioned by a block-triangular Stokes "
-                              "preconditioner with a smoothed-aggregation AMG velocity block"
-                              if n0 > 4096 else "bordered dense inverse"),
+                   "coarse": coarse_desc,
                    "smoother": "GMRES(2), right-preconditioned by cell-patch additive Schwarz"},
         "converged": converged,
         "failures": rec["failures"],

@@ -79,7 +79,9 @@ extern "C" {
                                FP32 vectors and arithmetic */
 
 /* coarsest-level solver */
-#define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns, else AMG when k_L = 0, else GMRES */
+#define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns; else, when k_L = 0, DIRECT for a
+                                 single 2D problem (the paper's 2D choice) and AMG otherwise;
+                                 else GMRES                                                   */
 #define HHO_COARSE_DENSE  1   /* bordered dense inverse (FP64)                                */
 #define HHO_COARSE_GMRES  2   /* GMRES to coarse_rtol, cell-patch Schwarz preconditioner      */
 #define HHO_COARSE_AMG    3   /* GMRES to coarse_rtol, block-triangular Stokes preconditioner
@@ -335,7 +337,9 @@ int hho_coarse_solve_apply(hho_problem *p, const double *b, double *x);
  * elimination order), "cmap" (2 per front position: position in child 0/1's
  * update part, -1 if absent), "hptr"/"hfront" (fronts by tree height), "pinned"
  * (the unknown fixed to zero, or -1), "sizes" (fronts, heights, front entries,
- * factor entries used by the solves, largest front).  cap: room in out;
+ * factor entries used by the solves, largest front), "hfwd"/"hbwd" (per tree
+ * height, two values: the front entries the forward / backward pass reads, and
+ * the unknowns of its fronts).  cap: room in out;
  * *n_out receives the length (HHO_E_CAPACITY when it exceeds cap). */
 int hho_direct_info(const hho_problem *p, const char *name, int64_t *out, int64_t cap, int64_t *n_out);
 
@@ -386,7 +390,9 @@ int hho_get_timings(const hho_problem *p, double *t, int n);
 #define HHO_PROBE_AMG_SWEEP       32   /* AMG damped-Jacobi sweeps, AMG level l                             */
 #define HHO_PROBE_AMG_PROLONG     64   /* AMG prolongation with the first post-sweep, AMG level l           */
 #define HHO_PROBE_AMG_DENSE      128   /* AMG explicit small-level operator or dense coarsest inverse       */
-#define HHO_PROBE_ALL            255
+#define HHO_PROBE_DIRECT_FWD     256   /* sparse direct coarse solve, forward pass, tree height l           */
+#define HHO_PROBE_DIRECT_BWD     512   /* sparse direct coarse solve, backward pass, tree height l          */
+#define HHO_PROBE_ALL           1023
 
 /* Arms the classes of `mask` (0 disarms) and discards recorded launches; every
  * stride-th launch (>= 1) of each armed class and level is timed, the first one

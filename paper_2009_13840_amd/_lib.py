@@ -20,7 +20,7 @@ ERRORS = {-1: "HHO_E_INVALID_ARG", -2: "HHO_E_MESH", -3: "HHO_E_LOCAL_SINGULAR",
           -5: "HHO_E_BREAKDOWN", -6: "HHO_E_DEVICE", -7: "HHO_E_CAPACITY", -8: "HHO_E_OOM"}
 COND = {"v": 1, "vp": 2}
 PROBE = {"operator": 1, "smoother": 2, "coarse_operator": 4, "outer_operator": 8, "amg_restrict": 16,
-         "amg_sweep": 32, "amg_prolong": 64, "amg_dense": 128}
+         "amg_sweep": 32, "amg_prolong": 64, "amg_dense": 128, "direct_fwd": 256, "direct_bwd": 512}
 PREC = {"fp64": 0, "fp32": 1, "bf16": 2}
 COARSE = {"auto": 0, "dense": 1, "gmres": 2, "amg": 3, "direct": 4}
 COPY = {"convert": 0, "product": 1}

@@ -8,6 +8,7 @@
 
 #include "device.h"
 #include "direct.h"
+#include "probe.h"
 
 namespace hho {
 
@@ -32,7 +33,8 @@ void launch_nd_factor(const NdHost &H, const NdDev &D, const DLevel<double> &L, 
 // x = S^{-1} b on the coarsest level; with a pinned unknown (constant-pressure
 // null space, zmean the null vector's cell coefficients, zz its squared norm)
 // b is first made orthogonal to the null vector and so is x afterwards.
+// probe: live timing of the passes (classes HHO_PROBE_DIRECT_FWD / _BWD, level = tree height), or null.
 void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int nc, const double *zmean, double zz,
-                     const double *b, double *x, hipStream_t s);
+                     const double *b, double *x, hipStream_t s, KernelProbe *probe);
 
 }  // namespace hho

@@ -487,7 +487,7 @@ void launch_nd_factor(const NdHost &H, const NdDev &D, const DLevel<double> &L, 
 }
 
 void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int nc, const double *zmean, double zz,
-                     const double *b, double *x, hipStream_t s) {
+                     const double *b, double *x, hipStream_t s, KernelProbe *probe) {
   static std::once_flag once_f, once_b;
   static hipError_t attr_f = hipSuccess, attr_b = hipSuccess;
   reserve_lds((const void *)k_nd_fwd, once_f, attr_f);
@@ -498,14 +498,17 @@ void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int 
     const int nch = H.cptr[h + 1] - H.cptr[h];
     if (nch == 0) continue;
     const size_t lds = (size_t)H.hmaxm[h] * sizeof(double);
-    hipLaunchKernelGGL(k_nd_fwd, dim3(nch), dim3(kNdThreads), lds, s, D, D.chunks + 2 * (int64_t)H.cptr[h], b, nface,
-                       t, zmean, pin ? (const double *)D.coef : nullptr);
+    const int32_t *ch = D.chunks + 2 * (int64_t)H.cptr[h];
+    const double *cf = pin ? (const double *)D.coef : nullptr;
+    HHO_PROBED(probe, HHO_PROBE_DIRECT_FWD, h, s,
+               HHO_LAUNCH(k_nd_fwd, dim3(nch), dim3(kNdThreads), lds, s, D, ch, b, nface, t, zmean, cf));
   }
   for (int h = H.nheight - 1; h >= 0; --h) {
     const int nch = H.cptr[h + 1] - H.cptr[h];
     if (nch == 0) continue;
     const size_t lds = (size_t)H.hmaxm[h] * sizeof(double);
-    hipLaunchKernelGGL(k_nd_bwd, dim3(nch), dim3(kNdThreads), lds, s, D, D.chunks + 2 * (int64_t)H.cptr[h], x);
+    const int32_t *ch = D.chunks + 2 * (int64_t)H.cptr[h];
+    HHO_PROBED(probe, HHO_PROBE_DIRECT_BWD, h, s, HHO_LAUNCH(k_nd_bwd, dim3(nch), dim3(kNdThreads), lds, s, D, ch, x));
   }
   if (pin) hipLaunchKernelGGL(k_nd_proj_out, dim3(1), dim3(1024), 0, s, nc, nface, t, zmean, zz, H.pinned, x);
 }

@@ -17,7 +17,7 @@
 
 namespace hho {
 
-constexpr int kProbeClasses = 8, kProbeLevels = 16;
+constexpr int kProbeClasses = 10, kProbeLevels = 16;
 
 struct KernelProbe {
   unsigned mask = 0;  // armed classes (HHO_PROBE_* bits)

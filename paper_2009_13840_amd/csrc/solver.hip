@@ -813,7 +813,9 @@ static void init_levels(hho_problem *P) {
     fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
   if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
   P->dense_n = nd;
-  P->coarse_direct = !P->coarse_dense && P->opt.coarse_mode == HHO_COARSE_DIRECT;
+  P->coarse_direct = !P->coarse_dense && (P->opt.coarse_mode == HHO_COARSE_DIRECT ||
+                                          (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0 && P->d == 2 &&
+                                           P->nseg == 0));
   if (P->coarse_direct && LC.k != 0) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver needs a coarsest degree of 0");
   if (P->coarse_direct && P->nseg > 1 && P->border)
     fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
@@ -1418,7 +1420,7 @@ static void coarse_solve(hho_problem *P) {
     return;
   }
   if (P->coarse_direct) {
-    launch_nd_solve(P->nd, P->ndd, L.nface, L.t, (int)P->mesh->nc, P->tp.zmean, P->nd_zz, V.b, V.w, s);
+    launch_nd_solve(P->nd, P->ndd, L.nface, L.t, (int)P->mesh->nc, P->tp.zmean, P->nd_zz, V.b, V.w, s, &P->probe);
     return;
   }
   if (P->in_capture) {
@@ -2378,6 +2380,18 @@ int hho_direct_info(const hho_problem *p, const char *name, int64_t *out, int64_
   else if (n == "hfront") put(H.hfront);
   else if (n == "pinned") v = {H.pinned};
   else if (n == "sizes") v = {H.nfront, H.nheight, H.total, H.factor_entries, H.maxm};
+  else if (n == "hfwd" || n == "hbwd") {
+    for (int h = 0; h < H.nheight; ++h) {
+      int64_t ent = 0, unk = 0;
+      for (int32_t x = H.hptr[h]; x < H.hptr[h + 1]; ++x) {
+        const int64_t m = H.m[H.hfront[x]], f = H.nfs[H.hfront[x]];
+        ent += n == "hfwd" ? (m - f) * f : f * m;
+        unk += m;
+      }
+      v.push_back(ent);
+      v.push_back(unk);
+    }
+  }
   else hho::fail(HHO_E_INVALID_ARG, "direct_info: unknown name " + n);
   *n_out = (int64_t)v.size();
   if ((int64_t)v.size() > cap) hho::fail(HHO_E_CAPACITY, "direct_info: buffer too small");
