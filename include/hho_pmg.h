@@ -80,7 +80,8 @@ extern "C" {
 
 /* coarsest-level solver */
 #define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns; else, when k_L = 0, DIRECT for a
-                                 single 2D problem (the paper's 2D choice) and AMG otherwise;
+                                 single problem whose fronts fit (32 GiB of fronts, the largest
+                                 within one compute unit's LDS) and AMG otherwise (batches);
                                  else GMRES                                                   */
 #define HHO_COARSE_DENSE  1   /* bordered dense inverse (FP64)                                */
 #define HHO_COARSE_GMRES  2   /* GMRES to coarse_rtol, cell-patch Schwarz preconditioner      */

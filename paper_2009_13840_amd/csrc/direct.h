@@ -42,7 +42,7 @@ struct NdHost {
   std::vector<int64_t> soff;                 // [nfront] panel scratch offset (fronts of the larger heights)
   std::vector<int64_t> src, dst;             // operator entry (bsr | cpl | spp concatenated) -> front entry
   std::vector<int32_t> hfront, hptr;         // fronts by height
-  std::vector<int32_t> tiles, tptr;          // (front, row, col) tiles of each larger height
+  std::vector<int32_t> tiles, tptr;          // (front, row, col) tiles (col <= row) of each larger height
   std::vector<int32_t> chunks, cptr;         // (front, first row) chunks of every height
   std::vector<uint8_t> big;                  // [nheight] height eliminated by panels
   std::vector<int32_t> hmaxnfs, hmaxm;       // [nheight]

@@ -153,14 +153,18 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_small(NdDev D, const int
   }
 }
 
-// Larger fronts: children's updates added, one 64 x 64 tile per block.
+// Larger fronts: children's updates added, one 64 x 64 tile of the lower
+// triangle per block; the updates are symmetric, so an off-diagonal tile's sums
+// are also added, transposed through LDS, to its mirror tile.
 __global__ void __launch_bounds__(kNdThreads) k_nd_extend(NdDev D, const int32_t *tiles) {
   __shared__ int rm[2][kNdTile], cm[2][kNdTile];
+  __shared__ double T[kNdTile * kNdLd];
   const int F = tiles[3 * blockIdx.x], r0 = tiles[3 * blockIdx.x + 1], q0 = tiles[3 * blockIdx.x + 2];
   const ChildRef ch[2] = {child_ref(D, F, 0), child_ref(D, F, 1)};
   if (ch[0].f < 0 && ch[1].f < 0) return;
   const int m = D.m[F];
   const int64_t dofo = D.dofoff[F];
+  double *M = D.F + D.off[F];
   for (int e = threadIdx.x; e < 2 * kNdTile; e += kNdThreads) {
     const int s = e / kNdTile, i = e % kNdTile;
     rm[s][i] = (ch[s].f >= 0 && r0 + i < m) ? D.cmap[2 * (dofo + r0 + i) + s] : -1;
@@ -168,16 +172,18 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_extend(NdDev D, const int32_t
   }
   __syncthreads();
   const int j = threadIdx.x % kNdTile;
-  if (q0 + j >= m) return;
-  for (int i = threadIdx.x / kNdTile; i < kNdTile && r0 + i < m; i += kNdThreads / kNdTile) {
+  for (int i = threadIdx.x / kNdTile; i < kNdTile; i += kNdThreads / kNdTile) {
     double v = 0;
-    bool any = false;
     for (int s = 0; s < 2; ++s)
-      if (rm[s][i] >= 0 && cm[s][j] >= 0) {
-        v += child_u(D, ch[s], rm[s][i], cm[s][j]);
-        any = true;
-      }
-    if (any) D.F[D.off[F] + (int64_t)(r0 + i) * m + q0 + j] += v;
+      if (rm[s][i] >= 0 && cm[s][j] >= 0) v += child_u(D, ch[s], rm[s][i], cm[s][j]);
+    T[i * kNdLd + j] = v;
+    if (r0 + i < m && q0 + j < m && v != 0.0) M[(int64_t)(r0 + i) * m + q0 + j] += v;
+  }
+  if (r0 == q0) return;
+  __syncthreads();
+  for (int i = threadIdx.x / kNdTile; i < kNdTile; i += kNdThreads / kNdTile) {  // mirror tile: row q0 + i
+    const double v = T[j * kNdLd + i];
+    if (q0 + i < m && r0 + j < m && v != 0.0) M[(int64_t)(q0 + i) * m + r0 + j] += v;
   }
 }
 
@@ -272,8 +278,9 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_panel(NdDev D, const int
   }
 }
 
-// The panel's sweep applied to one 64 x 64 tile of a larger front.  Thread
-// (ty, tx) owns rows ty + 16 r and columns tx + 16 c (r, c < 4).
+// The panel's sweep applied to one 64 x 64 tile of the lower triangle of a
+// larger front, and its transpose written to the mirror tile (the front is
+// symmetric).  Thread (ty, tx) owns rows ty + 16 r and columns tx + 16 c (r, c < 4).
 __global__ void __launch_bounds__(kNdThreads) k_nd_update(NdDev D, const int32_t *tiles, int k0) {
   extern __shared__ double lds_update[];
   double *Wt = lds_update;                 // Wt[p * kNdLd + i]: W of the tile's rows, transposed
@@ -304,26 +311,38 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_update(NdDev D, const int32_t
       for (int c = 0; c < 4; ++c) acc[r][c] += a[r] * b[c];
   }
   double *M = D.F + D.off[F];
+  const bool mirror = r0 != q0;
+  __syncthreads();  // Wt / St no longer read: the tile's new values are staged in Wt
+  double *T = Wt;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = r0 + ty + 16 * r;
-    if (row >= m) continue;
     const bool iP = row >= k0 && row < k0 + nb;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int cl = q0 + tx + 16 * c;
-      if (cl >= m) continue;
+      if (row >= m || cl >= m) continue;
       const bool jP = cl >= k0 && cl < k0 + nb;
       double &x = M[(int64_t)row * m + cl];
+      double nv;
       if (!iP && !jP)
-        x -= acc[r][c];
+        nv = x - acc[r][c];
       else if (!iP)
-        x = Wt[(cl - k0) * kNdLd + ty + 16 * r];
+        nv = W[(int64_t)row * kNdPanel + (cl - k0)];
       else if (!jP)
-        x = W[(int64_t)cl * kNdPanel + (row - k0)];
+        nv = W[(int64_t)cl * kNdPanel + (row - k0)];
       else
-        x = -Sc[(row - k0) * kNdPanel + (cl - k0)];
+        nv = -Sc[(row - k0) * kNdPanel + (cl - k0)];
+      x = nv;
+      if (mirror) T[(ty + 16 * r) * kNdLd + tx + 16 * c] = nv;
     }
+  }
+  if (!mirror) return;
+  __syncthreads();
+  // the front stays symmetric: the mirror tile (rows q0.., columns r0..) is the transpose
+  for (int i = w; i < kNdTile; i += kNdWaves) {
+    if (q0 + i >= m || r0 + lane >= m) continue;
+    M[(int64_t)(q0 + i) * m + r0 + lane] = T[lane * kNdLd + i];
   }
 }
 

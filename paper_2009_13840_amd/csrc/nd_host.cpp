@@ -359,7 +359,7 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
         H->soff[i] = scratch;
         scratch += (int64_t)kNdPanel * kNdPanel + 2 * (int64_t)m * kNdPanel;
         for (int r = 0; r < m; r += kNdTile)
-          for (int c = 0; c < m; c += kNdTile) {
+          for (int c = 0; c <= r; c += kNdTile) {  // lower triangle; the kernels mirror the rest
             H->tiles.push_back(i);
             H->tiles.push_back(r);
             H->tiles.push_back(c);

@@ -814,8 +814,7 @@ static void init_levels(hho_problem *P) {
   if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
   P->dense_n = nd;
   P->coarse_direct = !P->coarse_dense && (P->opt.coarse_mode == HHO_COARSE_DIRECT ||
-                                          (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0 && P->d == 2 &&
-                                           P->nseg == 0));
+                                          (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0 && P->nseg == 0));
   if (P->coarse_direct && LC.k != 0) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver needs a coarsest degree of 0");
   if (P->coarse_direct && P->nseg > 1 && P->border)
     fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
@@ -824,6 +823,23 @@ static void init_levels(hho_problem *P) {
                   (P->opt.coarse_mode == HHO_COARSE_AMG || (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
   if (P->coarse_amg && LC.k != 0) fail(HHO_E_INVALID_ARG, "AMG coarse solver needs a coarsest degree of 0");
   P->amgh.levels.clear();  // built by amg_levels() once the problem's data are set
+}
+
+// AUTO's sparse direct solve only while its fronts fit: their storage within
+// kNdAutoBytes and the largest front within the solve kernels' LDS; otherwise
+// the AMG-preconditioned GMRES (decided once the symbolic phase has run)
+constexpr int64_t kNdAutoBytes = int64_t(32) << 30;
+static void settle_auto_coarse(hho_problem *P) {
+  if (P->opt.coarse_mode != HHO_COARSE_AUTO || !P->coarse_direct || !P->nd.m.empty()) return;
+  const LevelInfo &LC = P->lev[P->nlev - 1];
+  nd_symbolic(P->mesh, P->d, LC.p, LC.t, P->cond, P->border != 0, P->rowptr, P->col, &P->nd);
+  const NdHost &H = P->nd;
+  if (H.total * (int64_t)sizeof(double) <= kNdAutoBytes &&
+      (int64_t)H.maxm * (int64_t)sizeof(double) <= (int64_t)kMaxLdsBytes - 1024)
+    return;
+  P->nd = NdHost{};
+  P->coarse_direct = false;
+  P->coarse_amg = true;
 }
 
 // symbolic smoothed-aggregation hierarchy of the coarsest level (topology only)
@@ -1972,6 +1988,7 @@ int hho_problem_set_data(hho_problem *p, hho_field_fn f, hho_field_fn gD, hho_fi
     hho::build_local(p->mesh, p->k, p->eta, p->cell_eta.empty() ? nullptr : p->cell_eta.data(), qdeg, f, gD, gN,
                      ctx, &p->loc);
   }
+  hho::settle_auto_coarse(p);
   hho::amg_levels(p);
   p->have_data = true;
   p->setup_done = false;
