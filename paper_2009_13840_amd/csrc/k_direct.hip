@@ -16,8 +16,10 @@
 //                         front's first nfs rows times [v1; x2].
 // Fronts of at most kNdSmall unknowns are swept in LDS by one block; larger ones
 // in panels of kNdPanel pivots: one launch inverts the panel's pivot block and
-// forms W = M_RP M_PP^{-1} by row chunks, the next updates the whole front by
-// 64 x 64 tiles (M_RR -= W M_PR, M_RP = W, M_PR = W^T, M_PP = -M_PP^{-1}).
+// forms W = M_RP M_PP^{-1} by row chunks, the next updates the front's lower
+// triangle by 64 x 64 tiles and mirrors it (M_RR -= W M_PR, M_RP = W,
+// M_PR = W^T, M_PP = -M_PP^{-1}); the first panel's two launches also add the
+// children's updates to what they read.
 #include <mutex>
 
 #include "dev_common.h"
@@ -74,6 +76,18 @@ __device__ inline ChildRef child_ref(const NdDev &D, int F, int s) {
 // entry (ia, ib) of a child's update block
 __device__ inline double child_u(const NdDev &D, const ChildRef &c, int ia, int ib) {
   return D.F[c.off + (int64_t)(c.nfs + ia) * c.m + c.nfs + ib];
+}
+
+// what the children pass to entry (a, b) of front F (child 0's, then child 1's)
+__device__ inline double children_sum(const NdDev &D, const ChildRef (&ch)[2], int64_t dofo, int a, int b) {
+  double v = 0.0;
+#pragma unroll
+  for (int s = 0; s < 2; ++s) {
+    if (ch[s].f < 0) continue;
+    const int ca = D.cmap[2 * (dofo + a) + s], cb = D.cmap[2 * (dofo + b) + s];
+    if (ca >= 0 && cb >= 0) v += child_u(D, ch[s], ca, cb);
+  }
+  return v;
 }
 
 // Fronts of one height with at most kNdSmall (128) unknowns: one block each,
@@ -153,40 +167,6 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_small(NdDev D, const int
   }
 }
 
-// Larger fronts: children's updates added, one 64 x 64 tile of the lower
-// triangle per block; the updates are symmetric, so an off-diagonal tile's sums
-// are also added, transposed through LDS, to its mirror tile.
-__global__ void __launch_bounds__(kNdThreads) k_nd_extend(NdDev D, const int32_t *tiles) {
-  __shared__ int rm[2][kNdTile], cm[2][kNdTile];
-  __shared__ double T[kNdTile * kNdLd];
-  const int F = tiles[3 * blockIdx.x], r0 = tiles[3 * blockIdx.x + 1], q0 = tiles[3 * blockIdx.x + 2];
-  const ChildRef ch[2] = {child_ref(D, F, 0), child_ref(D, F, 1)};
-  if (ch[0].f < 0 && ch[1].f < 0) return;
-  const int m = D.m[F];
-  const int64_t dofo = D.dofoff[F];
-  double *M = D.F + D.off[F];
-  for (int e = threadIdx.x; e < 2 * kNdTile; e += kNdThreads) {
-    const int s = e / kNdTile, i = e % kNdTile;
-    rm[s][i] = (ch[s].f >= 0 && r0 + i < m) ? D.cmap[2 * (dofo + r0 + i) + s] : -1;
-    cm[s][i] = (ch[s].f >= 0 && q0 + i < m) ? D.cmap[2 * (dofo + q0 + i) + s] : -1;
-  }
-  __syncthreads();
-  const int j = threadIdx.x % kNdTile;
-  for (int i = threadIdx.x / kNdTile; i < kNdTile; i += kNdThreads / kNdTile) {
-    double v = 0;
-    for (int s = 0; s < 2; ++s)
-      if (rm[s][i] >= 0 && cm[s][j] >= 0) v += child_u(D, ch[s], rm[s][i], cm[s][j]);
-    T[i * kNdLd + j] = v;
-    if (r0 + i < m && q0 + j < m && v != 0.0) M[(int64_t)(r0 + i) * m + q0 + j] += v;
-  }
-  if (r0 == q0) return;
-  __syncthreads();
-  for (int i = threadIdx.x / kNdTile; i < kNdTile; i += kNdThreads / kNdTile) {  // mirror tile: row q0 + i
-    const double v = T[j * kNdLd + i];
-    if (q0 + i < m && r0 + j < m && v != 0.0) M[(int64_t)(q0 + i) * m + r0 + j] += v;
-  }
-}
-
 // Panel [k0, k0 + nb) of a larger front: the pivot block swept in registers
 // (thread (w, lane) of the block's eight waves holds entries (w + 8 u, lane),
 // u < 8; the block stays symmetric, so its pivot column also gives the pivot
@@ -205,12 +185,22 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_panel(NdDev D, const int
   const int nb = min(kNdPanel, nfs - k0);
   const double *M = D.F + D.off[F];
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+  // the first panel adds the children's updates to the entries it reads (the
+  // first update launch adds them to the rest of the front)
+  const ChildRef ch[2] = {child_ref(D, F, 0), child_ref(D, F, 1)};
+  const bool ext = k0 == 0 && (ch[0].f >= 0 || ch[1].f >= 0);
+  const int64_t dofo = D.dofoff[F];
   constexpr int U = kNdPanel / kNdSweepWaves;
   double q[U];
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int a = w + kNdSweepWaves * u;
-    q[u] = (a < nb && lane < nb) ? M[(int64_t)(k0 + a) * m + k0 + lane] : 0.0;
+    double v = 0.0;
+    if (a < nb && lane < nb) {
+      v = M[(int64_t)(k0 + a) * m + k0 + lane];
+      if (ext) v += children_sum(D, ch, dofo, k0 + a, k0 + lane);
+    }
+    q[u] = v;
   }
   for (int k = 0; k < nb; ++k) {
     double *ck = colk + (k & 1) * kNdPanel;
@@ -247,7 +237,11 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_panel(NdDev D, const int
     }
   const int nr = min(kNdChunk, m - r0);
   for (int i = w; i < nr; i += kNdSweepWaves) {
-    const double v = lane < nb ? M[(int64_t)(r0 + i) * m + k0 + lane] : 0.0;
+    double v = 0.0;
+    if (lane < nb) {
+      v = M[(int64_t)(r0 + i) * m + k0 + lane];
+      if (ext) v += children_sum(D, ch, dofo, r0 + i, k0 + lane);
+    }
     Sr[i * kNdLd + lane] = v;
     if (lane < nb) S1[(int64_t)(r0 + i) * kNdPanel + lane] = v;
   }
@@ -287,8 +281,12 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_update(NdDev D, const int32_t
   double *St = Wt + kNdPanel * kNdLd;      // St[p * kNdLd + j]: S1 of the tile's columns, transposed
   const int F = tiles[3 * blockIdx.x], r0 = tiles[3 * blockIdx.x + 1], q0 = tiles[3 * blockIdx.x + 2];
   const int m = D.m[F], nfs = D.nfs[F];
-  if (k0 >= nfs) return;
-  const int nb = min(kNdPanel, nfs - k0);
+  if (k0 > 0 && k0 >= nfs) return;
+  const int nb = max(0, min(kNdPanel, nfs - k0));  // 0: a front with no own unknown, only extended
+  const ChildRef ch[2] = {child_ref(D, F, 0), child_ref(D, F, 1)};
+  const bool ext = k0 == 0 && (ch[0].f >= 0 || ch[1].f >= 0);
+  if (nb == 0 && !ext) return;
+  const int64_t dofo = D.dofoff[F];
   const double *Sc = D.S + D.soff[F];
   const double *S1 = Sc + kNdPanel * kNdPanel, *W = S1 + (int64_t)m * kNdPanel;
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
@@ -326,7 +324,7 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_update(NdDev D, const int32_t
       double &x = M[(int64_t)row * m + cl];
       double nv;
       if (!iP && !jP)
-        nv = x - acc[r][c];
+        nv = (ext ? x + children_sum(D, ch, dofo, row, cl) : x) - acc[r][c];
       else if (!iP)
         nv = W[(int64_t)row * kNdPanel + (cl - k0)];
       else if (!jP)
@@ -497,8 +495,8 @@ void launch_nd_factor(const NdHost &H, const NdDev &D, const DLevel<double> &L, 
     }
     const int ntile = H.tptr[h + 1] - H.tptr[h], nch = H.cptr[h + 1] - H.cptr[h];
     const int32_t *tiles = D.tiles + 3 * (int64_t)H.tptr[h], *chunks = D.chunks + 2 * (int64_t)H.cptr[h];
-    hipLaunchKernelGGL(k_nd_extend, dim3(ntile), dim3(kNdThreads), 0, s, D, tiles);
-    for (int k0 = 0; k0 < H.hmaxnfs[h]; k0 += kNdPanel) {
+    // (the first panel's two launches also add the children's updates)
+    for (int k0 = 0; k0 < std::max(H.hmaxnfs[h], 1); k0 += kNdPanel) {
       hipLaunchKernelGGL(k_nd_panel, dim3(nch), dim3(kNdSweepThreads), lds_p, s, D, chunks, k0, err);
       hipLaunchKernelGGL(k_nd_update, dim3(ntile), dim3(kNdThreads), lds_u, s, D, tiles, k0);
     }
