@@ -131,10 +131,14 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_small(NdDev D, const int
   }
   for (int k = 0; k < nfs; ++k) {
     double *ck = colk[k & 1];
-    if (lane == (k & (kWave - 1))) {  // these lanes hold column k
-      const bool hi = k >= kWave;
+    if (lane == (k & (kWave - 1))) {  // these lanes hold column k (k is the same in every thread)
+      if (k >= kWave) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) ck[w + kNdSweepWaves * u] = hi ? q[u][1] : q[u][0];
+        for (int u = 0; u < 16; ++u) ck[w + kNdSweepWaves * u] = q[u][1];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) ck[w + kNdSweepWaves * u] = q[u][0];
+      }
     }
     __syncthreads();
     const double piv = ck[k];
@@ -144,15 +148,30 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_small(NdDev D, const int
     double ca[16];
 #pragma unroll
     for (int u = 0; u < 16; ++u) ca[u] = ck[w + kNdSweepWaves * u];
-    const bool isk0 = lane == k, isk1 = lane + kWave == k;
-    const double rv0 = isk0 ? -inv : rb0, rv1 = isk1 ? -inv : rb1;
+    // every entry as if off the pivot row and column, then the pivot column (one
+    // lane of each wave) and the pivot row (one wave) overwritten
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {  // branch-free: row k, column k, the rest
-      const bool rowk_here = w + kNdSweepWaves * u == k;
-      const double r0v = isk0 ? ca[u] * inv : q[u][0] - ca[u] * rb0;
-      q[u][0] = rowk_here ? rv0 : r0v;
-      const double r1v = isk1 ? ca[u] * inv : q[u][1] - ca[u] * rb1;
-      q[u][1] = rowk_here ? rv1 : r1v;
+    for (int u = 0; u < 16; ++u) {
+      q[u][0] -= ca[u] * rb0;
+      q[u][1] -= ca[u] * rb1;
+    }
+    if (lane == (k & (kWave - 1))) {
+      if (k >= kWave) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) q[u][1] = ca[u] * inv;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) q[u][0] = ca[u] * inv;
+      }
+    }
+    if (w == (k & (kNdSweepWaves - 1))) {
+      const int ks = k / kNdSweepWaves;
+      const double rv0 = lane == k ? -inv : rb0, rv1 = lane + kWave == k ? -inv : rb1;
+#pragma unroll
+      for (int u = 0; u < 16; ++u) {
+        q[u][0] = u == ks ? rv0 : q[u][0];
+        q[u][1] = u == ks ? rv1 : q[u][1];
+      }
     }
   }
 #pragma unroll
@@ -216,12 +235,19 @@ __global__ void __launch_bounds__(kNdSweepThreads) k_nd_panel(NdDev D, const int
     double ca[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) ca[u] = ck[w + kNdSweepWaves * u];  // all reads in flight at once
-    const bool colk_lane = lane == k;
-    const double rowk_val = colk_lane ? -inv : rb;
+    // every entry as if off the pivot row and column, then the pivot column (one
+    // lane of each wave) and the pivot row (one wave) overwritten
 #pragma unroll
-    for (int u = 0; u < U; ++u) {  // branch-free: row k, column k, the rest
-      const double rest = colk_lane ? ca[u] * inv : q[u] - ca[u] * rb;
-      q[u] = (w + kNdSweepWaves * u == k) ? rowk_val : rest;
+    for (int u = 0; u < U; ++u) q[u] -= ca[u] * rb;
+    if (lane == k) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u] = ca[u] * inv;
+    }
+    if (w == (k & (kNdSweepWaves - 1))) {
+      const int ks = k / kNdSweepWaves;
+      const double rv = lane == k ? -inv : rb;
+#pragma unroll
+      for (int u = 0; u < U; ++u) q[u] = u == ks ? rv : q[u];
     }
   }
   // q = -M_PP^{-1}
