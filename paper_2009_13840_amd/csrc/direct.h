@@ -30,7 +30,8 @@ constexpr int kNdLeafCells = 8;   // cells of a leaf of the dissection
 constexpr int kNdSmall = 128;     // fronts of at most this many unknowns are eliminated in LDS
 constexpr int kNdPanel = 64;      // pivots per panel of a larger front
 constexpr int kNdTile = 64;       // rows and columns of a tile of a larger front
-constexpr int kNdChunk = 64;      // rows of a front per block of the panel and solve kernels
+constexpr int kNdChunk = 64;      // rows of a front per block of the panel kernel
+constexpr int kNdSolveRows = 32;  // rows of a front per block of the solve kernels (two waves of 16)
 
 struct NdHost {
   int nfront = 0, nheight = 0;
@@ -43,7 +44,8 @@ struct NdHost {
   std::vector<int64_t> src, dst;             // operator entry (bsr | cpl | spp concatenated) -> front entry
   std::vector<int32_t> hfront, hptr;         // fronts by height
   std::vector<int32_t> tiles, tptr;          // (front, row, col) tiles (col <= row) of each larger height
-  std::vector<int32_t> chunks, cptr;         // (front, first row) chunks of every height
+  std::vector<int32_t> chunks, cptr;         // (front, first row) chunks of kNdChunk rows, every height
+  std::vector<int32_t> schunks, scptr;       // the same with kNdSolveRows rows (solve kernels)
   std::vector<uint8_t> big;                  // [nheight] height eliminated by panels
   std::vector<int32_t> hmaxnfs, hmaxm;       // [nheight]
   int64_t total = 0, vtotal = 0, stotal = 0; // doubles of the fronts, solve vectors, panel scratch

@@ -17,7 +17,7 @@ struct NdDev {
   const int64_t *off = nullptr, *voff = nullptr, *dofoff = nullptr, *soff = nullptr;
   const int32_t *dof = nullptr, *cmap = nullptr;
   const int64_t *src = nullptr, *dst = nullptr;
-  const int32_t *hfront = nullptr, *tiles = nullptr, *chunks = nullptr;
+  const int32_t *hfront = nullptr, *tiles = nullptr, *chunks = nullptr, *schunks = nullptr;
   double *F = nullptr;  // fronts, m*m each, row-major
   double *V = nullptr;  // solve vectors, m each
   double *S = nullptr;  // panel scratch of the height being eliminated

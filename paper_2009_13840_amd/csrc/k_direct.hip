@@ -31,6 +31,7 @@ namespace {
 constexpr int kNdThreads = 256;
 constexpr int kNdWaves = kNdThreads / kWave;
 constexpr int kNdSweepThreads = 512;  // the sweeping kernels: eight waves
+constexpr int kNdSolveThreads = kNdSolveRows / 16 * kWave;  // the solve kernels: 16 rows per wave
 constexpr int kNdSweepWaves = kNdSweepThreads / kWave;
 constexpr int kNdLd = kNdPanel + 1;  // padded row length of LDS tiles (no bank conflicts on transposed writes)
 
@@ -370,11 +371,11 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_update(NdDev D, const int32_t
   }
 }
 
-// Forward elimination over one height, one block per chunk of a front's rows:
+// Forward elimination over one height, one block per kNdSolveRows rows of a front:
 // v = the front's own unknowns of b (minus coef times the null vector) plus what
 // its children passed up; the first chunk keeps v1 = v[0, nfs) for the backward
 // pass and every chunk writes u = v2 - (F21 F11^{-1}) v1 for its update rows.
-__global__ void __launch_bounds__(kNdThreads) k_nd_fwd(NdDev D, const int32_t *chunks, const double *b,
+__global__ void __launch_bounds__(kNdSolveThreads) k_nd_fwd(NdDev D, const int32_t *chunks, const double *b,
                                                         int64_t nface, int t, const double *zmean,
                                                         const double *coef) {
   extern __shared__ double v[];
@@ -383,7 +384,7 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_fwd(NdDev D, const int32_t *c
   const int64_t dofo = D.dofoff[F];
   const ChildRef c0 = child_ref(D, F, 0), c1 = child_ref(D, F, 1);
   const double cf = coef ? *coef : 0.0;
-  for (int a = threadIdx.x; a < m; a += kNdThreads) {
+  for (int a = threadIdx.x; a < m; a += kNdSolveThreads) {
     double x = 0;
     if (a < nfs) {
       const int64_t g = D.dof[dofo + a];
@@ -403,7 +404,7 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_fwd(NdDev D, const int32_t *c
   __syncthreads();
   double *Vf = D.V + D.voff[F];
   if (r0 == 0)
-    for (int a = threadIdx.x; a < nfs; a += kNdThreads) Vf[a] = v[a];
+    for (int a = threadIdx.x; a < nfs; a += kNdSolveThreads) Vf[a] = v[a];
   // each wave takes 16 of the chunk's rows at once (16 loads in flight per lane)
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lo = max(r0 + 16 * w, nfs), hi = min(r0 + 16 * w + 16, m);
@@ -430,14 +431,14 @@ __global__ void __launch_bounds__(kNdThreads) k_nd_fwd(NdDev D, const int32_t *c
 
 // Backward substitution over one height (root first): x1 = -[front row] . [v1; x2]
 // for the chunk's rows among the front's own unknowns.
-__global__ void __launch_bounds__(kNdThreads) k_nd_bwd(NdDev D, const int32_t *chunks, double *x) {
+__global__ void __launch_bounds__(kNdSolveThreads) k_nd_bwd(NdDev D, const int32_t *chunks, double *x) {
   extern __shared__ double y[];
   const int F = chunks[2 * blockIdx.x], r0 = chunks[2 * blockIdx.x + 1];
   const int m = D.m[F], nfs = D.nfs[F];
   if (r0 >= nfs) return;
   const int64_t dofo = D.dofoff[F];
   const double *Vf = D.V + D.voff[F];
-  for (int a = threadIdx.x; a < m; a += kNdThreads) y[a] = a < nfs ? Vf[a] : x[D.dof[dofo + a]];
+  for (int a = threadIdx.x; a < m; a += kNdSolveThreads) y[a] = a < nfs ? Vf[a] : x[D.dof[dofo + a]];
   __syncthreads();
   const int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
   const int lo = r0 + 16 * w, hi = min(r0 + 16 * w + 16, nfs);
@@ -538,20 +539,21 @@ void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int 
   const bool pin = H.pinned >= 0;
   if (pin) hipLaunchKernelGGL(k_nd_proj_in, dim3(1), dim3(1024), 0, s, nc, nface, t, zmean, zz, b, D.coef);
   for (int h = 0; h < H.nheight; ++h) {
-    const int nch = H.cptr[h + 1] - H.cptr[h];
+    const int nch = H.scptr[h + 1] - H.scptr[h];
     if (nch == 0) continue;
     const size_t lds = (size_t)H.hmaxm[h] * sizeof(double);
-    const int32_t *ch = D.chunks + 2 * (int64_t)H.cptr[h];
+    const int32_t *ch = D.schunks + 2 * (int64_t)H.scptr[h];
     const double *cf = pin ? (const double *)D.coef : nullptr;
     HHO_PROBED(probe, HHO_PROBE_DIRECT_FWD, h, s,
-               HHO_LAUNCH(k_nd_fwd, dim3(nch), dim3(kNdThreads), lds, s, D, ch, b, nface, t, zmean, cf));
+               HHO_LAUNCH(k_nd_fwd, dim3(nch), dim3(kNdSolveThreads), lds, s, D, ch, b, nface, t, zmean, cf));
   }
   for (int h = H.nheight - 1; h >= 0; --h) {
-    const int nch = H.cptr[h + 1] - H.cptr[h];
+    const int nch = H.scptr[h + 1] - H.scptr[h];
     if (nch == 0) continue;
     const size_t lds = (size_t)H.hmaxm[h] * sizeof(double);
-    const int32_t *ch = D.chunks + 2 * (int64_t)H.cptr[h];
-    HHO_PROBED(probe, HHO_PROBE_DIRECT_BWD, h, s, HHO_LAUNCH(k_nd_bwd, dim3(nch), dim3(kNdThreads), lds, s, D, ch, x));
+    const int32_t *ch = D.schunks + 2 * (int64_t)H.scptr[h];
+    HHO_PROBED(probe, HHO_PROBE_DIRECT_BWD, h, s,
+               HHO_LAUNCH(k_nd_bwd, dim3(nch), dim3(kNdSolveThreads), lds, s, D, ch, x));
   }
   if (pin) hipLaunchKernelGGL(k_nd_proj_out, dim3(1), dim3(1024), 0, s, nc, nface, t, zmean, zz, H.pinned, x);
 }

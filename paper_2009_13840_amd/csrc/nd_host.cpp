@@ -340,6 +340,7 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
   H->soff.assign(nn, 0);
   H->tptr.assign(H->nheight + 1, 0);
   H->cptr.assign(H->nheight + 1, 0);
+  H->scptr.assign(H->nheight + 1, 0);
   for (int h = 0; h < H->nheight; ++h) {
     int64_t scratch = 0;
     for (int32_t x = H->hptr[h]; x < H->hptr[h + 1]; ++x) {
@@ -355,6 +356,10 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
         H->chunks.push_back(i);
         H->chunks.push_back(r);
       }
+      for (int r = 0; r < m; r += kNdSolveRows) {
+        H->schunks.push_back(i);
+        H->schunks.push_back(r);
+      }
       if (H->big[h]) {
         H->soff[i] = scratch;
         scratch += (int64_t)kNdPanel * kNdPanel + 2 * (int64_t)m * kNdPanel;
@@ -369,6 +374,7 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
     H->stotal = std::max(H->stotal, scratch);
     H->tptr[h + 1] = (int32_t)(H->tiles.size() / 3);
     H->cptr[h + 1] = (int32_t)(H->chunks.size() / 2);
+    H->scptr[h + 1] = (int32_t)(H->schunks.size() / 2);
   }
 }
 

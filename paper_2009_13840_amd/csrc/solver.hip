@@ -461,6 +461,7 @@ static void plan(hho_problem *P, Arena &A) {
     D.hfront = A.take<int32_t>(H.hfront.size());
     D.tiles = A.take<int32_t>(H.tiles.size());
     D.chunks = A.take<int32_t>(H.chunks.size());
+    D.schunks = A.take<int32_t>(H.schunks.size());
     D.F = A.take<double>(H.total);
     D.V = A.take<double>(H.vtotal);
     D.S = A.take<double>(H.stotal);
@@ -956,6 +957,7 @@ static void device_upload(hho_problem *P) {
     h2d((void *)D.hfront, H.hfront.data(), H.hfront.size() * 4);
     if (!H.tiles.empty()) h2d((void *)D.tiles, H.tiles.data(), H.tiles.size() * 4);
     h2d((void *)D.chunks, H.chunks.data(), H.chunks.size() * 4);
+    h2d((void *)D.schunks, H.schunks.data(), H.schunks.size() * 4);
     P->nd_zz = 0;
     for (double z : P->zmean) P->nd_zz += z * z;
   }
