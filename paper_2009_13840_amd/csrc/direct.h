@@ -11,7 +11,8 @@
 // left at the root is the constant-pressure null space, which is pinned to zero
 // (the solution is then made orthogonal to that null vector, which gives the
 // bordered system's solution) or, when the operator is nonsingular, eliminated
-// last.  Within a front the faces come first, then the pressures placed there.
+// last; a batch of disjoint problems leaves one per member, each member's null
+// space.  Within a front the faces come first, then the pressures placed there.
 //
 // The numeric phase (k_direct.hip) eliminates each front's own unknowns with the
 // sweep operator, so that the stored front holds -F11^{-1}, F11^{-1} F12,
@@ -49,7 +50,9 @@ struct NdHost {
   std::vector<uint8_t> big;                  // [nheight] height eliminated by panels
   std::vector<int32_t> hmaxnfs, hmaxm;       // [nheight]
   int64_t total = 0, vtotal = 0, stotal = 0; // doubles of the fronts, solve vectors, panel scratch
-  int64_t pinned = -1;                       // unknown fixed to zero, or -1
+  std::vector<int64_t> pins;                 // per member: the unknown fixed to zero, or -1
+  std::vector<int64_t> segp;                 // [members+1] cell ranges of the members (one member: all cells)
+  std::vector<int32_t> cseg;                 // [cells] member of every cell
   int maxm = 0;
   int64_t factor_entries = 0;                // stored entries used by the solves (sum of m^2 - up^2)
 };
@@ -58,8 +61,9 @@ struct NdHost {
 // (face-major), t per cell after the faces; bsr blocks of size bs (v-cond: p, the
 // block acting on every component; v&p-cond: d*p), cpl per (cell-face entry,
 // face unknown, cell unknown), spp per cell (v-cond only).  pin: the operator has
-// the constant-pressure null space (pure Dirichlet).
+// the constant-pressure null space (pure Dirichlet), one per member of a batch.
+// seg_cell_ptr: the members' cell ranges of a batch (empty: one problem).
 void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, const std::vector<int32_t> &rowptr,
-                 const std::vector<int32_t> &col, NdHost *H);
+                 const std::vector<int32_t> &col, const std::vector<int64_t> &seg_cell_ptr, NdHost *H);
 
 }  // namespace hho

@@ -21,7 +21,9 @@ struct NdDev {
   double *F = nullptr;  // fronts, m*m each, row-major
   double *V = nullptr;  // solve vectors, m each
   double *S = nullptr;  // panel scratch of the height being eliminated
-  double *coef = nullptr;  // projection coefficient of the right-hand side on the null vector
+  double *coef = nullptr;  // per member: projection coefficient of the right-hand side on its null vector
+  const int64_t *pins = nullptr, *segp = nullptr;  // per member: pinned unknown; cell ranges
+  const int32_t *cseg = nullptr;                   // member of every cell
   int64_t npair = 0;
 };
 
@@ -30,11 +32,11 @@ struct NdDev {
 // non-finite pivot, plus one.
 void launch_nd_factor(const NdHost &H, const NdDev &D, const DLevel<double> &L, int64_t nb, int64_t ncpl,
                       int *err, hipStream_t s);
-// x = S^{-1} b on the coarsest level; with a pinned unknown (constant-pressure
-// null space, zmean the null vector's cell coefficients, zz its squared norm)
-// b is first made orthogonal to the null vector and so is x afterwards.
+// x = S^{-1} b on the coarsest level; with pinned unknowns (each member's
+// constant-pressure null space, zmean the null vectors' cell coefficients) b is
+// first made orthogonal to every member's null vector and so is x afterwards.
 // probe: live timing of the passes (classes HHO_PROBE_DIRECT_FWD / _BWD, level = tree height), or null.
-void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int nc, const double *zmean, double zz,
-                     const double *b, double *x, hipStream_t s, KernelProbe *probe);
+void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, const double *zmean, const double *b,
+                     double *x, hipStream_t s, KernelProbe *probe);
 
 }  // namespace hho

@@ -383,13 +383,15 @@ __global__ void __launch_bounds__(kNdSolveThreads) k_nd_fwd(NdDev D, const int32
   const int m = D.m[F], nfs = D.nfs[F];
   const int64_t dofo = D.dofoff[F];
   const ChildRef c0 = child_ref(D, F, 0), c1 = child_ref(D, F, 1);
-  const double cf = coef ? *coef : 0.0;
   for (int a = threadIdx.x; a < m; a += kNdSolveThreads) {
     double x = 0;
     if (a < nfs) {
       const int64_t g = D.dof[dofo + a];
       x = b[g];
-      if (coef && g >= nface && (g - nface) % t == 0) x -= cf * zmean[(g - nface) / t];
+      if (coef && g >= nface && (g - nface) % t == 0) {
+        const int64_t T = (g - nface) / t;
+        x -= coef[D.cseg[T]] * zmean[T];
+      }
     }
     if (c0.f >= 0) {
       const int ca = D.cmap[2 * (dofo + a)];
@@ -463,32 +465,44 @@ __global__ void __launch_bounds__(kNdSolveThreads) k_nd_bwd(NdDev D, const int32
   if ((lane & 3) == 0 && r < nrw) x[D.dof[dofo + lo + r]] = -acc[0];
 }
 
-// coef = (z . b) / (z . z), z the constant-pressure null vector (cell mean modes)
-__global__ void __launch_bounds__(1024) k_nd_proj_in(int nc, int64_t nface, int t, const double *zmean, double zz,
+// per member (one block each): coef = (z . b) / (z . z), z the member's
+// constant-pressure null vector (its cells' mean modes)
+__global__ void __launch_bounds__(1024) k_nd_proj_in(const int64_t *segp, int64_t nface, int t, const double *zmean,
                                                       const double *b, double *coef) {
   __shared__ double red[16];
-  double s = 0;
-  for (int T = threadIdx.x; T < nc; T += blockDim.x) s += zmean[T] * b[nface + (int64_t)T * t];
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) *coef = s / zz;
+  const int64_t c0 = segp[blockIdx.x], c1 = segp[blockIdx.x + 1];
+  double zb = 0, zz = 0;
+  for (int64_t T = c0 + threadIdx.x; T < c1; T += blockDim.x) {
+    zb += zmean[T] * b[nface + T * t];
+    zz += zmean[T] * zmean[T];
+  }
+  zb = block_sum(zb, red);
+  __syncthreads();
+  zz = block_sum(zz, red);
+  if (threadIdx.x == 0) coef[blockIdx.x] = zb / zz;
 }
 
-// pinned unknown set to zero, then x <- x - ((z . x) / (z . z)) z
-__global__ void __launch_bounds__(1024) k_nd_proj_out(int nc, int64_t nface, int t, const double *zmean, double zz,
-                                                       int64_t pinned, double *x) {
+// per member (one block each): its pinned unknown set to zero, then
+// x <- x - ((z . x) / (z . z)) z on its cells
+__global__ void __launch_bounds__(1024) k_nd_proj_out(const int64_t *segp, const int64_t *pins, int64_t nface, int t,
+                                                       const double *zmean, double *x) {
   __shared__ double red[16];
   __shared__ double c;
-  double s = 0;
-  for (int T = threadIdx.x; T < nc; T += blockDim.x) {
-    const int64_t i = nface + (int64_t)T * t;
-    s += zmean[T] * (i == pinned ? 0.0 : x[i]);
+  const int64_t c0 = segp[blockIdx.x], c1 = segp[blockIdx.x + 1], pin = pins[blockIdx.x];
+  double zx = 0, zz = 0;
+  for (int64_t T = c0 + threadIdx.x; T < c1; T += blockDim.x) {
+    const int64_t i = nface + T * t;
+    zx += zmean[T] * (i == pin ? 0.0 : x[i]);
+    zz += zmean[T] * zmean[T];
   }
-  s = block_sum(s, red);
-  if (threadIdx.x == 0) c = s / zz;
+  zx = block_sum(zx, red);
   __syncthreads();
-  for (int T = threadIdx.x; T < nc; T += blockDim.x) {
-    const int64_t i = nface + (int64_t)T * t;
-    x[i] = (i == pinned ? 0.0 : x[i]) - c * zmean[T];
+  zz = block_sum(zz, red);
+  if (threadIdx.x == 0) c = zx / zz;
+  __syncthreads();
+  for (int64_t T = c0 + threadIdx.x; T < c1; T += blockDim.x) {
+    const int64_t i = nface + T * t;
+    x[i] = (i == pin ? 0.0 : x[i]) - c * zmean[T];
   }
 }
 
@@ -530,14 +544,15 @@ void launch_nd_factor(const NdHost &H, const NdDev &D, const DLevel<double> &L, 
   }
 }
 
-void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int nc, const double *zmean, double zz,
-                     const double *b, double *x, hipStream_t s, KernelProbe *probe) {
+void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, const double *zmean, const double *b,
+                     double *x, hipStream_t s, KernelProbe *probe) {
   static std::once_flag once_f, once_b;
   static hipError_t attr_f = hipSuccess, attr_b = hipSuccess;
   reserve_lds((const void *)k_nd_fwd, once_f, attr_f);
   reserve_lds((const void *)k_nd_bwd, once_b, attr_b);
-  const bool pin = H.pinned >= 0;
-  if (pin) hipLaunchKernelGGL(k_nd_proj_in, dim3(1), dim3(1024), 0, s, nc, nface, t, zmean, zz, b, D.coef);
+  const bool pin = !H.pins.empty() && H.pins[0] >= 0;  // every member has its null space, or none
+  const int nsegp = (int)H.pins.size();
+  if (pin) hipLaunchKernelGGL(k_nd_proj_in, dim3(nsegp), dim3(1024), 0, s, D.segp, nface, t, zmean, b, D.coef);
   for (int h = 0; h < H.nheight; ++h) {
     const int nch = H.scptr[h + 1] - H.scptr[h];
     if (nch == 0) continue;
@@ -555,7 +570,7 @@ void launch_nd_solve(const NdHost &H, const NdDev &D, int64_t nface, int t, int 
     HHO_PROBED(probe, HHO_PROBE_DIRECT_BWD, h, s,
                HHO_LAUNCH(k_nd_bwd, dim3(nch), dim3(kNdSolveThreads), lds, s, D, ch, x));
   }
-  if (pin) hipLaunchKernelGGL(k_nd_proj_out, dim3(1), dim3(1024), 0, s, nc, nface, t, zmean, zz, H.pinned, x);
+  if (pin) hipLaunchKernelGGL(k_nd_proj_out, dim3(nsegp), dim3(1024), 0, s, D.segp, D.pins, nface, t, zmean, x);
 }
 
 }  // namespace hho

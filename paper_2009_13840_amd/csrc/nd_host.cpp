@@ -36,13 +36,23 @@ struct Sets {  // disjoint sets of cells with path halving
 }  // namespace
 
 void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, const std::vector<int32_t> &rowptr,
-                 const std::vector<int32_t> &col, NdHost *H) {
+                 const std::vector<int32_t> &col, const std::vector<int64_t> &seg_cell_ptr, NdHost *H) {
   const int nc = (int)mesh->nc, nf = (int)mesh->nf;
   const int dp = d * p;
   const int64_t nface = (int64_t)nf * dp;
   const int bs = cond == HHO_COND_V ? p : dp;
   if (pin && t != 1) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: a pressure null space needs t = 1");
   *H = NdHost{};
+  // members (a batch's disjoint problems; one problem: all cells)
+  if (seg_cell_ptr.empty())
+    H->segp = {0, (int64_t)nc};
+  else
+    H->segp = seg_cell_ptr;
+  const int nsegp = (int)H->segp.size() - 1;
+  H->cseg.assign(nc, 0);
+  for (int s = 0; s < nsegp; ++s)
+    for (int64_t c = H->segp[s]; c < H->segp[s + 1]; ++c) H->cseg[c] = s;
+  H->pins.assign(nsegp, -1);
 
   // ---- nested dissection of the cells: recursive coordinate bisection at the
   // median of the cell centres along the longest side of their bounding box
@@ -123,7 +133,7 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
   // all but one are eliminated at the node; the last is passed up
   Sets sets(nc);
   std::vector<int32_t> last_of(nc, -1);
-  int32_t pinned_cell = -1;
+  std::vector<int32_t> pinned_cells;
   for (int i = 0; i < nn; ++i) {
     const int32_t k = post[i];
     for (int32_t f : fs_faces[k]) {
@@ -141,19 +151,24 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
     for (int32_t c : cand) last_of[sets.find(c)] = c;
     for (int32_t c : cand) (last_of[sets.find(c)] == c ? delayed[k] : placed[k]).push_back(c);
     for (int32_t c : cand) last_of[sets.find(c)] = -1;
-    if (k == 0) {  // root
-      if (pin) {
-        if (delayed[0].size() != 1)
-          fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: the mesh of a problem with a pressure null space "
-                                  "must be connected");
-        pinned_cell = delayed[0][0];
+    if (k == 0) {  // root: one pressure left per connected set of cells
+      if (pin) {  // each must be one member's null space
+        for (int32_t c : delayed[0]) {
+          int64_t &slot = H->pins[H->cseg[c]];
+          if (slot >= 0)
+            fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: the mesh of a problem with a pressure null space "
+                                    "must be connected");
+          slot = nface + (int64_t)c * t;
+        }
+        for (int64_t v : H->pins)
+          if (v < 0) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: a member without its null space");
+        pinned_cells = delayed[0];
       } else {
         placed[0].insert(placed[0].end(), delayed[0].begin(), delayed[0].end());
       }
       delayed[0].clear();
     }
   }
-  if (pinned_cell >= 0) H->pinned = nface + (int64_t)pinned_cell * t;
 
   // ---- unknown groups (face f: f; cell T: nf + T), their front and elimination key
   const int ng = nf + nc;
@@ -173,7 +188,7 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
       key += gsize(g);
     }
   }
-  if (pinned_cell >= 0) gfront[nf + pinned_cell] = -1;
+  for (int32_t c : pinned_cells) gfront[nf + c] = -1;
 
   // ---- update sets (groups adjacent to the subtree, eliminated above it), by front rank
   std::vector<std::vector<int32_t>> upg(nn);

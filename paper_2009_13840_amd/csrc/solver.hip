@@ -145,7 +145,6 @@ struct hho_problem {
   bool coarse_direct = false;
   NdHost nd;
   NdDev ndd;
-  double nd_zz = 0;  // squared norm of the constant-pressure null vector
   std::vector<double> zhost;
   size_t lds_condense = 0, lds_patch = 0;
   // batched problems (disjoint union): per-segment FGMRES state
@@ -441,7 +440,7 @@ static void plan(hho_problem *P, Arena &A) {
   } else if (P->coarse_direct) {
     NdHost &H = P->nd;
     if (H.m.empty())
-      nd_symbolic(P->mesh, d, LC.p, LC.t, P->cond, P->border != 0, P->rowptr, P->col, &H);
+      nd_symbolic(P->mesh, d, LC.p, LC.t, P->cond, P->border != 0, P->rowptr, P->col, P->seg_cell_ptr, &H);
     if ((int64_t)H.maxm * (int64_t)sizeof(double) > (int64_t)kMaxLdsBytes - 1024)
       fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: a front exceeds the LDS of one compute unit");
     NdDev &D = P->ndd;
@@ -465,7 +464,10 @@ static void plan(hho_problem *P, Arena &A) {
     D.F = A.take<double>(H.total);
     D.V = A.take<double>(H.vtotal);
     D.S = A.take<double>(H.stotal);
-    D.coef = A.take<double>(1);
+    D.coef = A.take<double>(H.pins.size());
+    D.pins = A.take<int64_t>(H.pins.size());
+    D.segp = A.take<int64_t>(H.segp.size());
+    D.cseg = A.take<int32_t>(H.cseg.size());
   } else {
     const int R = P->opt.coarse_restart;
     P->cV = A.take<double>((int64_t)(R + 1) * LC.N);
@@ -815,10 +817,8 @@ static void init_levels(hho_problem *P) {
   if (P->coarse_dense && nd > 8192) fail(HHO_E_INVALID_ARG, "dense coarse solver limited to 8192 unknowns");
   P->dense_n = nd;
   P->coarse_direct = !P->coarse_dense && (P->opt.coarse_mode == HHO_COARSE_DIRECT ||
-                                          (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0 && P->nseg == 0));
+                                          (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
   if (P->coarse_direct && LC.k != 0) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver needs a coarsest degree of 0");
-  if (P->coarse_direct && P->nseg > 1 && P->border)
-    fail(HHO_E_INVALID_ARG, "a batch of problems with pure Dirichlet boundaries needs an iterative coarse solver");
   P->nd = NdHost{};  // built when the workspace is planned
   P->coarse_amg = !P->coarse_dense && !P->coarse_direct &&
                   (P->opt.coarse_mode == HHO_COARSE_AMG || (P->opt.coarse_mode == HHO_COARSE_AUTO && LC.k == 0));
@@ -833,7 +833,7 @@ constexpr int64_t kNdAutoBytes = int64_t(32) << 30;
 static void settle_auto_coarse(hho_problem *P) {
   if (P->opt.coarse_mode != HHO_COARSE_AUTO || !P->coarse_direct || !P->nd.m.empty()) return;
   const LevelInfo &LC = P->lev[P->nlev - 1];
-  nd_symbolic(P->mesh, P->d, LC.p, LC.t, P->cond, P->border != 0, P->rowptr, P->col, &P->nd);
+  nd_symbolic(P->mesh, P->d, LC.p, LC.t, P->cond, P->border != 0, P->rowptr, P->col, P->seg_cell_ptr, &P->nd);
   const NdHost &H = P->nd;
   if (H.total * (int64_t)sizeof(double) <= kNdAutoBytes &&
       (int64_t)H.maxm * (int64_t)sizeof(double) <= (int64_t)kMaxLdsBytes - 1024)
@@ -958,8 +958,9 @@ static void device_upload(hho_problem *P) {
     if (!H.tiles.empty()) h2d((void *)D.tiles, H.tiles.data(), H.tiles.size() * 4);
     h2d((void *)D.chunks, H.chunks.data(), H.chunks.size() * 4);
     h2d((void *)D.schunks, H.schunks.data(), H.schunks.size() * 4);
-    P->nd_zz = 0;
-    for (double z : P->zmean) P->nd_zz += z * z;
+    h2d((void *)D.pins, H.pins.data(), H.pins.size() * 8);
+    h2d((void *)D.segp, H.segp.data(), H.segp.size() * 8);
+    h2d((void *)D.cseg, H.cseg.data(), H.cseg.size() * 4);
   }
   if (P->coarse_amg) {
     h2d(P->d_fdiag, P->fdiag.data(), P->fdiag.size() * 4);
@@ -1438,7 +1439,7 @@ static void coarse_solve(hho_problem *P) {
     return;
   }
   if (P->coarse_direct) {
-    launch_nd_solve(P->nd, P->ndd, L.nface, L.t, (int)P->mesh->nc, P->tp.zmean, P->nd_zz, V.b, V.w, s, &P->probe);
+    launch_nd_solve(P->nd, P->ndd, L.nface, L.t, P->tp.zmean, V.b, V.w, s, &P->probe);
     return;
   }
   if (P->in_capture) {
@@ -2397,7 +2398,7 @@ int hho_direct_info(const hho_problem *p, const char *name, int64_t *out, int64_
   else if (n == "cmap") put(H.cmap);
   else if (n == "hptr") put(H.hptr);
   else if (n == "hfront") put(H.hfront);
-  else if (n == "pinned") v = {H.pinned};
+  else if (n == "pinned") put(H.pins);
   else if (n == "sizes") v = {H.nfront, H.nheight, H.total, H.factor_entries, H.maxm};
   else if (n == "hfwd" || n == "hbwd") {
     for (int h = 0; h < H.nheight; ++h) {
@@ -3128,6 +3129,7 @@ int hho_batch_create(hho_problem *const *ps, int n, hho_batch **out) {
   }
   P->opt.eta = p0->opt.eta;
   P->cell_eta.clear();
+  hho::settle_auto_coarse(P);
   hho::amg_levels(P);
   P->have_data = true;
   P->setup_done = false;

@@ -18,7 +18,7 @@ from synth.fields import problem_data
 NAMES = ["m", "nfs", "child", "dofoff", "dof", "cmap", "hptr", "hfront", "pinned", "sizes"]
 
 
-def _eliminate(S, z, I, b):
+def _eliminate(S, z, I, b, allow_missing=()):
     m, nfs, child, dofoff, dof, cmap = (I[n] for n in NAMES[:6])
     nn, N = len(m), S.shape[0]
     pinned = int(I["pinned"][0])
@@ -31,8 +31,9 @@ def _eliminate(S, z, I, b):
         ekey[own] = np.arange(key, key + nfs[f])
         front_of[own] = f
         key += nfs[f]
-    assert key == N - (pinned >= 0)
+    assert key == N - (pinned >= 0) - len(allow_missing)
     assert (front_of >= 0).sum() == key and (pinned < 0 or front_of[pinned] < 0)
+    assert all(front_of[i] < 0 for i in allow_missing)
     fronts = []
     for f in range(nn):
         d = dof[dofoff[f]:dofoff[f + 1]]
@@ -84,6 +85,26 @@ def _eliminate(S, z, I, b):
     return x
 
 
+def _eliminate_batch(S, zs, I, b):
+    """The same for a batch: zs are the members' null vectors, one pinned
+    unknown per member; b is made orthogonal to each, and so is x."""
+    pins = [int(v) for v in I["pinned"]]
+    assert len(pins) == len(zs) and all(v >= 0 for v in pins)
+    bp = b.copy()
+    for z in zs:
+        bp -= (z @ bp) / (z @ z) * z
+    I1 = dict(I)
+    I1["pinned"] = np.array([-1])
+    keep = np.ones(S.shape[0], bool)
+    keep[pins] = False
+    # eliminate with the pinned unknowns' rows and columns removed (they are in no front)
+    x = _eliminate(np.where(np.outer(keep, keep), S, 0.0) + np.diag(~keep * 1.0), None, I1, bp, allow_missing=pins)
+    x[pins] = 0.0
+    for z in zs:
+        x -= (z @ x) / (z @ z) * z
+    return x
+
+
 @pytest.mark.parametrize("name,mk,k,cond", [
     ("vor60_k2_v", lambda: voronoi_lloyd(60, 2), 2, "v"),
     ("vor60_k2_vp", lambda: voronoi_lloyd(60, 2), 2, "vp"),
@@ -121,3 +142,46 @@ def test_direct_mode_rejects_what_it_cannot_solve():
     import paper_2009_13840_amd as H
     with pytest.raises(H.HHOError):
         H.Problem(H.Mesh(cartesian_quads(2)), 1, "v", coarse_mode="direct", degrees=[1])  # coarsest degree 1
+
+
+def test_batch_fronts_pin_one_pressure_per_member():
+    """A batch of pure-Dirichlet members (disjoint union): the symbolic phase
+    leaves one pressure per member at the root and pins it; the elimination with
+    per-member projections reproduces each member's bordered direct solution."""
+    import scipy.sparse as sp
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    from synth.batch import shifted, region_fields
+    members = [voronoi_lloyd(40, 3), cartesian_quads(5), voronoi_lloyd(25, 6)]
+    k, cond, width = 2, "v", 2.0
+    fields = [problem_data(polynomial_stokes(2, k + 1, 50 + i), None, 2) for i in range(len(members))]
+    U, fo, co = H.Mesh.union([shifted(m, width * i) for i, m in enumerate(members)])
+    P = H.Problem(U, k, cond, coarse_mode="direct")
+    P.set_segments(fo, co)
+    P.set_data(*region_fields(fields, 2, width))
+    I = {n: P.direct_info(n) for n in NAMES}
+    assert len(I["pinned"]) == len(members)
+    # the union's coarsest operator from the members' own (block diagonal, union layout)
+    Os = [OS.build(m, k, cond, f, eta=None) for m, f in zip(members, fields)]
+    dp = Os[0].lays[-1].off // members[0].n_faces     # face unknowns per face on the coarsest level
+    nface = int(fo[-1]) * dp
+    N = nface + int(co[-1])
+    S = np.zeros((N, N))
+    zs = []
+    for i, O in enumerate(Os):
+        Si, nf_i = O.S[-1].toarray(), O.lays[-1].off
+        idx = np.concatenate([np.arange(fo[i] * dp, fo[i] * dp + nf_i), nface + np.arange(co[i], co[i + 1])])
+        S[np.ix_(idx, idx)] = Si
+        z = np.zeros(N)
+        z[idx] = O.z[-1]
+        zs.append(z)
+    b = np.random.default_rng(2).standard_normal(N)
+    x = _eliminate_batch(S, zs, I, b)
+    for i, O in enumerate(Os):
+        Si, z, nf_i = O.S[-1].toarray(), O.z[-1], O.lays[-1].off
+        idx = np.concatenate([np.arange(fo[i] * dp, fo[i] * dp + nf_i), nface + np.arange(co[i], co[i + 1])])
+        n = len(idx)
+        xd = np.linalg.solve(np.block([[Si, z[:, None]], [z[None, :], np.zeros((1, 1))]]), np.append(b[idx], 0.0))[:n]
+        err = np.abs(x[idx] - xd).max() / np.abs(xd).max()
+        print(f"[direct symbolic batch] member {i}: err {err:.1e}")
+        assert err <= 1e-11

@@ -13,7 +13,9 @@ the paper's 2D coarse solver is a direct factorisation, Section 5.2).
   solution x satisfies S x = b to 1e-10 relative, and x is orthogonal to the
   constant-pressure null vector.
 * The whole solver with the direct coarse solve, in a batch of problems with a
-  Neumann boundary (no null space), reaches every member's direct solution."""
+  Neumann boundary (no null space) or of pure-Dirichlet problems (a pinned
+  pressure and a projection per member), reaches every member's direct
+  solution."""
 import numpy as np
 import pytest
 
@@ -104,13 +106,18 @@ def test_direct_coarse_solve_at_full_size():
     assert ok and relf <= 1e-8
 
 
-def test_direct_coarse_solve_in_a_batch():
+@pytest.mark.parametrize("boundary", ["neumann", "dirichlet"])
+def test_direct_coarse_solve_in_a_batch(boundary):
+    """Members with a Neumann boundary (no null space) or pure Dirichlet ones
+    (one pinned pressure and one projection per member)."""
     import paper_2009_13840_amd as H
     import oracle.solve as OS
-    meshes = [_neumann(cartesian_quads(6)), _neumann(voronoi_lloyd(50, 3))]
+    meshes = [cartesian_quads(6), voronoi_lloyd(50, 3), voronoi_lloyd(30, 8)]
+    if boundary == "neumann":
+        meshes = [_neumann(m) for m in meshes]
     k = 2
-    fields = [problem_data(polynomial_stokes(2, k + 1, 70 + i), None, 2) for i in range(2)]
-    print("[case] direct coarse solve in a batch", flush=True)
+    fields = [problem_data(polynomial_stokes(2, k + 1, 70 + i), None, 2) for i in range(len(meshes))]
+    print(f"[case] direct coarse solve in a batch ({boundary})", flush=True)
     probs = []
     for m, f in zip(meshes, fields):
         Q = H.Problem(H.Mesh(m), k, "v", coarse_mode="direct", rtol=1e-12)
@@ -123,7 +130,7 @@ def test_direct_coarse_solve_in_a_batch():
     for i, (m, f) in enumerate(zip(meshes, fields)):
         face, pres, its, hist, rel, status = out[i]
         O = OS.build(m, k, "v", f, eta=None)
-        xd = OS.solve_direct(O)
+        xd = OS.normalise_pressure(O, OS.solve_direct(O))
         nf = face.size
         ef = np.linalg.norm(face - xd[:nf]) / np.linalg.norm(xd[:nf])
         print(f"[direct batch] member {i}: its {its}, face error vs direct {ef:.1e}")
