@@ -307,8 +307,9 @@ def run_batch(args, record=False):
     """256 independent 2D Stokes problems (Cartesian meshes, side ~ U{16..96},
     k ~ U{1..4}, trig-series force with seed 4000+i, v-cond, homogeneous
     Dirichlet): members of equal degree form one disjoint-union problem with one
-    FGMRES process, one set of V-cycle coefficients and one coarse GMRES per
-    member; the four degree groups run concurrently, one host thread and one HIP
+    FGMRES process and one set of V-cycle coefficients per member, the coarsest
+    levels solved by the sparse direct solve (one pinned pressure and one
+    projection per member); the four degree groups run concurrently, one host thread and one HIP
     stream each.  A step = setup + solve of every group.  The V-cycle is FP32 and
     the outer solve FP64; launch shapes come from the library's autotuner
     (untimed).  The groups are timed with eager launches and with every V-cycle
@@ -741,8 +742,8 @@ def main():
     ap.add_argument("--coarse-rtol", type=float, default=0.0,
                     help="coarsest-level GMRES tolerance (0: the library's default, 1e-3 in 3D and 1e-2 in 2D)")
     ap.add_argument("--coarse", default="auto", choices=["auto", "direct", "amg", "gmres", "dense"],
-                    help="coarsest-level solver (auto: the sparse direct solve for a single 2D problem, "
-                         "AMG-preconditioned GMRES in 3D and for batches)")
+                    help="coarsest-level solver (auto: the sparse direct solve whenever its fronts fit, "
+                         "else AMG-preconditioned GMRES)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batch of 256 problems in the default run")
     ap.add_argument("--probe-stride", type=int, default=PROBE_STRIDE,
@@ -773,7 +774,7 @@ def main():
     if not args.no_cpu_baseline:
         try:
             spec0 = WORKLOADS[args.workload]
-            direct = args.coarse == "direct" or (args.coarse == "auto" and spec0["mesh"] != "hex")
+            direct = args.coarse in ("auto", "direct")
             cpu = cpu_baseline(spec0, args.cpu_sample_cells, coarse="direct" if direct else "amg")
         except Exception as e:  # pragma: no cover
             cpu = {"error": repr(e)}

@@ -79,9 +79,9 @@ extern "C" {
                                FP32 vectors and arithmetic */
 
 /* coarsest-level solver */
-#define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns; else, when k_L = 0, DIRECT for a
-                                 single problem whose fronts fit (32 GiB of fronts, the largest
-                                 within one compute unit's LDS) and AMG otherwise (batches);
+#define HHO_COARSE_AUTO   0   /* DENSE up to 1024 unknowns (single problems); else, when
+                                 k_L = 0, DIRECT when its fronts fit (32 GiB of fronts, the
+                                 largest within one compute unit's LDS) and AMG otherwise;
                                  else GMRES                                                   */
 #define HHO_COARSE_DENSE  1   /* bordered dense inverse (FP64)                                */
 #define HHO_COARSE_GMRES  2   /* GMRES to coarse_rtol, cell-patch Schwarz preconditioner      */
@@ -89,8 +89,8 @@ extern "C" {
                                  with a smoothed-aggregation velocity block (k_L = 0 only)     */
 #define HHO_COARSE_DIRECT 4   /* sparse direct solve (Section 5.2: the 2D coarse solver is a
                                  direct factorisation): multifrontal elimination in a nested
-                                 dissection order, factorised at setup (k_L = 0 only; single
-                                 problems, or batches without a pressure null space)          */
+                                 dissection order, factorised at setup (k_L = 0 only; in a
+                                 batch one pinned pressure per member with a null space)       */
 
 /* how the face blocks of the V-cycle's level-0 copy are formed (FP32/BF16 V-cycles) */
 #define HHO_COPY_CONVERT  0   /* the FP64 operator rounded to the copy's precision */
