@@ -2,6 +2,7 @@
 // dissection, fronts, index maps); see direct.h for the ordering and the
 // numeric scheme.  Depends on the mesh topology and the level's layout only.
 #include <algorithm>
+#include <cstdlib>
 #include <numeric>
 #include <string>
 
@@ -54,14 +55,34 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
     for (int64_t c = H->segp[s]; c < H->segp[s + 1]; ++c) H->cseg[c] = s;
   H->pins.assign(nsegp, -1);
 
-  // ---- nested dissection of the cells: recursive coordinate bisection at the
-  // median of the cell centres along the longest side of their bounding box
+  // ---- nested dissection of the cells: a node holding cells of several members
+  // (disjoint problems, cells numbered member by member) is split between
+  // members, near the middle, at no cost; within one member, recursive
+  // coordinate bisection at the median of the cell centres along the longest
+  // side of their bounding box
   std::vector<int32_t> perm(nc);
   std::iota(perm.begin(), perm.end(), 0);
   std::vector<Node> nodes;
   nodes.push_back(Node{0, nc});
   for (size_t k = 0; k < nodes.size(); ++k) {
     const int32_t lo = nodes[k].lo, hi = nodes[k].hi;
+    const int32_t s0 = H->cseg[perm[lo]], s1 = H->cseg[perm[hi - 1]];
+    if (s0 != s1) {  // perm is still the identity here: members are contiguous ranges
+      int32_t best = -1;
+      for (int32_t s = s0 + 1; s <= s1; ++s) {
+        const int32_t b = (int32_t)H->segp[s];
+        if (best < 0 || std::abs(2 * b - lo - hi) < std::abs(2 * best - lo - hi)) best = b;
+      }
+      const int32_t depth = nodes[k].depth + 1;
+      for (int c = 0; c < 2; ++c) {
+        Node ch{c == 0 ? lo : best, c == 0 ? best : hi};
+        ch.parent = (int32_t)k;
+        ch.depth = depth;
+        nodes[k].c[c] = (int32_t)nodes.size();
+        nodes.push_back(ch);
+      }
+      continue;
+    }
     if (hi - lo <= kNdLeafCells) continue;
     double bl[3] = {1e300, 1e300, 1e300}, bh[3] = {-1e300, -1e300, -1e300};
     for (int32_t i = lo; i < hi; ++i)
