@@ -14,8 +14,9 @@
 //   forward (leaves up):  u = v2 - (F21 F11^{-1}) v1, passed to the parent;
 //   backward (root down): x1 = F11^{-1} v1 - (F11^{-1} F12) x2, i.e. minus the
 //                         front's first nfs rows times [v1; x2].
-// Fronts of at most kNdSmall unknowns are swept in LDS by one block; larger ones
-// in panels of kNdPanel pivots: one launch inverts the panel's pivot block and
+// Fronts of at most kNdSmall unknowns are swept by one block each, the front in
+// its registers; larger ones in panels of kNdPanel pivots: one launch inverts
+// the panel's pivot block and
 // forms W = M_RP M_PP^{-1} by row chunks, the next updates the front's lower
 // triangle by 64 x 64 tiles and mirrors it (M_RR -= W M_PR, M_RP = W,
 // M_PR = W^T, M_PP = -M_PP^{-1}); the first panel's two launches also add the
