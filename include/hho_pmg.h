@@ -337,7 +337,8 @@ int hho_coarse_solve_apply(hho_problem *p, const double *b, double *x);
  * "dof" (the unknowns of each front: its own first, then its update part in
  * elimination order), "cmap" (2 per front position: position in child 0/1's
  * update part, -1 if absent), "hptr"/"hfront" (fronts by tree height), "pinned"
- * (the unknown fixed to zero, or -1), "sizes" (fronts, heights, front entries,
+ * (per member of a batch, one for a single problem: the unknown fixed to zero,
+ * or -1 when there is no pressure null space), "sizes" (fronts, heights, front entries,
  * factor entries used by the solves, largest front), "hfwd"/"hbwd" (per tree
  * height, two values: the front entries the forward / backward pass reads, and
  * the unknowns of its fronts).  cap: room in out;
