@@ -728,8 +728,9 @@ LocalLds local_lds(int d, int k, int max_faces, int max_nq, int max_nqf) {
   // Latency decides the speed (every phase is a chain of short LDS-bound loops):
   // a cell whose work arrays leave room for a second workgroup on the compute
   // unit runs with 512 threads, two or more cells per unit (measured on 2D
-  // k = 3 Voronoi cells: 6.1 ms against 6.7 ms with 256 threads and more with
-  // 1024); a cell that takes the unit alone gets 1024 threads (16 waves) to hide
+  // k = 3 Voronoi cells: 6.1 ms against 6.7 ms with 256 threads, 11.1 ms with
+  // 768 and more with 1024); a cell that takes the unit alone gets 1024 threads
+  // (16 waves) to hide
   // the latency itself.  Every rhs_u entry needs its own thread.
   L.threads = L.bytes > kMaxLdsBytes / 2 ? 1024 : 512;
   while (L.threads < d * nlocmax && L.threads < kLocalThreads) L.threads *= 2;
