@@ -142,6 +142,14 @@ def test_direct_mode_rejects_what_it_cannot_solve():
     import paper_2009_13840_amd as H
     with pytest.raises(H.HHOError):
         H.Problem(H.Mesh(cartesian_quads(2)), 1, "v", coarse_mode="direct", degrees=[1])  # coarsest degree 1
+    with pytest.raises(H.HHOError):
+        H.Problem(H.Mesh(cartesian_quads(2)), 1, "v", coarse_mode=5)                     # no such solver
+    P = H.Problem(H.Mesh(cartesian_quads(4)), 1, "v", coarse_mode="direct")
+    with pytest.raises(H.HHOError):
+        P.direct_info("m")                                                               # before set_data
+    P.set_data(*problem_data(polynomial_stokes(2, 2, 3), None, 2))
+    with pytest.raises(H.HHOError):
+        P.direct_info("no such array")
 
 
 def test_batch_fronts_pin_one_pressure_per_member():
