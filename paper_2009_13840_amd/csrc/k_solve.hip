@@ -232,13 +232,17 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T, Sto, StoP
   T *rpr = yp + t + 1;         // [t]
   T *ydot = rpr + t;           // [n]
   T *red = ydot + n;           // [64] partial sums
+  int *fl = (int *)(red + kWave);  // [2 n] face of each patch row, and its sides (2: first cell is Tc, 1: interior)
   const StoP *Si = L.sinv + tp.pairoff[Tc] * (int64_t)((L.cond == 1) ? p * p : dp * dp);  // packed lower triangle
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const int fi = i / dp, k = i % dp;
     const int f = tp.cface[eb + fi];
     const T val = sc * r[(int64_t)f * dp + k];
+    const int c0 = tp.fcell[2 * f], c1 = tp.fcell[2 * f + 1];  // read with r, kept for the write-back
     ru[i] = val;
-    if (v && tp.fcell[2 * f] == Tc) v[(int64_t)f * dp + k] = val;
+    fl[2 * i] = f;
+    fl[2 * i + 1] = (c0 == Tc ? 2 : 0) | (c1 >= 0 ? 1 : 0);
+    if (v && c0 == Tc) v[(int64_t)f * dp + k] = val;
   }
   for (int q = threadIdx.x; q < t; q += blockDim.x) {
     const T val = sc * r[L.nface + (int64_t)Tc * t + q];
@@ -306,10 +310,10 @@ __global__ void __launch_bounds__(kWave) k_precond(DTopo tp, DLevel<T, Sto, StoP
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int fi = i / dp, k = i % dp;
-    const int f = tp.cface[eb + fi];
-    const bool first = tp.fcell[2 * f] == Tc;
-    const bool interior = tp.fcell[2 * f + 1] >= 0;
+    const int k = i % dp;
+    const int f = fl[2 * i];
+    const bool first = fl[2 * i + 1] & 2;
+    const bool interior = fl[2 * i + 1] & 1;
     const T val = interior ? (T)0.5 * u1[i] : u1[i];
     if (first) {
       z[(int64_t)f * dp + k] = val;
@@ -521,7 +525,7 @@ void launch_residual(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *b,
 }
 size_t precond_lds_bytes(int d, int cond, int p, int t, int max_faces, size_t elem) {
   const int n = max_faces * d * p;
-  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2 + kWave) * elem;
+  return (size_t)(3 * n + std::max(n, t) + 2 * t + 2 + kWave) * elem + 2 * n * sizeof(int);
 }
 template <typename T, typename Sto, typename StoP>
 void launch_precond(const DTopo &tp, const DLevel<T, Sto, StoP> &L, const T *r, const double *scale, T *v, T *z, T *zs1,
