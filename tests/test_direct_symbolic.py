@@ -138,6 +138,39 @@ def test_fronts_reproduce_the_bordered_direct_solution(name, mk, k, cond):
     assert nheight >= 2 and err <= 1e-11
 
 
+@pytest.mark.parametrize("name,mk,k,cond", [
+    ("quad1_k1_v", lambda: cartesian_quads(1), 1, "v"),
+    ("quad1_k2_vp", lambda: cartesian_quads(1), 2, "vp"),
+    ("hex1_k1_v", lambda: cartesian_hexes(1), 1, "v"),
+    ("quad1_k1_v_neumann", lambda: cartesian_quads(1).with_bc(lambda x: 2 if x[0] > 1 - 1e-12 else 1), 1, "v"),
+])
+def test_one_cell_is_one_front(name, mk, k, cond):
+    """Degenerate input: a single cell is one leaf front that eliminates all it
+    holds: every unknown, except, with the constant-pressure null space, the
+    cell's one pressure, which is the pinned unknown (in no front); without it (a
+    Neumann side) nothing is pinned."""
+    import paper_2009_13840_amd as H
+    import oracle.solve as OS
+    mesh = mk()
+    data = problem_data(polynomial_stokes(mesh.dim, k + 1, 3), None, mesh.dim)
+    P = H.Problem(H.Mesh(mesh), k, cond, coarse_mode="direct")
+    P.set_data(*data)
+    I = {n: P.direct_info(n) for n in NAMES}
+    O = OS.build(mesh, k, cond, data, eta=None)
+    S, z = O.S[-1].toarray(), O.z[-1]
+    N = S.shape[0]
+    assert list(I["sizes"][:2]) == [1, 1]
+    assert I["m"][0] == I["nfs"][0] == N - (z is not None)
+    assert (I["pinned"][0] == N - 1) if z is not None else (I["pinned"][0] < 0)
+    b = np.random.default_rng(4).standard_normal(N)
+    x = _eliminate(S, z, I, b)
+    if z is not None:
+        xd = np.linalg.solve(np.block([[S, z[:, None]], [z[None, :], np.zeros((1, 1))]]), np.append(b, 0.0))[:N]
+    else:
+        xd = np.linalg.solve(S, b)
+    assert np.abs(x - xd).max() <= 1e-12 * np.abs(xd).max()
+
+
 def test_direct_mode_rejects_what_it_cannot_solve():
     import paper_2009_13840_amd as H
     with pytest.raises(H.HHOError):
