@@ -36,6 +36,9 @@ CASES = [
     ("hex6_k1_vp", lambda: cartesian_hexes(6), 1, "vp"),
     ("hex5_k1_v", lambda: cartesian_hexes(5), 1, "v"),
     ("quad3_k2_v", lambda: cartesian_quads(3), 2, "v"),      # one front, no panel
+    # one cell with a Neumann side: one front, nothing pinned (with an all-Dirichlet
+    # boundary the one cell's smoother patch is singular, rejected at setup)
+    ("quad1_k1_v_neumann", lambda: _neumann(cartesian_quads(1)), 1, "v"),
 ]
 
 
