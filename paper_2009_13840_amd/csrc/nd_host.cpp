@@ -43,6 +43,8 @@ void nd_symbolic(const hho_mesh *mesh, int d, int p, int t, int cond, bool pin, 
   const int64_t nface = (int64_t)nf * dp;
   const int bs = cond == HHO_COND_V ? p : dp;
   if (pin && t != 1) fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: a pressure null space needs t = 1");
+  if (nface + (int64_t)nc * t > INT32_MAX)  // unknowns are stored as 32-bit indices
+    fail(HHO_E_INVALID_ARG, "sparse direct coarse solver: more than 2^31 - 1 coarse unknowns");
   *H = NdHost{};
   // members (a batch's disjoint problems; one problem: all cells)
   if (seg_cell_ptr.empty())
