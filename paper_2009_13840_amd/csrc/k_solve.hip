@@ -184,27 +184,31 @@ __device__ void sym_packed_apply(const Sto *__restrict__ S, int m, int p, const 
   __syncthreads();
 }
 
-// The same product for patches of at most 64 rows: one thread per output entry
-// walks its whole row through the packed index (the triangle stays in the L1/L2
-// caches after its first touch), no cross-lane reduction.
+// The same product for patches of at most 64 rows: one thread per row i walks
+// its whole row through the packed index (the triangle stays in the L1/L2 caches
+// after its first touch) and forms that row's DC outputs, so that each entry of
+// the triangle is loaded by one lane; no cross-lane reduction.
 template <typename T, typename Sto, int DC>
 __device__ void sym_row_apply(const Sto *__restrict__ S, int m, int p, const T *x, T *y) {
-  const int n = m * DC;
-  for (int e = threadIdx.x; e < n; e += blockDim.x) {
-    const int fi = e / (DC * p), c = (e / p) % DC, rr = e % p;
-    const int i = fi * p + rr;
-    T acc = 0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    const int fi = i / p, rr = i % p;
+    T acc[DC];
+#pragma unroll
+    for (int c = 0; c < DC; ++c) acc[c] = 0;
     int jf = 0, jr = 0;
 #pragma unroll 8
     for (int j = 0; j < m; ++j) {
       const int lo = j < i ? j : i, hi = j < i ? i : j;
-      acc += (T)S[hi * (hi + 1) / 2 + lo] * x[(jf * DC + c) * p + jr];
+      const T sij = (T)S[hi * (hi + 1) / 2 + lo];
+#pragma unroll
+      for (int c = 0; c < DC; ++c) acc[c] += sij * x[(jf * DC + c) * p + jr];
       if (++jr == p) {
         jr = 0;
         ++jf;
       }
     }
-    y[e] = acc;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) y[(fi * DC + c) * p + rr] = acc[c];
   }
   __syncthreads();
 }
