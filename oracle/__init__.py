@@ -14,6 +14,8 @@ Modules, each written from the paper's definitions:
 * ``bases``      -- hierarchical L2-orthonormal bases on cells and faces (Sec. 4.2)
 * ``hho``        -- potential reconstruction, face residuals, HHO-dp local residuals
                     in matrix form (Sec. 2.2, 2.3.1, eq. def:HHOAB)
+* ``hho_hp``     -- the HHO-hp scheme (cell velocity of degree k+1, hybrid
+                    pressure; Sec. 2.3.2): local residuals, global system, v&p-cond
 * ``condense``   -- v-cond and v&p-cond Schur complements (eqs. ST.1, ST.2)
 * ``system``     -- global assembly, DOF/MNZ counts (Table tab:DOFsMNZsFormula),
                     level hierarchy by Galerkin projection (Sec. 3.1-3.2, 4.2)
