@@ -339,3 +339,64 @@ def face_pressure(P: HPProblem, x: np.ndarray, f: int):
     xf, wf = P.geo.face_q[f]
     psi = P.geo.face_basis[f].values(xf)
     return psi @ x[P.NU + f * nF:P.NU + (f + 1) * nF], xf, wf
+
+
+def skeletal_order(P: HPProblem) -> np.ndarray:
+    """perm[new] = old: the skeletal unknowns face by face, each face's d velocity
+    components and then its pressure (P^k(F) modes each), the layout of a level
+    with d + 1 components per face and no cell unknowns."""
+    d, nF, nf = P.mesh.dim, P.locs[0].nF, P.mesh.n_faces
+    perm = np.empty(P.nskel, dtype=np.int64)
+    for f in range(nf):
+        for cc in range(d + 1):
+            for j in range(nF):
+                old = f * d * nF + cc * nF + j if cc < d else P.NU + f * nF + j
+                perm[(f * (d + 1) + cc) * nF + j] = old
+    return perm
+
+
+def multilevel_problem(P: HPProblem, degrees=None):
+    """The v&p-cond skeletal system of Scheme 2 as a level hierarchy for the
+    p-multilevel solver of Section 3: level l holds every face's d velocity
+    components and its pressure in P^{k_l}(F); the prolongation injects the
+    leading modes of the hierarchical face bases (Section 3.1) and the coarse
+    operators are the Galerkin products, i.e. sub-blocks of the fine one.  The
+    cell-patch Schwarz smoother then patches the faces of each cell.  Returns an
+    ``oracle.solve.Problem`` (driven by ``oracle.solve.solve_fgmres`` and
+    ``oracle.solve.solve_direct``) and the permutation of ``skeletal_order``."""
+    from .solve import Problem
+    from .system import LevelLayout, coarse_indices
+    mesh, d, k = P.mesh, P.mesh.dim, P.k
+    degrees = list(range(k, -1, -1)) if degrees is None else list(degrees)
+    assert degrees[0] == k and all(a > b for a, b in zip(degrees, degrees[1:])) and degrees[-1] >= 0
+    Sg, g, _ = condense_vp(P)
+    perm = skeletal_order(P)
+    S0 = Sg[perm][:, perm].tocsr()
+    b = g[perm]
+    lays = [LevelLayout(kl, d + 1, dim_poly(d - 1, kl), 0, mesh.n_faces, mesh.n_cells) for kl in degrees]
+    S, idx = [S0], []
+    for l in range(len(degrees) - 1):
+        ii = coarse_indices(lays[l], lays[l + 1])
+        idx.append(ii)
+        S.append(S[-1][ii][:, ii].tocsr())
+    zs = []
+    for lay in lays:
+        if P.z is None:
+            zs.append(None)
+            continue
+        z = np.zeros(lay.N)
+        for f in range(mesh.n_faces):
+            z[(f * (d + 1) + d) * lay.nF] = np.sqrt(P.geo.faces[f].area)
+        zs.append(z)
+    return Problem(mesh, P.geo, k, "hp", degrees, P.eta, P.locs, None, lays, S, b, idx, zs), perm
+
+
+def recover_from_skeleton(P: HPProblem, xs_ordered: np.ndarray, perm: np.ndarray) -> np.ndarray:
+    """All unknowns (layout of ``HPProblem``) from a skeletal solution in the
+    order of ``skeletal_order``."""
+    _, _, keep = condense_vp(P)
+    x = np.zeros(P.N)
+    x[perm] = xs_ordered
+    for gi, nint, X in keep:
+        x[gi[:nint]] = X[:, -1] - X[:, :-1] @ x[gi[nint:]]
+    return x

@@ -170,3 +170,57 @@ def test_hp_viscous_form_from_its_definition_on_the_unit_square(k):
     for i, (f, Y, n, vF) in enumerate(sides):
         vl[L.N1 + i * L.nF:L.N1 + (i + 1) * L.nF] = np.einsum("q,qj,q->j", sw, geo.face_basis[f].values(Y), vF)
     assert abs(vl @ L.a @ vl - a_def) <= 1e-12 * a_def
+
+
+@pytest.mark.parametrize("mesh,k", [(voronoi_lloyd(20, 3), 2), (cartesian_hexes(2), 1),
+                                    (_neumann_right(cartesian_quads(3)), 2)])
+def test_hp_levels_are_galerkin_products_and_keep_the_kernel(mesh, k):
+    """Level l + 1 of the skeletal hierarchy is P^T S_l P with P injecting the
+    leading P^{k_{l+1}}(F) modes of every face's d velocity components and its
+    pressure (built here by explicit loops); with a pure Dirichlet boundary each
+    level's constant face pressure is in its kernel."""
+    import scipy.sparse as sp
+    P = HP.build_hp(mesh, k, problem_data(None, trig_series(mesh.dim, 3), mesh.dim))
+    Q, _ = HP.multilevel_problem(P)
+    d, nf = mesh.dim, mesh.n_faces
+    from math import comb
+    for l in range(len(Q.S) - 1):
+        nFf, nFc = comb(Q.degrees[l] + d - 1, d - 1), comb(Q.degrees[l + 1] + d - 1, d - 1)
+        r = [(f * (d + 1) + cc) * nFf + j for f in range(nf) for cc in range(d + 1) for j in range(nFc)]
+        c = [(f * (d + 1) + cc) * nFc + j for f in range(nf) for cc in range(d + 1) for j in range(nFc)]
+        Pm = sp.csr_matrix((np.ones(len(r)), (r, c)), shape=(nf * (d + 1) * nFf, nf * (d + 1) * nFc))
+        G = (Pm.T @ Q.S[l] @ Pm).toarray()
+        assert np.abs(G - Q.S[l + 1].toarray()).max() <= 1e-14 * np.abs(G).max()
+    for S, z in zip(Q.S, Q.z):
+        if P.z is None:
+            assert z is None
+        else:
+            assert np.abs(S @ z).max() <= 1e-11 * abs(S).max() * np.abs(z).max()
+
+
+@pytest.mark.parametrize("mesh,k", [(voronoi_lloyd(40, 3), 1), (voronoi_lloyd(30, 2), 2), (cartesian_hexes(3), 1),
+                                    (_neumann_right(voronoi_lloyd(40, 3)), 2)])
+def test_hp_fgmres_vcycle_reaches_the_direct_solution(mesh, k):
+    """The p-multilevel solver on the HHO-hp skeleton (levels k..0, cell-patch
+    Schwarz smoothing over the faces of each cell, exact coarsest solve): FGMRES
+    converges, and the cell unknowns recovered from its skeletal solution are the
+    uncondensed solution."""
+    import oracle.solve as OS
+    P = HP.build_hp(mesh, k, problem_data(None, trig_series(mesh.dim, 7), mesh.dim))
+    Q, perm = HP.multilevel_problem(P)
+    x, its, hist, conv = OS.solve_fgmres(Q, rtol=1e-11)
+    assert conv and its <= 60
+    full = HP.normalise_pressure(P, HP.recover_from_skeleton(P, x, perm))
+    xu = HP.normalise_pressure(P, HP.solve_uncondensed(P))
+    assert np.abs(full - xu).max() <= 1e-6 * np.abs(xu).max()
+
+
+def test_hp_one_level_vcycle_is_the_skeletal_direct_solve():
+    """With a single level the V-cycle is the bordered direct solve of the
+    skeleton: FGMRES converges in one iteration."""
+    import oracle.solve as OS
+    mesh = voronoi_lloyd(16, 9)
+    P = HP.build_hp(mesh, 1, problem_data(None, trig_series(2, 4), 2))
+    Q, perm = HP.multilevel_problem(P, degrees=[1])
+    x, its, hist, conv = OS.solve_fgmres(Q, rtol=1e-10)
+    assert conv and its == 1
