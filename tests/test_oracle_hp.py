@@ -224,3 +224,17 @@ def test_hp_one_level_vcycle_is_the_skeletal_direct_solve():
     Q, perm = HP.multilevel_problem(P, degrees=[1])
     x, its, hist, conv = OS.solve_fgmres(Q, rtol=1e-10)
     assert conv and its == 1
+
+
+@pytest.mark.parametrize("mesh,k", [(cartesian_quads(4), 1), (cartesian_quads(3), 2), (voronoi_lloyd(20, 3), 1)])
+def test_hp_skeleton_size_and_pattern_match_the_table_formulas(mesh, k):
+    """The v&p-cond skeleton of Scheme 2 has the DOF and MNZ counts of the
+    paper's tables for HHO-hp (Table tab:DOFsMNZsFormula; the formula is pinned
+    against the printed table values by the golden file of the DOF/MNZ test):
+    (d + 1) dim P^k(F) unknowns per face, one dense block per pair of faces of a
+    common cell."""
+    from oracle.system import counts
+    P = HP.build_hp(mesh, k, problem_data(None, trig_series(2, 1), 2))
+    Sg, _, _ = HP.condense_vp(P)
+    c = counts(mesh, k)
+    assert Sg.shape[0] == c["dof_hp"] and Sg.nnz == c["mnz_hp"]
