@@ -305,6 +305,25 @@ int hho_get_condensed_cell(hho_problem *p, int64_t cell, double *S, double *rhs,
 int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B, double *rhs_u,
                        double *rhs_p, int64_t cap, int64_t *nloc_out);
 
+/* The local operators of the HHO scheme with hybrid pressure (Section 2.3.2,
+ * Scheme 2), on the host, for one cell of a mesh: velocity with cell modes of
+ * degree k + 1 and face modes of degree k, pressure with cell and face modes of
+ * degree k (hierarchical orthonormal bases).  a [nloc x nloc] scalar viscous
+ * matrix (the N1 = dim P^{k+1}(T) cell modes first, then the faces in mesh
+ * order, dim P^k(F) each), B [d x npl x nloc] pressure-velocity coupling per
+ * velocity component (pressure rows: dim P^k(T) cell modes, then dim P^k(F) per
+ * face), rhs_u [d x nloc], rhs_p [npl]; nloc = N1 + card(F_T) dim P^k(F),
+ * npl = dim P^k(T) + card(F_T) dim P^k(F).  The coupling is used for both the
+ * momentum and the mass balance (a symmetric system; the mass datum is
+ * (g_D . n_TF, q_F)_F on Dirichlet faces).  eta: Nitsche penalty; qdeg:
+ * quadrature degree of the data integrals (>= 2k + 2).  Builds every cell of
+ * the mesh (host threads) and copies one; caller-owned host buffers, any of
+ * them may be NULL; HHO_E_CAPACITY if cap < max(nloc^2, d npl nloc), the sizes
+ * still written.  No device is used. */
+int hho_local_hp_cell(const hho_mesh *m, int k, double eta, int qdeg, int64_t cell, hho_field_fn f,
+                      hho_field_fn gD, hho_field_fn gN, void *ctx, double *a, double *B, double *rhs_u,
+                      double *rhs_p, int64_t cap, int64_t *nloc_out, int64_t *npl_out);
+
 /* y = S_l x on level l in FP64 (device vectors in the global layout). */
 int hho_level_apply(hho_problem *p, int level, const double *x_dev, double *y_dev);
 

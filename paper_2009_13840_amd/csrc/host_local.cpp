@@ -13,6 +13,7 @@
 //    (B v, q) = sum_c (v_T,c, d_c q)_T - sum_{F not Dirichlet} (v_F . n_TF, q)_F,
 //    which equals the three terms of eq. HHOdiscrCNT for exact quadrature.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -707,6 +708,336 @@ void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, i
         for (int cc = 0; cc < d; ++cc) {
           const double fv = Rd.w[q] * fval[(coff[c] + q) * d + cc];
           for (int j = 0; j < nT; ++j) ru[cc * nloc + j] += fv * phid[(size_t)q * N1 + j];
+        }
+    }
+  });
+}
+
+// Local operators of the HHO scheme with hybrid pressure (Section 2.3.2,
+// Scheme 2): cell velocity in P^{k+1}(T) (all N1 modes of the cell basis), face
+// velocity and face pressure in P^k(F), cell pressure in P^k(T).  The viscous
+// part is Scheme 1's with k' = k + 1, its face residual
+// pi_F^k(v_F - p v) - (v_T - p v)|_F (degree k + 1 on the face) integrated at
+// the face's quadrature points; the coupling is the hybrid one,
+//   (B v, q) = -(div v_T, q_T)_T + sum_F ((v_T - v_F) . n_TF, q_F)_F
+//              + sum_{F Dirichlet} (v_F . n_TF, q_F)_F,
+// used for the momentum and (transposed, with the datum (g_D . n_TF, q_F)_F on
+// Dirichlet faces) for the mass balance, so that the system is symmetric.
+// Record of a cell: a [nloc x nloc], B [d][npl][nloc], rhs_u [d][nloc],
+// rhs_p [npl], with nloc = N1 + card(F_T) nF and npl = nT + card(F_T) nF.
+void build_local_hp(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f_fn, hho_field_fn gD_fn,
+                    hho_field_fn gN_fn, void *ctx, LocalDataHP *out) {
+  const int d = m->dim;
+  const int N1 = dim_poly(d, k + 1), nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
+  out->k = k;
+  out->d = d;
+  out->N1 = N1;
+  out->nT = nT;
+  out->nF = nF;
+  const int64_t nc = m->nc, nf = m->nf;
+  const int odeg = std::min(qdeg, 2 * k + 2);  // every operator integrand has degree <= 2k + 2
+  std::vector<Rule> crule(nc), frule(nf), corule(nc), forule(nf);
+  parallel_for(nc, [&](int64_t c) {
+    cell_rule(m, c, qdeg, crule[c]);
+    cell_rule(m, c, odeg, corule[c]);
+  });
+  parallel_for(nf, [&](int64_t f) {
+    face_rule(m, f, qdeg, frule[f]);
+    face_rule(m, f, odeg, forule[f]);
+  });
+  std::vector<FaceBasis> fb(nf);
+  std::vector<std::vector<double>> fpsi(nf), fpsio(nf);
+  const std::vector<int> EF = exponents(d - 1, k);
+  parallel_for(nf, [&](int64_t f) {
+    FaceBasis &B = fb[f];
+    B.nvar = d - 1;
+    B.N = nF;
+    B.E = EF;
+    B.h = m->fdiam[f];
+    for (int q = 0; q < 3; ++q) {
+      B.x0[q] = m->fcen[3 * f + q];
+      B.t1[q] = m->ft1[3 * f + q];
+      B.t2[q] = m->ft2[3 * f + q];
+    }
+    const Rule &R = forule[f];
+    int nq = R.n();
+    std::vector<double> xi((size_t)nq * B.nvar), M((size_t)nq * nF);
+    for (int q = 0; q < nq; ++q) {
+      const double *x = &R.x[3 * q];
+      double r[3] = {x[0] - B.x0[0], x[1] - B.x0[1], x[2] - B.x0[2]};
+      xi[q * B.nvar] = (r[0] * B.t1[0] + r[1] * B.t1[1] + r[2] * B.t1[2]) / B.h;
+      if (B.nvar == 2) xi[q * B.nvar + 1] = (r[0] * B.t2[0] + r[1] * B.t2[1] + r[2] * B.t2[2]) / B.h;
+    }
+    eval_monomials(B.E, B.nvar, xi.data(), nq, M.data());
+    gram_schmidt(M.data(), R.w.data(), nq, nF, B.C);
+    fpsio[f].resize((size_t)nq * nF);
+    B.values(R.x.data(), nq, fpsio[f].data());
+    fpsi[f].resize((size_t)frule[f].n() * nF);
+    B.values(frule[f].x.data(), frule[f].n(), fpsi[f].data());
+  });
+  // data at the data points
+  std::vector<int64_t> coff(nc + 1, 0), dof_(nf + 1, 0), nof(nf + 1, 0);
+  for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + crule[c].n();
+  for (int64_t f = 0; f < nf; ++f) {
+    dof_[f + 1] = dof_[f] + (m->fbc[f] == HHO_FACE_DIRICHLET ? frule[f].n() : 0);
+    nof[f + 1] = nof[f] + (m->fbc[f] == HHO_FACE_NEUMANN ? frule[f].n() : 0);
+  }
+  std::vector<double> fx(coff[nc] * d), fval(coff[nc] * d, 0.0);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int q = 0; q < crule[c].n(); ++q)
+      for (int a = 0; a < d; ++a) fx[(coff[c] + q) * d + a] = crule[c].x[3 * q + a];
+  if (f_fn && coff[nc]) f_fn(fx.data(), coff[nc], nullptr, fval.data(), ctx);
+  std::vector<double> dx(dof_[nf] * d), dn(dof_[nf] * d), dval(dof_[nf] * d, 0.0);
+  std::vector<double> nx(nof[nf] * d), nn(nof[nf] * d), nval(nof[nf] * d, 0.0);
+  for (int64_t f = 0; f < nf; ++f) {
+    if (m->fbc[f] == HHO_FACE_INTERIOR) continue;
+    int64_t c = m->fcell[0][f];
+    double sg = m->csign[m->cptr[c] + m->flocal[0][f]];
+    bool isD = m->fbc[f] == HHO_FACE_DIRICHLET;
+    int64_t o = isD ? dof_[f] : nof[f];
+    for (int q = 0; q < frule[f].n(); ++q)
+      for (int a = 0; a < d; ++a) {
+        (isD ? dx : nx)[(o + q) * d + a] = frule[f].x[3 * q + a];
+        (isD ? dn : nn)[(o + q) * d + a] = sg * m->fnrm[3 * f + a];
+      }
+  }
+  if (gD_fn && dof_[nf]) gD_fn(dx.data(), dof_[nf], dn.data(), dval.data(), ctx);
+  if (nof[nf]) {
+    if (!gN_fn) fail(HHO_E_INVALID_ARG, "local_hp: the mesh has Neumann faces but gN is NULL");
+    gN_fn(nx.data(), nof[nf], nn.data(), nval.data(), ctx);
+  }
+  out->off.assign(nc + 1, 0);
+  out->nloc.assign(nc, 0);
+  out->npl.assign(nc, 0);
+  for (int64_t c = 0; c < nc; ++c) {
+    const int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
+    const int nloc = N1 + nfc * nF, npl = nT + nfc * nF;
+    out->nloc[c] = nloc;
+    out->npl[c] = npl;
+    out->off[c + 1] = out->off[c] + (int64_t)nloc * nloc + (int64_t)d * npl * nloc + (int64_t)d * nloc + npl;
+  }
+  out->rec.assign(out->off[nc], 0.0);
+  const std::vector<int> EC = exponents(d, k + 1);
+
+  parallel_for(nc, [&](int64_t c) {
+    const Rule &R = corule[c];
+    const int nq = R.n();
+    const int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
+    const int nloc = N1 + nfc * nF, npl = nT + nfc * nF;
+    CellBasis cb;
+    cb.d = d;
+    cb.N = N1;
+    cb.E = EC;
+    cb.h = m->cdiam[c];
+    for (int q = 0; q < 3; ++q) cb.x0[q] = m->ccen[3 * c + q];
+    {
+      std::vector<double> xi((size_t)nq * d), M((size_t)nq * N1);
+      for (int q = 0; q < nq; ++q)
+        for (int a = 0; a < d; ++a) xi[q * d + a] = (R.x[3 * q + a] - cb.x0[a]) / cb.h;
+      eval_monomials(cb.E, d, xi.data(), nq, M.data());
+      gram_schmidt(M.data(), R.w.data(), nq, N1, cb.C);
+    }
+    std::vector<double> phi((size_t)nq * N1), gphi((size_t)nq * N1 * d);
+    cb.values(R.x.data(), nq, phi.data());
+    cb.grads(R.x.data(), nq, gphi.data());
+    std::vector<double> K((size_t)N1 * N1, 0.0);
+    for (int q = 0; q < nq; ++q)
+      for (int i = 0; i < N1; ++i)
+        for (int j = 0; j <= i; ++j) {
+          double s = 0;
+          for (int a = 0; a < d; ++a) s += gphi[((size_t)q * N1 + i) * d + a] * gphi[((size_t)q * N1 + j) * d + a];
+          K[(size_t)i * N1 + j] += R.w[q] * s;
+        }
+    for (int i = 0; i < N1; ++i)
+      for (int j = 0; j < i; ++j) K[(size_t)j * N1 + i] = K[(size_t)i * N1 + j];
+    // reconstruction right-hand side: (grad v_T, grad w)_T + sum_F (v_F - v_T, grad w . n)_F
+    std::vector<double> G((size_t)N1 * nloc, 0.0);
+    for (int i = 0; i < N1; ++i)
+      for (int j = 0; j < N1; ++j) G[(size_t)i * nloc + j] = K[(size_t)i * N1 + j];
+    std::vector<std::vector<double>> phif(nfc), gnf(nfc);
+    std::vector<std::array<double, 3>> nrm(nfc);
+    for (int i = 0; i < nfc; ++i) {
+      const int64_t e = m->cptr[c] + i, f = m->cface[e];
+      for (int q = 0; q < 3; ++q) nrm[i][q] = m->csign[e] * m->fnrm[3 * f + q];
+      const Rule &Rf = forule[f];
+      const int nqf = Rf.n();
+      phif[i].resize((size_t)nqf * N1);
+      gnf[i].resize((size_t)nqf * N1);
+      cb.values(Rf.x.data(), nqf, phif[i].data());
+      std::vector<double> g((size_t)nqf * N1 * d);
+      cb.grads(Rf.x.data(), nqf, g.data());
+      for (int q = 0; q < nqf; ++q)
+        for (int t = 0; t < N1; ++t) {
+          double s = 0;
+          for (int a = 0; a < d; ++a) s += g[((size_t)q * N1 + t) * d + a] * nrm[i][a];
+          gnf[i][(size_t)q * N1 + t] = s;
+        }
+      const double *psi = fpsio[f].data();
+      for (int q = 0; q < nqf; ++q)
+        for (int t = 1; t < N1; ++t) {
+          const double gw = Rf.w[q] * gnf[i][(size_t)q * N1 + t];
+          for (int j = 0; j < N1; ++j) G[(size_t)t * nloc + j] -= gw * phif[i][(size_t)q * N1 + j];
+          for (int j = 0; j < nF; ++j) G[(size_t)t * nloc + N1 + i * nF + j] += gw * psi[(size_t)q * nF + j];
+        }
+    }
+    std::vector<double> Rm((size_t)N1 * nloc, 0.0);
+    Rm[0] = 1.0;  // same mean as v_T
+    {
+      const int n1 = N1 - 1;
+      std::vector<double> L((size_t)n1 * n1);
+      for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < n1; ++j) L[(size_t)i * n1 + j] = K[(size_t)(i + 1) * N1 + (j + 1)];
+      if (!cholesky(L.data(), n1, n1))
+        fail(HHO_E_LOCAL_SINGULAR, "reconstruction stiffness not SPD in cell " + std::to_string(c));
+      for (int i = 0; i < n1; ++i)
+        for (int j = 0; j < nloc; ++j) Rm[(size_t)(i + 1) * nloc + j] = G[(size_t)(i + 1) * nloc + j];
+      chol_solve(L.data(), n1, n1, &Rm[nloc], nloc, nloc);
+    }
+    double *A = &out->rec[out->off[c]];
+    double *Bm = A + (size_t)nloc * nloc;
+    double *ru = Bm + (size_t)d * npl * nloc;
+    double *rp = ru + (size_t)d * nloc;
+    // consistency (grad p u, grad p v)_T = R1^T G1, symmetrised
+    for (int a = 0; a < nloc; ++a)
+      for (int b = 0; b < nloc; ++b) {
+        double s = 0;
+        for (int t = 1; t < N1; ++t) s += Rm[(size_t)t * nloc + a] * G[(size_t)t * nloc + b];
+        A[(size_t)a * nloc + b] = s;
+      }
+    for (int a = 0; a < nloc; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double s = 0.5 * (A[(size_t)a * nloc + b] + A[(size_t)b * nloc + a]);
+        A[(size_t)a * nloc + b] = A[(size_t)b * nloc + a] = s;
+      }
+    std::vector<double> Pi((size_t)nF * N1), Nn((size_t)nF * N1), PR((size_t)nF * nloc);
+    for (int i = 0; i < nfc; ++i) {
+      const int64_t f = m->cface[m->cptr[c] + i];
+      const Rule &Rf = forule[f];
+      const int nqf = Rf.n();
+      const double *psi = fpsio[f].data();
+      const double hF = m->fdiam[f];
+      const int bc = m->fbc[f];
+      const int fc0 = N1 + i * nF, pc0 = nT + i * nF;  // this face's velocity column / pressure row
+      std::fill(Pi.begin(), Pi.end(), 0.0);
+      std::fill(Nn.begin(), Nn.end(), 0.0);
+      for (int q = 0; q < nqf; ++q)
+        for (int j = 0; j < nF; ++j) {
+          const double wp = Rf.w[q] * psi[(size_t)q * nF + j];
+          for (int t = 0; t < N1; ++t) {
+            Pi[(size_t)j * N1 + t] += wp * phif[i][(size_t)q * N1 + t];
+            Nn[(size_t)j * N1 + t] += wp * gnf[i][(size_t)q * N1 + t];
+          }
+        }
+      // coefficients of pi_F(v_F - p v): PR = E_F - Pi R
+      for (int j = 0; j < nF; ++j)
+        for (int b = 0; b < nloc; ++b) {
+          double s = (b == fc0 + j) ? 1.0 : 0.0;
+          for (int t = 0; t < N1; ++t) s -= Pi[(size_t)j * N1 + t] * Rm[(size_t)t * nloc + b];
+          PR[(size_t)j * nloc + b] = s;
+        }
+      // face residual at each quadrature point, its square integrated / h_F
+      std::vector<double> rq(nloc);
+      for (int q = 0; q < nqf; ++q) {
+        for (int b = 0; b < nloc; ++b) {
+          double s = 0;
+          for (int j = 0; j < nF; ++j) s += psi[(size_t)q * nF + j] * PR[(size_t)j * nloc + b];
+          for (int t = 0; t < N1; ++t)
+            s -= phif[i][(size_t)q * N1 + t] * (((b == t) ? 1.0 : 0.0) - Rm[(size_t)t * nloc + b]);
+          rq[b] = s;
+        }
+        const double wq = Rf.w[q] / hF;
+        for (int a = 0; a < nloc; ++a) {
+          const double ra = wq * rq[a];
+          if (ra == 0.0) continue;
+          for (int b = 0; b < nloc; ++b) A[(size_t)a * nloc + b] += ra * rq[b];
+        }
+      }
+      if (bc == HHO_FACE_DIRICHLET) {
+        std::vector<double> NR((size_t)nF * nloc, 0.0);
+        for (int j = 0; j < nF; ++j)
+          for (int b = 0; b < nloc; ++b) {
+            double s = 0;
+            for (int t = 0; t < N1; ++t) s += Nn[(size_t)j * N1 + t] * Rm[(size_t)t * nloc + b];
+            NR[(size_t)j * nloc + b] = s;
+          }
+        for (int j = 0; j < nF; ++j) {
+          const int r = fc0 + j;
+          for (int b = 0; b < nloc; ++b) {
+            A[(size_t)r * nloc + b] -= NR[(size_t)j * nloc + b];
+            A[(size_t)b * nloc + r] -= NR[(size_t)j * nloc + b];
+          }
+          A[(size_t)r * nloc + r] += eta / hF;
+        }
+        const double *g = &dval[dof_[f] * d];
+        const Rule &Rd = frule[f];
+        const int nqd = Rd.n();
+        const double *psid = fpsi[f].data();
+        std::vector<double> gd((size_t)nqd * N1 * d), gnd((size_t)nqd * N1);
+        cb.grads(Rd.x.data(), nqd, gd.data());
+        for (int q = 0; q < nqd; ++q)
+          for (int t = 0; t < N1; ++t) {
+            double s = 0;
+            for (int a = 0; a < d; ++a) s += gd[((size_t)q * N1 + t) * d + a] * nrm[i][a];
+            gnd[(size_t)q * N1 + t] = s;
+          }
+        for (int cc = 0; cc < d; ++cc) {
+          std::vector<double> gt(N1, 0.0), gp(nF, 0.0);
+          for (int q = 0; q < nqd; ++q) {
+            const double wg = Rd.w[q] * g[q * d + cc];
+            for (int t = 0; t < N1; ++t) gt[t] += wg * gnd[(size_t)q * N1 + t];
+            for (int j = 0; j < nF; ++j) gp[j] += wg * psid[(size_t)q * nF + j];
+          }
+          for (int b = 0; b < nloc; ++b) {
+            double s = 0;
+            for (int t = 0; t < N1; ++t) s += Rm[(size_t)t * nloc + b] * gt[t];
+            ru[cc * nloc + b] -= s;
+          }
+          for (int j = 0; j < nF; ++j) ru[cc * nloc + fc0 + j] += eta / hF * gp[j];
+        }
+        for (int q = 0; q < nqd; ++q) {  // mass datum (g_D . n, q_F)_F
+          double gn = 0;
+          for (int a = 0; a < d; ++a) gn += g[q * d + a] * nrm[i][a];
+          for (int j = 0; j < nF; ++j) rp[pc0 + j] += Rd.w[q] * gn * psid[(size_t)q * nF + j];
+        }
+      } else if (bc == HHO_FACE_NEUMANN) {
+        const double *g = &nval[nof[f] * d];
+        const Rule &Rd = frule[f];
+        const double *psid = fpsi[f].data();
+        for (int cc = 0; cc < d; ++cc)
+          for (int q = 0; q < Rd.n(); ++q)
+            for (int j = 0; j < nF; ++j) ru[cc * nloc + fc0 + j] += Rd.w[q] * g[q * d + cc] * psid[(size_t)q * nF + j];
+      }
+      // hybrid coupling: (q_F, v_T . n)_F, and -(q_F, v_F . n)_F off Dirichlet faces
+      for (int cc = 0; cc < d; ++cc)
+        for (int j = 0; j < nF; ++j) {
+          double *row = Bm + ((size_t)cc * npl + pc0 + j) * nloc;
+          for (int t = 0; t < N1; ++t) row[t] += nrm[i][cc] * Pi[(size_t)j * N1 + t];
+          if (bc != HHO_FACE_DIRICHLET)
+            for (int l = 0; l < nF; ++l) {
+              double s = 0;
+              for (int q = 0; q < nqf; ++q) s += Rf.w[q] * psi[(size_t)q * nF + j] * psi[(size_t)q * nF + l];
+              row[fc0 + l] -= nrm[i][cc] * s;
+            }
+        }
+    }
+    // -(q_T, div v_T)_T
+    for (int q = 0; q < nq; ++q)
+      for (int cc = 0; cc < d; ++cc)
+        for (int t = 0; t < nT; ++t) {
+          const double pt = R.w[q] * phi[(size_t)q * N1 + t];
+          double *row = Bm + ((size_t)cc * npl + t) * nloc;
+          for (int j = 0; j < N1; ++j) row[j] -= pt * gphi[((size_t)q * N1 + j) * d + cc];
+        }
+    // body force (f_c, v_T) on all N1 cell modes
+    {
+      const Rule &Rd = crule[c];
+      const int nqd = Rd.n();
+      std::vector<double> phid((size_t)nqd * N1);
+      cb.values(Rd.x.data(), nqd, phid.data());
+      for (int q = 0; q < nqd; ++q)
+        for (int cc = 0; cc < d; ++cc) {
+          const double fv = Rd.w[q] * fval[(coff[c] + q) * d + cc];
+          for (int j = 0; j < N1; ++j) ru[cc * nloc + j] += fv * phid[(size_t)q * N1 + j];
         }
     }
   });

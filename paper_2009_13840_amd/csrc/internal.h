@@ -67,6 +67,17 @@ struct LocalData {
 void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, int qdeg, hho_field_fn f,
                  hho_field_fn gD, hho_field_fn gN, void *ctx, LocalData *out);
 
+// The HHO-hp scheme's local operators (Section 2.3.2), host only; per cell the
+// record a [nloc^2], B [d][npl][nloc], rhs_u [d][nloc], rhs_p [npl].
+struct LocalDataHP {
+  int k = 0, d = 0, nT = 0, nF = 0, N1 = 0;
+  std::vector<int64_t> off;                // [nc+1] record offsets (doubles)
+  std::vector<int32_t> nloc, npl;          // [nc]
+  std::vector<double> rec;
+};
+void build_local_hp(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f, hho_field_fn gD,
+                    hho_field_fn gN, void *ctx, LocalDataHP *out);
+
 // The data of the device build of the local operators: integrals of the data
 // against scaled monomials, which the device maps onto the orthonormal bases.
 //   mf   [nc][d][nT]   (f_a, M_j)_T, M_j the cell monomials of degree <= k at

@@ -2176,6 +2176,36 @@ int hho_get_local_cell(const hho_problem *p, int64_t cell, double *a, double *B,
   ABI_END
 }
 
+int hho_local_hp_cell(const hho_mesh *m, int k, double eta, int qdeg, int64_t cell, hho_field_fn f,
+                      hho_field_fn gD, hho_field_fn gN, void *ctx, double *a, double *B, double *ru, double *rp,
+                      int64_t cap, int64_t *nloc_out, int64_t *npl_out) {
+  ABI_BEGIN
+  if (!m) hho::fail(HHO_E_INVALID_ARG, "local_hp_cell: no mesh");
+  if (k < 0 || k > 8) hho::fail(HHO_E_INVALID_ARG, "local_hp_cell: degree out of range (0..8)");
+  if (!(eta > 0)) hho::fail(HHO_E_INVALID_ARG, "local_hp_cell: eta must be positive");
+  if (qdeg < 2 * k + 2) hho::fail(HHO_E_INVALID_ARG, "local_hp_cell: qdeg below 2k + 2");
+  if (cell < 0 || cell >= m->nc) hho::fail(HHO_E_INVALID_ARG, "local_hp_cell: cell out of range");
+  hho::LocalDataHP L;
+  hho::build_local_hp(m, k, eta, qdeg, f, gD, gN, ctx, &L);
+  const int64_t nloc = L.nloc[cell], npl = L.npl[cell], d = L.d;
+  if (nloc_out) *nloc_out = nloc;
+  if (npl_out) *npl_out = npl;
+  if (cap < nloc * nloc || cap < d * npl * nloc) {
+    hho::set_error("local_hp_cell: capacity too small");
+    return HHO_E_CAPACITY;
+  }
+  const double *r = &L.rec[L.off[cell]];
+  if (a) std::memcpy(a, r, sizeof(double) * nloc * nloc);
+  r += nloc * nloc;
+  if (B) std::memcpy(B, r, sizeof(double) * d * npl * nloc);
+  r += d * npl * nloc;
+  if (ru) std::memcpy(ru, r, sizeof(double) * d * nloc);
+  r += d * nloc;
+  if (rp) std::memcpy(rp, r, sizeof(double) * npl);
+  return HHO_OK;
+  ABI_END
+}
+
 int hho_get_condensed_cell(hho_problem *p, int64_t cell, double *S, double *rhs, int64_t cap, int64_t *n_out) {
   ABI_BEGIN
   need_setup(p);

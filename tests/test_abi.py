@@ -250,3 +250,34 @@ def test_solution_sizes():
     assert P.solution_sizes() == (mesh.n_faces * 2 * 3, mesh.n_cells)
     Q = H.Problem(H.Mesh(mesh), 2, "v")
     assert Q.solution_sizes() == (mesh.n_faces * 2 * 3, mesh.n_cells * 6)
+
+
+@pytest.mark.parametrize("mk,k", [(lambda: cartesian_quads(2), 1), (lambda: voronoi_lloyd(10, 2), 2),
+                                  (lambda: cartesian_hexes(2), 1), (lambda: voronoi_lloyd(8, 3), 0)])
+def test_host_hp_local_operators_match_oracle(mk, k):
+    """hho_local_hp_cell (the HHO-hp scheme's local operators, Section 2.3.2, built
+    by the library on the host) against oracle.hho_hp.local_hp on every cell:
+    viscous matrix, coupling and data vectors (polynomial data, so both
+    quadratures are exact), with a Neumann side on the 2D Voronoi mesh."""
+    import oracle.hho_hp as HP
+    import paper_2009_13840_amd as H
+    mesh = mk()
+    if mesh.dim == 2 and k == 2:
+        mesh = mesh.with_bc(lambda x: 2 if x[0] > 1 - 1e-12 else 1)
+    data = problem_data(polynomial_stokes(mesh.dim, k, seed=5), None, mesh.dim)
+    P = HP.build_hp(mesh, k, data, eta=7.0)
+    M = H.Mesh(mesh)
+    for c in range(mesh.n_cells):
+        got = M.local_hp_cell(k, c, *data, eta=7.0)
+        L = P.locs[c]
+        for key, ref in (("a", L.a), ("B", L.B), ("rhs_u", L.rhs_u), ("rhs_p", L.rhs_p)):
+            assert np.abs(got[key] - ref).max() <= 1e-12 * np.abs(ref).max(), (c, key)
+
+
+def test_host_hp_local_operators_validation():
+    import paper_2009_13840_amd as H
+    M = H.Mesh(cartesian_quads(2))
+    data = problem_data(polynomial_stokes(2, 1, seed=5), None, 2)
+    for kw in (dict(k=-1, cell=0), dict(k=1, cell=4), dict(k=1, cell=0, eta=0.0), dict(k=1, cell=0, qdeg=1)):
+        with pytest.raises(H.HHOError):
+            M.local_hp_cell(kw.pop("k"), kw.pop("cell"), *data, **kw)
