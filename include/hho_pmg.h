@@ -324,6 +324,20 @@ int hho_local_hp_cell(const hho_mesh *m, int k, double eta, int qdeg, int64_t ce
                       hho_field_fn gD, hho_field_fn gN, void *ctx, double *a, double *B, double *rhs_u,
                       double *rhs_p, int64_t cap, int64_t *nloc_out, int64_t *npl_out);
 
+/* The v&p-cond skeleton of the HHO-hp scheme (Section 2.3.2 condensed as in
+ * Section 4.1.2), on the host: every cell's velocity and pressure unknowns
+ * eliminated (through the Cholesky factor of a_TT and the SPD pressure Schur
+ * complement), leaving per face its d velocity components and its pressure,
+ * dim P^k(F) modes each; unknown (f (d + 1) + c) dim P^k(F) + j (c = d: the
+ * pressure).  CSR in caller-owned host buffers: rowptr [n + 1], col and val
+ * [nnz] (rows sorted; every block of a pair of faces of a common cell stored in
+ * full), rhs [n].  With a pure Dirichlet boundary the constant face pressure
+ * spans the kernel.  Arguments as hho_local_hp_cell; HHO_E_CAPACITY (sizes
+ * still written) if cap_nnz < nnz.  No device is used. */
+int hho_hp_skeleton(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f, hho_field_fn gD,
+                    hho_field_fn gN, void *ctx, int64_t *rowptr, int64_t *col, double *val, double *rhs,
+                    int64_t cap_nnz, int64_t *n_out, int64_t *nnz_out);
+
 /* y = S_l x on level l in FP64 (device vectors in the global layout). */
 int hho_level_apply(hho_problem *p, int level, const double *x_dev, double *y_dev);
 

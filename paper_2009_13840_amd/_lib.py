@@ -32,7 +32,7 @@ EXPORTS = ["hho_last_error", "hho_options_default", "hho_mesh_create", "hho_mesh
            "hho_set_stream", "hho_set_graph", "hho_setup", "hho_level_size", "hho_solve", "hho_solve_device", "hho_solution_sizes",
            "hho_moments_size", "hho_set_moments", "hho_batch_create", "hho_batch_destroy", "hho_batch_problem",
            "hho_batch_sizes", "hho_batch_solve", "hho_learned_save", "hho_learned_load", "hho_get_rhs", "hho_get_condensed_cell",
-           "hho_get_local_cell", "hho_local_hp_cell", "hho_level_apply", "hho_vcycle_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
+           "hho_get_local_cell", "hho_local_hp_cell", "hho_hp_skeleton", "hho_level_apply", "hho_vcycle_level_apply", "hho_precond_apply", "hho_vcycle_apply", "hho_get_timings", "hho_upload",
            "hho_time_kernel", "hho_coarse_prec_apply", "hho_coarse_solve_apply", "hho_direct_info", "hho_debug_copy", "hho_learned_dims",
            "hho_learned_set_params", "hho_learned_get_params", "hho_learned_enable", "hho_learned_apply",
            "hho_learned_collect", "hho_learned_grad", "hho_learned_grad_noalloc", "hho_learned_train", "hho_mesh_create_union",
@@ -113,6 +113,8 @@ def load():
         "hho_get_local_cell": ([P, I64, D, D, D, D, I64, C.POINTER(I64)], I32),
         "hho_local_hp_cell": ([P, C.c_int, C.c_double, C.c_int, I64, FIELD_FN, FIELD_FN, FIELD_FN, P, D, D, D, D,
                                I64, C.POINTER(I64), C.POINTER(I64)], I32),
+        "hho_hp_skeleton": ([P, C.c_int, C.c_double, C.c_int, FIELD_FN, FIELD_FN, FIELD_FN, P, P, P, D, D, I64,
+                             C.POINTER(I64), C.POINTER(I64)], I32),
         "hho_level_apply": ([P, I32, P, P], I32),
         "hho_precond_apply": ([P, I32, P, P], I32),
         "hho_vcycle_level_apply": ([P, I32, I32, P, P], I32),
@@ -209,6 +211,26 @@ class Mesh:
                                      _dptr(rp), cap, C.byref(nloc), C.byref(npl)))
         return {"a": a[:n * n].reshape(n, n).copy(), "B": B[:d * m * n].reshape(d, m, n).copy(),
                 "rhs_u": ru.reshape(d, n).copy(), "rhs_p": rp.copy()}
+
+    def hp_skeleton(self, k: int, f=None, gD=None, gN=None, eta: float = 1.0, qdeg=None):
+        """The HHO-hp scheme's v&p-cond skeleton (hho_hp_skeleton): a scipy CSR
+        matrix and its right-hand side."""
+        import scipy.sparse as sp
+        lib = load()
+        d = self.dim
+        cbs = (_wrap_field(f, d, False), _wrap_field(gD, d, False), _wrap_field(gN, d, True))
+        qdeg = 2 * k + 8 if qdeg is None else qdeg
+        n, nnz = C.c_int64(), C.c_int64()
+        st = lib.hho_hp_skeleton(self.h, k, eta, qdeg, *cbs, None, None, None, None, None, 0, C.byref(n), C.byref(nnz))
+        if st not in (0, -7):
+            _check(st)
+        rp = np.zeros(n.value + 1, dtype=np.int64)
+        ci = np.zeros(nnz.value, dtype=np.int64)
+        v, b = np.zeros(nnz.value), np.zeros(n.value)
+        _check(lib.hho_hp_skeleton(self.h, k, eta, qdeg, *cbs, None, rp.ctypes.data_as(C.c_void_p),
+                                   ci.ctypes.data_as(C.c_void_p), _dptr(v), _dptr(b), nnz.value,
+                                   C.byref(n), C.byref(nnz)))
+        return sp.csr_matrix((v, ci, rp), shape=(n.value, n.value)), b
 
     @classmethod
     def union(cls, meshes):

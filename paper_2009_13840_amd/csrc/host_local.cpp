@@ -1043,6 +1043,182 @@ void build_local_hp(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn
   });
 }
 
+// v&p-cond of the HHO-hp scheme (Section 4.1.2 applied to Scheme 2): every
+// cell's velocity (d N1) and pressure (nT) unknowns are eliminated from its
+// local saddle-point system [[A (x) I_d, B^T], [B, 0]], leaving the face
+// velocities and face pressures.  The cell block is solved through the
+// Cholesky factor of the scalar a_TT and the SPD pressure Schur complement
+// S_p = sum_c B_c a_TT^{-1} B_c^T (nonsingular: the divergence maps
+// P^{k+1}(T)^d onto P^k(T)).  Skeletal unknown of face f, component c (c = d:
+// the pressure), mode j: (f (d + 1) + c) nF + j.  Output: CSR (rows sorted, every
+// block of a pair of faces of a common cell stored in full, explicit zeros
+// included) and the right-hand side.
+void build_skeleton_hp(const hho_mesh *m, const LocalDataHP &L, std::vector<int64_t> &rowptr,
+                       std::vector<int64_t> &colidx, std::vector<double> &val, std::vector<double> &rhs) {
+  const int d = L.d, N1 = L.N1, nT = L.nT, nF = L.nF, bs = (d + 1) * nF;
+  const int64_t nc = m->nc, nf = m->nf, n = nf * bs;
+  std::vector<std::vector<double>> Sc(nc), gc(nc);
+  parallel_for(nc, [&](int64_t c) {
+    const int nfc = (int)(m->cptr[c + 1] - m->cptr[c]);
+    const int nloc = L.nloc[c], npl = L.npl[c];
+    const double *a = &L.rec[L.off[c]];
+    const double *B = a + (size_t)nloc * nloc;
+    const double *ru = B + (size_t)d * npl * nloc;
+    const double *rp = ru + (size_t)d * nloc;
+    auto Bc = [&](int cc, int r, int col) { return B[((size_t)cc * npl + r) * nloc + col]; };
+    // Cholesky of a_TT
+    std::vector<double> La((size_t)N1 * N1);
+    for (int i = 0; i < N1; ++i)
+      for (int j = 0; j < N1; ++j) La[(size_t)i * N1 + j] = a[(size_t)i * nloc + j];
+    if (!cholesky(La.data(), N1, N1)) fail(HHO_E_LOCAL_SINGULAR, "hp: a_TT not SPD in cell " + std::to_string(c));
+    // W_c = a_TT^{-1} B_c^T (cell pressure rows), S_p = sum_c B_c W_c
+    std::vector<double> W((size_t)d * N1 * nT), Sp((size_t)nT * nT, 0.0);
+    for (int cc = 0; cc < d; ++cc) {
+      double *Wc = &W[(size_t)cc * N1 * nT];
+      for (int i = 0; i < N1; ++i)
+        for (int t = 0; t < nT; ++t) Wc[(size_t)i * nT + t] = Bc(cc, t, i);
+      chol_solve(La.data(), N1, N1, Wc, nT, nT);
+      for (int t = 0; t < nT; ++t)
+        for (int u = 0; u < nT; ++u) {
+          double s = 0;
+          for (int i = 0; i < N1; ++i) s += Bc(cc, t, i) * Wc[(size_t)i * nT + u];
+          Sp[(size_t)t * nT + u] += s;
+        }
+    }
+    if (!cholesky(Sp.data(), nT, nT)) fail(HHO_E_LOCAL_SINGULAR, "hp: pressure Schur complement not SPD in cell " + std::to_string(c));
+    // the cell's skeletal unknowns: velocity (face i, component cc, mode j), then pressure (face i, mode j)
+    const int nk = nfc * bs;
+    auto kcol = [&](int kk, int cc) -> int {  // local velocity column of skeletal unknown kk for component cc (-1: none)
+      const int nv = nfc * d * nF;
+      if (kk >= nv) return -1;
+      const int i = kk / (d * nF), c2 = (kk / nF) % d, j = kk % nF;
+      return c2 == cc ? N1 + i * nF + j : -1;
+    };
+    auto krow = [&](int kk) -> int {  // local pressure row of skeletal unknown kk (-1: a velocity)
+      const int nv = nfc * d * nF;
+      return kk < nv ? -1 : nT + (kk - nv);
+    };
+    // columns: M_IK (one per skeletal unknown) and the interior right-hand side
+    const int nI = d * N1 + nT, ncol = nk + 1;
+    std::vector<double> X((size_t)nI * ncol, 0.0);  // rows: cell velocity (cc, i), then cell pressure t
+    for (int kk = 0; kk <= nk; ++kk) {
+      std::vector<double> fu((size_t)d * N1, 0.0), fp(nT, 0.0);
+      if (kk < nk) {
+        const int pr = krow(kk);
+        for (int cc = 0; cc < d; ++cc) {
+          const int vc = kcol(kk, cc);
+          for (int i = 0; i < N1; ++i)
+            fu[(size_t)cc * N1 + i] = vc >= 0 ? a[(size_t)i * nloc + vc] : (pr >= 0 ? Bc(cc, pr, i) : 0.0);
+          if (vc >= 0)
+            for (int t = 0; t < nT; ++t) fp[t] += Bc(cc, t, vc);
+        }
+      } else {
+        for (int cc = 0; cc < d; ++cc)
+          for (int i = 0; i < N1; ++i) fu[(size_t)cc * N1 + i] = ru[cc * nloc + i];
+        for (int t = 0; t < nT; ++t) fp[t] = rp[t];
+      }
+      // saddle solve: g_c = a^{-1} f_c; S_p x_p = sum_c B_c g_c - f_p; x_c = g_c - W_c x_p
+      std::vector<double> g(fu), xp(nT, 0.0);
+      for (int cc = 0; cc < d; ++cc) chol_solve(La.data(), N1, N1, &g[(size_t)cc * N1], 1, 1);
+      for (int t = 0; t < nT; ++t) {
+        double s = -fp[t];
+        for (int cc = 0; cc < d; ++cc)
+          for (int i = 0; i < N1; ++i) s += Bc(cc, t, i) * g[(size_t)cc * N1 + i];
+        xp[t] = s;
+      }
+      chol_solve(Sp.data(), nT, nT, xp.data(), 1, 1);
+      for (int cc = 0; cc < d; ++cc)
+        for (int i = 0; i < N1; ++i) {
+          double s = g[(size_t)cc * N1 + i];
+          for (int t = 0; t < nT; ++t) s -= W[((size_t)cc * N1 + i) * nT + t] * xp[t];
+          X[((size_t)cc * N1 + i) * ncol + kk] = s;
+        }
+      for (int t = 0; t < nT; ++t) X[((size_t)d * N1 + t) * ncol + kk] = xp[t];
+    }
+    // S = M_KK - M_KI X_K, g = rhs_K - M_KI X_rhs; M_KI row kk is column kk of M_IK
+    std::vector<double> &S = Sc[c];
+    std::vector<double> &gl = gc[c];
+    S.assign((size_t)nk * nk, 0.0);
+    gl.assign(nk, 0.0);
+    for (int r = 0; r < nk; ++r) {
+      const int pr = krow(r);
+      std::vector<double> mki(nI, 0.0);  // row r of M_KI
+      for (int cc = 0; cc < d; ++cc) {
+        const int vc = kcol(r, cc);
+        for (int i = 0; i < N1; ++i)
+          mki[(size_t)cc * N1 + i] = vc >= 0 ? a[(size_t)vc * nloc + i] : (pr >= 0 ? Bc(cc, pr, i) : 0.0);
+        if (vc >= 0)
+          for (int t = 0; t < nT; ++t) mki[(size_t)d * N1 + t] += Bc(cc, t, vc);
+      }
+      for (int s2 = 0; s2 <= nk; ++s2) {
+        double v = 0;
+        if (s2 < nk) {  // M_KK entry
+          const int ps = krow(s2);
+          for (int cc = 0; cc < d; ++cc) {
+            const int vr = kcol(r, cc), vs = kcol(s2, cc);
+            if (vr >= 0 && vs >= 0) v += a[(size_t)vr * nloc + vs];
+            if (pr >= 0 && vs >= 0) v += Bc(cc, pr, vs);
+            if (vr >= 0 && ps >= 0) v += Bc(cc, ps, vr);
+          }
+        } else {        // right-hand side entry
+          if (pr >= 0) v = rp[pr];
+          else
+            for (int cc = 0; cc < d; ++cc)
+              if (kcol(r, cc) >= 0) v = ru[cc * nloc + kcol(r, cc)];
+        }
+        for (int q = 0; q < nI; ++q) v -= mki[q] * X[(size_t)q * ncol + s2];
+        if (s2 < nk) S[(size_t)r * nk + s2] = v;
+        else gl[r] = v;
+      }
+    }
+  });
+  // global index of each of a cell's skeletal unknowns
+  auto gidx = [&](int64_t c, int kk) -> int64_t {
+    const int nv = (int)(m->cptr[c + 1] - m->cptr[c]) * d * nF;
+    if (kk < nv) {
+      const int i = kk / (d * nF), cc = (kk / nF) % d, j = kk % nF;
+      return (m->cface[m->cptr[c] + i] * (d + 1) + cc) * nF + j;
+    }
+    const int i = (kk - nv) / nF, j = (kk - nv) % nF;
+    return (m->cface[m->cptr[c] + i] * (d + 1) + d) * nF + j;
+  };
+  // face-face pattern: faces of a common cell, sorted
+  std::vector<std::vector<int64_t>> nb(nf);
+  for (int64_t c = 0; c < nc; ++c)
+    for (int64_t e = m->cptr[c]; e < m->cptr[c + 1]; ++e)
+      for (int64_t e2 = m->cptr[c]; e2 < m->cptr[c + 1]; ++e2) nb[m->cface[e]].push_back(m->cface[e2]);
+  for (auto &v : nb) {
+    std::sort(v.begin(), v.end());
+    v.erase(std::unique(v.begin(), v.end()), v.end());
+  }
+  rowptr.assign(n + 1, 0);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int r = 0; r < bs; ++r) rowptr[f * bs + r + 1] = (int64_t)nb[f].size() * bs;
+  for (int64_t i = 0; i < n; ++i) rowptr[i + 1] += rowptr[i];
+  colidx.assign(rowptr[n], 0);
+  val.assign(rowptr[n], 0.0);
+  rhs.assign(n, 0.0);
+  for (int64_t f = 0; f < nf; ++f)
+    for (int r = 0; r < bs; ++r) {
+      int64_t o = rowptr[f * bs + r];
+      for (int64_t g2 : nb[f])
+        for (int cidx = 0; cidx < bs; ++cidx) colidx[o++] = g2 * bs + cidx;
+    }
+  for (int64_t c = 0; c < nc; ++c) {
+    const int nk = (int)(m->cptr[c + 1] - m->cptr[c]) * bs;
+    for (int r = 0; r < nk; ++r) {
+      const int64_t gr = gidx(c, r);
+      rhs[gr] += gc[c][r];
+      const int64_t *cb = &colidx[rowptr[gr]], *ce = &colidx[rowptr[gr + 1]];
+      for (int s2 = 0; s2 < nk; ++s2) {
+        const int64_t gs = gidx(c, s2);
+        const int64_t pos = std::lower_bound(cb, ce, gs) - colidx.data();
+        val[pos] += Sc[c][(size_t)r * nk + s2];
+      }
+    }
+  }
+}
+
 void build_data_moments(const hho_mesh *m, int k, int qdeg, hho_field_fn f_fn, hho_field_fn gD_fn,
                         hho_field_fn gN_fn, void *ctx, DataMoments *out, LocalData *lay) {
   const int d = m->dim;

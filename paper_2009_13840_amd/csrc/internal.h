@@ -77,6 +77,9 @@ struct LocalDataHP {
 };
 void build_local_hp(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f, hho_field_fn gD,
                     hho_field_fn gN, void *ctx, LocalDataHP *out);
+// its v&p-cond skeleton (face velocities and face pressures) as CSR + right-hand side
+void build_skeleton_hp(const hho_mesh *m, const LocalDataHP &L, std::vector<int64_t> &rowptr,
+                       std::vector<int64_t> &col, std::vector<double> &val, std::vector<double> &rhs);
 
 // The data of the device build of the local operators: integrals of the data
 // against scaled monomials, which the device maps onto the orthonormal bases.

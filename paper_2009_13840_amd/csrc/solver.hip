@@ -2206,6 +2206,34 @@ int hho_local_hp_cell(const hho_mesh *m, int k, double eta, int qdeg, int64_t ce
   ABI_END
 }
 
+int hho_hp_skeleton(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn f, hho_field_fn gD, hho_field_fn gN,
+                    void *ctx, int64_t *rowptr, int64_t *col, double *val, double *rhs, int64_t cap_nnz,
+                    int64_t *n_out, int64_t *nnz_out) {
+  ABI_BEGIN
+  if (!m) hho::fail(HHO_E_INVALID_ARG, "hp_skeleton: no mesh");
+  if (k < 0 || k > 8) hho::fail(HHO_E_INVALID_ARG, "hp_skeleton: degree out of range (0..8)");
+  if (!(eta > 0)) hho::fail(HHO_E_INVALID_ARG, "hp_skeleton: eta must be positive");
+  if (qdeg < 2 * k + 2) hho::fail(HHO_E_INVALID_ARG, "hp_skeleton: qdeg below 2k + 2");
+  hho::LocalDataHP L;
+  hho::build_local_hp(m, k, eta, qdeg, f, gD, gN, ctx, &L);
+  std::vector<int64_t> rp, ci;
+  std::vector<double> v, b;
+  hho::build_skeleton_hp(m, L, rp, ci, v, b);
+  const int64_t n = (int64_t)b.size(), nnz = rp.back();
+  if (n_out) *n_out = n;
+  if (nnz_out) *nnz_out = nnz;
+  if (cap_nnz < nnz) {
+    hho::set_error("hp_skeleton: capacity too small");
+    return HHO_E_CAPACITY;
+  }
+  if (rowptr) std::memcpy(rowptr, rp.data(), sizeof(int64_t) * (n + 1));
+  if (col) std::memcpy(col, ci.data(), sizeof(int64_t) * nnz);
+  if (val) std::memcpy(val, v.data(), sizeof(double) * nnz);
+  if (rhs) std::memcpy(rhs, b.data(), sizeof(double) * n);
+  return HHO_OK;
+  ABI_END
+}
+
 int hho_get_condensed_cell(hho_problem *p, int64_t cell, double *S, double *rhs, int64_t cap, int64_t *n_out) {
   ABI_BEGIN
   need_setup(p);
