@@ -370,23 +370,29 @@ void chol_solve(const double *L, int n, int lda, double *B, int nrhs, int ldb) {
 }  // namespace
 
 // ---------------------------------------------------------------- driver
-void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, int qdeg, hho_field_fn f_fn,
-                 hho_field_fn gD_fn, hho_field_fn gN_fn, void *ctx, LocalData *out) {
-  const int d = m->dim;
-  const int N1 = dim_poly(d, k + 1), nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
-  out->k = k;
-  out->d = d;
-  out->nT = nT;
-  out->nF = nF;
-  out->N1 = N1;
+namespace {
+// Inputs shared by the local builds: quadrature rules, face basis values and
+// the data at the data points.
+struct LocalInputs {
+  std::vector<Rule> crule, frule, corule, forule;         // data / operator rules of cells and faces
+  std::vector<std::vector<double>> fpsi, fpsio;           // face basis values at the data / operator points
+  std::vector<int64_t> coff, dof_, nof;                   // offsets of the cell / Dirichlet / Neumann data points
+  std::vector<double> fval, dval, nval;                   // f, g_D, g_N at those points
+};
+void prepare_local_inputs(const hho_mesh *m, int k, int qdeg, hho_field_fn f_fn, hho_field_fn gD_fn,
+                          hho_field_fn gN_fn, void *ctx, const char *who, LocalInputs &I) {
+  const int d = m->dim, nF = dim_poly(d - 1, k);
   const int64_t nc = m->nc, nf = m->nf;
-
   // quadrature rules: the data integrals (f, g_D, g_N) use rules exact to qdeg;
   // every other integrand (Gram matrices of the bases, stiffness, reconstruction
   // right-hand side, trace projections, coupling) is a polynomial of degree at
   // most 2k + 2, integrated exactly by the cheaper operator rules
   const int odeg = std::min(qdeg, 2 * k + 2);
-  std::vector<Rule> crule(nc), frule(nf), corule(nc), forule(nf);
+  I.crule.resize(nc);
+  I.corule.resize(nc);
+  I.frule.resize(nf);
+  I.forule.resize(nf);
+  auto &crule = I.crule, &frule = I.frule, &corule = I.corule, &forule = I.forule;
   parallel_for(nc, [&](int64_t c) {
     cell_rule(m, c, qdeg, crule[c]);
     cell_rule(m, c, odeg, corule[c]);
@@ -398,7 +404,9 @@ void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, i
 
   // face bases (shared by the two cells of a face)
   std::vector<FaceBasis> fb(nf);
-  std::vector<std::vector<double>> fpsi(nf), fpsio(nf);  // values at the data / operator points
+  I.fpsi.resize(nf);
+  I.fpsio.resize(nf);
+  auto &fpsi = I.fpsi, &fpsio = I.fpsio;  // values at the data / operator points
   const std::vector<int> EF = exponents(d - 1, k);
   parallel_for(nf, [&](int64_t f) {
     FaceBasis &B = fb[f];
@@ -429,19 +437,28 @@ void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, i
   });
 
   // data at the quadrature points: body force on cells, Dirichlet / Neumann data on faces
-  std::vector<int64_t> coff(nc + 1, 0), dof_(nf + 1, 0), nof(nf + 1, 0);
+  I.coff.assign(nc + 1, 0);
+  I.dof_.assign(nf + 1, 0);
+  I.nof.assign(nf + 1, 0);
+  auto &coff = I.coff, &dof_ = I.dof_, &nof = I.nof;
   for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + crule[c].n();
   for (int64_t f = 0; f < nf; ++f) {
     dof_[f + 1] = dof_[f] + (m->fbc[f] == HHO_FACE_DIRICHLET ? frule[f].n() : 0);
     nof[f + 1] = nof[f] + (m->fbc[f] == HHO_FACE_NEUMANN ? frule[f].n() : 0);
   }
-  std::vector<double> fx(coff[nc] * d), fval(coff[nc] * d, 0.0);
+  std::vector<double> fx(coff[nc] * d);
+  I.fval.assign(coff[nc] * d, 0.0);
+  auto &fval = I.fval;
   for (int64_t c = 0; c < nc; ++c)
     for (int q = 0; q < crule[c].n(); ++q)
       for (int a = 0; a < d; ++a) fx[(coff[c] + q) * d + a] = crule[c].x[3 * q + a];
   if (f_fn && coff[nc]) f_fn(fx.data(), coff[nc], nullptr, fval.data(), ctx);
-  std::vector<double> dx(dof_[nf] * d), dn(dof_[nf] * d), dval(dof_[nf] * d, 0.0);
-  std::vector<double> nx(nof[nf] * d), nn(nof[nf] * d), nval(nof[nf] * d, 0.0);
+  std::vector<double> dx(dof_[nf] * d), dn(dof_[nf] * d);
+  I.dval.assign(dof_[nf] * d, 0.0);
+  auto &dval = I.dval;
+  std::vector<double> nx(nof[nf] * d), nn(nof[nf] * d);
+  I.nval.assign(nof[nf] * d, 0.0);
+  auto &nval = I.nval;
   for (int64_t f = 0; f < nf; ++f) {
     if (m->fbc[f] == HHO_FACE_INTERIOR) continue;
     int64_t c = m->fcell[0][f];
@@ -456,9 +473,30 @@ void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, i
   }
   if (gD_fn && dof_[nf]) gD_fn(dx.data(), dof_[nf], dn.data(), dval.data(), ctx);
   if (nof[nf]) {
-    if (!gN_fn) fail(HHO_E_INVALID_ARG, "set_data: the mesh has Neumann faces but gN is NULL");
+    if (!gN_fn) fail(HHO_E_INVALID_ARG, std::string(who) + ": the mesh has Neumann faces but gN is NULL");
     gN_fn(nx.data(), nof[nf], nn.data(), nval.data(), ctx);
   }
+
+}
+}  // namespace
+
+void build_local(const hho_mesh *m, int k, double eta, const double *cell_eta, int qdeg, hho_field_fn f_fn,
+                 hho_field_fn gD_fn, hho_field_fn gN_fn, void *ctx, LocalData *out) {
+  const int d = m->dim;
+  const int N1 = dim_poly(d, k + 1), nT = dim_poly(d, k), nF = dim_poly(d - 1, k);
+  out->k = k;
+  out->d = d;
+  out->nT = nT;
+  out->nF = nF;
+  out->N1 = N1;
+  const int64_t nc = m->nc, nf = m->nf;
+
+  LocalInputs I;
+  prepare_local_inputs(m, k, qdeg, f_fn, gD_fn, gN_fn, ctx, "set_data", I);
+  const std::vector<Rule> &crule = I.crule, &frule = I.frule, &corule = I.corule, &forule = I.forule;
+  const std::vector<std::vector<double>> &fpsi = I.fpsi, &fpsio = I.fpsio;
+  const std::vector<int64_t> &coff = I.coff, &dof_ = I.dof_, &nof = I.nof;
+  const std::vector<double> &fval = I.fval, &dval = I.dval, &nval = I.nval;
 
   // record layout
   out->off.assign(nc + 1, 0);
@@ -735,77 +773,13 @@ void build_local_hp(const hho_mesh *m, int k, double eta, int qdeg, hho_field_fn
   out->nT = nT;
   out->nF = nF;
   const int64_t nc = m->nc, nf = m->nf;
-  const int odeg = std::min(qdeg, 2 * k + 2);  // every operator integrand has degree <= 2k + 2
-  std::vector<Rule> crule(nc), frule(nf), corule(nc), forule(nf);
-  parallel_for(nc, [&](int64_t c) {
-    cell_rule(m, c, qdeg, crule[c]);
-    cell_rule(m, c, odeg, corule[c]);
-  });
-  parallel_for(nf, [&](int64_t f) {
-    face_rule(m, f, qdeg, frule[f]);
-    face_rule(m, f, odeg, forule[f]);
-  });
-  std::vector<FaceBasis> fb(nf);
-  std::vector<std::vector<double>> fpsi(nf), fpsio(nf);
-  const std::vector<int> EF = exponents(d - 1, k);
-  parallel_for(nf, [&](int64_t f) {
-    FaceBasis &B = fb[f];
-    B.nvar = d - 1;
-    B.N = nF;
-    B.E = EF;
-    B.h = m->fdiam[f];
-    for (int q = 0; q < 3; ++q) {
-      B.x0[q] = m->fcen[3 * f + q];
-      B.t1[q] = m->ft1[3 * f + q];
-      B.t2[q] = m->ft2[3 * f + q];
-    }
-    const Rule &R = forule[f];
-    int nq = R.n();
-    std::vector<double> xi((size_t)nq * B.nvar), M((size_t)nq * nF);
-    for (int q = 0; q < nq; ++q) {
-      const double *x = &R.x[3 * q];
-      double r[3] = {x[0] - B.x0[0], x[1] - B.x0[1], x[2] - B.x0[2]};
-      xi[q * B.nvar] = (r[0] * B.t1[0] + r[1] * B.t1[1] + r[2] * B.t1[2]) / B.h;
-      if (B.nvar == 2) xi[q * B.nvar + 1] = (r[0] * B.t2[0] + r[1] * B.t2[1] + r[2] * B.t2[2]) / B.h;
-    }
-    eval_monomials(B.E, B.nvar, xi.data(), nq, M.data());
-    gram_schmidt(M.data(), R.w.data(), nq, nF, B.C);
-    fpsio[f].resize((size_t)nq * nF);
-    B.values(R.x.data(), nq, fpsio[f].data());
-    fpsi[f].resize((size_t)frule[f].n() * nF);
-    B.values(frule[f].x.data(), frule[f].n(), fpsi[f].data());
-  });
-  // data at the data points
-  std::vector<int64_t> coff(nc + 1, 0), dof_(nf + 1, 0), nof(nf + 1, 0);
-  for (int64_t c = 0; c < nc; ++c) coff[c + 1] = coff[c] + crule[c].n();
-  for (int64_t f = 0; f < nf; ++f) {
-    dof_[f + 1] = dof_[f] + (m->fbc[f] == HHO_FACE_DIRICHLET ? frule[f].n() : 0);
-    nof[f + 1] = nof[f] + (m->fbc[f] == HHO_FACE_NEUMANN ? frule[f].n() : 0);
-  }
-  std::vector<double> fx(coff[nc] * d), fval(coff[nc] * d, 0.0);
-  for (int64_t c = 0; c < nc; ++c)
-    for (int q = 0; q < crule[c].n(); ++q)
-      for (int a = 0; a < d; ++a) fx[(coff[c] + q) * d + a] = crule[c].x[3 * q + a];
-  if (f_fn && coff[nc]) f_fn(fx.data(), coff[nc], nullptr, fval.data(), ctx);
-  std::vector<double> dx(dof_[nf] * d), dn(dof_[nf] * d), dval(dof_[nf] * d, 0.0);
-  std::vector<double> nx(nof[nf] * d), nn(nof[nf] * d), nval(nof[nf] * d, 0.0);
-  for (int64_t f = 0; f < nf; ++f) {
-    if (m->fbc[f] == HHO_FACE_INTERIOR) continue;
-    int64_t c = m->fcell[0][f];
-    double sg = m->csign[m->cptr[c] + m->flocal[0][f]];
-    bool isD = m->fbc[f] == HHO_FACE_DIRICHLET;
-    int64_t o = isD ? dof_[f] : nof[f];
-    for (int q = 0; q < frule[f].n(); ++q)
-      for (int a = 0; a < d; ++a) {
-        (isD ? dx : nx)[(o + q) * d + a] = frule[f].x[3 * q + a];
-        (isD ? dn : nn)[(o + q) * d + a] = sg * m->fnrm[3 * f + a];
-      }
-  }
-  if (gD_fn && dof_[nf]) gD_fn(dx.data(), dof_[nf], dn.data(), dval.data(), ctx);
-  if (nof[nf]) {
-    if (!gN_fn) fail(HHO_E_INVALID_ARG, "local_hp: the mesh has Neumann faces but gN is NULL");
-    gN_fn(nx.data(), nof[nf], nn.data(), nval.data(), ctx);
-  }
+  LocalInputs I;
+  prepare_local_inputs(m, k, qdeg, f_fn, gD_fn, gN_fn, ctx, "local_hp", I);
+  const std::vector<Rule> &crule = I.crule, &frule = I.frule, &corule = I.corule, &forule = I.forule;
+  const std::vector<std::vector<double>> &fpsi = I.fpsi, &fpsio = I.fpsio;
+  const std::vector<int64_t> &coff = I.coff, &dof_ = I.dof_, &nof = I.nof;
+  const std::vector<double> &fval = I.fval, &dval = I.dval, &nval = I.nval;
+
   out->off.assign(nc + 1, 0);
   out->nloc.assign(nc, 0);
   out->npl.assign(nc, 0);
