@@ -306,3 +306,30 @@ def test_host_hp_skeleton_matches_oracle(mk, k):
     assert np.abs(b - go).max() <= 1e-12 * np.abs(go).max()
     if mesh.dim == 2:
         assert S.nnz == counts(mesh, k)["mnz_hp"]
+
+
+def test_host_hp_skeleton_kernel_and_validation():
+    """With a pure Dirichlet boundary the constant face pressure spans the
+    library skeleton's kernel (as its header states); with a Neumann side it is
+    not in the kernel; bad arguments are refused."""
+    import paper_2009_13840_amd as H
+    from synth import trig_series
+    for neumann in (False, True):
+        mesh = voronoi_lloyd(15, 4)
+        if neumann:
+            mesh = mesh.with_bc(lambda x: 2 if x[0] > 1 - 1e-12 else 1)
+        M = H.Mesh(mesh)
+        S, _ = M.hp_skeleton(1, *problem_data(None, trig_series(2, 2), 2), eta=10.0)
+        nF, d = 2, 2
+        z = np.zeros(S.shape[0])
+        verts = mesh.verts
+        for f in range(mesh.n_faces):
+            a, b = verts[mesh.face_vertices(f)]
+            z[(f * (d + 1) + d) * nF] = np.sqrt(np.linalg.norm(b - a))
+        r = np.abs(S @ z).max() / (abs(S).max() * np.abs(z).max())
+        assert (r > 1e-6) if neumann else (r <= 1e-13), (neumann, r)
+    M = H.Mesh(cartesian_quads(2))
+    data = problem_data(polynomial_stokes(2, 1, seed=5), None, 2)
+    for kw in (dict(k=9), dict(k=1, eta=-1.0), dict(k=1, qdeg=3)):
+        with pytest.raises(H.HHOError):
+            M.hp_skeleton(kw.pop("k"), *data, **kw)
