@@ -238,3 +238,21 @@ def test_hp_skeleton_size_and_pattern_match_the_table_formulas(mesh, k):
     Sg, _, _ = HP.condense_vp(P)
     c = counts(mesh, k)
     assert Sg.shape[0] == c["dof_hp"] and Sg.nnz == c["mnz_hp"]
+
+
+@pytest.mark.parametrize("mesh,k", [(voronoi_lloyd(40, 3), 1), (voronoi_lloyd(30, 2), 2), (cartesian_hexes(3), 1)])
+def test_hp_with_the_papers_ilu_smoother(mesh, k):
+    """The paper's solver configuration (Section 3.3: smoothing by two
+    ILU(0)-preconditioned GMRES iterations) on the HHO-hp skeleton: FGMRES
+    reaches the uncondensed solution, in no more iterations than with the
+    cell-patch Schwarz smoother on these meshes."""
+    import oracle.solve as OS
+    P = HP.build_hp(mesh, k, problem_data(None, trig_series(mesh.dim, 7), mesh.dim))
+    Q, perm = HP.multilevel_problem(P)
+    xu = HP.normalise_pressure(P, HP.solve_uncondensed(P))
+    its = {}
+    for sm in ("ilu", "schwarz"):
+        x, its[sm], _, conv = OS.solve_fgmres(Q, rtol=1e-11, smoother=sm)
+        full = HP.normalise_pressure(P, HP.recover_from_skeleton(P, x, perm))
+        assert conv and np.abs(full - xu).max() <= 1e-6 * np.abs(xu).max()
+    assert its["ilu"] <= its["schwarz"], its
